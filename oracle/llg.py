@@ -1,0 +1,171 @@
+"""Landau-Lifshitz right-hand side and Runge-Kutta time stepping, FP64.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Sec. 2, Eq. 1 with M = Ms m:
+
+    dm/dt = -gamma/(1+alpha^2) m x H  -  alpha gamma/(1+alpha^2) m x (m x H)
+
+Sec. 2.2 lists the explicit Runge-Kutta schemes.  Every stage input and every
+accepted state is renormalised to |m| = 1 (the paper is silent on this; the
+exact flow keeps |m| = 1, and normalising the stage inputs is the same as
+integrating dm/dt = f(m/|m|), so the order of each scheme is kept).  The
+thermal field of Eq. 6 is drawn once per step and held fixed across the
+stages of that step.
+
+Adaptive Dormand-Prince 5(4) (Sec. 2.2 "RKDP"), with the reading of the
+"maximum tolerable error per integration step":
+    err  = max over cells |dt sum_j (b_j - bhat_j) k_j|
+    accept if err <= tol
+    dt  <- dt * clamp(0.9 (tol/err)^(1/5), 0.2, 5)      (5 if err == 0)
+    the last step is shortened to land on t_end.
+"""
+import math
+
+import numpy as np
+
+from .constants import GAMMA0
+from . import fields
+
+# --------------------------------------------------------------------------
+# Butcher tableaux (c implied by row sums)
+# --------------------------------------------------------------------------
+EULER = {"A": [[]], "b": [1.0]}
+HEUN = {"A": [[], [1.0]], "b": [0.5, 0.5]}
+RK4 = {"A": [[], [0.5], [0.0, 0.5], [0.0, 0.0, 1.0]],
+       "b": [1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0]}
+# Dormand & Prince (1980), RK5(4)7M
+DP45 = {
+    "A": [
+        [],
+        [1.0 / 5.0],
+        [3.0 / 40.0, 9.0 / 40.0],
+        [44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0],
+        [19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0],
+        [9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0],
+        [35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0],
+    ],
+    "b": [35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0, 0.0],
+    "bhat": [5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0, -92097.0 / 339200.0,
+             187.0 / 2100.0, 1.0 / 40.0],
+}
+TABLEAUX = {"euler": EULER, "heun": HEUN, "rk4": RK4, "rkdp45": DP45}
+
+
+def normalize(m):
+    return m / np.sqrt(np.sum(m * m, axis=0, keepdims=True))
+
+
+def ll_rhs(m, H, alpha):
+    """Eq. 1 divided by Ms: dm/dt for field H (A/m)."""
+    mxH = np.cross(m, H, axis=0)
+    mxmxH = np.cross(m, mxH, axis=0)
+    return -GAMMA0 / (1.0 + alpha * alpha) * (mxH + alpha * mxmxH)
+
+
+class Solver:
+    """Plain FP64 integrator state for one problem."""
+
+    def __init__(self, prob, m0, renormalize=True):
+        self.prob = dict(prob)
+        # the library renormalises the state it is given; so does the oracle
+        self.m = normalize(np.array(m0, dtype=np.float64)) if renormalize \
+            else np.array(m0, dtype=np.float64)
+        self.t = 0.0
+        self.step_count = 0          # accepted steps: thermal draw counter
+        self.evals = 0
+        self.renormalize = renormalize
+
+    # -- field and derivative -------------------------------------------------
+    def rhs(self, m, dt):
+        H = fields.heff(m, self.prob, dt=dt, step=self.step_count)
+        self.evals += 1
+        return ll_rhs(m, H, self.prob["alpha"])
+
+    def _norm(self, m):
+        return normalize(m) if self.renormalize else m
+
+    def _stages(self, tab, dt):
+        """Runs the stages of one explicit RK step from self.m; returns k."""
+        ks = []
+        for s, row in enumerate(tab["A"]):
+            if s == 0:
+                ms = self.m
+            else:
+                ms = self.m.copy()
+                for a, k in zip(row, ks):
+                    if a != 0.0:
+                        ms = ms + (dt * a) * k
+                ms = self._norm(ms)
+            ks.append(self.rhs(ms, dt))
+        return ks
+
+    def _combine(self, ks, weights, dt):
+        out = self.m.copy()
+        for w, k in zip(weights, ks):
+            if w != 0.0:
+                out = out + (dt * w) * k
+        return out
+
+    # -- fixed step -----------------------------------------------------------
+    def step(self, method, dt, nsteps=1):
+        tab = TABLEAUX[method]
+        for _ in range(nsteps):
+            ks = self._stages(tab, dt)
+            self.m = self._norm(self._combine(ks, tab["b"], dt))
+            self.t += dt
+            self.step_count += 1
+        return self.m
+
+    # -- adaptive Dormand-Prince -----------------------------------------------
+    def dp45_attempt(self, dt):
+        """One attempted step: returns (candidate m, err)."""
+        ks = self._stages(DP45, dt)
+        m5 = self._combine(ks, DP45["b"], dt)
+        diff = np.zeros_like(self.m)
+        for b, bh, k in zip(DP45["b"], DP45["bhat"], ks):
+            if b != bh:
+                diff = diff + (dt * (b - bh)) * k
+        err = float(np.max(np.sqrt(np.sum(diff * diff, axis=0))))
+        return self._norm(m5), err
+
+    @staticmethod
+    def next_dt(dt, err, tol):
+        if err == 0.0:
+            factor = 5.0
+        else:
+            factor = 0.9 * (tol / err) ** 0.2
+        return dt * min(5.0, max(0.2, factor))
+
+    def run_adaptive(self, t_end, tol, dt0, dt_min=1e-18, max_attempts=10 ** 7):
+        """Free-running DP45 to t_end; returns the list of attempts
+        (dt, err, accepted)."""
+        log = []
+        dt = dt0
+        while self.t < t_end and len(log) < max_attempts:
+            h = min(dt, t_end - self.t)
+            m_new, err = self.dp45_attempt(h)
+            ok = err <= tol
+            log.append((h, err, ok))
+            if ok:
+                self.m = m_new
+                self.t += h
+                self.step_count += 1
+            dt = self.next_dt(h, err, tol)
+            if dt < dt_min:
+                raise FloatingPointError("step size fell below dt_min")
+        return log
+
+    def replay(self, attempts):
+        """Replays a recorded attempt list [(dt, accepted), ...] (e.g. the GPU
+        run's), so both trajectories use the same step sizes; returns the
+        oracle's own error estimate per attempt."""
+        errs = []
+        for dt, ok in attempts:
+            m_new, err = self.dp45_attempt(dt)
+            errs.append(err)
+            if ok:
+                self.m = m_new
+                self.t += dt
+                self.step_count += 1
+        return errs

@@ -1,0 +1,314 @@
+"""Pins of the oracle's field terms, thermal draw, LL right-hand side and
+integrators against closed forms, invariants and order conditions (CPU)."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import fields, llg, philox
+from oracle.constants import MU0, GAMMA0, KB
+import workloads
+
+
+# --------------------------------------------------------------------------
+# exchange (Eq. 3)
+# --------------------------------------------------------------------------
+def test_exchange_on_periodic_spiral_is_exact():
+    """PIN-8: on a periodic spiral m = (cos kx, sin kx, 0) the six-neighbour
+    Laplacian is exactly -(2 - 2 cos k d)/d^2 m."""
+    nx, d = 24, 3e-9
+    q = 5
+    k = 2 * math.pi * q / (nx * d)
+    x = (np.arange(nx) + 0.5) * d
+    m = np.zeros((3, 2, 3, nx))
+    m[0] = np.cos(k * x)
+    m[1] = np.sin(k * x)
+    prob = dict(n=(nx, 3, 2), cell=(d, 2e-9, 5e-9), pbc=(True, False, False),
+                Ms=8e5, Aex=1.3e-11)
+    H = fields.exchange_field(m, prob)
+    expect = -2 * 1.3e-11 / (MU0 * 8e5) * (2 - 2 * math.cos(k * d)) / d ** 2 * m
+    np.testing.assert_allclose(H, expect, atol=1e-9 * np.abs(expect).max())
+
+
+def test_exchange_of_uniform_state_is_zero():
+    prob, _ = workloads.small_problem(n=(5, 4, 3), pbc=(False, True, False))
+    m = workloads.uniform((5, 4, 3), (0.3, -0.2, 0.9)).astype(np.float64)
+    assert np.abs(fields.exchange_field(m, prob)).max() == 0.0
+
+
+def test_exchange_free_edge_omits_missing_neighbour():
+    """A two-cell chain: each cell has exactly one neighbour."""
+    prob = dict(n=(2, 1, 1), cell=(2e-9, 2e-9, 2e-9), pbc=(False,) * 3, Ms=1e6, Aex=1e-11)
+    m = np.zeros((3, 1, 1, 2))
+    m[0, 0, 0, 0] = 1.0
+    m[1, 0, 0, 1] = 1.0
+    H = fields.exchange_field(m, prob)
+    c = 2e-11 / (MU0 * 1e6) / 4e-18
+    np.testing.assert_allclose(H[:, 0, 0, 0], c * (m[:, 0, 0, 1] - m[:, 0, 0, 0]))
+    np.testing.assert_allclose(H[:, 0, 0, 1], c * (m[:, 0, 0, 0] - m[:, 0, 0, 1]))
+
+
+# --------------------------------------------------------------------------
+# energy consistency of every term
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("term", ["demag", "exchange", "anisotropy", "cubic", "zeeman"])
+def test_field_is_minus_energy_gradient(term):
+    """PIN-9: H = -(1/(mu0 Ms V)) dE/dm for each term, by central differences
+    of the FP64 energy."""
+    prob, m0 = workloads.small_problem(n=(4, 3, 2), pbc=(True, False, False), images=1)
+    prob = dict(prob, Kc1=4e4, Kc2=-2e4, c1=(1.0, 1.0, 0.0), c2=(-1.0, 1.0, 0.5))
+    if term == "cubic":
+        prob["terms"] = ("anisotropy",)
+        prob["Ku"] = 0.0
+    elif term == "anisotropy":
+        prob["terms"] = ("anisotropy",)
+        prob["Kc1"] = prob["Kc2"] = 0.0
+    else:
+        prob["terms"] = (term,)
+    m = m0.astype(np.float64)
+    H = fields.heff(m, prob)
+    dx, dy, dz = prob["cell"]
+    V = dx * dy * dz
+    rng = np.random.default_rng(5)
+    h = 1e-5
+    for _ in range(12):
+        c = int(rng.integers(3))
+        idx = tuple(int(rng.integers(s)) for s in m.shape[1:])
+        mp = m.copy(); mp[(c,) + idx] += h
+        mm = m.copy(); mm[(c,) + idx] -= h
+        g = (fields.energy(mp, prob) - fields.energy(mm, prob)) / (2 * h)
+        expect = -g / (MU0 * prob["Ms"] * V)
+        assert H[(c,) + idx] == pytest.approx(expect, rel=1e-5, abs=1e-6 * np.abs(H).max())
+
+
+# --------------------------------------------------------------------------
+# thermal field (Eq. 6)
+# --------------------------------------------------------------------------
+KAT = [  # Philox4x32-10 known-answer vectors published with the generator
+    ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+    ((0xFFFFFFFF,) * 4, (0xFFFFFFFF, 0xFFFFFFFF), (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+    ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+     (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+]
+
+
+@pytest.mark.parametrize("ctr,key,out", KAT)
+def test_philox_known_answers(ctr, key, out):
+    got = philox.philox4x32_10([np.array([c], dtype=np.uint32) for c in ctr], key)
+    assert tuple(int(g[0]) for g in got) == out
+
+
+def test_thermal_eta_moments():
+    """PIN-14a: eta has mean 0, variance 1 and no correlation between
+    neighbouring cells or consecutive steps."""
+    n = 200000
+    e0 = philox.thermal_eta(n, 0, 12345)
+    e1 = philox.thermal_eta(n, 1, 12345)
+    for e in (e0, e1):
+        assert np.abs(e.mean(axis=1)).max() < 5 * 1 / math.sqrt(n)
+        assert np.abs(e.var(axis=1) - 1).max() < 5 * math.sqrt(2 / n)
+    lag_t = (e0 * e1).mean(axis=1)
+    lag_x = (e0[:, 1:] * e0[:, :-1]).mean(axis=1)
+    cross = (e0[0] * e0[1]).mean(), (e0[0] * e0[2]).mean()
+    for v in list(lag_t) + list(lag_x) + list(cross):
+        assert abs(v) < 5 / math.sqrt(n)
+
+
+def test_thermal_sigma_value():
+    prob, _, _ = workloads.film_3d()
+    s = fields.thermal_sigma(prob, 5e-14)
+    expect = math.sqrt(2 * 0.1 * KB * 300 / (GAMMA0 * MU0 * 1e6 * 27e-27 * 5e-14))
+    assert s == pytest.approx(expect, rel=1e-14)
+    assert s / 1e6 == pytest.approx(1.486, abs=1e-3)
+
+
+@pytest.mark.slow
+def test_langevin_equilibrium_of_independent_macrospins():
+    """PIN-14b: an ensemble of uncoupled cube spins in a field B at
+    temperature T relaxes to <cos theta> = coth(xi) - 1/xi with
+    xi = mu0 Ms V H/(k_B T)."""
+    n = (64, 64, 1)
+    d = 5e-9
+    Ms, T = 8e5, 300.0
+    xi = 2.0
+    H = xi * KB * T / (MU0 * Ms * d ** 3)
+    prob = dict(n=n, cell=(d, d, d), pbc=(False,) * 3, Ms=Ms, Aex=0.0, alpha=0.5,
+                B=(0.0, 0.0, MU0 * H), T=T, seed=99, terms=("zeeman", "thermal"))
+    s = llg.Solver(prob, workloads.uniform(n, (0, 0, 1)))
+    samples = []
+    for block in range(30):
+        s.step("heun", 1e-12, 50)
+        if block >= 10:
+            samples.append(float(s.m[2].mean()))
+    mean = float(np.mean(samples))
+    expect = 1 / math.tanh(xi) - 1 / xi
+    assert mean == pytest.approx(expect, abs=0.015)
+
+
+# --------------------------------------------------------------------------
+# LL right-hand side (Eq. 1) and integrators (Sec. 2.2)
+# --------------------------------------------------------------------------
+def test_torque_is_orthogonal_to_m():
+    """PIN-10a: m . f(m) = 0 for any field."""
+    rng = np.random.default_rng(2)
+    m = rng.standard_normal((3, 50))
+    m /= np.linalg.norm(m, axis=0)
+    H = rng.standard_normal((3, 50)) * 1e5
+    f = llg.ll_rhs(m, H, 0.3)
+    assert np.abs((m * f).sum(axis=0)).max() < 1e-9 * np.abs(f).max()
+
+
+def _macrospin(alpha, Bz, theta0=1.0, phi0=0.3):
+    """One cubic cell: its self-demag field is parallel to m, so only the
+    applied field exerts a torque."""
+    prob = dict(n=(1, 1, 1), cell=(5e-9,) * 3, pbc=(False,) * 3, Ms=8e5, Aex=1.3e-11,
+                alpha=alpha, Ku=0.0, B=(0.0, 0.0, Bz), T=0.0, seed=0)
+    m0 = np.array([math.sin(theta0) * math.cos(phi0), math.sin(theta0) * math.sin(phi0),
+                   math.cos(theta0)]).reshape(3, 1, 1, 1)
+    return prob, m0
+
+
+def _macrospin_exact(alpha, Bz, t, theta0=1.0, phi0=0.3):
+    H = Bz / MU0
+    w = GAMMA0 * H / (1 + alpha * alpha)
+    th = 2 * math.atan(math.tan(theta0 / 2) * math.exp(-alpha * w * t))
+    ph = phi0 + w * t
+    return np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+
+
+def test_macrospin_closed_form():
+    """PIN-11: precession at gamma0 H/(1+alpha^2) and damping of
+    tan(theta/2) at rate alpha gamma0 H/(1+alpha^2), via the whole field
+    pipeline (demag included)."""
+    alpha, Bz = 0.1, 0.1
+    prob, m0 = _macrospin(alpha, Bz)
+    s = llg.Solver(prob, m0)
+    s.step("rk4", 1e-13, 2000)
+    np.testing.assert_allclose(s.m[:, 0, 0, 0], _macrospin_exact(alpha, Bz, 2e-10), atol=1e-9)
+
+
+@pytest.mark.parametrize("method,order", [("euler", 1), ("heun", 2), ("rk4", 4), ("rkdp45", 5)])
+def test_convergence_order(method, order):
+    """PIN-12a: the global error on the macrospin problem falls as dt^p."""
+    alpha, Bz, t_end = 0.2, 0.2, 1e-10
+    errs = []
+    # DP45 reaches its asymptotic rate only below ~1e-10 error here
+    nsteps = (80, 160) if method == "rkdp45" else (40, 80)
+    for n in nsteps:
+        prob, m0 = _macrospin(alpha, Bz)
+        s = llg.Solver(prob, m0)
+        dt = t_end / n
+        if method == "rkdp45":
+            for _ in range(n):
+                s.m, _err = s.dp45_attempt(dt)
+        else:
+            s.step(method, dt, n)
+        errs.append(np.abs(s.m[:, 0, 0, 0] - _macrospin_exact(alpha, Bz, t_end)).max())
+    p = math.log2(errs[0] / errs[1])
+    assert abs(p - order) < 0.35, (errs, p)
+
+
+def _order_conditions(A, b, p):
+    """The Butcher order conditions up to order p (all rooted trees up to
+    order 5), with exact rational arithmetic."""
+    s = len(b)
+    A = [[Fraction(A[i][j]) if j < len(A[i]) else Fraction(0) for j in range(s)] for i in range(s)]
+    b = [Fraction(x) for x in b]
+    c = [sum(row) for row in A]
+    dot = lambda u, v: sum(x * y for x, y in zip(u, v))
+    Av = lambda v: [dot(row, v) for row in A]
+    mul = lambda u, v: [x * y for x, y in zip(u, v)]
+    one = [Fraction(1)] * s
+    conds = [(dot(b, one), Fraction(1))]
+    if p >= 2:
+        conds += [(dot(b, c), Fraction(1, 2))]
+    if p >= 3:
+        conds += [(dot(b, mul(c, c)), Fraction(1, 3)), (dot(b, Av(c)), Fraction(1, 6))]
+    if p >= 4:
+        c2 = mul(c, c)
+        conds += [(dot(b, mul(c2, c)), Fraction(1, 4)), (dot(b, mul(c, Av(c))), Fraction(1, 8)),
+                  (dot(b, Av(c2)), Fraction(1, 12)), (dot(b, Av(Av(c))), Fraction(1, 24))]
+    if p >= 5:
+        c2 = mul(c, c)
+        c3 = mul(c2, c)
+        Ac = Av(c)
+        conds += [(dot(b, mul(c3, c)), Fraction(1, 5)), (dot(b, mul(c2, Ac)), Fraction(1, 10)),
+                  (dot(b, mul(c, Av(c2))), Fraction(1, 15)), (dot(b, mul(c, Av(Ac))), Fraction(1, 30)),
+                  (dot(b, mul(Ac, Ac)), Fraction(1, 20)), (dot(b, Av(c3)), Fraction(1, 20)),
+                  (dot(b, Av(mul(c, Ac))), Fraction(1, 40)), (dot(b, Av(Av(c2))), Fraction(1, 60)),
+                  (dot(b, Av(Av(Ac))), Fraction(1, 120))]
+    return conds
+
+
+def _as_fractions(tab):
+    # recover the exact rationals the tableaux were typed from
+    conv = lambda x: Fraction(x).limit_denominator(10 ** 7)
+    return [[conv(a) for a in row] for row in tab["A"]], [conv(x) for x in tab["b"]]
+
+
+@pytest.mark.parametrize("name,p", [("euler", 1), ("heun", 2), ("rk4", 4), ("rkdp45", 5)])
+def test_tableau_order_conditions(name, p):
+    """PIN-12b: each tableau satisfies every order condition up to its
+    order (a single mistyped coefficient fails one of them)."""
+    A, b = _as_fractions(llg.TABLEAUX[name])
+    for got, want in _order_conditions(A, b, p):
+        assert got == want
+
+
+def test_dp45_embedded_pair_is_fourth_order():
+    A, _ = _as_fractions(llg.DP45)
+    bh = [Fraction(x).limit_denominator(10 ** 7) for x in llg.DP45["bhat"]]
+    for got, want in _order_conditions(A, bh, 4):
+        assert got == want
+    conds5 = _order_conditions(A, bh, 5)
+    assert any(g != w for g, w in conds5)            # the embedded pair is not 5th order
+    # FSAL: the last stage row equals b
+    assert [Fraction(x).limit_denominator(10 ** 7) for x in llg.DP45["A"][6]] == \
+        [Fraction(x).limit_denominator(10 ** 7) for x in llg.DP45["b"][:6]]
+
+
+def test_norm_drift_without_renormalisation_is_high_order():
+    """PIN-10b: with renormalisation off, |m| drifts by O(dt^(p+1)) per
+    step (the exact flow conserves |m|)."""
+    drifts = []
+    for dt in (2e-13, 1e-13):
+        prob, m0 = _macrospin(0.2, 0.5)
+        s = llg.Solver(prob, m0, renormalize=False)
+        s.step("rk4", dt, 1)
+        drifts.append(abs(np.linalg.norm(s.m[:, 0, 0, 0]) - 1))
+    assert math.log2(drifts[0] / drifts[1]) > 4.5
+
+
+def test_energy_decays_with_damping_and_is_conserved_without():
+    """PIN-13: with alpha > 0 and a static field the energy never rises; with
+    alpha = 0 it is conserved to integrator error."""
+    prob, m0 = workloads.small_problem(n=(12, 10, 1), alpha=0.5)
+    s = llg.Solver(prob, m0)
+    E = [fields.energy(s.m, prob)]
+    for _ in range(40):
+        s.step("rk4", 2e-14, 5)
+        E.append(fields.energy(s.m, prob))
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(E, E[1:]))
+    assert E[-1] < E[0]
+    prob0 = dict(prob, alpha=0.0)
+    s = llg.Solver(prob0, m0)
+    E0 = fields.energy(s.m, prob0)
+    s.step("rk4", 5e-15, 100)
+    assert abs(fields.energy(s.m, prob0) - E0) < 1e-6 * abs(E0)
+
+
+def test_dp45_controller_and_replay():
+    """Free-running DP45 reaches t_end exactly; replaying its own attempt log
+    reproduces the trajectory bit for bit."""
+    prob, m0 = workloads.small_problem(n=(6, 5, 1), alpha=0.3)
+    a = llg.Solver(prob, m0)
+    log = a.run_adaptive(2e-11, 1e-5, 1e-14)
+    assert a.t == pytest.approx(2e-11, rel=1e-12)
+    assert any(not ok for _, _, ok in log) or len(log) > 3
+    b = llg.Solver(prob, m0)
+    b.replay([(h, ok) for h, _, ok in log])
+    assert np.array_equal(a.m, b.m)
+    assert llg.Solver.next_dt(1.0, 0.0, 1e-5) == 5.0
+    assert llg.Solver.next_dt(1.0, 1.0, 1e-5) == 0.2
+    assert llg.Solver.next_dt(1.0, 1e-5, 1e-5) == pytest.approx(0.9)
