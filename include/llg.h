@@ -1,0 +1,203 @@
+/*
+ * llg.h -- C ABI of the MI355X finite-difference Landau-Lifshitz solver.
+ *
+ * The library evaluates the effective field of a finite-difference
+ * micromagnetic model and integrates the Landau-Lifshitz equation
+ * (Vansteenkiste & Van de Wiele, "MuMax: a new high-performance
+ * micromagnetic simulation tool", Sec. 2, Eq. 1) on one AMD Instinct MI355X
+ * (gfx950).  The magnetostatic field is a zero-padded FFT convolution of the
+ * magnetisation with the cell-averaged demagnetising tensor (Sec. 2.1.1,
+ * Eq. 2; Sec. 3.2), computed by the library's own FFT kernels.
+ *
+ * Units: every quantity crossing this interface is SI (m, A/m, J/m, J/m^3,
+ * tesla for applied fields given as mu0*H, K, s).  Internally the library
+ * works in reduced units (field / Ms, time * gamma0 * Ms), as Sec. 3.3
+ * recommends; the conversion is hidden.
+ *
+ * Arrays: a vector field is float32, component-major, x fastest:
+ *     v[c][k][j][i]  at  v + c*nx*ny*nz + (k*ny + j)*nx + i,
+ * c = 0,1,2 for x,y,z.  Where an argument says llg_mem, LLG_HOST means a
+ * host pointer (the call copies synchronously) and LLG_DEVICE a device
+ * pointer on the solver's device (the call is ordered on the solver's stream
+ * and returns once its work is complete).  The caller owns every buffer it
+ * passes; the library never keeps a caller pointer after a call returns.
+ *
+ * Errors: every call returns an llg_status; LLG_OK is 0.  The text of the
+ * last error of a solver is available through llg_last_error.  A solver is
+ * not thread-safe; separate solvers are independent.
+ */
+#ifndef LLG_H
+#define LLG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct llg_solver llg_solver;
+
+typedef enum {
+    LLG_OK = 0,
+    LLG_E_ARG = 1,          /* invalid argument (size, sign, range, null)         */
+    LLG_E_STATE = 2,        /* call out of order (e.g. eval before set_m)         */
+    LLG_E_NOMEM = 3,        /* device allocation failed                           */
+    LLG_E_DEVICE = 4,       /* HIP runtime error                                  */
+    LLG_E_UNSUPPORTED = 5,  /* size or option this build does not handle          */
+    LLG_E_DIVERGED = 6      /* NaN/Inf in the state or the step fell below dt_min */
+} llg_status;
+
+/* Time integrators of Sec. 2.2 (RK1 Euler, RK2 Heun, RK4 classical, RKDP
+ * Dormand-Prince 5(4) with adaptive steps). */
+typedef enum {
+    LLG_EULER = 0,
+    LLG_HEUN = 1,
+    LLG_RK4 = 2,
+    LLG_RKDP45 = 3
+} llg_method;
+
+typedef enum { LLG_HOST = 0, LLG_DEVICE = 1 } llg_mem;
+
+/* Field terms (Sec. 2.1); a bit mask for llg_set_terms. */
+enum {
+    LLG_TERM_DEMAG = 1,       /* magnetostatic, Sec. 2.1.1 Eq. 2      */
+    LLG_TERM_EXCHANGE = 2,    /* exchange, Sec. 2.1.2 Eq. 3           */
+    LLG_TERM_ANISOTROPY = 4,  /* uniaxial anisotropy, Sec. 2.1.3 Eq. 4 */
+    LLG_TERM_ZEEMAN = 8,      /* applied field, Sec. 2.1.3            */
+    LLG_TERM_THERMAL = 16,    /* thermal field, Sec. 2.1.3 Eq. 6      */
+    LLG_TERM_ALL = 31
+};
+
+/* Run statistics. */
+typedef struct {
+    double t;            /* simulated time, s                                  */
+    double dt;           /* last attempted step (fixed: the step), s           */
+    double dt_next;      /* adaptive: the controller's next step, s            */
+    double max_err;      /* adaptive: error estimate of the last attempt       */
+    int64_t steps;       /* accepted steps since llg_set_m                     */
+    int64_t rejected;    /* rejected attempts since llg_set_m                  */
+    int64_t evals;       /* effective-field evaluations since llg_set_m        */
+    int32_t health;      /* bit 0: NaN/Inf seen; bit 1: dt below dt_min        */
+    int32_t done;        /* adaptive: 1 once t reached t_end                   */
+} llg_stats;
+
+/* One attempted adaptive step, as recorded on the device. */
+typedef struct {
+    double dt;           /* attempted step, s             */
+    float err;           /* error estimate (dimensionless) */
+    int32_t accepted;    /* 1 accepted, 0 rejected          */
+} llg_attempt;
+
+/* ---- lifetime -------------------------------------------------------------
+ * llg_create: makes a solver on HIP device `device`.  `hip_stream` is a
+ * hipStream_t to order all work on, or NULL for a stream the solver creates
+ * and owns.  The solver owns all its device memory; llg_destroy frees it.
+ */
+llg_status  llg_create(int device, void *hip_stream, llg_solver **out);
+void        llg_destroy(llg_solver *s);
+/* Text of the last error on this solver; owned by the solver, valid until the
+ * next call on it.  Never NULL. */
+const char *llg_last_error(const llg_solver *s);
+
+/* ---- problem (Sec. 2: FD grid of cuboid cells; Sec. 2.1.1: periodic
+ * boundary conditions) ------------------------------------------------------
+ * llg_set_geometry: nx, ny, nz >= 1 cells.  pbc_* != 0 makes that axis
+ * periodic (its length must then be a product of 2, 3, 5, 7);
+ * `pbc_images` (>= 0) periodic images are added per periodic axis on each
+ * side.  Open axes are zero padded to an FFT length >= 2n made of the
+ * factors 2, 3, 5, 7 (Sec. 3.3).  Invalidates m and the demag kernel.
+ * LLG_E_UNSUPPORTED if a padded length exceeds the library's limits
+ * (x: 2048, y and z: 4096).
+ */
+llg_status llg_set_geometry(llg_solver *s, int nx, int ny, int nz,
+                            int pbc_x, int pbc_y, int pbc_z, int pbc_images);
+/* Cell edges dx, dy, dz > 0, metres.  Invalidates the demag kernel. */
+llg_status llg_set_cellsize(llg_solver *s, double dx, double dy, double dz);
+/* Saturation magnetisation Ms > 0 (A/m), exchange stiffness Aex >= 0 (J/m),
+ * damping alpha >= 0 (Eq. 1 and Eq. 3). */
+llg_status llg_set_material(llg_solver *s, double Ms, double Aex, double alpha);
+/* Uniaxial anisotropy Ku (J/m^3; energy density Ku sin^2 theta, Eq. 4) along
+ * the axis u[3] (need not be normalised; must be non-zero). */
+llg_status llg_set_anisotropy_uniaxial(llg_solver *s, double Ku, const double u[3]);
+/* Uniform applied field B[3] = mu0 H in tesla. */
+llg_status llg_set_applied_field(llg_solver *s, const double B[3]);
+/* Temperature T >= 0 (K) and the 64-bit seed of the thermal field of Eq. 6.
+ * The Gaussian vector eta of a cell at a step comes from Philox4x32-10
+ * (Salmon et al., SC'11) with key (seed lo, seed hi) and counter
+ * (cell index, step lo, step hi, 0), Box-Muller on 24-bit uniforms; it is
+ * drawn once per step and held across the stages of that step.  The thermal
+ * field is only applied by fixed-step integration (llg_step). */
+llg_status llg_set_temperature(llg_solver *s, double T, uint64_t seed);
+/* Mask of LLG_TERM_* bits that H_eff includes (default LLG_TERM_ALL). */
+llg_status llg_set_terms(llg_solver *s, int mask);
+
+/* ---- state ------------------------------------------------------------------
+ * llg_set_m: unit vectors, layout above.  LLG_E_ARG if some | |m| - 1 | > 1e-3
+ * or a value is not finite; otherwise the vectors are renormalised.  Resets
+ * time, step counters and statistics.
+ */
+llg_status llg_set_m(llg_solver *s, const float *m, llg_mem where);
+llg_status llg_get_m(llg_solver *s, float *m, llg_mem where);
+/* Effective field H_eff (A/m) of the current m, layout above (Sec. 2.1).
+ * The thermal term, if enabled, uses the step size of the last llg_step
+ * call and the current step counter. */
+llg_status llg_eval_heff(llg_solver *s, float *h_out, llg_mem where);
+
+/* ---- time integration (Sec. 2.2) --------------------------------------------
+ * llg_step: `nsteps` fixed steps of size dt (s) with LLG_EULER, LLG_HEUN or
+ * LLG_RK4.  Every stage input and every new state is renormalised.
+ * LLG_E_DIVERGED if a NaN/Inf appears.
+ */
+llg_status llg_step(llg_solver *s, llg_method method, double dt, int64_t nsteps);
+/* llg_run: adaptive LLG_RKDP45 from the current time to t_end (s).  An
+ * attempt is accepted when max over cells |m5 - m4| <= max_err; the next
+ * step is dt * clamp(0.9 (max_err/err)^(1/5), 0.2, 5); the last step lands
+ * on t_end; dt0 is the first attempted step.  The controller runs on the
+ * device: attempts are replayed from a captured HIP graph and the host only
+ * polls the done flag.  LLG_E_DIVERGED if the step falls below 1e-18 s or a
+ * NaN/Inf appears.  `out` may be NULL. */
+llg_status llg_run(llg_solver *s, llg_method method, double t_end, double max_err,
+                   double dt0, llg_stats *out);
+/* As llg_run but stops after at most `max_attempts` attempts (for timing a
+ * fixed amount of work); t may then be < t_end. */
+llg_status llg_run_attempts(llg_solver *s, double t_end, double max_err, double dt0,
+                            int64_t max_attempts, llg_stats *out);
+llg_status llg_get_stats(llg_solver *s, llg_stats *out);
+/* Copies up to `cap` recorded adaptive attempts (oldest first, since the last
+ * llg_set_m) into `out` (host memory) and stores their number in *n. */
+llg_status llg_get_attempts(llg_solver *s, llg_attempt *out, int64_t cap, int64_t *n);
+
+/* ---- measurement -------------------------------------------------------------
+ * llg_profile_evals: runs `n` H_eff evaluations back to back on the solver's
+ * stream (forward x pass, spectral pass(es), inverse x pass with the local
+ * terms; output kept on the device) and reports, from HIP events recorded on
+ * that stream around each kernel, the mean duration in milliseconds of each
+ * kernel kind in ms_out[0..n_kinds-1] (0: forward x pass, 1: spectral pass
+ * incl. multiply (2D) or the z pass (3D), 2: inverse x pass with local
+ * terms, 3: y forward pass (3D), 4: y inverse pass (3D)) and the total
+ * wall time in *total_ms.  `n_kinds` must be >= 5.
+ */
+llg_status llg_profile_evals(llg_solver *s, int n, double *ms_out, int n_kinds, double *total_ms);
+/* Algorithmic HBM bytes per evaluation of each kernel kind (same order as
+ * llg_profile_evals), from the sizes of what it must read and write. */
+llg_status llg_kernel_bytes(llg_solver *s, double *bytes_out, int n_kinds);
+
+/* ---- diagnostics ------------------------------------------------------------
+ * llg_fft_roundtrip: forward then inverse FP32 FFT, by the library's own FFT
+ * kernels, of `batch` complex vectors of length n (interleaved re, im float32
+ * in host memory, overwritten in place, result divided by n).  n must be a
+ * product of 2, 3, 5, 7 not above 4096.  For checking the FFT alone.
+ */
+llg_status llg_fft_roundtrip(llg_solver *s, float *data, int n, int batch, int inverse_only);
+/* llg_demag_tensor: the FP64 real-space kernel entries (the cell-averaged
+ * tensor plus periodic images) the library built, for `count` integer cell
+ * offsets (di, dj, dk) given in host memory; writes 6*count doubles (xx, yy,
+ * zz, xy, xz, yz per offset) to `out` (host).  Offsets must lie within the
+ * convolution range (|d| < n along open axes). */
+llg_status llg_demag_tensor(llg_solver *s, const int32_t *offsets, int64_t count, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LLG_H */

@@ -1,0 +1,255 @@
+"""Python binding of the MI355X finite-difference Landau-Lifshitz library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libllg.so`` (built in-tree by ``build.py``); the names follow
+the C ABI of ``include/llg.h``.  Arrays are float32 of shape (3, nz, ny, nx),
+x fastest, either numpy arrays (host) or torch CUDA tensors (device).  The
+library raises if it is not built; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libllg.so")
+
+LLG_OK, LLG_E_ARG, LLG_E_STATE, LLG_E_NOMEM, LLG_E_DEVICE, LLG_E_UNSUPPORTED, LLG_E_DIVERGED = range(7)
+STATUS_NAMES = ["LLG_OK", "LLG_E_ARG", "LLG_E_STATE", "LLG_E_NOMEM", "LLG_E_DEVICE",
+                "LLG_E_UNSUPPORTED", "LLG_E_DIVERGED"]
+LLG_EULER, LLG_HEUN, LLG_RK4, LLG_RKDP45 = range(4)
+METHODS = {"euler": LLG_EULER, "heun": LLG_HEUN, "rk4": LLG_RK4, "rkdp45": LLG_RKDP45}
+LLG_HOST, LLG_DEVICE = 0, 1
+TERM_DEMAG, TERM_EXCHANGE, TERM_ANISOTROPY, TERM_ZEEMAN, TERM_THERMAL = 1, 2, 4, 8, 16
+TERM_ALL = 31
+TERM_BITS = {"demag": TERM_DEMAG, "exchange": TERM_EXCHANGE, "anisotropy": TERM_ANISOTROPY,
+             "zeeman": TERM_ZEEMAN, "thermal": TERM_THERMAL}
+KERNEL_KINDS = ("row_fwd", "spectral", "row_inv", "y_fwd", "y_inv")
+
+
+class LLGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES[code] if 0 <= code < 7 else code}: {msg}")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double), ("dt_next", ctypes.c_double),
+                ("max_err", ctypes.c_double), ("steps", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("evals", ctypes.c_int64), ("health", ctypes.c_int32), ("done", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Attempt(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("err", ctypes.c_float), ("accepted", ctypes.c_int32)]
+
+
+_lib = None
+
+# exported symbols of include/llg.h with their argument and result types
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "llg_create": ([ctypes.c_int, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "llg_destroy": ([_P], None),
+    "llg_last_error": ([_P], ctypes.c_char_p),
+    "llg_set_geometry": ([_P] + [ctypes.c_int] * 7, ctypes.c_int),
+    "llg_set_cellsize": ([_P] + [ctypes.c_double] * 3, ctypes.c_int),
+    "llg_set_material": ([_P] + [ctypes.c_double] * 3, ctypes.c_int),
+    "llg_set_anisotropy_uniaxial": ([_P, ctypes.c_double, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "llg_set_applied_field": ([_P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "llg_set_temperature": ([_P, ctypes.c_double, ctypes.c_uint64], ctypes.c_int),
+    "llg_set_terms": ([_P, ctypes.c_int], ctypes.c_int),
+    "llg_set_m": ([_P, _P, ctypes.c_int], ctypes.c_int),
+    "llg_get_m": ([_P, _P, ctypes.c_int], ctypes.c_int),
+    "llg_eval_heff": ([_P, _P, ctypes.c_int], ctypes.c_int),
+    "llg_step": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_int64], ctypes.c_int),
+    "llg_run": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                 ctypes.POINTER(Stats)], ctypes.c_int),
+    "llg_run_attempts": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                          ctypes.POINTER(Stats)], ctypes.c_int),
+    "llg_get_stats": ([_P, ctypes.POINTER(Stats)], ctypes.c_int),
+    "llg_get_attempts": ([_P, ctypes.POINTER(Attempt), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
+                         ctypes.c_int),
+    "llg_profile_evals": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "llg_kernel_bytes": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
+    "llg_fft_roundtrip": ([_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "llg_demag_tensor": ([_P, _P, ctypes.c_int64, _P], ctypes.c_int),
+}
+EXPORTS = tuple(_SIGNATURES)
+
+
+def load(path=LIB_PATH):
+    """Loads libllg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1102_3069_amd/build.py "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _arr3(v):
+    return (ctypes.c_double * 3)(*[float(x) for x in v])
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+class Solver:
+    """One solver on one HIP device (see include/llg.h for every call)."""
+
+    def __init__(self, device=0, stream=None):
+        self._lib = load()
+        h = _P()
+        rc = self._lib.llg_create(int(device), _P(stream) if stream else None, ctypes.byref(h))
+        if rc != LLG_OK:
+            raise LLGError(rc, "llg_create failed")
+        self._h = h
+        self.n = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.llg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != LLG_OK:
+            raise LLGError(rc, self._lib.llg_last_error(self._h).decode())
+
+    # ---- problem ----------------------------------------------------------
+    def set_geometry(self, n, pbc=(False, False, False), images=10):
+        nx, ny, nz = (int(v) for v in n)
+        self._chk(self._lib.llg_set_geometry(self._h, nx, ny, nz, int(bool(pbc[0])), int(bool(pbc[1])),
+                                             int(bool(pbc[2])), int(images)))
+        self.n = (nx, ny, nz)
+
+    def set_cellsize(self, cell):
+        self._chk(self._lib.llg_set_cellsize(self._h, *[float(c) for c in cell]))
+
+    def set_material(self, Ms, Aex, alpha):
+        self._chk(self._lib.llg_set_material(self._h, float(Ms), float(Aex), float(alpha)))
+
+    def set_anisotropy_uniaxial(self, Ku, u):
+        self._chk(self._lib.llg_set_anisotropy_uniaxial(self._h, float(Ku), _arr3(u)))
+
+    def set_applied_field(self, B):
+        self._chk(self._lib.llg_set_applied_field(self._h, _arr3(B)))
+
+    def set_temperature(self, T, seed):
+        self._chk(self._lib.llg_set_temperature(self._h, float(T), int(seed) & 0xFFFFFFFFFFFFFFFF))
+
+    def set_terms(self, terms):
+        mask = terms if isinstance(terms, int) else sum(TERM_BITS[t] for t in terms)
+        self._chk(self._lib.llg_set_terms(self._h, int(mask)))
+
+    def set_problem(self, prob):
+        """Applies a problem dict (keys as in workloads.py)."""
+        self.set_geometry(prob["n"], prob.get("pbc", (False,) * 3), prob.get("images", 10))
+        self.set_cellsize(prob["cell"])
+        self.set_material(prob["Ms"], prob["Aex"], prob["alpha"])
+        self.set_anisotropy_uniaxial(prob.get("Ku", 0.0), prob.get("u", (1.0, 0.0, 0.0)))
+        self.set_applied_field(prob.get("B", (0.0, 0.0, 0.0)))
+        self.set_temperature(prob.get("T", 0.0), prob.get("seed", 0))
+        terms = prob.get("terms")
+        self.set_terms(TERM_ALL if terms is None else terms)
+
+    # ---- state --------------------------------------------------------------
+    def _shape(self):
+        nx, ny, nz = self.n
+        return (3, nz, ny, nx)
+
+    def set_m(self, m):
+        if _is_torch(m) and m.is_cuda:
+            assert m.dtype.__str__() == "torch.float32" and m.is_contiguous()
+            self._chk(self._lib.llg_set_m(self._h, _P(m.data_ptr()), LLG_DEVICE))
+        else:
+            a = np.ascontiguousarray(m, dtype=np.float32).reshape(self._shape())
+            self._chk(self._lib.llg_set_m(self._h, a.ctypes.data_as(_P), LLG_HOST))
+
+    def get_m(self, out=None):
+        if out is not None and _is_torch(out) and out.is_cuda:
+            self._chk(self._lib.llg_get_m(self._h, _P(out.data_ptr()), LLG_DEVICE))
+            return out
+        a = np.empty(self._shape(), dtype=np.float32)
+        self._chk(self._lib.llg_get_m(self._h, a.ctypes.data_as(_P), LLG_HOST))
+        return a
+
+    def eval_heff(self, out=None):
+        if out is not None and _is_torch(out) and out.is_cuda:
+            self._chk(self._lib.llg_eval_heff(self._h, _P(out.data_ptr()), LLG_DEVICE))
+            return out
+        a = np.empty(self._shape(), dtype=np.float32)
+        self._chk(self._lib.llg_eval_heff(self._h, a.ctypes.data_as(_P), LLG_HOST))
+        return a
+
+    # ---- integration ---------------------------------------------------------
+    def step(self, method, dt, nsteps=1):
+        self._chk(self._lib.llg_step(self._h, METHODS[method], float(dt), int(nsteps)))
+
+    def run(self, t_end, max_err=1e-5, dt0=1e-14):
+        st = Stats()
+        self._chk(self._lib.llg_run(self._h, LLG_RKDP45, float(t_end), float(max_err), float(dt0),
+                                    ctypes.byref(st)))
+        return st.as_dict()
+
+    def run_attempts(self, t_end, max_err, dt0, max_attempts):
+        st = Stats()
+        self._chk(self._lib.llg_run_attempts(self._h, float(t_end), float(max_err), float(dt0),
+                                             int(max_attempts), ctypes.byref(st)))
+        return st.as_dict()
+
+    def stats(self):
+        st = Stats()
+        self._chk(self._lib.llg_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def attempts(self, cap=1 << 20):
+        buf = (Attempt * cap)()
+        n = ctypes.c_int64()
+        self._chk(self._lib.llg_get_attempts(self._h, buf, cap, ctypes.byref(n)))
+        return [(buf[i].dt, float(buf[i].err), bool(buf[i].accepted)) for i in range(n.value)]
+
+    # ---- measurement and diagnostics -----------------------------------------
+    def profile_evals(self, n):
+        ms = (ctypes.c_double * 5)()
+        tot = ctypes.c_double()
+        self._chk(self._lib.llg_profile_evals(self._h, int(n), ms, 5, ctypes.byref(tot)))
+        return dict(zip(KERNEL_KINDS, list(ms))), tot.value
+
+    def kernel_bytes(self):
+        b = (ctypes.c_double * 5)()
+        self._chk(self._lib.llg_kernel_bytes(self._h, b, 5))
+        return dict(zip(KERNEL_KINDS, list(b)))
+
+    def fft_roundtrip(self, data, inverse_only=False):
+        """data: complex64 array (batch, n); returns the library's
+        forward+inverse (or inverse only) transform divided by n."""
+        a = np.ascontiguousarray(data, dtype=np.complex64)
+        batch, n = a.shape
+        self._chk(self._lib.llg_fft_roundtrip(self._h, a.ctypes.data_as(_P), int(n), int(batch),
+                                              int(bool(inverse_only))))
+        return a
+
+    def demag_tensor(self, offsets):
+        o = np.ascontiguousarray(offsets, dtype=np.int32).reshape(-1, 3)
+        out = np.empty((o.shape[0], 6), dtype=np.float64)
+        self._chk(self._lib.llg_demag_tensor(self._h, o.ctypes.data_as(_P), o.shape[0],
+                                             out.ctypes.data_as(_P)))
+        return out

@@ -1,0 +1,155 @@
+// Internal types of the solver library: problem geometry on the FFT grid,
+// reduced-unit coefficients, the device-resident integrator state and the
+// argument blocks of the hot-path kernels, plus the launchers the host
+// runtime calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+#include "llg.h"
+
+namespace llg {
+
+// Geometry of the cell grid and of the convolution (FFT) grid.
+//   rows  = ny*nz x-rows of nx cells, row r = k*ny + j
+//   P*    = FFT length per axis (2n or more on open axes, n on periodic ones)
+//   nkx   = Px/2 + 1 retained x frequencies (real-to-complex)
+//   nkxp  = row stride of the spectrum buffers (nkx rounded up to 16)
+struct Grid {
+    int nx, ny, nz;
+    int nrows, ncells;
+    int pbc[3];
+    int Px, Py, Pz;
+    int nkx, nkxp;
+    int split_y, split_z;   // 1 on an open axis: even/odd half transforms
+};
+
+// Coefficients in reduced units: fields are divided by Ms, time is scaled by
+// gamma0*Ms (so dm/dtau = -1/(1+alpha^2) (m x h + alpha m x (m x h))).
+struct Phys {
+    float cex[3];     // 2A/(mu0 Ms^2 d_a^2): exchange coupling per axis
+    float ku;         // 2Ku/(mu0 Ms^2)
+    float u[3];       // anisotropy axis (unit)
+    float hz[3];      // applied field B/(mu0 Ms)
+    float alpha;
+    float llpre;      // -1/(1+alpha^2)
+    float sig_th;     // thermal sigma/Ms for the current step size (0: off)
+    float Ms;         // A/m, for SI output
+    uint32_t seed_lo, seed_hi;
+    int demag_on;
+};
+
+// Integrator state kept on the device so that the adaptive controller and
+// the buffer swaps run without the host.
+struct DevState {
+    int cur;              // which of the two state buffers holds m
+    int done;             // adaptive: reached t_end / diverged; kernels exit early
+    int health;           // bit 0: NaN/Inf seen; bit 1: step below dt_min
+    uint32_t err_bits;    // max error of the current attempt (float bits)
+    int clipped;          // the pending attempt was shortened to land on t_end
+    int pad0;
+    double t, dt, dt_next, t_end, tol, dt_min, gms;
+    double last_err;
+    float dtau;           // dt * gamma0 * Ms
+    float pad1;
+    long long step;       // accepted steps (thermal draw counter)
+    long long nsteps, nrej, nevals, nattempt;
+    long long log_cap;
+    llg_attempt* log;
+};
+
+// A buffer argument that may follow the state-buffer swap:
+// sel 0 -> p[0]; sel 1 -> p[cur]; sel 2 -> p[cur ^ 1].
+struct BufRef {
+    float* p[2];
+    int sel;
+};
+__host__ __device__ inline BufRef bref(float* p) { BufRef r; r.p[0] = p; r.p[1] = p; r.sel = 0; return r; }
+__host__ __device__ inline BufRef bref_cur(float* a, float* b, int which) {
+    BufRef r; r.p[0] = a; r.p[1] = b; r.sel = which; return r;
+}
+__device__ __forceinline__ float* resolve(const BufRef& r, int cur) {
+    return r.sel == 0 ? r.p[0] : r.p[r.sel == 1 ? cur : (cur ^ 1)];
+}
+
+enum RowMode {
+    ROW_EVAL = 0,    // write H_eff (A/m)
+    ROW_STAGE = 1,   // k_s, next stage input, its forward x transform
+    ROW_ERROR = 2,   // k_s (last stage) and the embedded error estimate
+    ROW_KONLY = 3    // k_s only
+};
+
+constexpr int kMaxK = 7;
+
+// What the inverse x pass does after computing H_eff.
+struct StageArgs {
+    int mode;
+    int nk;                  // number of k's in the combination (incl. the current one)
+    float a[kMaxK];          // combination weights of k_1..k_nk (times dtau)
+    float e[kMaxK];          // error weights (ROW_ERROR)
+    BufRef m_in;             // stage input m_s
+    BufRef m0;               // state at the start of the step
+    BufRef m_out;            // next stage input / new state
+    BufRef k_out;            // where k_s goes (p[0] == nullptr: nowhere)
+    BufRef kprev[kMaxK];     // k_1 .. k_{nk-1}
+    float* h_out;            // ROW_EVAL output
+};
+
+// Forward x pass prologue: either plain m, or m_out = normalize(m0 + dtau a1 k1).
+struct FwdArgs {
+    BufRef m_in;             // plain input (combine == 0)
+    int combine;
+    float a1;
+    BufRef m0, k1, m_out;
+};
+
+// Column (y or z) pass.
+enum ColMode { COL_FWD = 0, COL_FULL = 1, COL_INV = 2 };
+
+struct ColArgs {
+    const float2* in;
+    float2* out;
+    long long cs_in, os_in, as_in;     // strides (complex elements)
+    long long cs_out, os_out, as_out;
+    int nouter, nkx, W, ntiles;
+    int n_in, n_out, P, split;
+    FftPlan plan;                      // length P/2 (split) or P
+    const float2* tw;                  // exp(-2 pi i m / P), m < P
+    // multiply (COL_FULL): kernel spectrum K[comp][o'][kx][a'], mirror
+    // compressed along the multiply axis a and the other axis o.
+    const float* K;
+    int ncomp;                         // 4 (2D: xx,yy,zz,xy) or 6
+    int Pa, Po, na_c, no_c;            // lengths and compressed extents
+    int o_split;                       // 3D: the outer (y) index is in split order
+    int sign_a[6], sign_o[6];
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+hipError_t launch_row_fwd(const Grid& g, const Phys& p, const FftPlan& px, const float2* twx,
+                          float2* S, const FwdArgs& fa, DevState* st, hipStream_t s);
+hipError_t launch_row_inv(const Grid& g, const Phys& p, const FftPlan& px, const float2* twx,
+                          float2* S, const StageArgs& sa, DevState* st, hipStream_t s);
+hipError_t launch_col(const ColArgs& a, DevState* st, int mode, hipStream_t s);
+hipError_t launch_ctrl_fixed(DevState* st, int evals, double dt, hipStream_t s);
+hipError_t launch_ctrl_dp45(DevState* st, hipStream_t s);
+hipError_t launch_state_add_evals(DevState* st, int evals, hipStream_t s);
+hipError_t launch_normalize_check(float* m, int ncells, int* bad, hipStream_t s);
+hipError_t launch_fft_test(float2* data, int n, int batch, const FftPlan& pl, const float2* tw,
+                           int inverse_only, hipStream_t s);
+
+// ---- demag tensor (tensor.hip) --------------------------------------------------
+struct TensorGeom {
+    int n[3];
+    int P[3];
+    int pbc[3];
+    int images;
+    double d[3];       // cell edges scaled by the largest one
+};
+hipError_t build_kernel_spectrum(const Grid& g, const TensorGeom& tg, float* K, double* resid_out,
+                                 hipStream_t s);
+hipError_t tensor_at_offsets(const TensorGeom& tg, const int32_t* offs_dev, long long count,
+                             double* out_dev, hipStream_t s);
+
+}  // namespace llg

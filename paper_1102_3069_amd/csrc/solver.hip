@@ -1,0 +1,1069 @@
+// Host runtime of the solver: the C ABI of llg.h.
+//
+// The host validates parameters, converts SI input to the reduced units the
+// kernels use (fields / Ms, time * gamma0 Ms; Sec. 3.3 of the paper keeps
+// FP32 values O(1) this way), sizes the FFT grid, builds the FP64 demag
+// spectrum once per geometry, and launches the hot-path kernels on its own
+// HIP stream.  Integration steps are captured once into HIP graphs and
+// replayed; the adaptive controller, the state-buffer swap and the attempt
+// log live on the device, so the host only polls a done flag.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace llg;
+
+namespace {
+
+const double kMu0 = 4.0e-7 * M_PI;
+const double kGammaLL = 1.7595e11;
+const double kGamma0 = kMu0 * kGammaLL;
+const double kBoltzmann = 1.380649e-23;
+const double kDtMin = 1e-18;
+const int kMaxPx = 2048;
+const int kMaxHalf = 2048;
+
+// Butcher tableaux (rows of A for stages 2..S, then b)
+struct Tableau {
+    int S;
+    double A[7][7];
+    double b[7];
+    double bhat[7];
+};
+
+Tableau tab_euler() { Tableau t = {}; t.S = 1; t.b[0] = 1.0; return t; }
+Tableau tab_heun() { Tableau t = {}; t.S = 2; t.A[1][0] = 1.0; t.b[0] = 0.5; t.b[1] = 0.5; return t; }
+Tableau tab_rk4() {
+    Tableau t = {};
+    t.S = 4;
+    t.A[1][0] = 0.5; t.A[2][1] = 0.5; t.A[3][2] = 1.0;
+    t.b[0] = 1.0 / 6.0; t.b[1] = 1.0 / 3.0; t.b[2] = 1.0 / 3.0; t.b[3] = 1.0 / 6.0;
+    return t;
+}
+// Dormand & Prince (1980) RK5(4)7M; row 6 equals b (first same as last)
+Tableau tab_dp45() {
+    Tableau t = {};
+    t.S = 7;
+    t.A[1][0] = 1.0 / 5.0;
+    t.A[2][0] = 3.0 / 40.0; t.A[2][1] = 9.0 / 40.0;
+    t.A[3][0] = 44.0 / 45.0; t.A[3][1] = -56.0 / 15.0; t.A[3][2] = 32.0 / 9.0;
+    t.A[4][0] = 19372.0 / 6561.0; t.A[4][1] = -25360.0 / 2187.0; t.A[4][2] = 64448.0 / 6561.0;
+    t.A[4][3] = -212.0 / 729.0;
+    t.A[5][0] = 9017.0 / 3168.0; t.A[5][1] = -355.0 / 33.0; t.A[5][2] = 46732.0 / 5247.0;
+    t.A[5][3] = 49.0 / 176.0; t.A[5][4] = -5103.0 / 18656.0;
+    t.A[6][0] = 35.0 / 384.0; t.A[6][1] = 0.0; t.A[6][2] = 500.0 / 1113.0; t.A[6][3] = 125.0 / 192.0;
+    t.A[6][4] = -2187.0 / 6784.0; t.A[6][5] = 11.0 / 84.0;
+    for (int j = 0; j < 6; ++j) t.b[j] = t.A[6][j];
+    t.b[6] = 0.0;
+    t.bhat[0] = 5179.0 / 57600.0; t.bhat[1] = 0.0; t.bhat[2] = 7571.0 / 16695.0;
+    t.bhat[3] = 393.0 / 640.0; t.bhat[4] = -92097.0 / 339200.0; t.bhat[5] = 187.0 / 2100.0;
+    t.bhat[6] = 1.0 / 40.0;
+    return t;
+}
+
+bool good_len(int L) {
+    if (L < 1) return false;
+    for (int f : {2, 3, 5, 7})
+        while (L % f == 0) L /= f;
+    return L == 1;
+}
+
+// smallest even FFT length >= 2n made of 2, 3, 5, 7 (open axis)
+int pad_len(int n) {
+    int L = 2 * n;
+    while (!good_len(L)) L += 2;
+    return L;
+}
+
+bool make_plan(int L, FftPlan& p) {
+    p.L = L;
+    p.ns = 0;
+    int n = L;
+    const int order[6] = {8, 4, 2, 3, 5, 7};
+    for (int r : order)
+        while (n % r == 0) {
+            if (p.ns >= kMaxStages) return false;
+            p.rad[p.ns++] = r;
+            n /= r;
+        }
+    return n == 1;
+}
+
+struct Graph {
+    hipGraphExec_t exec = nullptr;
+    int method = -1;
+    double dt = 0.0;
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        method = -1;
+        dt = 0.0;
+    }
+};
+
+}  // namespace
+
+struct llg_solver {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t user = nullptr;
+    hipEvent_t sync_ev = nullptr;
+    std::string err = "";
+    // problem
+    int nx = 0, ny = 0, nz = 0;
+    int pbc[3] = {0, 0, 0};
+    int images = 10;
+    double dx = 0, dy = 0, dz = 0;
+    double Ms = 0, Aex = 0, alpha = 0;
+    double Ku = 0, u[3] = {1, 0, 0};
+    double B[3] = {0, 0, 0};
+    double T = 0;
+    uint64_t seed = 0;
+    int terms = LLG_TERM_ALL;
+    bool have_geom = false, have_cell = false, have_mat = false, have_m = false;
+    // plan
+    Grid g = {};
+    FftPlan px = {}, py = {}, pz = {};
+    float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
+    int wy = 1, wz = 1;       // column tile widths
+    // device buffers
+    float* K = nullptr;
+    bool K_valid = false;
+    double K_resid = 0.0;
+    float2* S = nullptr;
+    float2* Sy = nullptr;
+    float* mbuf[2] = {nullptr, nullptr};
+    float* ms[2] = {nullptr, nullptr};
+    float* kb[6] = {};
+    float* kfs[2] = {nullptr, nullptr};
+    float* hbuf = nullptr;
+    DevState* st = nullptr;
+    int* dflag = nullptr;
+    llg_attempt* log = nullptr;
+    long long log_cap = 0;
+    bool spec_valid = false;   // S holds the forward x transform of m
+    bool k1_valid = false;     // kfs[cur] holds f(m) for the adaptive method
+    double last_dt = 0.0;
+    Graph gfix, gdp;
+};
+
+namespace {
+
+llg_status fail(llg_solver* s, llg_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (s) s->err = buf;
+    return code;
+}
+
+#define HIPCHK(s, x)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(s, e_ == hipErrorOutOfMemory ? LLG_E_NOMEM : LLG_E_DEVICE, "%s: %s (%s:%d)", \
+                        #x, hipGetErrorString(e_), __FILE__, __LINE__);                           \
+    } while (0)
+
+void free_dev(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+void invalidate_graphs(llg_solver* s) {
+    s->gfix.reset();
+    s->gdp.reset();
+}
+
+void free_buffers(llg_solver* s) {
+    invalidate_graphs(s);
+    free_dev(s->K); s->K = nullptr;
+    free_dev(s->S); s->S = nullptr;
+    free_dev(s->Sy); s->Sy = nullptr;
+    for (auto& p : s->mbuf) { free_dev(p); p = nullptr; }
+    for (auto& p : s->ms) { free_dev(p); p = nullptr; }
+    for (auto& p : s->kb) { free_dev(p); p = nullptr; }
+    for (auto& p : s->kfs) { free_dev(p); p = nullptr; }
+    free_dev(s->hbuf); s->hbuf = nullptr;
+    free_dev(s->twx); s->twx = nullptr;
+    free_dev(s->twy); s->twy = nullptr;
+    free_dev(s->twz); s->twz = nullptr;
+    free_dev(s->log); s->log = nullptr;
+    s->K_valid = false;
+    s->spec_valid = false;
+    s->k1_valid = false;
+}
+
+hipError_t make_tw(int L, float2** out) {
+    std::vector<float2> h(L);
+    for (int m = 0; m < L; ++m) {
+        const double a = -2.0 * M_PI * (double)m / (double)L;
+        h[m].x = (float)cos(a);
+        h[m].y = (float)sin(a);
+    }
+    hipError_t e = hipMalloc(out, sizeof(float2) * L);
+    if (e == hipSuccess) e = hipMemcpy(*out, h.data(), sizeof(float2) * L, hipMemcpyHostToDevice);
+    return e;
+}
+
+// widest column tile whose FFT buffer and kept values fit 12 elements per
+// thread (the 24-element variant is kept for lengths that need it)
+int col_width(int Lh, int n) {
+    const int m = Lh > n ? Lh : n;
+    for (int W : {16, 8, 4, 2, 1})
+        if (3 * W * m <= 12 * 256) return W;
+    return 3 * m <= 24 * 256 ? 1 : 0;
+}
+
+bool two_d(const llg_solver* s) { return s->nz == 1; }
+
+Phys make_phys(const llg_solver* s, double dt_thermal) {
+    Phys p = {};
+    const double Ms2 = s->Ms * s->Ms;
+    const double d[3] = {s->dx, s->dy, s->dz};
+    for (int a = 0; a < 3; ++a)
+        p.cex[a] = (s->terms & LLG_TERM_EXCHANGE) ? (float)(2.0 * s->Aex / (kMu0 * Ms2 * d[a] * d[a])) : 0.f;
+    const double un = sqrt(s->u[0] * s->u[0] + s->u[1] * s->u[1] + s->u[2] * s->u[2]);
+    p.ku = (s->terms & LLG_TERM_ANISOTROPY) ? (float)(2.0 * s->Ku / (kMu0 * Ms2)) : 0.f;
+    for (int a = 0; a < 3; ++a) {
+        p.u[a] = (float)(s->u[a] / un);
+        p.hz[a] = (s->terms & LLG_TERM_ZEEMAN) ? (float)(s->B[a] / (kMu0 * s->Ms)) : 0.f;
+    }
+    p.alpha = (float)s->alpha;
+    p.llpre = (float)(-1.0 / (1.0 + s->alpha * s->alpha));
+    p.sig_th = 0.f;
+    if ((s->terms & LLG_TERM_THERMAL) && s->T > 0.0 && dt_thermal > 0.0) {
+        const double V = s->dx * s->dy * s->dz;
+        const double sig = sqrt(2.0 * s->alpha * kBoltzmann * s->T / (kGamma0 * kMu0 * s->Ms * V * dt_thermal));
+        p.sig_th = (float)(sig / s->Ms);
+    }
+    p.Ms = (float)s->Ms;
+    p.seed_lo = (uint32_t)(s->seed & 0xffffffffu);
+    p.seed_hi = (uint32_t)(s->seed >> 32);
+    p.demag_on = (s->terms & LLG_TERM_DEMAG) ? 1 : 0;
+    return p;
+}
+
+llg_status enter(llg_solver* s) {
+    if (!s) return LLG_E_ARG;
+    s->err.clear();
+    HIPCHK(s, hipSetDevice(s->device));
+    if (s->user) {
+        HIPCHK(s, hipEventRecord(s->sync_ev, s->user));
+        HIPCHK(s, hipStreamWaitEvent(s->stream, s->sync_ev, 0));
+    }
+    return LLG_OK;
+}
+
+llg_status ready(llg_solver* s, bool need_m) {
+    if (!s->have_geom) return fail(s, LLG_E_STATE, "geometry not set");
+    if (!s->have_cell) return fail(s, LLG_E_STATE, "cell size not set");
+    if (!s->have_mat) return fail(s, LLG_E_STATE, "material not set");
+    if (need_m && !s->have_m) return fail(s, LLG_E_STATE, "magnetisation not set");
+    return LLG_OK;
+}
+
+llg_status ensure_kernel(llg_solver* s) {
+    if (s->K_valid || !(s->terms & LLG_TERM_DEMAG)) return LLG_OK;
+    TensorGeom tg = {};
+    const double d[3] = {s->dx, s->dy, s->dz};
+    const double dm = fmax(d[0], fmax(d[1], d[2]));
+    const int n[3] = {s->nx, s->ny, s->nz};
+    const int P[3] = {s->g.Px, s->g.Py, s->g.Pz};
+    for (int a = 0; a < 3; ++a) {
+        tg.n[a] = n[a];
+        tg.P[a] = P[a];
+        tg.pbc[a] = s->pbc[a];
+        tg.d[a] = d[a] / dm;
+    }
+    tg.images = s->images;
+    double resid = 0.0;
+    HIPCHK(s, build_kernel_spectrum(s->g, tg, s->K, &resid, s->stream));
+    s->K_resid = resid;
+    if (!(resid <= 1e-9))
+        return fail(s, LLG_E_DEVICE, "demag kernel spectrum is not real (residue %g)", resid);
+    s->K_valid = true;
+    return LLG_OK;
+}
+
+ColArgs col_base(const llg_solver* s) {
+    ColArgs a = {};
+    a.nkx = s->g.nkx;
+    return a;
+}
+
+// the spectral pass(es) between the forward and the inverse x transform
+llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
+    const Grid& g = s->g;
+    const long long nkxp = g.nkxp;
+    if (two_d(s)) {
+        ColArgs a = col_base(s);
+        a.in = s->S; a.out = s->S;
+        a.cs_in = a.cs_out = (long long)g.nrows * nkxp;
+        a.os_in = a.os_out = 0;
+        a.as_in = a.as_out = nkxp;
+        a.nouter = 1;
+        a.W = s->wy;
+        a.ntiles = (g.nkx + a.W - 1) / a.W;
+        a.n_in = a.n_out = g.ny;
+        a.P = g.Py; a.split = g.split_y; a.plan = s->py; a.tw = s->twy;
+        a.K = s->K; a.ncomp = 4;
+        a.Pa = g.Py; a.Po = 1; a.na_c = g.Py / 2 + 1; a.no_c = 1; a.o_split = 0;
+        const int sa[6] = {1, 1, 1, -1, 1, -1};
+        for (int c = 0; c < 6; ++c) { a.sign_a[c] = sa[c]; a.sign_o[c] = 1; }
+        HIPCHK(s, launch_col(a, s->st, COL_FULL, s->stream));
+        return LLG_OK;
+    }
+    // 3D: y forward, z with product, y inverse
+    ColArgs y = col_base(s);
+    y.W = s->wy;
+    y.ntiles = (g.nkx + y.W - 1) / y.W;
+    y.P = g.Py; y.split = g.split_y; y.plan = s->py; y.tw = s->twy;
+    y.nouter = g.nz;
+    ColArgs yf = y;
+    yf.in = s->S; yf.out = s->Sy;
+    yf.cs_in = (long long)g.nrows * nkxp; yf.os_in = (long long)g.ny * nkxp; yf.as_in = nkxp;
+    yf.cs_out = (long long)g.nz * g.Py * nkxp; yf.os_out = (long long)g.Py * nkxp; yf.as_out = nkxp;
+    yf.n_in = g.ny; yf.n_out = g.Py;
+    HIPCHK(s, launch_col(yf, s->st, COL_FWD, s->stream));
+    if (ev_after_y) HIPCHK(s, hipEventRecord(ev_after_y[0], s->stream));
+    ColArgs z = col_base(s);
+    z.in = s->Sy; z.out = s->Sy;
+    z.cs_in = z.cs_out = (long long)g.nz * g.Py * nkxp;
+    z.os_in = z.os_out = nkxp;
+    z.as_in = z.as_out = (long long)g.Py * nkxp;
+    z.nouter = g.Py;
+    z.W = s->wz;
+    z.ntiles = (g.nkx + z.W - 1) / z.W;
+    z.n_in = z.n_out = g.nz;
+    z.P = g.Pz; z.split = g.split_z; z.plan = s->pz; z.tw = s->twz;
+    z.K = s->K; z.ncomp = 6;
+    z.Pa = g.Pz; z.Po = g.Py; z.na_c = g.Pz / 2 + 1; z.no_c = g.Py / 2 + 1; z.o_split = g.split_y;
+    const int sz_[6] = {1, 1, 1, 1, -1, -1};   // along z: xz, yz odd
+    const int sy_[6] = {1, 1, 1, -1, 1, -1};   // along y: xy, yz odd
+    for (int c = 0; c < 6; ++c) { z.sign_a[c] = sz_[c]; z.sign_o[c] = sy_[c]; }
+    HIPCHK(s, launch_col(z, s->st, COL_FULL, s->stream));
+    if (ev_after_y) HIPCHK(s, hipEventRecord(ev_after_y[1], s->stream));
+    ColArgs yi = y;
+    yi.in = s->Sy; yi.out = s->S;
+    yi.cs_in = (long long)g.nz * g.Py * nkxp; yi.os_in = (long long)g.Py * nkxp; yi.as_in = nkxp;
+    yi.cs_out = (long long)g.nrows * nkxp; yi.os_out = (long long)g.ny * nkxp; yi.as_out = nkxp;
+    yi.n_in = g.Py; yi.n_out = g.ny;
+    HIPCHK(s, launch_col(yi, s->st, COL_INV, s->stream));
+    return LLG_OK;
+}
+
+llg_status launch_fwd_plain(llg_solver* s, int sel) {
+    FwdArgs fa = {};
+    fa.m_in = bref_cur(s->mbuf[0], s->mbuf[1], sel);
+    fa.combine = 0;
+    fa.m0 = fa.m_in; fa.k1 = fa.m_in; fa.m_out = bref(nullptr);
+    const Phys p = make_phys(s, 0.0);
+    HIPCHK(s, launch_row_fwd(s->g, p, s->px, s->twx, s->S, fa, s->st, s->stream));
+    return LLG_OK;
+}
+
+llg_status sync(llg_solver* s) {
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return LLG_OK;
+}
+
+llg_status read_state(llg_solver* s, DevState* h) {
+    HIPCHK(s, hipMemcpyAsync(h, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+    return sync(s);
+}
+
+llg_status write_state(llg_solver* s, const DevState* h) {
+    HIPCHK(s, hipMemcpyAsync(s->st, h, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
+    return sync(s);
+}
+
+// H_eff of m (mbuf[cur]) into `out` (device); tracks spectrum validity
+llg_status eval_into(llg_solver* s, float* out, const Phys& p) {
+    llg_status rc;
+    if (p.demag_on) {
+        if ((rc = launch_fwd_plain(s, 1)) != LLG_OK) return rc;
+        if ((rc = launch_spectral(s)) != LLG_OK) return rc;
+    }
+    StageArgs sa = {};
+    sa.mode = ROW_EVAL;
+    sa.m_in = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+    sa.m0 = sa.m_in;
+    sa.m_out = bref(nullptr);
+    sa.k_out = bref(nullptr);
+    sa.h_out = out;
+    HIPCHK(s, launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream));
+    s->spec_valid = p.demag_on != 0;
+    return LLG_OK;
+}
+
+Tableau tableau_of(llg_method m) {
+    switch (m) {
+        case LLG_EULER: return tab_euler();
+        case LLG_HEUN: return tab_heun();
+        case LLG_RK4: return tab_rk4();
+        default: return tab_dp45();
+    }
+}
+
+// one fixed step of tableau t: S x (spectral + fused row pass) + controller
+llg_status enqueue_fixed_step(llg_solver* s, const Tableau& t, const Phys& p) {
+    llg_status rc;
+    for (int st = 1; st <= t.S; ++st) {
+        if (p.demag_on && (rc = launch_spectral(s)) != LLG_OK) return rc;
+        StageArgs sa = {};
+        sa.mode = ROW_STAGE;
+        sa.m_in = st == 1 ? bref_cur(s->mbuf[0], s->mbuf[1], 1) : bref(s->ms[st % 2]);
+        sa.m0 = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+        sa.m_out = st == t.S ? bref_cur(s->mbuf[0], s->mbuf[1], 2) : bref(s->ms[(st + 1) % 2]);
+        bool needed = false;
+        if (st < t.S) {
+            if (t.b[st - 1] != 0.0) needed = true;
+            for (int r = st; r < t.S; ++r)
+                if (t.A[r][st - 1] != 0.0) needed = true;
+        }
+        sa.k_out = bref(needed ? s->kb[st - 1] : nullptr);
+        sa.nk = st;
+        for (int j = 0; j < st; ++j) sa.a[j] = (float)(st < t.S ? t.A[st][j] : t.b[j]);
+        for (int j = 0; j + 1 < st; ++j) sa.kprev[j] = bref(s->kb[j]);
+        sa.h_out = nullptr;
+        HIPCHK(s, launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream));
+    }
+    HIPCHK(s, launch_ctrl_fixed(s->st, t.S, 0.0, s->stream));
+    return LLG_OK;
+}
+
+// one adaptive Dormand-Prince attempt (FSAL: k1 is the previous k7)
+llg_status enqueue_dp45_attempt(llg_solver* s, const Phys& p) {
+    const Tableau t = tab_dp45();
+    llg_status rc;
+    // k_j buffers: k1 = kfs[cur], k2..k6 = kb[1..5], k7 -> kfs[cur^1]
+    BufRef kref[7];
+    kref[0] = bref_cur(s->kfs[0], s->kfs[1], 1);
+    for (int j = 1; j <= 5; ++j) kref[j] = bref(s->kb[j]);
+    kref[6] = bref_cur(s->kfs[0], s->kfs[1], 2);
+    // stage 2 input: m_2 = normalize(m0 + dtau a21 k1)
+    FwdArgs fa = {};
+    fa.combine = 1;
+    fa.a1 = (float)t.A[1][0];
+    fa.m0 = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+    fa.k1 = kref[0];
+    fa.m_in = fa.m0;
+    fa.m_out = bref(s->ms[0]);
+    HIPCHK(s, launch_row_fwd(s->g, p, s->px, s->twx, s->S, fa, s->st, s->stream));
+    for (int st = 2; st <= 7; ++st) {
+        if (p.demag_on && (rc = launch_spectral(s)) != LLG_OK) return rc;
+        StageArgs sa = {};
+        sa.m0 = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+        sa.m_in = st == 7 ? bref_cur(s->mbuf[0], s->mbuf[1], 2) : bref(s->ms[st % 2 == 0 ? 0 : 1]);
+        sa.k_out = kref[st - 1];
+        sa.nk = st;
+        for (int j = 0; j + 1 < st; ++j) sa.kprev[j] = kref[j];
+        if (st < 7) {
+            sa.mode = ROW_STAGE;
+            sa.m_out = st == 6 ? bref_cur(s->mbuf[0], s->mbuf[1], 2) : bref(s->ms[st % 2 == 0 ? 1 : 0]);
+            for (int j = 0; j < st; ++j) sa.a[j] = (float)t.A[st][j];
+        } else {
+            sa.mode = ROW_ERROR;
+            sa.m_out = bref(nullptr);
+            for (int j = 0; j < 7; ++j) sa.e[j] = (float)(t.b[j] - t.bhat[j]);
+        }
+        HIPCHK(s, launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream));
+    }
+    HIPCHK(s, launch_ctrl_dp45(s->st, s->stream));
+    return LLG_OK;
+}
+
+llg_status capture(llg_solver* s, Graph& gr, llg_status (*body)(llg_solver*, const Tableau&, const Phys&),
+                   const Tableau& t, const Phys& p) {
+    hipGraph_t graph = nullptr;
+    HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    llg_status rc = body(s, t, p);
+    hipError_t e = hipStreamEndCapture(s->stream, &graph);
+    if (rc != LLG_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    HIPCHK(s, e);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(s, e);
+    gr.reset();
+    gr.exec = exec;
+    return LLG_OK;
+}
+
+llg_status dp45_body(llg_solver* s, const Tableau&, const Phys& p) { return enqueue_dp45_attempt(s, p); }
+
+llg_status ensure_k1(llg_solver* s, const Phys& p) {
+    if (s->k1_valid) return LLG_OK;
+    llg_status rc;
+    if (p.demag_on) {
+        if ((rc = launch_fwd_plain(s, 1)) != LLG_OK) return rc;
+        if ((rc = launch_spectral(s)) != LLG_OK) return rc;
+    }
+    StageArgs sa = {};
+    sa.mode = ROW_KONLY;
+    sa.m_in = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+    sa.m0 = sa.m_in;
+    sa.m_out = bref(nullptr);
+    sa.k_out = bref_cur(s->kfs[0], s->kfs[1], 1);
+    HIPCHK(s, launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream));
+    HIPCHK(s, launch_state_add_evals(s->st, 1, s->stream));
+    s->k1_valid = true;
+    return LLG_OK;
+}
+
+llg_status run_adaptive(llg_solver* s, double t_end, double max_err, double dt0, long long max_attempts,
+                        llg_stats* out);
+
+void fill_stats(const DevState& h, llg_stats* out) {
+    out->t = h.t;
+    out->dt = h.dt;
+    out->dt_next = h.dt_next;
+    out->max_err = h.last_err;
+    out->steps = h.nsteps;
+    out->rejected = h.nrej;
+    out->evals = h.nevals;
+    out->health = h.health;
+    out->done = h.done;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+llg_status llg_create(int device, void* hip_stream, llg_solver** out) {
+    if (!out) return LLG_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LLG_E_DEVICE;
+    if (device < 0 || device >= ndev) return LLG_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return LLG_E_DEVICE;
+    llg_solver* s = new llg_solver();
+    s->device = device;
+    s->user = (hipStream_t)hip_stream;
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->sync_ev, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&s->st, sizeof(DevState)) != hipSuccess ||
+        hipMalloc(&s->dflag, sizeof(int)) != hipSuccess) {
+        llg_destroy(s);
+        return LLG_E_DEVICE;
+    }
+    DevState h = {};
+    if (hipMemcpy(s->st, &h, sizeof h, hipMemcpyHostToDevice) != hipSuccess) {
+        llg_destroy(s);
+        return LLG_E_DEVICE;
+    }
+    *out = s;
+    return LLG_OK;
+}
+
+void llg_destroy(llg_solver* s) {
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    free_buffers(s);
+    free_dev(s->st);
+    free_dev(s->dflag);
+    if (s->sync_ev) (void)hipEventDestroy(s->sync_ev);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+const char* llg_last_error(const llg_solver* s) { return s ? s->err.c_str() : "null solver"; }
+
+llg_status llg_set_geometry(llg_solver* s, int nx, int ny, int nz, int pbc_x, int pbc_y, int pbc_z,
+                            int pbc_images) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (nx < 1 || ny < 1 || nz < 1 || pbc_images < 0)
+        return fail(s, LLG_E_ARG, "invalid geometry %d x %d x %d, images %d", nx, ny, nz, pbc_images);
+    const int pb[3] = {pbc_x != 0, pbc_y != 0, pbc_z != 0};
+    const int n[3] = {nx, ny, nz};
+    int P[3];
+    for (int a = 0; a < 3; ++a) {
+        if (pb[a]) {
+            if (!good_len(n[a])) return fail(s, LLG_E_UNSUPPORTED, "periodic length %d is not a product of 2,3,5,7", n[a]);
+            P[a] = n[a];
+        } else {
+            P[a] = pad_len(n[a]);
+        }
+    }
+    if (nz == 1) P[2] = 1;
+    const int split_y = !pb[1], split_z = nz > 1 && !pb[2];
+    const int Ly = split_y ? P[1] / 2 : P[1];
+    const int Lz = split_z ? P[2] / 2 : P[2];
+    if (P[0] > kMaxPx || Ly > kMaxHalf || Lz > kMaxHalf)
+        return fail(s, LLG_E_UNSUPPORTED, "FFT lengths %d x %d x %d exceed this build's limits", P[0], P[1], P[2]);
+    if (P[0] % 2) return fail(s, LLG_E_UNSUPPORTED, "x FFT length must be even (periodic nx odd)");
+    (void)hipStreamSynchronize(s->stream);
+    free_buffers(s);
+    s->have_geom = false;
+    s->have_m = false;
+    s->nx = nx; s->ny = ny; s->nz = nz;
+    for (int a = 0; a < 3; ++a) s->pbc[a] = pb[a];
+    s->images = pbc_images;
+    Grid& g = s->g;
+    g = Grid{};
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    g.nrows = ny * nz;
+    g.ncells = nx * ny * nz;
+    for (int a = 0; a < 3; ++a) g.pbc[a] = pb[a];
+    g.Px = P[0]; g.Py = P[1]; g.Pz = P[2];
+    g.nkx = P[0] / 2 + 1;
+    g.nkxp = (g.nkx + 15) / 16 * 16;
+    g.split_y = split_y;
+    g.split_z = split_z;
+    if (!make_plan(P[0], s->px) || !make_plan(Ly, s->py) || !make_plan(Lz, s->pz))
+        return fail(s, LLG_E_UNSUPPORTED, "cannot factor FFT lengths");
+    s->wy = col_width(Ly, ny);
+    s->wz = col_width(Lz, nz);
+    if (s->wy < 1 || s->wz < 1) return fail(s, LLG_E_UNSUPPORTED, "column pass does not fit");
+    const size_t vec = sizeof(float) * 3 * (size_t)g.ncells;
+    HIPCHK(s, make_tw(P[0], &s->twx));
+    HIPCHK(s, make_tw(P[1], &s->twy));
+    HIPCHK(s, make_tw(P[2], &s->twz));
+    HIPCHK(s, hipMalloc(&s->S, sizeof(float2) * 3 * (size_t)g.nrows * g.nkxp));
+    if (!two_d(s)) HIPCHK(s, hipMalloc(&s->Sy, sizeof(float2) * 3 * (size_t)g.nz * g.Py * g.nkxp));
+    const size_t kcount = two_d(s) ? 4 * (size_t)g.nkx * (g.Py / 2 + 1)
+                                   : 6 * (size_t)(g.Py / 2 + 1) * g.nkx * (g.Pz / 2 + 1);
+    HIPCHK(s, hipMalloc(&s->K, sizeof(float) * kcount));
+    for (auto& p : s->mbuf) HIPCHK(s, hipMalloc(&p, vec));
+    for (auto& p : s->ms) HIPCHK(s, hipMalloc(&p, vec));
+    for (auto& p : s->kb) HIPCHK(s, hipMalloc(&p, vec));
+    for (auto& p : s->kfs) HIPCHK(s, hipMalloc(&p, vec));
+    HIPCHK(s, hipMalloc(&s->hbuf, vec));
+    s->log_cap = 1 << 20;
+    HIPCHK(s, hipMalloc(&s->log, sizeof(llg_attempt) * s->log_cap));
+    s->have_geom = true;
+    return LLG_OK;
+}
+
+llg_status llg_set_cellsize(llg_solver* s, double dx, double dy, double dz) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!(dx > 0 && dy > 0 && dz > 0) || !isfinite(dx) || !isfinite(dy) || !isfinite(dz))
+        return fail(s, LLG_E_ARG, "cell size must be positive");
+    s->dx = dx; s->dy = dy; s->dz = dz;
+    s->have_cell = true;
+    s->K_valid = false;
+    s->spec_valid = false;
+    s->k1_valid = false;
+    invalidate_graphs(s);
+    return LLG_OK;
+}
+
+llg_status llg_set_material(llg_solver* s, double Ms, double Aex, double alpha) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!(Ms > 0) || !(Aex >= 0) || !(alpha >= 0) || !isfinite(Ms) || !isfinite(Aex) || !isfinite(alpha))
+        return fail(s, LLG_E_ARG, "need Ms > 0, Aex >= 0, alpha >= 0");
+    s->Ms = Ms; s->Aex = Aex; s->alpha = alpha;
+    s->have_mat = true;
+    s->k1_valid = false;
+    invalidate_graphs(s);
+    return LLG_OK;
+}
+
+llg_status llg_set_anisotropy_uniaxial(llg_solver* s, double Ku, const double u[3]) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!u || !isfinite(Ku)) return fail(s, LLG_E_ARG, "invalid anisotropy");
+    const double n = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(n > 0) || !isfinite(n)) return fail(s, LLG_E_ARG, "anisotropy axis must be non-zero");
+    s->Ku = Ku;
+    for (int a = 0; a < 3; ++a) s->u[a] = u[a];
+    s->k1_valid = false;
+    invalidate_graphs(s);
+    return LLG_OK;
+}
+
+llg_status llg_set_applied_field(llg_solver* s, const double B[3]) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!B || !isfinite(B[0]) || !isfinite(B[1]) || !isfinite(B[2])) return fail(s, LLG_E_ARG, "invalid field");
+    for (int a = 0; a < 3; ++a) s->B[a] = B[a];
+    s->k1_valid = false;
+    invalidate_graphs(s);
+    return LLG_OK;
+}
+
+llg_status llg_set_temperature(llg_solver* s, double T, uint64_t seed) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!(T >= 0) || !isfinite(T)) return fail(s, LLG_E_ARG, "temperature must be >= 0");
+    s->T = T;
+    s->seed = seed;
+    s->k1_valid = false;
+    invalidate_graphs(s);
+    return LLG_OK;
+}
+
+llg_status llg_set_terms(llg_solver* s, int mask) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (mask & ~LLG_TERM_ALL) return fail(s, LLG_E_ARG, "unknown term bits 0x%x", mask);
+    s->terms = mask;
+    s->k1_valid = false;
+    s->spec_valid = false;
+    invalidate_graphs(s);
+    return LLG_OK;
+}
+
+llg_status llg_set_m(llg_solver* s, const float* m, llg_mem where) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!m) return fail(s, LLG_E_ARG, "null m");
+    if (!s->have_geom) return fail(s, LLG_E_STATE, "geometry not set");
+    const size_t bytes = sizeof(float) * 3 * (size_t)s->g.ncells;
+    HIPCHK(s, hipMemcpyAsync(s->mbuf[0], m, bytes, where == LLG_DEVICE ? hipMemcpyDeviceToDevice
+                                                                        : hipMemcpyHostToDevice, s->stream));
+    int zero = 0, bad = 0;
+    HIPCHK(s, hipMemcpyAsync(s->dflag, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, launch_normalize_check(s->mbuf[0], s->g.ncells, s->dflag, s->stream));
+    HIPCHK(s, hipMemcpyAsync(&bad, s->dflag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    if ((rc = sync(s)) != LLG_OK) return rc;
+    if (bad) {
+        s->have_m = false;
+        return fail(s, LLG_E_ARG, "m is not a field of unit vectors (| |m| - 1 | > 1e-3 or non-finite)");
+    }
+    DevState h = {};
+    h.cur = 0;
+    h.log = s->log;
+    h.log_cap = s->log_cap;
+    h.gms = kGamma0 * (s->have_mat ? s->Ms : 0.0);
+    if ((rc = write_state(s, &h)) != LLG_OK) return rc;
+    s->have_m = true;
+    s->spec_valid = false;
+    s->k1_valid = false;
+    return LLG_OK;
+}
+
+llg_status llg_get_m(llg_solver* s, float* m, llg_mem where) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!m) return fail(s, LLG_E_ARG, "null m");
+    if (!s->have_m) return fail(s, LLG_E_STATE, "magnetisation not set");
+    DevState h;
+    if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    const size_t bytes = sizeof(float) * 3 * (size_t)s->g.ncells;
+    HIPCHK(s, hipMemcpyAsync(m, s->mbuf[h.cur], bytes, where == LLG_DEVICE ? hipMemcpyDeviceToDevice
+                                                                           : hipMemcpyDeviceToHost, s->stream));
+    return sync(s);
+}
+
+llg_status llg_eval_heff(llg_solver* s, float* h_out, llg_mem where) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!h_out) return fail(s, LLG_E_ARG, "null output");
+    if ((rc = ready(s, true)) != LLG_OK) return rc;
+    if ((rc = ensure_kernel(s)) != LLG_OK) return rc;
+    const Phys p = make_phys(s, s->last_dt);
+    float* dst = where == LLG_DEVICE ? h_out : s->hbuf;
+    if ((rc = eval_into(s, dst, p)) != LLG_OK) return rc;
+    if (where != LLG_DEVICE)
+        HIPCHK(s, hipMemcpyAsync(h_out, s->hbuf, sizeof(float) * 3 * (size_t)s->g.ncells,
+                                 hipMemcpyDeviceToHost, s->stream));
+    return sync(s);
+}
+
+llg_status llg_step(llg_solver* s, llg_method method, double dt, int64_t nsteps) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (method != LLG_EULER && method != LLG_HEUN && method != LLG_RK4)
+        return fail(s, LLG_E_ARG, "llg_step takes Euler, Heun or RK4");
+    if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return fail(s, LLG_E_ARG, "need dt > 0, nsteps >= 0");
+    if ((rc = ready(s, true)) != LLG_OK) return rc;
+    if ((rc = ensure_kernel(s)) != LLG_OK) return rc;
+    if (nsteps == 0) return LLG_OK;
+    const Phys p = make_phys(s, dt);
+    // device state: fixed step size
+    DevState h;
+    if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    h.dt = dt;
+    h.dtau = (float)(dt * kGamma0 * s->Ms);
+    h.gms = kGamma0 * s->Ms;
+    h.done = 0;
+    if ((rc = write_state(s, &h)) != LLG_OK) return rc;
+    if (p.demag_on && !s->spec_valid)
+        if ((rc = launch_fwd_plain(s, 1)) != LLG_OK) return rc;
+    const Tableau t = tableau_of(method);
+    if (!s->gfix.exec || s->gfix.method != (int)method || s->gfix.dt != dt) {
+        if ((rc = capture(s, s->gfix, enqueue_fixed_step, t, p)) != LLG_OK) return rc;
+        s->gfix.method = (int)method;
+        s->gfix.dt = dt;
+    }
+    for (int64_t i = 0; i < nsteps; ++i) HIPCHK(s, hipGraphLaunch(s->gfix.exec, s->stream));
+    if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    s->spec_valid = p.demag_on != 0;
+    s->k1_valid = false;
+    s->last_dt = dt;
+    if (h.health) return fail(s, LLG_E_DIVERGED, "non-finite field or torque during fixed steps");
+    return LLG_OK;
+}
+
+llg_status llg_run(llg_solver* s, llg_method method, double t_end, double max_err, double dt0,
+                   llg_stats* out) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (method != LLG_RKDP45) return fail(s, LLG_E_ARG, "llg_run takes LLG_RKDP45");
+    return run_adaptive(s, t_end, max_err, dt0, -1, out);
+}
+
+llg_status llg_run_attempts(llg_solver* s, double t_end, double max_err, double dt0, int64_t max_attempts,
+                            llg_stats* out) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (max_attempts < 1) return fail(s, LLG_E_ARG, "max_attempts must be >= 1");
+    return run_adaptive(s, t_end, max_err, dt0, max_attempts, out);
+}
+
+llg_status llg_get_stats(llg_solver* s, llg_stats* out) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!out) return fail(s, LLG_E_ARG, "null output");
+    DevState h;
+    if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    fill_stats(h, out);
+    return LLG_OK;
+}
+
+llg_status llg_get_attempts(llg_solver* s, llg_attempt* out, int64_t cap, int64_t* n) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!n || (cap > 0 && !out)) return fail(s, LLG_E_ARG, "null output");
+    DevState h;
+    if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    long long have = h.nattempt < s->log_cap ? h.nattempt : s->log_cap;
+    if (have > cap) have = cap;
+    *n = have;
+    if (have > 0) {
+        HIPCHK(s, hipMemcpyAsync(out, s->log, sizeof(llg_attempt) * have, hipMemcpyDeviceToHost, s->stream));
+        return sync(s);
+    }
+    return LLG_OK;
+}
+
+llg_status llg_profile_evals(llg_solver* s, int n, double* ms_out, int n_kinds, double* total_ms) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (n < 1 || !ms_out || n_kinds < 5 || !total_ms) return fail(s, LLG_E_ARG, "bad profile arguments");
+    if ((rc = ready(s, true)) != LLG_OK) return rc;
+    if ((rc = ensure_kernel(s)) != LLG_OK) return rc;
+    const Phys p = make_phys(s, s->last_dt);
+    if (!p.demag_on) return fail(s, LLG_E_STATE, "profiling needs the demag term");
+    std::vector<hipEvent_t> ev(6 * (size_t)n);
+    for (auto& e : ev) HIPCHK(s, hipEventCreate(&e));
+    for (int i = 0; i < n; ++i) {
+        hipEvent_t* E = &ev[6 * (size_t)i];
+        HIPCHK(s, hipEventRecord(E[0], s->stream));
+        if ((rc = launch_fwd_plain(s, 1)) != LLG_OK) return rc;
+        HIPCHK(s, hipEventRecord(E[1], s->stream));
+        if (two_d(s)) {
+            if ((rc = launch_spectral(s)) != LLG_OK) return rc;
+            HIPCHK(s, hipEventRecord(E[2], s->stream));
+            HIPCHK(s, hipEventRecord(E[3], s->stream));
+            HIPCHK(s, hipEventRecord(E[4], s->stream));
+        } else {
+            hipEvent_t mid[2] = {E[2], E[3]};
+            if ((rc = launch_spectral(s, mid)) != LLG_OK) return rc;
+            HIPCHK(s, hipEventRecord(E[4], s->stream));
+        }
+        StageArgs sa = {};
+        sa.mode = ROW_EVAL;
+        sa.m_in = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+        sa.m0 = sa.m_in;
+        sa.m_out = bref(nullptr);
+        sa.k_out = bref(nullptr);
+        sa.h_out = s->hbuf;
+        HIPCHK(s, launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream));
+        HIPCHK(s, hipEventRecord(E[5], s->stream));
+    }
+    if ((rc = sync(s)) != LLG_OK) return rc;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        hipEvent_t* E = &ev[6 * (size_t)i];
+        float t01, t12, t23, t34, t45;
+        HIPCHK(s, hipEventElapsedTime(&t01, E[0], E[1]));
+        HIPCHK(s, hipEventElapsedTime(&t12, E[1], E[2]));
+        HIPCHK(s, hipEventElapsedTime(&t23, E[2], E[3]));
+        HIPCHK(s, hipEventElapsedTime(&t34, E[3], E[4]));
+        HIPCHK(s, hipEventElapsedTime(&t45, E[4], E[5]));
+        acc[0] += t01;
+        if (two_d(s)) {
+            acc[1] += t12;
+        } else {
+            acc[3] += t12;   // y forward
+            acc[1] += t23;   // z pass with the product
+            acc[4] += t34;   // y inverse
+        }
+        acc[2] += t45;
+    }
+    float tot;
+    HIPCHK(s, hipEventElapsedTime(&tot, ev[0], ev[6 * (size_t)(n - 1) + 5]));
+    for (int k = 0; k < 5; ++k) ms_out[k] = acc[k] / n;
+    for (int k = 5; k < n_kinds; ++k) ms_out[k] = 0.0;
+    *total_ms = tot;
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    s->spec_valid = true;
+    return LLG_OK;
+}
+
+llg_status llg_kernel_bytes(llg_solver* s, double* bytes_out, int n_kinds) {
+    if (!s) return LLG_E_ARG;
+    if (!bytes_out || n_kinds < 5) return fail(s, LLG_E_ARG, "bad arguments");
+    if (!s->have_geom) return fail(s, LLG_E_STATE, "geometry not set");
+    const Grid& g = s->g;
+    const double cell_vec = 12.0 * g.ncells;                     // 3 floats per cell
+    const double spec_x = 3.0 * 8.0 * g.nrows * g.nkx;          // x-transformed spectrum
+    for (int k = 0; k < n_kinds; ++k) bytes_out[k] = 0.0;
+    bytes_out[0] = cell_vec + spec_x;                            // read m, write X
+    bytes_out[2] = spec_x + 2.0 * cell_vec;                      // read Y and m, write H
+    if (two_d(s)) {
+        const double K = 4.0 * 4.0 * g.nkx * (g.Py / 2 + 1);
+        bytes_out[1] = 2.0 * spec_x + K;                         // read X and K, write Y
+    } else {
+        const double spec_y = 3.0 * 8.0 * g.nz * g.Py * g.nkx;
+        const double K = 6.0 * 4.0 * (g.Py / 2 + 1) * g.nkx * (g.Pz / 2 + 1);
+        bytes_out[3] = spec_x + spec_y;
+        bytes_out[1] = 2.0 * spec_y + K;
+        bytes_out[4] = spec_y + spec_x;
+    }
+    return LLG_OK;
+}
+
+llg_status llg_fft_roundtrip(llg_solver* s, float* data, int n, int batch, int inverse_only) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!data || n < 1 || n > 4096 || batch < 1 || !good_len(n))
+        return fail(s, LLG_E_ARG, "need 1 <= n <= 4096 made of 2,3,5,7 and batch >= 1");
+    FftPlan pl;
+    if (!make_plan(n, pl)) return fail(s, LLG_E_UNSUPPORTED, "cannot factor %d", n);
+    float2* d = nullptr;
+    float2* tw = nullptr;
+    const size_t bytes = sizeof(float2) * (size_t)n * batch;
+    HIPCHK(s, make_tw(n, &tw));
+    HIPCHK(s, hipMalloc(&d, bytes));
+    HIPCHK(s, hipMemcpyAsync(d, data, bytes, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, launch_fft_test(d, n, batch, pl, tw, inverse_only, s->stream));
+    HIPCHK(s, hipMemcpyAsync(data, d, bytes, hipMemcpyDeviceToHost, s->stream));
+    rc = sync(s);
+    free_dev(d);
+    free_dev(tw);
+    return rc;
+}
+
+llg_status llg_demag_tensor(llg_solver* s, const int32_t* offsets, int64_t count, double* out) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (count < 0 || (count > 0 && (!offsets || !out))) return fail(s, LLG_E_ARG, "bad arguments");
+    if (!s->have_geom || !s->have_cell) return fail(s, LLG_E_STATE, "geometry and cell size needed");
+    const int n[3] = {s->nx, s->ny, s->nz};
+    for (int64_t i = 0; i < count; ++i)
+        for (int a = 0; a < 3; ++a)
+            if (!s->pbc[a] && (offsets[3 * i + a] <= -n[a] || offsets[3 * i + a] >= n[a]))
+                return fail(s, LLG_E_ARG, "offset %lld out of range on axis %d", (long long)i, a);
+    if (count == 0) return LLG_OK;
+    TensorGeom tg = {};
+    const double d[3] = {s->dx, s->dy, s->dz};
+    const double dm = fmax(d[0], fmax(d[1], d[2]));
+    for (int a = 0; a < 3; ++a) {
+        tg.n[a] = n[a];
+        tg.P[a] = a == 0 ? s->g.Px : a == 1 ? s->g.Py : s->g.Pz;
+        tg.pbc[a] = s->pbc[a];
+        tg.d[a] = d[a] / dm;
+    }
+    tg.images = s->images;
+    int32_t* od = nullptr;
+    double* rd = nullptr;
+    HIPCHK(s, hipMalloc(&od, sizeof(int32_t) * 3 * count));
+    HIPCHK(s, hipMalloc(&rd, sizeof(double) * 6 * count));
+    HIPCHK(s, hipMemcpyAsync(od, offsets, sizeof(int32_t) * 3 * count, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, tensor_at_offsets(tg, od, count, rd, s->stream));
+    HIPCHK(s, hipMemcpyAsync(out, rd, sizeof(double) * 6 * count, hipMemcpyDeviceToHost, s->stream));
+    rc = sync(s);
+    free_dev(od);
+    free_dev(rd);
+    return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+llg_status run_adaptive(llg_solver* s, double t_end, double max_err, double dt0, long long max_attempts,
+                        llg_stats* out) {
+    llg_status rc;
+    if (!(max_err > 0) || !(dt0 > 0) || !isfinite(t_end) || !isfinite(max_err) || !isfinite(dt0))
+        return fail(s, LLG_E_ARG, "need max_err > 0, dt0 > 0");
+    if ((rc = ready(s, true)) != LLG_OK) return rc;
+    if ((rc = ensure_kernel(s)) != LLG_OK) return rc;
+    const Phys p = make_phys(s, 0.0);   // thermal field: fixed steps only
+    DevState h;
+    if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    if (h.health) return fail(s, LLG_E_DIVERGED, "state already diverged");
+    if (!(t_end > h.t)) {
+        if (out) fill_stats(h, out);
+        return LLG_OK;
+    }
+    if ((rc = ensure_k1(s, p)) != LLG_OK) return rc;
+    if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    h.t_end = t_end;
+    h.tol = max_err;
+    h.dt_min = kDtMin;
+    h.gms = kGamma0 * s->Ms;
+    h.done = 0;
+    h.err_bits = 0u;
+    const double rem = t_end - h.t;
+    if (dt0 >= rem) { h.dt = rem; h.clipped = 1; } else { h.dt = dt0; h.clipped = 0; }
+    h.dtau = (float)(h.dt * h.gms);
+    if ((rc = write_state(s, &h)) != LLG_OK) return rc;
+    if (!s->gdp.exec) {
+        Tableau t = tab_dp45();
+        if ((rc = capture(s, s->gdp, dp45_body, t, p)) != LLG_OK) return rc;
+        s->gdp.method = LLG_RKDP45;
+    }
+    const long long a0 = h.nattempt;
+    const int chunk = 8;
+    int done = 0;
+    long long launched = 0;
+    while (!done) {
+        int nl = chunk;
+        if (max_attempts > 0) {
+            const long long left = max_attempts - launched;
+            if (left <= 0) break;
+            if (left < nl) nl = (int)left;
+        }
+        for (int i = 0; i < nl; ++i) HIPCHK(s, hipGraphLaunch(s->gdp.exec, s->stream));
+        launched += nl;
+        HIPCHK(s, hipMemcpyAsync(&done, &s->st->done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+        if ((rc = sync(s)) != LLG_OK) return rc;
+        if (max_attempts < 0 && launched > (1LL << 32)) break;
+    }
+    (void)a0;
+    if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    // the state buffers now hold the accepted solution; the x spectrum and
+    // k1 buffers follow the last accepted attempt only
+    s->spec_valid = false;
+    s->k1_valid = true;
+    if (out) fill_stats(h, out);
+    if (h.health & 2) return fail(s, LLG_E_DIVERGED, "step size fell below %g s", kDtMin);
+    if (h.health) return fail(s, LLG_E_DIVERGED, "non-finite field or torque");
+    return LLG_OK;
+}
+
+}  // namespace

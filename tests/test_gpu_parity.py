@@ -1,0 +1,268 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Error measures: max-relative = max_cells |v_gpu - v_ref| / max_cells |v_ref|
+(vector norms per cell), RMS-relative = sqrt(sum |dv|^2 / sum |v_ref|^2).
+The FP32 bar for H_eff is 1e-5 max-relative (single-precision FFTs with
+FP64-rounded twiddles give ~1e-6; the product with the kernel and the
+local terms add a few ulps)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import demag, fields, llg as ollg
+
+pytestmark = pytest.mark.gpu
+
+
+def maxrel(a, b):
+    a = np.asarray(a, dtype=np.float64).reshape(3, -1)
+    b = np.asarray(b, dtype=np.float64).reshape(3, -1)
+    return float(np.max(np.linalg.norm(a - b, axis=0)) / np.max(np.linalg.norm(b, axis=0)))
+
+
+def rmsrel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(math.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def note(*args):
+    print(*args, flush=True)
+    sys.stdout.flush()
+
+
+def make_solver(lib, prob, m0):
+    s = lib.Solver(0)
+    s.set_problem(prob)
+    s.set_m(m0)
+    return s
+
+
+# --------------------------------------------------------------------------
+# FFT (PIN-7)
+# --------------------------------------------------------------------------
+FFT_SIZES = [1, 2, 3, 4, 5, 7, 8, 12, 16, 20, 28, 32, 48, 64, 96, 128, 160, 192, 224, 256, 384,
+             448, 512, 640, 768, 1024, 1536, 2048, 4096]
+
+
+@pytest.mark.parametrize("n", FFT_SIZES)
+def test_fft_matches_numpy_and_roundtrips(lib, n):
+    note("fft", n)
+    rng = np.random.default_rng(n)
+    batch = max(1, min(64, 8192 // n))
+    x = (rng.standard_normal((batch, n)) + 1j * rng.standard_normal((batch, n))).astype(np.complex64)
+    s = lib.Solver(0)
+    inv = s.fft_roundtrip(x.copy(), inverse_only=True)
+    ref = np.fft.ifft(x.astype(np.complex128), axis=1)
+    assert np.max(np.abs(inv - ref)) <= 2e-6 * np.max(np.abs(ref)) * max(1.0, math.log2(n))
+    rt = s.fft_roundtrip(x.copy())
+    err = np.max(np.abs(rt - x)) / np.max(np.abs(x))
+    note("  roundtrip err", err)
+    assert err < 5e-6          # the paper reports O(1e-6) at these sizes
+
+
+# --------------------------------------------------------------------------
+# demag tensor (FP64 on the GPU vs the oracle)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,pbc,cell", [((40, 30, 1), (False,) * 3, (4e-9, 4e-9, 3e-9)),
+                                        ((16, 12, 10), (True, True, False), (3e-9, 3e-9, 3e-9)),
+                                        ((9, 11, 6), (False, True, True), (2e-9, 3e-9, 2.5e-9))])
+def test_demag_tensor_entries(lib, n, pbc, cell):
+    note("tensor", n, pbc)
+    rng = np.random.default_rng(1)
+    offs = np.stack([rng.integers(-(n[a] - 1), n[a], 300) for a in range(3)], axis=1)
+    offs[:20] = 0
+    offs[1:20, 0] = np.arange(1, 20) % n[0]
+    s = lib.Solver(0)
+    s.set_geometry(n, pbc, images=3)
+    s.set_cellsize(cell)
+    got = s.demag_tensor(offs)
+    geom = {"n": n, "cell": cell, "pbc": pbc, "images": 3}
+    ref = demag.kernel_for_offsets(offs[:, 0], offs[:, 1], offs[:, 2], geom).T
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(got - ref)) <= 1e-10 * scale
+
+
+# --------------------------------------------------------------------------
+# H_eff parity, per term and total
+# --------------------------------------------------------------------------
+CASES = [
+    dict(n=(8, 6, 1)),
+    dict(n=(17, 9, 1)),                                         # ragged, non-2^n padding
+    dict(n=(32, 32, 1), cell=(4e-9, 4e-9, 4e-9)),
+    dict(n=(70, 45, 1)),                                        # several column tiles, ragged
+    dict(n=(6, 5, 4)),                                          # 3D open
+    dict(n=(8, 8, 3), pbc=(True, True, False), cell=(3e-9, 3e-9, 3e-9)),
+    dict(n=(12, 10, 5), pbc=(True, False, True)),
+    dict(n=(16, 6, 2), pbc=(False, True, False)),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c["n"])) + "-" +
+                         "".join("p" if p else "o" for p in c.get("pbc", (False,) * 3)))
+@pytest.mark.parametrize("term", ["demag", "exchange", "anisotropy", "zeeman", "all"])
+def test_heff_parity(lib, case, term):
+    prob, m0 = workloads.small_problem(**case)
+    if term != "all":
+        prob["terms"] = (term,)
+    note("heff", case, term)
+    s = make_solver(lib, prob, m0)
+    h = s.eval_heff()
+    ref = fields.heff(m0.astype(np.float64), prob)
+    e = maxrel(h, ref)
+    note("  maxrel", e, "rmsrel", rmsrel(h, ref))
+    assert e <= 1e-5
+
+
+def test_heff_parity_film_32(lib):
+    prob, m0, _ = workloads.film_32()
+    s = make_solver(lib, prob, m0)
+    h = s.eval_heff()
+    ref = fields.heff(m0.astype(np.float64), prob)
+    e = maxrel(h, ref)
+    note("film_32 heff maxrel", e, "rms", rmsrel(h, ref))
+    assert e <= 1e-5
+
+
+def test_heff_parity_film_512(lib):
+    """The full 512 x 512 film the benchmark times, every output compared."""
+    prob, m0, _ = workloads.film_512()
+    m0 = workloads.random_unit(prob["n"], 11)   # a rich state exercises every frequency
+    s = make_solver(lib, prob, m0)
+    h = s.eval_heff()
+    ref = fields.heff(m0.astype(np.float64), prob)
+    e = maxrel(h, ref)
+    note("film_512 heff maxrel", e, "rms", rmsrel(h, ref))
+    assert e <= 1e-5
+
+
+def test_macrospin_cell(lib):
+    """One cubic cell (the smallest FFT grid): self-demag -Ms/3 m plus B/mu0."""
+    prob = dict(n=(1, 1, 1), cell=(5e-9,) * 3, pbc=(False,) * 3, Ms=8e5, Aex=1.3e-11, alpha=0.1,
+                Ku=0.0, u=(1, 0, 0), B=(0.0, 0.0, 0.1), T=0.0, seed=0)
+    m0 = workloads.uniform((1, 1, 1), (0.3, 0.4, 0.866))
+    s = make_solver(lib, prob, m0)
+    h = s.eval_heff()
+    ref = fields.heff(m0.astype(np.float64), prob)
+    assert maxrel(h, ref) <= 1e-6
+
+
+# --------------------------------------------------------------------------
+# trajectories
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("method", ["euler", "heun", "rk4"])
+def test_fixed_step_parity_small(lib, method):
+    prob, m0 = workloads.small_problem(n=(12, 10, 1), alpha=0.3)
+    s = make_solver(lib, prob, m0)
+    o = ollg.Solver(prob, m0)
+    for _ in range(4):
+        s.step(method, 2e-14, 25)
+        o.step(method, 2e-14, 25)
+        e = maxrel(s.get_m(), o.m)
+        note(method, "m maxrel", e)
+        assert e <= 1e-5
+    st = s.stats()
+    assert st["steps"] == 100
+    assert st["t"] == pytest.approx(100 * 2e-14, rel=1e-12)
+
+
+@pytest.mark.parametrize("method", ["heun", "rk4"])
+def test_film_32_trajectory(lib, method):
+    """1000 fixed steps at dt = 1e-13 s from a random state, m and H_eff
+    compared every 100 steps."""
+    prob, m0, run = workloads.film_32()
+    s = make_solver(lib, prob, m0)
+    o = ollg.Solver(prob, m0)
+    worst_m, worst_h = 0.0, 0.0
+    for blk in range(run["steps"] // 100):
+        s.step(method, run["dt"], 100)
+        o.step(method, run["dt"], 100)
+        em = maxrel(s.get_m(), o.m)
+        eh = maxrel(s.eval_heff(), fields.heff(o.m, prob))
+        worst_m, worst_h = max(worst_m, em), max(worst_h, eh)
+        note(method, (blk + 1) * 100, "m maxrel", em, "H maxrel", eh)
+    assert worst_m <= 1e-5
+    assert worst_h <= 1e-5
+
+
+def test_dp45_replay_parity(lib):
+    """Adaptive Dormand-Prince on the GPU; the oracle replays the GPU's
+    recorded step sizes and acceptances (the exact dt sequence depends on
+    rounding), then m is compared, and the oracle's own error estimates
+    agree with the GPU's on the accepted attempts."""
+    prob, m0 = workloads.small_problem(n=(24, 20, 1), alpha=0.05)
+    s = make_solver(lib, prob, m0)
+    st = s.run(3e-11, 1e-5, 1e-14)
+    log = s.attempts()
+    note("dp45 stats", st, "attempts", len(log))
+    assert st["done"] == 1 and st["t"] == pytest.approx(3e-11, rel=1e-12)
+    assert len(log) == st["steps"] + st["rejected"]
+    o = ollg.Solver(prob, m0)
+    errs = o.replay([(dt, ok) for dt, _, ok in log])
+    e = maxrel(s.get_m(), o.m)
+    note("dp45 m maxrel", e)
+    assert e <= 1e-5
+    for (dt, eg, ok), eo in zip(log, errs):
+        assert eg == pytest.approx(eo, rel=1e-2, abs=1e-9)
+
+
+def test_dp45_film_512_scaled(lib):
+    """The benchmark configuration scaled to 64 x 64, 20 ps, replay parity."""
+    prob, m0, run = workloads.film_512(64)
+    s = make_solver(lib, prob, m0)
+    st = s.run(2e-11, run["tol"], run["dt0"])
+    log = s.attempts()
+    o = ollg.Solver(prob, m0)
+    o.replay([(dt, ok) for dt, _, ok in log])
+    e = maxrel(s.get_m(), o.m)
+    note("film_512(64) dp45: attempts", len(log), "m maxrel", e)
+    assert e <= 1e-5
+
+
+def test_macrospin_precession_on_gpu(lib):
+    """PIN-11 on the GPU path: one cube cell precesses and damps as the
+    closed form says."""
+    alpha, Bz = 0.1, 0.1
+    th0, ph0 = 1.0, 0.3
+    prob = dict(n=(1, 1, 1), cell=(5e-9,) * 3, pbc=(False,) * 3, Ms=8e5, Aex=1.3e-11, alpha=alpha,
+                Ku=0.0, u=(1, 0, 0), B=(0.0, 0.0, Bz), T=0.0, seed=0)
+    m0 = np.array([math.sin(th0) * math.cos(ph0), math.sin(th0) * math.sin(ph0), math.cos(th0)],
+                  dtype=np.float32).reshape(3, 1, 1, 1)
+    s = make_solver(lib, prob, m0)
+    s.step("rk4", 1e-13, 2000)
+    H = Bz / (4e-7 * math.pi)
+    w = 4e-7 * math.pi * 1.7595e11 * H / (1 + alpha ** 2)
+    t = 2e-10
+    th = 2 * math.atan(math.tan(th0 / 2) * math.exp(-alpha * w * t))
+    ph = ph0 + w * t
+    exact = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+    assert np.max(np.abs(s.get_m()[:, 0, 0, 0] - exact)) < 2e-5
+
+
+# --------------------------------------------------------------------------
+# errors
+# --------------------------------------------------------------------------
+def test_error_paths(lib):
+    s = lib.Solver(0)
+    with pytest.raises(lib.LLGError) as e:
+        s.eval_heff()
+    assert e.value.code in (lib.LLG_E_STATE, lib.LLG_E_ARG)
+    prob, m0 = workloads.small_problem()
+    s.set_problem(prob)
+    with pytest.raises(lib.LLGError) as e:
+        s.eval_heff()
+    assert e.value.code == lib.LLG_E_STATE
+    bad = m0.copy()
+    bad[0, 0, 0, 0] *= 1.1
+    with pytest.raises(lib.LLGError) as e:
+        s.set_m(bad)
+    assert e.value.code == lib.LLG_E_ARG
+    with pytest.raises(lib.LLGError) as e:
+        s.set_material(-1.0, 1e-11, 0.1)
+    assert e.value.code == lib.LLG_E_ARG
+    with pytest.raises(lib.LLGError) as e:
+        s.set_geometry((7, 5, 1), (True, False, False))
+    assert e.value.code == lib.LLG_E_UNSUPPORTED
