@@ -172,6 +172,8 @@ class Solver:
 
     # ---- state --------------------------------------------------------------
     def _shape(self):
+        if self.n is None:
+            raise LLGError(LLG_E_STATE, "geometry not set")
         nx, ny, nz = self.n
         return (3, nz, ny, nx)
 

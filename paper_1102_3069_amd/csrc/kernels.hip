@@ -624,8 +624,10 @@ static hipError_t launch_col_mode(const ColArgs& a, DevState* st, int me, hipStr
 hipError_t launch_col(const ColArgs& a, DevState* st, int mode, hipStream_t s) {
     const int Lh = a.split ? a.P / 2 : a.P;
     if (a.plan.L != Lh || a.W < 1 || a.ntiles != (a.nkx + a.W - 1) / a.W) return hipErrorInvalidValue;
-    if (a.split && (a.P % 2 || a.n_in > Lh || a.n_out > Lh)) return hipErrorInvalidValue;
-    if (!a.split && (a.n_in > a.P || a.n_out > a.P)) return hipErrorInvalidValue;
+    if (a.split && a.P % 2) return hipErrorInvalidValue;
+    // non-zero inputs (forward) and kept outputs (inverse) fit one half
+    if (mode != COL_INV && (a.n_in < 1 || a.n_in > Lh)) return hipErrorInvalidValue;
+    if (mode != COL_FWD && (a.n_out < 1 || a.n_out > Lh)) return hipErrorInvalidValue;
     if (mode == COL_FULL && a.n_in != a.n_out) return hipErrorInvalidValue;
     // elements per thread: FFT buffer, kept inputs and outputs
     int need = 3 * a.W * Lh;

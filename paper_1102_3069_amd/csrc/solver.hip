@@ -402,7 +402,8 @@ llg_status eval_into(llg_solver* s, float* out, const Phys& p) {
     sa.k_out = bref(nullptr);
     sa.h_out = out;
     HIPCHK(s, launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream));
-    s->spec_valid = p.demag_on != 0;
+    // the column pass transformed S in place: it no longer holds X(m)
+    s->spec_valid = false;
     return LLG_OK;
 }
 
@@ -919,7 +920,7 @@ llg_status llg_profile_evals(llg_solver* s, int n, double* ms_out, int n_kinds, 
     for (int k = 5; k < n_kinds; ++k) ms_out[k] = 0.0;
     *total_ms = tot;
     for (auto& e : ev) (void)hipEventDestroy(e);
-    s->spec_valid = true;
+    s->spec_valid = false;
     return LLG_OK;
 }
 
