@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libllg.so")
-SOURCES = ["kernels.hip", "tensor.hip", "solver.hip"]
+SOURCES = ["kernels.hip", "fast2d.hip", "tensor.hip", "solver.hip"]
 
 
 def hipcc():

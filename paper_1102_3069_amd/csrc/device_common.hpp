@@ -233,6 +233,16 @@ __device__ __forceinline__ void lds_fft(C* buf, const FftPlan& p, int nbatch,
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; give
+// each XCD a contiguous range of logical tiles so that tiles sharing cache
+// lines share one L2 (a bijection of [0, n)).
+__device__ __forceinline__ int xcd_remap_blocks(int b, int n) {
+    const int X = 8;
+    const int x = b % X, i = b / X;
+    const int q = n / X, rmd = n % X;
+    return x * q + min(x, rmd) + i;
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of
 // (hi0,lo0) = M0*x0, (hi1,lo1) = M1*x2, x <- (hi1^x1^k0, lo1, hi0^x3^k1, lo0)

@@ -126,6 +126,15 @@ struct ColArgs {
     int sign_a[6], sign_o[6];
 };
 
+// Column pass of the 2D fast path (packed spectrum, see fast2d.hip).
+struct Col2dArgs {
+    float2* S;              // packed spectrum [3][ny][nkxp], nkx = Px/2 columns
+    const float* K;         // kernel spectrum [4][nkx_full][Py/2+1]
+    const float2* tw;       // exp(-2 pi i m / Py), m < Py
+    int nkx, nkx_full, nkxp;
+    int ny, Py;
+};
+
 // ---- launchers (kernels.hip) ------------------------------------------------
 hipError_t launch_row_fwd(const Grid& g, const Phys& p, const FftPlan& px, const float2* twx,
                           float2* S, const FwdArgs& fa, DevState* st, hipStream_t s);
@@ -138,6 +147,15 @@ hipError_t launch_state_add_evals(DevState* st, int evals, hipStream_t s);
 hipError_t launch_normalize_check(float* m, int ncells, int* bad, hipStream_t s);
 hipError_t launch_fft_test(float2* data, int n, int batch, const FftPlan& pl, const float2* tw,
                            int inverse_only, hipStream_t s);
+
+// ---- 2D fast path (fast2d.hip) ---------------------------------------------------
+bool fast2d_row_ok(int Px);
+bool fast2d_col_ok(int L, int split);
+hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, const FwdArgs& fa,
+                               DevState* st, hipStream_t s);
+hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, float2* S,
+                               const StageArgs& sa, DevState* st, hipStream_t s);
+hipError_t launch_col2d_fast(const Col2dArgs& a, DevState* st, hipStream_t s);
 
 // ---- demag tensor (tensor.hip) --------------------------------------------------
 struct TensorGeom {

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
+#include "cell_physics.hpp"
 
 namespace llg {
 
@@ -30,69 +31,6 @@ constexpr int CT = 256;   // threads of the column kernel
 // helpers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float2 f2(float x, float y) { float2 r; r.x = x; r.y = y; return r; }
-
-// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; give
-// each XCD a contiguous range of logical tiles so that tiles sharing cache
-// lines share one L2.
-__device__ __forceinline__ int xcd_remap(int b, int n) {
-    const int X = 8;
-    const int x = b % X, i = b / X;
-    const int q = n / X, rmd = n % X;
-    return x * q + min(x, rmd) + i;
-}
-
-// effective field without the demag term (reduced units), for cell (r, x)
-__device__ __forceinline__ void local_field(const Grid& g, const Phys& p, const float* __restrict__ m,
-                                            int r, int x, float mx, float my, float mz,
-                                            uint64_t step, float& hx, float& hy, float& hz) {
-    const long long cs = g.ncells;
-    float sx = 0.f, sy = 0.f, sz = 0.f;
-    auto nb = [&](int rr, int xx, float c) {
-        const long long i = (long long)rr * g.nx + xx;
-        sx += c * (m[i] - mx);
-        sy += c * (m[cs + i] - my);
-        sz += c * (m[2 * cs + i] - mz);
-    };
-    if (p.cex[0] != 0.f && g.nx > 1) {
-        const float c = p.cex[0];
-        if (x > 0) nb(r, x - 1, c); else if (g.pbc[0]) nb(r, g.nx - 1, c);
-        if (x < g.nx - 1) nb(r, x + 1, c); else if (g.pbc[0]) nb(r, 0, c);
-    }
-    if (p.cex[1] != 0.f && g.ny > 1) {
-        const float c = p.cex[1];
-        const int y = r % g.ny;
-        if (y > 0) nb(r - 1, x, c); else if (g.pbc[1]) nb(r + g.ny - 1, x, c);
-        if (y < g.ny - 1) nb(r + 1, x, c); else if (g.pbc[1]) nb(r - (g.ny - 1), x, c);
-    }
-    if (p.cex[2] != 0.f && g.nz > 1) {
-        const float c = p.cex[2];
-        const int z = r / g.ny;
-        if (z > 0) nb(r - g.ny, x, c); else if (g.pbc[2]) nb(r + (g.nz - 1) * g.ny, x, c);
-        if (z < g.nz - 1) nb(r + g.ny, x, c); else if (g.pbc[2]) nb(r - (g.nz - 1) * g.ny, x, c);
-    }
-    hx += sx; hy += sy; hz += sz;
-    if (p.ku != 0.f) {
-        const float mu = p.ku * (mx * p.u[0] + my * p.u[1] + mz * p.u[2]);
-        hx += mu * p.u[0]; hy += mu * p.u[1]; hz += mu * p.u[2];
-    }
-    hx += p.hz[0]; hy += p.hz[1]; hz += p.hz[2];
-    if (p.sig_th != 0.f) {
-        float ex, ey, ez;
-        thermal_eta((uint32_t)((long long)r * g.nx + x), step, p.seed_lo, p.seed_hi, ex, ey, ez);
-        hx += p.sig_th * ex; hy += p.sig_th * ey; hz += p.sig_th * ez;
-    }
-}
-
-// dm/dtau = -1/(1+alpha^2) (m x h + alpha m x (m x h))
-__device__ __forceinline__ void ll_torque(const Phys& p, float mx, float my, float mz,
-                                          float hx, float hy, float hz,
-                                          float& kx, float& ky, float& kz) {
-    const float ax = my * hz - mz * hy, ay = mz * hx - mx * hz, az = mx * hy - my * hx;
-    const float bx = my * az - mz * ay, by = mz * ax - mx * az, bz = mx * ay - my * ax;
-    kx = p.llpre * (ax + p.alpha * bx);
-    ky = p.llpre * (ay + p.alpha * by);
-    kz = p.llpre * (az + p.alpha * bz);
-}
 
 // Forward x transform of the two rows r0, r0+1 whose values sit in the
 // per-thread slots nm[q] (slot q covers cell e = tid + q*RT, row e / nx),
@@ -356,7 +294,7 @@ __global__ __launch_bounds__(CT) void col_kernel(ColArgs a, DevState* __restrict
     extern __shared__ float2 lds[];
     if (st->done) return;
     const int tid = threadIdx.x;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int lb = xcd_remap_blocks(blockIdx.x, gridDim.x);
     const int o = lb / a.ntiles;
     const int tile = lb - o * a.ntiles;
     const int kx0 = tile * a.W;

@@ -1,0 +1,173 @@
+// Compile-time-length FFTs computed by a group of P lanes of one wavefront.
+//
+// Lane lg (0 <= lg < P) of the group holds E = L/P elements in registers,
+// element i being index lg + P*i of the sequence ("natural" layout).  The
+// transform is a Stockham autosort sequence of radix-R stages (every R
+// divides E): the first stage reads its butterfly inputs straight from the
+// registers, the last one writes its outputs straight back to registers in
+// the same natural layout, and the stages in between exchange through a
+// per-group LDS scratch of L + L/16 elements (padded against bank conflicts).  A group never spans two wavefronts,
+// so no workgroup barrier is needed inside a transform: the lanes of one
+// wavefront issue their LDS operations in program order.
+//
+// Twiddles come from an LDS table tw[m] = exp(-2 pi i m / (L * TM)) that the
+// calling kernel loaded once (TM = 1 or 2 so that one table serves both the
+// half-length transforms of a zero-padded axis and its pre/post twiddles).
+#pragma once
+
+#include "device_common.hpp"
+
+namespace llg {
+
+// one more DFT size used by the lane FFTs: 16 = 4 x 4
+template <typename C> struct Dft<16, C> {
+    static __device__ __forceinline__ void run(C* v, bool inv) {
+        using T = typename real_of<C>::type;
+        C a[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            a[n2][0] = v[n2]; a[n2][1] = v[4 + n2]; a[n2][2] = v[8 + n2]; a[n2][3] = v[12 + n2];
+            dft4(a[n2][0], a[n2][1], a[n2][2], a[n2][3], inv);
+        }
+        // twiddles W16^(n2 k1)
+        const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;
+        const T r2 = (T)0.70710678118654752440;
+        const T sg = inv ? (T)1 : (T)-1;
+        const C w1 = cmk<C>(c1, sg * s1), w2 = cmk<C>(r2, sg * r2), w3 = cmk<C>(s1, sg * c1);
+        const C w6 = cmk<C>(-r2, sg * r2), w9 = cmk<C>(-c1, -sg * s1);
+        a[1][1] = cmul(a[1][1], w1); a[1][2] = cmul(a[1][2], w2); a[1][3] = cmul(a[1][3], w3);
+        a[2][1] = cmul(a[2][1], w2); a[2][2] = inv ? mul_pi(a[2][2]) : mul_mi(a[2][2]);
+        a[2][3] = cmul(a[2][3], w6);
+        a[3][1] = cmul(a[3][1], w3); a[3][2] = cmul(a[3][2], w6); a[3][3] = cmul(a[3][3], w9);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            C b0 = a[0][k1], b1 = a[1][k1], b2 = a[2][k1], b3 = a[3][k1];
+            dft4(b0, b1, b2, b3, inv);
+            v[k1] = b0; v[k1 + 4] = b1; v[k1 + 8] = b2; v[k1 + 12] = b3;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// stage plan: greedy radices from {16, 8, 4, 2, 3, 5, 7}, each dividing both
+// the remaining length and E
+// ---------------------------------------------------------------------------
+constexpr int lf_pick(int rem, int E) {
+    return (rem % 16 == 0 && E % 16 == 0) ? 16
+         : (rem % 8 == 0 && E % 8 == 0) ? 8
+         : (rem % 4 == 0 && E % 4 == 0) ? 4
+         : (rem % 2 == 0 && E % 2 == 0) ? 2
+         : (rem % 3 == 0 && E % 3 == 0) ? 3
+         : (rem % 5 == 0 && E % 5 == 0) ? 5
+         : (rem % 7 == 0 && E % 7 == 0) ? 7 : 0;
+}
+constexpr int lf_radix(int L, int E, int s) {
+    int rem = L;
+    for (int i = 0; i < s; ++i) {
+        const int r = lf_pick(rem, E);
+        if (r == 0) return 0;
+        rem /= r;
+    }
+    return rem == 1 ? 1 : lf_pick(rem, E);
+}
+constexpr int lf_nstages(int L, int E) {
+    int rem = L, n = 0;
+    while (rem > 1) {
+        const int r = lf_pick(rem, E);
+        if (r == 0) return -1;
+        rem /= r;
+        ++n;
+    }
+    return n;
+}
+constexpr int lf_ns(int L, int E, int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= lf_radix(L, E, i);
+    return p;
+}
+
+// shift/mask friendly modulo for the compile-time Ns
+template <int N> __device__ __forceinline__ int cmod(int a) { return a % N; }
+
+// LDS scratch index with one pad element per 16: the Stockham stores of a
+// radix-R stage are R elements apart across lanes, which would otherwise
+// fall into the same few LDS banks.
+__device__ __forceinline__ int lf_pad(int i) { return i + (i >> 4); }
+template <int L> struct LfScratch { static constexpr int size = L + L / 16; };
+
+template <int L, int E, int TM, typename C>
+struct LaneFFT {
+    static constexpr int P = L / E;
+    static constexpr int NS = lf_nstages(L, E);
+    static constexpr int SCRATCH = LfScratch<L>::size;   // elements per group
+    static_assert(L % E == 0 && NS >= 0, "length must factor into radices dividing E");
+    static_assert(64 % P == 0, "a lane group must fit one wavefront");
+
+    template <int S, bool INV>
+    static __device__ __forceinline__ void stage(C (&x)[E], C* sc, const C* tw, int lg) {
+        constexpr int R = lf_radix(L, E, S);
+        constexpr int Ns = lf_ns(L, E, S);
+        constexpr int U = E / R;          // butterflies per lane
+        constexpr int LR = L / R;
+        constexpr int TS = (L / (Ns * R)) * TM;
+        constexpr bool FIRST = S == 0, LAST = S == NS - 1;
+        C v[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = lg + P * u;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[u][r] = FIRST ? x[u + r * U] : sc[lf_pad(j + r * LR)];
+            if (Ns > 1) {
+                const int k = cmod<Ns>(j);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C w = tw[k * r * TS];
+                    if (INV) w.y = -w.y;
+                    v[u][r] = cmul(v[u][r], w);
+                }
+            }
+            Dft<R, C>::run(v[u], INV);
+        }
+        if (LAST) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int r = 0; r < R; ++r) x[u + r * U] = v[u][r];
+        } else {
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = lg + P * u;
+                const int k = cmod<Ns>(j);
+                const int d = (j - k) * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) sc[lf_pad(d + r * Ns)] = v[u][r];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+
+    template <int S, bool INV>
+    static __device__ __forceinline__ void stages(C (&x)[E], C* sc, const C* tw, int lg) {
+        if constexpr (S < NS) {
+            stage<S, INV>(x, sc, tw, lg);
+            stages<S + 1, INV>(x, sc, tw, lg);
+        }
+    }
+
+    // unnormalised transform, forward (exp(-i...)) or inverse (exp(+i...))
+    template <bool INV>
+    static __device__ __forceinline__ void run(C (&x)[E], C* sc, const C* tw, int lg) {
+        stages<0, INV>(x, sc, tw, lg);
+    }
+};
+
+// value held by lane `src` (absolute lane id in the wavefront) of register v
+__device__ __forceinline__ float2 lane_shfl(float2 v, int src) {
+    float2 r;
+    r.x = __shfl(v.x, src);
+    r.y = __shfl(v.y, src);
+    return r;
+}
+
+}  // namespace llg

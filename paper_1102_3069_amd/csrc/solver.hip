@@ -12,6 +12,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
@@ -134,6 +135,7 @@ struct llg_solver {
     FftPlan px = {}, py = {}, pz = {};
     float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
     int wy = 1, wz = 1;       // column tile widths
+    bool fast2d = false;      // 2D with compiled FFT lengths: packed spectrum kernels
     // device buffers
     float* K = nullptr;
     bool K_valid = false;
@@ -295,6 +297,16 @@ llg_status ensure_kernel(llg_solver* s) {
     return LLG_OK;
 }
 
+// row passes: packed fast kernels or the generic ones
+hipError_t row_fwd(llg_solver* s, const Phys& p, const FwdArgs& fa) {
+    if (s->fast2d) return launch_row_fwd_fast(s->g, s->twx, s->S, fa, s->st, s->stream);
+    return launch_row_fwd(s->g, p, s->px, s->twx, s->S, fa, s->st, s->stream);
+}
+hipError_t row_inv(llg_solver* s, const Phys& p, const StageArgs& sa) {
+    if (s->fast2d) return launch_row_inv_fast(s->g, p, s->twx, s->S, sa, s->st, s->stream);
+    return launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream);
+}
+
 ColArgs col_base(const llg_solver* s) {
     ColArgs a = {};
     a.nkx = s->g.nkx;
@@ -305,6 +317,19 @@ ColArgs col_base(const llg_solver* s) {
 llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
     const Grid& g = s->g;
     const long long nkxp = g.nkxp;
+    if (two_d(s) && s->fast2d) {
+        Col2dArgs c = {};
+        c.S = s->S;
+        c.K = s->K;
+        c.tw = s->twy;
+        c.nkx = g.Px / 2;
+        c.nkx_full = g.nkx;
+        c.nkxp = g.nkxp;
+        c.ny = g.ny;
+        c.Py = g.Py;
+        HIPCHK(s, launch_col2d_fast(c, s->st, s->stream));
+        return LLG_OK;
+    }
     if (two_d(s)) {
         ColArgs a = col_base(s);
         a.in = s->S; a.out = s->S;
@@ -368,7 +393,7 @@ llg_status launch_fwd_plain(llg_solver* s, int sel) {
     fa.combine = 0;
     fa.m0 = fa.m_in; fa.k1 = fa.m_in; fa.m_out = bref(nullptr);
     const Phys p = make_phys(s, 0.0);
-    HIPCHK(s, launch_row_fwd(s->g, p, s->px, s->twx, s->S, fa, s->st, s->stream));
+    HIPCHK(s, row_fwd(s, p, fa));
     return LLG_OK;
 }
 
@@ -401,7 +426,7 @@ llg_status eval_into(llg_solver* s, float* out, const Phys& p) {
     sa.m_out = bref(nullptr);
     sa.k_out = bref(nullptr);
     sa.h_out = out;
-    HIPCHK(s, launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream));
+    HIPCHK(s, row_inv(s, p, sa));
     // the column pass transformed S in place: it no longer holds X(m)
     s->spec_valid = false;
     return LLG_OK;
@@ -437,7 +462,7 @@ llg_status enqueue_fixed_step(llg_solver* s, const Tableau& t, const Phys& p) {
         for (int j = 0; j < st; ++j) sa.a[j] = (float)(st < t.S ? t.A[st][j] : t.b[j]);
         for (int j = 0; j + 1 < st; ++j) sa.kprev[j] = bref(s->kb[j]);
         sa.h_out = nullptr;
-        HIPCHK(s, launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream));
+        HIPCHK(s, row_inv(s, p, sa));
     }
     HIPCHK(s, launch_ctrl_fixed(s->st, t.S, 0.0, s->stream));
     return LLG_OK;
@@ -460,7 +485,7 @@ llg_status enqueue_dp45_attempt(llg_solver* s, const Phys& p) {
     fa.k1 = kref[0];
     fa.m_in = fa.m0;
     fa.m_out = bref(s->ms[0]);
-    HIPCHK(s, launch_row_fwd(s->g, p, s->px, s->twx, s->S, fa, s->st, s->stream));
+    HIPCHK(s, row_fwd(s, p, fa));
     for (int st = 2; st <= 7; ++st) {
         if (p.demag_on && (rc = launch_spectral(s)) != LLG_OK) return rc;
         StageArgs sa = {};
@@ -478,7 +503,7 @@ llg_status enqueue_dp45_attempt(llg_solver* s, const Phys& p) {
             sa.m_out = bref(nullptr);
             for (int j = 0; j < 7; ++j) sa.e[j] = (float)(t.b[j] - t.bhat[j]);
         }
-        HIPCHK(s, launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream));
+        HIPCHK(s, row_inv(s, p, sa));
     }
     HIPCHK(s, launch_ctrl_dp45(s->st, s->stream));
     return LLG_OK;
@@ -519,7 +544,7 @@ llg_status ensure_k1(llg_solver* s, const Phys& p) {
     sa.m0 = sa.m_in;
     sa.m_out = bref(nullptr);
     sa.k_out = bref_cur(s->kfs[0], s->kfs[1], 1);
-    HIPCHK(s, launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream));
+    HIPCHK(s, row_inv(s, p, sa));
     HIPCHK(s, launch_state_add_evals(s->st, 1, s->stream));
     s->k1_valid = true;
     return LLG_OK;
@@ -634,6 +659,11 @@ llg_status llg_set_geometry(llg_solver* s, int nx, int ny, int nz, int pbc_x, in
     s->wy = col_width(Ly, ny);
     s->wz = col_width(Lz, nz);
     if (s->wy < 1 || s->wz < 1) return fail(s, LLG_E_UNSUPPORTED, "column pass does not fit");
+    // LLG_FORCE_GENERIC=1 selects the runtime-length kernels everywhere (used
+    // by the tests to check both implementations against the oracle)
+    const char* gen = getenv("LLG_FORCE_GENERIC");
+    s->fast2d = nz == 1 && fast2d_row_ok(P[0]) && fast2d_col_ok(Ly, split_y) && ny <= Ly &&
+                (P[0] / 2) % 16 == 0 && !(gen && gen[0] == '1');
     const size_t vec = sizeof(float) * 3 * (size_t)g.ncells;
     HIPCHK(s, make_tw(P[0], &s->twx));
     HIPCHK(s, make_tw(P[1], &s->twy));
@@ -891,7 +921,7 @@ llg_status llg_profile_evals(llg_solver* s, int n, double* ms_out, int n_kinds, 
         sa.m_out = bref(nullptr);
         sa.k_out = bref(nullptr);
         sa.h_out = s->hbuf;
-        HIPCHK(s, launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream));
+        HIPCHK(s, row_inv(s, p, sa));
         HIPCHK(s, hipEventRecord(E[5], s->stream));
     }
     if ((rc = sync(s)) != LLG_OK) return rc;
