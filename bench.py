@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--profile-evals", type=int, default=200)
     ap.add_argument("--cpu-baseline-evals", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("film512", "batch"), default="film512",
+                    help="film512: the 512x512 film (the headline); batch: the 64-film sweep")
     return ap.parse_args()
 
 
@@ -54,8 +56,42 @@ def cpu_baseline(prob, m0, nevals):
                       f"({dt:.1f} s; kernel spectrum built beforehand, not timed)"}
 
 
+def bench_batch(args):
+    """64 independent films of uneven size (sides 64..256) advanced together:
+    one grouped launch per pass over all films, per-film adaptive steps."""
+    import numpy as np
+    import torch
+    import paper_1102_3069_amd as llg
+    import workloads
+    llg.load()
+    films, run = workloads.film_batch()
+    cells = np.array([int(np.prod(p["n"])) for p, _ in films])
+    b = llg.Batch(films)
+    st0 = b.run(run["t_end"], run["tol"], run["dt0"], max_attempts=max(1, args.warmup))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st1 = b.run(run["t_end"], run["tol"], run["dt0"], max_attempts=args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    evals = np.array([s1["evals"] - s0["evals"] for s0, s1 in zip(st0, st1)])
+    value = float(np.sum(cells * evals)) / wall
+    out = {"metric": "cell-updates/s (H_eff evals), 64-film batch", "value": value, "unit": "cell-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "64 films, sides from {64,96,128,192,256}, adaptive Dormand-Prince, "
+                                  "grouped launches over all films", "cells": int(cells.sum()),
+                      "films_done": int(sum(s["done"] for s in st1))}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "batch":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        return bench_batch(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is "
               "described in DESIGN.md but not built", file=sys.stderr)

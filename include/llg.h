@@ -196,6 +196,44 @@ llg_status llg_fft_roundtrip(llg_solver *s, float *data, int n, int batch, int i
  * convolution range (|d| < n along open axes). */
 llg_status llg_demag_tensor(llg_solver *s, const int32_t *offsets, int64_t count, double *out);
 
+/* ---- batched films ----------------------------------------------------------
+ * Many independent 2D films (nz = 1, open boundaries, no thermal field) of
+ * uneven size, e.g. a parameter sweep, integrated together with adaptive
+ * Dormand-Prince 5(4).  Every pass of an attempt is one grouped launch over
+ * all films; each film keeps its own step size, accept/reject decisions,
+ * time and attempt log on the device, and its arithmetic is that of the
+ * single-film solver (same kernels, same order), so results do not depend
+ * on the batch composition.  Film sizes must have compiled FFT lengths
+ * (padded lengths 2^n or 3*2^n between 64 and 1024; e.g. sides 32, 48,
+ * 64, 96, 128, 192, 256, 384, 512), else llg_batch_create returns
+ * LLG_E_UNSUPPORTED.
+ */
+typedef struct llg_batch llg_batch;
+
+typedef struct {
+    int nx, ny;               /* cells                                   */
+    double dx, dy, dz;        /* cell edges, m                           */
+    double Ms, Aex, alpha;    /* A/m, J/m, 1                             */
+    double Ku;                /* uniaxial anisotropy, J/m^3              */
+    double u[3];              /* anisotropy axis (non-zero)              */
+    double B[3];              /* applied field mu0 H, tesla              */
+    const float *m0;          /* host, [3][ny][nx] unit vectors; copied  */
+} llg_film_desc;
+
+/* Builds every film's demag kernel (FP64) and uploads its initial state.
+ * LLG_E_ARG for invalid parameters or m0 not of unit vectors. */
+llg_status  llg_batch_create(int device, const llg_film_desc *films, int nfilms, llg_batch **out);
+void        llg_batch_destroy(llg_batch *b);
+const char *llg_batch_last_error(const llg_batch *b);
+/* Advances every film toward t_end (s) with tolerance max_err; dt0 is each
+ * film's first attempted step of this call.  Stops when all films are done
+ * or after max_attempts attempts (<= 0: no limit).  per_film (host, nfilms
+ * entries) may be NULL.  LLG_E_DIVERGED if any film diverged. */
+llg_status  llg_batch_run(llg_batch *b, double t_end, double max_err, double dt0,
+                          int64_t max_attempts, llg_stats *per_film);
+llg_status  llg_batch_get_m(llg_batch *b, int film, float *m);
+llg_status  llg_batch_get_attempts(llg_batch *b, int film, llg_attempt *out, int64_t cap, int64_t *n);
+
 #ifdef __cplusplus
 }
 #endif

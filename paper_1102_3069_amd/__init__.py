@@ -46,6 +46,14 @@ class Attempt(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("err", ctypes.c_float), ("accepted", ctypes.c_int32)]
 
 
+class FilmDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("Ms", ctypes.c_double), ("Aex", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("Ku", ctypes.c_double), ("u", ctypes.c_double * 3), ("B", ctypes.c_double * 3),
+                ("m0", ctypes.c_void_p)]
+
+
 _lib = None
 
 # exported symbols of include/llg.h with their argument and result types
@@ -77,6 +85,15 @@ _SIGNATURES = {
     "llg_kernel_bytes": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
     "llg_fft_roundtrip": ([_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "llg_demag_tensor": ([_P, _P, ctypes.c_int64, _P], ctypes.c_int),
+    "llg_batch_create": ([ctypes.c_int, ctypes.POINTER(FilmDesc), ctypes.c_int, ctypes.POINTER(_P)],
+                         ctypes.c_int),
+    "llg_batch_destroy": ([_P], None),
+    "llg_batch_last_error": ([_P], ctypes.c_char_p),
+    "llg_batch_run": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                       ctypes.POINTER(Stats)], ctypes.c_int),
+    "llg_batch_get_m": ([_P, ctypes.c_int, _P], ctypes.c_int),
+    "llg_batch_get_attempts": ([_P, ctypes.c_int, ctypes.POINTER(Attempt), ctypes.c_int64,
+                                ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
 }
 EXPORTS = tuple(_SIGNATURES)
 
@@ -255,3 +272,69 @@ class Solver:
         self._chk(self._lib.llg_demag_tensor(self._h, o.ctypes.data_as(_P), o.shape[0],
                                              out.ctypes.data_as(_P)))
         return out
+
+
+class Batch:
+    """Independent 2D films integrated together (see llg_batch_* in llg.h).
+    films: list of (problem dict, m0 float32 array) as made by workloads.py."""
+
+    def __init__(self, films, device=0):
+        self._lib = load()
+        self.shapes = []
+        self._keep = []
+        descs = (FilmDesc * len(films))()
+        for d, (prob, m0) in zip(descs, films):
+            nx, ny, nz = prob["n"]
+            if nz != 1:
+                raise LLGError(LLG_E_ARG, "batched films are one cell thick")
+            a = np.ascontiguousarray(m0, dtype=np.float32).reshape(3, 1, ny, nx)
+            self._keep.append(a)
+            self.shapes.append((3, 1, ny, nx))
+            d.nx, d.ny = nx, ny
+            d.dx, d.dy, d.dz = (float(c) for c in prob["cell"])
+            d.Ms, d.Aex, d.alpha = float(prob["Ms"]), float(prob["Aex"]), float(prob["alpha"])
+            d.Ku = float(prob.get("Ku", 0.0))
+            d.u = (ctypes.c_double * 3)(*[float(v) for v in prob.get("u", (1.0, 0.0, 0.0))])
+            d.B = (ctypes.c_double * 3)(*[float(v) for v in prob.get("B", (0.0, 0.0, 0.0))])
+            d.m0 = a.ctypes.data
+        h = _P()
+        rc = self._lib.llg_batch_create(int(device), descs, len(films), ctypes.byref(h))
+        if rc != LLG_OK:
+            msg = self._lib.llg_batch_last_error(h).decode() if h else "llg_batch_create failed"
+            if h:
+                self._lib.llg_batch_destroy(h)
+            raise LLGError(rc, msg)
+        self._h = h
+        self.n = len(films)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.llg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != LLG_OK:
+            raise LLGError(rc, self._lib.llg_batch_last_error(self._h).decode())
+
+    def run(self, t_end, max_err=1e-5, dt0=1e-14, max_attempts=0):
+        st = (Stats * self.n)()
+        self._chk(self._lib.llg_batch_run(self._h, float(t_end), float(max_err), float(dt0),
+                                          int(max_attempts), st))
+        return [s.as_dict() for s in st]
+
+    def get_m(self, film):
+        a = np.empty(self.shapes[film], dtype=np.float32)
+        self._chk(self._lib.llg_batch_get_m(self._h, int(film), a.ctypes.data_as(_P)))
+        return a
+
+    def attempts(self, film, cap=1 << 16):
+        buf = (Attempt * cap)()
+        n = ctypes.c_int64()
+        self._chk(self._lib.llg_batch_get_attempts(self._h, int(film), buf, cap, ctypes.byref(n)))
+        return [(buf[i].dt, float(buf[i].err), bool(buf[i].accepted)) for i in range(n.value)]

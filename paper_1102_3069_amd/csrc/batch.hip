@@ -1,0 +1,433 @@
+// Batched runtime: many independent 2D films of uneven size (a parameter
+// sweep) integrated together with adaptive Dormand-Prince 5(4).
+//
+// Every pass of an attempt (the first-stage forward transform, then per
+// stage the column pass and the fused row pass, then the step controller)
+// is ONE grouped launch that covers all films: its blocks are mapped to
+// (film, local tile) by a table, and every block runs the compiled-length
+// kernel body of its film's size.  Each film keeps its own device state
+// (time, step size, accept/reject, buffer swap, attempt log), so films
+// advance with their own steps inside the same launches; a film that has
+// reached t_end leaves its blocks idle.  The attempt is captured once into a
+// HIP graph and replayed.  The per-film arithmetic is exactly that of the
+// single-film solver, so a film's result does not depend on the batch it
+// runs in.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "host_common.hpp"
+#include "internal.hpp"
+
+using namespace llg;
+using namespace llg::host;
+
+namespace {
+
+struct BatchFilm {
+    Material mat;
+    Grid g = {};
+    float2 *twx = nullptr, *twy = nullptr;
+    float* K = nullptr;
+    float2* S = nullptr;
+    float* mbuf[2] = {nullptr, nullptr};
+    float* ms[2] = {nullptr, nullptr};
+    float* kb[6] = {};
+    float* kfs[2] = {nullptr, nullptr};
+    llg_attempt* log = nullptr;
+    int row_blocks = 0, col_blocks = 0;
+};
+
+}  // namespace
+
+struct llg_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<BatchFilm> films;
+    DevState* st = nullptr;             // one state per film, contiguous
+    long long log_cap = 1 << 16;
+    // grouped launch arguments (device arrays, one entry per film)
+    FilmRow* d_fwd_plain = nullptr;     // k1 initialisation: forward pass of m
+    FilmRow* d_konly = nullptr;         // k1 initialisation: k of m
+    FilmRow* d_prep = nullptr;          // stage-2 input and its forward pass
+    FilmRow* d_stage[6] = {};           // stages 2..7
+    FilmCol* d_col = nullptr;
+    int2* d_rowmap = nullptr;
+    int2* d_colmap = nullptr;
+    int nrowblk = 0, ncolblk = 0;
+    int lds_fwd = 0, lds_inv = 0, lds_col = 0;
+    hipGraphExec_t graph = nullptr;
+    bool k1_valid = false;
+};
+
+namespace {
+
+llg_status bfail(llg_batch* b, llg_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b) b->err = buf;
+    return code;
+}
+
+#define BCHK(b, x)                                                                                \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess)                                                                     \
+            return bfail(b, e_ == hipErrorOutOfMemory ? LLG_E_NOMEM : LLG_E_DEVICE, "%s: %s (%s:%d)", \
+                         #x, hipGetErrorString(e_), __FILE__, __LINE__);                          \
+    } while (0)
+
+void bfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& v) {
+    hipError_t e = hipMalloc(dst, sizeof(T) * v.size());
+    if (e == hipSuccess) e = hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+    return e;
+}
+
+Col2dArgs col_args(const BatchFilm& f) {
+    Col2dArgs c = {};
+    c.S = f.S;
+    c.K = f.K;
+    c.tw = f.twy;
+    c.nkx = f.g.Px / 2;
+    c.nkx_full = f.g.nkx;
+    c.nkxp = f.g.nkxp;
+    c.ny = f.g.ny;
+    c.Py = f.g.Py;
+    return c;
+}
+
+FilmRow row_base(const llg_batch* b, int i) {
+    const BatchFilm& f = b->films[i];
+    FilmRow r = {};
+    r.g = f.g;
+    r.p = phys_of(f.mat, 0.0);
+    r.twx = f.twx;
+    r.S = f.S;
+    r.st = b->st + i;
+    return r;
+}
+
+// the per-film arguments of every grouped launch of an attempt; buffer
+// roles follow the single-film Dormand-Prince attempt exactly
+llg_status build_launch_args(llg_batch* b) {
+    const int nf = (int)b->films.size();
+    const Tableau t = tab_dp45();
+    std::vector<FilmRow> fwd_plain(nf), konly(nf), prep(nf), stage[6];
+    std::vector<FilmCol> col(nf);
+    for (auto& v : stage) v.resize(nf);
+    for (int i = 0; i < nf; ++i) {
+        BatchFilm& f = b->films[i];
+        const BufRef mcur = bref_cur(f.mbuf[0], f.mbuf[1], 1);
+        const BufRef mnext = bref_cur(f.mbuf[0], f.mbuf[1], 2);
+        BufRef kref[7];
+        kref[0] = bref_cur(f.kfs[0], f.kfs[1], 1);
+        for (int j = 1; j <= 5; ++j) kref[j] = bref(f.kb[j]);
+        kref[6] = bref_cur(f.kfs[0], f.kfs[1], 2);
+
+        FilmRow r = row_base(b, i);
+        r.fa.m_in = mcur; r.fa.combine = 0; r.fa.m0 = mcur; r.fa.k1 = mcur; r.fa.m_out = bref(nullptr);
+        fwd_plain[i] = r;
+
+        r = row_base(b, i);
+        r.sa.mode = ROW_KONLY;
+        r.sa.m_in = mcur; r.sa.m0 = mcur; r.sa.m_out = bref(nullptr); r.sa.k_out = kref[0];
+        konly[i] = r;
+
+        r = row_base(b, i);
+        r.fa.combine = 1;
+        r.fa.a1 = (float)t.A[1][0];
+        r.fa.m0 = mcur; r.fa.k1 = kref[0]; r.fa.m_in = mcur; r.fa.m_out = bref(f.ms[0]);
+        prep[i] = r;
+
+        for (int s = 2; s <= 7; ++s) {
+            r = row_base(b, i);
+            StageArgs& sa = r.sa;
+            sa.m0 = mcur;
+            sa.m_in = s == 7 ? mnext : bref(f.ms[s % 2 == 0 ? 0 : 1]);
+            sa.k_out = kref[s - 1];
+            sa.nk = s;
+            for (int j = 0; j + 1 < s; ++j) sa.kprev[j] = kref[j];
+            if (s < 7) {
+                sa.mode = ROW_STAGE;
+                sa.m_out = s == 6 ? mnext : bref(f.ms[s % 2 == 0 ? 1 : 0]);
+                for (int j = 0; j < s; ++j) sa.a[j] = (float)t.A[s][j];
+            } else {
+                sa.mode = ROW_ERROR;
+                sa.m_out = bref(nullptr);
+                for (int j = 0; j < 7; ++j) sa.e[j] = (float)(t.b[j] - t.bhat[j]);
+            }
+            stage[s - 2][i] = r;
+        }
+        col[i].a = col_args(f);
+        col[i].st = b->st + i;
+    }
+    BCHK(b, upload(&b->d_fwd_plain, fwd_plain));
+    BCHK(b, upload(&b->d_konly, konly));
+    BCHK(b, upload(&b->d_prep, prep));
+    for (int s = 0; s < 6; ++s) BCHK(b, upload(&b->d_stage[s], stage[s]));
+    BCHK(b, upload(&b->d_col, col));
+    // block maps
+    std::vector<int2> rmap, cmap;
+    for (int i = 0; i < nf; ++i) {
+        for (int k = 0; k < b->films[i].row_blocks; ++k) rmap.push_back(make_int2(i, k));
+        for (int k = 0; k < b->films[i].col_blocks; ++k) cmap.push_back(make_int2(i, k));
+    }
+    b->nrowblk = (int)rmap.size();
+    b->ncolblk = (int)cmap.size();
+    BCHK(b, upload(&b->d_rowmap, rmap));
+    BCHK(b, upload(&b->d_colmap, cmap));
+    return LLG_OK;
+}
+
+llg_status enqueue_attempt(llg_batch* b) {
+    const int nf = (int)b->films.size();
+    BCHK(b, launch_row_fwd_group(b->d_prep, b->d_rowmap, b->nrowblk, b->lds_fwd, b->stream));
+    for (int s = 0; s < 6; ++s) {
+        BCHK(b, launch_col_group(b->d_col, b->d_colmap, b->ncolblk, b->lds_col, b->stream));
+        BCHK(b, launch_row_inv_group(b->d_stage[s], b->d_rowmap, b->nrowblk, b->lds_inv, b->stream));
+    }
+    BCHK(b, launch_ctrl_dp45_group(b->st, nf, b->stream));
+    return LLG_OK;
+}
+
+llg_status read_states(llg_batch* b, std::vector<DevState>& h) {
+    h.resize(b->films.size());
+    BCHK(b, hipMemcpyAsync(h.data(), b->st, sizeof(DevState) * h.size(), hipMemcpyDeviceToHost, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    return LLG_OK;
+}
+
+llg_status write_states(llg_batch* b, const std::vector<DevState>& h) {
+    BCHK(b, hipMemcpyAsync(b->st, h.data(), sizeof(DevState) * h.size(), hipMemcpyHostToDevice, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    return LLG_OK;
+}
+
+void fill(const DevState& h, llg_stats* o) {
+    o->t = h.t; o->dt = h.dt; o->dt_next = h.dt_next; o->max_err = h.last_err;
+    o->steps = h.nsteps; o->rejected = h.nrej; o->evals = h.nevals;
+    o->health = h.health; o->done = h.done;
+}
+
+}  // namespace
+
+extern "C" {
+
+llg_status llg_batch_create(int device, const llg_film_desc* films, int nfilms, llg_batch** out) {
+    if (!out || !films || nfilms < 1) return LLG_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LLG_E_DEVICE;
+    if (device < 0 || device >= ndev) return LLG_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return LLG_E_DEVICE;
+    llg_batch* b = new llg_batch();
+    b->device = device;
+    *out = b;
+    BCHK(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    b->films.resize(nfilms);
+    for (int i = 0; i < nfilms; ++i) {
+        const llg_film_desc& d = films[i];
+        BatchFilm& f = b->films[i];
+        if (d.nx < 1 || d.ny < 1 || !(d.dx > 0 && d.dy > 0 && d.dz > 0) || !(d.Ms > 0) || !(d.Aex >= 0) ||
+            !(d.alpha >= 0) || !d.m0)
+            return bfail(b, LLG_E_ARG, "film %d: invalid parameters", i);
+        const double un = sqrt(d.u[0] * d.u[0] + d.u[1] * d.u[1] + d.u[2] * d.u[2]);
+        if (!(un > 0)) return bfail(b, LLG_E_ARG, "film %d: anisotropy axis must be non-zero", i);
+        const int Px = pad_len(d.nx), Py = pad_len(d.ny);
+        const int L = Py / 2;
+        if (!fast2d_row_ok(Px) || !fast2d_col_ok(L, 1) || (Px / 2) % fast2d_col_width(L) || d.ny > L)
+            return bfail(b, LLG_E_UNSUPPORTED,
+                         "film %d: %d x %d needs FFT lengths %d x %d without a compiled batched kernel", i,
+                         d.nx, d.ny, Px, Py);
+        f.mat.Ms = d.Ms; f.mat.Aex = d.Aex; f.mat.alpha = d.alpha; f.mat.Ku = d.Ku;
+        for (int a = 0; a < 3; ++a) { f.mat.u[a] = d.u[a]; f.mat.B[a] = d.B[a]; }
+        f.mat.d[0] = d.dx; f.mat.d[1] = d.dy; f.mat.d[2] = d.dz;
+        f.mat.terms = LLG_TERM_ALL & ~LLG_TERM_THERMAL;
+        Grid& g = f.g;
+        g.nx = d.nx; g.ny = d.ny; g.nz = 1;
+        g.nrows = d.ny; g.ncells = d.nx * d.ny;
+        g.Px = Px; g.Py = Py; g.Pz = 1;
+        g.nkx = Px / 2 + 1;
+        g.nkxp = (g.nkx + 15) / 16 * 16;
+        g.split_y = 1; g.split_z = 0;
+        const int rpb = fast2d_row_rows_per_block(Px);
+        f.row_blocks = (g.nrows + rpb - 1) / rpb;
+        f.col_blocks = (Px / 2) / fast2d_col_width(L);
+        b->lds_fwd = std::max(b->lds_fwd, fast2d_row_fwd_lds(Px));
+        b->lds_inv = std::max(b->lds_inv, fast2d_row_inv_lds(Px));
+        b->lds_col = std::max(b->lds_col, fast2d_col_lds(L));
+        const size_t vec = sizeof(float) * 3 * (size_t)g.ncells;
+        BCHK(b, make_tw(Px, &f.twx));
+        BCHK(b, make_tw(Py, &f.twy));
+        BCHK(b, hipMalloc(&f.S, sizeof(float2) * 3 * (size_t)g.nrows * g.nkxp));
+        BCHK(b, hipMalloc(&f.K, sizeof(float) * 4 * (size_t)g.nkx * (Py / 2 + 1)));
+        for (auto& p : f.mbuf) BCHK(b, hipMalloc(&p, vec));
+        for (auto& p : f.ms) BCHK(b, hipMalloc(&p, vec));
+        for (auto& p : f.kb) BCHK(b, hipMalloc(&p, vec));
+        for (auto& p : f.kfs) BCHK(b, hipMalloc(&p, vec));
+        BCHK(b, hipMalloc(&f.log, sizeof(llg_attempt) * b->log_cap));
+        // demag kernel spectrum (FP64 build, FP32 store)
+        TensorGeom tg = {};
+        const double dm = std::max(d.dx, std::max(d.dy, d.dz));
+        tg.n[0] = d.nx; tg.n[1] = d.ny; tg.n[2] = 1;
+        tg.P[0] = Px; tg.P[1] = Py; tg.P[2] = 1;
+        tg.d[0] = d.dx / dm; tg.d[1] = d.dy / dm; tg.d[2] = d.dz / dm;
+        tg.images = 0;
+        double resid = 0.0;
+        BCHK(b, build_kernel_spectrum(g, tg, f.K, &resid, b->stream));
+        if (!(resid <= 1e-9)) return bfail(b, LLG_E_DEVICE, "film %d: kernel spectrum not real (%g)", i, resid);
+        // initial magnetisation, checked and renormalised
+        int* bad = nullptr;
+        int hbad = 0;
+        BCHK(b, hipMalloc(&bad, sizeof(int)));
+        BCHK(b, hipMemsetAsync(bad, 0, sizeof(int), b->stream));
+        BCHK(b, hipMemcpyAsync(f.mbuf[0], d.m0, vec, hipMemcpyHostToDevice, b->stream));
+        BCHK(b, launch_normalize_check(f.mbuf[0], g.ncells, bad, b->stream));
+        BCHK(b, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+        BCHK(b, hipStreamSynchronize(b->stream));
+        bfree(bad);
+        if (hbad) return bfail(b, LLG_E_ARG, "film %d: m is not a field of unit vectors", i);
+    }
+    std::vector<DevState> h(nfilms);
+    for (int i = 0; i < nfilms; ++i) {
+        h[i] = DevState{};
+        h[i].log = b->films[i].log;
+        h[i].log_cap = b->log_cap;
+        h[i].gms = kGamma0 * b->films[i].mat.Ms;
+    }
+    BCHK(b, hipMalloc(&b->st, sizeof(DevState) * nfilms));
+    llg_status rc = write_states(b, h);
+    if (rc != LLG_OK) return rc;
+    return build_launch_args(b);
+}
+
+void llg_batch_destroy(llg_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (auto& f : b->films) {
+        bfree(f.twx); bfree(f.twy); bfree(f.K); bfree(f.S); bfree(f.log);
+        for (auto p : f.mbuf) bfree(p);
+        for (auto p : f.ms) bfree(p);
+        for (auto p : f.kb) bfree(p);
+        for (auto p : f.kfs) bfree(p);
+    }
+    bfree(b->st);
+    bfree(b->d_fwd_plain); bfree(b->d_konly); bfree(b->d_prep); bfree(b->d_col);
+    for (auto p : b->d_stage) bfree(p);
+    bfree(b->d_rowmap); bfree(b->d_colmap);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+const char* llg_batch_last_error(const llg_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0, int64_t max_attempts,
+                         llg_stats* per_film) {
+    if (!b) return LLG_E_ARG;
+    b->err.clear();
+    BCHK(b, hipSetDevice(b->device));
+    if (!(max_err > 0) || !(dt0 > 0) || !isfinite(t_end)) return bfail(b, LLG_E_ARG, "need max_err > 0, dt0 > 0");
+    const int nf = (int)b->films.size();
+    std::vector<DevState> h;
+    llg_status rc = read_states(b, h);
+    if (rc != LLG_OK) return rc;
+    if (!b->k1_valid) {
+        BCHK(b, launch_row_fwd_group(b->d_fwd_plain, b->d_rowmap, b->nrowblk, b->lds_fwd, b->stream));
+        BCHK(b, launch_col_group(b->d_col, b->d_colmap, b->ncolblk, b->lds_col, b->stream));
+        BCHK(b, launch_row_inv_group(b->d_konly, b->d_rowmap, b->nrowblk, b->lds_inv, b->stream));
+        b->k1_valid = true;
+        for (auto& s : h) s.nevals += 1;
+    }
+    for (auto& s : h) {
+        if (s.health) return bfail(b, LLG_E_DIVERGED, "a film has already diverged");
+        s.t_end = t_end;
+        s.tol = max_err;
+        s.dt_min = kDtMin;
+        s.err_bits = 0u;
+        s.done = !(t_end > s.t);
+        const double rem = t_end - s.t;
+        if (dt0 >= rem) { s.dt = rem; s.clipped = 1; } else { s.dt = dt0; s.clipped = 0; }
+        s.dtau = (float)(s.dt * s.gms);
+    }
+    if ((rc = write_states(b, h)) != LLG_OK) return rc;
+    if (!b->graph) {
+        hipGraph_t graph = nullptr;
+        BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_attempt(b);
+        hipError_t e = hipStreamEndCapture(b->stream, &graph);
+        if (rc != LLG_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        BCHK(b, e);
+        e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        BCHK(b, e);
+    }
+    long long launched = 0;
+    for (;;) {
+        int nl = 8;
+        if (max_attempts > 0) {
+            const long long left = max_attempts - launched;
+            if (left <= 0) break;
+            nl = (int)std::min<long long>(nl, left);
+        }
+        for (int i = 0; i < nl; ++i) BCHK(b, hipGraphLaunch(b->graph, b->stream));
+        launched += nl;
+        if ((rc = read_states(b, h)) != LLG_OK) return rc;
+        bool all = true;
+        for (auto& s : h) all = all && s.done;
+        if (all) break;
+    }
+    if (per_film)
+        for (int i = 0; i < nf; ++i) fill(h[i], per_film + i);
+    for (auto& s : h)
+        if (s.health) return bfail(b, LLG_E_DIVERGED, "a film diverged (health %d)", s.health);
+    return LLG_OK;
+}
+
+llg_status llg_batch_get_m(llg_batch* b, int film, float* m) {
+    if (!b || !m || film < 0 || film >= (int)b->films.size()) return LLG_E_ARG;
+    BCHK(b, hipSetDevice(b->device));
+    std::vector<DevState> h;
+    llg_status rc = read_states(b, h);
+    if (rc != LLG_OK) return rc;
+    const BatchFilm& f = b->films[film];
+    BCHK(b, hipMemcpyAsync(m, f.mbuf[h[film].cur], sizeof(float) * 3 * (size_t)f.g.ncells,
+                           hipMemcpyDeviceToHost, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    return LLG_OK;
+}
+
+llg_status llg_batch_get_attempts(llg_batch* b, int film, llg_attempt* out, int64_t cap, int64_t* n) {
+    if (!b || !n || film < 0 || film >= (int)b->films.size() || (cap > 0 && !out)) return LLG_E_ARG;
+    BCHK(b, hipSetDevice(b->device));
+    std::vector<DevState> h;
+    llg_status rc = read_states(b, h);
+    if (rc != LLG_OK) return rc;
+    long long have = std::min<long long>(h[film].nattempt, b->log_cap);
+    have = std::min<long long>(have, cap);
+    *n = have;
+    if (have > 0) {
+        BCHK(b, hipMemcpyAsync(out, b->films[film].log, sizeof(llg_attempt) * have, hipMemcpyDeviceToHost,
+                               b->stream));
+        BCHK(b, hipStreamSynchronize(b->stream));
+    }
+    return LLG_OK;
+}
+
+}  // extern "C"

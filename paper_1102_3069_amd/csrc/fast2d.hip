@@ -43,12 +43,27 @@ __device__ __forceinline__ float2 partner_odd(const float2 (&z)[E], int i, int l
 // ---------------------------------------------------------------------------
 // rows: forward transform of the new magnetisation and packed store
 // ---------------------------------------------------------------------------
+constexpr int lds_align(int b) { return (b + 15) / 16 * 16; }
+
 template <int PX, int E>
 struct RowFast {
     static constexpr int P = PX / E;
     static constexpr int RP = 64 / P;
     static constexpr int HE = E / 2;
+    static constexpr int SC = LfScratch<PX>::size;
+    static constexpr int NR = 2 * RP + 2;               // staged m rows
     using F = LaneFFT<PX, E, 1, float2>;
+    // dynamic LDS carve-up (bytes): twiddles, FFT scratch, exchange rows,
+    // staged m rows, staged m0 rows, reduction slots
+    static constexpr int O_TW = 0;
+    static constexpr int O_SCR = lds_align(O_TW + PX * 8);
+    static constexpr int O_XCH = lds_align(O_SCR + 3 * RP * SC * 8);
+    static constexpr int O_M = lds_align(O_XCH + RP * 2 * PX * 4);
+    static constexpr int fwd_bytes() { return O_M; }
+    template <bool XPER> static constexpr int nxm() { return XPER ? PX : PX / 2; }
+    template <bool XPER> static constexpr int o_m0() { return lds_align(O_M + NR * 3 * nxm<XPER>() * 4); }
+    template <bool XPER> static constexpr int o_wmax() { return lds_align(o_m0<XPER>() + 2 * RP * 3 * nxm<XPER>() * 4); }
+    template <bool XPER> static constexpr int inv_bytes() { return lds_align(o_wmax<XPER>() + 16); }
 
     // kind 0/1 lanes hold the new (mx, my, mz) of their row in nx/ny/nz
     // (cells x = lg + P i); kind 2 lanes collect mz of both rows from xch.
@@ -109,20 +124,20 @@ struct RowFast {
 };
 
 template <int PX, int E>
-__global__ __launch_bounds__(FRT) void row_fwd_fast(Grid g, const float2* __restrict__ twx,
-                                                    float2* __restrict__ S, FwdArgs fa,
-                                                    DevState* __restrict__ st) {
+__device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __restrict__ twx,
+                                             float2* __restrict__ S, const FwdArgs& fa,
+                                             DevState* __restrict__ st, int blk, char* lds) {
     using R = RowFast<PX, E>;
     constexpr int P = R::P, RP = R::RP;
-    __shared__ float2 tw[PX];
-    __shared__ float2 scr[3 * RP][LfScratch<PX>::size];
-    __shared__ float xch[RP][2 * PX];
+    float2* tw = (float2*)(lds + R::O_TW);
+    float2* scr = (float2*)(lds + R::O_SCR);
+    float* xch = (float*)(lds + R::O_XCH);
     if (st->done) return;
     const int tid = threadIdx.x;
     const int gi = tid / P, lg = tid % P;
     const int pair = gi / 3, kind = gi % 3;
     const int gbase = (tid & 63) - lg;
-    const int r0 = 2 * (blockIdx.x * RP + pair);
+    const int r0 = 2 * (blk * RP + pair);
     const bool v0 = r0 < g.nrows, v1 = r0 + 1 < g.nrows;
     for (int m = tid; m < PX; m += FRT) tw[m] = twx[m];
     const int cur = st->cur;
@@ -155,7 +170,15 @@ __global__ __launch_bounds__(FRT) void row_fwd_fast(Grid g, const float2* __rest
         }
     }
     __syncthreads();   // twiddle table
-    R::forward_store(g, S, scr[gi], tw, &xch[pair][0], nmx, nmy, nmz, kind, lg, gbase, r0, v0, v1);
+    R::forward_store(g, S, scr + gi * R::SC, tw, xch + pair * 2 * PX, nmx, nmy, nmz, kind, lg, gbase, r0, v0, v1);
+}
+
+template <int PX, int E>
+__global__ __launch_bounds__(FRT) void row_fwd_fast(Grid g, const float2* __restrict__ twx,
+                                                    float2* __restrict__ S, FwdArgs fa,
+                                                    DevState* __restrict__ st) {
+    extern __shared__ char dyn_lds[];
+    row_fwd_body<PX, E>(g, twx, S, fa, st, blockIdx.x, dyn_lds);
 }
 
 // exchange + anisotropy + applied + thermal field of cell x of a row whose
@@ -196,27 +219,27 @@ __device__ __forceinline__ void local_field_lds(const Grid& g, const Phys& p, co
 
 // XPER: the x axis is periodic (nx == PX), else nx <= PX/2
 template <int PX, int E, bool XPER>
-__global__ __launch_bounds__(FRT) void row_inv_fast(Grid g, Phys p, const float2* __restrict__ twx,
-                                                    float2* __restrict__ S, StageArgs sa,
-                                                    DevState* __restrict__ st) {
+__device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const float2* __restrict__ twx,
+                                             float2* __restrict__ S, const StageArgs& sa,
+                                             DevState* __restrict__ st, int blk, char* lds) {
     using R = RowFast<PX, E>;
     using F = typename R::F;
     constexpr int P = R::P, RP = R::RP;
-    constexpr int NXM = XPER ? PX : PX / 2;      // largest nx
-    constexpr int IC = XPER ? E : E / 2;         // cell slots per lane
-    constexpr int NR = 2 * RP + 2;               // staged m rows (with the y neighbours)
-    __shared__ float2 tw[PX];
-    __shared__ float2 scr[3 * RP][LfScratch<PX>::size];
-    __shared__ float xch[RP][2 * PX];
-    __shared__ float mrow[NR][3 * NXM];
-    __shared__ float m0row[2 * RP][3 * NXM];
-    __shared__ float wmax[FRT / 64];
+    constexpr int NXM = R::template nxm<XPER>();     // largest nx
+    constexpr int IC = XPER ? E : E / 2;             // cell slots per lane
+    constexpr int NR = R::NR;                        // staged m rows (with the y neighbours)
+    float2* tw = (float2*)(lds + R::O_TW);
+    float2* scr = (float2*)(lds + R::O_SCR);
+    float* xch = (float*)(lds + R::O_XCH);
+    float* mrow = (float*)(lds + R::O_M);
+    float* m0row = (float*)(lds + R::template o_m0<XPER>());
+    float* wmax = (float*)(lds + R::template o_wmax<XPER>());
     if (st->done) return;
     const int tid = threadIdx.x;
     const int gi = tid / P, lg = tid % P;
     const int pair = gi / 3, kind = gi % 3;
     const int gbase = (tid & 63) - lg;
-    const int rb = 2 * blockIdx.x * RP;             // first row of the block
+    const int rb = 2 * blk * RP;                    // first row of the block
     const int r0 = rb + 2 * pair;
     const bool v0 = r0 < g.nrows, v1 = r0 + 1 < g.nrows;
     const int cur = st->cur;
@@ -239,14 +262,14 @@ __global__ __launch_bounds__(FRT) void row_inv_fast(Grid g, Phys p, const float2
         int row = rb - 1 + q;
         bool ok = row >= 0 && row < g.nrows;
         if (g.pbc[1]) { row = (row + ny) % ny; ok = true; }
-        mrow[q][t] = ok ? mi[c * cs + (long long)row * nx + x] : 0.f;
+        mrow[q * 3 * NXM + t] = ok ? mi[c * cs + (long long)row * nx + x] : 0.f;
     }
     if (stage) {
         for (int e = tid; e < 2 * RP * 3 * nx; e += FRT) {
             const int q = e / (3 * nx), t = e - q * 3 * nx;
             const int c = t / nx, x = t - c * nx;
             const int row = rb + q;
-            m0row[q][t] = row < g.nrows ? m0[c * cs + (long long)row * nx + x] : 0.f;
+            m0row[q * 3 * NXM + t] = row < g.nrows ? m0[c * cs + (long long)row * nx + x] : 0.f;
         }
     }
     float2 z[E];
@@ -281,12 +304,12 @@ __global__ __launch_bounds__(FRT) void row_inv_fast(Grid g, Phys p, const float2
     }
     __syncthreads();   // twiddles and staged rows
     if (p.demag_on) {
-        F::template run<true>(z, scr[gi], tw, lg);
+        F::template run<true>(z, scr + gi * R::SC, tw, lg);
         if (kind == 2) {
 #pragma unroll
             for (int i = 0; i < IC; ++i) {
                 const int x = lg + P * i;
-                if (x < nx) { xch[pair][x] = z[i].x; xch[pair][PX + x] = z[i].y; }
+                if (x < nx) { xch[pair * 2 * PX + x] = z[i].x; xch[pair * 2 * PX + PX + x] = z[i].y; }
             }
         }
     }
@@ -298,9 +321,9 @@ __global__ __launch_bounds__(FRT) void row_inv_fast(Grid g, Phys p, const float2
     const bool vr = kind < 2 && (rr == 0 ? v0 : v1);
     const int q = 2 * pair + rr + 1;              // staged row of this lane's cells
     const int y = r % ny;
-    const float* rc = mrow[q];
-    const float* rm = (y > 0 || g.pbc[1]) ? mrow[q - 1] : nullptr;
-    const float* rp = (y < ny - 1 || g.pbc[1]) ? mrow[q + 1] : nullptr;
+    const float* rc = mrow + q * 3 * NXM;
+    const float* rm = (y > 0 || g.pbc[1]) ? rc - 3 * NXM : nullptr;
+    const float* rp = (y < ny - 1 || g.pbc[1]) ? rc + 3 * NXM : nullptr;
     if (ny == 1) { rm = nullptr; rp = nullptr; }
     float kx[IC], ky[IC], kz[IC];
     bool bad = false;
@@ -310,7 +333,7 @@ __global__ __launch_bounds__(FRT) void row_inv_fast(Grid g, Phys p, const float2
         const int x = lg + P * i;
         if (!(vr && x < nx)) continue;
         float hx = 0.f, hy = 0.f, hz = 0.f;
-        if (p.demag_on) { hx = z[i].x; hy = z[i].y; hz = xch[pair][rr * PX + x]; }
+        if (p.demag_on) { hx = z[i].x; hy = z[i].y; hz = xch[pair * 2 * PX + rr * PX + x]; }
         local_field_lds(g, p, rm, rc, rp, r, x, step, hx, hy, hz);
         if (sa.mode == ROW_EVAL) {
             float* h = sa.h_out;
@@ -333,7 +356,7 @@ __global__ __launch_bounds__(FRT) void row_inv_fast(Grid g, Phys p, const float2
     for (int i = 0; i < IC; ++i) {
         const int x = lg + P * i;
         const bool ok = vr && x < nx;
-        const float* m0r = m0row[2 * pair + rr];
+        const float* m0r = m0row + (2 * pair + rr) * 3 * NXM;
         ax[i] = cl * kx[i] + ((stage && ok) ? m0r[x] : 0.f);
         ay[i] = cl * ky[i] + ((stage && ok) ? m0r[nx + x] : 0.f);
         az[i] = cl * kz[i] + ((stage && ok) ? m0r[2 * nx + x] : 0.f);
@@ -389,8 +412,16 @@ __global__ __launch_bounds__(FRT) void row_inv_fast(Grid g, Phys p, const float2
     }
     if (stage && p.demag_on) {
         __syncthreads();   // everyone has read xch
-        R::forward_store(g, S, scr[gi], tw, &xch[pair][0], nmx, nmy, nmz, kind, lg, gbase, r0, v0, v1);
+        R::forward_store(g, S, scr + gi * R::SC, tw, xch + pair * 2 * PX, nmx, nmy, nmz, kind, lg, gbase, r0, v0, v1);
     }
+}
+
+template <int PX, int E, bool XPER>
+__global__ __launch_bounds__(FRT) void row_inv_fast(Grid g, Phys p, const float2* __restrict__ twx,
+                                                    float2* __restrict__ S, StageArgs sa,
+                                                    DevState* __restrict__ st) {
+    extern __shared__ char dyn_lds[];
+    row_inv_body<PX, E, XPER>(g, p, twx, S, sa, st, blockIdx.x, dyn_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -406,17 +437,22 @@ struct ColFast {
     static_assert(NT == 512, "column blocks have 512 threads");
     static constexpr int TM = SPLIT ? 2 : 1;
     using F = LaneFFT<L, E, TM, float2>;
+    static constexpr int SC = LfScratch<L>::size;
+    static constexpr int O_TW = 0;
+    static constexpr int O_SCR = lds_align(O_TW + L * TM * 8);
+    static constexpr int O_COMB = lds_align(O_SCR + UNITS * SC * 8);
+    static constexpr int bytes() { return lds_align(O_COMB + (SPLIT ? W * 3 * L * 8 : 16)); }
 };
 
 template <int L, int E, bool SPLIT>
-__global__ __launch_bounds__(512) void col2d_fast(Col2dArgs a, DevState* __restrict__ st) {
+__device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restrict__ st, int lb, char* lds) {
     using CF = ColFast<L, E, SPLIT>;
     using F = typename CF::F;
-    constexpr int P = CF::P, NH = CF::NH, W = CF::W, UNITS = CF::UNITS, NT = CF::NT;
+    constexpr int P = CF::P, NH = CF::NH, W = CF::W, NT = CF::NT;
     constexpr int TL = L * CF::TM;       // twiddle table length (= Py)
-    __shared__ float2 tw[TL];
-    __shared__ float2 scr[UNITS][LfScratch<L>::size];
-    __shared__ float2 comb[SPLIT ? W : 1][3][SPLIT ? L : 1];
+    float2* tw = (float2*)(lds + CF::O_TW);
+    float2* scr = (float2*)(lds + CF::O_SCR);
+    float2* comb = (float2*)(lds + CF::O_COMB);
     if (st->done) return;
     const int tid = threadIdx.x;
     const int u = tid / P, lg = tid % P;
@@ -424,7 +460,6 @@ __global__ __launch_bounds__(512) void col2d_fast(Col2dArgs a, DevState* __restr
     const int grp = u % 2;               // 0: x and y components, 1: z
     const int h = (u / 2) % NH;          // frequency half
     const int w = u / (2 * NH);
-    const int lb = xcd_remap_blocks(blockIdx.x, gridDim.x);
     const int kx = lb * W + w;
     const bool packed = kx == 0;
     for (int m = tid; m < TL; m += NT) tw[m] = a.tw[m];
@@ -480,8 +515,9 @@ __global__ __launch_bounds__(512) void col2d_fast(Col2dArgs a, DevState* __restr
             x1[i] = cmul(x1[i], t);
         }
     }
-    F::template run<false>(x0, scr[u], tw, lg);
-    if (grp == 0) F::template run<false>(x1, scr[u], tw, lg);
+    float2* sc = scr + u * CF::SC;
+    F::template run<false>(x0, sc, tw, lg);
+    if (grp == 0) F::template run<false>(x1, sc, tw, lg);
 
     if (!packed) {
         if (grp == 0) {
@@ -530,8 +566,8 @@ __global__ __launch_bounds__(512) void col2d_fast(Col2dArgs a, DevState* __restr
             }
         }
     }
-    F::template run<true>(x0, scr[u], tw, lg);
-    if (grp == 0) F::template run<true>(x1, scr[u], tw, lg);
+    F::template run<true>(x0, sc, tw, lg);
+    if (grp == 0) F::template run<true>(x1, sc, tw, lg);
 
     const int cA = grp == 0 ? 0 : 2;
     if (SPLIT) {
@@ -541,8 +577,8 @@ __global__ __launch_bounds__(512) void col2d_fast(Col2dArgs a, DevState* __restr
                 const int y = lg + P * i;
                 if (y < ny) {
                     const float2 t = cconj(tw[y]);
-                    comb[w][cA][y] = cmul(x0[i], t);
-                    if (grp == 0) comb[w][1][y] = cmul(x1[i], t);
+                    comb[(w * 3 + cA) * L + y] = cmul(x0[i], t);
+                    if (grp == 0) comb[(w * 3 + 1) * L + y] = cmul(x1[i], t);
                 }
             }
         }
@@ -557,14 +593,71 @@ __global__ __launch_bounds__(512) void col2d_fast(Col2dArgs a, DevState* __restr
         if (y < ny) {
             float2 v0 = x0[i], v1 = x1[i];
             if (SPLIT) {
-                const float2 c0v = comb[w][cA][y];
+                const float2 c0v = comb[(w * 3 + cA) * L + y];
                 v0 = mk2(v0.x + c0v.x, v0.y + c0v.y);
-                if (grp == 0) { const float2 c1v = comb[w][1][y]; v1 = mk2(v1.x + c1v.x, v1.y + c1v.y); }
+                if (grp == 0) { const float2 c1v = comb[(w * 3 + 1) * L + y]; v1 = mk2(v1.x + c1v.x, v1.y + c1v.y); }
             }
             o0[(long long)y * a.nkxp] = v0;
             if (grp == 0) o1[(long long)y * a.nkxp] = v1;
         }
     }
+}
+
+template <int L, int E, bool SPLIT>
+__global__ __launch_bounds__(512) void col2d_fast(Col2dArgs a, DevState* __restrict__ st) {
+    extern __shared__ char dyn_lds[];
+    col2d_body<L, E, SPLIT>(a, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
+}
+
+// ---------------------------------------------------------------------------
+// grouped launches: one launch runs a pass for many films of different
+// sizes; block b works on film map[b].x, local block map[b].y
+// ---------------------------------------------------------------------------
+#define ROW_GROUP_SIZES(X) X(64, 8) X(128, 8) X(192, 12) X(256, 8) X(384, 12) X(512, 8) X(768, 12) X(1024, 16)
+#define COL_GROUP_SIZES(X) X(32, 8) X(64, 8) X(96, 12) X(128, 8) X(192, 12) X(256, 8) X(384, 12) X(512, 8)
+
+__global__ __launch_bounds__(FRT) void row_fwd_group(const FilmRow* __restrict__ films,
+                                                     const int2* __restrict__ map) {
+    extern __shared__ char dyn_lds[];
+    const int2 m = map[blockIdx.x];
+    const FilmRow& f = films[m.x];
+    switch (f.g.Px) {
+#define CASE(PX, E) case PX: row_fwd_body<PX, E>(f.g, f.twx, f.S, f.fa, f.st, m.y, dyn_lds); break;
+        ROW_GROUP_SIZES(CASE)
+#undef CASE
+        default: break;
+    }
+}
+
+__global__ __launch_bounds__(FRT) void row_inv_group(const FilmRow* __restrict__ films,
+                                                     const int2* __restrict__ map) {
+    extern __shared__ char dyn_lds[];
+    const int2 m = map[blockIdx.x];
+    const FilmRow& f = films[m.x];
+    switch (f.g.Px) {
+#define CASE(PX, E) case PX: row_inv_body<PX, E, false>(f.g, f.p, f.twx, f.S, f.sa, f.st, m.y, dyn_lds); break;
+        ROW_GROUP_SIZES(CASE)
+#undef CASE
+        default: break;
+    }
+}
+
+__global__ __launch_bounds__(512) void col_group(const FilmCol* __restrict__ films, const int2* __restrict__ map) {
+    extern __shared__ char dyn_lds[];
+    const int2 m = map[blockIdx.x];
+    const FilmCol& f = films[m.x];
+    switch (f.a.Py / 2) {
+#define CASE(LL, E) case LL: col2d_body<LL, E, true>(f.a, f.st, m.y, dyn_lds); break;
+        COL_GROUP_SIZES(CASE)
+#undef CASE
+        default: break;
+    }
+}
+
+// kernels whose dynamic LDS may exceed 64 KB need the limit raised once
+static hipError_t allow_lds(const void* kernel, int bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 }  // namespace
@@ -596,8 +689,11 @@ hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, cons
 #define CASE(PX, E)                                                                       \
     if (g.Px == PX) {                                                                     \
         constexpr int rows = 2 * RowFast<PX, E>::RP;                                      \
-        hipLaunchKernelGGL((row_fwd_fast<PX, E>), dim3((g.nrows + rows - 1) / rows), dim3(FRT), 0, s, \
-                           g, twx, S, fa, st);                                            \
+        constexpr int lds = RowFast<PX, E>::fwd_bytes();                                  \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E>), lds); \
+        if (e_ != hipSuccess) return e_;                                                  \
+        hipLaunchKernelGGL((row_fwd_fast<PX, E>), dim3((g.nrows + rows - 1) / rows), dim3(FRT), \
+                           lds, s, g, twx, S, fa, st);                                    \
         return hipGetLastError();                                                         \
     }
     ROW_SIZES(CASE)
@@ -613,10 +709,17 @@ hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, 
     if (g.Px == PX) {                                                                     \
         constexpr int rows = 2 * RowFast<PX, E>::RP;                                      \
         const dim3 grid((g.nrows + rows - 1) / rows);                                     \
+        constexpr int lds_p = RowFast<PX, E>::template inv_bytes<true>();                 \
+        constexpr int lds_o = RowFast<PX, E>::template inv_bytes<false>();                \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, true>), lds_p); \
+        if (e_ == hipSuccess) e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, false>), lds_o); \
+        if (e_ != hipSuccess) return e_;                                                  \
         if (g.nx == PX)                                                                   \
-            hipLaunchKernelGGL((row_inv_fast<PX, E, true>), grid, dim3(FRT), 0, s, g, p, twx, S, sa, st); \
+            hipLaunchKernelGGL((row_inv_fast<PX, E, true>), grid, dim3(FRT),              \
+                               lds_p, s, g, p, twx, S, sa, st);                           \
         else if (2 * g.nx <= PX)                                                          \
-            hipLaunchKernelGGL((row_inv_fast<PX, E, false>), grid, dim3(FRT), 0, s, g, p, twx, S, sa, st); \
+            hipLaunchKernelGGL((row_inv_fast<PX, E, false>), grid, dim3(FRT),             \
+                               lds_o, s, g, p, twx, S, sa, st);                           \
         else                                                                              \
             return hipErrorInvalidValue;                                                  \
         return hipGetLastError();                                                         \
@@ -633,12 +736,65 @@ hipError_t launch_col2d_fast(const Col2dArgs& a, DevState* st, hipStream_t s) {
     if (L == LL) {                                                                        \
         using CF = ColFast<LL, E, true>;                                                  \
         if (a.nkx % CF::W) return hipErrorInvalidValue;                                   \
-        hipLaunchKernelGGL((col2d_fast<LL, E, true>), dim3(a.nkx / CF::W), dim3(CF::NT), 0, s, a, st); \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&col2d_fast<LL, E, true>), CF::bytes());                  \
+        if (e_ != hipSuccess) return e_;                                                  \
+        hipLaunchKernelGGL((col2d_fast<LL, E, true>), dim3(a.nkx / CF::W), dim3(CF::NT), CF::bytes(), s, a, st); \
         return hipGetLastError();                                                         \
     }
     COL_SIZES(CASE)
 #undef CASE
     return hipErrorInvalidValue;
+}
+
+// ---- grouped launchers ------------------------------------------------------------
+int fast2d_row_rows_per_block(int Px) {
+#define CASE(PX, E) if (Px == PX) return 2 * RowFast<PX, E>::RP;
+    ROW_GROUP_SIZES(CASE)
+#undef CASE
+    return 0;
+}
+int fast2d_row_fwd_lds(int Px) {
+#define CASE(PX, E) if (Px == PX) return RowFast<PX, E>::fwd_bytes();
+    ROW_GROUP_SIZES(CASE)
+#undef CASE
+    return 0;
+}
+int fast2d_row_inv_lds(int Px) {
+#define CASE(PX, E) if (Px == PX) return RowFast<PX, E>::template inv_bytes<false>();
+    ROW_GROUP_SIZES(CASE)
+#undef CASE
+    return 0;
+}
+int fast2d_col_width(int L) {
+#define CASE(LL, E) if (L == LL) return ColFast<LL, E, true>::W;
+    COL_GROUP_SIZES(CASE)
+#undef CASE
+    return 0;
+}
+int fast2d_col_lds(int L) {
+#define CASE(LL, E) if (L == LL) return ColFast<LL, E, true>::bytes();
+    COL_GROUP_SIZES(CASE)
+#undef CASE
+    return 0;
+}
+
+hipError_t launch_row_fwd_group(const FilmRow* films, const int2* map, int nblocks, int lds, hipStream_t s) {
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&row_fwd_group), lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(row_fwd_group, dim3(nblocks), dim3(FRT), lds, s, films, map);
+    return hipGetLastError();
+}
+hipError_t launch_row_inv_group(const FilmRow* films, const int2* map, int nblocks, int lds, hipStream_t s) {
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&row_inv_group), lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(row_inv_group, dim3(nblocks), dim3(FRT), lds, s, films, map);
+    return hipGetLastError();
+}
+hipError_t launch_col_group(const FilmCol* films, const int2* map, int nblocks, int lds, hipStream_t s) {
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&col_group), lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(col_group, dim3(nblocks), dim3(512), lds, s, films, map);
+    return hipGetLastError();
 }
 
 }  // namespace llg

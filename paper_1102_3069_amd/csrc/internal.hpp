@@ -157,6 +157,30 @@ hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, 
                                const StageArgs& sa, DevState* st, hipStream_t s);
 hipError_t launch_col2d_fast(const Col2dArgs& a, DevState* st, hipStream_t s);
 
+// grouped (multi-film) launches: per-film arguments of one pass
+struct FilmRow {
+    Grid g;
+    Phys p;
+    const float2* twx;
+    float2* S;
+    DevState* st;
+    StageArgs sa;     // row_inv
+    FwdArgs fa;       // row_fwd
+};
+struct FilmCol {
+    Col2dArgs a;
+    DevState* st;
+};
+int fast2d_row_rows_per_block(int Px);
+int fast2d_row_fwd_lds(int Px);
+int fast2d_row_inv_lds(int Px);
+int fast2d_col_width(int L);
+int fast2d_col_lds(int L);
+hipError_t launch_row_fwd_group(const FilmRow* films, const int2* map, int nblocks, int lds, hipStream_t s);
+hipError_t launch_row_inv_group(const FilmRow* films, const int2* map, int nblocks, int lds, hipStream_t s);
+hipError_t launch_col_group(const FilmCol* films, const int2* map, int nblocks, int lds, hipStream_t s);
+hipError_t launch_ctrl_dp45_group(DevState* states, int nfilms, hipStream_t s);
+
 // ---- demag tensor (tensor.hip) --------------------------------------------------
 struct TensorGeom {
     int n[3];

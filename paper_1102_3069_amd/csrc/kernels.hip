@@ -430,8 +430,7 @@ __global__ void ctrl_fixed_kernel(DevState* st, int evals) {
 
 // Dormand-Prince step control: accept if err <= tol, next step
 // dt * clamp(0.9 (tol/err)^(1/5), 0.2, 5), last step lands on t_end.
-__global__ void ctrl_dp45_kernel(DevState* st) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void dp45_control(DevState* st) {
     if (st->done) return;
     const float errf = __uint_as_float(st->err_bits);
     st->err_bits = 0u;
@@ -467,6 +466,17 @@ __global__ void ctrl_dp45_kernel(DevState* st) {
     if (dn >= rem) { st->dt = rem; st->clipped = 1; }
     else { st->dt = dn; st->clipped = 0; }
     st->dtau = (float)(st->dt * st->gms);
+}
+
+__global__ void ctrl_dp45_kernel(DevState* st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    dp45_control(st);
+}
+
+// one thread per film of a batch
+__global__ void ctrl_dp45_group_kernel(DevState* states, int nfilms) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < nfilms) dp45_control(states + f);
 }
 
 __global__ void state_add_evals_kernel(DevState* st, int evals) {
@@ -589,6 +599,11 @@ hipError_t launch_ctrl_fixed(DevState* st, int evals, double dt, hipStream_t s) 
 
 hipError_t launch_ctrl_dp45(DevState* st, hipStream_t s) {
     hipLaunchKernelGGL(ctrl_dp45_kernel, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl_dp45_group(DevState* states, int nfilms, hipStream_t s) {
+    hipLaunchKernelGGL(ctrl_dp45_group_kernel, dim3((nfilms + 63) / 64), dim3(64), 0, s, states, nfilms);
     return hipGetLastError();
 }
 

@@ -1,0 +1,85 @@
+"""Batched films (one grouped launch per pass over all films): each film's
+result equals the single-film solver's bit for bit, does not depend on the
+order of films in the batch, and matches the FP64 oracle."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import llg as ollg
+
+pytestmark = pytest.mark.gpu
+
+
+def sweep(sides, seed):
+    rng = np.random.default_rng(seed)
+    films = []
+    for side in sides:
+        n = (side, side, 1)
+        prob = dict(n=n, cell=(4e-9, 4e-9, 3e-9), pbc=(False, False, False),
+                    Ms=float(rng.uniform(6e5, 1.2e6)), Aex=1.3e-11, alpha=float(rng.uniform(0.2, 0.5)),
+                    Ku=float(rng.uniform(0, 5e3)), u=(1.0, 0.0, 0.0),
+                    B=workloads.field_in_plane(float(rng.uniform(0, 0.1)), float(rng.uniform(0, 360))),
+                    T=0.0, seed=0)
+        films.append((prob, workloads.random_unit(n, int(rng.integers(1 << 30)))))
+    return films
+
+
+def maxrel(a, b):
+    a = np.asarray(a, dtype=np.float64).reshape(3, -1)
+    b = np.asarray(b, dtype=np.float64).reshape(3, -1)
+    return float(np.max(np.linalg.norm(a - b, axis=0)) / np.max(np.linalg.norm(b, axis=0)))
+
+
+def test_batch_equals_single_films_bitwise(lib):
+    films = sweep((32, 64, 96, 128, 64), 11)
+    b = lib.Batch(films)
+    st = b.run(4e-12, 1e-5, 1e-14)
+    assert all(s["done"] == 1 for s in st)
+    for i, (prob, m0) in enumerate(films):
+        s = lib.Solver(0)
+        s.set_problem(prob)
+        s.set_m(m0)
+        ss = s.run(4e-12, 1e-5, 1e-14)
+        assert b.attempts(i) == s.attempts()
+        assert np.array_equal(b.get_m(i), s.get_m())
+        assert st[i]["evals"] == ss["evals"] and st[i]["steps"] == ss["steps"]
+        print("film", i, prob["n"], "attempts", len(s.attempts()), "identical", flush=True)
+
+
+def test_batch_order_does_not_matter(lib):
+    films = sweep((32, 96, 64), 5)
+    a = lib.Batch(films)
+    a.run(3e-12, 1e-5, 1e-14)
+    perm = [2, 0, 1]
+    b = lib.Batch([films[p] for p in perm])
+    b.run(3e-12, 1e-5, 1e-14)
+    for j, p in enumerate(perm):
+        assert np.array_equal(b.get_m(j), a.get_m(p))
+
+
+def test_batch_film_matches_oracle(lib):
+    films = sweep((64, 32), 21)
+    b = lib.Batch(films)
+    b.run(3e-12, 1e-5, 1e-14)
+    for i, (prob, m0) in enumerate(films):
+        o = ollg.Solver(prob, m0)
+        o.replay([(dt, ok) for dt, _, ok in b.attempts(i)])
+        e = maxrel(b.get_m(i), o.m)
+        print("batch film", i, "m maxrel vs oracle", e, flush=True)
+        assert e <= 1e-5
+
+
+def test_batch_rejects_uncompiled_sizes(lib):
+    prob, m0 = workloads.small_problem(n=(17, 9, 1))
+    with pytest.raises(lib.LLGError) as e:
+        lib.Batch([(prob, m0)])
+    assert e.value.code == lib.LLG_E_UNSUPPORTED
+
+
+def test_full_sweep_creates_and_steps(lib):
+    """The 64-film sweep of uneven sizes (sides 64..256) in one batch."""
+    films, run = workloads.film_batch()
+    b = lib.Batch(films)
+    st = b.run(run["t_end"], run["tol"], run["dt0"], max_attempts=4)
+    assert all(s["health"] == 0 for s in st)
+    assert all(s["evals"] == 1 + 6 * 4 for s in st)

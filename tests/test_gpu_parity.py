@@ -319,3 +319,54 @@ def test_error_paths(lib):
     with pytest.raises(lib.LLGError) as e:
         s.set_geometry((7, 5, 1), (True, False, False))
     assert e.value.code == lib.LLG_E_UNSUPPORTED
+
+
+# --------------------------------------------------------------------------
+# thermal field and the 3D periodic path
+# --------------------------------------------------------------------------
+def test_thermal_steps_parity(lib):
+    """Fixed Heun steps with only the applied and thermal fields: the GPU
+    and the oracle draw the same Philox stream (24-bit uniforms, Box-Muller
+    in each precision), so the trajectories agree to rounding."""
+    prob, m0 = workloads.small_problem(n=(16, 12, 1), T=300.0, seed=77,
+                                       terms=("zeeman", "thermal"), alpha=0.1)
+    dt = 5e-14
+    s = make_solver(lib, prob, m0)
+    o = ollg.Solver(prob, m0)
+    s.step("heun", dt, 10)
+    o.step("heun", dt, 10)
+    e = maxrel(s.get_m(), o.m)
+    note("thermal heun m maxrel", e)
+    assert e <= 1e-5
+    h = s.eval_heff()
+    ref = fields.heff(s.get_m().astype(np.float64), prob, dt=dt, step=10)
+    eh = maxrel(h, ref)
+    note("thermal field maxrel", eh)
+    assert eh <= 1e-5
+
+
+def test_film_3d_scaled_parity(lib):
+    """The 3D workload's physics at 16 x 16 x 8 cells: periodic in x and y,
+    open z, 300 K thermal field, vortex start, Heun at 5e-14 s."""
+    prob, m0, run = workloads.film_3d((16, 16, 8))
+    prob["images"] = 3
+    s = make_solver(lib, prob, m0)
+    o = ollg.Solver(prob, m0)
+    for blk in range(3):
+        s.step("heun", run["dt"], 5)
+        o.step("heun", run["dt"], 5)
+        e = maxrel(s.get_m(), o.m)
+        note("3d step", (blk + 1) * 5, "m maxrel", e)
+        assert e <= 1e-5
+
+
+def test_film_3d_heff_parity(lib):
+    prob, m0, run = workloads.film_3d((32, 16, 6))
+    prob["images"] = 4
+    prob["terms"] = ("demag", "exchange", "anisotropy", "zeeman")
+    s = make_solver(lib, prob, m0)
+    h = s.eval_heff()
+    ref = fields.heff(m0.astype(np.float64), prob)
+    e = maxrel(h, ref)
+    note("3d heff maxrel", e)
+    assert e <= 1e-5
