@@ -231,8 +231,96 @@ const char *llg_batch_last_error(const llg_batch *b);
  * entries) may be NULL.  LLG_E_DIVERGED if any film diverged. */
 llg_status  llg_batch_run(llg_batch *b, double t_end, double max_err, double dt0,
                           int64_t max_attempts, llg_stats *per_film);
-llg_status  llg_batch_get_m(llg_batch *b, int film, float *m);
+/* Fixed steps (LLG_EULER, LLG_HEUN or LLG_RK4, Sec. 2.2) of size dt (s) for
+ * every film, one grouped launch per stage; the per-film arithmetic is that
+ * of llg_step on a single-film solver.  LLG_E_DIVERGED if a film's state
+ * becomes non-finite. */
+llg_status  llg_batch_step(llg_batch *b, llg_method method, double dt, int64_t nsteps);
+/* Replaces the state of one film (layout of llg_film_desc.m0; host or
+ * device memory on the batch's device), checked and renormalised as by
+ * llg_set_m; that film's time, counters and attempt log restart at 0. */
+llg_status  llg_batch_set_m(llg_batch *b, int film, const float *m, llg_mem where);
+/* Current state of one film into host or device memory. */
+llg_status  llg_batch_get_m(llg_batch *b, int film, float *m, llg_mem where);
 llg_status  llg_batch_get_attempts(llg_batch *b, int film, llg_attempt *out, int64_t cap, int64_t *n);
+
+/* ---- learned surrogate ------------------------------------------------------
+ * Not part of the paper's method: a small convolutional network that
+ * proposes the state of a film `seg_steps` fixed RK4 steps (Sec. 2.2) ahead,
+ * so that the plain solver can check many proposals at once instead of
+ * advancing one segment after another.  Every committed state comes from the
+ * plain solver; the network only decides how far a round may jump.
+ *
+ * Network: six 3x3 convolutions with zero ("same") padding,
+ *   6 -> 32, four times 32 -> 32, 32 -> 3, SiLU after all but the last;
+ *   input (m_x, m_y, m_z, B_x, B_y, B_z) / (1, 1, 1, 50 mT, 50 mT, 50 mT)
+ *   per cell, output dm; proposal m' = (m + dm) / |m + dm|.
+ * Parameters (FP32, host layout of llg_sur_set_params): per layer the
+ * weights [cout][cin][3][3] (cross-correlation: out[o][y][x] = b[o] +
+ * sum w[o][c][u][v] in[c][y+u-1][x+v-1]) followed by the bias [cout].
+ * Arithmetic: BF16 operands (round to nearest even) on MFMA with FP32
+ * accumulation; FP32 master weights, Adam (beta1 0.9, beta2 0.999, eps
+ * 1e-8, bias corrected) on the device.  States use the layout of
+ * llg_film_desc.m0 ([3][H][W] float); batches of states are contiguous.
+ */
+typedef struct llg_sur llg_sur;
+
+typedef struct {
+    int64_t rounds;          /* verification rounds (one batched plain launch each) */
+    int64_t proposals;       /* proposals compared with a plain segment             */
+    int64_t accepted;        /* proposals accepted                                  */
+    int64_t segments;        /* segments advanced                                   */
+    double max_dm_accepted;  /* largest max-cell |m' - m_plain| that was accepted   */
+    double max_dm_seen;      /* largest max-cell |m' - m_plain| compared            */
+} llg_sur_stats;
+
+/* A network for films of H x W cells and batches of up to max_batch states;
+ * parameters must be set before use. */
+llg_status  llg_sur_create(int device, int H, int W, int max_batch, llg_sur **out);
+void        llg_sur_destroy(llg_sur *s);
+const char *llg_sur_last_error(const llg_sur *s);
+/* Number of FP32 parameters (39,619). */
+int64_t     llg_sur_num_params(void);
+/* Host arrays of llg_sur_num_params() floats.  set_params also clears the
+ * Adam moments and step count. */
+llg_status  llg_sur_set_params(llg_sur *s, const float *params, int64_t n);
+llg_status  llg_sur_get_params(llg_sur *s, float *params, int64_t n);
+/* Gradient of the last llg_sur_train_step, parameter layout. */
+llg_status  llg_sur_get_grads(llg_sur *s, float *grads, int64_t n);
+/* Loss L = mean over cells, components and states of (dm - (m_target -
+ * m_in))^2 and its gradient for `batch` pairs (m_in, m_target) with applied
+ * fields B[batch][3] (tesla, host); then, if lr > 0, one Adam step with
+ * learning rate lr.  m_in and m_target in host or device memory per
+ * `where`.  *loss (host, may be NULL) receives L. */
+llg_status  llg_sur_train_step(llg_sur *s, const float *m_in, const float *m_target, const float *B,
+                               int batch, llg_mem where, float lr, float *loss);
+/* Proposals m' for `batch` states (host or device memory per `where`). */
+llg_status  llg_sur_predict(llg_sur *s, const float *m_in, const float *B, int batch, llg_mem where,
+                            float *m_out);
+/* Pre-activation of layer `layer` (0..5) for host inputs, [batch][H][W][32]
+ * float into host memory (channels past the layer's width are 0). */
+llg_status  llg_sur_forward_raw(llg_sur *s, const float *m_in, const float *B, int batch, int layer,
+                                float *z_out);
+/* One layer through the training kernels: x and gy [batch][H][W][32] float
+ * (host), rounded to BF16 on the device; y = conv(x) + bias and, if gy is not
+ * NULL, the weight, bias and input gradients of sum(gy * y) (host). */
+llg_status  llg_sur_conv_check(llg_sur *s, int layer, const float *x, const float *gy, int batch,
+                               float *y, float *gx, float *gw, float *gb);
+/* Advances the state m (host or device per `where`, overwritten) of `film`
+ * (its m0 is ignored; its size must be the network's) by n_segments
+ * segments of seg_steps RK4 steps of dt (s).  A round chains up to `window`
+ * proposals m'_1..m'_w from the current state m'_0; one batched plain launch
+ * advances m'_0..m'_{w-1} by a segment each, giving p_1..p_w; d_j = max over
+ * cells |m'_j - p_j|.  With j* the first j where d_j > max_dm (or w + 1),
+ * the round commits p_{min(j*, w)} and advances min(j*, w) segments.  With
+ * max_dm = 0 every round commits p_1, the plain segment.  `out` may be
+ * NULL. */
+llg_status  llg_sur_advance(llg_sur *s, const llg_film_desc *film, int window, int64_t n_segments,
+                            int seg_steps, double dt, double max_dm, float *m, llg_mem where,
+                            llg_sur_stats *out);
+/* Diagnostic: one 16x32 by 32x16 product (row-major float inputs rounded to
+ * BF16, host) by a single MFMA instruction, to check its lane layout. */
+llg_status  llg_mfma_selftest(int device, const float *A, const float *B, float *C);
 
 #ifdef __cplusplus
 }

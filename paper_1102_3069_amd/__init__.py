@@ -46,6 +46,15 @@ class Attempt(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("err", ctypes.c_float), ("accepted", ctypes.c_int32)]
 
 
+class SurStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("proposals", ctypes.c_int64), ("accepted", ctypes.c_int64),
+                ("segments", ctypes.c_int64), ("max_dm_accepted", ctypes.c_double),
+                ("max_dm_seen", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class FilmDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
@@ -91,9 +100,28 @@ _SIGNATURES = {
     "llg_batch_last_error": ([_P], ctypes.c_char_p),
     "llg_batch_run": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                        ctypes.POINTER(Stats)], ctypes.c_int),
-    "llg_batch_get_m": ([_P, ctypes.c_int, _P], ctypes.c_int),
+    "llg_batch_step": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_int64], ctypes.c_int),
+    "llg_batch_set_m": ([_P, ctypes.c_int, _P, ctypes.c_int], ctypes.c_int),
+    "llg_batch_get_m": ([_P, ctypes.c_int, _P, ctypes.c_int], ctypes.c_int),
     "llg_batch_get_attempts": ([_P, ctypes.c_int, ctypes.POINTER(Attempt), ctypes.c_int64,
                                 ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "llg_sur_create": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_P)],
+                       ctypes.c_int),
+    "llg_sur_destroy": ([_P], None),
+    "llg_sur_last_error": ([_P], ctypes.c_char_p),
+    "llg_sur_num_params": ([], ctypes.c_int64),
+    "llg_sur_set_params": ([_P, _P, ctypes.c_int64], ctypes.c_int),
+    "llg_sur_get_params": ([_P, _P, ctypes.c_int64], ctypes.c_int),
+    "llg_sur_get_grads": ([_P, _P, ctypes.c_int64], ctypes.c_int),
+    "llg_sur_train_step": ([_P, _P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                            ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "llg_sur_predict": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, _P], ctypes.c_int),
+    "llg_sur_forward_raw": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, _P], ctypes.c_int),
+    "llg_sur_conv_check": ([_P, ctypes.c_int, _P, _P, ctypes.c_int, _P, _P, _P, _P], ctypes.c_int),
+    "llg_sur_advance": ([_P, ctypes.POINTER(FilmDesc), ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                         ctypes.c_double, ctypes.c_double, _P, ctypes.c_int, ctypes.POINTER(SurStats)],
+                        ctypes.c_int),
+    "llg_mfma_selftest": ([ctypes.c_int, _P, _P, _P], ctypes.c_int),
 }
 EXPORTS = tuple(_SIGNATURES)
 
@@ -274,6 +302,24 @@ class Solver:
         return out
 
 
+def film_desc(prob, m0, d=None):
+    """Fills an llg_film_desc from a problem dict; returns the float32
+    (3, 1, ny, nx) copy of m0 that d.m0 points to (keep it alive)."""
+    d = FilmDesc() if d is None else d
+    nx, ny, nz = prob["n"]
+    if nz != 1:
+        raise LLGError(LLG_E_ARG, "batched films are one cell thick")
+    a = np.ascontiguousarray(m0, dtype=np.float32).reshape(3, 1, ny, nx)
+    d.nx, d.ny = nx, ny
+    d.dx, d.dy, d.dz = (float(c) for c in prob["cell"])
+    d.Ms, d.Aex, d.alpha = float(prob["Ms"]), float(prob["Aex"]), float(prob["alpha"])
+    d.Ku = float(prob.get("Ku", 0.0))
+    d.u = (ctypes.c_double * 3)(*[float(v) for v in prob.get("u", (1.0, 0.0, 0.0))])
+    d.B = (ctypes.c_double * 3)(*[float(v) for v in prob.get("B", (0.0, 0.0, 0.0))])
+    d.m0 = a.ctypes.data
+    return a
+
+
 class Batch:
     """Independent 2D films integrated together (see llg_batch_* in llg.h).
     films: list of (problem dict, m0 float32 array) as made by workloads.py."""
@@ -284,19 +330,9 @@ class Batch:
         self._keep = []
         descs = (FilmDesc * len(films))()
         for d, (prob, m0) in zip(descs, films):
-            nx, ny, nz = prob["n"]
-            if nz != 1:
-                raise LLGError(LLG_E_ARG, "batched films are one cell thick")
-            a = np.ascontiguousarray(m0, dtype=np.float32).reshape(3, 1, ny, nx)
+            a = film_desc(prob, m0, d)
             self._keep.append(a)
-            self.shapes.append((3, 1, ny, nx))
-            d.nx, d.ny = nx, ny
-            d.dx, d.dy, d.dz = (float(c) for c in prob["cell"])
-            d.Ms, d.Aex, d.alpha = float(prob["Ms"]), float(prob["Aex"]), float(prob["alpha"])
-            d.Ku = float(prob.get("Ku", 0.0))
-            d.u = (ctypes.c_double * 3)(*[float(v) for v in prob.get("u", (1.0, 0.0, 0.0))])
-            d.B = (ctypes.c_double * 3)(*[float(v) for v in prob.get("B", (0.0, 0.0, 0.0))])
-            d.m0 = a.ctypes.data
+            self.shapes.append(a.shape)
         h = _P()
         rc = self._lib.llg_batch_create(int(device), descs, len(films), ctypes.byref(h))
         if rc != LLG_OK:
@@ -328,9 +364,23 @@ class Batch:
                                           int(max_attempts), st))
         return [s.as_dict() for s in st]
 
-    def get_m(self, film):
+    def step(self, method, dt, nsteps=1):
+        self._chk(self._lib.llg_batch_step(self._h, METHODS[method], float(dt), int(nsteps)))
+
+    def set_m(self, film, m):
+        if _is_torch(m) and m.is_cuda:
+            assert str(m.dtype) == "torch.float32" and m.is_contiguous()
+            self._chk(self._lib.llg_batch_set_m(self._h, int(film), _P(m.data_ptr()), LLG_DEVICE))
+        else:
+            a = np.ascontiguousarray(m, dtype=np.float32).reshape(self.shapes[film])
+            self._chk(self._lib.llg_batch_set_m(self._h, int(film), a.ctypes.data_as(_P), LLG_HOST))
+
+    def get_m(self, film, out=None):
+        if out is not None and _is_torch(out) and out.is_cuda:
+            self._chk(self._lib.llg_batch_get_m(self._h, int(film), _P(out.data_ptr()), LLG_DEVICE))
+            return out
         a = np.empty(self.shapes[film], dtype=np.float32)
-        self._chk(self._lib.llg_batch_get_m(self._h, int(film), a.ctypes.data_as(_P)))
+        self._chk(self._lib.llg_batch_get_m(self._h, int(film), a.ctypes.data_as(_P), LLG_HOST))
         return a
 
     def attempts(self, film, cap=1 << 16):
@@ -338,3 +388,160 @@ class Batch:
         n = ctypes.c_int64()
         self._chk(self._lib.llg_batch_get_attempts(self._h, int(film), buf, cap, ctypes.byref(n)))
         return [(buf[i].dt, float(buf[i].err), bool(buf[i].accepted)) for i in range(n.value)]
+
+
+def _ptr_mem(x):
+    """(pointer, llg_mem) of a float32 array: torch CUDA tensor or numpy."""
+    if _is_torch(x) and x.is_cuda:
+        assert str(x.dtype) == "torch.float32" and x.is_contiguous()
+        return _P(x.data_ptr()), LLG_DEVICE
+    assert x.dtype == np.float32 and x.flags["C_CONTIGUOUS"]
+    return x.ctypes.data_as(_P), LLG_HOST
+
+
+class Surrogate:
+    """The learned multi-step proposer (see llg_sur_* in llg.h).  Parameters
+    travel as a flat float32 vector in the layout of llg_sur_set_params; the
+    helpers pack()/unpack() convert from/to a list of (w, b) per layer."""
+
+    LAYERS = ((6, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3))
+
+    def __init__(self, H, W, max_batch=1, device=0):
+        self._lib = load()
+        h = _P()
+        rc = self._lib.llg_sur_create(int(device), int(H), int(W), int(max_batch), ctypes.byref(h))
+        if rc != LLG_OK:
+            msg = self._lib.llg_sur_last_error(h).decode() if h else "llg_sur_create failed"
+            if h:
+                self._lib.llg_sur_destroy(h)
+            raise LLGError(rc, msg)
+        self._h = h
+        self.H, self.W, self.max_batch = int(H), int(W), int(max_batch)
+        self.nparam = int(self._lib.llg_sur_num_params())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.llg_sur_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != LLG_OK:
+            raise LLGError(rc, self._lib.llg_sur_last_error(self._h).decode())
+
+    @classmethod
+    def pack(cls, params):
+        return np.concatenate([np.concatenate([np.asarray(w, np.float32).reshape(-1),
+                                               np.asarray(b, np.float32).reshape(-1)]) for w, b in params])
+
+    @classmethod
+    def unpack(cls, flat):
+        out, o = [], 0
+        for ci, co in cls.LAYERS:
+            w = flat[o:o + co * ci * 9].reshape(co, ci, 3, 3)
+            o += co * ci * 9
+            b = flat[o:o + co]
+            o += co
+            out.append((w, b))
+        return out
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(params if isinstance(params, np.ndarray) else self.pack(params),
+                                    dtype=np.float32)
+        self._chk(self._lib.llg_sur_set_params(self._h, flat.ctypes.data_as(_P), flat.size))
+
+    def get_params(self):
+        a = np.empty(self.nparam, np.float32)
+        self._chk(self._lib.llg_sur_get_params(self._h, a.ctypes.data_as(_P), a.size))
+        return a
+
+    def get_grads(self):
+        a = np.empty(self.nparam, np.float32)
+        self._chk(self._lib.llg_sur_get_grads(self._h, a.ctypes.data_as(_P), a.size))
+        return a
+
+    def train_step(self, m_in, m_target, B, lr=0.0):
+        """m_in, m_target: (batch, 3, H, W) float32 (numpy or CUDA tensor);
+        B: (batch, 3) tesla.  Returns the loss."""
+        Bh = np.ascontiguousarray(B, dtype=np.float32).reshape(-1, 3)
+        pi, where = _ptr_mem(m_in)
+        pt, where2 = _ptr_mem(m_target)
+        assert where == where2
+        loss = ctypes.c_float()
+        self._chk(self._lib.llg_sur_train_step(self._h, pi, pt, Bh.ctypes.data_as(_P), Bh.shape[0], where,
+                                               float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def predict(self, m_in, B, out=None):
+        Bh = np.ascontiguousarray(B, dtype=np.float32).reshape(-1, 3)
+        pi, where = _ptr_mem(m_in)
+        if out is None:
+            assert where == LLG_HOST
+            out = np.empty((Bh.shape[0], 3, self.H, self.W), np.float32)
+        po, _ = _ptr_mem(out)
+        self._chk(self._lib.llg_sur_predict(self._h, pi, Bh.ctypes.data_as(_P), Bh.shape[0], where, po))
+        return out
+
+    def forward_raw(self, m_in, B, layer):
+        m = np.ascontiguousarray(m_in, dtype=np.float32)
+        Bh = np.ascontiguousarray(B, dtype=np.float32).reshape(-1, 3)
+        z = np.empty((Bh.shape[0], self.H, self.W, 32), np.float32)
+        self._chk(self._lib.llg_sur_forward_raw(self._h, m.ctypes.data_as(_P), Bh.ctypes.data_as(_P),
+                                                Bh.shape[0], int(layer), z.ctypes.data_as(_P)))
+        return z
+
+    def conv_check(self, layer, x, gy=None):
+        """x, gy: (batch, H, W, 32) float32.  Returns y or (y, gx, gw, gb)."""
+        ci, co = self.LAYERS[layer]
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.empty_like(x)
+        if gy is None:
+            self._chk(self._lib.llg_sur_conv_check(self._h, int(layer), x.ctypes.data_as(_P), None,
+                                                   x.shape[0], y.ctypes.data_as(_P), None, None, None))
+            return y
+        gy = np.ascontiguousarray(gy, dtype=np.float32)
+        gx = np.empty_like(x)
+        gw = np.empty((co, ci, 3, 3), np.float32)
+        gb = np.empty(co, np.float32)
+        self._chk(self._lib.llg_sur_conv_check(self._h, int(layer), x.ctypes.data_as(_P),
+                                               gy.ctypes.data_as(_P), x.shape[0], y.ctypes.data_as(_P),
+                                               gx.ctypes.data_as(_P), gw.ctypes.data_as(_P),
+                                               gb.ctypes.data_as(_P)))
+        return y, gx, gw, gb
+
+    def advance(self, prob, m, n_segments, window=16, seg_steps=10, dt=1e-13, max_dm=1e-2):
+        """Advances m (float32 (3, 1, H, W) numpy array or CUDA tensor, in
+        place for a tensor) by n_segments segments; returns (m, stats)."""
+        d = FilmDesc()
+        keep = film_desc(prob, np.zeros((3, 1, self.H, self.W), np.float32), d)
+        d.m0 = None
+        if _is_torch(m) and m.is_cuda:
+            pm, where = _ptr_mem(m)
+            out = m
+        else:
+            out = np.ascontiguousarray(m, dtype=np.float32).copy()
+            pm, where = _ptr_mem(out)
+        st = SurStats()
+        self._chk(self._lib.llg_sur_advance(self._h, ctypes.byref(d), int(window), int(n_segments),
+                                            int(seg_steps), float(dt), float(max_dm), pm, where,
+                                            ctypes.byref(st)))
+        del keep
+        return out, st.as_dict()
+
+
+def mfma_selftest(A, B, device=0):
+    """One 16x32 by 32x16 product on a single MFMA instruction (BF16 inputs)."""
+    lib = load()
+    a = np.ascontiguousarray(A, dtype=np.float32)
+    b = np.ascontiguousarray(B, dtype=np.float32)
+    assert a.shape == (16, 32) and b.shape == (32, 16)
+    c = np.empty((16, 16), np.float32)
+    rc = lib.llg_mfma_selftest(int(device), a.ctypes.data_as(_P), b.ctypes.data_as(_P), c.ctypes.data_as(_P))
+    if rc != LLG_OK:
+        raise LLGError(rc, "llg_mfma_selftest failed")
+    return c

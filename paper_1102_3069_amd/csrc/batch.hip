@@ -1,5 +1,6 @@
 // Batched runtime: many independent 2D films of uneven size (a parameter
-// sweep) integrated together with adaptive Dormand-Prince 5(4).
+// sweep) integrated together with adaptive Dormand-Prince 5(4) or with
+// fixed Euler, Heun or RK4 steps.
 //
 // Every pass of an attempt (the first-stage forward transform, then per
 // stage the column pass and the fused row pass, then the step controller)
@@ -65,6 +66,11 @@ struct llg_batch {
     int lds_fwd = 0, lds_inv = 0, lds_col = 0;
     hipGraphExec_t graph = nullptr;
     bool k1_valid = false;
+    // fixed steps: per-stage arguments and the captured step of one method
+    FilmRow* d_fix[4] = {};
+    int fix_method = -1;
+    hipGraphExec_t gfix = nullptr;
+    bool spec_valid = false;            // S holds the forward x pass of every film's m
 };
 
 namespace {
@@ -205,6 +211,53 @@ llg_status enqueue_attempt(llg_batch* b) {
     return LLG_OK;
 }
 
+Tableau fixed_tableau(llg_method m) {
+    return m == LLG_EULER ? tab_euler() : m == LLG_HEUN ? tab_heun() : tab_rk4();
+}
+
+// per-stage arguments of a fixed step; buffer roles follow the single-film
+// fixed step exactly (stage inputs alternate between ms[0] and ms[1], k_j
+// in kb[j-1], the last stage writes the next state and its forward pass)
+llg_status build_fixed_args(llg_batch* b, const Tableau& t) {
+    const int nf = (int)b->films.size();
+    for (int st = 1; st <= t.S; ++st) {
+        std::vector<FilmRow> v(nf);
+        bool needed = false;
+        if (st < t.S) {
+            if (t.b[st - 1] != 0.0) needed = true;
+            for (int r = st; r < t.S; ++r)
+                if (t.A[r][st - 1] != 0.0) needed = true;
+        }
+        for (int i = 0; i < nf; ++i) {
+            BatchFilm& f = b->films[i];
+            FilmRow r = row_base(b, i);
+            StageArgs& sa = r.sa;
+            sa.mode = ROW_STAGE;
+            sa.m_in = st == 1 ? bref_cur(f.mbuf[0], f.mbuf[1], 1) : bref(f.ms[st % 2]);
+            sa.m0 = bref_cur(f.mbuf[0], f.mbuf[1], 1);
+            sa.m_out = st == t.S ? bref_cur(f.mbuf[0], f.mbuf[1], 2) : bref(f.ms[(st + 1) % 2]);
+            sa.k_out = bref(needed ? f.kb[st - 1] : nullptr);
+            sa.nk = st;
+            for (int j = 0; j < st; ++j) sa.a[j] = (float)(st < t.S ? t.A[st][j] : t.b[j]);
+            for (int j = 0; j + 1 < st; ++j) sa.kprev[j] = bref(f.kb[j]);
+            v[i] = r;
+        }
+        bfree(b->d_fix[st - 1]);
+        b->d_fix[st - 1] = nullptr;
+        BCHK(b, upload(&b->d_fix[st - 1], v));
+    }
+    return LLG_OK;
+}
+
+llg_status enqueue_fixed(llg_batch* b, int nstages) {
+    for (int st = 0; st < nstages; ++st) {
+        BCHK(b, launch_col_group(b->d_col, b->d_colmap, b->ncolblk, b->lds_col, b->stream));
+        BCHK(b, launch_row_inv_group(b->d_fix[st], b->d_rowmap, b->nrowblk, b->lds_inv, b->stream));
+    }
+    BCHK(b, launch_ctrl_fixed_group(b->st, (int)b->films.size(), nstages, b->stream));
+    return LLG_OK;
+}
+
 llg_status read_states(llg_batch* b, std::vector<DevState>& h) {
     h.resize(b->films.size());
     BCHK(b, hipMemcpyAsync(h.data(), b->st, sizeof(DevState) * h.size(), hipMemcpyDeviceToHost, b->stream));
@@ -321,6 +374,8 @@ void llg_batch_destroy(llg_batch* b) {
     (void)hipSetDevice(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->gfix) (void)hipGraphExecDestroy(b->gfix);
+    for (auto p : b->d_fix) bfree(p);
     for (auto& f : b->films) {
         bfree(f.twx); bfree(f.twy); bfree(f.K); bfree(f.S); bfree(f.log);
         for (auto p : f.mbuf) bfree(p);
@@ -355,6 +410,7 @@ llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0,
         b->k1_valid = true;
         for (auto& s : h) s.nevals += 1;
     }
+    b->spec_valid = false;
     for (auto& s : h) {
         if (s.health) return bfail(b, LLG_E_DIVERGED, "a film has already diverged");
         s.t_end = t_end;
@@ -400,7 +456,7 @@ llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0,
     return LLG_OK;
 }
 
-llg_status llg_batch_get_m(llg_batch* b, int film, float* m) {
+llg_status llg_batch_get_m(llg_batch* b, int film, float* m, llg_mem where) {
     if (!b || !m || film < 0 || film >= (int)b->films.size()) return LLG_E_ARG;
     BCHK(b, hipSetDevice(b->device));
     std::vector<DevState> h;
@@ -408,7 +464,7 @@ llg_status llg_batch_get_m(llg_batch* b, int film, float* m) {
     if (rc != LLG_OK) return rc;
     const BatchFilm& f = b->films[film];
     BCHK(b, hipMemcpyAsync(m, f.mbuf[h[film].cur], sizeof(float) * 3 * (size_t)f.g.ncells,
-                           hipMemcpyDeviceToHost, b->stream));
+                           where == LLG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream));
     BCHK(b, hipStreamSynchronize(b->stream));
     return LLG_OK;
 }
@@ -430,4 +486,103 @@ llg_status llg_batch_get_attempts(llg_batch* b, int film, llg_attempt* out, int6
     return LLG_OK;
 }
 
+llg_status llg_batch_step(llg_batch* b, llg_method method, double dt, int64_t nsteps) {
+    if (!b) return LLG_E_ARG;
+    b->err.clear();
+    BCHK(b, hipSetDevice(b->device));
+    if (method != LLG_EULER && method != LLG_HEUN && method != LLG_RK4)
+        return bfail(b, LLG_E_ARG, "llg_batch_step takes Euler, Heun or RK4");
+    if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return bfail(b, LLG_E_ARG, "need dt > 0, nsteps >= 0");
+    if (nsteps == 0) return LLG_OK;
+    std::vector<DevState> h;
+    llg_status rc = read_states(b, h);
+    if (rc != LLG_OK) return rc;
+    for (size_t i = 0; i < h.size(); ++i) {
+        if (h[i].health) return bfail(b, LLG_E_DIVERGED, "film %d has already diverged", (int)i);
+        h[i].dt = dt;
+        h[i].dtau = (float)(dt * kGamma0 * b->films[i].mat.Ms);
+        h[i].gms = kGamma0 * b->films[i].mat.Ms;
+        h[i].done = 0;
+    }
+    if ((rc = write_states(b, h)) != LLG_OK) return rc;
+    if (!b->spec_valid)
+        BCHK(b, launch_row_fwd_group(b->d_fwd_plain, b->d_rowmap, b->nrowblk, b->lds_fwd, b->stream));
+    const Tableau t = fixed_tableau(method);
+    if (!b->gfix || b->fix_method != (int)method) {
+        if (b->gfix) (void)hipGraphExecDestroy(b->gfix);
+        b->gfix = nullptr;
+        b->fix_method = -1;
+        if ((rc = build_fixed_args(b, t)) != LLG_OK) return rc;
+        hipGraph_t graph = nullptr;
+        BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_fixed(b, t.S);
+        hipError_t e = hipStreamEndCapture(b->stream, &graph);
+        if (rc != LLG_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        BCHK(b, e);
+        e = hipGraphInstantiate(&b->gfix, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        BCHK(b, e);
+        b->fix_method = (int)method;
+    }
+    for (int64_t i = 0; i < nsteps; ++i) BCHK(b, hipGraphLaunch(b->gfix, b->stream));
+    b->spec_valid = true;
+    b->k1_valid = false;
+    if ((rc = read_states(b, h)) != LLG_OK) return rc;
+    for (size_t i = 0; i < h.size(); ++i)
+        if (h[i].health) return bfail(b, LLG_E_DIVERGED, "film %d: non-finite field or torque", (int)i);
+    return LLG_OK;
+}
+
+llg_status llg_batch_set_m(llg_batch* b, int film, const float* m, llg_mem where) {
+    if (!b || !m || film < 0 || film >= (int)b->films.size()) return LLG_E_ARG;
+    b->err.clear();
+    BCHK(b, hipSetDevice(b->device));
+    std::vector<DevState> h;
+    llg_status rc = read_states(b, h);
+    if (rc != LLG_OK) return rc;
+    BatchFilm& f = b->films[film];
+    const size_t vec = sizeof(float) * 3 * (size_t)f.g.ncells;
+    float* dst = f.mbuf[h[film].cur];
+    BCHK(b, hipMemcpyAsync(dst, m, vec, where == LLG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           b->stream));
+    int* bad = nullptr;
+    int hbad = 0;
+    BCHK(b, hipMalloc(&bad, sizeof(int)));
+    BCHK(b, hipMemsetAsync(bad, 0, sizeof(int), b->stream));
+    BCHK(b, launch_normalize_check(dst, f.g.ncells, bad, b->stream));
+    BCHK(b, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    bfree(bad);
+    b->spec_valid = false;
+    b->k1_valid = false;
+    DevState& s = h[film];
+    s.t = 0.0; s.step = 0; s.nsteps = 0; s.nrej = 0; s.nevals = 0; s.nattempt = 0;
+    s.health = 0; s.done = 0; s.err_bits = 0u;
+    if ((rc = write_states(b, h)) != LLG_OK) return rc;
+    if (hbad) return bfail(b, LLG_E_ARG, "film %d: m is not a field of unit vectors", film);
+    return LLG_OK;
+}
+
 }  // extern "C"
+
+// ---- shared with the surrogate's speculative verification ------------------
+
+hipStream_t llg_batch_stream_(llg_batch* b) { return b->stream; }
+
+// the device buffer that holds a film's current state (reads the device
+// state, so the stream is synchronised)
+llg_status llg_batch_state_ptr_(llg_batch* b, int film, float** m) {
+    if (!b || !m || film < 0 || film >= (int)b->films.size()) return LLG_E_ARG;
+    std::vector<DevState> h;
+    llg_status rc = read_states(b, h);
+    if (rc != LLG_OK) return rc;
+    *m = b->films[film].mbuf[h[film].cur];
+    return LLG_OK;
+}
+
+// marks the states as replaced in place (by copies into the buffers named by
+// llg_batch_state_ptr_), so the next step recomputes the forward pass
+void llg_batch_states_replaced_(llg_batch* b) {
+    b->spec_valid = false;
+    b->k1_valid = false;
+}

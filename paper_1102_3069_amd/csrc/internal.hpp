@@ -180,6 +180,7 @@ hipError_t launch_row_fwd_group(const FilmRow* films, const int2* map, int nbloc
 hipError_t launch_row_inv_group(const FilmRow* films, const int2* map, int nblocks, int lds, hipStream_t s);
 hipError_t launch_col_group(const FilmCol* films, const int2* map, int nblocks, int lds, hipStream_t s);
 hipError_t launch_ctrl_dp45_group(DevState* states, int nfilms, hipStream_t s);
+hipError_t launch_ctrl_fixed_group(DevState* states, int nfilms, int evals, hipStream_t s);
 
 // ---- demag tensor (tensor.hip) --------------------------------------------------
 struct TensorGeom {
@@ -195,3 +196,8 @@ hipError_t tensor_at_offsets(const TensorGeom& tg, const int32_t* offs_dev, long
                              double* out_dev, hipStream_t s);
 
 }  // namespace llg
+
+// batch internals shared with the surrogate (batch.hip)
+hipStream_t llg_batch_stream_(llg_batch* b);
+llg_status llg_batch_state_ptr_(llg_batch* b, int film, float** m);
+void llg_batch_states_replaced_(llg_batch* b);

@@ -428,6 +428,17 @@ __global__ void ctrl_fixed_kernel(DevState* st, int evals) {
     st->nevals += evals;
 }
 
+__global__ void ctrl_fixed_group_kernel(DevState* states, int nfilms, int evals) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nfilms) return;
+    DevState* st = states + i;
+    st->t += st->dt;
+    st->cur ^= 1;
+    st->step += 1;
+    st->nsteps += 1;
+    st->nevals += evals;
+}
+
 // Dormand-Prince step control: accept if err <= tol, next step
 // dt * clamp(0.9 (tol/err)^(1/5), 0.2, 5), last step lands on t_end.
 __device__ void dp45_control(DevState* st) {
@@ -594,6 +605,11 @@ hipError_t launch_col(const ColArgs& a, DevState* st, int mode, hipStream_t s) {
 hipError_t launch_ctrl_fixed(DevState* st, int evals, double dt, hipStream_t s) {
     (void)dt;
     hipLaunchKernelGGL(ctrl_fixed_kernel, dim3(1), dim3(64), 0, s, st, evals);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl_fixed_group(DevState* states, int nfilms, int evals, hipStream_t s) {
+    hipLaunchKernelGGL(ctrl_fixed_group_kernel, dim3((nfilms + 63) / 64), dim3(64), 0, s, states, nfilms, evals);
     return hipGetLastError();
 }
 

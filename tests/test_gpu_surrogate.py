@@ -1,0 +1,265 @@
+"""The learned surrogate on the GPU: MFMA lane layout, every training kernel
+against the FP64 oracle fed the same BF16-rounded operands (only the FP32
+accumulation order differs), the whole network and its gradients within the
+error that BF16 activations allow, Adam's first step, batched fixed RK4
+steps against the single-film solver, and speculative verification."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import surrogate as osg
+
+pytestmark = pytest.mark.gpu
+
+LAYERS = osg.LAYERS
+
+
+def bf16(a):
+    """Rounds to the nearest BF16 value (ties to even), returned as float32;
+    the same rounding the kernels apply to their operands."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def rounded_params(seed):
+    """Oracle initial weights rounded to BF16, biases random (FP32)."""
+    rng = np.random.default_rng(seed + 100)
+    out = []
+    for w, b in osg.init_params(seed):
+        out.append((bf16(w).astype(np.float64),
+                    rng.standard_normal(b.shape).astype(np.float32).astype(np.float64) * 0.1))
+    return out
+
+
+def rel_max(a, ref):
+    return float(np.max(np.abs(a - ref)) / np.max(np.abs(ref)))
+
+
+def test_mfma_lane_layout(lib):
+    rng = np.random.default_rng(0)
+    A = rng.integers(-8, 9, (16, 32)).astype(np.float32)
+    B = rng.integers(-8, 9, (32, 16)).astype(np.float32)
+    C = lib.mfma_selftest(A, B)
+    assert np.array_equal(C, A @ B)      # small integers: exact in BF16 and FP32
+
+
+@pytest.mark.parametrize("layer", [0, 1, 5])
+def test_conv_layer_parity(lib, layer):
+    """PIN-18: forward, weight, bias and input gradients of one layer, BF16
+    operands, against the FP64 oracle on the same rounded values."""
+    H, W, N = 37, 70, 2           # two column tiles with a ragged tail, odd rows
+    ci, co = LAYERS[layer]
+    params = rounded_params(3)
+    sur = lib.Surrogate(H, W, max_batch=N)
+    sur.set_params(params)
+    rng = np.random.default_rng(layer)
+    x = bf16(rng.standard_normal((N, H, W, 32)))
+    gy = bf16(rng.standard_normal((N, H, W, 32)))
+    y, gx, gw, gb = sur.conv_check(layer, x, gy)
+    w, b = params[layer]
+    gw_ref = np.zeros_like(w)
+    gb_ref = np.zeros_like(b)
+    for n in range(N):
+        xo = x[n, :, :, :ci].transpose(2, 0, 1).astype(np.float64)
+        go = gy[n, :, :, :co].transpose(2, 0, 1).astype(np.float64)
+        y_ref = osg.conv3x3(xo, w, b)
+        gx_ref, gwn, gbn = osg.conv3x3_backward(xo, w, go)
+        gw_ref += gwn
+        gb_ref += gbn
+        assert rel_max(y[n, :, :, :co].transpose(2, 0, 1), y_ref) <= 1e-5
+        assert rel_max(gx[n, :, :, :ci].transpose(2, 0, 1), gx_ref) <= 1e-5
+        assert not np.any(y[n, :, :, co:]) and not np.any(gx[n, :, :, ci:])
+    assert rel_max(gw, gw_ref) <= 1e-5
+    assert rel_max(gb, gb_ref) <= 1e-5
+
+
+def emulated_forward(params, x):
+    """FP64 oracle layers with the activations rounded to BF16 between
+    layers, as the kernels store them."""
+    h = bf16(x).astype(np.float64)
+    for li, (w, b) in enumerate(params):
+        z = osg.conv3x3(h, w, b)
+        if li == len(params) - 1:
+            return z
+        h = bf16(osg.silu(z)).astype(np.float64)
+
+
+def test_network_forward_and_proposal(lib):
+    H, W = 40, 72
+    m = workloads.random_unit((W, H, 1), 4).reshape(3, H, W)
+    B = (0.03, -0.01, 0.0)
+    params = rounded_params(5)
+    sur = lib.Surrogate(H, W, max_batch=1)
+    sur.set_params(params)
+    z = sur.forward_raw(m[None], np.array([B]), 5)[0, :, :, :3].transpose(2, 0, 1)
+    x = osg.net_input(m.astype(np.float64), B)
+    assert rel_max(z, emulated_forward(params, x)) <= 2e-3
+    assert rel_max(z, osg.forward(params, x)[0]) <= 3e-2
+    # layer 0 alone sees only the input rounding, done the same way on both sides
+    z0 = sur.forward_raw(m[None], np.array([B]), 0)[0].transpose(2, 0, 1)
+    assert rel_max(z0, osg.conv3x3(bf16(x).astype(np.float64), *params[0])) <= 1e-5
+    # proposal = normalize(m + dm)
+    mp = sur.predict(m[None].astype(np.float32), np.array([B]))[0]
+    ref = m + z
+    ref = ref / np.linalg.norm(ref, axis=0, keepdims=True)
+    assert np.max(np.abs(mp - ref)) <= 1e-6
+    assert np.allclose(np.linalg.norm(mp, axis=0), 1.0, atol=1e-6)
+
+
+def test_train_step_gradients(lib):
+    """Loss and all parameter gradients of a batch against the FP64 oracle
+    (BF16 activations and gradients: loose bound, plus the direction)."""
+    H, W, N = 24, 40, 2
+    params = rounded_params(7)
+    sur = lib.Surrogate(H, W, max_batch=N)
+    sur.set_params(params)
+    rng = np.random.default_rng(9)
+    m = np.stack([workloads.random_unit((W, H, 1), 20 + i).reshape(3, H, W) for i in range(N)])
+    mt = m + 0.05 * rng.standard_normal(m.shape).astype(np.float32)
+    Bs = np.array([[0.02, 0.01, 0.0], [-0.04, 0.0, 0.0]], np.float32)
+    loss = sur.train_step(m.astype(np.float32), mt.astype(np.float32), Bs, lr=0.0)
+    g = lib.Surrogate.unpack(sur.get_grads())
+    # oracle: the loss is a mean over all samples, so gradients are the mean
+    # of per-sample gradients
+    lref, gref = 0.0, None
+    for n in range(N):
+        x = osg.net_input(m[n].astype(np.float64), Bs[n])
+        l, gr = osg.loss_and_grads(params, x, (mt[n] - m[n]).astype(np.float64))
+        lref += l / N
+        gr = [(gw / N, gb / N) for gw, gb in gr]
+        gref = gr if gref is None else [(a + c, b + d) for (a, b), (c, d) in zip(gref, gr)]
+    assert abs(loss - lref) <= 1e-2 * lref
+    for li, ((gw, gb), (rw, rb)) in enumerate(zip(g, gref)):
+        for a, r in ((gw, rw), (gb, rb)):
+            a = np.asarray(a, np.float64).ravel()
+            r = r.ravel()
+            cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r)))
+            print(f"layer {li} size {r.size} rel {rel_max(a, r):.2e} cos {cos:.6f}", flush=True)
+            assert rel_max(a, r) <= 5e-2
+            assert cos >= 0.999
+
+
+def test_adam_first_step(lib):
+    """First Adam step: bias correction makes every update lr * g / (|g| +
+    eps), i.e. lr * sign(g) wherever |g| >> eps."""
+    H, W = 16, 20
+    params = rounded_params(11)
+    sur = lib.Surrogate(H, W, max_batch=1)
+    sur.set_params(params)
+    p0 = sur.get_params()
+    m = workloads.random_unit((W, H, 1), 3).reshape(1, 3, H, W)
+    mt = workloads.random_unit((W, H, 1), 4).reshape(1, 3, H, W)
+    lr = 1e-3
+    sur.train_step(m, mt, np.array([[0.01, 0.0, 0.0]]), lr=lr)
+    g = sur.get_grads().astype(np.float64)
+    p1 = sur.get_params().astype(np.float64)
+    want = p0.astype(np.float64) - lr * g / (np.abs(g) + 1e-8)
+    # FP32 bias-correction constants carry ~1e-5 relative error
+    assert np.max(np.abs(p1 - want)) <= 1e-4 * lr + 4 * np.max(np.abs(np.spacing(p0)))
+
+
+def test_batch_fixed_rk4_equals_single(lib):
+    """Batched fixed RK4 steps give each film the single-film solver's
+    result bit for bit."""
+    films = []
+    for i, side in enumerate((32, 64, 48)):
+        prob, _ = workloads.small_problem((side, side, 1), seed=30 + i)
+        prob["pbc"] = (False, False, False)
+        films.append((prob, workloads.random_unit((side, side, 1), 40 + i)))
+    b = lib.Batch(films)
+    b.step("rk4", 1e-13, 7)
+    for i, (prob, m0) in enumerate(films):
+        s = lib.Solver(0)
+        s.set_problem(prob)
+        s.set_m(m0)
+        s.step("rk4", 1e-13, 7)
+        assert np.array_equal(b.get_m(i), s.get_m()), f"film {i}"
+
+
+def held_out(n, seed):
+    films, run = workloads.surrogate_films(1, seed=seed, n_side=n)
+    return films[0][0], films[0][1], run
+
+
+def test_speculative_threshold_zero_is_plain(lib):
+    """With max_dm = 0 every proposal falls back and the result equals the
+    plain run bit for bit."""
+    n = 64
+    prob, m0, run = held_out(n, 77)
+    sur = lib.Surrogate(n, n, max_batch=1)
+    sur.set_params(osg.init_params(0))
+    m, st = sur.advance(prob, m0, n_segments=5, window=4, seg_steps=10, dt=run["dt"], max_dm=0.0)
+    assert st["accepted"] == 0 and st["segments"] == 5 and st["rounds"] == 5
+    s = lib.Solver(0)
+    s.set_problem(prob)
+    s.set_m(m0)
+    s.step("rk4", run["dt"], 50)
+    assert np.array_equal(m, s.get_m())
+
+
+def test_speculative_accept_all(lib):
+    """With a threshold no proposal can exceed, each round jumps `window`
+    segments: the committed state is the plain segment from the last
+    proposal of the chain."""
+    n = 64
+    prob, m0, run = held_out(n, 78)
+    sur = lib.Surrogate(n, n, max_batch=1)
+    sur.set_params(osg.init_params(1))
+    m, st = sur.advance(prob, m0, n_segments=6, window=3, seg_steps=10, dt=run["dt"], max_dm=10.0)
+    assert st["rounds"] == 2 and st["accepted"] == 6 and st["proposals"] == 6 and st["segments"] == 6
+    # rebuild the chain: proposals, then one plain segment from the last
+    B = np.array([prob["B"]], np.float32)
+    cur = m0.reshape(1, 3, n, n).astype(np.float32)
+    for r in range(2):
+        for j in range(2):
+            cur = sur.predict(cur, B)
+        s = lib.Solver(0)
+        s.set_problem(prob)
+        s.set_m(cur[0])
+        s.step("rk4", run["dt"], 10)
+        cur = s.get_m().reshape(1, 3, n, n)
+    assert np.max(np.abs(m - cur.reshape(m.shape))) <= 1e-5
+
+
+def test_trained_surrogate_gains(lib):
+    """Trains the network on solver-generated pairs (small film), then
+    advances a held-out trajectory with speculative verification and with
+    the plain solver: reports the acceptance, the wall-time ratio and the
+    end-to-end deviation."""
+    import torch
+    from paper_1102_3069_amd import surrogate_train as tr
+    n = 64
+    films, run = workloads.surrogate_films(8, seed=5, n_side=n)
+    X, B = tr.generate_pairs(lib, films, run, pairs_per_traj=40)
+    sur = lib.Surrogate(n, n, max_batch=16)
+    sur.set_params(osg.init_params(0))
+    res = tr.train(sur, X, B, steps=600, batch=16, lr0=2e-3, log_every=100)
+    first, last = np.mean(res["losses"][:20]), np.mean(res["losses"][-20:])
+    print(f"loss {first:.3e} -> {last:.3e}; {res['px_per_s']:.3e} px/s", flush=True)
+    assert last < 0.2 * first
+    prob, m0, _ = held_out(n, 1234)
+    nseg = 40
+    s = lib.Solver(0)
+    s.set_problem(prob)
+    s.set_m(m0)
+    s.step("rk4", run["dt"], 10)        # warm-up (graph capture)
+    s.set_m(m0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step("rk4", run["dt"], 10 * nseg)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    m_plain = s.get_m()
+    sur.advance(prob, m0, n_segments=2, window=8, dt=run["dt"])       # warm-up
+    t0 = time.perf_counter()
+    m_sur, st = sur.advance(prob, m0, n_segments=nseg, window=8, dt=run["dt"], max_dm=1e-2)
+    t_sur = time.perf_counter() - t0
+    dev = float(np.max(np.linalg.norm((m_sur - m_plain).reshape(3, -1), axis=0)))
+    print(f"plain {t_plain * 1e3:.1f} ms, speculative {t_sur * 1e3:.1f} ms, speedup {t_plain / t_sur:.2f}; "
+          f"stats {st}; max |m - m_plain| {dev:.2e}", flush=True)
+    assert st["segments"] == nseg
+    assert st["max_dm_accepted"] <= 1e-2
+    assert np.allclose(np.linalg.norm(m_sur.reshape(3, -1), axis=0), 1.0, atol=1e-5)

@@ -113,6 +113,23 @@ def film_batch(nfilms=64, seed=4, sizes=(64, 96, 128, 192, 256)):
     return films, run
 
 
+def surrogate_films(ntraj, seed=5, n_side=256):
+    """Trajectories for the learned surrogate: the thin film of film_512 at
+    n x n cells, each with its own applied field of magnitude U[0, 50] mT at
+    a uniformly random in-plane angle, all starting along (1,1,1)/sqrt(3).
+    Pairs (m_t, m_t+10 steps) come from fixed RK4 steps of 1e-13 s after a
+    50-step burn-in, one pair every 10 steps."""
+    rng = np.random.default_rng(seed)
+    prob0, m0, _ = film_512(n_side)
+    films = []
+    for _ in range(ntraj):
+        prob = dict(prob0)
+        prob["B"] = field_in_plane(float(rng.uniform(0.0, 0.05)), float(rng.uniform(0.0, 360.0)))
+        films.append((prob, m0.copy()))
+    run = dict(method="rk4", dt=1e-13, seg_steps=10, burn_in=50)
+    return films, run
+
+
 def small_problem(n=(8, 6, 1), cell=(4e-9, 4e-9, 3e-9), pbc=(False, False, False), seed=7,
                   **over):
     """A small random problem with every deterministic term switched on,
