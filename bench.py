@@ -34,8 +34,17 @@ def parse():
     ap.add_argument("--profile-evals", type=int, default=200)
     ap.add_argument("--cpu-baseline-evals", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("film512", "batch"), default="film512",
-                    help="film512: the 512x512 film (the headline); batch: the 64-film sweep")
+    ap.add_argument("--evals-only", action="store_true",
+                    help="run only the H_eff evaluations of the roofline measurement (for counter runs)")
+    ap.add_argument("--workload", choices=("film512", "batch", "surrogate"), default="film512",
+                    help="film512: the 512x512 film (the headline); batch: the 64-film sweep; "
+                         "surrogate: train the learned proposer and time speculative verification")
+    ap.add_argument("--sur-traj", type=int, default=100, help="surrogate: training trajectories")
+    ap.add_argument("--sur-pairs", type=int, default=200, help="surrogate: pairs per trajectory")
+    ap.add_argument("--sur-epochs", type=float, default=4.0, help="surrogate: passes over the pairs")
+    ap.add_argument("--sur-window", type=int, default=8, help="surrogate: proposals per round")
+    ap.add_argument("--sur-held-out", type=int, default=8, help="surrogate: held-out trajectories")
+    ap.add_argument("--sur-segments", type=int, default=200, help="surrogate: segments per held-out run")
     return ap.parse_args()
 
 
@@ -54,6 +63,39 @@ def cpu_baseline(prob, m0, nevals):
     return {"value": ncells * nevals / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{nevals} FP64 H_eff evaluations of the same {prob['n'][0]}x{prob['n'][1]}x1 film "
                       f"({dt:.1f} s; kernel spectrum built beforehand, not timed)"}
+
+
+# kernel names of the 2D compiled-length path, per kernel kind of
+# llg_profile_evals, for the padded lengths of an n x n film
+def _kernel_name(kind, px, py):
+    return {"row_fwd": f"row_fwd_fast<{px},", "spectral": f"col2d_fast<{py // 2},",
+            "row_inv": f"row_inv_fast<{px},"}.get(kind)
+
+
+def measured_traffic(kind, prob):
+    """HBM bytes per launch of the kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary (scaled by a plain copy), or None when
+    that summary was taken on other kernel sources or another size."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"film{prob['n'][0]}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    csrc = os.path.join(ROOT, "paper_1102_3069_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    px = 2 * prob["n"][0]
+    key = _kernel_name(kind, px, 2 * prob["n"][1])
+    for name, t in rec["kernels"].items():
+        if key and key in name:
+            return t["read_bytes"] + t["write_bytes"]
+    return None
 
 
 def bench_batch(args):
@@ -85,8 +127,76 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_surrogate(args):
+    """The learned surrogate on 256 x 256 films: solver-generated pairs,
+    training on the MFMA kernels, then the held-out trajectories advanced by
+    plain RK4 and by speculative verification on the same GPU."""
+    import numpy as np
+    import torch
+    import paper_1102_3069_amd as llg
+    import workloads
+    from paper_1102_3069_amd import surrogate_train as tr
+    llg.load()
+    n = 256
+    films, run = workloads.surrogate_films(args.sur_traj, seed=5, n_side=n)
+    t0 = time.perf_counter()
+    X, B = tr.generate_pairs(llg, films, run, pairs_per_traj=args.sur_pairs)
+    t_data = time.perf_counter() - t0
+    npairs = X.shape[0] * (X.shape[1] - 1)
+    batch = 16
+    steps = int(args.sur_epochs * npairs / batch)
+    sur = llg.Surrogate(n, n, max_batch=batch)
+    sur.set_params(workloads.surrogate_init(0))
+    res = tr.train(sur, X, B, steps=steps, batch=batch, lr0=2e-3)
+    del X
+    torch.cuda.empty_cache()
+    train_flops = 236.7e3 * n * n * steps * batch
+    held, _ = workloads.surrogate_films(args.sur_held_out, seed=6, n_side=n)
+    t_plain = t_sur = 0.0
+    dev = 0.0
+    stats = []
+    for prob, m0 in held:
+        s = llg.Solver(0)
+        s.set_problem(prob)
+        s.set_m(m0)
+        s.step("rk4", run["dt"], run["burn_in"])
+        m_start = s.get_m()
+        s.set_m(m_start)
+        t0 = time.perf_counter()
+        s.step("rk4", run["dt"], run["seg_steps"] * args.sur_segments)
+        t_plain += time.perf_counter() - t0
+        m_plain = s.get_m()
+        sur.advance(prob, m_start, n_segments=1, window=args.sur_window, dt=run["dt"])   # builds the batch
+        t0 = time.perf_counter()
+        m_s, st = sur.advance(prob, m_start, n_segments=args.sur_segments, window=args.sur_window,
+                              dt=run["dt"], max_dm=1e-2)
+        t_sur += time.perf_counter() - t0
+        stats.append(st)
+        dev = max(dev, float(np.max(np.linalg.norm((m_s - m_plain).reshape(3, -1), axis=0))))
+    acc = sum(s["accepted"] for s in stats) / max(1, sum(s["proposals"] for s in stats))
+    segs = args.sur_held_out * args.sur_segments
+    out = {"metric": "speedup of speculative verification over plain RK4 at max |dm| <= 1e-2",
+           "value": t_plain / t_sur, "unit": "x", "n_gpus": 1, "steps": segs, "warmup": 1,
+           "ms_per_step": t_sur * 1e3 / segs, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16 (network), f32 (solver)", "data": "synthetic",
+           "config": {"workload": f"{args.sur_held_out} held-out 256x256 films, {args.sur_segments} segments of "
+                                  f"10 RK4 steps (dt 1e-13 s), window {args.sur_window}",
+                      "plain_s": t_plain, "speculative_s": t_sur, "acceptance": acc,
+                      "max_dm_accepted": max(s["max_dm_accepted"] for s in stats),
+                      "end_to_end_max_dev": dev, "train_pairs": npairs, "train_steps": steps,
+                      "train_batch": batch, "final_loss": float(np.mean(res["losses"][-50:])),
+                      "train_px_per_s": res["px_per_s"],
+                      "train_tflops": train_flops / res["wall_s"] / 1e12, "data_gen_s": t_data}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "surrogate":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        return bench_surrogate(args)
     if args.workload == "batch":
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
@@ -107,6 +217,10 @@ def main():
     s = llg.Solver(0)
     s.set_problem(prob)
     s.set_m(m0)
+    if args.evals_only:
+        prof, total = s.profile_evals(args.profile_evals)
+        print(json.dumps({"evals": args.profile_evals, "kernel_ms": prof, "eval_ms": total / args.profile_evals}))
+        return
     # warm-up attempts (also builds the demag kernel and captures the graph)
     s.run_attempts(run["t_end"], run["tol"], run["dt0"], max(1, args.warmup))
     st0 = s.stats()
@@ -126,7 +240,7 @@ def main():
     dom = max(prof, key=lambda k: prof[k])
     achieved = nbytes[dom] / (prof[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(dom, prob),
                 "kernel_ms": prof, "kernel_bytes": nbytes,
                 "eval_ms": prof_total / args.profile_evals}
 

@@ -47,13 +47,19 @@ typedef enum {
     LLG_E_DIVERGED = 6      /* NaN/Inf in the state or the step fell below dt_min */
 } llg_status;
 
-/* Time integrators of Sec. 2.2 (RK1 Euler, RK2 Heun, RK4 classical, RKDP
- * Dormand-Prince 5(4) with adaptive steps). */
+/* Time integrators of Sec. 2.2.  Fixed steps: RK1 Euler, RK2 Heun, RK3
+ * Kutta, RK4 classical.  Adaptive embedded pairs: Dormand-Prince 5(4)
+ * (RKDP), Bogacki-Shampine 3(2) (RK23), Cash-Karp 5(4) (RKCK), Heun-Euler
+ * 2(1) (RK12). */
 typedef enum {
     LLG_EULER = 0,
     LLG_HEUN = 1,
     LLG_RK4 = 2,
-    LLG_RKDP45 = 3
+    LLG_RKDP45 = 3,
+    LLG_RK12 = 4,
+    LLG_RK3 = 5,
+    LLG_RK23 = 6,
+    LLG_RKCK = 7
 } llg_method;
 
 typedef enum { LLG_HOST = 0, LLG_DEVICE = 1 } llg_mem;
@@ -144,22 +150,24 @@ llg_status llg_get_m(llg_solver *s, float *m, llg_mem where);
 llg_status llg_eval_heff(llg_solver *s, float *h_out, llg_mem where);
 
 /* ---- time integration (Sec. 2.2) --------------------------------------------
- * llg_step: `nsteps` fixed steps of size dt (s) with LLG_EULER, LLG_HEUN or
- * LLG_RK4.  Every stage input and every new state is renormalised.
- * LLG_E_DIVERGED if a NaN/Inf appears.
+ * llg_step: `nsteps` fixed steps of size dt (s) with LLG_EULER, LLG_HEUN,
+ * LLG_RK3 or LLG_RK4.  Every stage input and every new state is
+ * renormalised.  LLG_E_DIVERGED if a NaN/Inf appears.
  */
 llg_status llg_step(llg_solver *s, llg_method method, double dt, int64_t nsteps);
-/* llg_run: adaptive LLG_RKDP45 from the current time to t_end (s).  An
- * attempt is accepted when max over cells |m5 - m4| <= max_err; the next
- * step is dt * clamp(0.9 (max_err/err)^(1/5), 0.2, 5); the last step lands
- * on t_end; dt0 is the first attempted step.  The controller runs on the
- * device: attempts are replayed from a captured HIP graph and the host only
- * polls the done flag.  LLG_E_DIVERGED if the step falls below 1e-18 s or a
- * NaN/Inf appears.  `out` may be NULL. */
+/* llg_run: adaptive integration with an embedded pair (LLG_RKDP45,
+ * LLG_RK23, LLG_RKCK or LLG_RK12) from the current time to t_end (s).  An
+ * attempt is accepted when err = max over cells |dt sum_j (b_j - bhat_j)
+ * k_j| <= max_err; the next step is dt * clamp(0.9 (max_err/err)^(1/(q+1)),
+ * 0.2, 5), q the order of the embedded estimate (4, 2, 4, 1); the last step
+ * lands on t_end; dt0 is the first attempted step.  The controller runs on
+ * the device: attempts are replayed from a captured HIP graph and the host
+ * only polls the done flag.  LLG_E_DIVERGED if the step falls below 1e-18 s
+ * or a NaN/Inf appears.  `out` may be NULL. */
 llg_status llg_run(llg_solver *s, llg_method method, double t_end, double max_err,
                    double dt0, llg_stats *out);
-/* As llg_run but stops after at most `max_attempts` attempts (for timing a
- * fixed amount of work); t may then be < t_end. */
+/* As llg_run with LLG_RKDP45 but stops after at most `max_attempts`
+ * attempts (for timing a fixed amount of work); t may then be < t_end. */
 llg_status llg_run_attempts(llg_solver *s, double t_end, double max_err, double dt0,
                             int64_t max_attempts, llg_stats *out);
 llg_status llg_get_stats(llg_solver *s, llg_stats *out);
@@ -181,6 +189,24 @@ llg_status llg_profile_evals(llg_solver *s, int n, double *ms_out, int n_kinds, 
 /* Algorithmic HBM bytes per evaluation of each kernel kind (same order as
  * llg_profile_evals), from the sizes of what it must read and write. */
 llg_status llg_kernel_bytes(llg_solver *s, double *bytes_out, int n_kinds);
+
+/* ---- tuning -------------------------------------------------------------------
+ * The 2D path has two compiled variants (elements per lane, hence lanes and
+ * wavefronts per transform) for every row length and every column length.
+ * The variant in use for a length is held in a process-wide table shared by
+ * every solver and by llg_batch_create; it starts at variant 0.
+ * llg_autotune times `iters` H_eff evaluations of the solver's current state
+ * with each of the four (row, column) variant pairs of its lengths, keeps the
+ * fastest in the table and returns the mean milliseconds per evaluation of
+ * pair (r, c) in ms_out[2r + c] (-1 if that pair cannot serve this geometry;
+ * ms_out may be NULL, n_out its length) and the chosen pair in choice[0..1]
+ * (may be NULL).  Solvers and batches made afterwards, and this solver, use
+ * the new table entry; results of different variants differ by FP32
+ * rounding only.  LLG_E_UNSUPPORTED unless the geometry is 2D with compiled
+ * lengths.  llg_set_variants sets the table entry for the solver's lengths
+ * directly. */
+llg_status llg_autotune(llg_solver *s, int iters, double *ms_out, int n_out, int *choice);
+llg_status llg_set_variants(llg_solver *s, int row_var, int col_var);
 
 /* ---- diagnostics ------------------------------------------------------------
  * llg_fft_roundtrip: forward then inverse FP32 FFT, by the library's own FFT
@@ -231,7 +257,7 @@ const char *llg_batch_last_error(const llg_batch *b);
  * entries) may be NULL.  LLG_E_DIVERGED if any film diverged. */
 llg_status  llg_batch_run(llg_batch *b, double t_end, double max_err, double dt0,
                           int64_t max_attempts, llg_stats *per_film);
-/* Fixed steps (LLG_EULER, LLG_HEUN or LLG_RK4, Sec. 2.2) of size dt (s) for
+/* Fixed steps (LLG_EULER, LLG_HEUN, LLG_RK3 or LLG_RK4, Sec. 2.2) of size dt (s) for
  * every film, one grouped launch per stage; the per-film arithmetic is that
  * of llg_step on a single-film solver.  LLG_E_DIVERGED if a film's state
  * becomes non-finite. */

@@ -13,11 +13,13 @@ integrating dm/dt = f(m/|m|), so the order of each scheme is kept).  The
 thermal field of Eq. 6 is drawn once per step and held fixed across the
 stages of that step.
 
-Adaptive Dormand-Prince 5(4) (Sec. 2.2 "RKDP"), with the reading of the
-"maximum tolerable error per integration step":
+Adaptive embedded pairs of Sec. 2.2 (Dormand-Prince 5(4), Bogacki-Shampine
+3(2), Cash-Karp 5(4), Heun-Euler 2(1)), with the reading of the "maximum
+tolerable error per integration step":
     err  = max over cells |dt sum_j (b_j - bhat_j) k_j|
     accept if err <= tol
-    dt  <- dt * clamp(0.9 (tol/err)^(1/5), 0.2, 5)      (5 if err == 0)
+    dt  <- dt * clamp(0.9 (tol/err)^(1/(q+1)), 0.2, 5)  (5 if err == 0),
+           q the order of the embedded estimate
     the last step is shortened to land on t_end.
 """
 import math
@@ -49,7 +51,34 @@ DP45 = {
     "bhat": [5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0, -92097.0 / 339200.0,
              187.0 / 2100.0, 1.0 / 40.0],
 }
-TABLEAUX = {"euler": EULER, "heun": HEUN, "rk4": RK4, "rkdp45": DP45}
+# Kutta's third-order method
+RK3 = {"A": [[], [0.5], [-1.0, 2.0]], "b": [1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0]}
+# Heun-Euler 2(1): Heun's method with Euler's as the embedded estimate
+RK12 = {"A": [[], [1.0]], "b": [0.5, 0.5], "bhat": [1.0, 0.0]}
+# Bogacki & Shampine (1989), 3(2) with the first-same-as-last property
+RK23 = {
+    "A": [[], [0.5], [0.0, 0.75], [2.0 / 9.0, 1.0 / 3.0, 4.0 / 9.0]],
+    "b": [2.0 / 9.0, 1.0 / 3.0, 4.0 / 9.0, 0.0],
+    "bhat": [7.0 / 24.0, 0.25, 1.0 / 3.0, 0.125],
+}
+# Cash & Karp (1990), 5(4)
+RKCK = {
+    "A": [
+        [],
+        [0.2],
+        [3.0 / 40.0, 9.0 / 40.0],
+        [0.3, -0.9, 1.2],
+        [-11.0 / 54.0, 2.5, -70.0 / 27.0, 35.0 / 27.0],
+        [1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0],
+    ],
+    "b": [37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0],
+    "bhat": [2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0, 277.0 / 14336.0, 0.25],
+}
+TABLEAUX = {"euler": EULER, "heun": HEUN, "rk3": RK3, "rk4": RK4, "rkdp45": DP45,
+            "rk12": RK12, "rk23": RK23, "rkck": RKCK}
+# adaptive pairs: (tableau, order of the embedded estimate q); the step
+# controller uses the exponent 1/(q+1)
+ADAPTIVE = {"rkdp45": (DP45, 4), "rk23": (RK23, 2), "rkck": (RKCK, 4), "rk12": (RK12, 1)}
 
 
 def normalize(m):
@@ -117,52 +146,60 @@ class Solver:
             self.step_count += 1
         return self.m
 
-    # -- adaptive Dormand-Prince -----------------------------------------------
-    def dp45_attempt(self, dt):
-        """One attempted step: returns (candidate m, err)."""
-        ks = self._stages(DP45, dt)
-        m5 = self._combine(ks, DP45["b"], dt)
+    # -- adaptive embedded pairs (Dormand-Prince by default) --------------------
+    def attempt(self, dt, method="rkdp45"):
+        """One attempted step of an embedded pair: returns (candidate m, err)
+        with err = max over cells |dt sum_j (b_j - bhat_j) k_j|."""
+        tab = ADAPTIVE[method][0]
+        ks = self._stages(tab, dt)
+        m_hi = self._combine(ks, tab["b"], dt)
         diff = np.zeros_like(self.m)
-        for b, bh, k in zip(DP45["b"], DP45["bhat"], ks):
+        for b, bh, k in zip(tab["b"], tab["bhat"], ks):
             if b != bh:
                 diff = diff + (dt * (b - bh)) * k
         err = float(np.max(np.sqrt(np.sum(diff * diff, axis=0))))
-        return self._norm(m5), err
+        return self._norm(m_hi), err
+
+    def dp45_attempt(self, dt):
+        return self.attempt(dt, "rkdp45")
 
     @staticmethod
-    def next_dt(dt, err, tol):
+    def next_dt(dt, err, tol, q=4):
+        """dt * clamp(0.9 (tol/err)^(1/(q+1)), 0.2, 5) for an embedded
+        estimate of order q."""
         if err == 0.0:
             factor = 5.0
         else:
-            factor = 0.9 * (tol / err) ** 0.2
+            factor = 0.9 * (tol / err) ** (1.0 / (q + 1))
         return dt * min(5.0, max(0.2, factor))
 
-    def run_adaptive(self, t_end, tol, dt0, dt_min=1e-18, max_attempts=10 ** 7):
-        """Free-running DP45 to t_end; returns the list of attempts
-        (dt, err, accepted)."""
+    def run_adaptive(self, t_end, tol, dt0, dt_min=1e-18, max_attempts=10 ** 7, method="rkdp45"):
+        """Free-running adaptive integration to t_end; returns the list of
+        attempts (dt, err, accepted)."""
+        q = ADAPTIVE[method][1]
         log = []
         dt = dt0
         while self.t < t_end and len(log) < max_attempts:
             h = min(dt, t_end - self.t)
-            m_new, err = self.dp45_attempt(h)
+            m_new, err = self.attempt(h, method)
             ok = err <= tol
             log.append((h, err, ok))
             if ok:
                 self.m = m_new
                 self.t += h
                 self.step_count += 1
-            dt = self.next_dt(h, err, tol)
+            dt = self.next_dt(h, err, tol, q)
             if dt < dt_min:
                 raise FloatingPointError("step size fell below dt_min")
         return log
 
-    def replay(self, attempts):
+    def replay(self, attempts, method="rkdp45"):
         """Replays a recorded attempt list [(dt, accepted), ...] (e.g. the GPU
         run's), so both trajectories use the same step sizes; returns the
         oracle's own error estimate per attempt."""
         errs = []
         for dt, ok in attempts:
-            m_new, err = self.dp45_attempt(dt)
+            m_new, err = self.attempt(dt, method)
             errs.append(err)
             if ok:
                 self.m = m_new

@@ -17,8 +17,9 @@ LIB_PATH = os.path.join(HERE, "libllg.so")
 LLG_OK, LLG_E_ARG, LLG_E_STATE, LLG_E_NOMEM, LLG_E_DEVICE, LLG_E_UNSUPPORTED, LLG_E_DIVERGED = range(7)
 STATUS_NAMES = ["LLG_OK", "LLG_E_ARG", "LLG_E_STATE", "LLG_E_NOMEM", "LLG_E_DEVICE",
                 "LLG_E_UNSUPPORTED", "LLG_E_DIVERGED"]
-LLG_EULER, LLG_HEUN, LLG_RK4, LLG_RKDP45 = range(4)
-METHODS = {"euler": LLG_EULER, "heun": LLG_HEUN, "rk4": LLG_RK4, "rkdp45": LLG_RKDP45}
+LLG_EULER, LLG_HEUN, LLG_RK4, LLG_RKDP45, LLG_RK12, LLG_RK3, LLG_RK23, LLG_RKCK = range(8)
+METHODS = {"euler": LLG_EULER, "heun": LLG_HEUN, "rk3": LLG_RK3, "rk4": LLG_RK4, "rkdp45": LLG_RKDP45,
+           "rk12": LLG_RK12, "rk23": LLG_RK23, "rkck": LLG_RKCK}
 LLG_HOST, LLG_DEVICE = 0, 1
 TERM_DEMAG, TERM_EXCHANGE, TERM_ANISOTROPY, TERM_ZEEMAN, TERM_THERMAL = 1, 2, 4, 8, 16
 TERM_ALL = 31
@@ -92,6 +93,9 @@ _SIGNATURES = {
     "llg_profile_evals": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                            ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "llg_kernel_bytes": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
+    "llg_autotune": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                      ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "llg_set_variants": ([_P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "llg_fft_roundtrip": ([_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "llg_demag_tensor": ([_P, _P, ctypes.c_int64, _P], ctypes.c_int),
     "llg_batch_create": ([ctypes.c_int, ctypes.POINTER(FilmDesc), ctypes.c_int, ctypes.POINTER(_P)],
@@ -134,6 +138,12 @@ def load(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_1102_3069_amd/build.py "
                            "(or __graft_entry__.build()); there is no fallback path")
+    # PyTorch ships its own HIP runtime; when both are used in one process,
+    # PyTorch's must be loaded first or it cannot find the GPU later
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (args, res) in _SIGNATURES.items():
         fn = getattr(lib, name)
@@ -250,9 +260,9 @@ class Solver:
     def step(self, method, dt, nsteps=1):
         self._chk(self._lib.llg_step(self._h, METHODS[method], float(dt), int(nsteps)))
 
-    def run(self, t_end, max_err=1e-5, dt0=1e-14):
+    def run(self, t_end, max_err=1e-5, dt0=1e-14, method="rkdp45"):
         st = Stats()
-        self._chk(self._lib.llg_run(self._h, LLG_RKDP45, float(t_end), float(max_err), float(dt0),
+        self._chk(self._lib.llg_run(self._h, METHODS[method], float(t_end), float(max_err), float(dt0),
                                     ctypes.byref(st)))
         return st.as_dict()
 
@@ -284,6 +294,17 @@ class Solver:
         b = (ctypes.c_double * 5)()
         self._chk(self._lib.llg_kernel_bytes(self._h, b, 5))
         return dict(zip(KERNEL_KINDS, list(b)))
+
+    def autotune(self, iters=20):
+        """Times the compiled (row, column) variants on H_eff evaluations of
+        the current state; returns ({(r, c): ms per eval}, (r, c) chosen)."""
+        ms = (ctypes.c_double * 4)()
+        ch = (ctypes.c_int * 2)()
+        self._chk(self._lib.llg_autotune(self._h, int(iters), ms, 4, ch))
+        return {(r, c): ms[2 * r + c] for r in range(2) for c in range(2)}, (ch[0], ch[1])
+
+    def set_variants(self, row_var, col_var):
+        self._chk(self._lib.llg_set_variants(self._h, int(row_var), int(col_var)))
 
     def fft_roundtrip(self, data, inverse_only=False):
         """data: complex64 array (batch, n); returns the library's

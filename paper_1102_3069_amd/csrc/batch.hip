@@ -43,6 +43,7 @@ struct BatchFilm {
     float* kfs[2] = {nullptr, nullptr};
     llg_attempt* log = nullptr;
     int row_blocks = 0, col_blocks = 0;
+    int rvar = 0, cvar = 0;             // compiled variants of its lengths
 };
 
 }  // namespace
@@ -60,10 +61,16 @@ struct llg_batch {
     FilmRow* d_prep = nullptr;          // stage-2 input and its forward pass
     FilmRow* d_stage[6] = {};           // stages 2..7
     FilmCol* d_col = nullptr;
-    int2* d_rowmap = nullptr;
-    int2* d_colmap = nullptr;
-    int nrowblk = 0, ncolblk = 0;
-    int lds_fwd = 0, lds_inv = 0, lds_col = 0;
+    // length classes: films of one compiled row (column) variant share a
+    // launch; the launches of one pass run as parallel branches
+    struct Class {
+        int len = 0, var = 0;
+        int2* map = nullptr;            // (film, local block) of every block
+        int nblocks = 0;
+    };
+    std::vector<Class> rows, cols;
+    std::vector<hipStream_t> aux;       // branch streams (default priority)
+    std::vector<hipEvent_t> ev;         // fork / join events
     hipGraphExec_t graph = nullptr;
     bool k1_valid = false;
     // fixed steps: per-stage arguments and the captured step of one method
@@ -125,6 +132,7 @@ FilmRow row_base(const llg_batch* b, int i) {
     r.twx = f.twx;
     r.S = f.S;
     r.st = b->st + i;
+    r.var = f.rvar;
     return r;
 }
 
@@ -181,38 +189,101 @@ llg_status build_launch_args(llg_batch* b) {
         }
         col[i].a = col_args(f);
         col[i].st = b->st + i;
+        col[i].var = f.cvar;
     }
     BCHK(b, upload(&b->d_fwd_plain, fwd_plain));
     BCHK(b, upload(&b->d_konly, konly));
     BCHK(b, upload(&b->d_prep, prep));
     for (int s = 0; s < 6; ++s) BCHK(b, upload(&b->d_stage[s], stage[s]));
     BCHK(b, upload(&b->d_col, col));
-    // block maps
-    std::vector<int2> rmap, cmap;
-    for (int i = 0; i < nf; ++i) {
-        for (int k = 0; k < b->films[i].row_blocks; ++k) rmap.push_back(make_int2(i, k));
-        for (int k = 0; k < b->films[i].col_blocks; ++k) cmap.push_back(make_int2(i, k));
+    // block maps per length class, largest classes first
+    auto build = [&](bool row, std::vector<llg_batch::Class>& out) -> llg_status {
+        std::vector<std::pair<int, int>> keys;
+        for (int i = 0; i < nf; ++i) {
+            const BatchFilm& f = b->films[i];
+            const std::pair<int, int> k = row ? std::make_pair(f.g.Px, f.rvar) : std::make_pair(f.g.Py / 2, f.cvar);
+            if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+        }
+        std::sort(keys.begin(), keys.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+            return x.first > y.first || (x.first == y.first && x.second < y.second);
+        });
+        for (const auto& k : keys) {
+            std::vector<int2> map;
+            for (int i = 0; i < nf; ++i) {
+                const BatchFilm& f = b->films[i];
+                const bool in = row ? (f.g.Px == k.first && f.rvar == k.second)
+                                    : (f.g.Py / 2 == k.first && f.cvar == k.second);
+                if (!in) continue;
+                const int nb = row ? f.row_blocks : f.col_blocks;
+                for (int j = 0; j < nb; ++j) map.push_back(make_int2(i, j));
+            }
+            llg_batch::Class c;
+            c.len = k.first;
+            c.var = k.second;
+            c.nblocks = (int)map.size();
+            BCHK(b, upload(&c.map, map));
+            out.push_back(c);
+        }
+        return LLG_OK;
+    };
+    llg_status rc = build(true, b->rows);
+    if (rc == LLG_OK) rc = build(false, b->cols);
+    if (rc != LLG_OK) return rc;
+    const size_t nbr = std::max(b->rows.size(), b->cols.size());
+    for (size_t i = 1; i < nbr; ++i) {
+        hipStream_t st = nullptr;
+        BCHK(b, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        b->aux.push_back(st);
     }
-    b->nrowblk = (int)rmap.size();
-    b->ncolblk = (int)cmap.size();
-    BCHK(b, upload(&b->d_rowmap, rmap));
-    BCHK(b, upload(&b->d_colmap, cmap));
+    for (size_t i = 0; i < nbr; ++i) {
+        hipEvent_t e = nullptr;
+        BCHK(b, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->ev.push_back(e);
+    }
     return LLG_OK;
 }
+
+// one pass over all films: a launch per length class, the classes as
+// parallel branches forked from and joined back into the batch stream
+enum PassKind { PASS_ROW_FWD, PASS_ROW_INV, PASS_COL };
+
+llg_status pass(llg_batch* b, PassKind kind, const FilmRow* rows) {
+    const std::vector<llg_batch::Class>& cl = kind == PASS_COL ? b->cols : b->rows;
+    const int n = (int)cl.size();
+    if (n > 1) {
+        BCHK(b, hipEventRecord(b->ev[0], b->stream));
+        for (int i = 1; i < n; ++i) BCHK(b, hipStreamWaitEvent(b->aux[i - 1], b->ev[0], 0));
+    }
+    for (int i = 0; i < n; ++i) {
+        hipStream_t st = i == 0 ? b->stream : b->aux[i - 1];
+        const llg_batch::Class& c = cl[i];
+        hipError_t e = kind == PASS_ROW_FWD ? launch_row_fwd_group(c.len, c.var, rows, c.map, c.nblocks, st)
+                     : kind == PASS_ROW_INV ? launch_row_inv_group(c.len, c.var, rows, c.map, c.nblocks, st)
+                                            : launch_col_group(c.len, c.var, b->d_col, c.map, c.nblocks, st);
+        BCHK(b, e);
+    }
+    for (int i = 1; i < n; ++i) {
+        BCHK(b, hipEventRecord(b->ev[i], b->aux[i - 1]));
+        BCHK(b, hipStreamWaitEvent(b->stream, b->ev[i], 0));
+    }
+    return LLG_OK;
+}
+
+#define PASS(b, kind, rows)                                  \
+    do {                                                     \
+        llg_status rc_ = pass((b), (kind), (rows));          \
+        if (rc_ != LLG_OK) return rc_;                       \
+    } while (0)
 
 llg_status enqueue_attempt(llg_batch* b) {
     const int nf = (int)b->films.size();
-    BCHK(b, launch_row_fwd_group(b->d_prep, b->d_rowmap, b->nrowblk, b->lds_fwd, b->stream));
+    PASS(b, PASS_ROW_FWD, b->d_prep);
     for (int s = 0; s < 6; ++s) {
-        BCHK(b, launch_col_group(b->d_col, b->d_colmap, b->ncolblk, b->lds_col, b->stream));
-        BCHK(b, launch_row_inv_group(b->d_stage[s], b->d_rowmap, b->nrowblk, b->lds_inv, b->stream));
+        PASS(b, PASS_COL, nullptr);
+        PASS(b, PASS_ROW_INV, b->d_stage[s]);
     }
     BCHK(b, launch_ctrl_dp45_group(b->st, nf, b->stream));
     return LLG_OK;
-}
-
-Tableau fixed_tableau(llg_method m) {
-    return m == LLG_EULER ? tab_euler() : m == LLG_HEUN ? tab_heun() : tab_rk4();
 }
 
 // per-stage arguments of a fixed step; buffer roles follow the single-film
@@ -251,8 +322,8 @@ llg_status build_fixed_args(llg_batch* b, const Tableau& t) {
 
 llg_status enqueue_fixed(llg_batch* b, int nstages) {
     for (int st = 0; st < nstages; ++st) {
-        BCHK(b, launch_col_group(b->d_col, b->d_colmap, b->ncolblk, b->lds_col, b->stream));
-        BCHK(b, launch_row_inv_group(b->d_fix[st], b->d_rowmap, b->nrowblk, b->lds_inv, b->stream));
+        PASS(b, PASS_COL, nullptr);
+        PASS(b, PASS_ROW_INV, b->d_fix[st]);
     }
     BCHK(b, launch_ctrl_fixed_group(b->st, (int)b->films.size(), nstages, b->stream));
     return LLG_OK;
@@ -303,7 +374,10 @@ llg_status llg_batch_create(int device, const llg_film_desc* films, int nfilms, 
         if (!(un > 0)) return bfail(b, LLG_E_ARG, "film %d: anisotropy axis must be non-zero", i);
         const int Px = pad_len(d.nx), Py = pad_len(d.ny);
         const int L = Py / 2;
-        if (!fast2d_row_ok(Px) || !fast2d_col_ok(L, 1) || (Px / 2) % fast2d_col_width(L) || d.ny > L)
+        f.rvar = fast2d_row_variant(Px);
+        f.cvar = fast2d_col_variant(L);
+        if (!fast2d_row_ok(Px, f.rvar) || !fast2d_col_ok(L, 1, f.cvar) || (Px / 2) % fast2d_col_width(L, f.cvar) ||
+            d.ny > L)
             return bfail(b, LLG_E_UNSUPPORTED,
                          "film %d: %d x %d needs FFT lengths %d x %d without a compiled batched kernel", i,
                          d.nx, d.ny, Px, Py);
@@ -318,12 +392,9 @@ llg_status llg_batch_create(int device, const llg_film_desc* films, int nfilms, 
         g.nkx = Px / 2 + 1;
         g.nkxp = (g.nkx + 15) / 16 * 16;
         g.split_y = 1; g.split_z = 0;
-        const int rpb = fast2d_row_rows_per_block(Px);
+        const int rpb = fast2d_row_rows_per_block(Px, f.rvar);
         f.row_blocks = (g.nrows + rpb - 1) / rpb;
-        f.col_blocks = (Px / 2) / fast2d_col_width(L);
-        b->lds_fwd = std::max(b->lds_fwd, fast2d_row_fwd_lds(Px));
-        b->lds_inv = std::max(b->lds_inv, fast2d_row_inv_lds(Px));
-        b->lds_col = std::max(b->lds_col, fast2d_col_lds(L));
+        f.col_blocks = (Px / 2) / fast2d_col_width(L, f.cvar);
         const size_t vec = sizeof(float) * 3 * (size_t)g.ncells;
         BCHK(b, make_tw(Px, &f.twx));
         BCHK(b, make_tw(Py, &f.twy));
@@ -386,7 +457,10 @@ void llg_batch_destroy(llg_batch* b) {
     bfree(b->st);
     bfree(b->d_fwd_plain); bfree(b->d_konly); bfree(b->d_prep); bfree(b->d_col);
     for (auto p : b->d_stage) bfree(p);
-    bfree(b->d_rowmap); bfree(b->d_colmap);
+    for (auto& c : b->rows) bfree(c.map);
+    for (auto& c : b->cols) bfree(c.map);
+    for (auto st : b->aux) (void)hipStreamDestroy(st);
+    for (auto e : b->ev) (void)hipEventDestroy(e);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -404,9 +478,9 @@ llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0,
     llg_status rc = read_states(b, h);
     if (rc != LLG_OK) return rc;
     if (!b->k1_valid) {
-        BCHK(b, launch_row_fwd_group(b->d_fwd_plain, b->d_rowmap, b->nrowblk, b->lds_fwd, b->stream));
-        BCHK(b, launch_col_group(b->d_col, b->d_colmap, b->ncolblk, b->lds_col, b->stream));
-        BCHK(b, launch_row_inv_group(b->d_konly, b->d_rowmap, b->nrowblk, b->lds_inv, b->stream));
+        PASS(b, PASS_ROW_FWD, b->d_fwd_plain);
+        PASS(b, PASS_COL, nullptr);
+        PASS(b, PASS_ROW_INV, b->d_konly);
         b->k1_valid = true;
         for (auto& s : h) s.nevals += 1;
     }
@@ -415,6 +489,8 @@ llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0,
         if (s.health) return bfail(b, LLG_E_DIVERGED, "a film has already diverged");
         s.t_end = t_end;
         s.tol = max_err;
+        s.ev_attempt = 6;          // Dormand-Prince: six evaluations per attempt
+        s.ctrl_exp = 0.2;
         s.dt_min = kDtMin;
         s.err_bits = 0u;
         s.done = !(t_end > s.t);
@@ -490,8 +566,8 @@ llg_status llg_batch_step(llg_batch* b, llg_method method, double dt, int64_t ns
     if (!b) return LLG_E_ARG;
     b->err.clear();
     BCHK(b, hipSetDevice(b->device));
-    if (method != LLG_EULER && method != LLG_HEUN && method != LLG_RK4)
-        return bfail(b, LLG_E_ARG, "llg_batch_step takes Euler, Heun or RK4");
+    Tableau t;
+    if (!fixed_of(method, &t)) return bfail(b, LLG_E_ARG, "llg_batch_step takes Euler, Heun, RK3 or RK4");
     if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return bfail(b, LLG_E_ARG, "need dt > 0, nsteps >= 0");
     if (nsteps == 0) return LLG_OK;
     std::vector<DevState> h;
@@ -506,8 +582,7 @@ llg_status llg_batch_step(llg_batch* b, llg_method method, double dt, int64_t ns
     }
     if ((rc = write_states(b, h)) != LLG_OK) return rc;
     if (!b->spec_valid)
-        BCHK(b, launch_row_fwd_group(b->d_fwd_plain, b->d_rowmap, b->nrowblk, b->lds_fwd, b->stream));
-    const Tableau t = fixed_tableau(method);
+        PASS(b, PASS_ROW_FWD, b->d_fwd_plain);
     if (!b->gfix || b->fix_method != (int)method) {
         if (b->gfix) (void)hipGraphExecDestroy(b->gfix);
         b->gfix = nullptr;

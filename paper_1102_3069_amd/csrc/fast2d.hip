@@ -14,6 +14,8 @@
 // group, the two halves of a zero-padded axis meet in LDS at the end.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "cell_physics.hpp"
 #include "internal.hpp"
 #include "lane_fft.hpp"
@@ -22,7 +24,7 @@ namespace llg {
 
 namespace {
 
-constexpr int FRT = 192;   // threads of a fast row block (three wavefronts)
+constexpr int FRT = 384;   // threads of a fast row block (six wavefronts)
 
 __device__ __forceinline__ float2 mk2(float x, float y) { float2 r; r.x = x; r.y = y; return r; }
 
@@ -41,159 +43,193 @@ __device__ __forceinline__ float2 partner_odd(const float2 (&z)[E], int i, int l
 }
 
 // ---------------------------------------------------------------------------
-// rows: forward transform of the new magnetisation and packed store
+// rows: every length-PX row transform is split into its even- and
+// odd-frequency halves of length H = PX/2, each computed by its own lane
+// group, so a row pair occupies six groups: (mx + i my of the first row,
+// of the second row, mz of the first + i mz of the second) x (even, odd).
+//   forward:  X[2j]   = FFT_H(a_n + a_{n+H})
+//             X[2j+1] = FFT_H((a_n - a_{n+H}) W^n)     (a_{n+H} = 0 unless x is periodic)
+//   inverse:  x_n     = IFFT_H(X[2j])[n] + W^-n IFFT_H(X[2j+1])[n]
+//             x_{n+H} = IFFT_H(X[2j])[n] - W^-n IFFT_H(X[2j+1])[n]
+// with W = exp(-2 pi i / PX).  Spectrum columns are stored in the order
+// col = h * PX/4 + j  <->  kx = 2j + h (h = 0 even, 1 odd), kx < PX/2.
+// The per-cell work (fields, torque, stage combination) is spread over all
+// threads of the block, cell by cell in row order.
 // ---------------------------------------------------------------------------
 constexpr int lds_align(int b) { return (b + 15) / 16 * 16; }
 
-template <int PX, int E>
-struct RowFast {
-    static constexpr int P = PX / E;
-    static constexpr int RP = 64 / P;
-    static constexpr int HE = E / 2;
-    static constexpr int SC = LfScratch<PX>::size;
-    static constexpr int NR = 2 * RP + 2;               // staged m rows
-    using F = LaneFFT<PX, E, 1, float2>;
-    // dynamic LDS carve-up (bytes): twiddles, FFT scratch, exchange rows,
-    // staged m rows, staged m0 rows, reduction slots
-    static constexpr int O_TW = 0;
-    static constexpr int O_SCR = lds_align(O_TW + PX * 8);
-    static constexpr int O_XCH = lds_align(O_SCR + 3 * RP * SC * 8);
-    static constexpr int O_M = lds_align(O_XCH + RP * 2 * PX * 4);
-    static constexpr int fwd_bytes() { return O_M; }
-    template <bool XPER> static constexpr int nxm() { return XPER ? PX : PX / 2; }
-    template <bool XPER> static constexpr int o_m0() { return lds_align(O_M + NR * 3 * nxm<XPER>() * 4); }
-    template <bool XPER> static constexpr int o_wmax() { return lds_align(o_m0<XPER>() + 2 * RP * 3 * nxm<XPER>() * 4); }
-    template <bool XPER> static constexpr int inv_bytes() { return lds_align(o_wmax<XPER>() + 16); }
+// (row, x) of flat cell index e of rows of length nx, without an integer
+// division: rnx = 1/nx in FP32 gives the row within one, fixed up exactly
+// (e < 2^24)
+__device__ __forceinline__ void split_cell(int e, int nx, float rnx, int& ri, int& x) {
+    ri = (int)((float)e * rnx);
+    x = e - ri * nx;
+    if (x >= nx) { ++ri; x -= nx; }
+    else if (x < 0) { --ri; x += nx; }
+}
 
-    // kind 0/1 lanes hold the new (mx, my, mz) of their row in nx/ny/nz
-    // (cells x = lg + P i); kind 2 lanes collect mz of both rows from xch.
-    static __device__ __forceinline__ void forward_store(const Grid& g, float2* __restrict__ S,
-                                                         float2* scr, const float2* tw, float* xch,
-                                                         const float (&nmx)[E], const float (&nmy)[E],
-                                                         const float (&nmz)[E], int kind, int lg,
-                                                         int gbase, int r0, bool v0, bool v1) {
+template <int PX, int E2>
+struct RowSplit {
+    static constexpr int H = PX / 2;
+    static constexpr int P = H / E2;               // lanes per half transform
+    static constexpr int RP = 64 / P;              // row pairs per block
+    static constexpr int NG = 6 * RP;              // lane groups per block
+    static constexpr int Q = PX / 4;               // stored columns per half
+    static_assert(NG * P == FRT, "row blocks have FRT threads");
+    static constexpr int SC = LfScratch<H>::size;
+    using F = LaneFFT<H, E2, 2, float2>;
+    // LDS (bytes): twiddles W^m (m < PX); FFT scratch, aliased by the
+    // exchange of the inverse transforms; staged m rows (with the y
+    // neighbours); new m rows; reduction slots
+    static constexpr int O_TW = 0;
+    static constexpr int O_SCR = lds_align(PX * 8);
+    static constexpr int SCR_BYTES = NG * SC * 8;
+    static_assert(NG * H * 8 <= SCR_BYTES, "the exchange fits the scratch");
+    static constexpr int O_M = lds_align(O_SCR + SCR_BYTES);
+    static constexpr int NR = 2 * RP + 2;
+    template <bool XPER> static constexpr int nxm() { return XPER ? PX : H; }
+    template <bool XPER> static constexpr int fwd_bytes() { return lds_align(O_M + 2 * RP * 3 * nxm<XPER>() * 4); }
+    template <bool XPER> static constexpr int o_nm() { return lds_align(O_M + NR * 3 * nxm<XPER>() * 4); }
+    template <bool XPER> static constexpr int o_wmax() { return lds_align(o_nm<XPER>() + 2 * RP * 3 * nxm<XPER>() * 4); }
+    template <bool XPER> static constexpr int inv_bytes() { return lds_align(o_wmax<XPER>() + 8 * 4); }
+
+    // group gi -> (kind, half, pair), the pair fastest: the groups of one
+    // wavefront share kind and half
+    static __device__ __forceinline__ void group(int gi, int& kind, int& half, int& pair) {
+        pair = gi % RP;
+        const int kh = gi / RP;
+        half = kh & 1;
+        kind = kh >> 1;
+    }
+
+    // forward transform of the block's rows, whose magnetisation sits in LDS
+    // nm[row][c][x] (row stride 3 NXM), and store of the columns kx < PX/2
+    template <int NXM>
+    static __device__ __forceinline__ void forward(const Grid& g, float2* __restrict__ S, float2* scr,
+                                                   const float2* tw, const float* nm, int kind, int half,
+                                                   int pair, int lg, int gbase, int rb) {
         const int nx = g.nx;
-        float* xr = xch + (kind & 1) * PX;
-        if (kind < 2) {
+        const int r0 = rb + 2 * pair;
+        const bool v0 = r0 < g.nrows, v1 = r0 + 1 < g.nrows;
+        const float* ra = nm + (2 * pair + (kind == 1 ? 1 : 0)) * 3 * NXM;
+        const float* rz0 = nm + (2 * pair) * 3 * NXM + 2 * NXM;
+        const float* rz1 = rz0 + 3 * NXM;
+        const bool va = kind == 1 ? v1 : v0;
+        auto at = [&](int n) -> float2 {
+            if (n >= nx) return mk2(0.f, 0.f);
+            if (kind < 2) return va ? mk2(ra[n], ra[NXM + n]) : mk2(0.f, 0.f);
+            return mk2(v0 ? rz0[n] : 0.f, v1 ? rz1[n] : 0.f);
+        };
+        float2 z[E2];
 #pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const int x = lg + P * i;
-                if (x < nx) xr[x] = nmz[i];
+        for (int i = 0; i < E2; ++i) {
+            const int n = lg + P * i;
+            float2 a = at(n);
+            if (NXM == PX) {
+                const float2 b = at(n + H);
+                a = half ? mk2(a.x - b.x, a.y - b.y) : mk2(a.x + b.x, a.y + b.y);
             }
-        }
-        __syncthreads();
-        float2 z[E];
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const int x = lg + P * i;
-            z[i] = mk2(0.f, 0.f);
-            if (x < nx) {
-                if (kind < 2) {
-                    z[i] = mk2(nmx[i], nmy[i]);
-                } else {
-                    z[i] = mk2(v0 ? xch[x] : 0.f, v1 ? xch[PX + x] : 0.f);
-                }
-            }
+            z[i] = half ? cmul(a, tw[n]) : a;
         }
         F::template run<false>(z, scr, tw, lg);
-        const long long cs = (long long)g.nrows * g.nkxp;
-        const float2 zN = z[HE];   // k = Px/2 on lane 0
+        const int cs = g.nrows * g.nkxp;
+        const float2 zN = z[E2 / 2];   // X[PX/2]: even half, lane 0
+        float2* s0 = S + r0 * g.nkxp;
+        float2* s1 = s0 + g.nkxp;
 #pragma unroll
-        for (int i = 0; i < HE; ++i) {
-            const int k = lg + P * i;
+        for (int i = 0; i < E2 / 2; ++i) {
+            const int j = lg + P * i;
             const float2 zk = z[i];
-            const float2 zm = partner_mirror<E, P>(z, i, lg, gbase);
+            const float2 zm = half ? partner_odd<E2, P>(z, i, lg, gbase) : partner_mirror<E2, P>(z, i, lg, gbase);
             float2 A = mk2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
             float2 B = mk2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-            if (k == 0) {   // pack the real DC and Nyquist coefficients
+            if (half == 0 && j == 0) {   // pack the real DC and Nyquist coefficients
                 A = mk2(zk.x, zN.x);
                 B = mk2(zk.y, zN.y);
             }
-            if (kind == 0 && v0) {
-                S[(long long)r0 * g.nkxp + k] = A;
-                S[cs + (long long)r0 * g.nkxp + k] = B;
-            } else if (kind == 1 && v1) {
-                S[(long long)(r0 + 1) * g.nkxp + k] = A;
-                S[cs + (long long)(r0 + 1) * g.nkxp + k] = B;
-            } else if (kind == 2) {
-                if (v0) S[2 * cs + (long long)r0 * g.nkxp + k] = A;
-                if (v1) S[2 * cs + (long long)(r0 + 1) * g.nkxp + k] = B;
+            const int col = half * Q + j;
+            if (kind == 0) {
+                if (v0) { s0[col] = A; s0[cs + col] = B; }
+            } else if (kind == 1) {
+                if (v1) { s1[col] = A; s1[cs + col] = B; }
+            } else {
+                if (v0) s0[2 * cs + col] = A;
+                if (v1) s1[2 * cs + col] = B;
             }
         }
     }
 };
 
-template <int PX, int E>
+template <int PX, int E2, bool XPER>
 __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __restrict__ twx,
                                              float2* __restrict__ S, const FwdArgs& fa,
                                              DevState* __restrict__ st, int blk, char* lds) {
-    using R = RowFast<PX, E>;
-    constexpr int P = R::P, RP = R::RP;
+    using R = RowSplit<PX, E2>;
+    constexpr int NXM = R::template nxm<XPER>();
     float2* tw = (float2*)(lds + R::O_TW);
     float2* scr = (float2*)(lds + R::O_SCR);
-    float* xch = (float*)(lds + R::O_XCH);
+    float* nm = (float*)(lds + R::O_M);
     if (st->done) return;
     const int tid = threadIdx.x;
-    const int gi = tid / P, lg = tid % P;
-    const int pair = gi / 3, kind = gi % 3;
+    const int gi = tid / R::P, lg = tid % R::P;
+    int kind, half, pair;
+    R::group(gi, kind, half, pair);
     const int gbase = (tid & 63) - lg;
-    const int r0 = 2 * (blk * RP + pair);
-    const bool v0 = r0 < g.nrows, v1 = r0 + 1 < g.nrows;
+    const int rb = 2 * R::RP * blk;
     for (int m = tid; m < PX; m += FRT) tw[m] = twx[m];
     const int cur = st->cur;
     const float c1 = st->dtau * fa.a1;
-    const long long cs = g.ncells;
+    const int cs = g.ncells;
     const float* mi = resolve(fa.m_in, cur);
     const float* m0 = resolve(fa.m0, cur);
     const float* k1 = resolve(fa.k1, cur);
     float* mo = resolve(fa.m_out, cur);
-    float nmx[E], nmy[E], nmz[E];
-    const int r = r0 + (kind & 1);
-    const bool vr = kind < 2 && ((kind == 0) ? v0 : v1);
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-        nmx[i] = nmy[i] = nmz[i] = 0.f;
-        const int x = lg + P * i;
-        if (vr && x < g.nx) {
-            const long long q = (long long)r * g.nx + x;
-            if (fa.combine) {
-                float ax = m0[q] + c1 * k1[q];
-                float ay = m0[cs + q] + c1 * k1[cs + q];
-                float az = m0[2 * cs + q] + c1 * k1[2 * cs + q];
-                const float inv = rsqrtf(ax * ax + ay * ay + az * az);
-                ax *= inv; ay *= inv; az *= inv;
-                mo[q] = ax; mo[cs + q] = ay; mo[2 * cs + q] = az;
-                nmx[i] = ax; nmy[i] = ay; nmz[i] = az;
-            } else {
-                nmx[i] = mi[q]; nmy[i] = mi[cs + q]; nmz[i] = mi[2 * cs + q];
-            }
+    const int nx = g.nx;
+    const float rnx = 1.0f / (float)nx;
+    const int nrow = min(2 * R::RP, g.nrows - rb);
+    for (int e = tid; e < nrow * nx; e += FRT) {
+        int ri, x;
+        split_cell(e, nx, rnx, ri, x);
+        const int q = (rb + ri) * nx + x;
+        float ax, ay, az;
+        if (fa.combine) {
+            ax = m0[q] + c1 * k1[q];
+            ay = m0[cs + q] + c1 * k1[cs + q];
+            az = m0[2 * cs + q] + c1 * k1[2 * cs + q];
+            const float inv = rsqrtf(ax * ax + ay * ay + az * az);
+            ax *= inv; ay *= inv; az *= inv;
+            mo[q] = ax; mo[cs + q] = ay; mo[2 * cs + q] = az;
+        } else {
+            ax = mi[q]; ay = mi[cs + q]; az = mi[2 * cs + q];
         }
+        float* row = nm + ri * 3 * NXM;
+        row[x] = ax; row[NXM + x] = ay; row[2 * NXM + x] = az;
     }
-    __syncthreads();   // twiddle table
-    R::forward_store(g, S, scr + gi * R::SC, tw, xch + pair * 2 * PX, nmx, nmy, nmz, kind, lg, gbase, r0, v0, v1);
+    __syncthreads();
+    R::template forward<NXM>(g, S, scr + gi * R::SC, tw, nm, kind, half, pair, lg, gbase, rb);
 }
 
-template <int PX, int E>
+template <int PX, int E2, bool XPER>
 __global__ __launch_bounds__(FRT) void row_fwd_fast(Grid g, const float2* __restrict__ twx,
                                                     float2* __restrict__ S, FwdArgs fa,
                                                     DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
-    row_fwd_body<PX, E>(g, twx, S, fa, st, blockIdx.x, dyn_lds);
+    row_fwd_body<PX, E2, XPER>(g, twx, S, fa, st, blockIdx.x, dyn_lds);
 }
 
 // exchange + anisotropy + applied + thermal field of cell x of a row whose
 // magnetisation and that of its y neighbours sit in LDS (rm, rc, rp: rows
-// y-1, y, y+1, component stride nx; null where the neighbour is missing)
+// y-1, y, y+1, component stride cstr; null where the neighbour is missing)
 __device__ __forceinline__ void local_field_lds(const Grid& g, const Phys& p, const float* rm,
-                                                const float* rc, const float* rp, int r, int x,
+                                                const float* rc, const float* rp, int cstr, int r, int x,
                                                 uint64_t step, float& hx, float& hy, float& hz) {
     const int nx = g.nx;
-    const float mx = rc[x], my = rc[nx + x], mz = rc[2 * nx + x];
+    const float mx = rc[x], my = rc[cstr + x], mz = rc[2 * cstr + x];
     float sx = 0.f, sy = 0.f, sz = 0.f;
     auto nb = [&](const float* row, int xx, float c) {
         sx += c * (row[xx] - mx);
-        sy += c * (row[nx + xx] - my);
-        sz += c * (row[2 * nx + xx] - mz);
+        sy += c * (row[cstr + xx] - my);
+        sz += c * (row[2 * cstr + xx] - mz);
     };
     if (p.cex[0] != 0.f && nx > 1) {
         const float c = p.cex[0];
@@ -218,188 +254,169 @@ __device__ __forceinline__ void local_field_lds(const Grid& g, const Phys& p, co
 }
 
 // XPER: the x axis is periodic (nx == PX), else nx <= PX/2
-template <int PX, int E, bool XPER>
+template <int PX, int E2, bool XPER>
 __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const float2* __restrict__ twx,
                                              float2* __restrict__ S, const StageArgs& sa,
                                              DevState* __restrict__ st, int blk, char* lds) {
-    using R = RowFast<PX, E>;
+    using R = RowSplit<PX, E2>;
     using F = typename R::F;
-    constexpr int P = R::P, RP = R::RP;
-    constexpr int NXM = R::template nxm<XPER>();     // largest nx
-    constexpr int IC = XPER ? E : E / 2;             // cell slots per lane
-    constexpr int NR = R::NR;                        // staged m rows (with the y neighbours)
+    constexpr int P = R::P, RP = R::RP, H = R::H, Q = R::Q;
+    constexpr int NXM = R::template nxm<XPER>();
     float2* tw = (float2*)(lds + R::O_TW);
     float2* scr = (float2*)(lds + R::O_SCR);
-    float* xch = (float*)(lds + R::O_XCH);
+    float2* xch = scr;                               // aliases the scratch after the transforms
     float* mrow = (float*)(lds + R::O_M);
-    float* m0row = (float*)(lds + R::template o_m0<XPER>());
+    float* nm = (float*)(lds + R::template o_nm<XPER>());
     float* wmax = (float*)(lds + R::template o_wmax<XPER>());
     if (st->done) return;
     const int tid = threadIdx.x;
     const int gi = tid / P, lg = tid % P;
-    const int pair = gi / 3, kind = gi % 3;
+    int kind, half, pair;
+    R::group(gi, kind, half, pair);
     const int gbase = (tid & 63) - lg;
-    const int rb = 2 * blk * RP;                    // first row of the block
+    const int rb = 2 * RP * blk;                     // first row of the block
     const int r0 = rb + 2 * pair;
     const bool v0 = r0 < g.nrows, v1 = r0 + 1 < g.nrows;
     const int cur = st->cur;
     const float dtau = st->dtau;
     const uint64_t step = (uint64_t)st->step;
     const int nx = g.nx, ny = g.ny;
-    const long long cs = g.ncells;
+    const int cs = g.ncells;
     const float* mi = resolve(sa.m_in, cur);
     const float* m0 = resolve(sa.m0, cur);
     float* mo = resolve(sa.m_out, cur);
     float* ko = resolve(sa.k_out, cur);
     const bool stage = sa.mode == ROW_STAGE;
+    const bool errm = sa.mode == ROW_ERROR || (stage && sa.with_err);
 
-    // ---- issue every global read of the block up front (coalesced rows)
+    // ---- global reads: twiddles, m rows rb-1 .. rb+2RP (y neighbours wrap
+    // on a periodic y axis), this group's half spectrum
     for (int m = tid; m < PX; m += FRT) tw[m] = twx[m];
-    // rows rb-1 .. rb+2RP (y neighbours wrap on a periodic y axis)
-    for (int e = tid; e < NR * 3 * nx; e += FRT) {
-        const int q = e / (3 * nx), t = e - q * 3 * nx;
-        const int c = t / nx, x = t - c * nx;
+    for (int q = 0; q < R::NR; ++q) {
         int row = rb - 1 + q;
         bool ok = row >= 0 && row < g.nrows;
-        if (g.pbc[1]) { row = (row + ny) % ny; ok = true; }
-        mrow[q * 3 * NXM + t] = ok ? mi[c * cs + (long long)row * nx + x] : 0.f;
-    }
-    if (stage) {
-        for (int e = tid; e < 2 * RP * 3 * nx; e += FRT) {
-            const int q = e / (3 * nx), t = e - q * 3 * nx;
-            const int c = t / nx, x = t - c * nx;
-            const int row = rb + q;
-            m0row[q * 3 * NXM + t] = row < g.nrows ? m0[c * cs + (long long)row * nx + x] : 0.f;
+        if (g.pbc[1]) { row = row < 0 ? row + ny : (row >= ny ? row - ny : row); ok = true; }
+        const float* src = mi + row * nx;
+        float* dst = mrow + q * 3 * NXM;
+        for (int t = tid; t < 3 * nx; t += FRT) {
+            const int c = t >= nx ? (t >= 2 * nx ? 2 : 1) : 0;
+            const int x = t - c * nx;
+            dst[c * NXM + x] = ok ? src[c * cs + x] : 0.f;
         }
     }
-    float2 z[E];
+    float2 z[E2];
 #pragma unroll
-    for (int i = 0; i < E; ++i) z[i] = mk2(0.f, 0.f);
+    for (int i = 0; i < E2; ++i) z[i] = mk2(0.f, 0.f);
     if (p.demag_on) {
-        const long long scs = (long long)g.nrows * g.nkxp;
+        const int scs = g.nrows * g.nkxp;
         const float2* sa_ = nullptr;
         const float2* sb_ = nullptr;
-        if (kind == 0) { if (v0) { sa_ = S + (long long)r0 * g.nkxp; sb_ = sa_ + scs; } }
-        else if (kind == 1) { if (v1) { sa_ = S + (long long)(r0 + 1) * g.nkxp; sb_ = sa_ + scs; } }
+        if (kind == 0) { if (v0) { sa_ = S + r0 * g.nkxp; sb_ = sa_ + scs; } }
+        else if (kind == 1) { if (v1) { sa_ = S + (r0 + 1) * g.nkxp; sb_ = sa_ + scs; } }
         else {
-            if (v0) sa_ = S + 2 * scs + (long long)r0 * g.nkxp;
-            if (v1) sb_ = S + 2 * scs + (long long)(r0 + 1) * g.nkxp;
+            if (v0) sa_ = S + 2 * scs + r0 * g.nkxp;
+            if (v1) sb_ = S + 2 * scs + (r0 + 1) * g.nkxp;
         }
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const int k = lg + P * i;
-            const bool up = k > PX / 2;
-            const int ka = up ? PX - k : k;
+        for (int i = 0; i < E2; ++i) {
+            // X[k], k = 2j + half, from the stored columns kx < PX/2 and the
+            // Hermitian symmetry X[PX - k] = conj X[k] of a real row
+            const int j = lg + P * i;
+            const int k = 2 * j + half;
             float2 A = mk2(0.f, 0.f), B = mk2(0.f, 0.f);
             if (k == 0 || k == PX / 2) {
                 const bool nyq = k != 0;
                 if (sa_) { const float2 v = sa_[0]; A = mk2(nyq ? v.y : v.x, 0.f); }
                 if (sb_) { const float2 v = sb_[0]; B = mk2(nyq ? v.y : v.x, 0.f); }
             } else {
-                if (sa_) { A = sa_[ka]; if (up) A.y = -A.y; }
-                if (sb_) { B = sb_[ka]; if (up) B.y = -B.y; }
+                const bool up = k > PX / 2;
+                const int col = half ? Q + (up ? H - 1 - j : j) : (up ? H - j : j);
+                if (sa_) { A = sa_[col]; if (up) A.y = -A.y; }
+                if (sb_) { B = sb_[col]; if (up) B.y = -B.y; }
             }
             z[i] = mk2(A.x - B.y, A.y + B.x);
         }
     }
     __syncthreads();   // twiddles and staged rows
+    if (p.demag_on) F::template run<true>(z, scr + gi * R::SC, tw, lg);
+    __syncthreads();   // every transform has left the scratch
     if (p.demag_on) {
-        F::template run<true>(z, scr + gi * R::SC, tw, lg);
-        if (kind == 2) {
+        float2* xo = xch + (((pair * 3 + kind) * 2) + half) * H;
 #pragma unroll
-            for (int i = 0; i < IC; ++i) {
-                const int x = lg + P * i;
-                if (x < nx) { xch[pair * 2 * PX + x] = z[i].x; xch[pair * 2 * PX + PX + x] = z[i].y; }
-            }
+        for (int i = 0; i < E2; ++i) {
+            const int n = lg + P * i;
+            xo[n] = half ? cmul(z[i], cconj(tw[n])) : z[i];
         }
     }
     __syncthreads();
 
-    // ---- per cell: field, torque (kinds 0 and 1: rows r0 and r0+1)
-    const int rr = kind & 1;
-    const int r = r0 + rr;
-    const bool vr = kind < 2 && (rr == 0 ? v0 : v1);
-    const int q = 2 * pair + rr + 1;              // staged row of this lane's cells
-    const int y = r % ny;
-    const float* rc = mrow + q * 3 * NXM;
-    const float* rm = (y > 0 || g.pbc[1]) ? rc - 3 * NXM : nullptr;
-    const float* rp = (y < ny - 1 || g.pbc[1]) ? rc + 3 * NXM : nullptr;
-    if (ny == 1) { rm = nullptr; rp = nullptr; }
-    float kx[IC], ky[IC], kz[IC];
+    // ---- per cell: field, torque, stage combination
+    const int nrow = min(2 * RP, g.nrows - rb);
+    const float rnx = 1.0f / (float)nx;
+    float errmax = 0.f;
     bool bad = false;
-#pragma unroll
-    for (int i = 0; i < IC; ++i) {
-        kx[i] = ky[i] = kz[i] = 0.f;
-        const int x = lg + P * i;
-        if (!(vr && x < nx)) continue;
+    for (int e = tid; e < nrow * nx; e += FRT) {
+        int ri, x;
+        split_cell(e, nx, rnx, ri, x);
+        const int pr = ri >> 1, rr = ri & 1;
+        const int r = rb + ri;
+        const int y = r < ny ? r : r - ny * (r / ny);
+        const float* rc = mrow + (ri + 1) * 3 * NXM;
+        const float* rm = (ny > 1 && (y > 0 || g.pbc[1])) ? rc - 3 * NXM : nullptr;
+        const float* rp = (ny > 1 && (y < ny - 1 || g.pbc[1])) ? rc + 3 * NXM : nullptr;
         float hx = 0.f, hy = 0.f, hz = 0.f;
-        if (p.demag_on) { hx = z[i].x; hy = z[i].y; hz = xch[pair * 2 * PX + rr * PX + x]; }
-        local_field_lds(g, p, rm, rc, rp, r, x, step, hx, hy, hz);
+        if (p.demag_on) {
+            const int n = XPER ? (x < H ? x : x - H) : x;
+            const float2* xa = xch + ((pr * 3 + rr) * 2) * H;
+            const float2* xz = xch + ((pr * 3 + 2) * 2) * H;
+            float2 a = xa[n], b = xa[H + n], c = xz[n], d = xz[H + n];
+            if (XPER && x >= H) { b = mk2(-b.x, -b.y); d = mk2(-d.x, -d.y); }
+            hx = a.x + b.x; hy = a.y + b.y;
+            hz = rr ? c.y + d.y : c.x + d.x;
+        }
+        local_field_lds(g, p, rm, rc, rp, NXM, r, x, step, hx, hy, hz);
+        const int qq = r * nx + x;
         if (sa.mode == ROW_EVAL) {
             float* h = sa.h_out;
-            const long long qq = (long long)r * nx + x;
             h[qq] = hx * p.Ms; h[cs + qq] = hy * p.Ms; h[2 * cs + qq] = hz * p.Ms;
             bad |= !(isfinite(hx) && isfinite(hy) && isfinite(hz));
             continue;
         }
-        ll_torque(p, rc[x], rc[nx + x], rc[2 * nx + x], hx, hy, hz, kx[i], ky[i], kz[i]);
-        bad |= !(isfinite(kx[i]) && isfinite(ky[i]) && isfinite(kz[i]));
+        float kx, ky, kz;
+        ll_torque(p, rc[x], rc[NXM + x], rc[2 * NXM + x], hx, hy, hz, kx, ky, kz);
+        bad |= !(isfinite(kx) && isfinite(ky) && isfinite(kz));
+        if (ko) { ko[qq] = kx; ko[cs + qq] = ky; ko[2 * cs + qq] = kz; }
+        if (sa.mode == ROW_KONLY) continue;
+        // combination with the earlier stages (stage input and/or error)
+        float ax = 0.f, ay = 0.f, az = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
+        if (stage) {
+            const float c = dtau * sa.a[sa.nk - 1];
+            ax = c * kx + m0[qq]; ay = c * ky + m0[cs + qq]; az = c * kz + m0[2 * cs + qq];
+        }
+        if (errm) {
+            const float c = sa.e[sa.nk - 1];
+            ex = c * kx; ey = c * ky; ez = c * kz;
+        }
+        for (int j = 0; j + 1 < sa.nk; ++j) {
+            const float ca = stage ? dtau * sa.a[j] : 0.f;
+            const float ce = errm ? sa.e[j] : 0.f;
+            if (ca == 0.f && ce == 0.f) continue;
+            const float* __restrict__ kj = resolve(sa.kprev[j], cur);
+            const float vx = kj[qq], vy = kj[cs + qq], vz = kj[2 * cs + qq];
+            if (ca != 0.f) { ax += ca * vx; ay += ca * vy; az += ca * vz; }
+            if (ce != 0.f) { ex += ce * vx; ey += ce * vy; ez += ce * vz; }
+        }
+        if (stage) {
+            const float inv = rsqrtf(ax * ax + ay * ay + az * az);
+            ax *= inv; ay *= inv; az *= inv;
+            mo[qq] = ax; mo[cs + qq] = ay; mo[2 * cs + qq] = az;
+            float* row = nm + ri * 3 * NXM;
+            row[x] = ax; row[NXM + x] = ay; row[2 * NXM + x] = az;
+        }
+        if (errm) errmax = fmaxf(errmax, dtau * sqrtf(ex * ex + ey * ey + ez * ez));
     }
     if (bad) atomicOr(&st->health, 1);
-    if (sa.mode == ROW_EVAL) return;
-
-    // ---- combination with the earlier stages: one pass over the cells per
-    // earlier k, all loads of a pass independent of each other
-    float ax[IC], ay[IC], az[IC];
-    const float cl = stage ? dtau * sa.a[sa.nk - 1] : sa.e[sa.nk - 1];
-#pragma unroll
-    for (int i = 0; i < IC; ++i) {
-        const int x = lg + P * i;
-        const bool ok = vr && x < nx;
-        const float* m0r = m0row + (2 * pair + rr) * 3 * NXM;
-        ax[i] = cl * kx[i] + ((stage && ok) ? m0r[x] : 0.f);
-        ay[i] = cl * ky[i] + ((stage && ok) ? m0r[nx + x] : 0.f);
-        az[i] = cl * kz[i] + ((stage && ok) ? m0r[2 * nx + x] : 0.f);
-    }
-    if (sa.mode == ROW_STAGE || sa.mode == ROW_ERROR) {
-        for (int j = 0; j + 1 < sa.nk; ++j) {
-            const float c = stage ? dtau * sa.a[j] : sa.e[j];
-            if (c == 0.f) continue;
-            const float* __restrict__ kj = resolve(sa.kprev[j], cur);
-            float vx[IC], vy[IC], vz[IC];
-#pragma unroll
-            for (int i = 0; i < IC; ++i) {
-                const int x = lg + P * i;
-                const long long qq = (long long)r * nx + x;
-                const bool ok = vr && x < nx;
-                vx[i] = ok ? kj[qq] : 0.f;
-                vy[i] = ok ? kj[cs + qq] : 0.f;
-                vz[i] = ok ? kj[2 * cs + qq] : 0.f;
-            }
-#pragma unroll
-            for (int i = 0; i < IC; ++i) { ax[i] += c * vx[i]; ay[i] += c * vy[i]; az[i] += c * vz[i]; }
-        }
-    }
-    // ---- stores
-    float errmax = 0.f;
-    float nmx[E], nmy[E], nmz[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) nmx[i] = nmy[i] = nmz[i] = 0.f;
-#pragma unroll
-    for (int i = 0; i < IC; ++i) {
-        const int x = lg + P * i;
-        if (!(vr && x < nx)) continue;
-        const long long qq = (long long)r * nx + x;
-        if (ko) { ko[qq] = kx[i]; ko[cs + qq] = ky[i]; ko[2 * cs + qq] = kz[i]; }
-        if (stage) {
-            const float inv = rsqrtf(ax[i] * ax[i] + ay[i] * ay[i] + az[i] * az[i]);
-            nmx[i] = ax[i] * inv; nmy[i] = ay[i] * inv; nmz[i] = az[i] * inv;
-            mo[qq] = nmx[i]; mo[cs + qq] = nmy[i]; mo[2 * cs + qq] = nmz[i];
-        } else if (sa.mode == ROW_ERROR) {
-            errmax = fmaxf(errmax, dtau * sqrtf(ax[i] * ax[i] + ay[i] * ay[i] + az[i] * az[i]));
-        }
-    }
-    if (sa.mode == ROW_ERROR) {
+    if (errm) {
         for (int off = 32; off > 0; off >>= 1) errmax = fmaxf(errmax, __shfl_xor(errmax, off));
         if ((tid & 63) == 0) wmax[tid >> 6] = errmax;
         __syncthreads();
@@ -408,250 +425,213 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             for (int w = 1; w < FRT / 64; ++w) m = fmaxf(m, wmax[w]);
             atomicMax(&st->err_bits, __float_as_uint(m));
         }
-        return;
+        if (!stage) return;
     }
-    if (stage && p.demag_on) {
-        __syncthreads();   // everyone has read xch
-        R::forward_store(g, S, scr + gi * R::SC, tw, xch + pair * 2 * PX, nmx, nmy, nmz, kind, lg, gbase, r0, v0, v1);
+    if (stage && p.demag_on && !sa.skip_fwd) {
+        __syncthreads();   // new rows complete, exchange no longer read
+        R::template forward<NXM>(g, S, scr + gi * R::SC, tw, nm, kind, half, pair, lg, gbase, rb);
     }
 }
 
-template <int PX, int E, bool XPER>
+template <int PX, int E2, bool XPER>
 __global__ __launch_bounds__(FRT) void row_inv_fast(Grid g, Phys p, const float2* __restrict__ twx,
                                                     float2* __restrict__ S, StageArgs sa,
                                                     DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
-    row_inv_body<PX, E, XPER>(g, p, twx, S, sa, st, blockIdx.x, dyn_lds);
+    row_inv_body<PX, E2, XPER>(g, p, twx, S, sa, st, blockIdx.x, dyn_lds);
 }
 
 // ---------------------------------------------------------------------------
-// columns (2D): y transform, product with the kernel spectrum, inverse
+// columns (2D): y transform, product with the kernel spectrum, inverse.
+// The y axis is zero padded (Py = 2L), so every column transform is split
+// into its even and odd frequencies (length L each).  One lane group per
+// (component, half, column): the x and y groups of a column swap their
+// spectra through LDS for the off-diagonal xy term; after the inverse the
+// odd half adds W^-y times its result to the even half's, which stores.
 // ---------------------------------------------------------------------------
-template <int L, int E, bool SPLIT>
-struct ColFast {
+constexpr int CT2 = 384;   // threads of a column block
+
+template <int L, int E>
+struct ColSplit {
     static constexpr int P = L / E;
-    static constexpr int NH = SPLIT ? 2 : 1;
-    static constexpr int W = (512 / (2 * NH * P)) > 0 ? 512 / (2 * NH * P) : 1;
-    static constexpr int UNITS = W * NH * 2;
-    static constexpr int NT = UNITS * P;
-    static_assert(NT == 512, "column blocks have 512 threads");
-    static constexpr int TM = SPLIT ? 2 : 1;
-    using F = LaneFFT<L, E, TM, float2>;
+    static constexpr int W = CT2 / (6 * P);        // columns per block
+    static_assert(W >= 1 && W * 6 * P == CT2, "column blocks have CT2 threads");
+    static constexpr int NG = 6 * W;
     static constexpr int SC = LfScratch<L>::size;
+    using F = LaneFFT<L, E, 2, float2>;
     static constexpr int O_TW = 0;
-    static constexpr int O_SCR = lds_align(O_TW + L * TM * 8);
-    static constexpr int O_COMB = lds_align(O_SCR + UNITS * SC * 8);
-    static constexpr int bytes() { return lds_align(O_COMB + (SPLIT ? W * 3 * L * 8 : 16)); }
+    static constexpr int O_SCR = lds_align(2 * L * 8);
+    static_assert(4 * W * L <= NG * SC && 3 * W * L <= NG * SC, "exchanges fit the scratch");
+    static constexpr int bytes() { return lds_align(O_SCR + NG * SC * 8); }
 };
 
-template <int L, int E, bool SPLIT>
+template <int L, int E>
 __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restrict__ st, int lb, char* lds) {
-    using CF = ColFast<L, E, SPLIT>;
+    using CF = ColSplit<L, E>;
     using F = typename CF::F;
-    constexpr int P = CF::P, NH = CF::NH, W = CF::W, NT = CF::NT;
-    constexpr int TL = L * CF::TM;       // twiddle table length (= Py)
+    constexpr int P = CF::P, W = CF::W;
     float2* tw = (float2*)(lds + CF::O_TW);
     float2* scr = (float2*)(lds + CF::O_SCR);
-    float2* comb = (float2*)(lds + CF::O_COMB);
+    float2* xch = scr;                   // aliases the scratch between transforms
     if (st->done) return;
     const int tid = threadIdx.x;
-    const int u = tid / P, lg = tid % P;
+    const int gi = tid / P, lg = tid % P;
+    const int w = gi % W;
+    const int h = (gi / W) & 1;          // frequency half
+    const int c = gi / (2 * W);          // component
     const int gbase = (tid & 63) - lg;
-    const int grp = u % 2;               // 0: x and y components, 1: z
-    const int h = (u / 2) % NH;          // frequency half
-    const int w = u / (2 * NH);
-    const int kx = lb * W + w;
-    const bool packed = kx == 0;
-    for (int m = tid; m < TL; m += NT) tw[m] = a.tw[m];
+    // stored column -> kx: columns are kept in even/odd order of kx
+    const int scol = lb * W + w;
+    const int kq = a.nkx / 2;
+    const int kx = 2 * (scol % kq) + scol / kq;
+    const bool packed = scol == 0;
     const int ny = a.ny, Py = a.Py;
-    const long long cs = (long long)ny * a.nkxp;
-    const long long kcs = (long long)a.nkx_full * (Py / 2 + 1);
-    const float* K = a.K;
-    // kernel values of this lane's elements (mirror compressed along y;
-    // the xy component is odd in ky)
-    float ka0[E], ka1[E], ka2[E], kn0[E], kn1[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int pos = lg + P * i;
-        const int ky = SPLIT ? 2 * pos + h : pos;
-        const bool flip = ky > Py - ky;
-        const int iy = flip ? Py - ky : ky;
-        const long long o = (long long)kx * (Py / 2 + 1) + iy;
-        const long long oN = (long long)(a.nkx_full - 1) * (Py / 2 + 1) + iy;
-        if (grp == 0) {
-            ka0[i] = K[o];                  // xx
-            ka1[i] = K[kcs + o];            // yy
-            const float kxy = K[3 * kcs + o];
-            ka2[i] = flip ? -kxy : kxy;     // xy
-            kn0[i] = packed ? K[oN] : 0.f;
-            kn1[i] = packed ? K[kcs + oN] : 0.f;
-        } else {
-            ka0[i] = K[2 * kcs + o];        // zz
-            kn0[i] = packed ? K[2 * kcs + oN] : 0.f;
-            ka1[i] = ka2[i] = kn1[i] = 0.f;
-        }
-    }
-    // input columns
-    float2 x0[E], x1[E];
-    const float2* c0 = a.S + (grp == 0 ? 0 : 2) * cs + kx;
-    const float2* c1p = a.S + cs + kx;
+    const int cs = ny * a.nkxp;
+    const int kcs = a.nkx_full * (Py / 2 + 1);
+    // this group's column, zero beyond ny
+    float2 x[E];
+    const float2* src = a.S + c * cs + scol;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int y = lg + P * i;
-        x0[i] = mk2(0.f, 0.f);
-        x1[i] = mk2(0.f, 0.f);
-        if (y < ny) {
-            x0[i] = c0[(long long)y * a.nkxp];
-            if (grp == 0) x1[i] = c1p[(long long)y * a.nkxp];
-        }
+        x[i] = y < ny ? src[y * a.nkxp] : mk2(0.f, 0.f);
+    }
+    for (int m = tid; m < 2 * L; m += CT2) tw[m] = a.tw[m];
+    // kernel values at ky = 2 pos + h (mirror compressed along y; xy is
+    // odd in ky): diagonal kd, off-diagonal ko (x, y), Nyquist-column kn
+    float kd[E], ko[E], kn[E];
+    const int cdiag = c == 0 ? 0 : (c == 1 ? 1 : 2);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int ky = 2 * (lg + P * i) + h;
+        const bool flip = ky > Py - ky;
+        const int iy = flip ? Py - ky : ky;
+        const int o = kx * (Py / 2 + 1) + iy;
+        kd[i] = a.K[cdiag * kcs + o];
+        ko[i] = 0.f;
+        kn[i] = 0.f;
+        if (c < 2) { const float v = a.K[3 * kcs + o]; ko[i] = flip ? -v : v; }
+        if (packed) kn[i] = a.K[cdiag * kcs + (a.nkx_full - 1) * (Py / 2 + 1) + iy];
     }
     __syncthreads();   // twiddle table
-    if (SPLIT && h == 1) {
+    if (h == 1) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const int y = lg + P * i;
-            const float2 t = tw[y];
-            x0[i] = cmul(x0[i], t);
-            x1[i] = cmul(x1[i], t);
-        }
+        for (int i = 0; i < E; ++i) x[i] = cmul(x[i], tw[lg + P * i]);
     }
-    float2* sc = scr + u * CF::SC;
-    F::template run<false>(x0, sc, tw, lg);
-    if (grp == 0) F::template run<false>(x1, sc, tw, lg);
-
-    if (!packed) {
-        if (grp == 0) {
+    F::template run<false>(x, scr + gi * CF::SC, tw, lg);
+    __syncthreads();   // scratch free
+    // x and y spectra of every (half, column) to LDS
+    if (c < 2) {
+        float2* xo = xch + ((c * 2 + h) * W + w) * L;
 #pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const float2 Mx = x0[i], My = x1[i];
-                x0[i] = mk2(ka0[i] * Mx.x + ka2[i] * My.x, ka0[i] * Mx.y + ka2[i] * My.y);
-                x1[i] = mk2(ka2[i] * Mx.x + ka1[i] * My.x, ka2[i] * Mx.y + ka1[i] * My.y);
-            }
+        for (int i = 0; i < E; ++i) xo[lg + P * i] = x[i];
+    }
+    __syncthreads();
+    float2 q[E];
+    if (c < 2 && !packed) {
+        const float2* xp = xch + (((1 - c) * 2 + h) * W + w) * L;
+#pragma unroll
+        for (int i = 0; i < E; ++i) q[i] = xp[lg + P * i];
+    }
+    __syncthreads();   // exchange read, scratch reused below
+    if (!packed) {
+        // H_x = Kxx M_x + Kxy M_y, H_y = Kxy M_x + Kyy M_y, H_z = Kzz M_z
+        if (c < 2) {
+#pragma unroll
+            for (int i = 0; i < E; ++i)
+                x[i] = mk2(kd[i] * x[i].x + ko[i] * q[i].x, kd[i] * x[i].y + ko[i] * q[i].y);
         } else {
 #pragma unroll
-            for (int i = 0; i < E; ++i) x0[i] = mk2(ka0[i] * x0[i].x, ka0[i] * x0[i].y);
+            for (int i = 0; i < E; ++i) x[i] = mk2(kd[i] * x[i].x, kd[i] * x[i].y);
         }
     } else {
         // column 0 carries (kx = 0) + i (kx = Px/2): separate with the
         // Hermitian symmetry in ky, apply each column's (diagonal) kernel,
-        // pack again.  The partner of ky is -ky: in the odd half of a split
-        // axis it is position L-1-pos, otherwise (L-pos) mod L.
-        float2 p0[E], p1[E];
+        // pack again.  The partner of ky is -ky: position L-1-pos in the odd
+        // half, (L-pos) mod L in the even half.
+        float2 pz[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i)
+            pz[i] = h ? partner_odd<E, P>(x, i, lg, gbase) : partner_mirror<E, P>(x, i, lg, gbase);
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            if (SPLIT && h == 1) {
-                p0[i] = partner_odd<E, P>(x0, i, lg, gbase);
-                p1[i] = partner_odd<E, P>(x1, i, lg, gbase);
-            } else {
-                p0[i] = partner_mirror<E, P>(x0, i, lg, gbase);
-                p1[i] = partner_mirror<E, P>(x1, i, lg, gbase);
-            }
+            const float2 z = x[i], zp = pz[i];
+            float2 A = mk2(0.5f * (z.x + zp.x), 0.5f * (z.y - zp.y));
+            float2 B = mk2(0.5f * (z.y + zp.y), -0.5f * (z.x - zp.x));
+            A = mk2(kd[i] * A.x, kd[i] * A.y);
+            B = mk2(kn[i] * B.x, kn[i] * B.y);
+            x[i] = mk2(A.x - B.y, A.y + B.x);
         }
+    }
+    F::template run<true>(x, scr + gi * CF::SC, tw, lg);
+    __syncthreads();   // scratch free
+    float2* comb = xch + (c * W + w) * L;
+    if (h == 1) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            // A = (Z + conj Zp)/2 (kx = 0), B = (Z - conj Zp)/(2i) (kx = Px/2)
-            const float2 z0 = x0[i], q0 = p0[i];
-            float2 A = mk2(0.5f * (z0.x + q0.x), 0.5f * (z0.y - q0.y));
-            float2 B = mk2(0.5f * (z0.y + q0.y), -0.5f * (z0.x - q0.x));
-            A = mk2(ka0[i] * A.x, ka0[i] * A.y);
-            B = mk2(kn0[i] * B.x, kn0[i] * B.y);
-            x0[i] = mk2(A.x - B.y, A.y + B.x);
-            if (grp == 0) {
-                const float2 z1 = x1[i], q1 = p1[i];
-                float2 C = mk2(0.5f * (z1.x + q1.x), 0.5f * (z1.y - q1.y));
-                float2 D = mk2(0.5f * (z1.y + q1.y), -0.5f * (z1.x - q1.x));
-                C = mk2(ka1[i] * C.x, ka1[i] * C.y);
-                D = mk2(kn1[i] * D.x, kn1[i] * D.y);
-                x1[i] = mk2(C.x - D.y, C.y + D.x);
-            }
+            const int y = lg + P * i;
+            if (y < ny) comb[y] = cmul(x[i], cconj(tw[y]));
         }
     }
-    F::template run<true>(x0, sc, tw, lg);
-    if (grp == 0) F::template run<true>(x1, sc, tw, lg);
-
-    const int cA = grp == 0 ? 0 : 2;
-    if (SPLIT) {
-        if (h == 1) {
-#pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const int y = lg + P * i;
-                if (y < ny) {
-                    const float2 t = cconj(tw[y]);
-                    comb[(w * 3 + cA) * L + y] = cmul(x0[i], t);
-                    if (grp == 0) comb[(w * 3 + 1) * L + y] = cmul(x1[i], t);
-                }
-            }
-        }
-        __syncthreads();
-        if (h == 1) return;
-    }
-    float2* o0 = a.S + cA * cs + kx;
-    float2* o1 = a.S + cs + kx;
+    __syncthreads();
+    if (h == 1) return;
+    float2* dst = a.S + c * cs + scol;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int y = lg + P * i;
         if (y < ny) {
-            float2 v0 = x0[i], v1 = x1[i];
-            if (SPLIT) {
-                const float2 c0v = comb[(w * 3 + cA) * L + y];
-                v0 = mk2(v0.x + c0v.x, v0.y + c0v.y);
-                if (grp == 0) { const float2 c1v = comb[(w * 3 + 1) * L + y]; v1 = mk2(v1.x + c1v.x, v1.y + c1v.y); }
-            }
-            o0[(long long)y * a.nkxp] = v0;
-            if (grp == 0) o1[(long long)y * a.nkxp] = v1;
+            const float2 v = comb[y];
+            dst[y * a.nkxp] = mk2(x[i].x + v.x, x[i].y + v.y);
         }
     }
 }
 
-template <int L, int E, bool SPLIT>
-__global__ __launch_bounds__(512) void col2d_fast(Col2dArgs a, DevState* __restrict__ st) {
+template <int L, int E>
+__global__ __launch_bounds__(CT2) void col2d_fast(Col2dArgs a, DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
-    col2d_body<L, E, SPLIT>(a, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
+    col2d_body<L, E>(a, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
 }
 
 // ---------------------------------------------------------------------------
-// grouped launches: one launch runs a pass for many films of different
-// sizes; block b works on film map[b].x, local block map[b].y
+// compiled variants: (length, elements per lane, variant index).  Rows are
+// keyed by the padded x length Px, columns by the half length L = Py/2; the
+// variant in use for a length comes from a process-wide table that
+// llg_autotune fills (variant 0 until then).
 // ---------------------------------------------------------------------------
-#define ROW_GROUP_SIZES(X) X(64, 8) X(128, 8) X(192, 12) X(256, 8) X(384, 12) X(512, 8) X(768, 12) X(1024, 16)
-#define COL_GROUP_SIZES(X) X(32, 8) X(64, 8) X(96, 12) X(128, 8) X(192, 12) X(256, 8) X(384, 12) X(512, 8)
+#define ROW_VARIANTS(X) X(64, 4, 0) X(64, 8, 1) X(128, 4, 0) X(128, 8, 1) X(192, 12, 0) X(192, 24, 1) \
+    X(256, 4, 0) X(256, 8, 1) X(384, 12, 0) X(384, 24, 1) X(512, 4, 0) X(512, 8, 1) X(768, 12, 0)    \
+    X(768, 24, 1) X(1024, 8, 0) X(1024, 16, 1)
+#define COL_VARIANTS(X) X(32, 4, 0) X(32, 8, 1) X(64, 4, 0) X(64, 8, 1) X(96, 12, 0) X(96, 6, 1) \
+    X(128, 4, 0) X(128, 8, 1) X(192, 12, 0) X(192, 6, 1) X(256, 4, 0) X(256, 8, 1) X(384, 12, 0) \
+    X(384, 6, 1) X(512, 8, 0) X(512, 16, 1)
 
+// grouped launches: one launch runs a pass for all films of one length
+// class (same compiled variant); block b works on film map[b].x, local
+// block map[b].y of that film
+template <int PX, int E2>
 __global__ __launch_bounds__(FRT) void row_fwd_group(const FilmRow* __restrict__ films,
                                                      const int2* __restrict__ map) {
     extern __shared__ char dyn_lds[];
     const int2 m = map[blockIdx.x];
     const FilmRow& f = films[m.x];
-    switch (f.g.Px) {
-#define CASE(PX, E) case PX: row_fwd_body<PX, E>(f.g, f.twx, f.S, f.fa, f.st, m.y, dyn_lds); break;
-        ROW_GROUP_SIZES(CASE)
-#undef CASE
-        default: break;
-    }
+    row_fwd_body<PX, E2, false>(f.g, f.twx, f.S, f.fa, f.st, m.y, dyn_lds);
 }
 
+template <int PX, int E2>
 __global__ __launch_bounds__(FRT) void row_inv_group(const FilmRow* __restrict__ films,
                                                      const int2* __restrict__ map) {
     extern __shared__ char dyn_lds[];
     const int2 m = map[blockIdx.x];
     const FilmRow& f = films[m.x];
-    switch (f.g.Px) {
-#define CASE(PX, E) case PX: row_inv_body<PX, E, false>(f.g, f.p, f.twx, f.S, f.sa, f.st, m.y, dyn_lds); break;
-        ROW_GROUP_SIZES(CASE)
-#undef CASE
-        default: break;
-    }
+    row_inv_body<PX, E2, false>(f.g, f.p, f.twx, f.S, f.sa, f.st, m.y, dyn_lds);
 }
 
-__global__ __launch_bounds__(512) void col_group(const FilmCol* __restrict__ films, const int2* __restrict__ map) {
+template <int L, int E>
+__global__ __launch_bounds__(CT2) void col_group(const FilmCol* __restrict__ films, const int2* __restrict__ map) {
     extern __shared__ char dyn_lds[];
     const int2 m = map[blockIdx.x];
     const FilmCol& f = films[m.x];
-    switch (f.a.Py / 2) {
-#define CASE(LL, E) case LL: col2d_body<LL, E, true>(f.a, f.st, m.y, dyn_lds); break;
-        COL_GROUP_SIZES(CASE)
-#undef CASE
-        default: break;
-    }
+    col2d_body<L, E>(f.a, f.st, m.y, dyn_lds);
 }
 
 // kernels whose dynamic LDS may exceed 64 KB need the limit raised once
@@ -660,25 +640,37 @@ static hipError_t allow_lds(const void* kernel, int bytes) {
     return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+// the variant table: lengths up to 2048 in steps of 32
+std::atomic<int> g_row_var[65], g_col_var[65];
+int slot(int len) { return (len % 32 == 0 && len >= 32 && len <= 2048) ? len / 32 : 0; }
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-#define ROW_SIZES(X) X(64, 8) X(128, 8) X(192, 12) X(256, 8) X(384, 12) X(512, 8) X(768, 12) X(1024, 16)
-#define COL_SIZES(X) X(32, 8) X(64, 8) X(96, 12) X(128, 8) X(192, 12) X(256, 8) X(384, 12) X(512, 8)
+int fast2d_row_variant(int Px) { return g_row_var[slot(Px)].load(); }
+int fast2d_col_variant(int L) { return g_col_var[slot(L)].load(); }
+bool fast2d_set_variants(int Px, int rv, int L, int cv) {
+    if (!fast2d_row_ok(Px, rv) || !fast2d_col_ok(L, 1, cv)) return false;
+    g_row_var[slot(Px)].store(rv);
+    g_col_var[slot(L)].store(cv);
+    return true;
+}
 
-bool fast2d_row_ok(int Px) {
-#define CASE(PX, E) if (Px == PX) return true;
-    ROW_SIZES(CASE)
+bool fast2d_row_ok(int Px, int var) {
+    if (var < 0) var = fast2d_row_variant(Px);
+#define CASE(PX, E, V) if (Px == PX && var == V) return true;
+    ROW_VARIANTS(CASE)
 #undef CASE
     return false;
 }
 
-bool fast2d_col_ok(int L, int split) {
+bool fast2d_col_ok(int L, int split, int var) {
     if (!split) return false;
-#define CASE(LL, E) if (L == LL) return true;
-    COL_SIZES(CASE)
+    if (var < 0) var = fast2d_col_variant(L);
+#define CASE(LL, E, V) if (L == LL && var == V) return true;
+    COL_VARIANTS(CASE)
 #undef CASE
     return false;
 }
@@ -686,17 +678,25 @@ bool fast2d_col_ok(int L, int split) {
 hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, const FwdArgs& fa,
                                DevState* st, hipStream_t s) {
     if (g.nx > g.Px || g.nkxp < g.Px / 2) return hipErrorInvalidValue;
-#define CASE(PX, E)                                                                       \
-    if (g.Px == PX) {                                                                     \
-        constexpr int rows = 2 * RowFast<PX, E>::RP;                                      \
-        constexpr int lds = RowFast<PX, E>::fwd_bytes();                                  \
-        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E>), lds); \
+    const int var = fast2d_row_variant(g.Px);
+#define CASE(PX, E, V)                                                                    \
+    if (g.Px == PX && var == V) {                                                         \
+        constexpr int rows = 2 * RowSplit<PX, E>::RP;                                     \
+        const dim3 grid((g.nrows + rows - 1) / rows);                                     \
+        constexpr int lds_p = RowSplit<PX, E>::template fwd_bytes<true>();                \
+        constexpr int lds_o = RowSplit<PX, E>::template fwd_bytes<false>();               \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, true>), lds_p); \
+        if (e_ == hipSuccess) e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, false>), lds_o); \
         if (e_ != hipSuccess) return e_;                                                  \
-        hipLaunchKernelGGL((row_fwd_fast<PX, E>), dim3((g.nrows + rows - 1) / rows), dim3(FRT), \
-                           lds, s, g, twx, S, fa, st);                                    \
+        if (g.nx == PX)                                                                   \
+            hipLaunchKernelGGL((row_fwd_fast<PX, E, true>), grid, dim3(FRT), lds_p, s, g, twx, S, fa, st); \
+        else if (2 * g.nx <= PX)                                                          \
+            hipLaunchKernelGGL((row_fwd_fast<PX, E, false>), grid, dim3(FRT), lds_o, s, g, twx, S, fa, st); \
+        else                                                                              \
+            return hipErrorInvalidValue;                                                  \
         return hipGetLastError();                                                         \
     }
-    ROW_SIZES(CASE)
+    ROW_VARIANTS(CASE)
 #undef CASE
     return hipErrorInvalidValue;
 }
@@ -705,12 +705,13 @@ hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, 
                                const StageArgs& sa, DevState* st, hipStream_t s) {
     if (g.nx > g.Px || g.nkxp < g.Px / 2 || sa.nk > kMaxK) return hipErrorInvalidValue;
     if ((sa.mode == ROW_STAGE || sa.mode == ROW_ERROR) && sa.nk < 1) return hipErrorInvalidValue;
-#define CASE(PX, E)                                                                       \
-    if (g.Px == PX) {                                                                     \
-        constexpr int rows = 2 * RowFast<PX, E>::RP;                                      \
+    const int var = fast2d_row_variant(g.Px);
+#define CASE(PX, E, V)                                                                    \
+    if (g.Px == PX && var == V) {                                                         \
+        constexpr int rows = 2 * RowSplit<PX, E>::RP;                                     \
         const dim3 grid((g.nrows + rows - 1) / rows);                                     \
-        constexpr int lds_p = RowFast<PX, E>::template inv_bytes<true>();                 \
-        constexpr int lds_o = RowFast<PX, E>::template inv_bytes<false>();                \
+        constexpr int lds_p = RowSplit<PX, E>::template inv_bytes<true>();                \
+        constexpr int lds_o = RowSplit<PX, E>::template inv_bytes<false>();               \
         hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, true>), lds_p); \
         if (e_ == hipSuccess) e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, false>), lds_o); \
         if (e_ != hipSuccess) return e_;                                                  \
@@ -724,77 +725,86 @@ hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, 
             return hipErrorInvalidValue;                                                  \
         return hipGetLastError();                                                         \
     }
-    ROW_SIZES(CASE)
+    ROW_VARIANTS(CASE)
 #undef CASE
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_col2d_fast(const Col2dArgs& a, DevState* st, hipStream_t s) {
-    if (a.Py % 2 || a.ny > a.Py / 2 || a.nkx_full != a.nkx + 1) return hipErrorInvalidValue;
+    if (a.Py % 2 || a.ny > a.Py / 2 || a.nkx_full != a.nkx + 1 || a.nkx % 2) return hipErrorInvalidValue;
     const int L = a.Py / 2;
-#define CASE(LL, E)                                                                       \
-    if (L == LL) {                                                                        \
-        using CF = ColFast<LL, E, true>;                                                  \
+    const int var = fast2d_col_variant(L);
+#define CASE(LL, E, V)                                                                    \
+    if (L == LL && var == V) {                                                            \
+        using CF = ColSplit<LL, E>;                                                       \
         if (a.nkx % CF::W) return hipErrorInvalidValue;                                   \
-        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&col2d_fast<LL, E, true>), CF::bytes());                  \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&col2d_fast<LL, E>), CF::bytes()); \
         if (e_ != hipSuccess) return e_;                                                  \
-        hipLaunchKernelGGL((col2d_fast<LL, E, true>), dim3(a.nkx / CF::W), dim3(CF::NT), CF::bytes(), s, a, st); \
+        hipLaunchKernelGGL((col2d_fast<LL, E>), dim3(a.nkx / CF::W), dim3(CT2), CF::bytes(), s, a, st); \
         return hipGetLastError();                                                         \
     }
-    COL_SIZES(CASE)
+    COL_VARIANTS(CASE)
 #undef CASE
     return hipErrorInvalidValue;
 }
 
 // ---- grouped launchers ------------------------------------------------------------
-int fast2d_row_rows_per_block(int Px) {
-#define CASE(PX, E) if (Px == PX) return 2 * RowFast<PX, E>::RP;
-    ROW_GROUP_SIZES(CASE)
+int fast2d_row_rows_per_block(int Px, int var) {
+#define CASE(PX, E, V) if (Px == PX && var == V) return 2 * RowSplit<PX, E>::RP;
+    ROW_VARIANTS(CASE)
 #undef CASE
     return 0;
 }
-int fast2d_row_fwd_lds(int Px) {
-#define CASE(PX, E) if (Px == PX) return RowFast<PX, E>::fwd_bytes();
-    ROW_GROUP_SIZES(CASE)
-#undef CASE
-    return 0;
-}
-int fast2d_row_inv_lds(int Px) {
-#define CASE(PX, E) if (Px == PX) return RowFast<PX, E>::template inv_bytes<false>();
-    ROW_GROUP_SIZES(CASE)
-#undef CASE
-    return 0;
-}
-int fast2d_col_width(int L) {
-#define CASE(LL, E) if (L == LL) return ColFast<LL, E, true>::W;
-    COL_GROUP_SIZES(CASE)
-#undef CASE
-    return 0;
-}
-int fast2d_col_lds(int L) {
-#define CASE(LL, E) if (L == LL) return ColFast<LL, E, true>::bytes();
-    COL_GROUP_SIZES(CASE)
+int fast2d_col_width(int L, int var) {
+    if (var < 0) var = fast2d_col_variant(L);
+#define CASE(LL, E, V) if (L == LL && var == V) return ColSplit<LL, E>::W;
+    COL_VARIANTS(CASE)
 #undef CASE
     return 0;
 }
 
-hipError_t launch_row_fwd_group(const FilmRow* films, const int2* map, int nblocks, int lds, hipStream_t s) {
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&row_fwd_group), lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(row_fwd_group, dim3(nblocks), dim3(FRT), lds, s, films, map);
-    return hipGetLastError();
+hipError_t launch_row_fwd_group(int Px, int var, const FilmRow* films, const int2* map, int nblocks,
+                                hipStream_t s) {
+#define CASE(PX, E, V)                                                                    \
+    if (Px == PX && var == V) {                                                           \
+        constexpr int lds = RowSplit<PX, E>::template fwd_bytes<false>();                 \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_group<PX, E>), lds); \
+        if (e_ != hipSuccess) return e_;                                                  \
+        hipLaunchKernelGGL((row_fwd_group<PX, E>), dim3(nblocks), dim3(FRT), lds, s, films, map); \
+        return hipGetLastError();                                                         \
+    }
+    ROW_VARIANTS(CASE)
+#undef CASE
+    return hipErrorInvalidValue;
 }
-hipError_t launch_row_inv_group(const FilmRow* films, const int2* map, int nblocks, int lds, hipStream_t s) {
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&row_inv_group), lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(row_inv_group, dim3(nblocks), dim3(FRT), lds, s, films, map);
-    return hipGetLastError();
+
+hipError_t launch_row_inv_group(int Px, int var, const FilmRow* films, const int2* map, int nblocks,
+                                hipStream_t s) {
+#define CASE(PX, E, V)                                                                    \
+    if (Px == PX && var == V) {                                                           \
+        constexpr int lds = RowSplit<PX, E>::template inv_bytes<false>();                 \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_group<PX, E>), lds); \
+        if (e_ != hipSuccess) return e_;                                                  \
+        hipLaunchKernelGGL((row_inv_group<PX, E>), dim3(nblocks), dim3(FRT), lds, s, films, map); \
+        return hipGetLastError();                                                         \
+    }
+    ROW_VARIANTS(CASE)
+#undef CASE
+    return hipErrorInvalidValue;
 }
-hipError_t launch_col_group(const FilmCol* films, const int2* map, int nblocks, int lds, hipStream_t s) {
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&col_group), lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(col_group, dim3(nblocks), dim3(512), lds, s, films, map);
-    return hipGetLastError();
+
+hipError_t launch_col_group(int L, int var, const FilmCol* films, const int2* map, int nblocks, hipStream_t s) {
+#define CASE(LL, E, V)                                                                    \
+    if (L == LL && var == V) {                                                            \
+        constexpr int lds = ColSplit<LL, E>::bytes();                                     \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&col_group<LL, E>), lds);  \
+        if (e_ != hipSuccess) return e_;                                                  \
+        hipLaunchKernelGGL((col_group<LL, E>), dim3(nblocks), dim3(CT2), lds, s, films, map); \
+        return hipGetLastError();                                                         \
+    }
+    COL_VARIANTS(CASE)
+#undef CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace llg

@@ -62,6 +62,72 @@ inline Tableau tab_dp45() {
     return t;
 }
 
+// Kutta's third-order method
+inline Tableau tab_rk3() {
+    Tableau t = {};
+    t.S = 3;
+    t.A[1][0] = 0.5; t.A[2][0] = -1.0; t.A[2][1] = 2.0;
+    t.b[0] = 1.0 / 6.0; t.b[1] = 2.0 / 3.0; t.b[2] = 1.0 / 6.0;
+    return t;
+}
+// Heun-Euler 2(1): Heun's method, Euler's method as the embedded estimate
+inline Tableau tab_rk12() {
+    Tableau t = tab_heun();
+    t.bhat[0] = 1.0; t.bhat[1] = 0.0;
+    return t;
+}
+// Bogacki & Shampine (1989) 3(2); row 3 equals b (first same as last)
+inline Tableau tab_rk23() {
+    Tableau t = {};
+    t.S = 4;
+    t.A[1][0] = 0.5;
+    t.A[2][1] = 0.75;
+    t.A[3][0] = 2.0 / 9.0; t.A[3][1] = 1.0 / 3.0; t.A[3][2] = 4.0 / 9.0;
+    for (int j = 0; j < 3; ++j) t.b[j] = t.A[3][j];
+    t.bhat[0] = 7.0 / 24.0; t.bhat[1] = 0.25; t.bhat[2] = 1.0 / 3.0; t.bhat[3] = 0.125;
+    return t;
+}
+// Cash & Karp (1990) 5(4)
+inline Tableau tab_rkck() {
+    Tableau t = {};
+    t.S = 6;
+    t.A[1][0] = 0.2;
+    t.A[2][0] = 3.0 / 40.0; t.A[2][1] = 9.0 / 40.0;
+    t.A[3][0] = 0.3; t.A[3][1] = -0.9; t.A[3][2] = 1.2;
+    t.A[4][0] = -11.0 / 54.0; t.A[4][1] = 2.5; t.A[4][2] = -70.0 / 27.0; t.A[4][3] = 35.0 / 27.0;
+    t.A[5][0] = 1631.0 / 55296.0; t.A[5][1] = 175.0 / 512.0; t.A[5][2] = 575.0 / 13824.0;
+    t.A[5][3] = 44275.0 / 110592.0; t.A[5][4] = 253.0 / 4096.0;
+    t.b[0] = 37.0 / 378.0; t.b[2] = 250.0 / 621.0; t.b[3] = 125.0 / 594.0; t.b[5] = 512.0 / 1771.0;
+    t.bhat[0] = 2825.0 / 27648.0; t.bhat[2] = 18575.0 / 48384.0; t.bhat[3] = 13525.0 / 55296.0;
+    t.bhat[4] = 277.0 / 14336.0; t.bhat[5] = 0.25;
+    return t;
+}
+// an embedded pair: its tableau, the order q of its error estimate, and
+// whether its last stage is evaluated at the new state (first same as last)
+struct Adaptive {
+    Tableau t;
+    int q;
+    bool fsal;
+};
+inline bool adaptive_of(int method, Adaptive* out) {
+    switch (method) {
+        case LLG_RKDP45: *out = {tab_dp45(), 4, true}; return true;
+        case LLG_RK23: *out = {tab_rk23(), 2, true}; return true;
+        case LLG_RKCK: *out = {tab_rkck(), 4, false}; return true;
+        case LLG_RK12: *out = {tab_rk12(), 1, false}; return true;
+        default: return false;
+    }
+}
+inline bool fixed_of(int method, Tableau* out) {
+    switch (method) {
+        case LLG_EULER: *out = tab_euler(); return true;
+        case LLG_HEUN: *out = tab_heun(); return true;
+        case LLG_RK3: *out = tab_rk3(); return true;
+        case LLG_RK4: *out = tab_rk4(); return true;
+        default: return false;
+    }
+}
+
 inline bool good_len(int L) {
     if (L < 1) return false;
     for (int f : {2, 3, 5, 7})

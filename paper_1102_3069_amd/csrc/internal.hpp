@@ -49,9 +49,10 @@ struct DevState {
     int health;           // bit 0: NaN/Inf seen; bit 1: step below dt_min
     uint32_t err_bits;    // max error of the current attempt (float bits)
     int clipped;          // the pending attempt was shortened to land on t_end
-    int pad0;
+    int ev_attempt;       // adaptive: H_eff evaluations per attempt
     double t, dt, dt_next, t_end, tol, dt_min, gms;
     double last_err;
+    double ctrl_exp;      // adaptive: step-size exponent 1/(q+1)
     float dtau;           // dt * gamma0 * Ms
     float pad1;
     long long step;       // accepted steps (thermal draw counter)
@@ -88,7 +89,9 @@ struct StageArgs {
     int mode;
     int nk;                  // number of k's in the combination (incl. the current one)
     float a[kMaxK];          // combination weights of k_1..k_nk (times dtau)
-    float e[kMaxK];          // error weights (ROW_ERROR)
+    float e[kMaxK];          // error weights (ROW_ERROR, or ROW_STAGE with with_err)
+    int with_err;            // ROW_STAGE: also the embedded error estimate
+    int skip_fwd;            // ROW_STAGE: no forward transform of the new state
     BufRef m_in;             // stage input m_s
     BufRef m0;               // state at the start of the step
     BufRef m_out;            // next stage input / new state
@@ -149,8 +152,13 @@ hipError_t launch_fft_test(float2* data, int n, int batch, const FftPlan& pl, co
                            int inverse_only, hipStream_t s);
 
 // ---- 2D fast path (fast2d.hip) ---------------------------------------------------
-bool fast2d_row_ok(int Px);
-bool fast2d_col_ok(int L, int split);
+// compiled variants per length (elements per lane); var < 0 selects the
+// variant of the process-wide table (llg_autotune), 0 until tuned
+bool fast2d_row_ok(int Px, int var = -1);
+bool fast2d_col_ok(int L, int split, int var = -1);
+int fast2d_row_variant(int Px);
+int fast2d_col_variant(int L);
+bool fast2d_set_variants(int Px, int row_var, int L, int col_var);
 hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, const FwdArgs& fa,
                                DevState* st, hipStream_t s);
 hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, float2* S,
@@ -166,19 +174,20 @@ struct FilmRow {
     DevState* st;
     StageArgs sa;     // row_inv
     FwdArgs fa;       // row_fwd
+    int var;          // compiled variant of the row length
 };
 struct FilmCol {
     Col2dArgs a;
     DevState* st;
+    int var;          // compiled variant of the column length
 };
-int fast2d_row_rows_per_block(int Px);
-int fast2d_row_fwd_lds(int Px);
-int fast2d_row_inv_lds(int Px);
-int fast2d_col_width(int L);
-int fast2d_col_lds(int L);
-hipError_t launch_row_fwd_group(const FilmRow* films, const int2* map, int nblocks, int lds, hipStream_t s);
-hipError_t launch_row_inv_group(const FilmRow* films, const int2* map, int nblocks, int lds, hipStream_t s);
-hipError_t launch_col_group(const FilmCol* films, const int2* map, int nblocks, int lds, hipStream_t s);
+int fast2d_row_rows_per_block(int Px, int var);
+int fast2d_col_width(int L, int var = -1);
+hipError_t launch_row_fwd_group(int Px, int var, const FilmRow* films, const int2* map, int nblocks,
+                                hipStream_t s);
+hipError_t launch_row_inv_group(int Px, int var, const FilmRow* films, const int2* map, int nblocks,
+                                hipStream_t s);
+hipError_t launch_col_group(int L, int var, const FilmCol* films, const int2* map, int nblocks, hipStream_t s);
 hipError_t launch_ctrl_dp45_group(DevState* states, int nfilms, hipStream_t s);
 hipError_t launch_ctrl_fixed_group(DevState* states, int nfilms, int evals, hipStream_t s);
 

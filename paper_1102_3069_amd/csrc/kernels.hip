@@ -232,7 +232,8 @@ __global__ __launch_bounds__(RT) void row_inv_kernel(Grid g, Phys p, FftPlan px,
                 ax *= inv; ay *= inv; az *= inv;
                 mo[i] = ax; mo[cs + i] = ay; mo[2 * cs + i] = az;
                 nm[q][0] = ax; nm[q][1] = ay; nm[q][2] = az;
-            } else if (sa.mode == ROW_ERROR) {
+            }
+            if (sa.mode == ROW_ERROR || (sa.mode == ROW_STAGE && sa.with_err)) {
                 float ex = 0.f, ey = 0.f, ez = 0.f;
                 for (int j = 0; j + 1 < sa.nk; ++j) {
                     const float c = sa.e[j];
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(RT) void row_inv_kernel(Grid g, Phys p, FftPlan px,
         }
     }
     if (bad) atomicOr(&st->health, 1);
-    if (sa.mode == ROW_ERROR) {
+    if (sa.mode == ROW_ERROR || (sa.mode == ROW_STAGE && sa.with_err)) {
         for (int off = 32; off > 0; off >>= 1) errmax = fmaxf(errmax, __shfl_xor(errmax, off));
         if ((tid & 63) == 0) wmax[tid >> 6] = errmax;
         __syncthreads();
@@ -258,9 +259,9 @@ __global__ __launch_bounds__(RT) void row_inv_kernel(Grid g, Phys p, FftPlan px,
             for (int w = 1; w < RT / 64; ++w) m = fmaxf(m, wmax[w]);
             atomicMax(&st->err_bits, __float_as_uint(m));
         }
-        return;
+        if (sa.mode == ROW_ERROR) return;
     }
-    if (sa.mode == ROW_STAGE && p.demag_on) {
+    if (sa.mode == ROW_STAGE && p.demag_on && !sa.skip_fwd) {
         __syncthreads();   // every thread is done reading the inverse transform
         row_forward_store<MAXE>(g, px, twx, S, lds, nm, r0, has1);
     }
@@ -447,7 +448,7 @@ __device__ void dp45_control(DevState* st) {
     st->err_bits = 0u;
     const double err = (double)errf;
     const double h = st->dt;
-    st->nevals += 6;
+    st->nevals += st->ev_attempt;
     st->last_err = err;
     const bool ok = (st->health == 0) && (err <= st->tol);
     const long long a = st->nattempt++;
@@ -467,7 +468,7 @@ __device__ void dp45_control(DevState* st) {
     } else {
         st->nrej += 1;
     }
-    double f = (err == 0.0) ? 5.0 : 0.9 * pow(st->tol / err, 0.2);
+    double f = (err == 0.0) ? 5.0 : 0.9 * pow(st->tol / err, st->ctrl_exp);
     f = fmin(5.0, fmax(0.2, f));
     const double dn = h * f;
     st->dt_next = dn;

@@ -330,14 +330,6 @@ llg_status eval_into(llg_solver* s, float* out, const Phys& p) {
     return LLG_OK;
 }
 
-Tableau tableau_of(llg_method m) {
-    switch (m) {
-        case LLG_EULER: return tab_euler();
-        case LLG_HEUN: return tab_heun();
-        case LLG_RK4: return tab_rk4();
-        default: return tab_dp45();
-    }
-}
 
 // one fixed step of tableau t: S x (spectral + fused row pass) + controller
 llg_status enqueue_fixed_step(llg_solver* s, const Tableau& t, const Phys& p) {
@@ -366,15 +358,16 @@ llg_status enqueue_fixed_step(llg_solver* s, const Tableau& t, const Phys& p) {
     return LLG_OK;
 }
 
-// one adaptive Dormand-Prince attempt (FSAL: k1 is the previous k7)
-llg_status enqueue_dp45_attempt(llg_solver* s, const Phys& p) {
-    const Tableau t = tab_dp45();
+// one attempt of an embedded pair whose last stage is evaluated at the new
+// state (first same as last: k1 is the previous attempt's last k).  With S
+// stages: k1 = kfs[cur], k2..k_{S-1} = kb[1..S-2], k_S -> kfs[cur^1].
+llg_status enqueue_fsal_attempt(llg_solver* s, const Tableau& t, const Phys& p) {
+    const int S = t.S;
     llg_status rc;
-    // k_j buffers: k1 = kfs[cur], k2..k6 = kb[1..5], k7 -> kfs[cur^1]
     BufRef kref[7];
     kref[0] = bref_cur(s->kfs[0], s->kfs[1], 1);
-    for (int j = 1; j <= 5; ++j) kref[j] = bref(s->kb[j]);
-    kref[6] = bref_cur(s->kfs[0], s->kfs[1], 2);
+    for (int j = 1; j + 1 < S; ++j) kref[j] = bref(s->kb[j]);
+    kref[S - 1] = bref_cur(s->kfs[0], s->kfs[1], 2);
     // stage 2 input: m_2 = normalize(m0 + dtau a21 k1)
     FwdArgs fa = {};
     fa.combine = 1;
@@ -384,22 +377,51 @@ llg_status enqueue_dp45_attempt(llg_solver* s, const Phys& p) {
     fa.m_in = fa.m0;
     fa.m_out = bref(s->ms[0]);
     HIPCHK(s, row_fwd(s, p, fa));
-    for (int st = 2; st <= 7; ++st) {
+    for (int st = 2; st <= S; ++st) {
         if (p.demag_on && (rc = launch_spectral(s)) != LLG_OK) return rc;
         StageArgs sa = {};
         sa.m0 = bref_cur(s->mbuf[0], s->mbuf[1], 1);
-        sa.m_in = st == 7 ? bref_cur(s->mbuf[0], s->mbuf[1], 2) : bref(s->ms[st % 2 == 0 ? 0 : 1]);
+        sa.m_in = st == S ? bref_cur(s->mbuf[0], s->mbuf[1], 2) : bref(s->ms[st % 2 == 0 ? 0 : 1]);
         sa.k_out = kref[st - 1];
         sa.nk = st;
         for (int j = 0; j + 1 < st; ++j) sa.kprev[j] = kref[j];
-        if (st < 7) {
+        if (st < S) {
             sa.mode = ROW_STAGE;
-            sa.m_out = st == 6 ? bref_cur(s->mbuf[0], s->mbuf[1], 2) : bref(s->ms[st % 2 == 0 ? 1 : 0]);
+            sa.m_out = st == S - 1 ? bref_cur(s->mbuf[0], s->mbuf[1], 2) : bref(s->ms[st % 2 == 0 ? 1 : 0]);
             for (int j = 0; j < st; ++j) sa.a[j] = (float)t.A[st][j];
         } else {
             sa.mode = ROW_ERROR;
             sa.m_out = bref(nullptr);
-            for (int j = 0; j < 7; ++j) sa.e[j] = (float)(t.b[j] - t.bhat[j]);
+            for (int j = 0; j < S; ++j) sa.e[j] = (float)(t.b[j] - t.bhat[j]);
+        }
+        HIPCHK(s, row_inv(s, p, sa));
+    }
+    HIPCHK(s, launch_ctrl_dp45(s->st, s->stream));
+    return LLG_OK;
+}
+
+// one attempt of an embedded pair without that property: the forward pass
+// of the state, S stages (k_j in kb[j-1]), the last one writing the
+// candidate state and the error estimate together
+llg_status enqueue_plain_attempt(llg_solver* s, const Tableau& t, const Phys& p) {
+    const int S = t.S;
+    llg_status rc;
+    if (p.demag_on && (rc = launch_fwd_plain(s, 1)) != LLG_OK) return rc;
+    for (int st = 1; st <= S; ++st) {
+        if (p.demag_on && (rc = launch_spectral(s)) != LLG_OK) return rc;
+        StageArgs sa = {};
+        sa.mode = ROW_STAGE;
+        sa.m0 = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+        sa.m_in = st == 1 ? sa.m0 : bref(s->ms[st % 2]);
+        sa.m_out = st == S ? bref_cur(s->mbuf[0], s->mbuf[1], 2) : bref(s->ms[(st + 1) % 2]);
+        sa.k_out = bref(st < S ? s->kb[st - 1] : nullptr);
+        sa.nk = st;
+        for (int j = 0; j + 1 < st; ++j) sa.kprev[j] = bref(s->kb[j]);
+        for (int j = 0; j < st; ++j) sa.a[j] = (float)(st < S ? t.A[st][j] : t.b[j]);
+        if (st == S) {
+            sa.with_err = 1;
+            sa.skip_fwd = 1;
+            for (int j = 0; j < S; ++j) sa.e[j] = (float)(t.b[j] - t.bhat[j]);
         }
         HIPCHK(s, row_inv(s, p, sa));
     }
@@ -427,7 +449,8 @@ llg_status capture(llg_solver* s, Graph& gr, llg_status (*body)(llg_solver*, con
     return LLG_OK;
 }
 
-llg_status dp45_body(llg_solver* s, const Tableau&, const Phys& p) { return enqueue_dp45_attempt(s, p); }
+llg_status fsal_body(llg_solver* s, const Tableau& t, const Phys& p) { return enqueue_fsal_attempt(s, t, p); }
+llg_status plain_body(llg_solver* s, const Tableau& t, const Phys& p) { return enqueue_plain_attempt(s, t, p); }
 
 llg_status ensure_k1(llg_solver* s, const Phys& p) {
     if (s->k1_valid) return LLG_OK;
@@ -448,8 +471,8 @@ llg_status ensure_k1(llg_solver* s, const Phys& p) {
     return LLG_OK;
 }
 
-llg_status run_adaptive(llg_solver* s, double t_end, double max_err, double dt0, long long max_attempts,
-                        llg_stats* out);
+llg_status run_adaptive(llg_solver* s, int method, double t_end, double max_err, double dt0,
+                        long long max_attempts, llg_stats* out);
 
 void fill_stats(const DevState& h, llg_stats* out) {
     out->t = h.t;
@@ -561,7 +584,7 @@ llg_status llg_set_geometry(llg_solver* s, int nx, int ny, int nz, int pbc_x, in
     // by the tests to check both implementations against the oracle)
     const char* gen = getenv("LLG_FORCE_GENERIC");
     s->fast2d = nz == 1 && fast2d_row_ok(P[0]) && fast2d_col_ok(Ly, split_y) && ny <= Ly &&
-                (P[0] / 2) % 16 == 0 && !(gen && gen[0] == '1');
+                (P[0] / 2) % fast2d_col_width(Ly) == 0 && !(gen && gen[0] == '1');
     const size_t vec = sizeof(float) * 3 * (size_t)g.ncells;
     HIPCHK(s, make_tw(P[0], &s->twx));
     HIPCHK(s, make_tw(P[1], &s->twy));
@@ -713,8 +736,8 @@ llg_status llg_eval_heff(llg_solver* s, float* h_out, llg_mem where) {
 llg_status llg_step(llg_solver* s, llg_method method, double dt, int64_t nsteps) {
     llg_status rc = enter(s);
     if (rc != LLG_OK) return rc;
-    if (method != LLG_EULER && method != LLG_HEUN && method != LLG_RK4)
-        return fail(s, LLG_E_ARG, "llg_step takes Euler, Heun or RK4");
+    Tableau tf;
+    if (!fixed_of(method, &tf)) return fail(s, LLG_E_ARG, "llg_step takes Euler, Heun, RK3 or RK4");
     if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return fail(s, LLG_E_ARG, "need dt > 0, nsteps >= 0");
     if ((rc = ready(s, true)) != LLG_OK) return rc;
     if ((rc = ensure_kernel(s)) != LLG_OK) return rc;
@@ -730,7 +753,7 @@ llg_status llg_step(llg_solver* s, llg_method method, double dt, int64_t nsteps)
     if ((rc = write_state(s, &h)) != LLG_OK) return rc;
     if (p.demag_on && !s->spec_valid)
         if ((rc = launch_fwd_plain(s, 1)) != LLG_OK) return rc;
-    const Tableau t = tableau_of(method);
+    const Tableau t = tf;
     if (!s->gfix.exec || s->gfix.method != (int)method || s->gfix.dt != dt) {
         if ((rc = capture(s, s->gfix, enqueue_fixed_step, t, p)) != LLG_OK) return rc;
         s->gfix.method = (int)method;
@@ -749,8 +772,7 @@ llg_status llg_run(llg_solver* s, llg_method method, double t_end, double max_er
                    llg_stats* out) {
     llg_status rc = enter(s);
     if (rc != LLG_OK) return rc;
-    if (method != LLG_RKDP45) return fail(s, LLG_E_ARG, "llg_run takes LLG_RKDP45");
-    return run_adaptive(s, t_end, max_err, dt0, -1, out);
+    return run_adaptive(s, (int)method, t_end, max_err, dt0, -1, out);
 }
 
 llg_status llg_run_attempts(llg_solver* s, double t_end, double max_err, double dt0, int64_t max_attempts,
@@ -758,7 +780,7 @@ llg_status llg_run_attempts(llg_solver* s, double t_end, double max_err, double 
     llg_status rc = enter(s);
     if (rc != LLG_OK) return rc;
     if (max_attempts < 1) return fail(s, LLG_E_ARG, "max_attempts must be >= 1");
-    return run_adaptive(s, t_end, max_err, dt0, max_attempts, out);
+    return run_adaptive(s, LLG_RKDP45, t_end, max_err, dt0, max_attempts, out);
 }
 
 llg_status llg_get_stats(llg_solver* s, llg_stats* out) {
@@ -852,6 +874,73 @@ llg_status llg_profile_evals(llg_solver* s, int n, double* ms_out, int n_kinds, 
     return LLG_OK;
 }
 
+llg_status llg_autotune(llg_solver* s, int iters, double* ms_out, int n_out, int* choice) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (iters < 1) return fail(s, LLG_E_ARG, "iters must be >= 1");
+    if ((rc = ready(s, true)) != LLG_OK) return rc;
+    if ((rc = ensure_kernel(s)) != LLG_OK) return rc;
+    if (!s->fast2d) return fail(s, LLG_E_UNSUPPORTED, "no compiled variants for this geometry");
+    const Phys p = make_phys(s, s->last_dt);
+    if (!p.demag_on) return fail(s, LLG_E_STATE, "tuning needs the demag term");
+    const int Px = s->g.Px, L = s->g.Py / 2;
+    const int r0 = fast2d_row_variant(Px), c0 = fast2d_col_variant(L);
+    double best = 1e300;
+    int br = r0, bc = c0;
+    hipEvent_t e0, e1;
+    HIPCHK(s, hipEventCreate(&e0));
+    HIPCHK(s, hipEventCreate(&e1));
+    for (int rv = 0; rv < 2; ++rv) {
+        for (int cv = 0; cv < 2; ++cv) {
+            const int k = rv * 2 + cv;
+            if (ms_out && k < n_out) ms_out[k] = -1.0;
+            if (!fast2d_set_variants(Px, rv, L, cv) || (Px / 2) % fast2d_col_width(L, cv)) continue;
+            // one untimed evaluation, then `iters` timed ones (H_eff of the
+            // current state, kept on the device)
+            for (int it = 0; it <= iters; ++it) {
+                if (it == 1) HIPCHK(s, hipEventRecord(e0, s->stream));
+                if ((rc = launch_fwd_plain(s, 1)) != LLG_OK) break;
+                if ((rc = launch_spectral(s)) != LLG_OK) break;
+                StageArgs sa = {};
+                sa.mode = ROW_EVAL;
+                sa.m_in = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+                sa.m0 = sa.m_in;
+                sa.m_out = bref(nullptr);
+                sa.k_out = bref(nullptr);
+                sa.h_out = s->hbuf;
+                if (row_inv(s, p, sa) != hipSuccess) { rc = LLG_E_DEVICE; break; }
+            }
+            if (rc != LLG_OK) { (void)fast2d_set_variants(Px, r0, L, c0); return fail(s, rc, "tuning launch failed"); }
+            HIPCHK(s, hipEventRecord(e1, s->stream));
+            HIPCHK(s, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(s, hipEventElapsedTime(&ms, e0, e1));
+            const double per = ms / iters;
+            if (ms_out && k < n_out) ms_out[k] = per;
+            if (per < best) { best = per; br = rv; bc = cv; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    fast2d_set_variants(Px, br, L, bc);
+    invalidate_graphs(s);
+    s->spec_valid = false;
+    if (choice) { choice[0] = br; choice[1] = bc; }
+    return LLG_OK;
+}
+
+llg_status llg_set_variants(llg_solver* s, int row_var, int col_var) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!s->fast2d) return fail(s, LLG_E_UNSUPPORTED, "no compiled variants for this geometry");
+    const int Px = s->g.Px, L = s->g.Py / 2;
+    if (!fast2d_set_variants(Px, row_var, L, col_var) || (Px / 2) % fast2d_col_width(L, col_var))
+        return fail(s, LLG_E_ARG, "no compiled variant (%d, %d) for lengths %d, %d", row_var, col_var, Px, L);
+    invalidate_graphs(s);
+    s->spec_valid = false;
+    return LLG_OK;
+}
+
 llg_status llg_kernel_bytes(llg_solver* s, double* bytes_out, int n_kinds) {
     if (!s) return LLG_E_ARG;
     if (!bytes_out || n_kinds < 5) return fail(s, LLG_E_ARG, "bad arguments");
@@ -934,9 +1023,11 @@ llg_status llg_demag_tensor(llg_solver* s, const int32_t* offsets, int64_t count
 
 namespace {
 
-llg_status run_adaptive(llg_solver* s, double t_end, double max_err, double dt0, long long max_attempts,
-                        llg_stats* out) {
+llg_status run_adaptive(llg_solver* s, int method, double t_end, double max_err, double dt0,
+                        long long max_attempts, llg_stats* out) {
     llg_status rc;
+    Adaptive ad;
+    if (!adaptive_of(method, &ad)) return fail(s, LLG_E_ARG, "method %d is not an adaptive pair", method);
     if (!(max_err > 0) || !(dt0 > 0) || !isfinite(t_end) || !isfinite(max_err) || !isfinite(dt0))
         return fail(s, LLG_E_ARG, "need max_err > 0, dt0 > 0");
     if ((rc = ready(s, true)) != LLG_OK) return rc;
@@ -949,8 +1040,14 @@ llg_status run_adaptive(llg_solver* s, double t_end, double max_err, double dt0,
         if (out) fill_stats(h, out);
         return LLG_OK;
     }
-    if ((rc = ensure_k1(s, p)) != LLG_OK) return rc;
+    if (ad.fsal) {
+        // k1 from the previous attempt is only reusable for the same pair
+        if (s->gdp.method != method) s->k1_valid = false;
+        if ((rc = ensure_k1(s, p)) != LLG_OK) return rc;
+    }
     if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    h.ev_attempt = ad.fsal ? ad.t.S - 1 : ad.t.S;
+    h.ctrl_exp = 1.0 / (ad.q + 1);
     h.t_end = t_end;
     h.tol = max_err;
     h.dt_min = kDtMin;
@@ -961,10 +1058,9 @@ llg_status run_adaptive(llg_solver* s, double t_end, double max_err, double dt0,
     if (dt0 >= rem) { h.dt = rem; h.clipped = 1; } else { h.dt = dt0; h.clipped = 0; }
     h.dtau = (float)(h.dt * h.gms);
     if ((rc = write_state(s, &h)) != LLG_OK) return rc;
-    if (!s->gdp.exec) {
-        Tableau t = tab_dp45();
-        if ((rc = capture(s, s->gdp, dp45_body, t, p)) != LLG_OK) return rc;
-        s->gdp.method = LLG_RKDP45;
+    if (!s->gdp.exec || s->gdp.method != method) {
+        if ((rc = capture(s, s->gdp, ad.fsal ? fsal_body : plain_body, ad.t, p)) != LLG_OK) return rc;
+        s->gdp.method = method;
     }
     const long long a0 = h.nattempt;
     const int chunk = 8;
@@ -988,7 +1084,7 @@ llg_status run_adaptive(llg_solver* s, double t_end, double max_err, double dt0,
     // the state buffers now hold the accepted solution; the x spectrum and
     // k1 buffers follow the last accepted attempt only
     s->spec_valid = false;
-    s->k1_valid = true;
+    s->k1_valid = ad.fsal;
     if (out) fill_stats(h, out);
     if (h.health & 2) return fail(s, LLG_E_DIVERGED, "step size fell below %g s", kDtMin);
     if (h.health) return fail(s, LLG_E_DIVERGED, "non-finite field or torque");

@@ -836,6 +836,16 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
     SCHK(s, hipMemcpyAsync(s->dB, Bf, sizeof Bf, hipMemcpyHostToDevice, s->stream));
     SCHK(s, hipMemcpyAsync(s->props, m, vec, where == LLG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            s->stream));
+    // the start state is checked and renormalised as llg_set_m does
+    {
+        hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s->stream, s->dmax, 1);
+        SCHK(s, hipGetLastError());
+        SCHK(s, llg::launch_normalize_check(s->props, ncells, reinterpret_cast<int*>(s->dmax), s->stream));
+        unsigned bad = 0;
+        SCHK(s, hipMemcpyAsync(&bad, s->dmax, sizeof bad, hipMemcpyDeviceToHost, s->stream));
+        SCHK(s, hipStreamSynchronize(s->stream));
+        if (bad) return sfail(s, LLG_E_ARG, "m is not a field of unit vectors");
+    }
     std::vector<float*> ptr(window);
     std::vector<unsigned> hd(2 * window);
     int64_t done = 0;

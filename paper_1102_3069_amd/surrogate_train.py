@@ -59,6 +59,7 @@ def train(sur, X, B, steps, batch, lr0=1e-3, seed=0, log_every=0, log=print):
         kit = torch.as_tensor(ki, device="cuda")
         m_in.copy_(X[tit, kit])
         m_t.copy_(X[tit, kit + 1])
+        torch.cuda.current_stream().synchronize()   # the library works on its own stream
         loss = sur.train_step(m_in, m_t, B[ti], lr=cosine_lr(s, steps, lr0))
         losses.append(loss)
         if log_every and (s % log_every == 0 or s == steps - 1):

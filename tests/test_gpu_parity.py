@@ -168,7 +168,7 @@ def test_macrospin_cell(lib):
 # --------------------------------------------------------------------------
 # trajectories
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("method", ["euler", "heun", "rk4"])
+@pytest.mark.parametrize("method", ["euler", "heun", "rk3", "rk4"])
 def test_fixed_step_parity_small(lib, impl, method):
     prob, m0 = workloads.small_problem(n=(32, 32, 1), alpha=0.3)
     s = make_solver(lib, prob, m0)
@@ -208,7 +208,7 @@ def test_film_32_trajectory(lib, impl, method):
     assert worst_h <= 1e-5
 
 
-def oracle_sensitivity(prob, m0, attempts, seed=0):
+def oracle_sensitivity(prob, m0, attempts, seed=0, method="rkdp45"):
     """How far the FP64 oracle itself moves when its start state is nudged
     by 3e-8 per component (FP32 rounding size) and replayed along the same
     attempts: the
@@ -216,9 +216,9 @@ def oracle_sensitivity(prob, m0, attempts, seed=0):
     meaningful where this stays well below it."""
     rng = np.random.default_rng(seed)
     a = ollg.Solver(prob, m0)
-    a.replay(attempts)
+    a.replay(attempts, method)
     b = ollg.Solver(prob, m0.astype(np.float64) + 3e-8 * rng.standard_normal(m0.shape))
-    b.replay(attempts)
+    b.replay(attempts, method)
     return maxrel(b.m, a.m)
 
 
@@ -248,6 +248,45 @@ def test_dp45_replay_parity(lib, impl, name, prob_m, t_end):
     assert e <= 1e-5
     for (dt, eg, ok), eo in zip(log, errs):
         assert eg == pytest.approx(eo, rel=2e-2, abs=1e-8)
+
+
+@pytest.mark.parametrize("method", ["rk23", "rkck", "rk12"])
+def test_embedded_pair_replay_parity(lib, impl, method):
+    """The other adaptive pairs of Sec. 2.2 on the GPU, replayed by the
+    oracle along the GPU's step sizes and acceptances: m to 1e-5 and every
+    attempt's error estimate to 2e-2."""
+    prob, m0 = workloads.small_problem(n=(24, 20, 1), alpha=0.5)
+    t_end = 5e-12
+    s = make_solver(lib, prob, m0)
+    st = s.run(t_end, 1e-5, 1e-14, method=method)
+    log = s.attempts()
+    note(method, "stats", st, "attempts", len(log))
+    assert st["done"] == 1 and st["t"] == pytest.approx(t_end, rel=1e-12)
+    assert len(log) == st["steps"] + st["rejected"]
+    attempts = [(dt, ok) for dt, _, ok in log]
+    sens = oracle_sensitivity(prob, m0, attempts, method=method)
+    o = ollg.Solver(prob, m0)
+    errs = o.replay(attempts, method)
+    e = maxrel(s.get_m(), o.m)
+    note(method, "m maxrel", e, "oracle sensitivity", sens)
+    assert sens <= 2e-6
+    assert e <= 1e-5
+    for (dt, eg, ok), eo in zip(log, errs):
+        assert eg == pytest.approx(eo, rel=2e-2, abs=1e-8)
+    # the step sizes follow the pair's controller: after each attempt the
+    # next one is dt * clamp(0.9 (tol/err)^(1/(q+1)), 0.2, 5), or the rest
+    q = ollg.ADAPTIVE[method][1]
+    t = 0.0
+    for (dt, eg, ok), (dn, _, _) in zip(log[:-1], log[1:]):
+        t = t + dt if ok else t
+        want = ollg.Solver.next_dt(dt, eg, 1e-5, q)
+        assert dn == pytest.approx(min(want, t_end - t), rel=1e-6)
+    # evaluations per attempt: S - 1 with first-same-as-last, else S (and
+    # one start-up evaluation for the former)
+    tab, _ = ollg.ADAPTIVE[method]
+    S = len(tab["b"])
+    fsal = method == "rk23"
+    assert st["evals"] == len(log) * (S - 1 if fsal else S) + (1 if fsal else 0)
 
 
 def test_dp45_film_512_scaled_reanchored(lib, impl):

@@ -1,0 +1,80 @@
+"""Compiled variants of the 2D kernels and the autotuner: every (row,
+column) variant pair gives H_eff within the FP32 bar of the FP64 oracle,
+the autotuner times all pairs and keeps one, and batched films follow the
+table bit for bit like single films."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import fields as ofields
+
+pytestmark = pytest.mark.gpu
+
+# (nx, ny): row lengths Px = 2 nx and column half lengths Py / 2 = ny that
+# have compiled variants, several tiles and both even and 3-smooth sizes
+SIZES = [(32, 32), (64, 96), (96, 64), (128, 192), (192, 128), (256, 32), (384, 96), (512, 64)]
+
+
+def maxrel(a, b):
+    a = np.asarray(a, dtype=np.float64).reshape(3, -1)
+    b = np.asarray(b, dtype=np.float64).reshape(3, -1)
+    return float(np.max(np.linalg.norm(a - b, axis=0)) / np.max(np.linalg.norm(b, axis=0)))
+
+
+@pytest.fixture
+def reset_table(lib):
+    made = []
+    yield made
+    for s in made:           # back to variant 0 for the lengths these solvers touched
+        s.set_variants(0, 0)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_every_variant_matches_oracle(lib, n, reset_table):
+    prob, m0 = workloads.small_problem((n[0], n[1], 1), seed=n[0] + n[1])
+    ref = ofields.heff(m0.astype(np.float64), prob)
+    s = lib.Solver(0)
+    s.set_problem(prob)
+    s.set_m(m0)
+    reset_table.append(s)
+    for rv in range(2):
+        for cv in range(2):
+            s.set_variants(rv, cv)
+            e = maxrel(s.eval_heff(), ref)
+            print(f"{n} variants ({rv}, {cv}): {e:.2e}", flush=True)
+            assert e <= 1e-5
+
+
+def test_autotune_times_all_pairs(lib, reset_table):
+    prob, m0, _ = workloads.film_512(512)
+    s = lib.Solver(0)
+    s.set_problem(prob)
+    s.set_m(m0)
+    reset_table.append(s)
+    ms, choice = s.autotune(10)
+    print("autotune 512x512:", ms, "->", choice, flush=True)
+    assert all(v > 0 for v in ms.values())
+    assert ms[choice] == min(ms.values())
+    ref = ofields.heff(m0.astype(np.float64), prob)
+    assert maxrel(s.eval_heff(), ref) <= 1e-5
+
+
+def test_batch_follows_the_table(lib, reset_table):
+    rng = np.random.default_rng(3)
+    films = []
+    for side in (64, 96, 128):
+        prob, _ = workloads.small_problem((side, side, 1), seed=side)
+        films.append((prob, workloads.random_unit((side, side, 1), int(rng.integers(1 << 30)))))
+    singles = []
+    for prob, m0 in films:
+        s = lib.Solver(0)
+        s.set_problem(prob)
+        s.set_m(m0)
+        s.set_variants(1, 1)
+        reset_table.append(s)
+        singles.append(s)
+    b = lib.Batch(films)
+    b.step("rk4", 1e-13, 5)
+    for i, s in enumerate(singles):
+        s.step("rk4", 1e-13, 5)
+        assert np.array_equal(b.get_m(i), s.get_m()), f"film {i}"

@@ -188,20 +188,22 @@ def test_macrospin_closed_form():
     np.testing.assert_allclose(s.m[:, 0, 0, 0], _macrospin_exact(alpha, Bz, 2e-10), atol=1e-9)
 
 
-@pytest.mark.parametrize("method,order", [("euler", 1), ("heun", 2), ("rk4", 4), ("rkdp45", 5)])
+@pytest.mark.parametrize("method,order", [("euler", 1), ("heun", 2), ("rk3", 3), ("rk4", 4), ("rkdp45", 5),
+                                          ("rk12", 2), ("rk23", 3), ("rkck", 5)])
 def test_convergence_order(method, order):
-    """PIN-12a: the global error on the macrospin problem falls as dt^p."""
+    """PIN-12a: the global error on the macrospin problem falls as dt^p
+    (embedded pairs: the order of the propagated solution)."""
     alpha, Bz, t_end = 0.2, 0.2, 1e-10
     errs = []
-    # DP45 reaches its asymptotic rate only below ~1e-10 error here
-    nsteps = (80, 160) if method == "rkdp45" else (40, 80)
+    # the fifth-order pairs reach their asymptotic rate only below ~1e-10 error here
+    nsteps = (80, 160) if order == 5 else (40, 80)
     for n in nsteps:
         prob, m0 = _macrospin(alpha, Bz)
         s = llg.Solver(prob, m0)
         dt = t_end / n
-        if method == "rkdp45":
+        if method in llg.ADAPTIVE:
             for _ in range(n):
-                s.m, _err = s.dp45_attempt(dt)
+                s.m, _err = s.attempt(dt, method)
         else:
             s.step(method, dt, n)
         errs.append(np.abs(s.m[:, 0, 0, 0] - _macrospin_exact(alpha, Bz, t_end)).max())
@@ -247,7 +249,8 @@ def _as_fractions(tab):
     return [[conv(a) for a in row] for row in tab["A"]], [conv(x) for x in tab["b"]]
 
 
-@pytest.mark.parametrize("name,p", [("euler", 1), ("heun", 2), ("rk4", 4), ("rkdp45", 5)])
+@pytest.mark.parametrize("name,p", [("euler", 1), ("heun", 2), ("rk3", 3), ("rk4", 4), ("rkdp45", 5),
+                                    ("rk12", 2), ("rk23", 3), ("rkck", 5)])
 def test_tableau_order_conditions(name, p):
     """PIN-12b: each tableau satisfies every order condition up to its
     order (a single mistyped coefficient fails one of them)."""
@@ -312,3 +315,43 @@ def test_dp45_controller_and_replay():
     assert llg.Solver.next_dt(1.0, 0.0, 1e-5) == 5.0
     assert llg.Solver.next_dt(1.0, 1.0, 1e-5) == 0.2
     assert llg.Solver.next_dt(1.0, 1e-5, 1e-5) == pytest.approx(0.9)
+
+
+@pytest.mark.parametrize("name,q,p", [("rk12", 1, 2), ("rk23", 2, 3), ("rkck", 4, 5)])
+def test_embedded_estimates_have_their_order(name, q, p):
+    """The embedded weights of each pair satisfy the order conditions up to
+    q and fail one of order q + 1 (so the error estimate is of order q + 1
+    in the step, as the controller assumes)."""
+    tab = llg.ADAPTIVE[name][0]
+    assert llg.ADAPTIVE[name][1] == q
+    A, _ = _as_fractions(tab)
+    bh = [Fraction(x).limit_denominator(10 ** 7) for x in tab["bhat"]]
+    for got, want in _order_conditions(A, bh, q):
+        assert got == want
+    assert any(g != w for g, w in _order_conditions(A, bh, q + 1))
+
+
+def test_rk23_is_first_same_as_last():
+    tab = llg.RK23
+    conv = lambda x: Fraction(x).limit_denominator(10 ** 7)
+    assert [conv(x) for x in tab["A"][3]] == [conv(x) for x in tab["b"][:3]] and tab["b"][3] == 0.0
+
+
+def test_adaptive_error_estimate_scales_with_its_order():
+    """On the macrospin the per-step error estimate of each pair falls as
+    dt^(q+1) when the step halves."""
+    alpha, Bz = 0.2, 0.2
+    for name, (tab, q) in llg.ADAPTIVE.items():
+        errs = []
+        for dt in (2e-13, 1e-13):
+            prob, m0 = _macrospin(alpha, Bz)
+            s = llg.Solver(prob, m0)
+            errs.append(s.attempt(dt, name)[1])
+        rate = math.log2(errs[0] / errs[1])
+        assert abs(rate - (q + 1)) < 0.3, (name, errs, rate)
+
+
+def test_controller_exponent_follows_the_pair():
+    # err = tol * 2^(q+1): the next step halves (times the 0.9 safety factor)
+    for q in (1, 2, 4):
+        assert llg.Solver.next_dt(1.0, 2.0 ** (q + 1), 1.0, q) == pytest.approx(0.45)

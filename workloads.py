@@ -130,6 +130,24 @@ def surrogate_films(ntraj, seed=5, n_side=256):
     return films, run
 
 
+SURROGATE_LAYERS = ((6, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3))
+
+
+def surrogate_init(seed=0):
+    """Seeded initial weights of the surrogate network, list of (w, b) per
+    layer with w of shape (cout, cin, 3, 3): normal with std sqrt(2 / (9
+    cin)) (the last layer ten times smaller, so the first proposals are
+    close to "no change"), zero biases."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for li, (ci, co) in enumerate(SURROGATE_LAYERS):
+        std = np.sqrt(2.0 / (9 * ci))
+        if li == len(SURROGATE_LAYERS) - 1:
+            std *= 0.1
+        params.append((rng.standard_normal((co, ci, 3, 3)) * std, np.zeros(co)))
+    return params
+
+
 def small_problem(n=(8, 6, 1), cell=(4e-9, 4e-9, 3e-9), pbc=(False, False, False), seed=7,
                   **over):
     """A small random problem with every deterministic term switched on,
