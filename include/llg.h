@@ -71,7 +71,8 @@ enum {
     LLG_TERM_ANISOTROPY = 4,  /* uniaxial anisotropy, Sec. 2.1.3 Eq. 4 */
     LLG_TERM_ZEEMAN = 8,      /* applied field, Sec. 2.1.3            */
     LLG_TERM_THERMAL = 16,    /* thermal field, Sec. 2.1.3 Eq. 6      */
-    LLG_TERM_ALL = 31
+    LLG_TERM_STT = 32,        /* Zhang-Li spin-transfer torque, Eq. 7 */
+    LLG_TERM_ALL = 63
 };
 
 /* Run statistics. */
@@ -125,6 +126,20 @@ llg_status llg_set_material(llg_solver *s, double Ms, double Aex, double alpha);
 /* Uniaxial anisotropy Ku (J/m^3; energy density Ku sin^2 theta, Eq. 4) along
  * the axis u[3] (need not be normalised; must be non-zero). */
 llg_status llg_set_anisotropy_uniaxial(llg_solver *s, double Ku, const double u[3]);
+/* Cubic anisotropy (Eq. 5): energy density K1 (a1^2 a2^2 + a2^2 a3^2 +
+ * a1^2 a3^2) + K2 a1^2 a2^2 a3^2 (J/m^3) with a_i = m . c_i, c3 = c1 x c2;
+ * c1 and c2 need not be normalised but must be non-zero and orthogonal
+ * (|cos| <= 1e-6), else LLG_E_ARG.  Part of LLG_TERM_ANISOTROPY; adds to the
+ * uniaxial term.  Default K1 = K2 = 0. */
+llg_status llg_set_anisotropy_cubic(llg_solver *s, double K1, double K2, const double c1[3],
+                                    const double c2[3]);
+/* Uniform current density j[3] (A/m^2), polarisation P and non-adiabaticity
+ * xi of the Zhang-Li spin-transfer torque (Eq. 7-8):
+ * -b_j/(1+alpha^2) [m x (m x (j.grad) m) + (xi - alpha) m x (j.grad) m],
+ * b_j = P mu_B / (e Ms (1 + xi^2)).  (j.grad) m is a central difference;
+ * at a free surface the missing neighbour is the cell itself.  It is a torque,
+ * not a field: llg_eval_heff does not include it.  Default j = 0. */
+llg_status llg_set_current(llg_solver *s, const double j[3], double P, double xi);
 /* Uniform applied field B[3] = mu0 H in tesla. */
 llg_status llg_set_applied_field(llg_solver *s, const double B[3]);
 /* Temperature T >= 0 (K) and the 64-bit seed of the thermal field of Eq. 6.

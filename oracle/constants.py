@@ -11,3 +11,5 @@ MU0 = 4.0e-7 * math.pi          # T m / A (vacuum permeability)
 GAMMA_LL = 1.7595e11            # rad / (s T)
 GAMMA0 = MU0 * GAMMA_LL         # m / (A s), the gamma of Eq. 1 and Eq. 6
 KB = 1.380649e-23               # J / K, Boltzmann constant (Eq. 6)
+MU_B = 9.2740100783e-24         # J / T, Bohr magneton (Eq. 8)
+E_CHARGE = 1.602176634e-19      # C, elementary charge (Eq. 8)

@@ -26,7 +26,7 @@ import math
 
 import numpy as np
 
-from .constants import GAMMA0
+from .constants import GAMMA0, MU_B, E_CHARGE
 from . import fields
 
 # --------------------------------------------------------------------------
@@ -92,6 +92,44 @@ def ll_rhs(m, H, alpha):
     return -GAMMA0 / (1.0 + alpha * alpha) * (mxH + alpha * mxmxH)
 
 
+def current_gradient(m, prob):
+    """(j . grad) m with central differences per axis, (m[i+1] - m[i-1]) /
+    (2 d); at a free surface the missing neighbour is the cell itself, a
+    periodic axis wraps, an axis one cell long contributes nothing."""
+    j = np.asarray(prob.get("j", (0.0, 0.0, 0.0)), dtype=np.float64)
+    D = np.zeros_like(m)
+    for a, axis in ((0, 3), (1, 2), (2, 1)):
+        n = m.shape[axis]
+        if j[a] == 0.0 or n == 1:
+            continue
+        up = np.roll(m, -1, axis=axis)     # neighbour at index i+1
+        dn = np.roll(m, 1, axis=axis)      # neighbour at index i-1
+        if not prob["pbc"][a]:
+            last = [slice(None)] * 4
+            last[axis] = n - 1
+            up[tuple(last)] = m[tuple(last)]
+            first = [slice(None)] * 4
+            first[axis] = 0
+            dn[tuple(first)] = m[tuple(first)]
+        D += j[a] * (up - dn) / (2.0 * prob["cell"][a])
+    return D
+
+
+def stt_rhs(m, prob):
+    """Sec. 2.1.3, Eq. 7-8 divided by Ms: the Zhang-Li terms
+    -b_j/(1+alpha^2) [m x (m x D) + (xi - alpha) m x D], D = (j . grad) m,
+    b_j = P mu_B / (e Ms (1 + xi^2))."""
+    j = np.asarray(prob.get("j", (0.0, 0.0, 0.0)), dtype=np.float64)
+    if not np.any(j):
+        return np.zeros_like(m)
+    alpha, xi, P = prob["alpha"], prob.get("xi", 0.0), prob.get("P", 0.0)
+    bj = P * MU_B / (E_CHARGE * prob["Ms"] * (1.0 + xi * xi))
+    D = current_gradient(m, prob)
+    mxD = np.cross(m, D, axis=0)
+    mxmxD = np.cross(m, mxD, axis=0)
+    return -bj / (1.0 + alpha * alpha) * (mxmxD + (xi - alpha) * mxD)
+
+
 class Solver:
     """Plain FP64 integrator state for one problem."""
 
@@ -109,7 +147,7 @@ class Solver:
     def rhs(self, m, dt):
         H = fields.heff(m, self.prob, dt=dt, step=self.step_count)
         self.evals += 1
-        return ll_rhs(m, H, self.prob["alpha"])
+        return ll_rhs(m, H, self.prob["alpha"]) + stt_rhs(m, self.prob)
 
     def _norm(self, m):
         return normalize(m) if self.renormalize else m

@@ -21,10 +21,10 @@ LLG_EULER, LLG_HEUN, LLG_RK4, LLG_RKDP45, LLG_RK12, LLG_RK3, LLG_RK23, LLG_RKCK 
 METHODS = {"euler": LLG_EULER, "heun": LLG_HEUN, "rk3": LLG_RK3, "rk4": LLG_RK4, "rkdp45": LLG_RKDP45,
            "rk12": LLG_RK12, "rk23": LLG_RK23, "rkck": LLG_RKCK}
 LLG_HOST, LLG_DEVICE = 0, 1
-TERM_DEMAG, TERM_EXCHANGE, TERM_ANISOTROPY, TERM_ZEEMAN, TERM_THERMAL = 1, 2, 4, 8, 16
-TERM_ALL = 31
+TERM_DEMAG, TERM_EXCHANGE, TERM_ANISOTROPY, TERM_ZEEMAN, TERM_THERMAL, TERM_STT = 1, 2, 4, 8, 16, 32
+TERM_ALL = 63
 TERM_BITS = {"demag": TERM_DEMAG, "exchange": TERM_EXCHANGE, "anisotropy": TERM_ANISOTROPY,
-             "zeeman": TERM_ZEEMAN, "thermal": TERM_THERMAL}
+             "zeeman": TERM_ZEEMAN, "thermal": TERM_THERMAL, "stt": TERM_STT}
 KERNEL_KINDS = ("row_fwd", "spectral", "row_inv", "y_fwd", "y_inv")
 
 
@@ -76,6 +76,9 @@ _SIGNATURES = {
     "llg_set_cellsize": ([_P] + [ctypes.c_double] * 3, ctypes.c_int),
     "llg_set_material": ([_P] + [ctypes.c_double] * 3, ctypes.c_int),
     "llg_set_anisotropy_uniaxial": ([_P, ctypes.c_double, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "llg_set_anisotropy_cubic": ([_P, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "llg_set_current": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double], ctypes.c_int),
     "llg_set_applied_field": ([_P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "llg_set_temperature": ([_P, ctypes.c_double, ctypes.c_uint64], ctypes.c_int),
     "llg_set_terms": ([_P, ctypes.c_int], ctypes.c_int),
@@ -204,6 +207,12 @@ class Solver:
     def set_anisotropy_uniaxial(self, Ku, u):
         self._chk(self._lib.llg_set_anisotropy_uniaxial(self._h, float(Ku), _arr3(u)))
 
+    def set_anisotropy_cubic(self, K1, K2, c1=(1.0, 0.0, 0.0), c2=(0.0, 1.0, 0.0)):
+        self._chk(self._lib.llg_set_anisotropy_cubic(self._h, float(K1), float(K2), _arr3(c1), _arr3(c2)))
+
+    def set_current(self, j, P, xi):
+        self._chk(self._lib.llg_set_current(self._h, _arr3(j), float(P), float(xi)))
+
     def set_applied_field(self, B):
         self._chk(self._lib.llg_set_applied_field(self._h, _arr3(B)))
 
@@ -220,10 +229,14 @@ class Solver:
         self.set_cellsize(prob["cell"])
         self.set_material(prob["Ms"], prob["Aex"], prob["alpha"])
         self.set_anisotropy_uniaxial(prob.get("Ku", 0.0), prob.get("u", (1.0, 0.0, 0.0)))
+        self.set_anisotropy_cubic(prob.get("Kc1", 0.0), prob.get("Kc2", 0.0), prob.get("c1", (1.0, 0.0, 0.0)),
+                                  prob.get("c2", (0.0, 1.0, 0.0)))
         self.set_applied_field(prob.get("B", (0.0, 0.0, 0.0)))
+        self.set_current(prob.get("j", (0.0, 0.0, 0.0)), prob.get("P", 0.0), prob.get("xi", 0.0))
         self.set_temperature(prob.get("T", 0.0), prob.get("seed", 0))
         terms = prob.get("terms")
-        self.set_terms(TERM_ALL if terms is None else terms)
+        # the oracle's term names are field terms; the torque follows the current
+        self.set_terms(TERM_ALL if terms is None else sum(TERM_BITS[t] for t in terms) | TERM_STT)
 
     # ---- state --------------------------------------------------------------
     def _shape(self):

@@ -119,6 +119,7 @@ Col2dArgs col_args(const BatchFilm& f) {
     c.nkx = f.g.Px / 2;
     c.nkx_full = f.g.nkx;
     c.nkxp = f.g.nkxp;
+    c.tsh = f.g.tsh;
     c.ny = f.g.ny;
     c.Py = f.g.Py;
     return c;
@@ -391,6 +392,7 @@ llg_status llg_batch_create(int device, const llg_film_desc* films, int nfilms, 
         g.Px = Px; g.Py = Py; g.Pz = 1;
         g.nkx = Px / 2 + 1;
         g.nkxp = (g.nkx + 15) / 16 * 16;
+        g.tsh = fast2d_tile_shift();
         g.split_y = 1; g.split_z = 0;
         const int rpb = fast2d_row_rows_per_block(Px, f.rvar);
         f.row_blocks = (g.nrows + rpb - 1) / rpb;

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cstdlib>
 
 #include "cell_physics.hpp"
 #include "internal.hpp"
@@ -134,8 +135,8 @@ struct RowSplit {
         F::template run<false>(z, scr, tw, lg);
         const int cs = g.nrows * g.nkxp;
         const float2 zN = z[E2 / 2];   // X[PX/2]: even half, lane 0
-        float2* s0 = S + r0 * g.nkxp;
-        float2* s1 = s0 + g.nkxp;
+        float2* s0 = S + (r0 << g.tsh);
+        float2* s1 = s0 + (1 << g.tsh);
 #pragma unroll
         for (int i = 0; i < E2 / 2; ++i) {
             const int j = lg + P * i;
@@ -147,7 +148,7 @@ struct RowSplit {
                 A = mk2(zk.x, zN.x);
                 B = mk2(zk.y, zN.y);
             }
-            const int col = half * Q + j;
+            const int col = tile_index(0, half * Q + j, g.nrows, g.tsh);
             if (kind == 0) {
                 if (v0) { s0[col] = A; s0[cs + col] = B; }
             } else if (kind == 1) {
@@ -245,6 +246,7 @@ __device__ __forceinline__ void local_field_lds(const Grid& g, const Phys& p, co
         const float mu = p.ku * (mx * p.u[0] + my * p.u[1] + mz * p.u[2]);
         hx += mu * p.u[0]; hy += mu * p.u[1]; hz += mu * p.u[2];
     }
+    if (p.kc1 != 0.f || p.kc2 != 0.f) cubic_field(p, mx, my, mz, hx, hy, hz);
     hx += p.hz[0]; hy += p.hz[1]; hz += p.hz[2];
     if (p.sig_th != 0.f) {
         float ex, ey, ez;
@@ -311,11 +313,11 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         const int scs = g.nrows * g.nkxp;
         const float2* sa_ = nullptr;
         const float2* sb_ = nullptr;
-        if (kind == 0) { if (v0) { sa_ = S + r0 * g.nkxp; sb_ = sa_ + scs; } }
-        else if (kind == 1) { if (v1) { sa_ = S + (r0 + 1) * g.nkxp; sb_ = sa_ + scs; } }
+        if (kind == 0) { if (v0) { sa_ = S + (r0 << g.tsh); sb_ = sa_ + scs; } }
+        else if (kind == 1) { if (v1) { sa_ = S + ((r0 + 1) << g.tsh); sb_ = sa_ + scs; } }
         else {
-            if (v0) sa_ = S + 2 * scs + r0 * g.nkxp;
-            if (v1) sb_ = S + 2 * scs + (r0 + 1) * g.nkxp;
+            if (v0) sa_ = S + 2 * scs + (r0 << g.tsh);
+            if (v1) sb_ = S + 2 * scs + ((r0 + 1) << g.tsh);
         }
 #pragma unroll
         for (int i = 0; i < E2; ++i) {
@@ -330,7 +332,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
                 if (sb_) { const float2 v = sb_[0]; B = mk2(nyq ? v.y : v.x, 0.f); }
             } else {
                 const bool up = k > PX / 2;
-                const int col = half ? Q + (up ? H - 1 - j : j) : (up ? H - j : j);
+                const int col = tile_index(0, half ? Q + (up ? H - 1 - j : j) : (up ? H - j : j), g.nrows, g.tsh);
                 if (sa_) { A = sa_[col]; if (up) A.y = -A.y; }
                 if (sb_) { B = sb_[col]; if (up) B.y = -B.y; }
             }
@@ -384,6 +386,28 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         }
         float kx, ky, kz;
         ll_torque(p, rc[x], rc[NXM + x], rc[2 * NXM + x], hx, hy, hz, kx, ky, kz);
+        if (p.stt_on) {
+            // D = (j . grad) m from the staged rows: x neighbours in the row,
+            // y neighbours in the rows above and below (the cell itself where
+            // a free surface has none)
+            const float mx = rc[x], my = rc[NXM + x], mz = rc[2 * NXM + x];
+            float Dx = 0.f, Dy = 0.f, Dz = 0.f;
+            if (p.cj[0] != 0.f && nx > 1) {
+                const int xu = x < nx - 1 ? x + 1 : (g.pbc[0] ? 0 : x);
+                const int xd = x > 0 ? x - 1 : (g.pbc[0] ? nx - 1 : x);
+                Dx += p.cj[0] * (rc[xu] - rc[xd]);
+                Dy += p.cj[0] * (rc[NXM + xu] - rc[NXM + xd]);
+                Dz += p.cj[0] * (rc[2 * NXM + xu] - rc[2 * NXM + xd]);
+            }
+            if (p.cj[1] != 0.f && ny > 1) {
+                const float* ru = rp ? rp : rc;
+                const float* rd = rm ? rm : rc;
+                Dx += p.cj[1] * (ru[x] - rd[x]);
+                Dy += p.cj[1] * (ru[NXM + x] - rd[NXM + x]);
+                Dz += p.cj[1] * (ru[2 * NXM + x] - rd[2 * NXM + x]);
+            }
+            stt_torque(p, mx, my, mz, Dx, Dy, Dz, kx, ky, kz);
+        }
         bad |= !(isfinite(kx) && isfinite(ky) && isfinite(kz));
         if (ko) { ko[qq] = kx; ko[cs + qq] = ky; ko[2 * cs + qq] = kz; }
         if (sa.mode == ROW_KONLY) continue;
@@ -490,11 +514,11 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     const int kcs = a.nkx_full * (Py / 2 + 1);
     // this group's column, zero beyond ny
     float2 x[E];
-    const float2* src = a.S + c * cs + scol;
+    const float2* src = a.S + c * cs + tile_index(0, scol, ny, a.tsh);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int y = lg + P * i;
-        x[i] = y < ny ? src[y * a.nkxp] : mk2(0.f, 0.f);
+        x[i] = y < ny ? src[y << a.tsh] : mk2(0.f, 0.f);
     }
     for (int m = tid; m < 2 * L; m += CT2) tw[m] = a.tw[m];
     // kernel values at ky = 2 pos + h (mirror compressed along y; xy is
@@ -575,13 +599,13 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     }
     __syncthreads();
     if (h == 1) return;
-    float2* dst = a.S + c * cs + scol;
+    float2* dst = a.S + c * cs + tile_index(0, scol, ny, a.tsh);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int y = lg + P * i;
         if (y < ny) {
             const float2 v = comb[y];
-            dst[y * a.nkxp] = mk2(x[i].x + v.x, x[i].y + v.y);
+            dst[y << a.tsh] = mk2(x[i].x + v.x, x[i].y + v.y);
         }
     }
 }
@@ -598,9 +622,9 @@ __global__ __launch_bounds__(CT2) void col2d_fast(Col2dArgs a, DevState* __restr
 // variant in use for a length comes from a process-wide table that
 // llg_autotune fills (variant 0 until then).
 // ---------------------------------------------------------------------------
-#define ROW_VARIANTS(X) X(64, 4, 0) X(64, 8, 1) X(128, 4, 0) X(128, 8, 1) X(192, 12, 0) X(192, 24, 1) \
-    X(256, 4, 0) X(256, 8, 1) X(384, 12, 0) X(384, 24, 1) X(512, 4, 0) X(512, 8, 1) X(768, 12, 0)    \
-    X(768, 24, 1) X(1024, 8, 0) X(1024, 16, 1)
+#define ROW_VARIANTS(X) X(64, 4, 0) X(64, 8, 1) X(128, 4, 0) X(128, 8, 1) X(192, 12, 0) X(192, 6, 1) \
+    X(256, 4, 0) X(256, 8, 1) X(384, 12, 0) X(384, 6, 1) X(512, 4, 0) X(512, 8, 1) X(768, 12, 0)     \
+    X(768, 6, 1) X(1024, 8, 0) X(1024, 16, 1)
 #define COL_VARIANTS(X) X(32, 4, 0) X(32, 8, 1) X(64, 4, 0) X(64, 8, 1) X(96, 12, 0) X(96, 6, 1) \
     X(128, 4, 0) X(128, 8, 1) X(192, 12, 0) X(192, 6, 1) X(256, 4, 0) X(256, 8, 1) X(384, 12, 0) \
     X(384, 6, 1) X(512, 8, 0) X(512, 16, 1)
@@ -634,10 +658,17 @@ __global__ __launch_bounds__(CT2) void col_group(const FilmCol* __restrict__ fil
     col2d_body<L, E>(f.a, f.st, m.y, dyn_lds);
 }
 
-// kernels whose dynamic LDS may exceed 64 KB need the limit raised once
+// LDS of one workgroup on gfx950
+constexpr int kMaxLds = 160 * 1024;
+
+// kernels whose dynamic LDS may exceed 64 KB need the limit raised once;
+// sizes beyond the hardware are refused before any runtime call
 static hipError_t allow_lds(const void* kernel, int bytes) {
+    if (bytes > kMaxLds) return hipErrorInvalidValue;
     if (bytes <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) (void)hipGetLastError();   // leave no error behind for later calls
+    return e;
 }
 
 // the variant table: lengths up to 2048 in steps of 32
@@ -650,17 +681,28 @@ int slot(int len) { return (len % 32 == 0 && len >= 32 && len <= 2048) ? len / 3
 // dispatch
 // ---------------------------------------------------------------------------
 int fast2d_row_variant(int Px) { return g_row_var[slot(Px)].load(); }
+
+// tile width of the 2D spectrum (log2); LLG_TILE_LOG2 overrides it for
+// layout experiments
+int fast2d_tile_shift() {
+    const char* e = getenv("LLG_TILE_LOG2");
+    if (e && e[0] >= '0' && e[0] <= '5' && e[1] == 0) return e[0] - '0';
+    return 2;
+}
 int fast2d_col_variant(int L) { return g_col_var[slot(L)].load(); }
-bool fast2d_set_variants(int Px, int rv, int L, int cv) {
-    if (!fast2d_row_ok(Px, rv) || !fast2d_col_ok(L, 1, cv)) return false;
+bool fast2d_set_variants(int Px, int rv, int L, int cv, bool xper) {
+    if (!fast2d_row_ok(Px, rv, xper) || !fast2d_col_ok(L, 1, cv)) return false;
     g_row_var[slot(Px)].store(rv);
     g_col_var[slot(L)].store(cv);
     return true;
 }
 
-bool fast2d_row_ok(int Px, int var) {
+bool fast2d_row_ok(int Px, int var, bool xper) {
     if (var < 0) var = fast2d_row_variant(Px);
-#define CASE(PX, E, V) if (Px == PX && var == V) return true;
+#define CASE(PX, E, V)                                                                    \
+    if (Px == PX && var == V)                                                             \
+        return (xper ? RowSplit<PX, E>::template inv_bytes<true>()                        \
+                     : RowSplit<PX, E>::template inv_bytes<false>()) <= kMaxLds;
     ROW_VARIANTS(CASE)
 #undef CASE
     return false;
@@ -677,7 +719,7 @@ bool fast2d_col_ok(int L, int split, int var) {
 
 hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, const FwdArgs& fa,
                                DevState* st, hipStream_t s) {
-    if (g.nx > g.Px || g.nkxp < g.Px / 2) return hipErrorInvalidValue;
+    if (g.nx > g.Px || g.nkxp < g.Px / 2 || g.tsh < 0 || (g.Px / 2) % (1 << g.tsh)) return hipErrorInvalidValue;
     const int var = fast2d_row_variant(g.Px);
 #define CASE(PX, E, V)                                                                    \
     if (g.Px == PX && var == V) {                                                         \
@@ -685,15 +727,17 @@ hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, cons
         const dim3 grid((g.nrows + rows - 1) / rows);                                     \
         constexpr int lds_p = RowSplit<PX, E>::template fwd_bytes<true>();                \
         constexpr int lds_o = RowSplit<PX, E>::template fwd_bytes<false>();               \
-        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, true>), lds_p); \
-        if (e_ == hipSuccess) e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, false>), lds_o); \
-        if (e_ != hipSuccess) return e_;                                                  \
-        if (g.nx == PX)                                                                   \
+        if (g.nx == PX) {                                                                 \
+            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, true>), lds_p); \
+            if (e_ != hipSuccess) return e_;                                              \
             hipLaunchKernelGGL((row_fwd_fast<PX, E, true>), grid, dim3(FRT), lds_p, s, g, twx, S, fa, st); \
-        else if (2 * g.nx <= PX)                                                          \
+        } else if (2 * g.nx <= PX) {                                                      \
+            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, false>), lds_o); \
+            if (e_ != hipSuccess) return e_;                                              \
             hipLaunchKernelGGL((row_fwd_fast<PX, E, false>), grid, dim3(FRT), lds_o, s, g, twx, S, fa, st); \
-        else                                                                              \
+        } else {                                                                          \
             return hipErrorInvalidValue;                                                  \
+        }                                                                                 \
         return hipGetLastError();                                                         \
     }
     ROW_VARIANTS(CASE)
@@ -703,7 +747,8 @@ hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, cons
 
 hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, float2* S,
                                const StageArgs& sa, DevState* st, hipStream_t s) {
-    if (g.nx > g.Px || g.nkxp < g.Px / 2 || sa.nk > kMaxK) return hipErrorInvalidValue;
+    if (g.nx > g.Px || g.nkxp < g.Px / 2 || sa.nk > kMaxK || g.tsh < 0 || (g.Px / 2) % (1 << g.tsh))
+        return hipErrorInvalidValue;
     if ((sa.mode == ROW_STAGE || sa.mode == ROW_ERROR) && sa.nk < 1) return hipErrorInvalidValue;
     const int var = fast2d_row_variant(g.Px);
 #define CASE(PX, E, V)                                                                    \
@@ -712,17 +757,19 @@ hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, 
         const dim3 grid((g.nrows + rows - 1) / rows);                                     \
         constexpr int lds_p = RowSplit<PX, E>::template inv_bytes<true>();                \
         constexpr int lds_o = RowSplit<PX, E>::template inv_bytes<false>();               \
-        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, true>), lds_p); \
-        if (e_ == hipSuccess) e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, false>), lds_o); \
-        if (e_ != hipSuccess) return e_;                                                  \
-        if (g.nx == PX)                                                                   \
+        if (g.nx == PX) {                                                                 \
+            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, true>), lds_p); \
+            if (e_ != hipSuccess) return e_;                                              \
             hipLaunchKernelGGL((row_inv_fast<PX, E, true>), grid, dim3(FRT),              \
                                lds_p, s, g, p, twx, S, sa, st);                           \
-        else if (2 * g.nx <= PX)                                                          \
+        } else if (2 * g.nx <= PX) {                                                      \
+            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, false>), lds_o); \
+            if (e_ != hipSuccess) return e_;                                              \
             hipLaunchKernelGGL((row_inv_fast<PX, E, false>), grid, dim3(FRT),             \
                                lds_o, s, g, p, twx, S, sa, st);                           \
-        else                                                                              \
+        } else {                                                                          \
             return hipErrorInvalidValue;                                                  \
+        }                                                                                 \
         return hipGetLastError();                                                         \
     }
     ROW_VARIANTS(CASE)
@@ -732,6 +779,7 @@ hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, 
 
 hipError_t launch_col2d_fast(const Col2dArgs& a, DevState* st, hipStream_t s) {
     if (a.Py % 2 || a.ny > a.Py / 2 || a.nkx_full != a.nkx + 1 || a.nkx % 2) return hipErrorInvalidValue;
+    if (a.tsh < 0 || a.nkx % (1 << a.tsh)) return hipErrorInvalidValue;
     const int L = a.Py / 2;
     const int var = fast2d_col_variant(L);
 #define CASE(LL, E, V)                                                                    \

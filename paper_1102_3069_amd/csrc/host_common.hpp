@@ -19,6 +19,8 @@ namespace host {
 constexpr double kMu0 = 4.0e-7 * M_PI;
 constexpr double kGammaLL = 1.7595e11;
 constexpr double kGamma0 = kMu0 * kGammaLL;
+constexpr double kBohrMagneton = 9.2740100783e-24;   // J/T
+constexpr double kElectronCharge = 1.602176634e-19;  // C
 constexpr double kBoltzmann = 1.380649e-23;
 constexpr double kDtMin = 1e-18;
 constexpr int kMaxPx = 2048;
@@ -161,6 +163,8 @@ inline bool make_plan(int L, FftPlan& p) {
 struct Material {
     double Ms = 0, Aex = 0, alpha = 0;
     double Ku = 0, u[3] = {1, 0, 0};
+    double Kc1 = 0, Kc2 = 0, c1[3] = {1, 0, 0}, c2[3] = {0, 1, 0};
+    double j[3] = {0, 0, 0}, P = 0, xi = 0;   // current density (A/m^2), polarisation, non-adiabaticity
     double B[3] = {0, 0, 0};
     double d[3] = {0, 0, 0};
     double T = 0;
@@ -179,6 +183,27 @@ inline Phys phys_of(const Material& s, double dt_thermal) {
     for (int a = 0; a < 3; ++a) {
         p.u[a] = (float)(s.u[a] / un);
         p.hz[a] = (s.terms & LLG_TERM_ZEEMAN) ? (float)(s.B[a] / (kMu0 * s.Ms)) : 0.f;
+    }
+    // cubic axes: c1 and c2 normalised, c3 = c1 x c2
+    {
+        double a[3], b[3];
+        const double na = sqrt(s.c1[0] * s.c1[0] + s.c1[1] * s.c1[1] + s.c1[2] * s.c1[2]);
+        const double nb = sqrt(s.c2[0] * s.c2[0] + s.c2[1] * s.c2[1] + s.c2[2] * s.c2[2]);
+        for (int k = 0; k < 3; ++k) { a[k] = s.c1[k] / na; b[k] = s.c2[k] / nb; }
+        const double c[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+        for (int k = 0; k < 3; ++k) { p.c[0][k] = (float)a[k]; p.c[1][k] = (float)b[k]; p.c[2][k] = (float)c[k]; }
+        const bool on = (s.terms & LLG_TERM_ANISOTROPY) != 0;
+        p.kc1 = on ? (float)(2.0 * s.Kc1 / (kMu0 * Ms2)) : 0.f;
+        p.kc2 = on ? (float)(2.0 * s.Kc2 / (kMu0 * Ms2)) : 0.f;
+    }
+    // Zhang-Li torque (Eq. 7-8): b_j = P mu_B / (e Ms (1 + xi^2)), reduced by
+    // gamma0 Ms, with the 1/(2 d) of a central difference folded in
+    {
+        const double bj = s.P * kBohrMagneton / (kElectronCharge * s.Ms * (1.0 + s.xi * s.xi));
+        const bool on = (s.terms & LLG_TERM_STT) && (s.j[0] != 0.0 || s.j[1] != 0.0 || s.j[2] != 0.0) && bj != 0.0;
+        p.stt_on = on ? 1 : 0;
+        for (int a = 0; a < 3; ++a) p.cj[a] = on ? (float)(bj * s.j[a] / (2.0 * s.d[a] * kGamma0 * s.Ms)) : 0.f;
+        p.xi_a = (float)(s.xi - s.alpha);
     }
     p.alpha = (float)s.alpha;
     p.llpre = (float)(-1.0 / (1.0 + s.alpha * s.alpha));

@@ -24,7 +24,15 @@ struct Grid {
     int Px, Py, Pz;
     int nkx, nkxp;
     int split_y, split_z;   // 1 on an open axis: even/odd half transforms
+    int tsh;                // 2D compiled path: spectrum columns in tiles of 2^tsh
 };
+
+// Spectrum layout of the 2D compiled path: per component, stored columns
+// are grouped in tiles of 2^tsh; a tile keeps its rows contiguous, so a
+// column read walks 2^tsh-element strides and a row read 2^tsh-element runs.
+__host__ __device__ inline int tile_index(int row, int col, int nrows, int tsh) {
+    return (((col >> tsh) * nrows + row) << tsh) + (col & ((1 << tsh) - 1));
+}
 
 // Coefficients in reduced units: fields are divided by Ms, time is scaled by
 // gamma0*Ms (so dm/dtau = -1/(1+alpha^2) (m x h + alpha m x (m x h))).
@@ -32,6 +40,11 @@ struct Phys {
     float cex[3];     // 2A/(mu0 Ms^2 d_a^2): exchange coupling per axis
     float ku;         // 2Ku/(mu0 Ms^2)
     float u[3];       // anisotropy axis (unit)
+    float kc1, kc2;   // cubic anisotropy 2K1/(mu0 Ms^2), 2K2/(mu0 Ms^2)
+    int stt_on;       // Zhang-Li spin-transfer torque present
+    float cj[3];      // b_j j_a / (2 d_a gamma0 Ms): central-difference weight per axis
+    float xi_a;       // xi - alpha
+    float c[3][3];    // cubic axes c1, c2, c3 = c1 x c2 (unit)
     float hz[3];      // applied field B/(mu0 Ms)
     float alpha;
     float llpre;      // -1/(1+alpha^2)
@@ -136,6 +149,7 @@ struct Col2dArgs {
     const float2* tw;       // exp(-2 pi i m / Py), m < Py
     int nkx, nkx_full, nkxp;
     int ny, Py;
+    int tsh;                // tile width log2 (see tile_index)
 };
 
 // ---- launchers (kernels.hip) ------------------------------------------------
@@ -154,11 +168,12 @@ hipError_t launch_fft_test(float2* data, int n, int batch, const FftPlan& pl, co
 // ---- 2D fast path (fast2d.hip) ---------------------------------------------------
 // compiled variants per length (elements per lane); var < 0 selects the
 // variant of the process-wide table (llg_autotune), 0 until tuned
-bool fast2d_row_ok(int Px, int var = -1);
+bool fast2d_row_ok(int Px, int var = -1, bool xper = false);
 bool fast2d_col_ok(int L, int split, int var = -1);
 int fast2d_row_variant(int Px);
+int fast2d_tile_shift();
 int fast2d_col_variant(int L);
-bool fast2d_set_variants(int Px, int row_var, int L, int col_var);
+bool fast2d_set_variants(int Px, int row_var, int L, int col_var, bool xper = false);
 hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, const FwdArgs& fa,
                                DevState* st, hipStream_t s);
 hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, float2* S,

@@ -215,6 +215,11 @@ __global__ __launch_bounds__(RT) void row_inv_kernel(Grid g, Phys p, FftPlan px,
             }
             float kx, ky, kz;
             ll_torque(p, mx, my, mz, hx, hy, hz, kx, ky, kz);
+            if (p.stt_on) {
+                float Dx, Dy, Dz;
+                stt_gradient(g, p, mi, r, x, mx, my, mz, Dx, Dy, Dz);
+                stt_torque(p, mx, my, mz, Dx, Dy, Dz, kx, ky, kz);
+            }
             bad |= !(isfinite(kx) && isfinite(ky) && isfinite(kz));
             if (ko) { ko[i] = kx; ko[cs + i] = ky; ko[2 * cs + i] = kz; }
             if (sa.mode == ROW_STAGE) {

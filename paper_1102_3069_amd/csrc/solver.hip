@@ -53,6 +53,8 @@ struct llg_solver {
     double dx = 0, dy = 0, dz = 0;
     double Ms = 0, Aex = 0, alpha = 0;
     double Ku = 0, u[3] = {1, 0, 0};
+    double Kc1 = 0, Kc2 = 0, c1[3] = {1, 0, 0}, c2[3] = {0, 1, 0};
+    double jc[3] = {0, 0, 0}, P = 0, xi = 0;
     double B[3] = {0, 0, 0};
     double T = 0;
     uint64_t seed = 0;
@@ -147,7 +149,10 @@ bool two_d(const llg_solver* s) { return s->nz == 1; }
 Phys make_phys(const llg_solver* s, double dt_thermal) {
     Material m;
     m.Ms = s->Ms; m.Aex = s->Aex; m.alpha = s->alpha; m.Ku = s->Ku;
-    for (int a = 0; a < 3; ++a) { m.u[a] = s->u[a]; m.B[a] = s->B[a]; }
+    for (int a = 0; a < 3; ++a) { m.u[a] = s->u[a]; m.B[a] = s->B[a]; m.c1[a] = s->c1[a]; m.c2[a] = s->c2[a]; }
+    m.Kc1 = s->Kc1; m.Kc2 = s->Kc2;
+    for (int a = 0; a < 3; ++a) m.j[a] = s->jc[a];
+    m.P = s->P; m.xi = s->xi;
     m.d[0] = s->dx; m.d[1] = s->dy; m.d[2] = s->dz;
     m.T = s->T; m.seed = s->seed; m.terms = s->terms;
     return phys_of(m, dt_thermal);
@@ -223,6 +228,7 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
         c.nkx = g.Px / 2;
         c.nkx_full = g.nkx;
         c.nkxp = g.nkxp;
+        c.tsh = g.tsh;
         c.ny = g.ny;
         c.Py = g.Py;
         HIPCHK(s, launch_col2d_fast(c, s->st, s->stream));
@@ -573,6 +579,7 @@ llg_status llg_set_geometry(llg_solver* s, int nx, int ny, int nz, int pbc_x, in
     g.Px = P[0]; g.Py = P[1]; g.Pz = P[2];
     g.nkx = P[0] / 2 + 1;
     g.nkxp = (g.nkx + 15) / 16 * 16;
+    g.tsh = fast2d_tile_shift();
     g.split_y = split_y;
     g.split_z = split_z;
     if (!make_plan(P[0], s->px) || !make_plan(Ly, s->py) || !make_plan(Lz, s->pz))
@@ -583,7 +590,7 @@ llg_status llg_set_geometry(llg_solver* s, int nx, int ny, int nz, int pbc_x, in
     // LLG_FORCE_GENERIC=1 selects the runtime-length kernels everywhere (used
     // by the tests to check both implementations against the oracle)
     const char* gen = getenv("LLG_FORCE_GENERIC");
-    s->fast2d = nz == 1 && fast2d_row_ok(P[0]) && fast2d_col_ok(Ly, split_y) && ny <= Ly &&
+    s->fast2d = nz == 1 && fast2d_row_ok(P[0], -1, nx == P[0]) && fast2d_col_ok(Ly, split_y) && ny <= Ly &&
                 (P[0] / 2) % fast2d_col_width(Ly) == 0 && !(gen && gen[0] == '1');
     const size_t vec = sizeof(float) * 3 * (size_t)g.ncells;
     HIPCHK(s, make_tw(P[0], &s->twx));
@@ -639,6 +646,37 @@ llg_status llg_set_anisotropy_uniaxial(llg_solver* s, double Ku, const double u[
     if (!(n > 0) || !isfinite(n)) return fail(s, LLG_E_ARG, "anisotropy axis must be non-zero");
     s->Ku = Ku;
     for (int a = 0; a < 3; ++a) s->u[a] = u[a];
+    s->k1_valid = false;
+    invalidate_graphs(s);
+    return LLG_OK;
+}
+
+llg_status llg_set_anisotropy_cubic(llg_solver* s, double K1, double K2, const double c1[3], const double c2[3]) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!c1 || !c2 || !isfinite(K1) || !isfinite(K2)) return fail(s, LLG_E_ARG, "invalid cubic anisotropy");
+    const double n1 = sqrt(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
+    const double n2 = sqrt(c2[0] * c2[0] + c2[1] * c2[1] + c2[2] * c2[2]);
+    if (!(n1 > 0) || !(n2 > 0) || !isfinite(n1) || !isfinite(n2))
+        return fail(s, LLG_E_ARG, "cubic axes must be non-zero");
+    const double d = (c1[0] * c2[0] + c1[1] * c2[1] + c1[2] * c2[2]) / (n1 * n2);
+    if (fabs(d) > 1e-6) return fail(s, LLG_E_ARG, "cubic axes must be orthogonal (cos %g)", d);
+    s->Kc1 = K1;
+    s->Kc2 = K2;
+    for (int a = 0; a < 3; ++a) { s->c1[a] = c1[a]; s->c2[a] = c2[a]; }
+    s->k1_valid = false;
+    invalidate_graphs(s);
+    return LLG_OK;
+}
+
+llg_status llg_set_current(llg_solver* s, const double j[3], double P, double xi) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!j || !isfinite(j[0]) || !isfinite(j[1]) || !isfinite(j[2]) || !isfinite(P) || !isfinite(xi))
+        return fail(s, LLG_E_ARG, "invalid current");
+    for (int a = 0; a < 3; ++a) s->jc[a] = j[a];
+    s->P = P;
+    s->xi = xi;
     s->k1_valid = false;
     invalidate_graphs(s);
     return LLG_OK;
@@ -894,7 +932,7 @@ llg_status llg_autotune(llg_solver* s, int iters, double* ms_out, int n_out, int
         for (int cv = 0; cv < 2; ++cv) {
             const int k = rv * 2 + cv;
             if (ms_out && k < n_out) ms_out[k] = -1.0;
-            if (!fast2d_set_variants(Px, rv, L, cv) || (Px / 2) % fast2d_col_width(L, cv)) continue;
+            if (!fast2d_set_variants(Px, rv, L, cv, s->g.nx == Px) || (Px / 2) % fast2d_col_width(L, cv)) continue;
             // one untimed evaluation, then `iters` timed ones (H_eff of the
             // current state, kept on the device)
             for (int it = 0; it <= iters; ++it) {
@@ -910,7 +948,7 @@ llg_status llg_autotune(llg_solver* s, int iters, double* ms_out, int n_out, int
                 sa.h_out = s->hbuf;
                 if (row_inv(s, p, sa) != hipSuccess) { rc = LLG_E_DEVICE; break; }
             }
-            if (rc != LLG_OK) { (void)fast2d_set_variants(Px, r0, L, c0); return fail(s, rc, "tuning launch failed"); }
+            if (rc != LLG_OK) { (void)fast2d_set_variants(Px, r0, L, c0, s->g.nx == Px); return fail(s, rc, "tuning launch failed"); }
             HIPCHK(s, hipEventRecord(e1, s->stream));
             HIPCHK(s, hipEventSynchronize(e1));
             float ms = 0.f;
@@ -922,7 +960,7 @@ llg_status llg_autotune(llg_solver* s, int iters, double* ms_out, int n_out, int
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    fast2d_set_variants(Px, br, L, bc);
+    fast2d_set_variants(Px, br, L, bc, s->g.nx == Px);
     invalidate_graphs(s);
     s->spec_valid = false;
     if (choice) { choice[0] = br; choice[1] = bc; }
@@ -934,7 +972,7 @@ llg_status llg_set_variants(llg_solver* s, int row_var, int col_var) {
     if (rc != LLG_OK) return rc;
     if (!s->fast2d) return fail(s, LLG_E_UNSUPPORTED, "no compiled variants for this geometry");
     const int Px = s->g.Px, L = s->g.Py / 2;
-    if (!fast2d_set_variants(Px, row_var, L, col_var) || (Px / 2) % fast2d_col_width(L, col_var))
+    if (!fast2d_set_variants(Px, row_var, L, col_var, s->g.nx == Px) || (Px / 2) % fast2d_col_width(L, col_var))
         return fail(s, LLG_E_ARG, "no compiled variant (%d, %d) for lengths %d, %d", row_var, col_var, Px, L);
     invalidate_graphs(s);
     s->spec_valid = false;

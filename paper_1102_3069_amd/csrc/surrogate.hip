@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ i
 // LDS holds gz^T [co][64 px] and the three input rows [ci][66 px] of a
 // chunk, so the MFMA fragments read contiguous k (pixel) runs.
 // ---------------------------------------------------------------------------
-constexpr int WG_ROWS = 4;
+constexpr int WG_ROWS = 16;
 
 __global__ __launch_bounds__(256) void conv_wgrad_kernel(const u16* __restrict__ gz, const u16* __restrict__ ain,
                                                          float* __restrict__ part_w, float* __restrict__ part_b,

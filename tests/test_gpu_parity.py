@@ -132,6 +132,106 @@ def test_heff_parity(lib, impl, case, term):
     assert e <= 1e-5
 
 
+@pytest.mark.parametrize("case", [dict(n=(17, 9, 1)), dict(n=(64, 96, 1)), dict(n=(6, 5, 4)),
+                                  dict(n=(8, 8, 3), pbc=(True, True, False), cell=(3e-9, 3e-9, 3e-9))],
+                         ids=lambda c: "x".join(map(str, c["n"])))
+@pytest.mark.parametrize("term", ["anisotropy", "all"])
+def test_heff_parity_cubic(lib, impl, case, term):
+    """Cubic anisotropy (Eq. 5) along rotated axes, with the uniaxial term."""
+    prob, m0 = workloads.small_problem(**case)
+    rng = np.random.default_rng(5)
+    q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    prob.update(Kc1=4e4, Kc2=-2.5e4, c1=tuple(q[:, 0]), c2=tuple(q[:, 1]))
+    if term != "all":
+        prob["terms"] = (term,)
+    s = make_solver(lib, prob, m0)
+    h = s.eval_heff()
+    ref = fields.heff(m0.astype(np.float64), prob)
+    e = maxrel(h, ref)
+    note("cubic", case, term, "maxrel", e)
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("K1,kind", [(5e5, "100"), (-5e5, "111")])
+def test_cubic_macrospin_on_gpu(lib, K1, kind):
+    """A strongly damped single cell relaxes onto the nearest easy axis of
+    the cubic term: the cube axes for K1 > 0, the body diagonals for K1 < 0."""
+    rng = np.random.default_rng(11)
+    q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    c1, c2 = q[:, 0], q[:, 1]
+    c3 = np.cross(c1, c2)
+    easy = c1 if kind == "100" else (c1 + c2 + c3) / np.sqrt(3.0)
+    perp = np.cross(easy, rng.standard_normal(3))
+    perp /= np.linalg.norm(perp)
+    m0 = (np.cos(0.4) * easy + np.sin(0.4) * perp).astype(np.float32).reshape(3, 1, 1, 1)
+    prob = dict(n=(1, 1, 1), cell=(5e-9,) * 3, pbc=(False,) * 3, Ms=8e5, Aex=1.3e-11, alpha=1.0,
+                Ku=0.0, Kc1=K1, Kc2=0.0, c1=tuple(c1), c2=tuple(c2), B=(0.0, 0.0, 0.0), T=0.0, seed=0)
+    s = make_solver(lib, prob, m0)
+    s.step("rk4", 1e-13, 3000)
+    assert np.max(np.abs(s.get_m()[:, 0, 0, 0] - easy)) < 1e-5
+
+
+def _stt_spiral(n, kc, alpha, xi, ny=1, along="x"):
+    """In-plane spiral on a ring periodic along the current, field terms
+    off: only the Zhang-Li torque acts."""
+    dx = 3e-9
+    q = 2 * np.pi * kc / (n * dx)
+    th = q * np.arange(n) * dx
+    if along == "x":
+        m0 = np.stack([np.cos(th), np.sin(th), np.zeros(n)])[:, None, None, :].repeat(ny, axis=2)
+        prob = dict(n=(n, ny, 1), pbc=(True, False, False), j=(1e12, 0.0, 0.0))
+    else:
+        m0 = np.stack([np.cos(th), np.sin(th), np.zeros(n)])[:, None, :, None].repeat(ny, axis=3)
+        prob = dict(n=(ny, n, 1), pbc=(False, True, False), j=(0.0, 1e12, 0.0))
+    prob.update(cell=(dx, dx, dx), Ms=8e5, Aex=1.3e-11, alpha=alpha, terms=(), P=0.6, xi=xi, T=0.0,
+                seed=0, images=0)
+    return prob, m0.astype(np.float32)
+
+
+@pytest.mark.parametrize("along", ["x", "y"])
+def test_stt_adiabatic_spiral_on_gpu(lib, impl, along):
+    """Eq. 7 with xi = alpha and no field: the spiral turns rigidly; the GPU
+    trajectory follows the oracle's (which is pinned to the closed form)."""
+    # along x: 64 x 32 cells (compiled lengths, periodic rows); along y: 4 x 32
+    prob, m0 = _stt_spiral(64 if along == "x" else 32, 2, 0.1, 0.1, ny=32 if along == "x" else 4, along=along)
+    s = make_solver(lib, prob, m0)
+    o = ollg.Solver(prob, m0)
+    s.step("rk4", 1e-13, 100)
+    o.step("rk4", 1e-13, 100)
+    e = maxrel(s.get_m(), o.m)
+    note("stt adiabatic", along, e)
+    assert e <= 1e-5
+
+
+def test_stt_with_fields_parity(lib, impl):
+    """The torque with every field term on, a non-adiabatic current at an
+    angle and free edges (one-sided differences there): fixed steps against
+    the oracle."""
+    prob, m0 = workloads.small_problem(n=(64, 32, 1), alpha=0.3)
+    prob.update(j=(8e11, -5e11, 0.0), P=0.7, xi=0.05)
+    s = make_solver(lib, prob, m0)
+    o = ollg.Solver(prob, m0)
+    for _ in range(3):
+        s.step("rk4", 2e-14, 20)
+        o.step("rk4", 2e-14, 20)
+        e = maxrel(s.get_m(), o.m)
+        note("stt fields", e)
+        assert e <= 1e-5
+
+
+def test_stt_uniform_state_on_gpu(lib):
+    """A uniform state has no gradient: the current changes nothing."""
+    prob, _ = workloads.small_problem(n=(16, 12, 1), alpha=0.2)
+    m0 = workloads.uniform((16, 12, 1), (0.6, 0.0, 0.8))
+    prob["terms"] = ()
+    a = make_solver(lib, prob, m0)
+    a.step("heun", 1e-13, 10)
+    prob.update(j=(1e12, 3e11, 0.0), P=0.6, xi=0.05)
+    b = make_solver(lib, prob, m0)
+    b.step("heun", 1e-13, 10)
+    assert np.array_equal(a.get_m(), b.get_m())
+
+
 def test_heff_parity_film_32(lib, impl):
     prob, m0, _ = workloads.film_32()
     s = make_solver(lib, prob, m0)

@@ -355,3 +355,83 @@ def test_controller_exponent_follows_the_pair():
     # err = tol * 2^(q+1): the next step halves (times the 0.9 safety factor)
     for q in (1, 2, 4):
         assert llg.Solver.next_dt(1.0, 2.0 ** (q + 1), 1.0, q) == pytest.approx(0.45)
+
+
+def _cubic_macrospin(K1, tilt, axis_kind):
+    """One cubic cell with cubic anisotropy along rotated axes and strong
+    damping, started `tilt` rad away from an easy axis."""
+    rng = np.random.default_rng(11)
+    q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    c1, c2 = q[:, 0], q[:, 1]
+    c3 = np.cross(c1, c2)
+    easy = c1 if axis_kind == "100" else (c1 + c2 + c3) / math.sqrt(3.0)
+    perp = np.cross(easy, rng.standard_normal(3))
+    perp /= np.linalg.norm(perp)
+    m0 = (math.cos(tilt) * easy + math.sin(tilt) * perp).reshape(3, 1, 1, 1)
+    prob = dict(n=(1, 1, 1), cell=(5e-9,) * 3, pbc=(False,) * 3, Ms=8e5, Aex=1.3e-11, alpha=1.0,
+                Ku=0.0, Kc1=K1, Kc2=0.0, c1=tuple(c1), c2=tuple(c2), B=(0.0, 0.0, 0.0), T=0.0, seed=0)
+    return prob, m0, easy
+
+
+@pytest.mark.parametrize("K1,kind", [(5e5, "100"), (-5e5, "111")])
+def test_cubic_macrospin_relaxes_to_the_easy_axis(K1, kind):
+    """Eq. 5: with K1 > 0 the easy axes are the cube axes c_i, with K1 < 0
+    the body diagonals; a strongly damped single cell (isotropic self-demag,
+    no other torque) relaxes onto the nearest one."""
+    prob, m0, easy = _cubic_macrospin(K1, 0.4, kind)
+    s = llg.Solver(prob, m0)
+    s.step("rk4", 1e-13, 3000)
+    np.testing.assert_allclose(s.m[:, 0, 0, 0], easy, atol=1e-6)
+
+
+# --------------------------------------------------------------------------
+# Zhang-Li spin-transfer torque (Eq. 7-8)
+# --------------------------------------------------------------------------
+MU_B, E_CHARGE = 9.2740100783e-24, 1.602176634e-19   # CODATA values
+
+
+def _spiral(n, k_cells, xi, alpha, j=1e12, P=0.6):
+    """In-plane spiral m = (cos q x, sin q x, 0), q = 2 pi k / (n dx), on a
+    ring periodic in x, with no field term at all: only the current acts."""
+    dx = 3e-9
+    x = np.arange(n) * dx
+    q = 2 * math.pi * k_cells / (n * dx)
+    m0 = np.stack([np.cos(q * x), np.sin(q * x), np.zeros(n)]).reshape(3, 1, 1, n)
+    prob = dict(n=(n, 1, 1), cell=(dx, dx, dx), pbc=(True, False, False), Ms=8e5, Aex=1.3e-11,
+                alpha=alpha, terms=(), j=(j, 0.0, 0.0), P=P, xi=xi, T=0.0, seed=0)
+    return prob, m0, q, dx
+
+
+def test_stt_uniform_state_is_left_alone():
+    prob, _, _, _ = _spiral(16, 1, 0.05, 0.1)
+    m = workloads.uniform((16, 1, 1), (0.3, -0.5, 0.8)).astype(np.float64)
+    assert np.max(np.abs(llg.stt_rhs(m, prob))) == 0.0
+
+
+def test_stt_initial_rate_on_a_spiral():
+    """dm/dt = b_j s / (1 + alpha^2) [e_theta - (xi - alpha) z] with
+    s = j sin(q dx) / dx, the discrete central difference of the spiral."""
+    alpha, xi, P, j = 0.1, 0.05, 0.6, 1e12
+    prob, m0, q, dx = _spiral(24, 2, xi, alpha, j, P)
+    bj = P * MU_B / (E_CHARGE * prob["Ms"] * (1 + xi * xi))
+    s = j * math.sin(q * dx) / dx
+    th = q * np.arange(24) * dx
+    want = bj * s / (1 + alpha ** 2) * np.stack([-np.sin(th), np.cos(th), -(xi - alpha) * np.ones(24)])
+    np.testing.assert_allclose(llg.stt_rhs(m0, prob).reshape(3, -1), want, rtol=1e-12,
+                               atol=1e-12 * np.max(np.abs(want)))
+
+
+def test_stt_adiabatic_spiral_rotates_rigidly():
+    """With xi = alpha the spiral stays a spiral and every cell turns at the
+    rate b_j s / (1 + alpha^2) (the discrete form of the rigid drift)."""
+    alpha = xi = 0.1
+    P, j, n = 0.6, 1e12, 24
+    prob, m0, q, dx = _spiral(n, 2, xi, alpha, j, P)
+    bj = P * MU_B / (E_CHARGE * prob["Ms"] * (1 + xi * xi))
+    w = bj * j * math.sin(q * dx) / dx / (1 + alpha ** 2)
+    o = llg.Solver(prob, m0)
+    t = 2e-11
+    o.step("rk4", 1e-13, 200)
+    th = q * np.arange(n) * dx + w * t
+    want = np.stack([np.cos(th), np.sin(th), np.zeros(n)])
+    np.testing.assert_allclose(o.m.reshape(3, -1), want, atol=1e-9)
