@@ -218,11 +218,19 @@ llg_status build_launch_args(llg_batch* b) {
                 const int nb = row ? f.row_blocks : f.col_blocks;
                 for (int j = 0; j < nb; ++j) map.push_back(make_int2(i, j));
             }
+            // XCD-aware order: hardware block h runs entry remap(h), so the
+            // blocks one XCD runs are contiguous rows or columns of a film
+            const int nb = (int)map.size();
+            std::vector<int2> order(nb);
+            for (int h = 0; h < nb; ++h) {
+                const int X = 8, x = h % X, i = h / X, q = nb / X, rmd = nb % X;
+                order[h] = map[x * q + std::min(x, rmd) + i];
+            }
             llg_batch::Class c;
             c.len = k.first;
             c.var = k.second;
-            c.nblocks = (int)map.size();
-            BCHK(b, upload(&c.map, map));
+            c.nblocks = nb;
+            BCHK(b, upload(&c.map, order));
             out.push_back(c);
         }
         return LLG_OK;

@@ -79,18 +79,24 @@ struct RowSplit {
     static_assert(NG * P == FRT, "row blocks have FRT threads");
     static constexpr int SC = LfScratch<H>::size;
     using F = LaneFFT<H, E2, 2, float2>;
-    // LDS (bytes): twiddles W^m (m < PX); FFT scratch, aliased by the
-    // exchange of the inverse transforms; staged m rows (with the y
+    // LDS (bytes): twiddles W^m (m < PX); FFT scratch; the exchange of the
+    // inverse transforms (inverse kernel only); staged m rows (with the y
     // neighbours); new m rows; reduction slots
     static constexpr int O_TW = 0;
     static constexpr int O_SCR = lds_align(PX * 8);
     static constexpr int SCR_BYTES = NG * SC * 8;
-    static_assert(NG * H * 8 <= SCR_BYTES, "the exchange fits the scratch");
-    static constexpr int O_M = lds_align(O_SCR + SCR_BYTES);
+    static constexpr int O_M = lds_align(O_SCR + SCR_BYTES);   // forward kernel: no exchange
     static constexpr int NR = 2 * RP + 2;
+    // the exchange gets its own region unless that would not fit the LDS
+    // (then it aliases the scratch, behind one more barrier)
+    static constexpr int SEP_BYTES = lds_align(O_M + NG * H * 8) + (NR + 2 * RP) * 3 * PX * 4 + 32;
+    static constexpr bool XALIAS = SEP_BYTES > 160 * 1024;
+    static constexpr int O_XCH = XALIAS ? O_SCR : O_M;
+    static_assert(NG * H * 8 <= SCR_BYTES, "the exchange fits the scratch");
+    static constexpr int O_MI = XALIAS ? O_M : lds_align(O_M + NG * H * 8);
     template <bool XPER> static constexpr int nxm() { return XPER ? PX : H; }
     template <bool XPER> static constexpr int fwd_bytes() { return lds_align(O_M + 2 * RP * 3 * nxm<XPER>() * 4); }
-    template <bool XPER> static constexpr int o_nm() { return lds_align(O_M + NR * 3 * nxm<XPER>() * 4); }
+    template <bool XPER> static constexpr int o_nm() { return lds_align(O_MI + NR * 3 * nxm<XPER>() * 4); }
     template <bool XPER> static constexpr int o_wmax() { return lds_align(o_nm<XPER>() + 2 * RP * 3 * nxm<XPER>() * 4); }
     template <bool XPER> static constexpr int inv_bytes() { return lds_align(o_wmax<XPER>() + 8 * 4); }
 
@@ -215,7 +221,7 @@ __global__ __launch_bounds__(FRT) void row_fwd_fast(Grid g, const float2* __rest
                                                     float2* __restrict__ S, FwdArgs fa,
                                                     DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
-    row_fwd_body<PX, E2, XPER>(g, twx, S, fa, st, blockIdx.x, dyn_lds);
+    row_fwd_body<PX, E2, XPER>(g, twx, S, fa, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
 }
 
 // exchange + anisotropy + applied + thermal field of cell x of a row whose
@@ -266,8 +272,8 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     constexpr int NXM = R::template nxm<XPER>();
     float2* tw = (float2*)(lds + R::O_TW);
     float2* scr = (float2*)(lds + R::O_SCR);
-    float2* xch = scr;                               // aliases the scratch after the transforms
-    float* mrow = (float*)(lds + R::O_M);
+    float2* xch = (float2*)(lds + R::O_XCH);
+    float* mrow = (float*)(lds + R::O_MI);
     float* nm = (float*)(lds + R::template o_nm<XPER>());
     float* wmax = (float*)(lds + R::template o_wmax<XPER>());
     if (st->done) return;
@@ -339,9 +345,36 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             z[i] = mk2(A.x - B.y, A.y + B.x);
         }
     }
+    // ---- the parts of the stage combination that do not depend on this
+    // stage's k: m0 + dtau sum_{j<s} a_j k_j and sum_{j<s} e_j k_j, for the
+    // cells this thread will handle, loaded while the transforms run
+    constexpr int MAXIT = (2 * RP * NXM + FRT - 1) / FRT;
+    const int nrow = min(2 * RP, g.nrows - rb);
+    const int ncb = nrow * nx;
+    const float rnx = 1.0f / (float)nx;
+    float px_[MAXIT], py_[MAXIT], pz_[MAXIT], ex_[MAXIT], ey_[MAXIT], ez_[MAXIT];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        px_[it] = py_[it] = pz_[it] = ex_[it] = ey_[it] = ez_[it] = 0.f;
+        const int e = tid + it * FRT;
+        if (e >= ncb || !(stage || errm)) continue;
+        int ri, x;
+        split_cell(e, nx, rnx, ri, x);
+        const int qq = (rb + ri) * nx + x;
+        if (stage) { px_[it] = m0[qq]; py_[it] = m0[cs + qq]; pz_[it] = m0[2 * cs + qq]; }
+        for (int j = 0; j + 1 < sa.nk; ++j) {
+            const float ca = stage ? dtau * sa.a[j] : 0.f;
+            const float ce = errm ? sa.e[j] : 0.f;
+            if (ca == 0.f && ce == 0.f) continue;
+            const float* __restrict__ kj = resolve(sa.kprev[j], cur);
+            const float vx = kj[qq], vy = kj[cs + qq], vz = kj[2 * cs + qq];
+            if (ca != 0.f) { px_[it] += ca * vx; py_[it] += ca * vy; pz_[it] += ca * vz; }
+            if (ce != 0.f) { ex_[it] += ce * vx; ey_[it] += ce * vy; ez_[it] += ce * vz; }
+        }
+    }
     __syncthreads();   // twiddles and staged rows
     if (p.demag_on) F::template run<true>(z, scr + gi * R::SC, tw, lg);
-    __syncthreads();   // every transform has left the scratch
+    if constexpr (R::XALIAS) __syncthreads();   // every transform has left the scratch
     if (p.demag_on) {
         float2* xo = xch + (((pair * 3 + kind) * 2) + half) * H;
 #pragma unroll
@@ -353,11 +386,12 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     __syncthreads();
 
     // ---- per cell: field, torque, stage combination
-    const int nrow = min(2 * RP, g.nrows - rb);
-    const float rnx = 1.0f / (float)nx;
     float errmax = 0.f;
     bool bad = false;
-    for (int e = tid; e < nrow * nx; e += FRT) {
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int e = tid + it * FRT;
+        if (e >= ncb) continue;
         int ri, x;
         split_cell(e, nx, rnx, ri, x);
         const int pr = ri >> 1, rr = ri & 1;
@@ -415,20 +449,11 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         float ax = 0.f, ay = 0.f, az = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
         if (stage) {
             const float c = dtau * sa.a[sa.nk - 1];
-            ax = c * kx + m0[qq]; ay = c * ky + m0[cs + qq]; az = c * kz + m0[2 * cs + qq];
+            ax = px_[it] + c * kx; ay = py_[it] + c * ky; az = pz_[it] + c * kz;
         }
         if (errm) {
             const float c = sa.e[sa.nk - 1];
-            ex = c * kx; ey = c * ky; ez = c * kz;
-        }
-        for (int j = 0; j + 1 < sa.nk; ++j) {
-            const float ca = stage ? dtau * sa.a[j] : 0.f;
-            const float ce = errm ? sa.e[j] : 0.f;
-            if (ca == 0.f && ce == 0.f) continue;
-            const float* __restrict__ kj = resolve(sa.kprev[j], cur);
-            const float vx = kj[qq], vy = kj[cs + qq], vz = kj[2 * cs + qq];
-            if (ca != 0.f) { ax += ca * vx; ay += ca * vy; az += ca * vz; }
-            if (ce != 0.f) { ex += ce * vx; ey += ce * vy; ez += ce * vz; }
+            ex = ex_[it] + c * kx; ey = ey_[it] + c * ky; ez = ez_[it] + c * kz;
         }
         if (stage) {
             const float inv = rsqrtf(ax * ax + ay * ay + az * az);
@@ -462,7 +487,7 @@ __global__ __launch_bounds__(FRT) void row_inv_fast(Grid g, Phys p, const float2
                                                     float2* __restrict__ S, StageArgs sa,
                                                     DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
-    row_inv_body<PX, E2, XPER>(g, p, twx, S, sa, st, blockIdx.x, dyn_lds);
+    row_inv_body<PX, E2, XPER>(g, p, twx, S, sa, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -483,10 +508,14 @@ struct ColSplit {
     static constexpr int NG = 6 * W;
     static constexpr int SC = LfScratch<L>::size;
     using F = LaneFFT<L, E, 2, float2>;
+    // LDS (bytes): twiddles, FFT scratch, the x/y spectrum exchange, the
+    // odd halves' inverse results (separate regions: no barrier is needed
+    // to free one before the next use)
     static constexpr int O_TW = 0;
     static constexpr int O_SCR = lds_align(2 * L * 8);
-    static_assert(4 * W * L <= NG * SC && 3 * W * L <= NG * SC, "exchanges fit the scratch");
-    static constexpr int bytes() { return lds_align(O_SCR + NG * SC * 8); }
+    static constexpr int O_XCH = lds_align(O_SCR + NG * SC * 8);
+    static constexpr int O_COMB = lds_align(O_XCH + 4 * W * L * 8);
+    static constexpr int bytes() { return lds_align(O_COMB + 3 * W * L * 8); }
 };
 
 template <int L, int E>
@@ -496,7 +525,8 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     constexpr int P = CF::P, W = CF::W;
     float2* tw = (float2*)(lds + CF::O_TW);
     float2* scr = (float2*)(lds + CF::O_SCR);
-    float2* xch = scr;                   // aliases the scratch between transforms
+    float2* xch = (float2*)(lds + CF::O_XCH);
+    float2* cmb = (float2*)(lds + CF::O_COMB);
     if (st->done) return;
     const int tid = threadIdx.x;
     const int gi = tid / P, lg = tid % P;
@@ -543,7 +573,6 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
         for (int i = 0; i < E; ++i) x[i] = cmul(x[i], tw[lg + P * i]);
     }
     F::template run<false>(x, scr + gi * CF::SC, tw, lg);
-    __syncthreads();   // scratch free
     // x and y spectra of every (half, column) to LDS
     if (c < 2) {
         float2* xo = xch + ((c * 2 + h) * W + w) * L;
@@ -557,7 +586,6 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
 #pragma unroll
         for (int i = 0; i < E; ++i) q[i] = xp[lg + P * i];
     }
-    __syncthreads();   // exchange read, scratch reused below
     if (!packed) {
         // H_x = Kxx M_x + Kxy M_y, H_y = Kxy M_x + Kyy M_y, H_z = Kzz M_z
         if (c < 2) {
@@ -588,8 +616,7 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
         }
     }
     F::template run<true>(x, scr + gi * CF::SC, tw, lg);
-    __syncthreads();   // scratch free
-    float2* comb = xch + (c * W + w) * L;
+    float2* comb = cmb + (c * W + w) * L;
     if (h == 1) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
