@@ -120,6 +120,7 @@ Col2dArgs col_args(const BatchFilm& f) {
     c.nkx_full = f.g.nkx;
     c.nkxp = f.g.nkxp;
     c.tsh = f.g.tsh;
+    c.nq = fast2d_row_classes(f.g.Px, f.rvar);
     c.ny = f.g.ny;
     c.Py = f.g.Py;
     return c;

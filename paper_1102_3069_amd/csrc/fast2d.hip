@@ -25,7 +25,7 @@ namespace llg {
 
 namespace {
 
-constexpr int FRT = 384;   // threads of a fast row block (six wavefronts)
+constexpr int kRowThreads = 768;   // launch bound of the row kernels (at most twelve wavefronts)
 
 __device__ __forceinline__ float2 mk2(float x, float y) { float2 r; r.x = x; r.y = y; return r; }
 
@@ -44,18 +44,20 @@ __device__ __forceinline__ float2 partner_odd(const float2 (&z)[E], int i, int l
 }
 
 // ---------------------------------------------------------------------------
-// rows: every length-PX row transform is split into its even- and
-// odd-frequency halves of length H = PX/2, each computed by its own lane
-// group, so a row pair occupies six groups: (mx + i my of the first row,
-// of the second row, mz of the first + i mz of the second) x (even, odd).
-//   forward:  X[2j]   = FFT_H(a_n + a_{n+H})
-//             X[2j+1] = FFT_H((a_n - a_{n+H}) W^n)     (a_{n+H} = 0 unless x is periodic)
-//   inverse:  x_n     = IFFT_H(X[2j])[n] + W^-n IFFT_H(X[2j+1])[n]
-//             x_{n+H} = IFFT_H(X[2j])[n] - W^-n IFFT_H(X[2j+1])[n]
-// with W = exp(-2 pi i / PX).  Spectrum columns are stored in the order
-// col = h * PX/4 + j  <->  kx = 2j + h (h = 0 even, 1 odd), kx < PX/2.
-// The per-cell work (fields, torque, stage combination) is spread over all
-// threads of the block, cell by cell in row order.
+// rows: every length-PX row transform is split into NQ frequency classes
+// (NQ = 2 or 4) of length LQ = PX/NQ, each computed by its own lane group,
+// so a row pair occupies 3 NQ groups: (mx + i my of the first row, of the
+// second row, mz of the first + i mz of the second) x (class q).  With
+// W = exp(-2 pi i / PX) and w = exp(-2 pi i / NQ):
+//   forward:  X[NQ j + q] = FFT_LQ( W^{nq} sum_r w^{rq} a_{n + r LQ} )[j]
+//             (a_{n + r LQ} = 0 for r >= NQ/2 unless x is periodic)
+//   inverse:  x_{n + r LQ} = sum_q w^{-rq} W^{-nq} IFFT_LQ(X[NQ j + q])[n]
+// Spectrum columns kx < PX/2 are stored in the order col = q QC + j <->
+// kx = NQ j + q, QC = PX/(2 NQ).  The Hermitian partner X[PX - k] of class q
+// lies in class (NQ - q) mod NQ: within the group for q = 0 and q = NQ/2,
+// in the partner group (through LDS) otherwise.  The per-cell work (fields,
+// torque, stage combination) is spread over all threads of the block, cell
+// by cell in row order.
 // ---------------------------------------------------------------------------
 constexpr int lds_align(int b) { return (b + 15) / 16 * 16; }
 
@@ -69,16 +71,29 @@ __device__ __forceinline__ void split_cell(int e, int nx, float rnx, int& ri, in
     else if (x < 0) { --ri; x += nx; }
 }
 
-template <int PX, int E2>
+// a * exp(-2 pi i m / 4) (m taken mod 4)
+__device__ __forceinline__ float2 rot4(float2 a, int m) {
+    switch (m & 3) {
+        case 0: return a;
+        case 1: return mk2(a.y, -a.x);
+        case 2: return mk2(-a.x, -a.y);
+        default: return mk2(-a.y, a.x);
+    }
+}
+
+template <int PX, int E2, int NQ>
 struct RowSplit {
-    static constexpr int H = PX / 2;
-    static constexpr int P = H / E2;               // lanes per half transform
+    static_assert(NQ == 2 || NQ == 4, "two or four frequency classes");
+    static constexpr int LQ = PX / NQ;             // length of a class transform
+    static constexpr int H = PX / 2;               // largest open-axis row length
+    static constexpr int P = LQ / E2;              // lanes per class transform
     static constexpr int RP = 64 / P;              // row pairs per block
-    static constexpr int NG = 6 * RP;              // lane groups per block
-    static constexpr int Q = PX / 4;               // stored columns per half
-    static_assert(NG * P == FRT, "row blocks have FRT threads");
-    static constexpr int SC = LfScratch<H>::size;
-    using F = LaneFFT<H, E2, 2, float2>;
+    static constexpr int NG = 3 * NQ * RP;         // lane groups per block
+    static constexpr int NT = NG * P;              // threads per block
+    static constexpr int QC = PX / (2 * NQ);       // stored columns per class
+    static_assert(NT <= kRowThreads, "row blocks fit the launch bound");
+    static constexpr int SC = LfScratch<LQ>::size;
+    using F = LaneFFT<LQ, E2, NQ, float2>;
     // LDS (bytes): twiddles W^m (m < PX); FFT scratch; the exchange of the
     // inverse transforms (inverse kernel only); staged m rows (with the y
     // neighbours); new m rows; reduction slots
@@ -89,31 +104,33 @@ struct RowSplit {
     static constexpr int NR = 2 * RP + 2;
     // the exchange gets its own region unless that would not fit the LDS
     // (then it aliases the scratch, behind one more barrier)
-    static constexpr int SEP_BYTES = lds_align(O_M + NG * H * 8) + (NR + 2 * RP) * 3 * PX * 4 + 32;
+    static constexpr int SEP_BYTES = lds_align(O_M + NG * LQ * 8) + (NR + 2 * RP) * 3 * PX * 4 + 64;
     static constexpr bool XALIAS = SEP_BYTES > 160 * 1024;
     static constexpr int O_XCH = XALIAS ? O_SCR : O_M;
-    static_assert(NG * H * 8 <= SCR_BYTES, "the exchange fits the scratch");
-    static constexpr int O_MI = XALIAS ? O_M : lds_align(O_M + NG * H * 8);
+    static_assert(NG * LQ * 8 <= SCR_BYTES, "the exchange fits the scratch");
+    static constexpr int O_MI = XALIAS ? O_M : lds_align(O_M + NG * LQ * 8);
     template <bool XPER> static constexpr int nxm() { return XPER ? PX : H; }
     template <bool XPER> static constexpr int fwd_bytes() { return lds_align(O_M + 2 * RP * 3 * nxm<XPER>() * 4); }
     template <bool XPER> static constexpr int o_nm() { return lds_align(O_MI + NR * 3 * nxm<XPER>() * 4); }
     template <bool XPER> static constexpr int o_wmax() { return lds_align(o_nm<XPER>() + 2 * RP * 3 * nxm<XPER>() * 4); }
-    template <bool XPER> static constexpr int inv_bytes() { return lds_align(o_wmax<XPER>() + 8 * 4); }
+    template <bool XPER> static constexpr int inv_bytes() { return lds_align(o_wmax<XPER>() + 16 * 4); }
 
-    // group gi -> (kind, half, pair), the pair fastest: the groups of one
-    // wavefront share kind and half
-    static __device__ __forceinline__ void group(int gi, int& kind, int& half, int& pair) {
+    // group gi -> (kind, class, pair), the pair fastest: the groups of one
+    // wavefront share kind and class
+    static __device__ __forceinline__ void group(int gi, int& kind, int& q, int& pair) {
         pair = gi % RP;
-        const int kh = gi / RP;
-        half = kh & 1;
-        kind = kh >> 1;
+        const int kq = gi / RP;
+        q = kq % NQ;
+        kind = kq / NQ;
     }
+    static __device__ __forceinline__ int group_of(int kind, int q, int pair) { return (kind * NQ + q) * RP + pair; }
 
     // forward transform of the block's rows, whose magnetisation sits in LDS
-    // nm[row][c][x] (row stride 3 NXM), and store of the columns kx < PX/2
+    // nm[row][c][x] (row stride 3 NXM), and store of the columns kx < PX/2;
+    // scr is the block's scratch (every group calls this)
     template <int NXM>
     static __device__ __forceinline__ void forward(const Grid& g, float2* __restrict__ S, float2* scr,
-                                                   const float2* tw, const float* nm, int kind, int half,
+                                                   const float2* tw, const float* nm, int kind, int q,
                                                    int pair, int lg, int gbase, int rb) {
         const int nx = g.nx;
         const int r0 = rb + 2 * pair;
@@ -127,34 +144,49 @@ struct RowSplit {
             if (kind < 2) return va ? mk2(ra[n], ra[NXM + n]) : mk2(0.f, 0.f);
             return mk2(v0 ? rz0[n] : 0.f, v1 ? rz1[n] : 0.f);
         };
+        constexpr int NRIN = NXM == PX ? NQ : NQ / 2;    // nonzero input blocks of length LQ
         float2 z[E2];
 #pragma unroll
         for (int i = 0; i < E2; ++i) {
             const int n = lg + P * i;
-            float2 a = at(n);
-            if (NXM == PX) {
-                const float2 b = at(n + H);
-                a = half ? mk2(a.x - b.x, a.y - b.y) : mk2(a.x + b.x, a.y + b.y);
+            float2 acc = at(n);
+#pragma unroll
+            for (int r = 1; r < NRIN; ++r) {
+                const float2 v = rot4(at(n + r * LQ), (r * q * (4 / NQ)));
+                acc.x += v.x; acc.y += v.y;
             }
-            z[i] = half ? cmul(a, tw[n]) : a;
+            z[i] = q ? cmul(acc, tw[n * q]) : acc;
         }
-        F::template run<false>(z, scr, tw, lg);
+        float2* own = scr + group_of(kind, q, pair) * SC;
+        F::template run<false>(z, own, tw, lg);
+        // partners in another class go through LDS (four classes only)
+        const float2* pz = nullptr;
+        if constexpr (NQ == 4) {
+            __syncthreads();   // every class transform has left the scratch
+#pragma unroll
+            for (int i = 0; i < E2; ++i) own[lg + P * i] = z[i];
+            __syncthreads();
+            pz = scr + group_of(kind, (NQ - q) % NQ, pair) * SC;
+        }
         const int cs = g.nrows * g.nkxp;
-        const float2 zN = z[E2 / 2];   // X[PX/2]: even half, lane 0
+        const float2 zN = z[E2 / 2];   // X[PX/2]: class 0, lane 0
         float2* s0 = S + (r0 << g.tsh);
         float2* s1 = s0 + (1 << g.tsh);
 #pragma unroll
         for (int i = 0; i < E2 / 2; ++i) {
             const int j = lg + P * i;
             const float2 zk = z[i];
-            const float2 zm = half ? partner_odd<E2, P>(z, i, lg, gbase) : partner_mirror<E2, P>(z, i, lg, gbase);
+            float2 zm;
+            if (q == 0) zm = partner_mirror<E2, P>(z, i, lg, gbase);
+            else if (2 * q == NQ) zm = partner_odd<E2, P>(z, i, lg, gbase);
+            else zm = pz[LQ - 1 - j];
             float2 A = mk2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
             float2 B = mk2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-            if (half == 0 && j == 0) {   // pack the real DC and Nyquist coefficients
+            if (q == 0 && j == 0) {   // pack the real DC and Nyquist coefficients
                 A = mk2(zk.x, zN.x);
                 B = mk2(zk.y, zN.y);
             }
-            const int col = tile_index(0, half * Q + j, g.nrows, g.tsh);
+            const int col = tile_index(0, q * QC + j, g.nrows, g.tsh);
             if (kind == 0) {
                 if (v0) { s0[col] = A; s0[cs + col] = B; }
             } else if (kind == 1) {
@@ -167,23 +199,24 @@ struct RowSplit {
     }
 };
 
-template <int PX, int E2, bool XPER>
+template <int PX, int E2, int NQ, bool XPER>
 __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __restrict__ twx,
                                              float2* __restrict__ S, const FwdArgs& fa,
                                              DevState* __restrict__ st, int blk, char* lds) {
-    using R = RowSplit<PX, E2>;
+    using R = RowSplit<PX, E2, NQ>;
     constexpr int NXM = R::template nxm<XPER>();
+    constexpr int NT = R::NT;
     float2* tw = (float2*)(lds + R::O_TW);
     float2* scr = (float2*)(lds + R::O_SCR);
     float* nm = (float*)(lds + R::O_M);
     if (st->done) return;
     const int tid = threadIdx.x;
     const int gi = tid / R::P, lg = tid % R::P;
-    int kind, half, pair;
-    R::group(gi, kind, half, pair);
+    int kind, q, pair;
+    R::group(gi, kind, q, pair);
     const int gbase = (tid & 63) - lg;
     const int rb = 2 * R::RP * blk;
-    for (int m = tid; m < PX; m += FRT) tw[m] = twx[m];
+    for (int m = tid; m < PX; m += NT) tw[m] = twx[m];
     const int cur = st->cur;
     const float c1 = st->dtau * fa.a1;
     const int cs = g.ncells;
@@ -194,34 +227,34 @@ __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __rest
     const int nx = g.nx;
     const float rnx = 1.0f / (float)nx;
     const int nrow = min(2 * R::RP, g.nrows - rb);
-    for (int e = tid; e < nrow * nx; e += FRT) {
+    for (int e = tid; e < nrow * nx; e += NT) {
         int ri, x;
         split_cell(e, nx, rnx, ri, x);
-        const int q = (rb + ri) * nx + x;
+        const int qq = (rb + ri) * nx + x;
         float ax, ay, az;
         if (fa.combine) {
-            ax = m0[q] + c1 * k1[q];
-            ay = m0[cs + q] + c1 * k1[cs + q];
-            az = m0[2 * cs + q] + c1 * k1[2 * cs + q];
+            ax = m0[qq] + c1 * k1[qq];
+            ay = m0[cs + qq] + c1 * k1[cs + qq];
+            az = m0[2 * cs + qq] + c1 * k1[2 * cs + qq];
             const float inv = rsqrtf(ax * ax + ay * ay + az * az);
             ax *= inv; ay *= inv; az *= inv;
-            mo[q] = ax; mo[cs + q] = ay; mo[2 * cs + q] = az;
+            mo[qq] = ax; mo[cs + qq] = ay; mo[2 * cs + qq] = az;
         } else {
-            ax = mi[q]; ay = mi[cs + q]; az = mi[2 * cs + q];
+            ax = mi[qq]; ay = mi[cs + qq]; az = mi[2 * cs + qq];
         }
         float* row = nm + ri * 3 * NXM;
         row[x] = ax; row[NXM + x] = ay; row[2 * NXM + x] = az;
     }
     __syncthreads();
-    R::template forward<NXM>(g, S, scr + gi * R::SC, tw, nm, kind, half, pair, lg, gbase, rb);
+    R::template forward<NXM>(g, S, scr, tw, nm, kind, q, pair, lg, gbase, rb);
 }
 
-template <int PX, int E2, bool XPER>
-__global__ __launch_bounds__(FRT) void row_fwd_fast(Grid g, const float2* __restrict__ twx,
-                                                    float2* __restrict__ S, FwdArgs fa,
-                                                    DevState* __restrict__ st) {
+template <int PX, int E2, int NQ, bool XPER>
+__global__ __launch_bounds__(kRowThreads) void row_fwd_fast(Grid g, const float2* __restrict__ twx,
+                                                            float2* __restrict__ S, FwdArgs fa,
+                                                            DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
-    row_fwd_body<PX, E2, XPER>(g, twx, S, fa, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
+    row_fwd_body<PX, E2, NQ, XPER>(g, twx, S, fa, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
 }
 
 // exchange + anisotropy + applied + thermal field of cell x of a row whose
@@ -262,13 +295,13 @@ __device__ __forceinline__ void local_field_lds(const Grid& g, const Phys& p, co
 }
 
 // XPER: the x axis is periodic (nx == PX), else nx <= PX/2
-template <int PX, int E2, bool XPER>
+template <int PX, int E2, int NQ, bool XPER>
 __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const float2* __restrict__ twx,
                                              float2* __restrict__ S, const StageArgs& sa,
                                              DevState* __restrict__ st, int blk, char* lds) {
-    using R = RowSplit<PX, E2>;
+    using R = RowSplit<PX, E2, NQ>;
     using F = typename R::F;
-    constexpr int P = R::P, RP = R::RP, H = R::H, Q = R::Q;
+    constexpr int P = R::P, RP = R::RP, LQ = R::LQ, QC = R::QC, NT = R::NT;
     constexpr int NXM = R::template nxm<XPER>();
     float2* tw = (float2*)(lds + R::O_TW);
     float2* scr = (float2*)(lds + R::O_SCR);
@@ -279,8 +312,8 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     if (st->done) return;
     const int tid = threadIdx.x;
     const int gi = tid / P, lg = tid % P;
-    int kind, half, pair;
-    R::group(gi, kind, half, pair);
+    int kind, q, pair;
+    R::group(gi, kind, q, pair);
     const int gbase = (tid & 63) - lg;
     const int rb = 2 * RP * blk;                     // first row of the block
     const int r0 = rb + 2 * pair;
@@ -298,15 +331,15 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     const bool errm = sa.mode == ROW_ERROR || (stage && sa.with_err);
 
     // ---- global reads: twiddles, m rows rb-1 .. rb+2RP (y neighbours wrap
-    // on a periodic y axis), this group's half spectrum
-    for (int m = tid; m < PX; m += FRT) tw[m] = twx[m];
-    for (int q = 0; q < R::NR; ++q) {
-        int row = rb - 1 + q;
+    // on a periodic y axis), this group's class of the spectrum
+    for (int m = tid; m < PX; m += NT) tw[m] = twx[m];
+    for (int rq = 0; rq < R::NR; ++rq) {
+        int row = rb - 1 + rq;
         bool ok = row >= 0 && row < g.nrows;
         if (g.pbc[1]) { row = row < 0 ? row + ny : (row >= ny ? row - ny : row); ok = true; }
         const float* src = mi + row * nx;
-        float* dst = mrow + q * 3 * NXM;
-        for (int t = tid; t < 3 * nx; t += FRT) {
+        float* dst = mrow + rq * 3 * NXM;
+        for (int t = tid; t < 3 * nx; t += NT) {
             const int c = t >= nx ? (t >= 2 * nx ? 2 : 1) : 0;
             const int x = t - c * nx;
             dst[c * NXM + x] = ok ? src[c * cs + x] : 0.f;
@@ -327,10 +360,11 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         }
 #pragma unroll
         for (int i = 0; i < E2; ++i) {
-            // X[k], k = 2j + half, from the stored columns kx < PX/2 and the
-            // Hermitian symmetry X[PX - k] = conj X[k] of a real row
+            // X[k], k = NQ j + q, from the stored columns kx < PX/2 and the
+            // Hermitian symmetry X[PX - k] = conj X[k] of a real row (class
+            // (NQ - q) mod NQ, index LQ - j for q = 0, LQ - 1 - j otherwise)
             const int j = lg + P * i;
-            const int k = 2 * j + half;
+            const int k = NQ * j + q;
             float2 A = mk2(0.f, 0.f), B = mk2(0.f, 0.f);
             if (k == 0 || k == PX / 2) {
                 const bool nyq = k != 0;
@@ -338,7 +372,8 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
                 if (sb_) { const float2 v = sb_[0]; B = mk2(nyq ? v.y : v.x, 0.f); }
             } else {
                 const bool up = k > PX / 2;
-                const int col = tile_index(0, half ? Q + (up ? H - 1 - j : j) : (up ? H - j : j), g.nrows, g.tsh);
+                const int sc = q == 0 ? (up ? LQ - j : j) : (up ? (NQ - q) * QC + LQ - 1 - j : q * QC + j);
+                const int col = tile_index(0, sc, g.nrows, g.tsh);
                 if (sa_) { A = sa_[col]; if (up) A.y = -A.y; }
                 if (sb_) { B = sb_[col]; if (up) B.y = -B.y; }
             }
@@ -348,7 +383,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     // ---- the parts of the stage combination that do not depend on this
     // stage's k: m0 + dtau sum_{j<s} a_j k_j and sum_{j<s} e_j k_j, for the
     // cells this thread will handle, loaded while the transforms run
-    constexpr int MAXIT = (2 * RP * NXM + FRT - 1) / FRT;
+    constexpr int MAXIT = (2 * RP * NXM + NT - 1) / NT;
     const int nrow = min(2 * RP, g.nrows - rb);
     const int ncb = nrow * nx;
     const float rnx = 1.0f / (float)nx;
@@ -356,7 +391,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
         px_[it] = py_[it] = pz_[it] = ex_[it] = ey_[it] = ez_[it] = 0.f;
-        const int e = tid + it * FRT;
+        const int e = tid + it * NT;
         if (e >= ncb || !(stage || errm)) continue;
         int ri, x;
         split_cell(e, nx, rnx, ri, x);
@@ -376,11 +411,11 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     if (p.demag_on) F::template run<true>(z, scr + gi * R::SC, tw, lg);
     if constexpr (R::XALIAS) __syncthreads();   // every transform has left the scratch
     if (p.demag_on) {
-        float2* xo = xch + (((pair * 3 + kind) * 2) + half) * H;
+        float2* xo = xch + ((pair * 3 + kind) * NQ + q) * LQ;
 #pragma unroll
         for (int i = 0; i < E2; ++i) {
             const int n = lg + P * i;
-            xo[n] = half ? cmul(z[i], cconj(tw[n])) : z[i];
+            xo[n] = q ? cmul(z[i], cconj(tw[n * q])) : z[i];
         }
     }
     __syncthreads();
@@ -390,7 +425,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     bool bad = false;
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
-        const int e = tid + it * FRT;
+        const int e = tid + it * NT;
         if (e >= ncb) continue;
         int ri, x;
         split_cell(e, nx, rnx, ri, x);
@@ -402,13 +437,20 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         const float* rp = (ny > 1 && (y < ny - 1 || g.pbc[1])) ? rc + 3 * NXM : nullptr;
         float hx = 0.f, hy = 0.f, hz = 0.f;
         if (p.demag_on) {
-            const int n = XPER ? (x < H ? x : x - H) : x;
-            const float2* xa = xch + ((pr * 3 + rr) * 2) * H;
-            const float2* xz = xch + ((pr * 3 + 2) * 2) * H;
-            float2 a = xa[n], b = xa[H + n], c = xz[n], d = xz[H + n];
-            if (XPER && x >= H) { b = mk2(-b.x, -b.y); d = mk2(-d.x, -d.y); }
-            hx = a.x + b.x; hy = a.y + b.y;
-            hz = rr ? c.y + d.y : c.x + d.x;
+            // x = n + r LQ: sum over the classes of w^{-rq} times the
+            // pre-twiddled class results
+            const int r = x / LQ, n = x - r * LQ;
+            const float2* xa = xch + ((pr * 3 + rr) * NQ) * LQ;
+            const float2* xz = xch + ((pr * 3 + 2) * NQ) * LQ;
+            float2 sa2 = xa[n], sz2 = xz[n];
+#pragma unroll
+            for (int cq = 1; cq < NQ; ++cq) {
+                const int m = -(r * cq * (4 / NQ));
+                const float2 u = rot4(xa[cq * LQ + n], m), v = rot4(xz[cq * LQ + n], m);
+                sa2.x += u.x; sa2.y += u.y; sz2.x += v.x; sz2.y += v.y;
+            }
+            hx = sa2.x; hy = sa2.y;
+            hz = rr ? sz2.y : sz2.x;
         }
         local_field_lds(g, p, rm, rc, rp, NXM, r, x, step, hx, hy, hz);
         const int qq = r * nx + x;
@@ -471,127 +513,134 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         __syncthreads();
         if (tid == 0) {
             float m = wmax[0];
-            for (int w = 1; w < FRT / 64; ++w) m = fmaxf(m, wmax[w]);
+            for (int w = 1; w < NT / 64; ++w) m = fmaxf(m, wmax[w]);
             atomicMax(&st->err_bits, __float_as_uint(m));
         }
         if (!stage) return;
     }
     if (stage && p.demag_on && !sa.skip_fwd) {
         __syncthreads();   // new rows complete, exchange no longer read
-        R::template forward<NXM>(g, S, scr + gi * R::SC, tw, nm, kind, half, pair, lg, gbase, rb);
+        R::template forward<NXM>(g, S, scr, tw, nm, kind, q, pair, lg, gbase, rb);
     }
 }
 
-template <int PX, int E2, bool XPER>
-__global__ __launch_bounds__(FRT) void row_inv_fast(Grid g, Phys p, const float2* __restrict__ twx,
-                                                    float2* __restrict__ S, StageArgs sa,
-                                                    DevState* __restrict__ st) {
+template <int PX, int E2, int NQ, bool XPER>
+__global__ __launch_bounds__(kRowThreads) void row_inv_fast(Grid g, Phys p, const float2* __restrict__ twx,
+                                                            float2* __restrict__ S, StageArgs sa,
+                                                            DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
-    row_inv_body<PX, E2, XPER>(g, p, twx, S, sa, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
+    row_inv_body<PX, E2, NQ, XPER>(g, p, twx, S, sa, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
 }
 
 // ---------------------------------------------------------------------------
 // columns (2D): y transform, product with the kernel spectrum, inverse.
-// The y axis is zero padded (Py = 2L), so every column transform is split
-// into its even and odd frequencies (length L each).  One lane group per
-// (component, half, column): the x and y groups of a column swap their
-// spectra through LDS for the off-diagonal xy term; after the inverse the
-// odd half adds W^-y times its result to the even half's, which stores.
+// The y axis is zero padded (Py = 2L, ny <= L), so every column transform
+// is split into NQ frequency classes of length LC = Py/NQ (class q holds
+// ky = NQ j + q), as the rows are.  One lane group per (component, class,
+// column): the x and y groups of a class swap their spectra through LDS
+// for the off-diagonal xy term, the packed column finds its Hermitian
+// partners (class (NQ - q) mod NQ) there too; after the inverse every class
+// leaves W^{-nq} times its result in LDS and the groups of the first NQ/2
+// classes each assemble and store one block of LC outputs.
 // ---------------------------------------------------------------------------
-constexpr int CT2 = 384;   // threads of a column block
+constexpr int kColThreads = 768;   // launch bound of the column kernels
 
-template <int L, int E>
+template <int L, int E, int NQ>
 struct ColSplit {
-    static constexpr int P = L / E;
-    static constexpr int W = CT2 / (6 * P);        // columns per block
-    static_assert(W >= 1 && W * 6 * P == CT2, "column blocks have CT2 threads");
-    static constexpr int NG = 6 * W;
-    static constexpr int SC = LfScratch<L>::size;
-    using F = LaneFFT<L, E, 2, float2>;
-    // LDS (bytes): twiddles, FFT scratch, the x/y spectrum exchange, the
-    // odd halves' inverse results (separate regions: no barrier is needed
-    // to free one before the next use)
+    static_assert(NQ == 2 || NQ == 4, "two or four frequency classes");
+    static constexpr int PY = 2 * L;
+    static constexpr int LC = PY / NQ;              // length of a class transform
+    static constexpr int P = LC / E;                // lanes per class transform
+    static constexpr int W = 64 / P;                // columns per block
+    static constexpr int NG = 3 * NQ * W;           // lane groups per block
+    static constexpr int NT = NG * P;               // threads per block
+    static_assert(W >= 1 && NT <= kColThreads, "column blocks fit the launch bound");
+    static constexpr int SC = LfScratch<LC>::size;
+    using F = LaneFFT<LC, E, NQ, float2>;
+    // LDS (bytes): twiddles, FFT scratch, the spectrum exchange (reused for
+    // the inverse results after a barrier)
     static constexpr int O_TW = 0;
-    static constexpr int O_SCR = lds_align(2 * L * 8);
+    static constexpr int O_SCR = lds_align(PY * 8);
     static constexpr int O_XCH = lds_align(O_SCR + NG * SC * 8);
-    static constexpr int O_COMB = lds_align(O_XCH + 4 * W * L * 8);
-    static constexpr int bytes() { return lds_align(O_COMB + 3 * W * L * 8); }
+    static constexpr int bytes() { return lds_align(O_XCH + NG * LC * 8); }
+    static __device__ __forceinline__ int slot(int c, int q, int w) { return (c * NQ + q) * W + w; }
 };
 
-template <int L, int E>
+template <int L, int E, int NQ>
 __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restrict__ st, int lb, char* lds) {
-    using CF = ColSplit<L, E>;
+    using CF = ColSplit<L, E, NQ>;
     using F = typename CF::F;
-    constexpr int P = CF::P, W = CF::W;
+    constexpr int P = CF::P, W = CF::W, LC = CF::LC, NT = CF::NT;
     float2* tw = (float2*)(lds + CF::O_TW);
     float2* scr = (float2*)(lds + CF::O_SCR);
     float2* xch = (float2*)(lds + CF::O_XCH);
-    float2* cmb = (float2*)(lds + CF::O_COMB);
     if (st->done) return;
     const int tid = threadIdx.x;
     const int gi = tid / P, lg = tid % P;
     const int w = gi % W;
-    const int h = (gi / W) & 1;          // frequency half
-    const int c = gi / (2 * W);          // component
+    const int q = (gi / W) % NQ;         // frequency class
+    const int c = gi / (NQ * W);         // component
     const int gbase = (tid & 63) - lg;
-    // stored column -> kx: columns are kept in even/odd order of kx
+    // stored column -> kx: columns are kept in the class order of the rows
     const int scol = lb * W + w;
-    const int kq = a.nkx / 2;
-    const int kx = 2 * (scol % kq) + scol / kq;
+    const int kq = a.nkx / a.nq;
+    const int kx = a.nq * (scol % kq) + scol / kq;
     const bool packed = scol == 0;
     const int ny = a.ny, Py = a.Py;
     const int cs = ny * a.nkxp;
     const int kcs = a.nkx_full * (Py / 2 + 1);
-    // this group's column, zero beyond ny
-    float2 x[E];
+    // this group's column, zero beyond ny: blocks n + r LC for r < NQ/2
+    float2 v0[E], v1[E];
     const float2* src = a.S + c * cs + tile_index(0, scol, ny, a.tsh);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int y = lg + P * i;
-        x[i] = y < ny ? src[y << a.tsh] : mk2(0.f, 0.f);
+        v0[i] = y < ny ? src[y << a.tsh] : mk2(0.f, 0.f);
+        v1[i] = mk2(0.f, 0.f);
+        if (NQ == 4 && y + LC < ny) v1[i] = src[(y + LC) << a.tsh];
     }
-    for (int m = tid; m < 2 * L; m += CT2) tw[m] = a.tw[m];
-    // kernel values at ky = 2 pos + h (mirror compressed along y; xy is
+    for (int m = tid; m < Py; m += NT) tw[m] = a.tw[m];
+    // kernel values at ky = NQ pos + q (mirror compressed along y; xy is
     // odd in ky): diagonal kd, off-diagonal ko (x, y), Nyquist-column kn
     float kd[E], ko[E], kn[E];
-    const int cdiag = c == 0 ? 0 : (c == 1 ? 1 : 2);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-        const int ky = 2 * (lg + P * i) + h;
+        const int ky = NQ * (lg + P * i) + q;
         const bool flip = ky > Py - ky;
         const int iy = flip ? Py - ky : ky;
         const int o = kx * (Py / 2 + 1) + iy;
-        kd[i] = a.K[cdiag * kcs + o];
+        kd[i] = a.K[c * kcs + o];
         ko[i] = 0.f;
         kn[i] = 0.f;
         if (c < 2) { const float v = a.K[3 * kcs + o]; ko[i] = flip ? -v : v; }
-        if (packed) kn[i] = a.K[cdiag * kcs + (a.nkx_full - 1) * (Py / 2 + 1) + iy];
+        if (packed) kn[i] = a.K[c * kcs + (a.nkx_full - 1) * (Py / 2 + 1) + iy];
     }
     __syncthreads();   // twiddle table
-    if (h == 1) {
+    float2 x[E];
 #pragma unroll
-        for (int i = 0; i < E; ++i) x[i] = cmul(x[i], tw[lg + P * i]);
+    for (int i = 0; i < E; ++i) {
+        const int n = lg + P * i;
+        float2 s = v0[i];
+        if (NQ == 4) { const float2 t = rot4(v1[i], q); s.x += t.x; s.y += t.y; }
+        x[i] = q ? cmul(s, tw[n * q]) : s;
     }
     F::template run<false>(x, scr + gi * CF::SC, tw, lg);
-    // x and y spectra of every (half, column) to LDS
-    if (c < 2) {
-        float2* xo = xch + ((c * 2 + h) * W + w) * L;
+    // every class spectrum to LDS
+    {
+        float2* xo = xch + CF::slot(c, q, w) * LC;
 #pragma unroll
         for (int i = 0; i < E; ++i) xo[lg + P * i] = x[i];
     }
     __syncthreads();
-    float2 q[E];
-    if (c < 2 && !packed) {
-        const float2* xp = xch + (((1 - c) * 2 + h) * W + w) * L;
-#pragma unroll
-        for (int i = 0; i < E; ++i) q[i] = xp[lg + P * i];
-    }
     if (!packed) {
         // H_x = Kxx M_x + Kxy M_y, H_y = Kxy M_x + Kyy M_y, H_z = Kzz M_z
         if (c < 2) {
+            const float2* xp = xch + CF::slot(1 - c, q, w) * LC;
 #pragma unroll
-            for (int i = 0; i < E; ++i)
-                x[i] = mk2(kd[i] * x[i].x + ko[i] * q[i].x, kd[i] * x[i].y + ko[i] * q[i].y);
+            for (int i = 0; i < E; ++i) {
+                const float2 o = xp[lg + P * i];
+                x[i] = mk2(kd[i] * x[i].x + ko[i] * o.x, kd[i] * x[i].y + ko[i] * o.y);
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < E; ++i) x[i] = mk2(kd[i] * x[i].x, kd[i] * x[i].y);
@@ -599,15 +648,14 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     } else {
         // column 0 carries (kx = 0) + i (kx = Px/2): separate with the
         // Hermitian symmetry in ky, apply each column's (diagonal) kernel,
-        // pack again.  The partner of ky is -ky: position L-1-pos in the odd
-        // half, (L-pos) mod L in the even half.
-        float2 pz[E];
-#pragma unroll
-        for (int i = 0; i < E; ++i)
-            pz[i] = h ? partner_odd<E, P>(x, i, lg, gbase) : partner_mirror<E, P>(x, i, lg, gbase);
+        // pack again.  The partner of ky is -ky: class (NQ - q) mod NQ,
+        // position (LC - pos) mod LC for q = 0, LC - 1 - pos otherwise.
+        const float2* xp = xch + CF::slot(c, (NQ - q) % NQ, w) * LC;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            const float2 z = x[i], zp = pz[i];
+            const int pos = lg + P * i;
+            const float2 z = x[i];
+            const float2 zp = xp[q == 0 ? (LC - pos) % LC : LC - 1 - pos];
             float2 A = mk2(0.5f * (z.x + zp.x), 0.5f * (z.y - zp.y));
             float2 B = mk2(0.5f * (z.y + zp.y), -0.5f * (z.x - zp.x));
             A = mk2(kd[i] * A.x, kd[i] * A.y);
@@ -616,31 +664,40 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
         }
     }
     F::template run<true>(x, scr + gi * CF::SC, tw, lg);
-    float2* comb = cmb + (c * W + w) * L;
-    if (h == 1) {
+    __syncthreads();   // every group has read the exchange
+    {
+        float2* xo = xch + CF::slot(c, q, w) * LC;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            const int y = lg + P * i;
-            if (y < ny) comb[y] = cmul(x[i], cconj(tw[y]));
+            const int n = lg + P * i;
+            xo[n] = q ? cmul(x[i], cconj(tw[n * q])) : x[i];
         }
     }
     __syncthreads();
-    if (h == 1) return;
+    // outputs y = n + r LC: the group of class r (r < NQ/2) assembles them
+    if (2 * q >= NQ) return;
+    const int r = q;
     float2* dst = a.S + c * cs + tile_index(0, scol, ny, a.tsh);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-        const int y = lg + P * i;
+        const int n = lg + P * i;
+        const int y = n + r * LC;
         if (y < ny) {
-            const float2 v = comb[y];
-            dst[y << a.tsh] = mk2(x[i].x + v.x, x[i].y + v.y);
+            float2 s = xch[CF::slot(c, 0, w) * LC + n];
+#pragma unroll
+            for (int cq = 1; cq < NQ; ++cq) {
+                const float2 t = rot4(xch[CF::slot(c, cq, w) * LC + n], -(r * cq * (4 / NQ)));
+                s.x += t.x; s.y += t.y;
+            }
+            dst[y << a.tsh] = s;
         }
     }
 }
 
-template <int L, int E>
-__global__ __launch_bounds__(CT2) void col2d_fast(Col2dArgs a, DevState* __restrict__ st) {
+template <int L, int E, int NQ>
+__global__ __launch_bounds__(kColThreads) void col2d_fast(Col2dArgs a, DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
-    col2d_body<L, E>(a, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
+    col2d_body<L, E, NQ>(a, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -649,40 +706,43 @@ __global__ __launch_bounds__(CT2) void col2d_fast(Col2dArgs a, DevState* __restr
 // variant in use for a length comes from a process-wide table that
 // llg_autotune fills (variant 0 until then).
 // ---------------------------------------------------------------------------
-#define ROW_VARIANTS(X) X(64, 4, 0) X(64, 8, 1) X(128, 4, 0) X(128, 8, 1) X(192, 12, 0) X(192, 6, 1) \
-    X(256, 4, 0) X(256, 8, 1) X(384, 12, 0) X(384, 6, 1) X(512, 4, 0) X(512, 8, 1) X(768, 12, 0)     \
-    X(768, 6, 1) X(1024, 8, 0) X(1024, 16, 1)
-#define COL_VARIANTS(X) X(32, 4, 0) X(32, 8, 1) X(64, 4, 0) X(64, 8, 1) X(96, 12, 0) X(96, 6, 1) \
-    X(128, 4, 0) X(128, 8, 1) X(192, 12, 0) X(192, 6, 1) X(256, 4, 0) X(256, 8, 1) X(384, 12, 0) \
-    X(384, 6, 1) X(512, 8, 0) X(512, 16, 1)
+// rows: (Px, elements per lane, frequency classes, variant)
+#define ROW_VARIANTS(X) X(64, 4, 2, 0) X(64, 8, 2, 1) X(128, 4, 2, 0) X(128, 4, 4, 1) X(192, 12, 2, 0)    \
+    X(192, 6, 2, 1) X(256, 4, 2, 0) X(256, 4, 4, 1) X(384, 12, 2, 0) X(384, 6, 4, 1) X(512, 4, 2, 0)    \
+    X(512, 4, 4, 1) X(768, 12, 2, 0) X(768, 6, 4, 1) X(1024, 8, 2, 0) X(1024, 4, 4, 1)
+// columns: (L = Py/2, elements per lane, frequency classes, variant)
+#define COL_VARIANTS(X) X(32, 4, 2, 0) X(32, 8, 2, 1) X(64, 4, 2, 0) X(64, 4, 4, 1) X(96, 12, 2, 0)        \
+    X(96, 6, 2, 1) X(128, 4, 2, 0) X(128, 4, 4, 1) X(192, 12, 2, 0) X(192, 6, 4, 1) X(256, 4, 2, 0)       \
+    X(256, 4, 4, 1) X(384, 12, 2, 0) X(384, 6, 4, 1) X(512, 8, 2, 0) X(512, 4, 4, 1)
 
 // grouped launches: one launch runs a pass for all films of one length
 // class (same compiled variant); block b works on film map[b].x, local
 // block map[b].y of that film
-template <int PX, int E2>
-__global__ __launch_bounds__(FRT) void row_fwd_group(const FilmRow* __restrict__ films,
-                                                     const int2* __restrict__ map) {
+template <int PX, int E2, int NQ>
+__global__ __launch_bounds__(kRowThreads) void row_fwd_group(const FilmRow* __restrict__ films,
+                                                             const int2* __restrict__ map) {
     extern __shared__ char dyn_lds[];
     const int2 m = map[blockIdx.x];
     const FilmRow& f = films[m.x];
-    row_fwd_body<PX, E2, false>(f.g, f.twx, f.S, f.fa, f.st, m.y, dyn_lds);
+    row_fwd_body<PX, E2, NQ, false>(f.g, f.twx, f.S, f.fa, f.st, m.y, dyn_lds);
 }
 
-template <int PX, int E2>
-__global__ __launch_bounds__(FRT) void row_inv_group(const FilmRow* __restrict__ films,
-                                                     const int2* __restrict__ map) {
+template <int PX, int E2, int NQ>
+__global__ __launch_bounds__(kRowThreads) void row_inv_group(const FilmRow* __restrict__ films,
+                                                             const int2* __restrict__ map) {
     extern __shared__ char dyn_lds[];
     const int2 m = map[blockIdx.x];
     const FilmRow& f = films[m.x];
-    row_inv_body<PX, E2, false>(f.g, f.p, f.twx, f.S, f.sa, f.st, m.y, dyn_lds);
+    row_inv_body<PX, E2, NQ, false>(f.g, f.p, f.twx, f.S, f.sa, f.st, m.y, dyn_lds);
 }
 
-template <int L, int E>
-__global__ __launch_bounds__(CT2) void col_group(const FilmCol* __restrict__ films, const int2* __restrict__ map) {
+template <int L, int E, int NQ>
+__global__ __launch_bounds__(kColThreads) void col_group(const FilmCol* __restrict__ films,
+                                                         const int2* __restrict__ map) {
     extern __shared__ char dyn_lds[];
     const int2 m = map[blockIdx.x];
     const FilmCol& f = films[m.x];
-    col2d_body<L, E>(f.a, f.st, m.y, dyn_lds);
+    col2d_body<L, E, NQ>(f.a, f.st, m.y, dyn_lds);
 }
 
 // LDS of one workgroup on gfx950
@@ -726,10 +786,10 @@ bool fast2d_set_variants(int Px, int rv, int L, int cv, bool xper) {
 
 bool fast2d_row_ok(int Px, int var, bool xper) {
     if (var < 0) var = fast2d_row_variant(Px);
-#define CASE(PX, E, V)                                                                    \
+#define CASE(PX, E, NQ, V)                                                                \
     if (Px == PX && var == V)                                                             \
-        return (xper ? RowSplit<PX, E>::template inv_bytes<true>()                        \
-                     : RowSplit<PX, E>::template inv_bytes<false>()) <= kMaxLds;
+        return (xper ? RowSplit<PX, E, NQ>::template inv_bytes<true>()                    \
+                     : RowSplit<PX, E, NQ>::template inv_bytes<false>()) <= kMaxLds;
     ROW_VARIANTS(CASE)
 #undef CASE
     return false;
@@ -738,7 +798,7 @@ bool fast2d_row_ok(int Px, int var, bool xper) {
 bool fast2d_col_ok(int L, int split, int var) {
     if (!split) return false;
     if (var < 0) var = fast2d_col_variant(L);
-#define CASE(LL, E, V) if (L == LL && var == V) return true;
+#define CASE(LL, E, NQ, V) if (L == LL && var == V) return ColSplit<LL, E, NQ>::bytes() <= kMaxLds;
     COL_VARIANTS(CASE)
 #undef CASE
     return false;
@@ -748,20 +808,21 @@ hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, cons
                                DevState* st, hipStream_t s) {
     if (g.nx > g.Px || g.nkxp < g.Px / 2 || g.tsh < 0 || (g.Px / 2) % (1 << g.tsh)) return hipErrorInvalidValue;
     const int var = fast2d_row_variant(g.Px);
-#define CASE(PX, E, V)                                                                    \
+#define CASE(PX, E, NQ, V)                                                                \
     if (g.Px == PX && var == V) {                                                         \
-        constexpr int rows = 2 * RowSplit<PX, E>::RP;                                     \
+        using R_ = RowSplit<PX, E, NQ>;                                                   \
+        constexpr int rows = 2 * R_::RP;                                                  \
         const dim3 grid((g.nrows + rows - 1) / rows);                                     \
-        constexpr int lds_p = RowSplit<PX, E>::template fwd_bytes<true>();                \
-        constexpr int lds_o = RowSplit<PX, E>::template fwd_bytes<false>();               \
+        constexpr int lds_p = R_::template fwd_bytes<true>();                             \
+        constexpr int lds_o = R_::template fwd_bytes<false>();                            \
         if (g.nx == PX) {                                                                 \
-            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, true>), lds_p); \
+            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, NQ, true>), lds_p); \
             if (e_ != hipSuccess) return e_;                                              \
-            hipLaunchKernelGGL((row_fwd_fast<PX, E, true>), grid, dim3(FRT), lds_p, s, g, twx, S, fa, st); \
+            hipLaunchKernelGGL((row_fwd_fast<PX, E, NQ, true>), grid, dim3(R_::NT), lds_p, s, g, twx, S, fa, st); \
         } else if (2 * g.nx <= PX) {                                                      \
-            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, false>), lds_o); \
+            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, NQ, false>), lds_o); \
             if (e_ != hipSuccess) return e_;                                              \
-            hipLaunchKernelGGL((row_fwd_fast<PX, E, false>), grid, dim3(FRT), lds_o, s, g, twx, S, fa, st); \
+            hipLaunchKernelGGL((row_fwd_fast<PX, E, NQ, false>), grid, dim3(R_::NT), lds_o, s, g, twx, S, fa, st); \
         } else {                                                                          \
             return hipErrorInvalidValue;                                                  \
         }                                                                                 \
@@ -778,21 +839,22 @@ hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, 
         return hipErrorInvalidValue;
     if ((sa.mode == ROW_STAGE || sa.mode == ROW_ERROR) && sa.nk < 1) return hipErrorInvalidValue;
     const int var = fast2d_row_variant(g.Px);
-#define CASE(PX, E, V)                                                                    \
+#define CASE(PX, E, NQ, V)                                                                \
     if (g.Px == PX && var == V) {                                                         \
-        constexpr int rows = 2 * RowSplit<PX, E>::RP;                                     \
+        using R_ = RowSplit<PX, E, NQ>;                                                   \
+        constexpr int rows = 2 * R_::RP;                                                  \
         const dim3 grid((g.nrows + rows - 1) / rows);                                     \
-        constexpr int lds_p = RowSplit<PX, E>::template inv_bytes<true>();                \
-        constexpr int lds_o = RowSplit<PX, E>::template inv_bytes<false>();               \
+        constexpr int lds_p = R_::template inv_bytes<true>();                             \
+        constexpr int lds_o = R_::template inv_bytes<false>();                            \
         if (g.nx == PX) {                                                                 \
-            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, true>), lds_p); \
+            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, NQ, true>), lds_p); \
             if (e_ != hipSuccess) return e_;                                              \
-            hipLaunchKernelGGL((row_inv_fast<PX, E, true>), grid, dim3(FRT),              \
+            hipLaunchKernelGGL((row_inv_fast<PX, E, NQ, true>), grid, dim3(R_::NT),       \
                                lds_p, s, g, p, twx, S, sa, st);                           \
         } else if (2 * g.nx <= PX) {                                                      \
-            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, false>), lds_o); \
+            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, NQ, false>), lds_o); \
             if (e_ != hipSuccess) return e_;                                              \
-            hipLaunchKernelGGL((row_inv_fast<PX, E, false>), grid, dim3(FRT),             \
+            hipLaunchKernelGGL((row_inv_fast<PX, E, NQ, false>), grid, dim3(R_::NT),      \
                                lds_o, s, g, p, twx, S, sa, st);                           \
         } else {                                                                          \
             return hipErrorInvalidValue;                                                  \
@@ -806,16 +868,16 @@ hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, 
 
 hipError_t launch_col2d_fast(const Col2dArgs& a, DevState* st, hipStream_t s) {
     if (a.Py % 2 || a.ny > a.Py / 2 || a.nkx_full != a.nkx + 1 || a.nkx % 2) return hipErrorInvalidValue;
-    if (a.tsh < 0 || a.nkx % (1 << a.tsh)) return hipErrorInvalidValue;
+    if (a.tsh < 0 || a.nkx % (1 << a.tsh) || (a.nq != 2 && a.nq != 4) || a.nkx % a.nq) return hipErrorInvalidValue;
     const int L = a.Py / 2;
     const int var = fast2d_col_variant(L);
-#define CASE(LL, E, V)                                                                    \
+#define CASE(LL, E, NQ, V)                                                                \
     if (L == LL && var == V) {                                                            \
-        using CF = ColSplit<LL, E>;                                                       \
+        using CF = ColSplit<LL, E, NQ>;                                                   \
         if (a.nkx % CF::W) return hipErrorInvalidValue;                                   \
-        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&col2d_fast<LL, E>), CF::bytes()); \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&col2d_fast<LL, E, NQ>), CF::bytes()); \
         if (e_ != hipSuccess) return e_;                                                  \
-        hipLaunchKernelGGL((col2d_fast<LL, E>), dim3(a.nkx / CF::W), dim3(CT2), CF::bytes(), s, a, st); \
+        hipLaunchKernelGGL((col2d_fast<LL, E, NQ>), dim3(a.nkx / CF::W), dim3(CF::NT), CF::bytes(), s, a, st); \
         return hipGetLastError();                                                         \
     }
     COL_VARIANTS(CASE)
@@ -825,14 +887,21 @@ hipError_t launch_col2d_fast(const Col2dArgs& a, DevState* st, hipStream_t s) {
 
 // ---- grouped launchers ------------------------------------------------------------
 int fast2d_row_rows_per_block(int Px, int var) {
-#define CASE(PX, E, V) if (Px == PX && var == V) return 2 * RowSplit<PX, E>::RP;
+#define CASE(PX, E, NQ, V) if (Px == PX && var == V) return 2 * RowSplit<PX, E, NQ>::RP;
+    ROW_VARIANTS(CASE)
+#undef CASE
+    return 0;
+}
+int fast2d_row_classes(int Px, int var) {
+    if (var < 0) var = fast2d_row_variant(Px);
+#define CASE(PX, E, NQ, V) if (Px == PX && var == V) return NQ;
     ROW_VARIANTS(CASE)
 #undef CASE
     return 0;
 }
 int fast2d_col_width(int L, int var) {
     if (var < 0) var = fast2d_col_variant(L);
-#define CASE(LL, E, V) if (L == LL && var == V) return ColSplit<LL, E>::W;
+#define CASE(LL, E, NQ, V) if (L == LL && var == V) return ColSplit<LL, E, NQ>::W;
     COL_VARIANTS(CASE)
 #undef CASE
     return 0;
@@ -840,12 +909,13 @@ int fast2d_col_width(int L, int var) {
 
 hipError_t launch_row_fwd_group(int Px, int var, const FilmRow* films, const int2* map, int nblocks,
                                 hipStream_t s) {
-#define CASE(PX, E, V)                                                                    \
+#define CASE(PX, E, NQ, V)                                                                \
     if (Px == PX && var == V) {                                                           \
-        constexpr int lds = RowSplit<PX, E>::template fwd_bytes<false>();                 \
-        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_group<PX, E>), lds); \
+        using R_ = RowSplit<PX, E, NQ>;                                                   \
+        constexpr int lds = R_::template fwd_bytes<false>();                              \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_group<PX, E, NQ>), lds); \
         if (e_ != hipSuccess) return e_;                                                  \
-        hipLaunchKernelGGL((row_fwd_group<PX, E>), dim3(nblocks), dim3(FRT), lds, s, films, map); \
+        hipLaunchKernelGGL((row_fwd_group<PX, E, NQ>), dim3(nblocks), dim3(R_::NT), lds, s, films, map); \
         return hipGetLastError();                                                         \
     }
     ROW_VARIANTS(CASE)
@@ -855,12 +925,13 @@ hipError_t launch_row_fwd_group(int Px, int var, const FilmRow* films, const int
 
 hipError_t launch_row_inv_group(int Px, int var, const FilmRow* films, const int2* map, int nblocks,
                                 hipStream_t s) {
-#define CASE(PX, E, V)                                                                    \
+#define CASE(PX, E, NQ, V)                                                                \
     if (Px == PX && var == V) {                                                           \
-        constexpr int lds = RowSplit<PX, E>::template inv_bytes<false>();                 \
-        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_group<PX, E>), lds); \
+        using R_ = RowSplit<PX, E, NQ>;                                                   \
+        constexpr int lds = R_::template inv_bytes<false>();                              \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_group<PX, E, NQ>), lds); \
         if (e_ != hipSuccess) return e_;                                                  \
-        hipLaunchKernelGGL((row_inv_group<PX, E>), dim3(nblocks), dim3(FRT), lds, s, films, map); \
+        hipLaunchKernelGGL((row_inv_group<PX, E, NQ>), dim3(nblocks), dim3(R_::NT), lds, s, films, map); \
         return hipGetLastError();                                                         \
     }
     ROW_VARIANTS(CASE)
@@ -869,12 +940,13 @@ hipError_t launch_row_inv_group(int Px, int var, const FilmRow* films, const int
 }
 
 hipError_t launch_col_group(int L, int var, const FilmCol* films, const int2* map, int nblocks, hipStream_t s) {
-#define CASE(LL, E, V)                                                                    \
+#define CASE(LL, E, NQ, V)                                                                \
     if (L == LL && var == V) {                                                            \
-        constexpr int lds = ColSplit<LL, E>::bytes();                                     \
-        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&col_group<LL, E>), lds);  \
+        using CF = ColSplit<LL, E, NQ>;                                                   \
+        constexpr int lds = CF::bytes();                                                  \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&col_group<LL, E, NQ>), lds); \
         if (e_ != hipSuccess) return e_;                                                  \
-        hipLaunchKernelGGL((col_group<LL, E>), dim3(nblocks), dim3(CT2), lds, s, films, map); \
+        hipLaunchKernelGGL((col_group<LL, E, NQ>), dim3(nblocks), dim3(CF::NT), lds, s, films, map); \
         return hipGetLastError();                                                         \
     }
     COL_VARIANTS(CASE)

@@ -150,6 +150,7 @@ struct Col2dArgs {
     int nkx, nkx_full, nkxp;
     int ny, Py;
     int tsh;                // tile width log2 (see tile_index)
+    int nq;                 // frequency classes of the row transforms (column order)
 };
 
 // ---- launchers (kernels.hip) ------------------------------------------------
@@ -197,6 +198,7 @@ struct FilmCol {
     int var;          // compiled variant of the column length
 };
 int fast2d_row_rows_per_block(int Px, int var);
+int fast2d_row_classes(int Px, int var = -1);
 int fast2d_col_width(int L, int var = -1);
 hipError_t launch_row_fwd_group(int Px, int var, const FilmRow* films, const int2* map, int nblocks,
                                 hipStream_t s);

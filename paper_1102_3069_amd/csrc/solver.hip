@@ -229,6 +229,7 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
         c.nkx_full = g.nkx;
         c.nkxp = g.nkxp;
         c.tsh = g.tsh;
+        c.nq = fast2d_row_classes(g.Px);
         c.ny = g.ny;
         c.Py = g.Py;
         HIPCHK(s, launch_col2d_fast(c, s->st, s->stream));
