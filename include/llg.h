@@ -177,18 +177,62 @@ llg_status llg_step(llg_solver *s, llg_method method, double dt, int64_t nsteps)
  * 0.2, 5), q the order of the embedded estimate (4, 2, 4, 1); the last step
  * lands on t_end; dt0 is the first attempted step.  The controller runs on
  * the device: attempts are replayed from a captured HIP graph and the host
- * only polls the done flag.  LLG_E_DIVERGED if the step falls below 1e-18 s
- * or a NaN/Inf appears.  `out` may be NULL. */
+ * only polls the done flag.  dt0 = 0 continues with the step the controller
+ * chose last (the dt_next of llg_get_stats, or of a state restored by
+ * llg_set_state; LLG_E_STATE if there is none).  LLG_E_DIVERGED if the step
+ * falls below 1e-18 s or a NaN/Inf appears.  `out` may be NULL. */
 llg_status llg_run(llg_solver *s, llg_method method, double t_end, double max_err,
                    double dt0, llg_stats *out);
 /* As llg_run with LLG_RKDP45 but stops after at most `max_attempts`
  * attempts (for timing a fixed amount of work); t may then be < t_end. */
 llg_status llg_run_attempts(llg_solver *s, double t_end, double max_err, double dt0,
                             int64_t max_attempts, llg_stats *out);
+/* llg_run_dm: integration to t_end (s) with a fixed tableau (LLG_EULER,
+ * LLG_HEUN, LLG_RK3 or LLG_RK4) whose step size bounds the variation of m per
+ * step (Sec. 2.2): before each step, dt = max_dm / max over cells |dm/dt|
+ * of the step's first stage (so the first-order change of every cell is at
+ * most max_dm, dimensionless), at most dt_max (s), and the last step lands
+ * on t_end.  The step size is chosen on the device inside a captured HIP
+ * graph; each step is recorded in the attempt log (dt, err = the first-order
+ * bound dt |dm/dt|max, accepted = 1).  The thermal field is not applied.
+ * LLG_E_ARG unless max_dm > 0 and dt_max > 0; LLG_E_DIVERGED if a NaN/Inf
+ * appears.  `out` may be NULL. */
+llg_status llg_run_dm(llg_solver *s, llg_method method, double t_end, double max_dm, double dt_max,
+                      llg_stats *out);
 llg_status llg_get_stats(llg_solver *s, llg_stats *out);
 /* Copies up to `cap` recorded adaptive attempts (oldest first, since the last
  * llg_set_m) into `out` (host memory) and stores their number in *n. */
 llg_status llg_get_attempts(llg_solver *s, llg_attempt *out, int64_t cap, int64_t *n);
+
+/* ---- checkpoint and resume ---------------------------------------------------
+ * The integration state besides m: simulated time, the last and the next
+ * step of the controller, the thermal draw counter (the Philox step counter
+ * of Eq. 6's noise) and the statistics.  llg_get_state copies it into *out
+ * and, if m is not NULL, the current m (layout above; host or device per
+ * `where`).  llg_set_state restores both into a solver with the same
+ * problem: m is taken bit for bit (no renormalisation; LLG_E_ARG if some
+ * | |m| - 1 | > 1e-3 or a value is not finite), and the attempt log starts
+ * empty.  A run resumed this way (llg_step with the same dt, llg_run_dm, or
+ * llg_run with dt0 = 0) takes exactly the steps the uninterrupted run would
+ * have taken, with the same results; a pair whose first stage is the last
+ * stage of the previous attempt (LLG_RKDP45, LLG_RK23) evaluates that stage
+ * once more on resuming, which the evaluation count shows.  LLG_E_ARG for a record with health != 0,
+ * a non-finite time or negative steps or counters.
+ */
+typedef struct {
+    double t;            /* simulated time, s                                */
+    double dt;           /* last step or attempted step, s                   */
+    double dt_next;      /* the controller's next step, s (0: none)          */
+    double last_err;     /* error estimate of the last adaptive attempt      */
+    int64_t step;        /* accepted steps: the thermal draw counter         */
+    int64_t steps;       /* statistics: accepted steps, rejected attempts,   */
+    int64_t rejected;    /*   effective-field evaluations                   */
+    int64_t evals;
+    int32_t health;      /* must be 0 for llg_set_state                      */
+    int32_t reserved;
+} llg_state;
+llg_status llg_get_state(llg_solver *s, llg_state *out, float *m, llg_mem where);
+llg_status llg_set_state(llg_solver *s, const llg_state *in, const float *m, llg_mem where);
 
 /* ---- measurement -------------------------------------------------------------
  * llg_profile_evals: runs `n` H_eff evaluations back to back on the solver's

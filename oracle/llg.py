@@ -21,6 +21,12 @@ tolerable error per integration step":
     dt  <- dt * clamp(0.9 (tol/err)^(1/(q+1)), 0.2, 5)  (5 if err == 0),
            q the order of the embedded estimate
     the last step is shortened to land on t_end.
+
+The fixed schemes may instead bound the variation of m per step (Sec. 2.2),
+read here as: before each step, dt = max_dm / max over cells |dm/dt| at the
+current state (the step's first stage), at most dt_max, the last step
+shortened to land on t_end; the thermal term is left out (its strength
+depends on a fixed step).
 """
 import math
 
@@ -152,10 +158,14 @@ class Solver:
     def _norm(self, m):
         return normalize(m) if self.renormalize else m
 
-    def _stages(self, tab, dt):
-        """Runs the stages of one explicit RK step from self.m; returns k."""
+    def _stages(self, tab, dt, k1=None):
+        """Runs the stages of one explicit RK step from self.m; returns k.
+        A given k1 (f at self.m) is used instead of evaluating it again."""
         ks = []
         for s, row in enumerate(tab["A"]):
+            if s == 0 and k1 is not None:
+                ks.append(k1)
+                continue
             if s == 0:
                 ms = self.m
             else:
@@ -183,6 +193,37 @@ class Solver:
             self.t += dt
             self.step_count += 1
         return self.m
+
+    # -- fixed tableau, step bounded by the variation of m -----------------------
+    def dm_step(self, max_dm, dt_max, t_end):
+        """(dt, k1) for the next step: k1 = f(m), dt = max_dm / max_i |k1_i|
+        limited to dt_max and to the time left."""
+        k1 = self.rhs(self.m, None)
+        kmax = float(np.max(np.sqrt(np.sum(k1 * k1, axis=0))))
+        dt = dt_max if kmax == 0.0 else min(dt_max, max_dm / kmax)
+        return min(dt, t_end - self.t), k1
+
+    def run_dm(self, method, t_end, max_dm, dt_max, dts=None):
+        """Integrates to t_end with the fixed tableau `method`, each step
+        chosen by dm_step.  With `dts` (a recorded list of steps, e.g. the
+        GPU run's) those steps are taken instead.  Returns [(dt taken, dt the
+        oracle chose)] per step."""
+        tab = TABLEAUX[method]
+        saved = self.prob
+        self.prob = dict(saved, T=0.0)
+        out = []
+        try:
+            while (self.t < t_end) if dts is None else (len(out) < len(dts)):
+                own, k1 = self.dm_step(max_dm, dt_max, t_end)
+                dt = own if dts is None else dts[len(out)]
+                ks = self._stages(tab, dt, k1)
+                self.m = self._norm(self._combine(ks, tab["b"], dt))
+                self.t = t_end if dt >= t_end - self.t else self.t + dt
+                self.step_count += 1
+                out.append((dt, own))
+        finally:
+            self.prob = saved
+        return out
 
     # -- adaptive embedded pairs (Dormand-Prince by default) --------------------
     def attempt(self, dt, method="rkdp45"):

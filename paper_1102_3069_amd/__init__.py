@@ -47,6 +47,16 @@ class Attempt(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("err", ctypes.c_float), ("accepted", ctypes.c_int32)]
 
 
+class State(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double), ("dt_next", ctypes.c_double),
+                ("last_err", ctypes.c_double), ("step", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("evals", ctypes.c_int64), ("health", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class SurStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("proposals", ctypes.c_int64), ("accepted", ctypes.c_int64),
                 ("segments", ctypes.c_int64), ("max_dm_accepted", ctypes.c_double),
@@ -90,7 +100,11 @@ _SIGNATURES = {
                  ctypes.POINTER(Stats)], ctypes.c_int),
     "llg_run_attempts": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                           ctypes.POINTER(Stats)], ctypes.c_int),
+    "llg_run_dm": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                    ctypes.POINTER(Stats)], ctypes.c_int),
     "llg_get_stats": ([_P, ctypes.POINTER(Stats)], ctypes.c_int),
+    "llg_get_state": ([_P, ctypes.POINTER(State), _P, ctypes.c_int], ctypes.c_int),
+    "llg_set_state": ([_P, ctypes.POINTER(State), _P, ctypes.c_int], ctypes.c_int),
     "llg_get_attempts": ([_P, ctypes.POINTER(Attempt), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
                          ctypes.c_int),
     "llg_profile_evals": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
@@ -284,6 +298,25 @@ class Solver:
         self._chk(self._lib.llg_run_attempts(self._h, float(t_end), float(max_err), float(dt0),
                                              int(max_attempts), ctypes.byref(st)))
         return st.as_dict()
+
+    def run_dm(self, method, t_end, max_dm, dt_max):
+        """Fixed tableau, step chosen so that max |dm| per step is about max_dm."""
+        st = Stats()
+        self._chk(self._lib.llg_run_dm(self._h, METHODS[method], float(t_end), float(max_dm), float(dt_max),
+                                       ctypes.byref(st)))
+        return st.as_dict()
+
+    def get_state(self):
+        """(state dict, m) for llg_set_state."""
+        st = State()
+        a = np.empty(self._shape(), dtype=np.float32)
+        self._chk(self._lib.llg_get_state(self._h, ctypes.byref(st), a.ctypes.data_as(_P), LLG_HOST))
+        return st.as_dict(), a
+
+    def set_state(self, state, m):
+        st = State(**{k: state[k] for k in state})
+        a = np.ascontiguousarray(m, dtype=np.float32).reshape(self._shape())
+        self._chk(self._lib.llg_set_state(self._h, ctypes.byref(st), a.ctypes.data_as(_P), LLG_HOST))
 
     def stats(self):
         st = Stats()

@@ -328,7 +328,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     float* mo = resolve(sa.m_out, cur);
     float* ko = resolve(sa.k_out, cur);
     const bool stage = sa.mode == ROW_STAGE;
-    const bool errm = sa.mode == ROW_ERROR || (stage && sa.with_err);
+    const bool errm = sa.mode == ROW_ERROR || ((stage || sa.mode == ROW_KONLY) && sa.with_err);
 
     // ---- global reads: twiddles, m rows rb-1 .. rb+2RP (y neighbours wrap
     // on a periodic y axis), this group's class of the spectrum
@@ -486,7 +486,10 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         }
         bad |= !(isfinite(kx) && isfinite(ky) && isfinite(kz));
         if (ko) { ko[qq] = kx; ko[cs + qq] = ky; ko[2 * cs + qq] = kz; }
-        if (sa.mode == ROW_KONLY) continue;
+        if (sa.mode == ROW_KONLY) {
+            if (errm) errmax = fmaxf(errmax, sqrtf(kx * kx + ky * ky + kz * kz));
+            continue;
+        }
         // combination with the earlier stages (stage input and/or error)
         float ax = 0.f, ay = 0.f, az = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
         if (stage) {

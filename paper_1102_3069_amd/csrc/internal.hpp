@@ -66,6 +66,7 @@ struct DevState {
     double t, dt, dt_next, t_end, tol, dt_min, gms;
     double last_err;
     double ctrl_exp;      // adaptive: step-size exponent 1/(q+1)
+    double dt_max;        // bounded-change runs: largest step, s
     float dtau;           // dt * gamma0 * Ms
     float pad1;
     long long step;       // accepted steps (thermal draw counter)
@@ -103,7 +104,8 @@ struct StageArgs {
     int nk;                  // number of k's in the combination (incl. the current one)
     float a[kMaxK];          // combination weights of k_1..k_nk (times dtau)
     float e[kMaxK];          // error weights (ROW_ERROR, or ROW_STAGE with with_err)
-    int with_err;            // ROW_STAGE: also the embedded error estimate
+    int with_err;            // ROW_STAGE: also the embedded error estimate;
+                             // ROW_KONLY: also max over cells |k| (into err_bits)
     int skip_fwd;            // ROW_STAGE: no forward transform of the new state
     BufRef m_in;             // stage input m_s
     BufRef m0;               // state at the start of the step
@@ -160,8 +162,11 @@ hipError_t launch_row_inv(const Grid& g, const Phys& p, const FftPlan& px, const
                           float2* S, const StageArgs& sa, DevState* st, hipStream_t s);
 hipError_t launch_col(const ColArgs& a, DevState* st, int mode, hipStream_t s);
 hipError_t launch_ctrl_fixed(DevState* st, int evals, double dt, hipStream_t s);
+hipError_t launch_ctrl_dm(DevState* st, hipStream_t s);
+hipError_t launch_ctrl_dm_accept(DevState* st, int evals, hipStream_t s);
 hipError_t launch_ctrl_dp45(DevState* st, hipStream_t s);
 hipError_t launch_state_add_evals(DevState* st, int evals, hipStream_t s);
+hipError_t launch_check_unit(const float* m, int ncells, int* bad, hipStream_t s);
 hipError_t launch_normalize_check(float* m, int ncells, int* bad, hipStream_t s);
 hipError_t launch_fft_test(float2* data, int n, int batch, const FftPlan& pl, const float2* tw,
                            int inverse_only, hipStream_t s);

@@ -222,6 +222,7 @@ __global__ __launch_bounds__(RT) void row_inv_kernel(Grid g, Phys p, FftPlan px,
             }
             bad |= !(isfinite(kx) && isfinite(ky) && isfinite(kz));
             if (ko) { ko[i] = kx; ko[cs + i] = ky; ko[2 * cs + i] = kz; }
+            if (sa.mode == ROW_KONLY && sa.with_err) errmax = fmaxf(errmax, sqrtf(kx * kx + ky * ky + kz * kz));
             if (sa.mode == ROW_STAGE) {
                 float ax = m0[i], ay = m0[cs + i], az = m0[2 * cs + i];
                 for (int j = 0; j + 1 < sa.nk; ++j) {
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(RT) void row_inv_kernel(Grid g, Phys p, FftPlan px,
         }
     }
     if (bad) atomicOr(&st->health, 1);
-    if (sa.mode == ROW_ERROR || (sa.mode == ROW_STAGE && sa.with_err)) {
+    if (sa.mode == ROW_ERROR || ((sa.mode == ROW_STAGE || sa.mode == ROW_KONLY) && sa.with_err)) {
         for (int off = 32; off > 0; off >>= 1) errmax = fmaxf(errmax, __shfl_xor(errmax, off));
         if ((tid & 63) == 0) wmax[tid >> 6] = errmax;
         __syncthreads();
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(RT) void row_inv_kernel(Grid g, Phys p, FftPlan px,
             for (int w = 1; w < RT / 64; ++w) m = fmaxf(m, wmax[w]);
             atomicMax(&st->err_bits, __float_as_uint(m));
         }
-        if (sa.mode == ROW_ERROR) return;
+        if (sa.mode != ROW_STAGE) return;
     }
     if (sa.mode == ROW_STAGE && p.demag_on && !sa.skip_fwd) {
         __syncthreads();   // every thread is done reading the inverse transform
@@ -434,6 +435,48 @@ __global__ void ctrl_fixed_kernel(DevState* st, int evals) {
     st->nevals += evals;
 }
 
+// Fixed tableau with a bounded change of m per step: the first stage of a
+// step left max over cells |k_1| in err_bits (k in units of dtau); the
+// step is max_dm / that (tol holds max_dm), at most dt_max, and the last
+// one lands on t_end.
+__global__ void ctrl_dm_kernel(DevState* st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (st->done) return;
+    const float kf = __uint_as_float(st->err_bits);
+    st->err_bits = 0u;
+    st->last_err = (double)kf;
+    if (st->health) { st->done = 1; return; }
+    double dt = st->dt_max;
+    if (kf > 0.f) dt = fmin(dt, st->tol / ((double)kf * st->gms));
+    const double rem = st->t_end - st->t;
+    if (dt >= rem) { dt = rem; st->clipped = 1; }
+    else st->clipped = 0;
+    st->dt = dt;
+    st->dt_next = dt;
+    st->dtau = (float)(dt * st->gms);
+}
+
+// end of such a step: the new state is in place
+__global__ void ctrl_dm_accept_kernel(DevState* st, int evals) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (st->done) return;
+    const long long a = st->nattempt++;
+    if (a < st->log_cap && st->log) {
+        llg_attempt r;
+        r.dt = st->dt;
+        r.err = (float)(st->last_err * (double)st->dtau);   // bound on |dm| of the first stage
+        r.accepted = 1;
+        st->log[a] = r;
+    }
+    st->nevals += evals;
+    if (st->health) { st->done = 1; return; }
+    st->t = st->clipped ? st->t_end : st->t + st->dt;
+    st->cur ^= 1;
+    st->step += 1;
+    st->nsteps += 1;
+    if (st->clipped) st->done = 1;
+}
+
 __global__ void ctrl_fixed_group_kernel(DevState* states, int nfilms, int evals) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nfilms) return;
@@ -508,6 +551,15 @@ __global__ void normalize_check_kernel(float* m, int ncells, int* bad) {
     const float n = sqrtf(x * x + y * y + z * z);
     if (!isfinite(n) || fabsf(n - 1.f) > 1e-3f) { atomicOr(bad, 1); return; }
     m[i] = x / n; m[ncells + i] = y / n; m[2 * ncells + i] = z / n;
+}
+
+// flag | |m| - 1 | > 1e-3 or non-finite values; m itself is left as it is
+__global__ void check_unit_kernel(const float* m, int ncells, int* bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncells) return;
+    const float x = m[i], y = m[ncells + i], z = m[2 * ncells + i];
+    const float n = sqrtf(x * x + y * y + z * z);
+    if (!isfinite(n) || fabsf(n - 1.f) > 1e-3f) atomicOr(bad, 1);
 }
 
 // FFT self-check: `batch` vectors of length n, forward+inverse (or inverse
@@ -624,6 +676,16 @@ hipError_t launch_ctrl_dp45(DevState* st, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_ctrl_dm(DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(ctrl_dm_kernel, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl_dm_accept(DevState* st, int evals, hipStream_t s) {
+    hipLaunchKernelGGL(ctrl_dm_accept_kernel, dim3(1), dim3(64), 0, s, st, evals);
+    return hipGetLastError();
+}
+
 hipError_t launch_ctrl_dp45_group(DevState* states, int nfilms, hipStream_t s) {
     hipLaunchKernelGGL(ctrl_dp45_group_kernel, dim3((nfilms + 63) / 64), dim3(64), 0, s, states, nfilms);
     return hipGetLastError();
@@ -631,6 +693,11 @@ hipError_t launch_ctrl_dp45_group(DevState* states, int nfilms, hipStream_t s) {
 
 hipError_t launch_state_add_evals(DevState* st, int evals, hipStream_t s) {
     hipLaunchKernelGGL(state_add_evals_kernel, dim3(1), dim3(64), 0, s, st, evals);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_unit(const float* m, int ncells, int* bad, hipStream_t s) {
+    hipLaunchKernelGGL(check_unit_kernel, dim3((ncells + 255) / 256), dim3(256), 0, s, m, ncells, bad);
     return hipGetLastError();
 }
 

@@ -84,7 +84,7 @@ struct llg_solver {
     bool spec_valid = false;   // S holds the forward x transform of m
     bool k1_valid = false;     // kfs[cur] holds f(m) for the adaptive method
     double last_dt = 0.0;
-    Graph gfix, gdp;
+    Graph gfix, gdp, gdm;
 };
 
 namespace {
@@ -114,6 +114,7 @@ void free_dev(void* p) {
 void invalidate_graphs(llg_solver* s) {
     s->gfix.reset();
     s->gdp.reset();
+    s->gdm.reset();
 }
 
 void free_buffers(llg_solver* s) {
@@ -433,6 +434,48 @@ llg_status enqueue_plain_attempt(llg_solver* s, const Tableau& t, const Phys& p)
         HIPCHK(s, row_inv(s, p, sa));
     }
     HIPCHK(s, launch_ctrl_dp45(s->st, s->stream));
+    return LLG_OK;
+}
+
+// one step of a fixed tableau whose size bounds the change of m per step
+// (Sec. 2.2): k_1 with max |k_1|, the step size chosen on the device, the
+// input of stage 2 (or, with one stage, the new state) with its forward x
+// transform, then the remaining stages as in a fixed step
+llg_status enqueue_dm_step(llg_solver* s, const Tableau& t, const Phys& p) {
+    llg_status rc;
+    const int S = t.S;
+    if (p.demag_on && (rc = launch_spectral(s)) != LLG_OK) return rc;
+    StageArgs sk = {};
+    sk.mode = ROW_KONLY;
+    sk.with_err = 1;
+    sk.m_in = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+    sk.m0 = sk.m_in;
+    sk.m_out = bref(nullptr);
+    sk.k_out = bref(s->kb[0]);
+    HIPCHK(s, row_inv(s, p, sk));
+    HIPCHK(s, launch_ctrl_dm(s->st, s->stream));
+    FwdArgs fa = {};
+    fa.combine = 1;
+    fa.a1 = (float)(S > 1 ? t.A[1][0] : t.b[0]);
+    fa.m0 = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+    fa.k1 = bref(s->kb[0]);
+    fa.m_in = fa.m0;
+    fa.m_out = S > 1 ? bref(s->ms[0]) : bref_cur(s->mbuf[0], s->mbuf[1], 2);
+    HIPCHK(s, row_fwd(s, p, fa));
+    for (int st = 2; st <= S; ++st) {
+        if (p.demag_on && (rc = launch_spectral(s)) != LLG_OK) return rc;
+        StageArgs sa = {};
+        sa.mode = ROW_STAGE;
+        sa.m0 = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+        sa.m_in = bref(s->ms[st % 2 == 0 ? 0 : 1]);
+        sa.m_out = st == S ? bref_cur(s->mbuf[0], s->mbuf[1], 2) : bref(s->ms[st % 2 == 0 ? 1 : 0]);
+        sa.k_out = bref(st < S ? s->kb[st - 1] : nullptr);
+        sa.nk = st;
+        for (int j = 0; j + 1 < st; ++j) sa.kprev[j] = bref(s->kb[j]);
+        for (int j = 0; j < st; ++j) sa.a[j] = (float)(st < S ? t.A[st][j] : t.b[j]);
+        HIPCHK(s, row_inv(s, p, sa));
+    }
+    HIPCHK(s, launch_ctrl_dm_accept(s->st, S, s->stream));
     return LLG_OK;
 }
 
@@ -822,6 +865,122 @@ llg_status llg_run_attempts(llg_solver* s, double t_end, double max_err, double 
     return run_adaptive(s, LLG_RKDP45, t_end, max_err, dt0, max_attempts, out);
 }
 
+llg_status llg_run_dm(llg_solver* s, llg_method method, double t_end, double max_dm, double dt_max,
+                      llg_stats* out) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    Tableau tf;
+    if (!fixed_of(method, &tf)) return fail(s, LLG_E_ARG, "llg_run_dm takes Euler, Heun, RK3 or RK4");
+    if (!(max_dm > 0) || !(dt_max > 0) || !isfinite(t_end) || !isfinite(max_dm) || !isfinite(dt_max))
+        return fail(s, LLG_E_ARG, "need max_dm > 0, dt_max > 0");
+    if ((rc = ready(s, true)) != LLG_OK) return rc;
+    if ((rc = ensure_kernel(s)) != LLG_OK) return rc;
+    const Phys p = make_phys(s, 0.0);   // thermal field: fixed steps only
+    DevState h;
+    if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    if (h.health) return fail(s, LLG_E_DIVERGED, "state already diverged");
+    if (!(t_end > h.t)) {
+        if (out) fill_stats(h, out);
+        return LLG_OK;
+    }
+    h.t_end = t_end;
+    h.tol = max_dm;
+    h.dt_max = dt_max;
+    h.gms = kGamma0 * s->Ms;
+    h.done = 0;
+    h.clipped = 0;
+    h.err_bits = 0u;
+    if ((rc = write_state(s, &h)) != LLG_OK) return rc;
+    if (p.demag_on && !s->spec_valid)
+        if ((rc = launch_fwd_plain(s, 1)) != LLG_OK) return rc;
+    if (!s->gdm.exec || s->gdm.method != (int)method) {
+        if ((rc = capture(s, s->gdm, enqueue_dm_step, tf, p)) != LLG_OK) return rc;
+        s->gdm.method = (int)method;
+    }
+    int done = 0;
+    long long launched = 0;
+    while (!done && launched < (1LL << 32)) {
+        for (int i = 0; i < 8; ++i) HIPCHK(s, hipGraphLaunch(s->gdm.exec, s->stream));
+        launched += 8;
+        HIPCHK(s, hipMemcpyAsync(&done, &s->st->done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+        if ((rc = sync(s)) != LLG_OK) return rc;
+    }
+    if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    s->spec_valid = p.demag_on != 0;
+    s->k1_valid = false;
+    if (out) fill_stats(h, out);
+    if (h.health) return fail(s, LLG_E_DIVERGED, "non-finite field or torque");
+    return LLG_OK;
+}
+
+llg_status llg_get_state(llg_solver* s, llg_state* out, float* m, llg_mem where) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!out) return fail(s, LLG_E_ARG, "null output");
+    if (!s->have_m) return fail(s, LLG_E_STATE, "magnetisation not set");
+    DevState h;
+    if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    llg_state o = {};
+    o.t = h.t;
+    o.dt = h.dt;
+    o.dt_next = h.dt_next;
+    o.last_err = h.last_err;
+    o.step = h.step;
+    o.steps = h.nsteps;
+    o.rejected = h.nrej;
+    o.evals = h.nevals;
+    o.health = h.health;
+    *out = o;
+    if (m) {
+        const size_t bytes = sizeof(float) * 3 * (size_t)s->g.ncells;
+        HIPCHK(s, hipMemcpyAsync(m, s->mbuf[h.cur], bytes, where == LLG_DEVICE ? hipMemcpyDeviceToDevice
+                                                                               : hipMemcpyDeviceToHost, s->stream));
+        return sync(s);
+    }
+    return LLG_OK;
+}
+
+llg_status llg_set_state(llg_solver* s, const llg_state* in, const float* m, llg_mem where) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!in || !m) return fail(s, LLG_E_ARG, "null state or m");
+    if (!s->have_geom) return fail(s, LLG_E_STATE, "geometry not set");
+    if (in->health != 0 || !isfinite(in->t) || !(in->dt >= 0) || !(in->dt_next >= 0) || !isfinite(in->dt) ||
+        !isfinite(in->dt_next) || in->step < 0 || in->steps < 0 || in->rejected < 0 || in->evals < 0)
+        return fail(s, LLG_E_ARG, "state record is not that of a healthy run");
+    const size_t bytes = sizeof(float) * 3 * (size_t)s->g.ncells;
+    HIPCHK(s, hipMemcpyAsync(s->mbuf[0], m, bytes, where == LLG_DEVICE ? hipMemcpyDeviceToDevice
+                                                                        : hipMemcpyHostToDevice, s->stream));
+    int zero = 0, bad = 0;
+    HIPCHK(s, hipMemcpyAsync(s->dflag, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, launch_check_unit(s->mbuf[0], s->g.ncells, s->dflag, s->stream));
+    HIPCHK(s, hipMemcpyAsync(&bad, s->dflag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    if ((rc = sync(s)) != LLG_OK) return rc;
+    if (bad) {
+        s->have_m = false;
+        return fail(s, LLG_E_ARG, "m is not a field of unit vectors (| |m| - 1 | > 1e-3 or non-finite)");
+    }
+    DevState h = {};
+    h.cur = 0;
+    h.log = s->log;
+    h.log_cap = s->log_cap;
+    h.gms = kGamma0 * (s->have_mat ? s->Ms : 0.0);
+    h.t = in->t;
+    h.dt = in->dt;
+    h.dt_next = in->dt_next;
+    h.last_err = in->last_err;
+    h.step = in->step;
+    h.nsteps = in->steps;
+    h.nrej = in->rejected;
+    h.nevals = in->evals;
+    if ((rc = write_state(s, &h)) != LLG_OK) return rc;
+    s->have_m = true;
+    s->spec_valid = false;
+    s->k1_valid = false;
+    s->last_dt = in->dt;
+    return LLG_OK;
+}
+
 llg_status llg_get_stats(llg_solver* s, llg_stats* out) {
     llg_status rc = enter(s);
     if (rc != LLG_OK) return rc;
@@ -1067,8 +1226,8 @@ llg_status run_adaptive(llg_solver* s, int method, double t_end, double max_err,
     llg_status rc;
     Adaptive ad;
     if (!adaptive_of(method, &ad)) return fail(s, LLG_E_ARG, "method %d is not an adaptive pair", method);
-    if (!(max_err > 0) || !(dt0 > 0) || !isfinite(t_end) || !isfinite(max_err) || !isfinite(dt0))
-        return fail(s, LLG_E_ARG, "need max_err > 0, dt0 > 0");
+    if (!(max_err > 0) || !(dt0 >= 0) || !isfinite(t_end) || !isfinite(max_err) || !isfinite(dt0))
+        return fail(s, LLG_E_ARG, "need max_err > 0, dt0 >= 0");
     if ((rc = ready(s, true)) != LLG_OK) return rc;
     if ((rc = ensure_kernel(s)) != LLG_OK) return rc;
     const Phys p = make_phys(s, 0.0);   // thermal field: fixed steps only
@@ -1085,6 +1244,11 @@ llg_status run_adaptive(llg_solver* s, int method, double t_end, double max_err,
         if ((rc = ensure_k1(s, p)) != LLG_OK) return rc;
     }
     if ((rc = read_state(s, &h)) != LLG_OK) return rc;
+    if (dt0 == 0) {
+        // continue with the step the controller chose last
+        if (!(h.dt_next > 0)) return fail(s, LLG_E_STATE, "dt0 = 0 needs an earlier adaptive step");
+        dt0 = h.dt_next;
+    }
     h.ev_attempt = ad.fsal ? ad.t.S - 1 : ad.t.S;
     h.ctrl_exp = 1.0 / (ad.q + 1);
     h.t_end = t_end;

@@ -435,3 +435,55 @@ def test_stt_adiabatic_spiral_rotates_rigidly():
     th = q * np.arange(n) * dx + w * t
     want = np.stack([np.cos(th), np.sin(th), np.zeros(n)])
     np.testing.assert_allclose(o.m.reshape(3, -1), want, atol=1e-9)
+
+
+def test_dm_controller_macrospin_closed_form():
+    """Bounded variation of m per step (Sec. 2.2) on an undamped macrospin:
+    |dm/dt| = gamma0 H sin(theta0) all along the precession, so every step is
+    max_dm / (gamma0 H sin theta0), the last one shortened to land on t_end,
+    and RK4 along those steps follows the closed-form precession."""
+    Bz, th0 = 0.1, 1.0
+    prob, m0 = _macrospin(0.0, Bz, theta0=th0)
+    s = llg.Solver(prob, m0)
+    max_dm, t_end = 1e-2, 2e-10
+    rec = s.run_dm("rk4", t_end, max_dm, dt_max=1e-9)
+    h = max_dm / (GAMMA0 * Bz / MU0 * math.sin(th0))
+    assert s.t == t_end
+    assert len(rec) == math.ceil(t_end / h)
+    for dt, own in rec[:-1]:
+        assert dt == own
+        assert dt == pytest.approx(h, rel=1e-9)
+    assert rec[-1][0] == pytest.approx(t_end - (len(rec) - 1) * h, rel=1e-6)
+    np.testing.assert_allclose(s.m[:, 0, 0, 0], _macrospin_exact(0.0, Bz, t_end, theta0=th0), atol=1e-8)
+
+
+def test_dm_controller_first_step_with_damping_and_cap():
+    """Damped macrospin: m x H and m x (m x H) are orthogonal and of equal
+    length, so |dm/dt| = gamma0 H sin(theta0) / sqrt(1 + alpha^2) and the
+    first step is max_dm sqrt(1 + alpha^2) / (gamma0 H sin theta0); dt_max
+    caps it."""
+    alpha, Bz, th0 = 0.5, 0.1, 1.0
+    prob, m0 = _macrospin(alpha, Bz, theta0=th0)
+    s = llg.Solver(prob, m0)
+    dt, _ = s.dm_step(1e-2, 1.0, 1.0)
+    assert dt == pytest.approx(1e-2 * math.sqrt(1 + alpha ** 2) / (GAMMA0 * Bz / MU0 * math.sin(th0)), rel=1e-12)
+    assert s.dm_step(1e-2, 1e-13, 1.0)[0] == 1e-13
+    assert s.dm_step(1e-2, 1.0, 1e-14)[0] == 1e-14          # time left
+    still = llg.Solver(_macrospin(alpha, Bz, theta0=0.0)[0], np.array([0.0, 0.0, 1.0]).reshape(3, 1, 1, 1))
+    assert still.dm_step(1e-2, 3e-12, 1.0)[0] == 3e-12      # no torque: the cap
+
+
+def test_dm_controller_bounds_the_change_of_every_cell():
+    """Euler on a random film: the torque is orthogonal to m, so a step of
+    size dt |k| = d moves a cell by 2 - 2/sqrt(1 + d^2) squared, i.e. by at
+    most d and by d (1 - O(d^2)) for the fastest cell, whose d is max_dm."""
+    prob, m0 = workloads.small_problem(n=(8, 6, 1), alpha=0.5)
+    s = llg.Solver(prob, m0)
+    max_dm = 1e-2
+    for _ in range(10):
+        before = s.m.copy()
+        dt, _ = s.dm_step(max_dm, 1e-9, 1.0)
+        s.run_dm("euler", 1.0, max_dm, 1e-9, dts=[dt])
+        d = np.sqrt(np.sum((s.m - before) ** 2, axis=0))
+        assert d.max() <= max_dm * (1 + 1e-12)
+        assert d.max() >= max_dm * (1 - max_dm ** 2)
