@@ -288,10 +288,13 @@ llg_status llg_demag_tensor(llg_solver *s, const int32_t *offsets, int64_t count
  * all films; each film keeps its own step size, accept/reject decisions,
  * time and attempt log on the device, and its arithmetic is that of the
  * single-film solver (same kernels, same order), so results do not depend
- * on the batch composition.  Film sizes must have compiled FFT lengths
- * (padded lengths 2^n or 3*2^n between 64 and 1024; e.g. sides 32, 48,
- * 64, 96, 128, 192, 256, 384, 512), else llg_batch_create returns
- * LLG_E_UNSUPPORTED.
+ * on the batch composition.  Each axis of a film is zero padded to the
+ * shortest compiled FFT length >= 2 n (x: 64, 128, 192, 256, 384, 512, 768,
+ * 1024; y: twice 32, 64, 96, 128, 192, 256, 384, 512), which leaves the
+ * convolution unchanged (Sec. 3.2 needs only >= 2 n - 1); where that is also
+ * the single-film solver's padding (sides 32, 64, 96, 128, 192, 256, 384,
+ * 512) a batched film equals the single-film run bit for bit.  Sides beyond
+ * 512 give LLG_E_UNSUPPORTED.
  */
 typedef struct llg_batch llg_batch;
 
@@ -311,7 +314,8 @@ llg_status  llg_batch_create(int device, const llg_film_desc *films, int nfilms,
 void        llg_batch_destroy(llg_batch *b);
 const char *llg_batch_last_error(const llg_batch *b);
 /* Advances every film toward t_end (s) with tolerance max_err; dt0 is each
- * film's first attempted step of this call.  Stops when all films are done
+ * film's first attempted step of this call (dt0 = 0: each film's controller's
+ * last choice, LLG_E_STATE if a film has none).  Stops when all films are done
  * or after max_attempts attempts (<= 0: no limit).  per_film (host, nfilms
  * entries) may be NULL.  LLG_E_DIVERGED if any film diverged. */
 llg_status  llg_batch_run(llg_batch *b, double t_end, double max_err, double dt0,

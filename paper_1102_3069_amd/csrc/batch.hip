@@ -382,8 +382,13 @@ llg_status llg_batch_create(int device, const llg_film_desc* films, int nfilms, 
             return bfail(b, LLG_E_ARG, "film %d: invalid parameters", i);
         const double un = sqrt(d.u[0] * d.u[0] + d.u[1] * d.u[1] + d.u[2] * d.u[2]);
         if (!(un > 0)) return bfail(b, LLG_E_ARG, "film %d: anisotropy axis must be non-zero", i);
-        const int Px = pad_len(d.nx), Py = pad_len(d.ny);
-        const int L = Py / 2;
+        // each axis is padded to the shortest compiled length >= 2 n
+        const int Px = fast2d_row_len_at_least(pad_len(d.nx));
+        const int L = fast2d_col_len_at_least(pad_len(d.ny) / 2);
+        const int Py = 2 * L;
+        if (Px == 0 || L == 0)
+            return bfail(b, LLG_E_UNSUPPORTED, "film %d: %d x %d exceeds the compiled batched lengths", i, d.nx,
+                         d.ny);
         f.rvar = fast2d_row_variant(Px);
         f.cvar = fast2d_col_variant(L);
         if (!fast2d_row_ok(Px, f.rvar) || !fast2d_col_ok(L, 1, f.cvar) || (Px / 2) % fast2d_col_width(L, f.cvar) ||
@@ -483,7 +488,8 @@ llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0,
     if (!b) return LLG_E_ARG;
     b->err.clear();
     BCHK(b, hipSetDevice(b->device));
-    if (!(max_err > 0) || !(dt0 > 0) || !isfinite(t_end)) return bfail(b, LLG_E_ARG, "need max_err > 0, dt0 > 0");
+    if (!(max_err > 0) || !(dt0 >= 0) || !isfinite(t_end) || !isfinite(dt0))
+        return bfail(b, LLG_E_ARG, "need max_err > 0, dt0 >= 0");
     const int nf = (int)b->films.size();
     std::vector<DevState> h;
     llg_status rc = read_states(b, h);
@@ -505,8 +511,11 @@ llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0,
         s.dt_min = kDtMin;
         s.err_bits = 0u;
         s.done = !(t_end > s.t);
+        // dt0 = 0: each film continues with its controller's last choice
+        const double first = dt0 > 0 ? dt0 : s.dt_next;
+        if (!(first > 0) && !s.done) return bfail(b, LLG_E_STATE, "dt0 = 0 needs an earlier adaptive step");
         const double rem = t_end - s.t;
-        if (dt0 >= rem) { s.dt = rem; s.clipped = 1; } else { s.dt = dt0; s.clipped = 0; }
+        if (first >= rem) { s.dt = rem; s.clipped = 1; } else { s.dt = first; s.clipped = 0; }
         s.dtau = (float)(s.dt * s.gms);
     }
     if ((rc = write_states(b, h)) != LLG_OK) return rc;

@@ -902,6 +902,24 @@ int fast2d_row_classes(int Px, int var) {
 #undef CASE
     return 0;
 }
+// smallest compiled row length Px >= n, and column half length L >= n
+// (0 if there is none): zero padding beyond 2 n - 1 leaves the convolution
+// unchanged, so a film may use a longer compiled transform
+int fast2d_row_len_at_least(int n) {
+    int best = 0;
+#define CASE(PX, E, NQ, V) if (V == 0 && PX >= n && (best == 0 || PX < best)) best = PX;
+    ROW_VARIANTS(CASE)
+#undef CASE
+    return best;
+}
+int fast2d_col_len_at_least(int n) {
+    int best = 0;
+#define CASE(LL, E, NQ, V) if (V == 0 && LL >= n && (best == 0 || LL < best)) best = LL;
+    COL_VARIANTS(CASE)
+#undef CASE
+    return best;
+}
+
 int fast2d_col_width(int L, int var) {
     if (var < 0) var = fast2d_col_variant(L);
 #define CASE(LL, E, NQ, V) if (L == LL && var == V) return ColSplit<LL, E, NQ>::W;

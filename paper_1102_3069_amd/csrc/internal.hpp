@@ -204,6 +204,8 @@ struct FilmCol {
 };
 int fast2d_row_rows_per_block(int Px, int var);
 int fast2d_row_classes(int Px, int var = -1);
+int fast2d_row_len_at_least(int n);
+int fast2d_col_len_at_least(int n);
 int fast2d_col_width(int L, int var = -1);
 hipError_t launch_row_fwd_group(int Px, int var, const FilmRow* films, const int2* map, int nblocks,
                                 hipStream_t s);

@@ -69,11 +69,61 @@ def test_batch_film_matches_oracle(lib):
         assert e <= 1e-5
 
 
-def test_batch_rejects_uncompiled_sizes(lib):
-    prob, m0 = workloads.small_problem(n=(17, 9, 1))
+def test_batch_rejects_sizes_beyond_the_compiled_lengths(lib):
+    prob, m0 = workloads.small_problem(n=(600, 4, 1))
     with pytest.raises(lib.LLGError) as e:
         lib.Batch([(prob, m0)])
     assert e.value.code == lib.LLG_E_UNSUPPORTED
+
+
+def test_batch_ragged_sizes_match_oracle(lib):
+    """Films whose 2n is no compiled length are padded further (17 x 9 to
+    64 x 64, 40 x 8 to 128 x 64, ...); the convolution is unchanged, so each
+    film still follows the oracle, which replays its attempts, to 1e-5."""
+    films = []
+    for n, seed in [((17, 9, 1), 1), ((40, 8, 1), 2), ((150, 30, 1), 3)]:
+        prob, m0 = workloads.small_problem(n=n, seed=seed, alpha=0.5)
+        films.append((prob, m0))
+    b = lib.Batch(films)
+    st = b.run(2e-12, 1e-5, 1e-14)
+    assert all(s["done"] == 1 for s in st)
+    for i, (prob, m0) in enumerate(films):
+        o = ollg.Solver(prob, m0)
+        o.replay([(dt, ok) for dt, _, ok in b.attempts(i)])
+        e = maxrel(b.get_m(i), o.m)
+        print("ragged film", prob["n"], "attempts", len(b.attempts(i)), "m maxrel vs oracle", e, flush=True)
+        assert e <= 1e-5
+
+
+def test_sp2_shaped_films_match_oracle(lib):
+    """Four films of the relaxation sweep (d/l_ex = 1, 10.7, 20.3, 30; alpha
+    = 1, demag and exchange only, from [1,1,1]): 5 ps in one batch, each
+    film replayed by the oracle to 1e-5."""
+    films, run = workloads.sp2_films(count=4)
+    b = lib.Batch(films)
+    st = b.run(5e-12, run["tol"], run["dt0"])
+    assert all(s["done"] == 1 for s in st)
+    for i, (prob, m0) in enumerate(films):
+        o = ollg.Solver(prob, m0)
+        o.replay([(dt, ok) for dt, _, ok in b.attempts(i)])
+        e = maxrel(b.get_m(i), o.m)
+        print("sp2 film d/lex", round(prob["d_over_lex"], 2), prob["n"], "attempts", len(b.attempts(i)),
+              "m maxrel vs oracle", e, flush=True)
+        assert e <= 1e-5
+
+
+def test_batch_continues_with_each_films_step(lib):
+    """Stopping after 5 attempts and continuing with dt0 = 0 (each film's own
+    next step) equals the uninterrupted run bit for bit."""
+    films = sweep((32, 64, 96), 9)
+    a = lib.Batch(films)
+    a.run(3e-12, 1e-5, 1e-14)
+    b = lib.Batch(films)
+    b.run(3e-12, 1e-5, 1e-14, max_attempts=5)
+    b.run(3e-12, 1e-5, 0.0)
+    for i in range(len(films)):
+        assert b.attempts(i) == a.attempts(i)
+        assert np.array_equal(b.get_m(i), a.get_m(i))
 
 
 def test_full_sweep_creates_and_steps(lib):

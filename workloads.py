@@ -113,6 +113,31 @@ def film_batch(nfilms=64, seed=4, sizes=(64, 96, 128, 192, 256)):
     return films, run
 
 
+def sp2_films(count=200, r_min=1.0, r_max=30.0, max_width=64):
+    """Films shaped like the static standard problem of Sec. 4.1: a cuboid of
+    5d x d x 0.1d with only demag and exchange, saturated along [1,1,1] at
+    the start and relaxed with alpha = 1, for `count` values of d/l_ex evenly
+    spaced in [r_min, r_max] (l_ex = sqrt(2A/(mu0 Ms^2)), 5.7 nm for the
+    material used here; only d/l_ex matters).  Cells: ny = clamp(ceil(2 d/l_ex),
+    4, max_width) across the width, so the cell edge stays at or below half
+    the exchange length up to d/l_ex = max_width/2; nx = 5 ny; one cell
+    through the thickness.  The paper ran 200 such relaxations."""
+    Ms, A = 8.0e5, 1.3e-11
+    lex = math.sqrt(2.0 * A / (4e-7 * math.pi * Ms * Ms))
+    films = []
+    for k in range(count):
+        r = r_min + (r_max - r_min) * k / max(count - 1, 1)
+        d = r * lex
+        ny = min(max(int(math.ceil(2.0 * r)), 4), max_width)
+        nx = 5 * ny
+        c = d / ny
+        prob = dict(n=(nx, ny, 1), cell=(c, c, 0.1 * d), pbc=(False, False, False), Ms=Ms, Aex=A,
+                    alpha=1.0, Ku=0.0, u=(1.0, 0.0, 0.0), B=(0.0, 0.0, 0.0), T=0.0, seed=0, d_over_lex=r)
+        films.append((prob, uniform((nx, ny, 1), (1.0, 1.0, 1.0))))
+    run = dict(methods=("rkdp45",), t_end=1e-9, tol=1e-5, dt0=1e-14)
+    return films, run
+
+
 def surrogate_films(ntraj, seed=5, n_side=256):
     """Trajectories for the learned surrogate: the thin film of film_512 at
     n x n cells, each with its own applied field of magnitude U[0, 50] mT at
