@@ -341,9 +341,19 @@ llg_status  llg_batch_get_attempts(llg_batch *b, int film, llg_attempt *out, int
  * plain solver; the network only decides how far a round may jump.
  *
  * Network: six 3x3 convolutions with zero ("same") padding,
- *   6 -> 32, four times 32 -> 32, 32 -> 3, SiLU after all but the last;
- *   input (m_x, m_y, m_z, B_x, B_y, B_z) / (1, 1, 1, 50 mT, 50 mT, 50 mT)
- *   per cell, output dm; proposal m' = (m + dm) / |m + dm|.
+ *   9 -> 32, four times 32 -> 32, 32 -> 3, SiLU after all but the last;
+ *   input per cell: m as a BF16 pair, hi = bf16(m) and lo = bf16(256 (m - hi))
+ *   (3 + 3 channels, so the first layer resolves m to about 16 bits), and
+ *   B / 50 mT (3)
+ *   per cell, output z; dm = scale * z (llg_sur_set_output_scale, default
+ *   1); proposal m' = (base + dm) / |base + dm|, where the
+ *   base is m itself (LLG_SUR_BASE_STATE) or one coarse step of the whole
+ *   segment length T by the plain solver: Euler (LLG_SUR_BASE_EULER, one
+ *   H_eff evaluation) or classical RK4 (LLG_SUR_BASE_RK4, four).  A coarse
+ *   step carries the bulk of the motion, including the long-range demag
+ *   field the network's 13 x 13-cell receptive field cannot see, and leaves
+ *   the network the correction.  Chained Euler steps of T = 1 ps amplify the
+ *   stiff exchange modes, so long chains of proposals need the RK4 base.
  * Parameters (FP32, host layout of llg_sur_set_params): per layer the
  * weights [cout][cin][3][3] (cross-correlation: out[o][y][x] = b[o] +
  * sum w[o][c][u][v] in[c][y+u-1][x+v-1]) followed by the bias [cout].
@@ -353,6 +363,8 @@ llg_status  llg_batch_get_attempts(llg_batch *b, int film, llg_attempt *out, int
  * llg_film_desc.m0 ([3][H][W] float); batches of states are contiguous.
  */
 typedef struct llg_sur llg_sur;
+
+enum { LLG_SUR_BASE_STATE = 0, LLG_SUR_BASE_EULER = 1, LLG_SUR_BASE_RK4 = 2 };
 
 typedef struct {
     int64_t rounds;          /* verification rounds (one batched plain launch each) */
@@ -368,24 +380,30 @@ typedef struct {
 llg_status  llg_sur_create(int device, int H, int W, int max_batch, llg_sur **out);
 void        llg_sur_destroy(llg_sur *s);
 const char *llg_sur_last_error(const llg_sur *s);
-/* Number of FP32 parameters (39,619). */
+/* Number of FP32 parameters (40,483). */
 int64_t     llg_sur_num_params(void);
 /* Host arrays of llg_sur_num_params() floats.  set_params also clears the
  * Adam moments and step count. */
 llg_status  llg_sur_set_params(llg_sur *s, const float *params, int64_t n);
 llg_status  llg_sur_get_params(llg_sur *s, float *params, int64_t n);
+/* Scale > 0 of the network output: dm = scale * z.  A base that already
+ * lands close (a coarse RK4 step leaves ~1e-4) needs a small scale so that
+ * the BF16 activations resolve the correction.  LLG_E_ARG otherwise. */
+llg_status  llg_sur_set_output_scale(llg_sur *s, double scale);
 /* Gradient of the last llg_sur_train_step, parameter layout. */
 llg_status  llg_sur_get_grads(llg_sur *s, float *grads, int64_t n);
-/* Loss L = mean over cells, components and states of (dm - (m_target -
- * m_in))^2 and its gradient for `batch` pairs (m_in, m_target) with applied
- * fields B[batch][3] (tesla, host); then, if lr > 0, one Adam step with
- * learning rate lr.  m_in and m_target in host or device memory per
- * `where`.  *loss (host, may be NULL) receives L. */
-llg_status  llg_sur_train_step(llg_sur *s, const float *m_in, const float *m_target, const float *B,
-                               int batch, llg_mem where, float lr, float *loss);
-/* Proposals m' for `batch` states (host or device memory per `where`). */
-llg_status  llg_sur_predict(llg_sur *s, const float *m_in, const float *B, int batch, llg_mem where,
-                            float *m_out);
+/* Loss L = mean over cells, components and states of (z - (m_target -
+ * base) / scale)^2 and its gradient for `batch` triples (m_in, m_target, m_base)
+ * with applied fields B[batch][3] (tesla, host); m_base NULL means base =
+ * m_in.  Then, if lr > 0, one Adam step with learning rate lr.  The state
+ * arrays are in host or device memory per `where`.  *loss (host, may be
+ * NULL) receives L. */
+llg_status  llg_sur_train_step(llg_sur *s, const float *m_in, const float *m_target, const float *m_base,
+                               const float *B, int batch, llg_mem where, float lr, float *loss);
+/* Proposals m' = normalize(base + scale z(m_in)) for `batch` states (host or
+ * device memory per `where`; m_base NULL means base = m_in). */
+llg_status  llg_sur_predict(llg_sur *s, const float *m_in, const float *m_base, const float *B, int batch,
+                            llg_mem where, float *m_out);
 /* Pre-activation of layer `layer` (0..5) for host inputs, [batch][H][W][32]
  * float into host memory (channels past the layer's width are 0). */
 llg_status  llg_sur_forward_raw(llg_sur *s, const float *m_in, const float *B, int batch, int layer,
@@ -398,14 +416,16 @@ llg_status  llg_sur_conv_check(llg_sur *s, int layer, const float *x, const floa
 /* Advances the state m (host or device per `where`, overwritten) of `film`
  * (its m0 is ignored; its size must be the network's) by n_segments
  * segments of seg_steps RK4 steps of dt (s).  A round chains up to `window`
- * proposals m'_1..m'_w from the current state m'_0; one batched plain launch
+ * proposals m'_1..m'_w from the current state m'_0, each with the base
+ * `predictor` (an LLG_SUR_BASE_* value, coarse steps with T = seg_steps dt;
+ * LLG_E_ARG otherwise); one batched plain launch
  * advances m'_0..m'_{w-1} by a segment each, giving p_1..p_w; d_j = max over
  * cells |m'_j - p_j|.  With j* the first j where d_j > max_dm (or w + 1),
  * the round commits p_{min(j*, w)} and advances min(j*, w) segments.  With
  * max_dm = 0 every round commits p_1, the plain segment.  `out` may be
  * NULL. */
 llg_status  llg_sur_advance(llg_sur *s, const llg_film_desc *film, int window, int64_t n_segments,
-                            int seg_steps, double dt, double max_dm, float *m, llg_mem where,
+                            int seg_steps, double dt, int predictor, double max_dm, float *m, llg_mem where,
                             llg_sur_stats *out);
 /* Diagnostic: one 16x32 by 32x16 product (row-major float inputs rounded to
  * BF16, host) by a single MFMA instruction, to check its lane layout. */

@@ -4,11 +4,15 @@ Adam update.
 TEST INFRASTRUCTURE ONLY (see the package docstring).  The surrogate is not
 part of the paper; it is the learned multi-step proposer of this project:
 
-    input  x (6 channels): m (3) and the applied field B / 50 mT (3)
-    net    conv3x3(6->32) SiLU, 4 x [conv3x3(32->32) SiLU], conv3x3(32->3)
+    input  x (9 channels): m as a pair (hi, lo) with hi = m rounded to BF16
+           (nearest, ties to even) and lo = 256 (m - hi) (m taken in FP32),
+           then the applied field B / 50 mT (3)
+    net    conv3x3(9->32) SiLU, 4 x [conv3x3(32->32) SiLU], conv3x3(32->3)
            ("same" size, zero padding outside the film)
-    output dm (3 channels); proposal m' = normalize(m + dm)
-    loss   mean over pixels and channels of (dm - (m_target - m))^2
+    output z (3 channels), dm = scale z; proposal m' = normalize(base + dm),
+           with base either m or the solver's one coarse step over the whole
+           segment (computed by the caller)
+    loss   mean over pixels and channels of (z - (m_target - base)/scale)^2
     Adam   lr, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected
 
 Layout here: activations (C, H, W) per sample, weights (Cout, Cin, 3, 3),
@@ -16,7 +20,7 @@ cross-correlation: y[o, i, j] = b[o] + sum_{c,u,v} w[o, c, u, v] x[c, i+u-1, j+v
 """
 import numpy as np
 
-LAYERS = ((6, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3))
+LAYERS = ((9, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3))
 B_SCALE = 0.05   # tesla: the applied field enters as B / 50 mT
 
 
@@ -68,10 +72,22 @@ def init_params(seed=0):
     return params
 
 
+def round_bf16(a):
+    """Nearest BF16 value of float32 a (ties to even): keep the upper 16 bits
+    of the IEEE single after adding half a unit of the dropped part."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
 def net_input(m, B):
-    """m (3, H, W), B (3,) tesla -> x (6, H, W)."""
+    """m (3, H, W), B (3,) tesla -> x (9, H, W): (hi, lo) of m, B / 50 mT."""
     H, W = m.shape[1:]
-    return np.concatenate([m, np.broadcast_to((np.asarray(B) / B_SCALE).reshape(3, 1, 1), (3, H, W))])
+    m32 = np.asarray(m, dtype=np.float32)
+    hi = round_bf16(m32)
+    lo = (m32 - hi) * np.float32(256.0)
+    return np.concatenate([hi.astype(np.float64), lo.astype(np.float64),
+                           np.broadcast_to((np.asarray(B) / B_SCALE).reshape(3, 1, 1), (3, H, W))])
 
 
 def forward(params, x):
@@ -119,8 +135,8 @@ def adam_step(params, grads, state, lr, t, b1=0.9, b2=0.999, eps=1e-8):
     return new
 
 
-def propose(params, m, B):
-    """m' = normalize(m + net(m, B))."""
-    dm, _, _ = forward(params, net_input(m, B))
-    mm = m + dm
+def propose(params, m, B, base=None, scale=1.0):
+    """m' = normalize(base + scale net(m, B)), base = m unless given."""
+    z, _, _ = forward(params, net_input(m, B))
+    mm = (m if base is None else base) + scale * z
     return mm / np.linalg.norm(mm, axis=0, keepdims=True)

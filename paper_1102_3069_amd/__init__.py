@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libllg.so")
 
 LLG_OK, LLG_E_ARG, LLG_E_STATE, LLG_E_NOMEM, LLG_E_DEVICE, LLG_E_UNSUPPORTED, LLG_E_DIVERGED = range(7)
+LLG_SUR_BASE_STATE, LLG_SUR_BASE_EULER, LLG_SUR_BASE_RK4 = 0, 1, 2
 STATUS_NAMES = ["LLG_OK", "LLG_E_ARG", "LLG_E_STATE", "LLG_E_NOMEM", "LLG_E_DEVICE",
                 "LLG_E_UNSUPPORTED", "LLG_E_DIVERGED"]
 LLG_EULER, LLG_HEUN, LLG_RK4, LLG_RKDP45, LLG_RK12, LLG_RK3, LLG_RK23, LLG_RKCK = range(8)
@@ -133,15 +134,16 @@ _SIGNATURES = {
     "llg_sur_num_params": ([], ctypes.c_int64),
     "llg_sur_set_params": ([_P, _P, ctypes.c_int64], ctypes.c_int),
     "llg_sur_get_params": ([_P, _P, ctypes.c_int64], ctypes.c_int),
+    "llg_sur_set_output_scale": ([_P, ctypes.c_double], ctypes.c_int),
     "llg_sur_get_grads": ([_P, _P, ctypes.c_int64], ctypes.c_int),
-    "llg_sur_train_step": ([_P, _P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+    "llg_sur_train_step": ([_P, _P, _P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_float,
                             ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
-    "llg_sur_predict": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, _P], ctypes.c_int),
+    "llg_sur_predict": ([_P, _P, _P, _P, ctypes.c_int, ctypes.c_int, _P], ctypes.c_int),
     "llg_sur_forward_raw": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, _P], ctypes.c_int),
     "llg_sur_conv_check": ([_P, ctypes.c_int, _P, _P, ctypes.c_int, _P, _P, _P, _P], ctypes.c_int),
     "llg_sur_advance": ([_P, ctypes.POINTER(FilmDesc), ctypes.c_int, ctypes.c_int64, ctypes.c_int,
-                         ctypes.c_double, ctypes.c_double, _P, ctypes.c_int, ctypes.POINTER(SurStats)],
-                        ctypes.c_int),
+                         ctypes.c_double, ctypes.c_int, ctypes.c_double, _P, ctypes.c_int,
+                         ctypes.POINTER(SurStats)], ctypes.c_int),
     "llg_mfma_selftest": ([ctypes.c_int, _P, _P, _P], ctypes.c_int),
 }
 EXPORTS = tuple(_SIGNATURES)
@@ -471,7 +473,7 @@ class Surrogate:
     travel as a flat float32 vector in the layout of llg_sur_set_params; the
     helpers pack()/unpack() convert from/to a list of (w, b) per layer."""
 
-    LAYERS = ((6, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3))
+    LAYERS = ((9, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3))
 
     def __init__(self, H, W, max_batch=1, device=0):
         self._lib = load()
@@ -532,26 +534,40 @@ class Surrogate:
         self._chk(self._lib.llg_sur_get_grads(self._h, a.ctypes.data_as(_P), a.size))
         return a
 
-    def train_step(self, m_in, m_target, B, lr=0.0):
-        """m_in, m_target: (batch, 3, H, W) float32 (numpy or CUDA tensor);
+    def set_output_scale(self, scale):
+        """dm = scale * network output."""
+        self._chk(self._lib.llg_sur_set_output_scale(self._h, float(scale)))
+
+    def train_step(self, m_in, m_target, B, lr=0.0, m_base=None):
+        """m_in, m_target, m_base: (batch, 3, H, W) float32 (numpy or CUDA
+        tensor; m_base None: the loss target is m_target - m_in);
         B: (batch, 3) tesla.  Returns the loss."""
         Bh = np.ascontiguousarray(B, dtype=np.float32).reshape(-1, 3)
         pi, where = _ptr_mem(m_in)
         pt, where2 = _ptr_mem(m_target)
         assert where == where2
+        pb = None
+        if m_base is not None:
+            pb, where3 = _ptr_mem(m_base)
+            assert where3 == where
         loss = ctypes.c_float()
-        self._chk(self._lib.llg_sur_train_step(self._h, pi, pt, Bh.ctypes.data_as(_P), Bh.shape[0], where,
+        self._chk(self._lib.llg_sur_train_step(self._h, pi, pt, pb, Bh.ctypes.data_as(_P), Bh.shape[0], where,
                                                float(lr), ctypes.byref(loss)))
         return loss.value
 
-    def predict(self, m_in, B, out=None):
+    def predict(self, m_in, B, out=None, m_base=None):
+        """normalize(base + dm(m_in)), base = m_base or m_in."""
         Bh = np.ascontiguousarray(B, dtype=np.float32).reshape(-1, 3)
         pi, where = _ptr_mem(m_in)
+        pb = None
+        if m_base is not None:
+            pb, where3 = _ptr_mem(m_base)
+            assert where3 == where
         if out is None:
             assert where == LLG_HOST
             out = np.empty((Bh.shape[0], 3, self.H, self.W), np.float32)
         po, _ = _ptr_mem(out)
-        self._chk(self._lib.llg_sur_predict(self._h, pi, Bh.ctypes.data_as(_P), Bh.shape[0], where, po))
+        self._chk(self._lib.llg_sur_predict(self._h, pi, pb, Bh.ctypes.data_as(_P), Bh.shape[0], where, po))
         return out
 
     def forward_raw(self, m_in, B, layer):
@@ -581,9 +597,12 @@ class Surrogate:
                                                gb.ctypes.data_as(_P)))
         return y, gx, gw, gb
 
-    def advance(self, prob, m, n_segments, window=16, seg_steps=10, dt=1e-13, max_dm=1e-2):
+    def advance(self, prob, m, n_segments, window=16, seg_steps=10, dt=1e-13, max_dm=1e-2, predictor="rk4"):
         """Advances m (float32 (3, 1, H, W) numpy array or CUDA tensor, in
-        place for a tensor) by n_segments segments; returns (m, stats)."""
+        place for a tensor) by n_segments segments; returns (m, stats).
+        predictor: the proposal base, "rk4" or "euler" (one plain step of
+        that scheme over the whole segment) or "state" (the state itself)."""
+        pred = {"state": LLG_SUR_BASE_STATE, "euler": LLG_SUR_BASE_EULER, "rk4": LLG_SUR_BASE_RK4}[predictor]
         d = FilmDesc()
         keep = film_desc(prob, np.zeros((3, 1, self.H, self.W), np.float32), d)
         d.m0 = None
@@ -595,7 +614,7 @@ class Surrogate:
             pm, where = _ptr_mem(out)
         st = SurStats()
         self._chk(self._lib.llg_sur_advance(self._h, ctypes.byref(d), int(window), int(n_segments),
-                                            int(seg_steps), float(dt), float(max_dm), pm, where,
+                                            int(seg_steps), float(dt), pred, float(max_dm), pm, where,
                                             ctypes.byref(st)))
         del keep
         return out, st.as_dict()

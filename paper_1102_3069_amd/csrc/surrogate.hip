@@ -16,6 +16,7 @@
 // the Adam moments stay FP32.
 #include <hip/hip_runtime.h>
 
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -34,9 +35,10 @@ typedef unsigned short u16;
 
 constexpr int CH = 32;          // padded channel count of every activation
 constexpr int NL = 6;           // layers
-constexpr int CIN[NL] = {6, 32, 32, 32, 32, 32};
+constexpr int CIN[NL] = {9, 32, 32, 32, 32, 32};
 constexpr int COUT[NL] = {32, 32, 32, 32, 32, 3};
 constexpr float B_SCALE = 0.05f;
+constexpr float LO_SCALE = 256.0f;   // the low part of m is scaled by 2^8 before its own BF16 rounding
 
 // round-to-nearest-even FP32 -> BF16 bits (NaN kept quiet)
 __host__ __device__ inline u16 f2bf(float f) {
@@ -257,14 +259,22 @@ __global__ void make_input_kernel(const float* m, const float* B, u16* x, int N,
     const int n = (int)(i / ((size_t)H * W));
     const size_t p = i - (size_t)n * H * W;
     u16* xo = x + i * CH;
-    for (int c = 0; c < 3; ++c) xo[c] = f2bf(m[((size_t)n * 3 + c) * H * W + p]);
-    for (int c = 0; c < 3; ++c) xo[3 + c] = f2bf(B[n * 3 + c] / B_SCALE);
-    for (int c = 6; c < CH; ++c) xo[c] = 0;
+    // m as a BF16 pair: hi = bf16(m), lo = bf16(256 (m - hi)) (m - hi is
+    // exact in FP32), so the first layer sees m to about 16 bits
+    for (int c = 0; c < 3; ++c) {
+        const float v = m[((size_t)n * 3 + c) * H * W + p];
+        const u16 hi = f2bf(v);
+        xo[c] = hi;
+        xo[3 + c] = f2bf((v - bf2f(hi)) * LO_SCALE);
+    }
+    for (int c = 0; c < 3; ++c) xo[6 + c] = f2bf(B[n * 3 + c] / B_SCALE);
+    for (int c = 9; c < CH; ++c) xo[c] = 0;
 }
 
-// loss gradient of the mean squared error and per-block loss partials
-__global__ void loss_kernel(const float* zout, const float* m, const float* mt, float* g, float* part, int N, int H,
-                            int W) {
+// loss gradient of the mean squared error of the network output against
+// (m_target - base) / scale, and per-block loss partials
+__global__ void loss_kernel(const float* zout, const float* base, const float* mt, float* g, float* part, int N,
+                            int H, int W, float inv_scale) {
     __shared__ float red[256];
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t npx = (size_t)N * H * W;
@@ -277,7 +287,7 @@ __global__ void loss_kernel(const float* zout, const float* m, const float* mt, 
             float gv = 0.f;
             if (c < 3) {
                 const size_t q = ((size_t)n * 3 + c) * H * W + p;
-                const float d = zout[i * CH + c] - (mt[q] - m[q]);
+                const float d = zout[i * CH + c] - (mt[q] - base[q]) * inv_scale;
                 l += d * d;
                 gv = 2.0f * d * inv;
             }
@@ -300,15 +310,15 @@ __global__ void sum_kernel(const float* part, int n, float* out) {
     *out = s;
 }
 
-// proposals m' = normalize(m + dm)
-__global__ void propose_kernel(const float* m, const float* zout, float* mo, int N, int H, int W) {
+// proposals m' = normalize(base + scale * out)
+__global__ void propose_kernel(const float* base, const float* zout, float* mo, int N, int H, int W, float scale) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t npx = (size_t)N * H * W;
     if (i >= npx) return;
     const int n = (int)(i / ((size_t)H * W));
     const size_t p = i - (size_t)n * H * W;
     float v[3];
-    for (int c = 0; c < 3; ++c) v[c] = m[((size_t)n * 3 + c) * H * W + p] + zout[i * CH + c];
+    for (int c = 0; c < 3; ++c) v[c] = base[((size_t)n * 3 + c) * H * W + p] + scale * zout[i * CH + c];
     const float inv = rsqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     for (int c = 0; c < 3; ++c) mo[((size_t)n * 3 + c) * H * W + p] = v[c] * inv;
 }
@@ -408,8 +418,10 @@ struct llg_sur {
     float* dm_out = nullptr;
     long long adam_t = 0;
     bool packed = false;
+    float out_scale = 1.f;                     // dm = out_scale * network output
     // speculative verification
     llg_batch* vb = nullptr;                   // window films advanced by the plain solver
+    llg_batch* eb = nullptr;                   // one film: the Euler predictor
     llg_film_desc vdesc = {};                  // the film the batch was built for
     int vwin = 0;
     float* props = nullptr;                    // proposals: window + 1 states
@@ -559,6 +571,7 @@ void llg_sur_destroy(llg_sur* s) {
     if (s->props) (void)hipFree(s->props);
     if (s->dmax) (void)hipFree(s->dmax);
     if (s->vb) llg_batch_destroy(s->vb);
+    if (s->eb) llg_batch_destroy(s->eb);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -585,6 +598,12 @@ llg_status llg_sur_set_params(llg_sur* s, const float* params, int64_t n) {
     return LLG_OK;
 }
 
+llg_status llg_sur_set_output_scale(llg_sur* s, double scale) {
+    if (!s || !(scale > 0) || !isfinite(scale) || scale > 1e30) return LLG_E_ARG;
+    s->out_scale = (float)scale;
+    return LLG_OK;
+}
+
 llg_status llg_sur_get_params(llg_sur* s, float* params, int64_t n) {
     if (!s || !params) return LLG_E_ARG;
     if (n != s->nparam) return sfail(s, LLG_E_ARG, "expected %lld parameters", s->nparam);
@@ -604,26 +623,32 @@ llg_status llg_sur_get_grads(llg_sur* s, float* grads, int64_t n) {
 }
 
 // gradient of the loss (and optionally one Adam step) for a batch
-llg_status llg_sur_train_step(llg_sur* s, const float* m_in, const float* m_target, const float* B, int batch,
-                              llg_mem where, float lr, float* loss) {
+llg_status llg_sur_train_step(llg_sur* s, const float* m_in, const float* m_target, const float* m_base,
+                              const float* B, int batch, llg_mem where, float lr, float* loss) {
     if (!s || !m_in || !m_target || !B || batch < 1 || batch > s->maxb) return LLG_E_ARG;
     SCHK(s, hipSetDevice(s->device));
     if (!s->packed) return sfail(s, LLG_E_STATE, "parameters not set");
     const size_t npx = (size_t)batch * s->H * s->W;
     const float* mi = m_in;
     const float* mt = m_target;
+    const float* mb = m_base;
     if (where != LLG_DEVICE) {
         SCHK(s, hipMemcpyAsync(s->dm_in, m_in, npx * 3 * 4, hipMemcpyHostToDevice, s->stream));
         SCHK(s, hipMemcpyAsync(s->dm_t, m_target, npx * 3 * 4, hipMemcpyHostToDevice, s->stream));
         mi = s->dm_in;
         mt = s->dm_t;
+        if (m_base) {
+            SCHK(s, hipMemcpyAsync(s->dm_out, m_base, npx * 3 * 4, hipMemcpyHostToDevice, s->stream));
+            mb = s->dm_out;
+        }
     }
+    if (!mb) mb = mi;
     SCHK(s, hipMemcpyAsync(s->dB, B, (size_t)batch * 3 * 4, hipMemcpyHostToDevice, s->stream));
     llg_status rc = forward(s, mi, s->dB, batch);
     if (rc != LLG_OK) return rc;
     const int lb = (int)((npx + 255) / 256);
-    hipLaunchKernelGGL(loss_kernel, dim3(lb), dim3(256), 0, s->stream, s->z[NL - 1], mi, mt, s->g, s->part_l, batch,
-                       s->H, s->W);
+    hipLaunchKernelGGL(loss_kernel, dim3(lb), dim3(256), 0, s->stream, s->z[NL - 1], mb, mt, s->g, s->part_l, batch,
+                       s->H, s->W, 1.0f / s->out_scale);
     SCHK(s, hipGetLastError());
     hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, s->stream, s->part_l, lb, s->dloss);
     SCHK(s, hipGetLastError());
@@ -669,23 +694,30 @@ llg_status llg_sur_train_step(llg_sur* s, const float* m_in, const float* m_targ
     return LLG_OK;
 }
 
-llg_status llg_sur_predict(llg_sur* s, const float* m_in, const float* B, int batch, llg_mem where, float* m_out) {
+llg_status llg_sur_predict(llg_sur* s, const float* m_in, const float* m_base, const float* B, int batch,
+                           llg_mem where, float* m_out) {
     if (!s || !m_in || !B || !m_out || batch < 1 || batch > s->maxb) return LLG_E_ARG;
     SCHK(s, hipSetDevice(s->device));
     if (!s->packed) return sfail(s, LLG_E_STATE, "parameters not set");
     const size_t npx = (size_t)batch * s->H * s->W;
     const float* mi = m_in;
+    const float* mb = m_base;
     float* mo = m_out;
     if (where != LLG_DEVICE) {
         SCHK(s, hipMemcpyAsync(s->dm_in, m_in, npx * 3 * 4, hipMemcpyHostToDevice, s->stream));
         mi = s->dm_in;
         mo = s->dm_out;
+        if (m_base) {
+            SCHK(s, hipMemcpyAsync(s->dm_t, m_base, npx * 3 * 4, hipMemcpyHostToDevice, s->stream));
+            mb = s->dm_t;
+        }
     }
+    if (!mb) mb = mi;
     SCHK(s, hipMemcpyAsync(s->dB, B, (size_t)batch * 3 * 4, hipMemcpyHostToDevice, s->stream));
     llg_status rc = forward(s, mi, s->dB, batch);
     if (rc != LLG_OK) return rc;
-    hipLaunchKernelGGL(propose_kernel, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s->stream, mi,
-                       s->z[NL - 1], mo, batch, s->H, s->W);
+    hipLaunchKernelGGL(propose_kernel, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s->stream, mb,
+                       s->z[NL - 1], mo, batch, s->H, s->W, s->out_scale);
     SCHK(s, hipGetLastError());
     if (where != LLG_DEVICE) SCHK(s, hipMemcpyAsync(m_out, s->dm_out, npx * 3 * 4, hipMemcpyDeviceToHost, s->stream));
     SCHK(s, hipStreamSynchronize(s->stream));
@@ -794,9 +826,10 @@ float bits_to_float(unsigned u) {
 }  // namespace
 
 llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, int64_t n_segments, int seg_steps,
-                           double dt, double max_dm, float* m, llg_mem where, llg_sur_stats* out) {
+                           double dt, int predictor, double max_dm, float* m, llg_mem where, llg_sur_stats* out) {
     if (!s || !film || !m || window < 1 || window > 256 || n_segments < 0 || seg_steps < 1 || !(dt > 0) ||
-        !(max_dm >= 0))
+        !(max_dm >= 0) ||
+        (predictor != LLG_SUR_BASE_STATE && predictor != LLG_SUR_BASE_EULER && predictor != LLG_SUR_BASE_RK4))
         return LLG_E_ARG;
     s->err.clear();
     SCHK(s, hipSetDevice(s->device));
@@ -810,7 +843,9 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
     // the verification batch: `window` copies of the film
     if (!s->vb || s->vwin != window || !same_film(s->vdesc, *film)) {
         if (s->vb) llg_batch_destroy(s->vb);
+        if (s->eb) llg_batch_destroy(s->eb);
         s->vb = nullptr;
+        s->eb = nullptr;
         if (s->props) (void)hipFree(s->props);
         if (s->dmax) (void)hipFree(s->dmax);
         s->props = nullptr;
@@ -825,6 +860,13 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
             if (s->vb) llg_batch_destroy(s->vb);
             s->vb = nullptr;
             return sfail(s, rc, "verification batch: %s", why.c_str());
+        }
+        rc = llg_batch_create(s->device, fd.data(), 1, &s->eb);
+        if (rc != LLG_OK) {
+            const std::string why = s->eb ? llg_batch_last_error(s->eb) : "batch creation failed";
+            if (s->eb) llg_batch_destroy(s->eb);
+            s->eb = nullptr;
+            return sfail(s, rc, "predictor batch: %s", why.c_str());
         }
         s->vdesc = *film;
         s->vdesc.m0 = nullptr;
@@ -852,13 +894,29 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
     while (done < n_segments) {
         const int w = (int)std::min<int64_t>(window, n_segments - done);
         float* P = s->props;
-        // proposals 1..w, each from the previous one
+        // proposals 1..w, each from the previous one: normalize(base + dm)
+        // with base the previous state or its one coarse step (Euler or
+        // RK4) over the whole segment by the plain solver
         for (int j = 1; j <= w; ++j) {
-            llg_status rc = forward(s, P + (size_t)(j - 1) * 3 * ncells, s->dB, 1);
+            const float* prev = P + (size_t)(j - 1) * 3 * ncells;
+            const float* base = prev;
+            if (predictor != LLG_SUR_BASE_STATE) {
+                float* em = nullptr;
+                llg_status rc = llg_batch_state_ptr_(s->eb, 0, &em);
+                if (rc != LLG_OK) return sfail(s, rc, "predictor batch: %s", llg_batch_last_error(s->eb));
+                SCHK(s, hipMemcpyAsync(em, prev, vec, hipMemcpyDeviceToDevice, s->stream));
+                SCHK(s, hipStreamSynchronize(s->stream));
+                llg_batch_states_replaced_(s->eb);
+                rc = llg_batch_step(s->eb, predictor == LLG_SUR_BASE_EULER ? LLG_EULER : LLG_RK4, dt * seg_steps, 1);
+                if (rc != LLG_OK) return sfail(s, rc, "predictor batch: %s", llg_batch_last_error(s->eb));
+                rc = llg_batch_state_ptr_(s->eb, 0, &em);
+                if (rc != LLG_OK) return sfail(s, rc, "predictor batch: %s", llg_batch_last_error(s->eb));
+                base = em;
+            }
+            llg_status rc = forward(s, prev, s->dB, 1);
             if (rc != LLG_OK) return rc;
-            hipLaunchKernelGGL(propose_kernel, dim3((ncells + 255) / 256), dim3(256), 0, s->stream,
-                               P + (size_t)(j - 1) * 3 * ncells, s->z[NL - 1], P + (size_t)j * 3 * ncells, 1, s->H,
-                               s->W);
+            hipLaunchKernelGGL(propose_kernel, dim3((ncells + 255) / 256), dim3(256), 0, s->stream, base,
+                               s->z[NL - 1], P + (size_t)j * 3 * ncells, 1, s->H, s->W, s->out_scale);
             SCHK(s, hipGetLastError());
         }
         // finiteness of the proposals (0 for finite, inf otherwise) and the

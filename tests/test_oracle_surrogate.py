@@ -91,3 +91,30 @@ def test_proposal_keeps_unit_norm():
     m /= np.linalg.norm(m, axis=0)
     mp = sg.propose(params, m, (0.01, 0.0, 0.0))
     np.testing.assert_allclose(np.linalg.norm(mp, axis=0), 1.0, rtol=1e-12)
+
+
+def test_bf16_rounding_and_split_input():
+    """round_bf16 is the nearest BF16 value with ties to even (checked
+    against a brute-force search over the neighbouring BF16 values), and the
+    input pair (hi, lo) holds m: hi + lo / 256 = m exactly in FP32, |lo| <=
+    256 * half a BF16 unit of hi."""
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.uniform(0.01, 1, 1000), -rng.uniform(0.01, 1, 1000),
+                        [1.0, -1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8]])
+    x = x.astype(np.float32)
+    r = sg.round_bf16(x)
+    assert sg.round_bf16(np.zeros(1, np.float32))[0] == 0.0
+    for v, got in zip(x, r):
+        u = int(np.array([v], np.float32).view(np.uint32)[0]) & 0xFFFF0000
+        cands = [np.array([c], np.uint32).view(np.float32)[0] for c in (u - 0x10000, u, u + 0x10000)]
+        d = [abs(float(c) - float(v)) for c in cands]
+        best = min(d)
+        ties = [c for c, e in zip(cands, d) if e == best]
+        want = ties[0] if len(ties) == 1 else [c for c in ties if (np.array([c], np.float32).view(np.uint32)[0] >> 16) % 2 == 0][0]
+        assert got == want
+    m = rng.standard_normal((3, 5, 7)).astype(np.float32)
+    xin = sg.net_input(m, (0.01, 0.02, 0.0))
+    hi, lo = xin[:3].astype(np.float32), xin[3:6].astype(np.float32)
+    assert np.array_equal(hi + lo / np.float32(256.0), m)
+    assert np.all(np.abs(lo) <= 256 * np.abs(hi) * 2.0 ** -8 + 1e-30)
+    assert np.allclose(xin[6:], np.array([0.2, 0.4, 0.0]).reshape(3, 1, 1))

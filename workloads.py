@@ -155,7 +155,7 @@ def surrogate_films(ntraj, seed=5, n_side=256):
     return films, run
 
 
-SURROGATE_LAYERS = ((6, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3))
+SURROGATE_LAYERS = ((9, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 3))
 
 
 def surrogate_init(seed=0):
