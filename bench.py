@@ -40,8 +40,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default compiled variants")
     ap.add_argument("--evals-only", action="store_true",
                     help="run only the H_eff evaluations of the roofline measurement (for counter runs)")
-    ap.add_argument("--workload", choices=("film512", "batch", "sp2", "surrogate"), default="film512",
-                    help="film512: the 512x512 film (the headline); batch: the 64-film sweep; "
+    ap.add_argument("--workload", choices=("film512", "film3d", "batch", "sp2", "surrogate"), default="film512",
+                    help="film512: the 512x512 film (the headline); film3d: the 256x256x64 periodic block "
+                         "with the thermal field; batch: the 64-film sweep; "
                          "sp2: 200 relaxations shaped like the static standard problem, in one batch; "
                          "surrogate: train the learned proposer and time speculative verification")
     ap.add_argument("--sur-traj", type=int, default=100, help="surrogate: training trajectories")
@@ -129,6 +130,46 @@ def bench_batch(args):
            "config": {"workload": "64 films, sides from {64,96,128,192,256}, adaptive Dormand-Prince, "
                                   "grouped launches over all films", "cells": int(cells.sum()),
                       "films_done": int(sum(s["done"] for s in st1))}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_film3d(args):
+    """The 256 x 256 x 64 block of 3 nm cubes, periodic in x and y (10
+    images), 300 K thermal field, vortex start: fixed Heun steps of 5e-14 s
+    (two H_eff evaluations each, the thermal draw held across both)."""
+    import numpy as np
+    import torch
+    import paper_1102_3069_amd as llg
+    import workloads
+    llg.load()
+    prob, m0, run = workloads.film_3d()
+    ncells = int(np.prod(prob["n"]))
+    s = llg.Solver(0)
+    s.set_problem(prob)
+    s.set_m(m0)
+    steps = min(args.steps, 200)
+    s.step("heun", run["dt"], max(1, min(args.warmup, 20)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step("heun", run["dt"], steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = ncells * 2 * steps / wall
+    prof, prof_total = s.profile_evals(20)
+    nbytes = s.kernel_bytes()
+    dom = max(prof, key=lambda k: prof[k])
+    achieved = nbytes[dom] / (prof[dom] * 1e-3) / 1e9
+    eval_bytes = sum(nbytes.values())
+    out = {"metric": "cell-updates/s (H_eff evals) at 256x256x64 FP32, periodic x/y, thermal", "value": value,
+           "unit": "cell-updates/s", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 20),
+           "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "256x256x64 cells of 3 nm, periodic x and y (10 images), 300 K, vortex start, "
+                                  "Heun steps of 5e-14 s (2 H_eff evals each)", "cells": ncells},
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel_ms": prof, "kernel_bytes": nbytes,
+                        "eval_ms": prof_total / 20,
+                        "eval_frac": eval_bytes / (prof_total / 20 * 1e-3) / 1e9 / PEAK_HBM_GBS}}
     print(json.dumps(out), flush=True)
 
 
@@ -264,11 +305,11 @@ def main():
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
         return bench_surrogate(args)
-    if args.workload in ("batch", "sp2"):
+    if args.workload in ("batch", "sp2", "film3d"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        return bench_batch(args) if args.workload == "batch" else bench_sp2(args)
+        return {"batch": bench_batch, "sp2": bench_sp2, "film3d": bench_film3d}[args.workload](args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is "
               "described in DESIGN.md but not built", file=sys.stderr)
