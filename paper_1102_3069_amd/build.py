@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libllg.so")
-SOURCES = ["kernels.hip", "fast2d.hip", "tensor.hip", "solver.hip", "batch.hip", "surrogate.hip"]
+SOURCES = ["kernels.hip", "fast2d.hip", "fast3d.hip", "tensor.hip", "solver.hip", "batch.hip", "surrogate.hip"]
 
 
 def hipcc():

@@ -66,6 +66,8 @@ struct llg_solver {
     float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
     int wy = 1, wz = 1;       // column tile widths
     bool fast2d = false;      // 2D with compiled FFT lengths: packed spectrum kernels
+    bool fast3dy = false;     // 3D, y axis of compiled length: tiled y passes
+    bool fast3dz = false;     // 3D, z axis of compiled length: tiled z pass
     // device buffers
     float* K = nullptr;
     bool K_valid = false;
@@ -265,7 +267,13 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
     yf.cs_in = (long long)g.nrows * nkxp; yf.os_in = (long long)g.ny * nkxp; yf.as_in = nkxp;
     yf.cs_out = (long long)g.nz * g.Py * nkxp; yf.os_out = (long long)g.Py * nkxp; yf.as_out = nkxp;
     yf.n_in = g.ny; yf.n_out = g.Py;
-    HIPCHK(s, launch_col(yf, s->st, COL_FWD, s->stream));
+    if (s->fast3dy) {
+        yf.W = fast3d_col_width(g.Py, g.split_y);
+        yf.ntiles = (g.nkx + yf.W - 1) / yf.W;
+        HIPCHK(s, launch_col3_tiled(yf, COL_FWD, s->st, s->stream));
+    } else {
+        HIPCHK(s, launch_col(yf, s->st, COL_FWD, s->stream));
+    }
     if (ev_after_y) HIPCHK(s, hipEventRecord(ev_after_y[0], s->stream));
     ColArgs z = col_base(s);
     z.in = s->Sy; z.out = s->Sy;
@@ -282,14 +290,26 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
     const int sz_[6] = {1, 1, 1, 1, -1, -1};   // along z: xz, yz odd
     const int sy_[6] = {1, 1, 1, -1, 1, -1};   // along y: xy, yz odd
     for (int c = 0; c < 6; ++c) { z.sign_a[c] = sz_[c]; z.sign_o[c] = sy_[c]; }
-    HIPCHK(s, launch_col(z, s->st, COL_FULL, s->stream));
+    if (s->fast3dz) {
+        z.W = fast3d_col_width(g.Pz, g.split_z);
+        z.ntiles = (g.nkx + z.W - 1) / z.W;
+        HIPCHK(s, launch_col3_tiled(z, COL_FULL, s->st, s->stream));
+    } else {
+        HIPCHK(s, launch_col(z, s->st, COL_FULL, s->stream));
+    }
     if (ev_after_y) HIPCHK(s, hipEventRecord(ev_after_y[1], s->stream));
     ColArgs yi = y;
     yi.in = s->Sy; yi.out = s->S;
     yi.cs_in = (long long)g.nz * g.Py * nkxp; yi.os_in = (long long)g.Py * nkxp; yi.as_in = nkxp;
     yi.cs_out = (long long)g.nrows * nkxp; yi.os_out = (long long)g.ny * nkxp; yi.as_out = nkxp;
     yi.n_in = g.Py; yi.n_out = g.ny;
-    HIPCHK(s, launch_col(yi, s->st, COL_INV, s->stream));
+    if (s->fast3dy) {
+        yi.W = fast3d_col_width(g.Py, g.split_y);
+        yi.ntiles = (g.nkx + yi.W - 1) / yi.W;
+        HIPCHK(s, launch_col3_tiled(yi, COL_INV, s->st, s->stream));
+    } else {
+        HIPCHK(s, launch_col(yi, s->st, COL_INV, s->stream));
+    }
     return LLG_OK;
 }
 
@@ -636,6 +656,8 @@ llg_status llg_set_geometry(llg_solver* s, int nx, int ny, int nz, int pbc_x, in
     const char* gen = getenv("LLG_FORCE_GENERIC");
     s->fast2d = nz == 1 && fast2d_row_ok(P[0], -1, nx == P[0]) && fast2d_col_ok(Ly, split_y) && ny <= Ly &&
                 (P[0] / 2) % fast2d_col_width(Ly) == 0 && !(gen && gen[0] == '1');
+    s->fast3dy = nz > 1 && fast3d_col_ok(P[1], split_y) && ny <= Ly && !(gen && gen[0] == '1');
+    s->fast3dz = nz > 1 && fast3d_col_ok(P[2], split_z) && nz <= Lz && !(gen && gen[0] == '1');
     const size_t vec = sizeof(float) * 3 * (size_t)g.ncells;
     HIPCHK(s, make_tw(P[0], &s->twx));
     HIPCHK(s, make_tw(P[1], &s->twy));

@@ -113,6 +113,13 @@ CASES = [
     dict(n=(96, 64, 1)),                                        # compiled 3*2^k row length
     dict(n=(128, 32, 1), pbc=(False, False, False)),
     dict(n=(64, 30, 1)),                                        # ragged rows below the padding
+    # 3D with an open z axis of compiled half length (tiled z pass), ragged
+    # kx tiles, periodic x/y with an odd y length, z shorter than the half
+    dict(n=(12, 10, 16)),
+    dict(n=(20, 9, 32), pbc=(True, True, False), cell=(3e-9, 3e-9, 3e-9)),
+    dict(n=(6, 5, 64)),
+    dict(n=(8, 6, 31)),
+    dict(n=(5, 4, 128), cell=(3e-9, 3e-9, 3e-9)),
 ]
 
 
@@ -124,6 +131,37 @@ def test_heff_parity(lib, impl, case, term):
     if term != "all":
         prob["terms"] = (term,)
     note("heff", case, term)
+    s = make_solver(lib, prob, m0)
+    h = s.eval_heff()
+    ref = fields.heff(m0.astype(np.float64), prob)
+    e = maxrel(h, ref)
+    note("  maxrel", e, "rmsrel", rmsrel(h, ref))
+    assert e <= 1e-5
+
+
+# 3D grids whose y or z axis has a compiled length (tiled column passes):
+# open and periodic y of 32 ... 512, periodic z, ragged kx tiles
+CASES_3D_TILED = [
+    dict(n=(10, 16, 8)),
+    dict(n=(8, 32, 16), pbc=(False, True, False)),
+    dict(n=(6, 64, 6), pbc=(True, True, False), cell=(3e-9, 3e-9, 3e-9)),
+    dict(n=(5, 64, 4)),
+    dict(n=(4, 128, 4), pbc=(False, True, False)),
+    dict(n=(3, 128, 3)),
+    dict(n=(4, 256, 3), pbc=(False, True, False), cell=(3e-9, 3e-9, 3e-9)),
+    dict(n=(3, 256, 2)),
+    dict(n=(4, 6, 32), pbc=(False, False, True)),
+]
+
+
+@pytest.mark.parametrize("case", CASES_3D_TILED, ids=lambda c: "x".join(map(str, c["n"])) + "-" +
+                         "".join("p" if p else "o" for p in c.get("pbc", (False,) * 3)))
+@pytest.mark.parametrize("term", ["demag", "all"])
+def test_heff_parity_3d_tiled(lib, impl, case, term):
+    prob, m0 = workloads.small_problem(**case)
+    if term != "all":
+        prob["terms"] = (term,)
+    note("heff 3d tiled", case, term)
     s = make_solver(lib, prob, m0)
     h = s.eval_heff()
     ref = fields.heff(m0.astype(np.float64), prob)
