@@ -78,12 +78,21 @@ def _kernel_name(kind, px, py):
             "row_inv": f"row_inv_fast<{px},"}.get(kind)
 
 
-def measured_traffic(kind, prob):
+# kernel names of the 3D path (256 x 256 x 64 block: x periodic of 256,
+# y periodic of 256, z open of 2 x 64), per kernel kind
+def _kernel_name_3d(kind):
+    return {"row_fwd": "row_fwd_kernel<", "spectral": "col3_tiled<64, 8, 8, 2, 1>",
+            "row_inv": "row_inv_kernel<", "y_fwd": "col3_tiled<256, 16, 8, 1, 0>",
+            "y_inv": "col3_tiled<256, 16, 8, 1, 2>"}.get(kind)
+
+
+def measured_traffic(kind, prob, path=None, key=None):
     """HBM bytes per launch of the kernel from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE summary (scaled by a plain copy), or None when
     that summary was taken on other kernel sources or another size."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"film{prob['n'][0]}_traffic.json")
+    if path is None:
+        path = os.path.join(ROOT, "profiles", f"film{prob['n'][0]}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -96,8 +105,8 @@ def measured_traffic(kind, prob):
                 h.update(name.encode() + b"\0" + fh.read())
     if h.hexdigest() != rec.get("source_sha256"):
         return None
-    px = 2 * prob["n"][0]
-    key = _kernel_name(kind, px, 2 * prob["n"][1])
+    if key is None:
+        key = _kernel_name(kind, 2 * prob["n"][0], 2 * prob["n"][1])
     for name, t in rec["kernels"].items():
         if key and key in name:
             return t["read_bytes"] + t["write_bytes"]
@@ -147,6 +156,10 @@ def bench_film3d(args):
     s = llg.Solver(0)
     s.set_problem(prob)
     s.set_m(m0)
+    if args.evals_only:
+        prof, total = s.profile_evals(args.profile_evals)
+        print(json.dumps({"evals": args.profile_evals, "kernel_ms": prof, "eval_ms": total / args.profile_evals}))
+        return
     steps = min(args.steps, 200)
     s.step("heun", run["dt"], max(1, min(args.warmup, 20)))
     torch.cuda.synchronize()
@@ -167,7 +180,10 @@ def bench_film3d(args):
            "config": {"workload": "256x256x64 cells of 3 nm, periodic x and y (10 images), 300 K, vortex start, "
                                   "Heun steps of 5e-14 s (2 H_eff evals each)", "cells": ncells},
            "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel_ms": prof, "kernel_bytes": nbytes,
+                        "frac": achieved / PEAK_HBM_GBS,
+                        "traffic": measured_traffic(dom, prob, os.path.join(ROOT, "profiles", "block256x256x64_traffic.json"),
+                                                    _kernel_name_3d(dom)),
+                        "kernel_ms": prof, "kernel_bytes": nbytes,
                         "eval_ms": prof_total / 20,
                         "eval_frac": eval_bytes / (prof_total / 20 * 1e-3) / 1e9 / PEAK_HBM_GBS}}
     print(json.dumps(out), flush=True)
