@@ -40,11 +40,13 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default compiled variants")
     ap.add_argument("--evals-only", action="store_true",
                     help="run only the H_eff evaluations of the roofline measurement (for counter runs)")
-    ap.add_argument("--workload", choices=("film512", "film3d", "batch", "sp2", "surrogate"), default="film512",
+    ap.add_argument("--workload", choices=("film512", "film3d", "batch", "sp2", "surrogate", "table1"),
+                    default="film512",
                     help="film512: the 512x512 film (the headline); film3d: the 256x256x64 periodic block "
                          "with the thermal field; batch: the 64-film sweep; "
                          "sp2: 200 relaxations shaped like the static standard problem, in one batch; "
-                         "surrogate: train the learned proposer and time speculative verification")
+                         "surrogate: train the learned proposer and time speculative verification; "
+                         "table1: Euler step time over the film and cube sizes of the paper's Table 1")
     ap.add_argument("--sur-traj", type=int, default=100, help="surrogate: training trajectories")
     ap.add_argument("--sur-pairs", type=int, default=200, help="surrogate: pairs per trajectory")
     ap.add_argument("--sur-epochs", type=float, default=4.0, help="surrogate: passes over the pairs")
@@ -189,6 +191,59 @@ def bench_film3d(args):
     print(json.dumps(out), flush=True)
 
 
+# GPU time per Euler step in the paper's Table 1 (GTX580, ms), context only
+PAPER_TABLE1_MS = {(32, 32, 1): 0.59, (64, 64, 1): 0.60, (128, 128, 1): 0.69, (256, 256, 1): 1.11,
+                   (512, 512, 1): 2.75, (1024, 1024, 1): 9.07, (2048, 2048, 1): 35.78, (8, 8, 8): 0.79,
+                   (16, 16, 16): 1.03, (32, 32, 32): 1.70, (64, 64, 64): 5.52, (128, 128, 128): 35.42}
+
+
+def bench_table1(args):
+    """One Euler step (one H_eff evaluation, the torque and the update) over
+    the sizes of the paper's Table 1: N x N films of 4 x 4 x 3 nm cells and
+    N^3 cubes of 3 nm cells, random start, all deterministic terms."""
+    import numpy as np
+    import torch
+    import paper_1102_3069_amd as llg
+    import workloads
+    llg.load()
+    rows = []
+    for n in list(PAPER_TABLE1_MS):
+        prob, _ = workloads.small_problem(n=n, cell=(4e-9, 4e-9, 3e-9) if n[2] == 1 else (3e-9,) * 3, seed=1)
+        m0 = workloads.random_unit(n, 2)
+        dt = 1e-13 if n[2] == 1 else 2e-14
+        rec = {"size": "x".join(map(str, n)), "paper_gpu_ms": PAPER_TABLE1_MS[n]}
+        try:
+            s = llg.Solver(0)
+            s.set_problem(prob)
+            s.set_m(m0)
+            s.step("euler", dt, 5)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step("euler", dt, 10)
+            torch.cuda.synchronize()
+            per = (time.perf_counter() - t0) / 10
+            k = int(min(2000, max(10, 0.2 / per)))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step("euler", dt, k)
+            torch.cuda.synchronize()
+            per = (time.perf_counter() - t0) / k
+            rec.update(ms_per_step=per * 1e3, cell_updates_per_s=int(np.prod(n)) / per, steps=k)
+            s.close()
+        except llg.LLGError as err:
+            rec["unsupported"] = str(err)
+        rows.append(rec)
+        print(json.dumps(rec), file=sys.stderr, flush=True)
+    ref = [r for r in rows if r["size"] == "512x512x1"][0]
+    out = {"metric": "Euler step time over the sizes of the paper's Table 1 (context)",
+           "value": ref["cell_updates_per_s"], "unit": "cell-updates/s at 512x512x1", "n_gpus": 1,
+           "steps": ref["steps"], "warmup": 5, "ms_per_step": ref["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "Euler steps, N x N films (4 x 4 x 3 nm) and N^3 cubes (3 nm), random start, "
+                                  "demag + exchange + anisotropy + Zeeman", "table": rows}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_sp2(args):
     """200 films of 5d x d x 0.1d (d/l_ex from 1 to 30, alpha = 1, demag and
     exchange only) relaxed from [1,1,1] saturation for 1 ns in one batch:
@@ -321,11 +376,12 @@ def main():
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
         return bench_surrogate(args)
-    if args.workload in ("batch", "sp2", "film3d"):
+    if args.workload in ("batch", "sp2", "film3d", "table1"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        return {"batch": bench_batch, "sp2": bench_sp2, "film3d": bench_film3d}[args.workload](args)
+        return {"batch": bench_batch, "sp2": bench_sp2, "film3d": bench_film3d,
+                "table1": bench_table1}[args.workload](args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is "
               "described in DESIGN.md but not built", file=sys.stderr)

@@ -290,11 +290,11 @@ llg_status llg_demag_tensor(llg_solver *s, const int32_t *offsets, int64_t count
  * single-film solver (same kernels, same order), so results do not depend
  * on the batch composition.  Each axis of a film is zero padded to the
  * shortest compiled FFT length >= 2 n (x: 64, 128, 192, 256, 384, 512, 768,
- * 1024; y: twice 32, 64, 96, 128, 192, 256, 384, 512), which leaves the
- * convolution unchanged (Sec. 3.2 needs only >= 2 n - 1); where that is also
- * the single-film solver's padding (sides 32, 64, 96, 128, 192, 256, 384,
- * 512) a batched film equals the single-film run bit for bit.  Sides beyond
- * 512 give LLG_E_UNSUPPORTED.
+ * 1024, 2048; y: twice 32, 64, 96, 128, 192, 256, 384, 512, 1024), which
+ * leaves the convolution unchanged (Sec. 3.2 needs only >= 2 n - 1); where
+ * that is also the single-film solver's padding (sides 32, 64, 96, 128, 192,
+ * 256, 384, 512, 1024) a batched film equals the single-film run bit for
+ * bit.  Sides beyond 1024 give LLG_E_UNSUPPORTED.
  */
 typedef struct llg_batch llg_batch;
 

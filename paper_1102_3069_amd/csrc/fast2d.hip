@@ -712,11 +712,13 @@ __global__ __launch_bounds__(kColThreads) void col2d_fast(Col2dArgs a, DevState*
 // rows: (Px, elements per lane, frequency classes, variant)
 #define ROW_VARIANTS(X) X(64, 4, 2, 0) X(64, 8, 2, 1) X(128, 4, 2, 0) X(128, 4, 4, 1) X(192, 12, 2, 0)    \
     X(192, 6, 2, 1) X(256, 4, 2, 0) X(256, 4, 4, 1) X(384, 12, 2, 0) X(384, 6, 4, 1) X(512, 4, 2, 0)    \
-    X(512, 4, 4, 1) X(768, 12, 2, 0) X(768, 6, 4, 1) X(1024, 8, 2, 0) X(1024, 4, 4, 1)
+    X(512, 4, 4, 1) X(768, 12, 2, 0) X(768, 6, 4, 1) X(1024, 8, 2, 0) X(1024, 4, 4, 1) X(2048, 8, 4, 0)  \
+    X(2048, 16, 2, 1)
 // columns: (L = Py/2, elements per lane, frequency classes, variant)
 #define COL_VARIANTS(X) X(32, 4, 2, 0) X(32, 8, 2, 1) X(64, 4, 2, 0) X(64, 4, 4, 1) X(96, 12, 2, 0)        \
     X(96, 6, 2, 1) X(128, 4, 2, 0) X(128, 4, 4, 1) X(192, 12, 2, 0) X(192, 6, 4, 1) X(256, 4, 2, 0)       \
-    X(256, 4, 4, 1) X(384, 12, 2, 0) X(384, 6, 4, 1) X(512, 8, 2, 0) X(512, 4, 4, 1)
+    X(256, 4, 4, 1) X(384, 12, 2, 0) X(384, 6, 4, 1) X(512, 8, 2, 0) X(512, 4, 4, 1) X(1024, 16, 2, 0)    \
+    X(1024, 8, 4, 1)
 
 // grouped launches: one launch runs a pass for all films of one length
 // class (same compiled variant); block b works on film map[b].x, local

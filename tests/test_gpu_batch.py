@@ -70,7 +70,7 @@ def test_batch_film_matches_oracle(lib):
 
 
 def test_batch_rejects_sizes_beyond_the_compiled_lengths(lib):
-    prob, m0 = workloads.small_problem(n=(600, 4, 1))
+    prob, m0 = workloads.small_problem(n=(1100, 4, 1))
     with pytest.raises(lib.LLGError) as e:
         lib.Batch([(prob, m0)])
     assert e.value.code == lib.LLG_E_UNSUPPORTED

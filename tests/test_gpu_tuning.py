@@ -12,7 +12,8 @@ pytestmark = pytest.mark.gpu
 
 # (nx, ny): row lengths Px = 2 nx and column half lengths Py / 2 = ny that
 # have compiled variants, several tiles and both even and 3-smooth sizes
-SIZES = [(32, 32), (64, 96), (96, 64), (128, 192), (192, 128), (256, 32), (384, 96), (512, 64)]
+SIZES = [(32, 32), (64, 96), (96, 64), (128, 192), (192, 128), (256, 32), (384, 96), (512, 64), (1024, 32),
+         (32, 1024)]
 
 
 def maxrel(a, b):
