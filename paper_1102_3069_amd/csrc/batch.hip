@@ -69,6 +69,7 @@ struct llg_batch {
         int nblocks = 0;
     };
     std::vector<Class> rows, cols;
+    std::vector<char> in_map;           // films whose blocks the maps hold
     std::vector<hipStream_t> aux;       // branch streams (default priority)
     std::vector<hipEvent_t> ev;         // fork / join events
     hipGraphExec_t graph = nullptr;
@@ -138,6 +139,83 @@ FilmRow row_base(const llg_batch* b, int i) {
     return r;
 }
 
+// block maps per length class (largest classes first) over the films
+// marked in `active`; the captured graphs, which hold the maps, are dropped
+llg_status build_classes(llg_batch* b, const std::vector<char>& active) {
+    const int nf = (int)b->films.size();
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    if (b->gfix) (void)hipGraphExecDestroy(b->gfix);
+    b->gfix = nullptr;
+    b->fix_method = -1;
+    for (auto& c : b->rows) bfree(c.map);
+    for (auto& c : b->cols) bfree(c.map);
+    b->rows.clear();
+    b->cols.clear();
+    auto build = [&](bool row, std::vector<llg_batch::Class>& out) -> llg_status {
+        std::vector<std::pair<int, int>> keys;
+        for (int i = 0; i < nf; ++i) {
+            if (!active[i]) continue;
+            const BatchFilm& f = b->films[i];
+            const std::pair<int, int> k = row ? std::make_pair(f.g.Px, f.rvar) : std::make_pair(f.g.Py / 2, f.cvar);
+            if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+        }
+        std::sort(keys.begin(), keys.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+            return x.first > y.first || (x.first == y.first && x.second < y.second);
+        });
+        for (const auto& k : keys) {
+            std::vector<int2> map;
+            for (int i = 0; i < nf; ++i) {
+                if (!active[i]) continue;
+                const BatchFilm& f = b->films[i];
+                const bool in = row ? (f.g.Px == k.first && f.rvar == k.second)
+                                    : (f.g.Py / 2 == k.first && f.cvar == k.second);
+                if (!in) continue;
+                const int nb = row ? f.row_blocks : f.col_blocks;
+                for (int j = 0; j < nb; ++j) map.push_back(make_int2(i, j));
+            }
+            // XCD-aware order: hardware block h runs entry remap(h), so the
+            // blocks one XCD runs are contiguous rows or columns of a film
+            const int nb = (int)map.size();
+            std::vector<int2> order(nb);
+            for (int h = 0; h < nb; ++h) {
+                const int X = 8, x = h % X, i = h / X, q = nb / X, rmd = nb % X;
+                order[h] = map[x * q + std::min(x, rmd) + i];
+            }
+            llg_batch::Class c;
+            c.len = k.first;
+            c.var = k.second;
+            c.nblocks = nb;
+            BCHK(b, upload(&c.map, order));
+            out.push_back(c);
+        }
+        return LLG_OK;
+    };
+    llg_status rc = build(true, b->rows);
+    if (rc == LLG_OK) rc = build(false, b->cols);
+    if (rc != LLG_OK) return rc;
+    const size_t nbr = std::max(b->rows.size(), b->cols.size());
+    while (b->aux.size() + 1 < nbr) {
+        hipStream_t st = nullptr;
+        BCHK(b, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        b->aux.push_back(st);
+    }
+    while (b->ev.size() < nbr) {
+        hipEvent_t e = nullptr;
+        BCHK(b, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->ev.push_back(e);
+    }
+    b->in_map = active;
+    return LLG_OK;
+}
+
+// all films in the block maps again (after a run dropped finished ones)
+llg_status restore_classes(llg_batch* b) {
+    const std::vector<char> all(b->films.size(), 1);
+    if (b->in_map == all) return LLG_OK;
+    return build_classes(b, all);
+}
+
 // the per-film arguments of every grouped launch of an attempt; buffer
 // roles follow the single-film Dormand-Prince attempt exactly
 llg_status build_launch_args(llg_batch* b) {
@@ -198,59 +276,8 @@ llg_status build_launch_args(llg_batch* b) {
     BCHK(b, upload(&b->d_prep, prep));
     for (int s = 0; s < 6; ++s) BCHK(b, upload(&b->d_stage[s], stage[s]));
     BCHK(b, upload(&b->d_col, col));
-    // block maps per length class, largest classes first
-    auto build = [&](bool row, std::vector<llg_batch::Class>& out) -> llg_status {
-        std::vector<std::pair<int, int>> keys;
-        for (int i = 0; i < nf; ++i) {
-            const BatchFilm& f = b->films[i];
-            const std::pair<int, int> k = row ? std::make_pair(f.g.Px, f.rvar) : std::make_pair(f.g.Py / 2, f.cvar);
-            if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
-        }
-        std::sort(keys.begin(), keys.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
-            return x.first > y.first || (x.first == y.first && x.second < y.second);
-        });
-        for (const auto& k : keys) {
-            std::vector<int2> map;
-            for (int i = 0; i < nf; ++i) {
-                const BatchFilm& f = b->films[i];
-                const bool in = row ? (f.g.Px == k.first && f.rvar == k.second)
-                                    : (f.g.Py / 2 == k.first && f.cvar == k.second);
-                if (!in) continue;
-                const int nb = row ? f.row_blocks : f.col_blocks;
-                for (int j = 0; j < nb; ++j) map.push_back(make_int2(i, j));
-            }
-            // XCD-aware order: hardware block h runs entry remap(h), so the
-            // blocks one XCD runs are contiguous rows or columns of a film
-            const int nb = (int)map.size();
-            std::vector<int2> order(nb);
-            for (int h = 0; h < nb; ++h) {
-                const int X = 8, x = h % X, i = h / X, q = nb / X, rmd = nb % X;
-                order[h] = map[x * q + std::min(x, rmd) + i];
-            }
-            llg_batch::Class c;
-            c.len = k.first;
-            c.var = k.second;
-            c.nblocks = nb;
-            BCHK(b, upload(&c.map, order));
-            out.push_back(c);
-        }
-        return LLG_OK;
-    };
-    llg_status rc = build(true, b->rows);
-    if (rc == LLG_OK) rc = build(false, b->cols);
-    if (rc != LLG_OK) return rc;
-    const size_t nbr = std::max(b->rows.size(), b->cols.size());
-    for (size_t i = 1; i < nbr; ++i) {
-        hipStream_t st = nullptr;
-        BCHK(b, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        b->aux.push_back(st);
-    }
-    for (size_t i = 0; i < nbr; ++i) {
-        hipEvent_t e = nullptr;
-        BCHK(b, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        b->ev.push_back(e);
-    }
-    return LLG_OK;
+    std::vector<char> all(nf, 1);
+    return build_classes(b, all);
 }
 
 // one pass over all films: a launch per length class, the classes as
@@ -492,8 +519,9 @@ llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0,
         return bfail(b, LLG_E_ARG, "need max_err > 0, dt0 >= 0");
     const int nf = (int)b->films.size();
     std::vector<DevState> h;
-    llg_status rc = read_states(b, h);
+    llg_status rc = restore_classes(b);
     if (rc != LLG_OK) return rc;
+    if ((rc = read_states(b, h)) != LLG_OK) return rc;
     if (!b->k1_valid) {
         PASS(b, PASS_ROW_FWD, b->d_fwd_plain);
         PASS(b, PASS_COL, nullptr);
@@ -519,17 +547,20 @@ llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0,
         s.dtau = (float)(s.dt * s.gms);
     }
     if ((rc = write_states(b, h)) != LLG_OK) return rc;
-    if (!b->graph) {
+    auto capture_attempt = [&]() -> llg_status {
         hipGraph_t graph = nullptr;
         BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_attempt(b);
+        llg_status r = enqueue_attempt(b);
         hipError_t e = hipStreamEndCapture(b->stream, &graph);
-        if (rc != LLG_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        if (r != LLG_OK) { if (graph) (void)hipGraphDestroy(graph); return r; }
         BCHK(b, e);
         e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         BCHK(b, e);
-    }
+        return LLG_OK;
+    };
+    if (!b->graph && (rc = capture_attempt()) != LLG_OK) return rc;
+    int mapped = nf;
     long long launched = 0;
     for (;;) {
         int nl = 8;
@@ -541,9 +572,19 @@ llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0,
         for (int i = 0; i < nl; ++i) BCHK(b, hipGraphLaunch(b->graph, b->stream));
         launched += nl;
         if ((rc = read_states(b, h)) != LLG_OK) return rc;
-        bool all = true;
-        for (auto& s : h) all = all && s.done;
-        if (all) break;
+        int active = 0;
+        for (auto& s : h) active += !s.done;
+        if (active == 0) break;
+        // once half the mapped films have finished, launch only the others
+        // (a finished film's blocks would exit at once; their launch is the
+        // cost).  A film's arithmetic does not depend on the maps.
+        if (2 * active <= mapped) {
+            std::vector<char> act(nf);
+            for (int i = 0; i < nf; ++i) act[i] = !h[i].done;
+            if ((rc = build_classes(b, act)) != LLG_OK) return rc;
+            if ((rc = capture_attempt()) != LLG_OK) return rc;
+            mapped = active;
+        }
     }
     if (per_film)
         for (int i = 0; i < nf; ++i) fill(h[i], per_film + i);
@@ -591,7 +632,9 @@ llg_status llg_batch_step(llg_batch* b, llg_method method, double dt, int64_t ns
     if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return bfail(b, LLG_E_ARG, "need dt > 0, nsteps >= 0");
     if (nsteps == 0) return LLG_OK;
     std::vector<DevState> h;
-    llg_status rc = read_states(b, h);
+    llg_status rc = restore_classes(b);
+    if (rc != LLG_OK) return rc;
+    if ((rc = read_states(b, h)) != LLG_OK) return rc;
     if (rc != LLG_OK) return rc;
     for (size_t i = 0; i < h.size(); ++i) {
         if (h[i].health) return bfail(b, LLG_E_DIVERGED, "film %d has already diverged", (int)i);
