@@ -127,8 +127,10 @@ struct RowSplit {
 
     // forward transform of the block's rows, whose magnetisation sits in LDS
     // nm[row][c][x] (row stride 3 NXM), and store of the columns kx < PX/2;
-    // scr is the block's scratch (every group calls this)
-    template <int NXM>
+    // scr is the block's scratch (every group calls this).  NAT: natural
+    // layout instead (row-major rows of PX/2 + 1 columns kx = 0 ... PX/2, as
+    // the 3D column passes read them)
+    template <int NXM, bool NAT>
     static __device__ __forceinline__ void forward(const Grid& g, float2* __restrict__ S, float2* scr,
                                                    const float2* tw, const float* nm, int kind, int q,
                                                    int pair, int lg, int gbase, int rb) {
@@ -170,8 +172,8 @@ struct RowSplit {
         }
         const int cs = g.nrows * g.nkxp;
         const float2 zN = z[E2 / 2];   // X[PX/2]: class 0, lane 0
-        float2* s0 = S + (r0 << g.tsh);
-        float2* s1 = s0 + (1 << g.tsh);
+        float2* s0 = NAT ? S + r0 * g.nkxp : S + (r0 << g.tsh);
+        float2* s1 = NAT ? s0 + g.nkxp : s0 + (1 << g.tsh);
 #pragma unroll
         for (int i = 0; i < E2 / 2; ++i) {
             const int j = lg + P * i;
@@ -182,11 +184,23 @@ struct RowSplit {
             else zm = pz[LQ - 1 - j];
             float2 A = mk2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
             float2 B = mk2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-            if (q == 0 && j == 0) {   // pack the real DC and Nyquist coefficients
+            if (!NAT && q == 0 && j == 0) {   // pack the real DC and Nyquist coefficients
                 A = mk2(zk.x, zN.x);
                 B = mk2(zk.y, zN.y);
             }
-            const int col = tile_index(0, q * QC + j, g.nrows, g.tsh);
+            const int col = NAT ? NQ * j + q : tile_index(0, q * QC + j, g.nrows, g.tsh);
+            if (kind == 0) {
+                if (v0) { s0[col] = A; s0[cs + col] = B; }
+            } else if (kind == 1) {
+                if (v1) { s1[col] = A; s1[cs + col] = B; }
+            } else {
+                if (v0) s0[2 * cs + col] = A;
+                if (v1) s1[2 * cs + col] = B;
+            }
+        }
+        if (NAT && q == 0 && lg == 0) {   // the real Nyquist coefficients, column PX/2
+            const float2 A = mk2(zN.x, 0.f), B = mk2(zN.y, 0.f);
+            const int col = PX / 2;
             if (kind == 0) {
                 if (v0) { s0[col] = A; s0[cs + col] = B; }
             } else if (kind == 1) {
@@ -199,7 +213,7 @@ struct RowSplit {
     }
 };
 
-template <int PX, int E2, int NQ, bool XPER>
+template <int PX, int E2, int NQ, bool XPER, bool NAT>
 __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __restrict__ twx,
                                              float2* __restrict__ S, const FwdArgs& fa,
                                              DevState* __restrict__ st, int blk, char* lds) {
@@ -246,15 +260,15 @@ __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __rest
         row[x] = ax; row[NXM + x] = ay; row[2 * NXM + x] = az;
     }
     __syncthreads();
-    R::template forward<NXM>(g, S, scr, tw, nm, kind, q, pair, lg, gbase, rb);
+    R::template forward<NXM, NAT>(g, S, scr, tw, nm, kind, q, pair, lg, gbase, rb);
 }
 
-template <int PX, int E2, int NQ, bool XPER>
+template <int PX, int E2, int NQ, bool XPER, bool NAT>
 __global__ __launch_bounds__(kRowThreads) void row_fwd_fast(Grid g, const float2* __restrict__ twx,
                                                             float2* __restrict__ S, FwdArgs fa,
                                                             DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
-    row_fwd_body<PX, E2, NQ, XPER>(g, twx, S, fa, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
+    row_fwd_body<PX, E2, NQ, XPER, NAT>(g, twx, S, fa, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
 }
 
 // exchange + anisotropy + applied + thermal field of cell x of a row whose
@@ -294,8 +308,35 @@ __device__ __forceinline__ void local_field_lds(const Grid& g, const Phys& p, co
     }
 }
 
+// exchange terms of a 3D grid that the staged rows of a block do not hold:
+// the periodic y wrap at the edges of a z plane and the z neighbours, read
+// from global memory (component stride ncells)
+__device__ __forceinline__ void exchange_wrap_z(const Grid& g, const Phys& p, const float* __restrict__ m, int r,
+                                                int x, int y, float mx, float my, float mz, float& hx, float& hy,
+                                                float& hz) {
+    const long long cs = g.ncells;
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    auto nb = [&](int rr, float c) {
+        const long long i = (long long)rr * g.nx + x;
+        sx += c * (m[i] - mx);
+        sy += c * (m[cs + i] - my);
+        sz += c * (m[2 * cs + i] - mz);
+    };
+    if (p.cex[1] != 0.f && g.ny > 1 && g.pbc[1]) {
+        if (y == 0) nb(r + g.ny - 1, p.cex[1]);
+        if (y == g.ny - 1) nb(r - (g.ny - 1), p.cex[1]);
+    }
+    if (p.cex[2] != 0.f && g.nz > 1) {
+        const int z = r / g.ny;
+        const float c = p.cex[2];
+        if (z > 0) nb(r - g.ny, c); else if (g.pbc[2]) nb(r + (g.nz - 1) * g.ny, c);
+        if (z < g.nz - 1) nb(r + g.ny, c); else if (g.pbc[2]) nb(r - (g.nz - 1) * g.ny, c);
+    }
+    hx += sx; hy += sy; hz += sz;
+}
+
 // XPER: the x axis is periodic (nx == PX), else nx <= PX/2
-template <int PX, int E2, int NQ, bool XPER>
+template <int PX, int E2, int NQ, bool XPER, bool NAT>
 __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const float2* __restrict__ twx,
                                              float2* __restrict__ S, const StageArgs& sa,
                                              DevState* __restrict__ st, int blk, char* lds) {
@@ -336,7 +377,9 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     for (int rq = 0; rq < R::NR; ++rq) {
         int row = rb - 1 + rq;
         bool ok = row >= 0 && row < g.nrows;
-        if (g.pbc[1]) { row = row < 0 ? row + ny : (row >= ny ? row - ny : row); ok = true; }
+        // NAT (3D): only the block's own rows are used, neighbours come from
+        // global memory
+        if (!NAT && g.pbc[1]) { row = row < 0 ? row + ny : (row >= ny ? row - ny : row); ok = true; }
         const float* src = mi + row * nx;
         float* dst = mrow + rq * 3 * NXM;
         for (int t = tid; t < 3 * nx; t += NT) {
@@ -352,11 +395,13 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         const int scs = g.nrows * g.nkxp;
         const float2* sa_ = nullptr;
         const float2* sb_ = nullptr;
-        if (kind == 0) { if (v0) { sa_ = S + (r0 << g.tsh); sb_ = sa_ + scs; } }
-        else if (kind == 1) { if (v1) { sa_ = S + ((r0 + 1) << g.tsh); sb_ = sa_ + scs; } }
+        const int rs0 = NAT ? r0 * g.nkxp : (r0 << g.tsh);
+        const int rs1 = NAT ? (r0 + 1) * g.nkxp : ((r0 + 1) << g.tsh);
+        if (kind == 0) { if (v0) { sa_ = S + rs0; sb_ = sa_ + scs; } }
+        else if (kind == 1) { if (v1) { sa_ = S + rs1; sb_ = sa_ + scs; } }
         else {
-            if (v0) sa_ = S + 2 * scs + (r0 << g.tsh);
-            if (v1) sb_ = S + 2 * scs + ((r0 + 1) << g.tsh);
+            if (v0) sa_ = S + 2 * scs + rs0;
+            if (v1) sb_ = S + 2 * scs + rs1;
         }
 #pragma unroll
         for (int i = 0; i < E2; ++i) {
@@ -366,7 +411,13 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             const int j = lg + P * i;
             const int k = NQ * j + q;
             float2 A = mk2(0.f, 0.f), B = mk2(0.f, 0.f);
-            if (k == 0 || k == PX / 2) {
+            if (NAT) {
+                // natural layout: kx = 0 ... PX/2 stored, the rest conjugate
+                const bool up = k > PX / 2;
+                const int col = up ? PX - k : k;
+                if (sa_) { A = sa_[col]; if (up) A.y = -A.y; }
+                if (sb_) { B = sb_[col]; if (up) B.y = -B.y; }
+            } else if (k == 0 || k == PX / 2) {
                 const bool nyq = k != 0;
                 if (sa_) { const float2 v = sa_[0]; A = mk2(nyq ? v.y : v.x, 0.f); }
                 if (sb_) { const float2 v = sb_[0]; B = mk2(nyq ? v.y : v.x, 0.f); }
@@ -452,7 +503,16 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             hx = sa2.x; hy = sa2.y;
             hz = rr ? sz2.y : sz2.x;
         }
-        local_field_lds(g, p, rm, rc, rp, NXM, r, x, step, hx, hy, hz);
+        if constexpr (NAT) {
+            // x and in-plane y neighbours from the staged rows (the block's
+            // rows and one halo row each side, consecutive in memory)
+            const float* rmn = (ny > 1 && y > 0) ? rc - 3 * NXM : nullptr;
+            const float* rpn = (ny > 1 && y < ny - 1) ? rc + 3 * NXM : nullptr;
+            local_field_lds(g, p, rmn, rc, rpn, NXM, r, x, step, hx, hy, hz);
+            exchange_wrap_z(g, p, mi, r, x, y, rc[x], rc[NXM + x], rc[2 * NXM + x], hx, hy, hz);
+        } else {
+            local_field_lds(g, p, rm, rc, rp, NXM, r, x, step, hx, hy, hz);
+        }
         const int qq = r * nx + x;
         if (sa.mode == ROW_EVAL) {
             float* h = sa.h_out;
@@ -468,14 +528,16 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             // a free surface has none)
             const float mx = rc[x], my = rc[NXM + x], mz = rc[2 * NXM + x];
             float Dx = 0.f, Dy = 0.f, Dz = 0.f;
-            if (p.cj[0] != 0.f && nx > 1) {
+            if (NAT) {
+                stt_gradient(g, p, mi, r, x, mx, my, mz, Dx, Dy, Dz);
+            } else if (p.cj[0] != 0.f && nx > 1) {
                 const int xu = x < nx - 1 ? x + 1 : (g.pbc[0] ? 0 : x);
                 const int xd = x > 0 ? x - 1 : (g.pbc[0] ? nx - 1 : x);
                 Dx += p.cj[0] * (rc[xu] - rc[xd]);
                 Dy += p.cj[0] * (rc[NXM + xu] - rc[NXM + xd]);
                 Dz += p.cj[0] * (rc[2 * NXM + xu] - rc[2 * NXM + xd]);
             }
-            if (p.cj[1] != 0.f && ny > 1) {
+            if (!NAT && p.cj[1] != 0.f && ny > 1) {
                 const float* ru = rp ? rp : rc;
                 const float* rd = rm ? rm : rc;
                 Dx += p.cj[1] * (ru[x] - rd[x]);
@@ -523,16 +585,16 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     }
     if (stage && p.demag_on && !sa.skip_fwd) {
         __syncthreads();   // new rows complete, exchange no longer read
-        R::template forward<NXM>(g, S, scr, tw, nm, kind, q, pair, lg, gbase, rb);
+        R::template forward<NXM, NAT>(g, S, scr, tw, nm, kind, q, pair, lg, gbase, rb);
     }
 }
 
-template <int PX, int E2, int NQ, bool XPER>
+template <int PX, int E2, int NQ, bool XPER, bool NAT>
 __global__ __launch_bounds__(kRowThreads) void row_inv_fast(Grid g, Phys p, const float2* __restrict__ twx,
                                                             float2* __restrict__ S, StageArgs sa,
                                                             DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
-    row_inv_body<PX, E2, NQ, XPER>(g, p, twx, S, sa, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
+    row_inv_body<PX, E2, NQ, XPER, NAT>(g, p, twx, S, sa, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -729,7 +791,7 @@ __global__ __launch_bounds__(kRowThreads) void row_fwd_group(const FilmRow* __re
     extern __shared__ char dyn_lds[];
     const int2 m = map[blockIdx.x];
     const FilmRow& f = films[m.x];
-    row_fwd_body<PX, E2, NQ, false>(f.g, f.twx, f.S, f.fa, f.st, m.y, dyn_lds);
+    row_fwd_body<PX, E2, NQ, false, false>(f.g, f.twx, f.S, f.fa, f.st, m.y, dyn_lds);
 }
 
 template <int PX, int E2, int NQ>
@@ -738,7 +800,7 @@ __global__ __launch_bounds__(kRowThreads) void row_inv_group(const FilmRow* __re
     extern __shared__ char dyn_lds[];
     const int2 m = map[blockIdx.x];
     const FilmRow& f = films[m.x];
-    row_inv_body<PX, E2, NQ, false>(f.g, f.p, f.twx, f.S, f.sa, f.st, m.y, dyn_lds);
+    row_inv_body<PX, E2, NQ, false, false>(f.g, f.p, f.twx, f.S, f.sa, f.st, m.y, dyn_lds);
 }
 
 template <int L, int E, int NQ>
@@ -809,30 +871,65 @@ bool fast2d_col_ok(int L, int split, int var) {
     return false;
 }
 
+// the fast row kernels of one compiled variant: periodic x (XPER) or
+// zero-padded, packed 2D (NAT false) or natural 3D (NAT true) spectrum
+template <int PX, int E, int NQ, bool NAT>
+hipError_t launch_row_fwd_t(const Grid& g, const float2* twx, float2* S, const FwdArgs& fa, DevState* st,
+                            hipStream_t s) {
+    using R_ = RowSplit<PX, E, NQ>;
+    constexpr int rows = 2 * R_::RP;
+    const dim3 grid((g.nrows + rows - 1) / rows);
+    constexpr int lds_p = R_::template fwd_bytes<true>();
+    constexpr int lds_o = R_::template fwd_bytes<false>();
+    if (g.nx == PX) {
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, NQ, true, NAT>), lds_p);
+        if (e_ != hipSuccess) return e_;
+        hipLaunchKernelGGL((row_fwd_fast<PX, E, NQ, true, NAT>), grid, dim3(R_::NT), lds_p, s, g, twx, S, fa, st);
+    } else if (2 * g.nx <= PX) {
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, NQ, false, NAT>), lds_o);
+        if (e_ != hipSuccess) return e_;
+        hipLaunchKernelGGL((row_fwd_fast<PX, E, NQ, false, NAT>), grid, dim3(R_::NT), lds_o, s, g, twx, S, fa, st);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int PX, int E, int NQ, bool NAT>
+hipError_t launch_row_inv_t(const Grid& g, const Phys& p, const float2* twx, float2* S, const StageArgs& sa,
+                            DevState* st, hipStream_t s) {
+    using R_ = RowSplit<PX, E, NQ>;
+    constexpr int rows = 2 * R_::RP;
+    const dim3 grid((g.nrows + rows - 1) / rows);
+    constexpr int lds_p = R_::template inv_bytes<true>();
+    constexpr int lds_o = R_::template inv_bytes<false>();
+    if (g.nx == PX) {
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, NQ, true, NAT>), lds_p);
+        if (e_ != hipSuccess) return e_;
+        hipLaunchKernelGGL((row_inv_fast<PX, E, NQ, true, NAT>), grid, dim3(R_::NT), lds_p, s, g, p, twx, S, sa, st);
+    } else if (2 * g.nx <= PX) {
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, NQ, false, NAT>), lds_o);
+        if (e_ != hipSuccess) return e_;
+        hipLaunchKernelGGL((row_inv_fast<PX, E, NQ, false, NAT>), grid, dim3(R_::NT), lds_o, s, g, p, twx, S, sa,
+                           st);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// 2D (nz = 1): the packed, tiled spectrum of the column kernel; 3D: the
+// natural layout [c][row][nkxp] of the 3D column passes
 hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, const FwdArgs& fa,
                                DevState* st, hipStream_t s) {
     if (g.nx > g.Px || g.nkxp < g.Px / 2 || g.tsh < 0 || (g.Px / 2) % (1 << g.tsh)) return hipErrorInvalidValue;
+    const bool nat = g.nz > 1;
+    if (nat && (g.nkxp < g.Px / 2 + 1 || g.nkx != g.Px / 2 + 1)) return hipErrorInvalidValue;
     const int var = fast2d_row_variant(g.Px);
 #define CASE(PX, E, NQ, V)                                                                \
-    if (g.Px == PX && var == V) {                                                         \
-        using R_ = RowSplit<PX, E, NQ>;                                                   \
-        constexpr int rows = 2 * R_::RP;                                                  \
-        const dim3 grid((g.nrows + rows - 1) / rows);                                     \
-        constexpr int lds_p = R_::template fwd_bytes<true>();                             \
-        constexpr int lds_o = R_::template fwd_bytes<false>();                            \
-        if (g.nx == PX) {                                                                 \
-            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, NQ, true>), lds_p); \
-            if (e_ != hipSuccess) return e_;                                              \
-            hipLaunchKernelGGL((row_fwd_fast<PX, E, NQ, true>), grid, dim3(R_::NT), lds_p, s, g, twx, S, fa, st); \
-        } else if (2 * g.nx <= PX) {                                                      \
-            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, NQ, false>), lds_o); \
-            if (e_ != hipSuccess) return e_;                                              \
-            hipLaunchKernelGGL((row_fwd_fast<PX, E, NQ, false>), grid, dim3(R_::NT), lds_o, s, g, twx, S, fa, st); \
-        } else {                                                                          \
-            return hipErrorInvalidValue;                                                  \
-        }                                                                                 \
-        return hipGetLastError();                                                         \
-    }
+    if (g.Px == PX && var == V)                                                           \
+        return nat ? launch_row_fwd_t<PX, E, NQ, true>(g, twx, S, fa, st, s)              \
+                   : launch_row_fwd_t<PX, E, NQ, false>(g, twx, S, fa, st, s);
     ROW_VARIANTS(CASE)
 #undef CASE
     return hipErrorInvalidValue;
@@ -843,29 +940,13 @@ hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, 
     if (g.nx > g.Px || g.nkxp < g.Px / 2 || sa.nk > kMaxK || g.tsh < 0 || (g.Px / 2) % (1 << g.tsh))
         return hipErrorInvalidValue;
     if ((sa.mode == ROW_STAGE || sa.mode == ROW_ERROR) && sa.nk < 1) return hipErrorInvalidValue;
+    const bool nat = g.nz > 1;
+    if (nat && (g.nkxp < g.Px / 2 + 1 || g.nkx != g.Px / 2 + 1)) return hipErrorInvalidValue;
     const int var = fast2d_row_variant(g.Px);
 #define CASE(PX, E, NQ, V)                                                                \
-    if (g.Px == PX && var == V) {                                                         \
-        using R_ = RowSplit<PX, E, NQ>;                                                   \
-        constexpr int rows = 2 * R_::RP;                                                  \
-        const dim3 grid((g.nrows + rows - 1) / rows);                                     \
-        constexpr int lds_p = R_::template inv_bytes<true>();                             \
-        constexpr int lds_o = R_::template inv_bytes<false>();                            \
-        if (g.nx == PX) {                                                                 \
-            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, NQ, true>), lds_p); \
-            if (e_ != hipSuccess) return e_;                                              \
-            hipLaunchKernelGGL((row_inv_fast<PX, E, NQ, true>), grid, dim3(R_::NT),       \
-                               lds_p, s, g, p, twx, S, sa, st);                           \
-        } else if (2 * g.nx <= PX) {                                                      \
-            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, NQ, false>), lds_o); \
-            if (e_ != hipSuccess) return e_;                                              \
-            hipLaunchKernelGGL((row_inv_fast<PX, E, NQ, false>), grid, dim3(R_::NT),      \
-                               lds_o, s, g, p, twx, S, sa, st);                           \
-        } else {                                                                          \
-            return hipErrorInvalidValue;                                                  \
-        }                                                                                 \
-        return hipGetLastError();                                                         \
-    }
+    if (g.Px == PX && var == V)                                                           \
+        return nat ? launch_row_inv_t<PX, E, NQ, true>(g, p, twx, S, sa, st, s)           \
+                   : launch_row_inv_t<PX, E, NQ, false>(g, p, twx, S, sa, st, s);
     ROW_VARIANTS(CASE)
 #undef CASE
     return hipErrorInvalidValue;

@@ -66,6 +66,7 @@ struct llg_solver {
     float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
     int wy = 1, wz = 1;       // column tile widths
     bool fast2d = false;      // 2D with compiled FFT lengths: packed spectrum kernels
+    bool fastrows = false;    // row passes of compiled length (2D packed or 3D natural layout)
     bool fast3dy = false;     // 3D, y axis of compiled length: tiled y passes
     bool fast3dz = false;     // 3D, z axis of compiled length: tiled z pass
     // device buffers
@@ -205,11 +206,11 @@ llg_status ensure_kernel(llg_solver* s) {
 
 // row passes: packed fast kernels or the generic ones
 hipError_t row_fwd(llg_solver* s, const Phys& p, const FwdArgs& fa) {
-    if (s->fast2d) return launch_row_fwd_fast(s->g, s->twx, s->S, fa, s->st, s->stream);
+    if (s->fastrows) return launch_row_fwd_fast(s->g, s->twx, s->S, fa, s->st, s->stream);
     return launch_row_fwd(s->g, p, s->px, s->twx, s->S, fa, s->st, s->stream);
 }
 hipError_t row_inv(llg_solver* s, const Phys& p, const StageArgs& sa) {
-    if (s->fast2d) return launch_row_inv_fast(s->g, p, s->twx, s->S, sa, s->st, s->stream);
+    if (s->fastrows) return launch_row_inv_fast(s->g, p, s->twx, s->S, sa, s->st, s->stream);
     return launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream);
 }
 
@@ -656,6 +657,8 @@ llg_status llg_set_geometry(llg_solver* s, int nx, int ny, int nz, int pbc_x, in
     const char* gen = getenv("LLG_FORCE_GENERIC");
     s->fast2d = nz == 1 && fast2d_row_ok(P[0], -1, nx == P[0]) && fast2d_col_ok(Ly, split_y) && ny <= Ly &&
                 (P[0] / 2) % fast2d_col_width(Ly) == 0 && !(gen && gen[0] == '1');
+    s->fastrows = s->fast2d || (nz > 1 && fast2d_row_ok(P[0], -1, nx == P[0]) && (nx == P[0] || 2 * nx <= P[0]) &&
+                                !(gen && gen[0] == '1'));
     s->fast3dy = nz > 1 && fast3d_col_ok(P[1], split_y) && ny <= Ly && !(gen && gen[0] == '1');
     s->fast3dz = nz > 1 && fast3d_col_ok(P[2], split_z) && nz <= Lz && !(gen && gen[0] == '1');
     const size_t vec = sizeof(float) * 3 * (size_t)g.ncells;

@@ -151,7 +151,40 @@ CASES_3D_TILED = [
     dict(n=(4, 256, 3), pbc=(False, True, False), cell=(3e-9, 3e-9, 3e-9)),
     dict(n=(3, 256, 2)),
     dict(n=(4, 6, 32), pbc=(False, False, True)),
+    # compiled x lengths: the fast row kernels with the natural 3D layout
+    dict(n=(32, 6, 4)),
+    dict(n=(64, 5, 3), pbc=(True, False, False)),
+    dict(n=(96, 4, 3)),
+    dict(n=(64, 32, 16), pbc=(True, True, False), cell=(3e-9, 3e-9, 3e-9)),
 ]
+
+
+@pytest.mark.parametrize("method", ["heun", "rk4"])
+def test_3d_fast_rows_fixed_steps(lib, impl, method):
+    """Fixed steps on a 3D grid whose rows have a compiled length (periodic
+    x): the fused row pass with the next stage's forward transform in the
+    natural layout, against the oracle over 20 steps."""
+    prob, m0 = workloads.small_problem(n=(64, 6, 4), pbc=(True, False, False), alpha=0.5)
+    s = make_solver(lib, prob, m0)
+    s.step(method, 1e-13, 20)
+    o = ollg.Solver(prob, m0)
+    o.step(method, 1e-13, 20)
+    e = maxrel(s.get_m(), o.m)
+    note("3d fast rows", method, impl, "m maxrel", e)
+    assert e <= 1e-5
+
+
+def test_3d_fast_rows_dp45_replay(lib, impl):
+    prob, m0 = workloads.small_problem(n=(32, 6, 4), alpha=0.5)
+    s = make_solver(lib, prob, m0)
+    st = s.run(3e-12, 1e-5, 1e-14)
+    log = s.attempts()
+    assert st["done"] == 1
+    o = ollg.Solver(prob, m0)
+    o.replay([(dt, ok) for dt, _, ok in log])
+    e = maxrel(s.get_m(), o.m)
+    note("3d fast rows dp45", impl, "attempts", len(log), "m maxrel", e)
+    assert e <= 1e-5
 
 
 @pytest.mark.parametrize("case", CASES_3D_TILED, ids=lambda c: "x".join(map(str, c["n"])) + "-" +
