@@ -2,18 +2,22 @@
 // the magnetisation ten fixed steps ahead, trained and evaluated with BF16
 // MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
 //
-//   input  x: m (3 channels) and the applied field B / 50 mT (3 channels)
-//   net    conv3x3(6->32) SiLU, 4 x [conv3x3(32->32) SiLU], conv3x3(32->3)
-//   output dm; proposal m' = normalize(m + dm); loss mean (dm - (m_t - m))^2
+//   input  x: m as a BF16 pair (hi, 256 (m - hi): 6 channels) and the
+//          applied field B / 50 mT (3 channels)
+//   net    conv3x3(9->32) SiLU, 4 x [conv3x3(32->32) SiLU], conv3x3(32->3)
+//   output o; proposal m' = normalize(base + s o) for a base state (m or a
+//          coarse step of it) and an output scale s; loss mean
+//          (o - (m_t - base) / s)^2
 //
 // Every convolution is an implicit GEMM over (pixels) x (output channels)
 // with K = 9 taps x 32 input channels.  Activations are BF16, channels
 // last ([n][y][x][32], channel counts padded to 32 with zeros), weights
 // BF16 [tap][cout][cin]; the data gradient is the same kernel with the
-// weights flipped in space and transposed in channels; the weight gradient
-// is an MFMA reduction over pixel chunks into per-block partial sums that a
-// second kernel adds in a fixed order (deterministic).  Master weights and
-// the Adam moments stay FP32.
+// weights flipped in space and transposed in channels, with the SiLU
+// derivative of the layer below applied in its epilogue; the weight
+// gradient is an MFMA reduction over pixel chunks into per-block partial
+// sums that two more kernels add in a fixed order (deterministic).  Master
+// weights and the Adam moments stay FP32.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -98,149 +102,232 @@ __global__ void mfma_selftest_kernel(const u16* A, const u16* B, float* C) {
 //   in   [N][H][W][32] bf16, wt [9][32 cout][32 cin] bf16, bias [32] (may be null)
 //   z    [N][H][W][32] float (pre-activation, may be null)
 //   a    [N][H][W][32] bf16 (SiLU(z) if act, else z; may be null)
-// block: 4 waves, 64 pixels of one row; a wave: 16 pixels x 32 channels
+//   zg   [N][H][W][32] float (may be null): data-gradient mode, a is then
+//        z times SiLU'(zg), the gradient at the previous layer's pre-activation
+// block: 4 waves, 64 pixels of `rows` consecutive rows; a wave: 16 pixels x
+// 32 channels per row, with the weight fragments of all nine taps held in
+// registers across the rows
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ in, const u16* __restrict__ wt,
                                                        const float* __restrict__ bias, float* __restrict__ z,
-                                                       u16* __restrict__ a, int H, int W, int act) {
+                                                       u16* __restrict__ a, const float* __restrict__ zg, int H,
+                                                       int W, int act, int rows) {
     __shared__ u16 ws[9 * CH * CH];
     const int tid = threadIdx.x;
     for (int i = tid; i < 9 * CH * CH / 8; i += 256)
         reinterpret_cast<uint4*>(ws)[i] = reinterpret_cast<const uint4*>(wt)[i];
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
-    const int n = blockIdx.z, y = blockIdx.y;
+    const int n = blockIdx.z;
     const int x0 = blockIdx.x * 64 + wave * 16;
     const int col = lane % 16, kg = lane / 16;
     const size_t img = (size_t)n * H * W;
-    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
-    for (int u = 0; u < 3; ++u) {
-        const int yy = y + u - 1;
-        for (int v = 0; v < 3; ++v) {
-            const int xx = x0 + col + v - 1;
-            bf16x8 A = zero8();
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W) A = load8(in + ((img + (size_t)yy * W + xx) * CH + 8 * kg));
-            const u16* wb = ws + (u * 3 + v) * CH * CH;
-            const bf16x8 B0 = load8(wb + col * CH + 8 * kg);
-            const bf16x8 B1 = load8(wb + (16 + col) * CH + 8 * kg);
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B1, acc1, 0, 0, 0);
-        }
+    bf16x8 B0[9], B1[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        B0[t] = load8(ws + t * CH * CH + col * CH + 8 * kg);
+        B1[t] = load8(ws + t * CH * CH + (16 + col) * CH + 8 * kg);
     }
-    // C layout: lane holds channel (col) of pixels 4 kg + r
-    for (int r = 0; r < 4; ++r) {
-        const int x = x0 + 4 * kg + r;
-        if (x >= W) continue;
-        const size_t p = (img + (size_t)y * W + x) * CH;
-        float v0 = acc0[r], v1 = acc1[r];
-        if (bias) { v0 += bias[col]; v1 += bias[16 + col]; }
-        if (z) { z[p + col] = v0; z[p + 16 + col] = v1; }
-        if (a) {
-            a[p + col] = f2bf(act ? silu(v0) : v0);
-            a[p + 16 + col] = f2bf(act ? silu(v1) : v1);
+    const float bias0 = bias ? bias[col] : 0.f, bias1 = bias ? bias[16 + col] : 0.f;
+    const int ya = blockIdx.y * rows, yb = min(ya + rows, H);
+    for (int y = ya; y < yb; ++y) {
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int yy = y + u - 1;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const int xx = x0 + col + v - 1;
+                bf16x8 A = zero8();
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    A = load8(in + ((img + (size_t)yy * W + xx) * CH + 8 * kg));
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B0[u * 3 + v], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B1[u * 3 + v], acc1, 0, 0, 0);
+            }
+        }
+        // C layout: lane holds channel (col) of pixels 4 kg + r
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int x = x0 + 4 * kg + r;
+            if (x >= W) continue;
+            const size_t p = (img + (size_t)y * W + x) * CH;
+            const float v0 = acc0[r] + bias0, v1 = acc1[r] + bias1;
+            if (z) { z[p + col] = v0; z[p + 16 + col] = v1; }
+            if (a) {
+                float o0 = v0, o1 = v1;
+                if (zg) {
+                    o0 *= silu_grad(zg[p + col]);
+                    o1 *= silu_grad(zg[p + 16 + col]);
+                } else if (act) {
+                    o0 = silu(v0);
+                    o1 = silu(v1);
+                }
+                a[p + col] = f2bf(o0);
+                a[p + 16 + col] = f2bf(o1);
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// weight gradient: dW[tap][co][ci] = sum_p gz[p][co] a_in[p + tap][ci],
-// db[co] = sum_p gz[p][co], over the pixel chunk of a block (64 pixels of
-// ROWS rows); partial sums per block, reduced by wgrad_reduce_kernel.
-// LDS holds gz^T [co][64 px] and the three input rows [ci][66 px] of a
-// chunk, so the MFMA fragments read contiguous k (pixel) runs.
+// weight gradient: dW[u][v][co][ci] = sum over pixels p of gz[p][co] times
+// a_in[p + (u - 1, v - 1)][ci], db[co] = sum_p gz[p][co].  Summed over the
+// input pixel q = p + (u - 1, v - 1) instead, the input is staged unshifted
+// and the gradient row in three horizontally shifted copies, so every MFMA
+// fragment is one aligned 16-byte LDS read.  A block owns 64 input columns
+// of `rows` consecutive gradient rows; the three input rows a gradient row
+// pairs with rotate through a ring in LDS, so each input row is staged
+// once.  Staging transposes channels-last data to [channel][pixel] in
+// registers (4 pixels x 8 channels per thread).  Wave w accumulates the
+// input-channel half 16 (w & 1) and the pixel half 32 (w >> 1) of every
+// tap; the two pixel halves are added in LDS at the end in a fixed order
+// and the block writes one partial sum, reduced by the two reduce kernels.
 // ---------------------------------------------------------------------------
-constexpr int WG_ROWS = 16;
+constexpr int WG_LD = 72;          // LDS row stride (u16): 64 pixels + 8, rows 16-byte aligned
+constexpr int WG_TARGET = 1024;    // blocks a weight-gradient launch aims for
+constexpr int WG_SEG = 64;         // segments of the first reduction stage
+constexpr int NWG = 9 * CH * CH;   // weight-gradient entries of one layer
+
+// pixels xs + 4 q .. xs + 4 q + 3 of row y, channels 8 cg .. 8 cg + 7, into
+// dst[channel][4 q + i] (zero outside the image)
+__device__ inline void stage_quad(u16* dst, const u16* __restrict__ src, size_t img, int H, int W, int y, int xs,
+                                  int q, int cg) {
+    unsigned w[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int x = xs + 4 * q + i;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (y >= 0 && y < H && x >= 0 && x < W)
+            v = *reinterpret_cast<const uint4*>(src + (img + (size_t)y * W + x) * CH + 8 * cg);
+        w[i][0] = v.x;
+        w[i][1] = v.y;
+        w[i][2] = v.z;
+        w[i][3] = v.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        // word k of a pixel holds channels 2k (low half) and 2k + 1 (high half)
+        uint2 lo, hi;
+        lo.x = (w[0][k] & 0xffffu) | (w[1][k] << 16);
+        lo.y = (w[2][k] & 0xffffu) | (w[3][k] << 16);
+        hi.x = (w[0][k] >> 16) | (w[1][k] & 0xffff0000u);
+        hi.y = (w[2][k] >> 16) | (w[3][k] & 0xffff0000u);
+        *reinterpret_cast<uint2*>(dst + (8 * cg + 2 * k) * WG_LD + 4 * q) = lo;
+        *reinterpret_cast<uint2*>(dst + (8 * cg + 2 * k + 1) * WG_LD + 4 * q) = hi;
+    }
+}
 
 __global__ __launch_bounds__(256) void conv_wgrad_kernel(const u16* __restrict__ gz, const u16* __restrict__ ain,
                                                          float* __restrict__ part_w, float* __restrict__ part_b,
-                                                         int H, int W) {
-    __shared__ u16 gT[CH][64];
-    __shared__ u16 aT[3][CH][72];
-    __shared__ float bsum[4][CH];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+                                                         int H, int W, int rows) {
+    // staging: gradient gT[3 shifts][32][72] and input aT[3 ring slots][32][72]
+    // (27 KB); at the end the same memory holds the pixel-half exchange (36 KB)
+    __shared__ __align__(16) unsigned char smem[2 * 72 * 64 * 4];
+    u16* gT = reinterpret_cast<u16*>(smem);
+    u16* aT = gT + 3 * CH * WG_LD;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane % 16, kg = lane / 16;
-    const int n = blockIdx.z;
-    const int x0 = blockIdx.x * 64;
-    const int yb = blockIdx.y * WG_ROWS;
+    const int cih = wave & 1, kh = wave >> 1;
+    const int n = blockIdx.z, x0 = blockIdx.x * 64;
+    const int ya = blockIdx.y * rows, yb = min(ya + rows, H);
     const size_t img = (size_t)n * H * W;
-    // a wave owns taps wave, wave+4 (and 8 for wave 0); each tap: 4 tiles
-    // (co half, ci half) of 16 x 16
-    f32x4 acc[3][4];
-    for (int t = 0; t < 3; ++t)
-        for (int q = 0; q < 4; ++q) acc[t][q] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    float bpart = 0.f;   // lanes 0..31 of wave 0..3 keep a channel's bias sum
-    for (int yy = yb; yy < yb + WG_ROWS && yy < H; ++yy) {
+    f32x4 acc[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) acc[i] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    float bpart = 0.f;   // channel tid / 8, pixels 8 (tid % 8) ..
+    // input rows ya - 1 and ya into their ring slots ((row + 3) mod 3)
+    if (tid < 128) {
+        const int r = ya - 1 + tid / 64;
+        stage_quad(aT + ((r + 3) % 3) * CH * WG_LD, ain, img, H, W, r, x0, (tid / 4) % 16, tid % 4);
+    }
+    for (int y = ya; y < yb; ++y) {
         __syncthreads();
-        // stage gz^T for pixels x0..x0+63 of row yy
-        for (int e = tid; e < 64 * CH; e += 256) {
-            const int px = e / CH, c = e % CH;
-            const int x = x0 + px;
-            gT[c][px] = x < W ? gz[(img + (size_t)yy * W + x) * CH + c] : (u16)0;
-        }
-        // stage input rows yy-1..yy+1, pixels x0-1..x0+64 (66, padded to 72)
-        for (int e = tid; e < 3 * 66 * CH; e += 256) {
-            const int r = e / (66 * CH), t = e % (66 * CH);
-            const int px = t / CH, c = t % CH;
-            const int y = yy + r - 1, x = x0 + px - 1;
-            aT[r][c][px] = (y >= 0 && y < H && x >= 0 && x < W) ? ain[(img + (size_t)y * W + x) * CH + c] : (u16)0;
+        if (tid < 192) {
+            // gT[v][co][px] = gz[y][x0 + px + 1 - v]
+            const int v = tid / 64;
+            stage_quad(gT + v * CH * WG_LD, gz, img, H, W, y, x0 + 1 - v, (tid / 4) % 16, tid % 4);
+        } else {
+            const int t = tid - 192;
+            stage_quad(aT + ((y + 1) % 3) * CH * WG_LD, ain, img, H, W, y + 1, x0, t / 4, t % 4);
         }
         __syncthreads();
-        if (tid < CH) {
-            float s = 0.f;
-            for (int px = 0; px < 64; ++px) s += bf2f(gT[tid][px]);
-            bpart += s;
+        {
+            const u16* g1 = gT + CH * WG_LD + (tid >> 3) * WG_LD + 8 * (tid & 7);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bpart += bf2f(g1[i]);
         }
-        for (int ti = 0; ti < 3; ++ti) {
-            const int tap = wave + 4 * ti;
-            if (tap >= 9) break;
-            const int u = tap / 3, v = tap % 3;
-            for (int kc = 0; kc < 64; kc += 32) {
-                for (int coh = 0; coh < 2; ++coh) {
-                    // A[co][p]: row co = 16 coh + col, k = pixels kc + 8 kg ..
-                    const bf16x8 A = load8(&gT[16 * coh + col][kc + 8 * kg]);
-                    for (int cih = 0; cih < 2; ++cih) {
-                        // B[p][ci]: column ci = 16 cih + col; pixel p reads input x + v - 1
-                        u16 bt[8];
-                        for (int i = 0; i < 8; ++i) bt[i] = aT[u][16 * cih + col][kc + 8 * kg + i + v];
-                        bf16x8 B;
-                        memcpy(&B, bt, 16);
-                        acc[ti][coh * 2 + cih] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[ti][coh * 2 + cih], 0, 0, 0);
-                    }
+        const int kc = 32 * kh + 8 * kg;
+        bf16x8 Bu[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) Bu[u] = load8(aT + ((y + u + 2) % 3) * CH * WG_LD + (16 * cih + col) * WG_LD + kc);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+#pragma unroll
+            for (int coh = 0; coh < 2; ++coh) {
+                const bf16x8 A = load8(gT + v * CH * WG_LD + (16 * coh + col) * WG_LD + kc);
+#pragma unroll
+                for (int u = 0; u < 3; ++u) {
+                    f32x4& c = acc[(u * 3 + v) * 2 + coh];
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bu[u], c, 0, 0, 0);
                 }
             }
         }
     }
+    // add the pixel halves: waves 2, 3 hand their sums to waves 0, 1
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(smem);
+    if (kh == 1) {
+#pragma unroll
+        for (int i = 0; i < 18; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[(cih * 72 + 4 * i + r) * 64 + lane] = acc[i][r];
+    }
+    __syncthreads();
     const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    float* pw = part_w + (size_t)blk * 9 * CH * CH;
-    for (int ti = 0; ti < 3; ++ti) {
-        const int tap = wave + 4 * ti;
-        if (tap >= 9) break;
-        for (int q = 0; q < 4; ++q) {
-            const int coh = q / 2, cih = q % 2;
+    if (kh == 0) {
+        float* pw = part_w + (size_t)blk * NWG;
+#pragma unroll
+        for (int i = 0; i < 18; ++i) {
+            const int tap = i / 2, coh = i % 2;
+#pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int co = 16 * coh + 4 * kg + r, ci = 16 * cih + col;
-                pw[(tap * CH + co) * CH + ci] = acc[ti][q][r];
+                pw[(tap * CH + co) * CH + ci] = acc[i][r] + red[(cih * 72 + 4 * i + r) * 64 + lane];
             }
         }
     }
-    if (tid < CH) part_b[(size_t)blk * CH + tid] = bpart;
-    (void)bsum;
+    bpart += __shfl_xor(bpart, 4);
+    bpart += __shfl_xor(bpart, 2);
+    bpart += __shfl_xor(bpart, 1);
+    if ((tid & 7) == 0) part_b[(size_t)blk * CH + (tid >> 3)] = bpart;
 }
 
-// sums the per-block partials in block order (deterministic)
-__global__ void wgrad_reduce_kernel(const float* part_w, const float* part_b, int nblk, float* gw, float* gb) {
+// first stage of the deterministic reduction: entry i (weights, then the 32
+// bias entries) summed over segment blockIdx.y of the block partials, in
+// block order
+__global__ void wgrad_reduce1_kernel(const float* part_w, const float* part_b, int nblk, float* part2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 9 * CH * CH) {
-        float s = 0.f;
-        for (int b = 0; b < nblk; ++b) s += part_w[(size_t)b * 9 * CH * CH + i];
+    if (i >= NWG + CH) return;
+    const int per = (nblk + gridDim.y - 1) / gridDim.y;
+    const int b0 = blockIdx.y * per, b1 = min(nblk, b0 + per);
+    float s = 0.f;
+    if (i < NWG)
+        for (int b = b0; b < b1; ++b) s += part_w[(size_t)b * NWG + i];
+    else
+        for (int b = b0; b < b1; ++b) s += part_b[(size_t)b * CH + i - NWG];
+    part2[(size_t)blockIdx.y * (NWG + CH) + i] = s;
+}
+
+// second stage: the segments in order
+__global__ void wgrad_reduce2_kernel(const float* part2, int nseg, float* gw, float* gb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NWG + CH) return;
+    float s = 0.f;
+    for (int k = 0; k < nseg; ++k) s += part2[(size_t)k * (NWG + CH) + i];
+    if (i < NWG)
         gw[i] = s;
-    }
-    if (i < CH) {
-        float s = 0.f;
-        for (int b = 0; b < nblk; ++b) s += part_b[(size_t)b * CH + i];
-        gb[i] = s;
-    }
+    else
+        gb[i - NWG] = s;
 }
 
 // gz = g * silu'(z) (hidden layers) or g (last layer), as bf16
@@ -271,9 +358,10 @@ __global__ void make_input_kernel(const float* m, const float* B, u16* x, int N,
     for (int c = 9; c < CH; ++c) xo[c] = 0;
 }
 
-// loss gradient of the mean squared error of the network output against
+// loss gradient (bf16: the gradient at the last layer's pre-activation) of
+// the mean squared error of the network output against
 // (m_target - base) / scale, and per-block loss partials
-__global__ void loss_kernel(const float* zout, const float* base, const float* mt, float* g, float* part, int N,
+__global__ void loss_kernel(const float* zout, const float* base, const float* mt, u16* gz, float* part, int N,
                             int H, int W, float inv_scale) {
     __shared__ float red[256];
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -291,7 +379,7 @@ __global__ void loss_kernel(const float* zout, const float* base, const float* m
                 l += d * d;
                 gv = 2.0f * d * inv;
             }
-            g[i * CH + c] = gv;
+            gz[i * CH + c] = f2bf(gv);
         }
     }
     red[threadIdx.x] = l;
@@ -303,11 +391,18 @@ __global__ void loss_kernel(const float* zout, const float* base, const float* m
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] * inv;
 }
 
+// one block of 256 threads: strided partial sums, then a fixed tree
 __global__ void sum_kernel(const float* part, int n, float* out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ float red[256];
     float s = 0.f;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
 }
 
 // proposals m' = normalize(base + scale * out)
@@ -403,13 +498,15 @@ struct llg_sur {
     float* mom2 = nullptr;
     u16* wf[NL] = {};                          // bf16 forward weights
     u16* wtr[NL] = {};                         // bf16 transposed/flipped weights
-    u16* act[NL + 1] = {};                     // activations (bf16, 32 ch)
+    u16* act[NL] = {};                         // layer inputs (bf16, 32 ch)
     float* z[NL] = {};                         // pre-activations (float, 32 ch)
     float* g = nullptr;                        // gradient w.r.t. a layer's output (float, 32 ch)
     u16* gz = nullptr;                         // gradient w.r.t. pre-activation (bf16)
+    u16* gz2 = nullptr;                        // the same for the layer below (ping-pong)
     float* gwp = nullptr;                      // reduced [tap][co][ci] weight gradient
     float* part_w = nullptr;
     float* part_b = nullptr;
+    float* part2 = nullptr;                    // first-stage sums of the weight-gradient reduction
     float* part_l = nullptr;
     float* dloss = nullptr;
     float* dm_in = nullptr;                    // staging for host inputs
@@ -448,8 +545,44 @@ llg_status sfail(llg_sur* s, llg_status c, const char* fmt, ...) {
                          hipGetErrorString(e_), __FILE__, __LINE__);                              \
     } while (0)
 
+// gradient rows per weight-gradient block: about WG_TARGET blocks, at
+// least 4 rows each
+int wg_rows(const llg_sur* s, int N) {
+    const long long rb = (long long)((s->W + 63) / 64) * s->H * N;
+    return (int)std::min<long long>(s->H, std::max<long long>(4, (rb + WG_TARGET - 1) / WG_TARGET));
+}
+dim3 wg_grid(const llg_sur* s, int N) {
+    const int r = wg_rows(s, N);
+    return dim3((s->W + 63) / 64, (s->H + r - 1) / r, N);
+}
 int wg_blocks(const llg_sur* s, int N) {
-    return ((s->W + 63) / 64) * ((s->H + WG_ROWS - 1) / WG_ROWS) * N;
+    const dim3 g = wg_grid(s, N);
+    return (int)(g.x * g.y * g.z);
+}
+
+// convolution rows per forward block: blocks of 64 pixels by `rows` rows,
+// about 2048 of them, at most 16 rows
+void launch_conv(llg_sur* s, const u16* in, const u16* wt, const float* bias, float* z, u16* a, const float* zg,
+                 int N, int act) {
+    const long long rb = (long long)((s->W + 63) / 64) * s->H * N;
+    const int rows = (int)std::min<long long>(16, std::max<long long>(1, rb / 2048));
+    hipLaunchKernelGGL(conv_fwd_kernel, dim3((s->W + 63) / 64, (s->H + rows - 1) / rows, N), dim3(256), 0,
+                       s->stream, in, wt, bias, z, a, zg, s->H, s->W, act, rows);
+}
+
+// weight and bias gradient of one layer from the pre-activation gradient
+// gz and the layer input ain: per-block partials, then two fixed-order
+// reduction stages into gwp ([tap][co][ci]) and gb (32 entries)
+void launch_wgrad(llg_sur* s, const u16* gz, const u16* ain, int N, float* gb) {
+    const dim3 grid = wg_grid(s, N);
+    const int nblk = (int)(grid.x * grid.y * grid.z);
+    hipLaunchKernelGGL(conv_wgrad_kernel, grid, dim3(256), 0, s->stream, gz, ain, s->part_w, s->part_b, s->H, s->W,
+                       wg_rows(s, N));
+    const int nseg = std::min(WG_SEG, nblk);
+    hipLaunchKernelGGL(wgrad_reduce1_kernel, dim3((NWG + CH + 255) / 256, nseg), dim3(256), 0, s->stream, s->part_w,
+                       s->part_b, nblk, s->part2);
+    hipLaunchKernelGGL(wgrad_reduce2_kernel, dim3((NWG + CH + 255) / 256), dim3(256), 0, s->stream, s->part2, nseg,
+                       s->gwp, gb);
 }
 
 llg_status pack(llg_sur* s) {
@@ -462,17 +595,18 @@ llg_status pack(llg_sur* s) {
     return LLG_OK;
 }
 
-llg_status forward(llg_sur* s, const float* m, const float* B, int N) {
+// keep_z: keep every layer's pre-activation (training needs them); else
+// only the last layer's (the output) is written
+llg_status forward(llg_sur* s, const float* m, const float* B, int N, bool keep_z) {
     const size_t npx = (size_t)N * s->H * s->W;
     hipLaunchKernelGGL(make_input_kernel, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s->stream, m, B,
                        s->act[0], N, s->H, s->W);
     SCHK(s, hipGetLastError());
-    const dim3 grid((s->W + 63) / 64, s->H, N);
     for (int l = 0; l < NL; ++l) {
         // the bias of a layer with fewer than 32 outputs is read through a
         // zero-padded 32-entry copy kept in the gradient buffer's tail
-        hipLaunchKernelGGL(conv_fwd_kernel, grid, dim3(256), 0, s->stream, s->act[l], s->wf[l],
-                           s->params + s->boff[l], s->z[l], s->act[l + 1], s->H, s->W, l < NL - 1 ? 1 : 0);
+        launch_conv(s, s->act[l], s->wf[l], s->params + s->boff[l], keep_z || l == NL - 1 ? s->z[l] : nullptr,
+                    l < NL - 1 ? s->act[l + 1] : nullptr, nullptr, N, l < NL - 1 ? 1 : 0);
         SCHK(s, hipGetLastError());
     }
     return LLG_OK;
@@ -538,12 +672,16 @@ llg_status llg_sur_create(int device, int H, int W, int max_batch, llg_sur** out
         SCHK(s, hipMalloc(&s->wtr[l], 9 * CH * CH * 2));
         SCHK(s, hipMalloc(&s->z[l], npx * CH * 4));
     }
-    for (int l = 0; l <= NL; ++l) SCHK(s, hipMalloc(&s->act[l], npx * CH * 2));
+    for (int l = 0; l < NL; ++l) SCHK(s, hipMalloc(&s->act[l], npx * CH * 2));
     SCHK(s, hipMalloc(&s->g, npx * CH * 4));
     SCHK(s, hipMalloc(&s->gz, npx * CH * 2));
+    SCHK(s, hipMalloc(&s->gz2, npx * CH * 2));
     SCHK(s, hipMalloc(&s->gwp, 9 * CH * CH * 4));
-    SCHK(s, hipMalloc(&s->part_w, (size_t)wg_blocks(s, max_batch) * 9 * CH * CH * 4));
-    SCHK(s, hipMalloc(&s->part_b, (size_t)wg_blocks(s, max_batch) * CH * 4));
+    int maxblk = 0;
+    for (int n = 1; n <= max_batch; ++n) maxblk = std::max(maxblk, wg_blocks(s, n));
+    SCHK(s, hipMalloc(&s->part_w, (size_t)maxblk * NWG * 4));
+    SCHK(s, hipMalloc(&s->part_b, (size_t)maxblk * CH * 4));
+    SCHK(s, hipMalloc(&s->part2, (size_t)WG_SEG * (NWG + CH) * 4));
     SCHK(s, hipMalloc(&s->part_l, ((npx + 255) / 256) * 4));
     SCHK(s, hipMalloc(&s->dloss, 4));
     SCHK(s, hipMalloc(&s->dm_in, npx * 3 * 4));
@@ -557,8 +695,8 @@ void llg_sur_destroy(llg_sur* s) {
     if (!s) return;
     (void)hipSetDevice(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    void* ptrs[] = {s->params, s->grads, s->mom1, s->mom2, s->g, s->gz, s->gwp, s->part_w, s->part_b,
-                    s->part_l, s->dloss, s->dm_in, s->dm_t, s->dm_out, s->dB};
+    void* ptrs[] = {s->params, s->grads, s->mom1, s->mom2, s->g, s->gz, s->gz2, s->gwp, s->part_w, s->part_b,
+                    s->part2, s->part_l, s->dloss, s->dm_in, s->dm_t, s->dm_out, s->dB};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (int l = 0; l < NL; ++l) {
@@ -566,7 +704,7 @@ void llg_sur_destroy(llg_sur* s) {
         if (s->wtr[l]) (void)hipFree(s->wtr[l]);
         if (s->z[l]) (void)hipFree(s->z[l]);
     }
-    for (int l = 0; l <= NL; ++l)
+    for (int l = 0; l < NL; ++l)
         if (s->act[l]) (void)hipFree(s->act[l]);
     if (s->props) (void)hipFree(s->props);
     if (s->dmax) (void)hipFree(s->dmax);
@@ -644,35 +782,29 @@ llg_status llg_sur_train_step(llg_sur* s, const float* m_in, const float* m_targ
     }
     if (!mb) mb = mi;
     SCHK(s, hipMemcpyAsync(s->dB, B, (size_t)batch * 3 * 4, hipMemcpyHostToDevice, s->stream));
-    llg_status rc = forward(s, mi, s->dB, batch);
+    llg_status rc = forward(s, mi, s->dB, batch, true);
     if (rc != LLG_OK) return rc;
     const int lb = (int)((npx + 255) / 256);
-    hipLaunchKernelGGL(loss_kernel, dim3(lb), dim3(256), 0, s->stream, s->z[NL - 1], mb, mt, s->g, s->part_l, batch,
+    hipLaunchKernelGGL(loss_kernel, dim3(lb), dim3(256), 0, s->stream, s->z[NL - 1], mb, mt, s->gz, s->part_l, batch,
                        s->H, s->W, 1.0f / s->out_scale);
     SCHK(s, hipGetLastError());
-    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, s->stream, s->part_l, lb, s->dloss);
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s->stream, s->part_l, lb, s->dloss);
     SCHK(s, hipGetLastError());
-    const dim3 fgrid((s->W + 63) / 64, s->H, batch);
-    const dim3 wgrid((s->W + 63) / 64, (s->H + WG_ROWS - 1) / WG_ROWS, batch);
-    const int nwb = wg_blocks(s, batch);
+    u16* gcur = s->gz;    // gradient at layer l's pre-activation
+    u16* gnext = s->gz2;
     for (int l = NL - 1; l >= 0; --l) {
-        hipLaunchKernelGGL(act_bwd_kernel, dim3((unsigned)((npx * CH + 255) / 256)), dim3(256), 0, s->stream, s->g,
-                           s->z[l], s->gz, npx * CH, l < NL - 1 ? 1 : 0);
-        SCHK(s, hipGetLastError());
-        hipLaunchKernelGGL(conv_wgrad_kernel, wgrid, dim3(256), 0, s->stream, s->gz, s->act[l], s->part_w,
-                           s->part_b, s->H, s->W);
-        SCHK(s, hipGetLastError());
-        hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((9 * CH * CH + 255) / 256), dim3(256), 0, s->stream, s->part_w,
-                           s->part_b, nwb, s->gwp, s->grads + s->boff[l]);
+        launch_wgrad(s, gcur, s->act[l], batch, s->grads + s->boff[l]);
         SCHK(s, hipGetLastError());
         hipLaunchKernelGGL(unpack_grad_kernel, dim3((COUT[l] * CIN[l] * 9 + 255) / 256), dim3(256), 0, s->stream,
                            s->gwp, CIN[l], COUT[l], s->grads + s->woff[l]);
         SCHK(s, hipGetLastError());
         if (l > 0) {
-            // data gradient: the same convolution with flipped, transposed weights
-            hipLaunchKernelGGL(conv_fwd_kernel, fgrid, dim3(256), 0, s->stream, s->gz, s->wtr[l], (const float*)nullptr,
-                               s->g, (u16*)nullptr, s->H, s->W, 0);
+            // data gradient: the same convolution with flipped, transposed
+            // weights, times SiLU'(z) of layer l - 1 (every hidden layer has
+            // the activation)
+            launch_conv(s, gcur, s->wtr[l], nullptr, nullptr, gnext, s->z[l - 1], batch, 0);
             SCHK(s, hipGetLastError());
+            std::swap(gcur, gnext);
         }
     }
     // note: the reduce kernel wrote 32 bias entries; the parameter arrays
@@ -714,7 +846,7 @@ llg_status llg_sur_predict(llg_sur* s, const float* m_in, const float* m_base, c
     }
     if (!mb) mb = mi;
     SCHK(s, hipMemcpyAsync(s->dB, B, (size_t)batch * 3 * 4, hipMemcpyHostToDevice, s->stream));
-    llg_status rc = forward(s, mi, s->dB, batch);
+    llg_status rc = forward(s, mi, s->dB, batch, false);
     if (rc != LLG_OK) return rc;
     hipLaunchKernelGGL(propose_kernel, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s->stream, mb,
                        s->z[NL - 1], mo, batch, s->H, s->W, s->out_scale);
@@ -733,7 +865,7 @@ llg_status llg_sur_forward_raw(llg_sur* s, const float* m_in, const float* B, in
     const size_t npx = (size_t)batch * s->H * s->W;
     SCHK(s, hipMemcpyAsync(s->dm_in, m_in, npx * 3 * 4, hipMemcpyHostToDevice, s->stream));
     SCHK(s, hipMemcpyAsync(s->dB, B, (size_t)batch * 3 * 4, hipMemcpyHostToDevice, s->stream));
-    llg_status rc = forward(s, s->dm_in, s->dB, batch);
+    llg_status rc = forward(s, s->dm_in, s->dB, batch, true);
     if (rc != LLG_OK) return rc;
     SCHK(s, hipMemcpyAsync(z_out, s->z[layer], npx * CH * 4, hipMemcpyDeviceToHost, s->stream));
     SCHK(s, hipStreamSynchronize(s->stream));
@@ -755,9 +887,7 @@ llg_status llg_sur_conv_check(llg_sur* s, int layer, const float* x, const float
     SCHK(s, hipMemcpyAsync(s->g, x, n * 4, hipMemcpyHostToDevice, s->stream));
     hipLaunchKernelGGL(to_bf16_kernel, dim3(nb), dim3(256), 0, s->stream, s->g, s->act[0], n);
     SCHK(s, hipGetLastError());
-    const dim3 fgrid((s->W + 63) / 64, s->H, batch);
-    hipLaunchKernelGGL(conv_fwd_kernel, fgrid, dim3(256), 0, s->stream, s->act[0], s->wf[layer],
-                       s->params + s->boff[layer], s->z[0], (u16*)nullptr, s->H, s->W, 0);
+    launch_conv(s, s->act[0], s->wf[layer], s->params + s->boff[layer], s->z[0], nullptr, nullptr, batch, 0);
     SCHK(s, hipGetLastError());
     SCHK(s, hipMemcpyAsync(y, s->z[0], n * 4, hipMemcpyDeviceToHost, s->stream));
     if (gy) {
@@ -767,18 +897,12 @@ llg_status llg_sur_conv_check(llg_sur* s, int layer, const float* x, const float
         SCHK(s, hipMemcpyAsync(s->g, gy, n * 4, hipMemcpyHostToDevice, s->stream));
         hipLaunchKernelGGL(act_bwd_kernel, dim3(nb), dim3(256), 0, s->stream, s->g, (const float*)nullptr, s->gz, n, 0);
         SCHK(s, hipGetLastError());
-        const dim3 wgrid((s->W + 63) / 64, (s->H + WG_ROWS - 1) / WG_ROWS, batch);
-        hipLaunchKernelGGL(conv_wgrad_kernel, wgrid, dim3(256), 0, s->stream, s->gz, s->act[0], s->part_w,
-                           s->part_b, s->H, s->W);
-        SCHK(s, hipGetLastError());
-        hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((9 * CH * CH + 255) / 256), dim3(256), 0, s->stream, s->part_w,
-                           s->part_b, wg_blocks(s, batch), s->gwp, dgb);
+        launch_wgrad(s, s->gz, s->act[0], batch, dgb);
         SCHK(s, hipGetLastError());
         hipLaunchKernelGGL(unpack_grad_kernel, dim3((COUT[layer] * CIN[layer] * 9 + 255) / 256), dim3(256), 0,
                            s->stream, s->gwp, CIN[layer], COUT[layer], dgw);
         SCHK(s, hipGetLastError());
-        hipLaunchKernelGGL(conv_fwd_kernel, fgrid, dim3(256), 0, s->stream, s->gz, s->wtr[layer],
-                           (const float*)nullptr, s->z[1], (u16*)nullptr, s->H, s->W, 0);
+        launch_conv(s, s->gz, s->wtr[layer], nullptr, s->z[1], nullptr, nullptr, batch, 0);
         SCHK(s, hipGetLastError());
         SCHK(s, hipMemcpyAsync(gx, s->z[1], n * 4, hipMemcpyDeviceToHost, s->stream));
         SCHK(s, hipMemcpyAsync(gw, dgw, sizeof(float) * COUT[layer] * CIN[layer] * 9, hipMemcpyDeviceToHost,
@@ -913,7 +1037,7 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
                 if (rc != LLG_OK) return sfail(s, rc, "predictor batch: %s", llg_batch_last_error(s->eb));
                 base = em;
             }
-            llg_status rc = forward(s, prev, s->dB, 1);
+            llg_status rc = forward(s, prev, s->dB, 1, false);
             if (rc != LLG_OK) return rc;
             hipLaunchKernelGGL(propose_kernel, dim3((ncells + 255) / 256), dim3(256), 0, s->stream, base,
                                s->z[NL - 1], P + (size_t)j * 3 * ncells, 1, s->H, s->W, s->out_scale);
