@@ -46,11 +46,14 @@ def test_mfma_lane_layout(lib):
     assert np.array_equal(C, A @ B)      # small integers: exact in BF16 and FP32
 
 
-@pytest.mark.parametrize("layer", [0, 1, 5])
-def test_conv_layer_parity(lib, layer):
+@pytest.mark.parametrize("layer,N", [(0, 2), (1, 2), (5, 2), (1, 56)])
+def test_conv_layer_parity(lib, layer, N):
     """PIN-18: forward, weight, bias and input gradients of one layer, BF16
-    operands, against the FP64 oracle on the same rounded values."""
-    H, W, N = 37, 70, 2           # two column tiles with a ragged tail, odd rows
+    operands, against the FP64 oracle on the same rounded values.  Two column
+    tiles with a ragged tail and an odd row count; at batch 56 a forward
+    block covers two rows and a weight-gradient block five (ragged last
+    block in both)."""
+    H, W = 37, 70
     ci, co = LAYERS[layer]
     params = rounded_params(3)
     sur = lib.Surrogate(H, W, max_batch=N)
