@@ -78,6 +78,7 @@ struct llg_batch {
     FilmRow* d_fix[4] = {};
     int fix_method = -1;
     hipGraphExec_t gfix = nullptr;
+    hipEvent_t ev_in = nullptr;         // start states ready on the caller's stream
     bool spec_valid = false;            // S holds the forward x pass of every film's m
 };
 
@@ -504,6 +505,7 @@ void llg_batch_destroy(llg_batch* b) {
     for (auto& c : b->cols) bfree(c.map);
     for (auto st : b->aux) (void)hipStreamDestroy(st);
     for (auto e : b->ev) (void)hipEventDestroy(e);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -623,27 +625,55 @@ llg_status llg_batch_get_attempts(llg_batch* b, int film, llg_attempt* out, int6
     return LLG_OK;
 }
 
-llg_status llg_batch_step(llg_batch* b, llg_method method, double dt, int64_t nsteps) {
-    if (!b) return LLG_E_ARG;
-    b->err.clear();
-    BCHK(b, hipSetDevice(b->device));
+}  // extern "C"
+
+namespace {
+
+// nsteps fixed steps of every film.  With src, films 0..nload-1 first take
+// new start states src + j * stride (floats), copied on the batch stream once
+// `producer` has reached this point; only those films' health is then
+// checked, and out[j] receives their end-state buffers.  The state block is
+// read twice (two host synchronisations) and written without a wait of its
+// own.
+llg_status fixed_core(llg_batch* b, llg_method method, double dt, int64_t nsteps, const float* src, size_t stride,
+                      int nload, hipStream_t producer, float** out) {
     Tableau t;
     if (!fixed_of(method, &t)) return bfail(b, LLG_E_ARG, "llg_batch_step takes Euler, Heun, RK3 or RK4");
     if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return bfail(b, LLG_E_ARG, "need dt > 0, nsteps >= 0");
-    if (nsteps == 0) return LLG_OK;
+    if (src && (nload < 1 || nload > (int)b->films.size())) return bfail(b, LLG_E_ARG, "bad start-state count");
+    if (nsteps == 0 && !src) return LLG_OK;
     std::vector<DevState> h;
     llg_status rc = restore_classes(b);
     if (rc != LLG_OK) return rc;
     if ((rc = read_states(b, h)) != LLG_OK) return rc;
-    if (rc != LLG_OK) return rc;
+    const int nchk = src ? nload : (int)h.size();
+    if (src) {
+        if (!b->ev_in) BCHK(b, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+        BCHK(b, hipEventRecord(b->ev_in, producer));
+        BCHK(b, hipStreamWaitEvent(b->stream, b->ev_in, 0));
+        for (int j = 0; j < nload; ++j) {
+            const BatchFilm& f = b->films[j];
+            BCHK(b, hipMemcpyAsync(f.mbuf[h[j].cur], src + (size_t)j * stride, sizeof(float) * 3 * (size_t)f.g.ncells,
+                                   hipMemcpyDeviceToDevice, b->stream));
+            h[j].health = 0;
+        }
+        b->spec_valid = false;
+        b->k1_valid = false;
+    }
     for (size_t i = 0; i < h.size(); ++i) {
-        if (h[i].health) return bfail(b, LLG_E_DIVERGED, "film %d has already diverged", (int)i);
+        if ((int)i < nchk && h[i].health) return bfail(b, LLG_E_DIVERGED, "film %d has already diverged", (int)i);
         h[i].dt = dt;
         h[i].dtau = (float)(dt * kGamma0 * b->films[i].mat.Ms);
         h[i].gms = kGamma0 * b->films[i].mat.Ms;
         h[i].done = 0;
     }
-    if ((rc = write_states(b, h)) != LLG_OK) return rc;
+    BCHK(b, hipMemcpyAsync(b->st, h.data(), sizeof(DevState) * h.size(), hipMemcpyHostToDevice, b->stream));
+    // every return from here on leaves the stream drained, so h (the copy's
+    // source) is never released under a pending transfer
+    struct Drain {
+        hipStream_t s;
+        ~Drain() { (void)hipStreamSynchronize(s); }
+    } drain{b->stream};
     if (!b->spec_valid)
         PASS(b, PASS_ROW_FWD, b->d_fwd_plain);
     if (!b->gfix || b->fix_method != (int)method) {
@@ -666,9 +696,22 @@ llg_status llg_batch_step(llg_batch* b, llg_method method, double dt, int64_t ns
     b->spec_valid = true;
     b->k1_valid = false;
     if ((rc = read_states(b, h)) != LLG_OK) return rc;
-    for (size_t i = 0; i < h.size(); ++i)
-        if (h[i].health) return bfail(b, LLG_E_DIVERGED, "film %d: non-finite field or torque", (int)i);
+    for (int i = 0; i < nchk; ++i)
+        if (h[i].health) return bfail(b, LLG_E_DIVERGED, "film %d: non-finite field or torque", i);
+    if (out)
+        for (int j = 0; j < nload; ++j) out[j] = b->films[j].mbuf[h[j].cur];
     return LLG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+llg_status llg_batch_step(llg_batch* b, llg_method method, double dt, int64_t nsteps) {
+    if (!b) return LLG_E_ARG;
+    b->err.clear();
+    BCHK(b, hipSetDevice(b->device));
+    return fixed_core(b, method, dt, nsteps, nullptr, 0, 0, nullptr, nullptr);
 }
 
 llg_status llg_batch_set_m(llg_batch* b, int film, const float* m, llg_mem where) {
@@ -705,22 +748,13 @@ llg_status llg_batch_set_m(llg_batch* b, int film, const float* m, llg_mem where
 
 // ---- shared with the surrogate's speculative verification ------------------
 
-hipStream_t llg_batch_stream_(llg_batch* b) { return b->stream; }
-
-// the device buffer that holds a film's current state (reads the device
-// state, so the stream is synchronised)
-llg_status llg_batch_state_ptr_(llg_batch* b, int film, float** m) {
-    if (!b || !m || film < 0 || film >= (int)b->films.size()) return LLG_E_ARG;
-    std::vector<DevState> h;
-    llg_status rc = read_states(b, h);
-    if (rc != LLG_OK) return rc;
-    *m = b->films[film].mbuf[h[film].cur];
-    return LLG_OK;
-}
-
-// marks the states as replaced in place (by copies into the buffers named by
-// llg_batch_state_ptr_), so the next step recomputes the forward pass
-void llg_batch_states_replaced_(llg_batch* b) {
-    b->spec_valid = false;
-    b->k1_valid = false;
+// films 0..nload-1 restart from src + j * stride (device floats, ready once
+// `producer` reaches this call), every film takes nsteps fixed steps, and
+// out[j] names film j's end state; two host synchronisations in all
+llg_status llg_batch_fixed_from_(llg_batch* b, llg_method method, double dt, int64_t nsteps, const float* src,
+                                 size_t stride, int nload, hipStream_t producer, float** out) {
+    if (!b || !src || !out) return LLG_E_ARG;
+    b->err.clear();
+    BCHK(b, hipSetDevice(b->device));
+    return fixed_core(b, method, dt, nsteps, src, stride, nload, producer, out);
 }

@@ -235,6 +235,5 @@ hipError_t tensor_at_offsets(const TensorGeom& tg, const int32_t* offs_dev, long
 }  // namespace llg
 
 // batch internals shared with the surrogate (batch.hip)
-hipStream_t llg_batch_stream_(llg_batch* b);
-llg_status llg_batch_state_ptr_(llg_batch* b, int film, float** m);
-void llg_batch_states_replaced_(llg_batch* b);
+llg_status llg_batch_fixed_from_(llg_batch* b, llg_method method, double dt, int64_t nsteps, const float* src,
+                                 size_t stride, int nload, hipStream_t producer, float** out);

@@ -1026,14 +1026,9 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
             const float* base = prev;
             if (predictor != LLG_SUR_BASE_STATE) {
                 float* em = nullptr;
-                llg_status rc = llg_batch_state_ptr_(s->eb, 0, &em);
-                if (rc != LLG_OK) return sfail(s, rc, "predictor batch: %s", llg_batch_last_error(s->eb));
-                SCHK(s, hipMemcpyAsync(em, prev, vec, hipMemcpyDeviceToDevice, s->stream));
-                SCHK(s, hipStreamSynchronize(s->stream));
-                llg_batch_states_replaced_(s->eb);
-                rc = llg_batch_step(s->eb, predictor == LLG_SUR_BASE_EULER ? LLG_EULER : LLG_RK4, dt * seg_steps, 1);
-                if (rc != LLG_OK) return sfail(s, rc, "predictor batch: %s", llg_batch_last_error(s->eb));
-                rc = llg_batch_state_ptr_(s->eb, 0, &em);
+                const llg_status rc = llg_batch_fixed_from_(
+                    s->eb, predictor == LLG_SUR_BASE_EULER ? LLG_EULER : LLG_RK4, dt * seg_steps, 1, prev, 0, 1,
+                    s->stream, &em);
                 if (rc != LLG_OK) return sfail(s, rc, "predictor batch: %s", llg_batch_last_error(s->eb));
                 base = em;
             }
@@ -1060,19 +1055,9 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
         for (int j = 1; j < w; ++j)
             if (hd[window + j - 1] != 0u) { nstart = j; break; }
         // plain segments from every start state, one batched launch per step
-        for (int j = 0; j < nstart; ++j) {
-            llg_status rc = llg_batch_state_ptr_(s->vb, j, &ptr[j]);
-            if (rc != LLG_OK) return sfail(s, rc, "verification batch: %s", llg_batch_last_error(s->vb));
-            SCHK(s, hipMemcpyAsync(ptr[j], P + (size_t)j * 3 * ncells, vec, hipMemcpyDeviceToDevice, s->stream));
-        }
-        SCHK(s, hipStreamSynchronize(s->stream));
-        llg_batch_states_replaced_(s->vb);
-        llg_status rc = llg_batch_step(s->vb, LLG_RK4, dt, seg_steps);
+        llg_status rc = llg_batch_fixed_from_(s->vb, LLG_RK4, dt, seg_steps, P, 3 * (size_t)ncells, nstart, s->stream,
+                                              ptr.data());
         if (rc != LLG_OK) return sfail(s, rc, "verification batch: %s", llg_batch_last_error(s->vb));
-        for (int j = 0; j < nstart; ++j) {
-            rc = llg_batch_state_ptr_(s->vb, j, &ptr[j]);
-            if (rc != LLG_OK) return sfail(s, rc, "verification batch: %s", llg_batch_last_error(s->vb));
-        }
         // distance of every proposal to the plain result from its predecessor
         for (int j = 1; j <= nstart; ++j) {
             rc = max_distance(s, P + (size_t)j * 3 * ncells, ptr[j - 1], ncells, s->dmax + j - 1);
