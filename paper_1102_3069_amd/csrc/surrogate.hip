@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ i
                 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B1[u * 3 + v], acc1, 0, 0, 0);
             }
         }
-        // C layout: lane holds channel (col) of pixels 4 kg + r
+        // C layout: lane holds channels col and 16 + col of pixel 4 kg + r
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int x = x0 + 4 * kg + r;
@@ -345,17 +345,22 @@ __global__ void make_input_kernel(const float* m, const float* B, u16* x, int N,
     if (i >= npx) return;
     const int n = (int)(i / ((size_t)H * W));
     const size_t p = i - (size_t)n * H * W;
-    u16* xo = x + i * CH;
     // m as a BF16 pair: hi = bf16(m), lo = bf16(256 (m - hi)) (m - hi is
     // exact in FP32), so the first layer sees m to about 16 bits
+    uint32_t ch[9];
     for (int c = 0; c < 3; ++c) {
         const float v = m[((size_t)n * 3 + c) * H * W + p];
         const u16 hi = f2bf(v);
-        xo[c] = hi;
-        xo[3 + c] = f2bf((v - bf2f(hi)) * LO_SCALE);
+        ch[c] = hi;
+        ch[3 + c] = f2bf((v - bf2f(hi)) * LO_SCALE);
     }
-    for (int c = 0; c < 3; ++c) xo[6 + c] = f2bf(B[n * 3 + c] / B_SCALE);
-    for (int c = 9; c < CH; ++c) xo[c] = 0;
+    for (int c = 0; c < 3; ++c) ch[6 + c] = f2bf(B[n * 3 + c] / B_SCALE);
+    // the pixel's 32 channels as four 16-byte stores (channels 9.. zero)
+    uint4* xo = reinterpret_cast<uint4*>(x + i * CH);
+    xo[0] = make_uint4(ch[0] | ch[1] << 16, ch[2] | ch[3] << 16, ch[4] | ch[5] << 16, ch[6] | ch[7] << 16);
+    xo[1] = make_uint4(ch[8], 0u, 0u, 0u);
+    xo[2] = make_uint4(0u, 0u, 0u, 0u);
+    xo[3] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // loss gradient (bf16: the gradient at the last layer's pre-activation) of
@@ -371,16 +376,19 @@ __global__ void loss_kernel(const float* zout, const float* base, const float* m
     if (i < npx) {
         const int n = (int)(i / ((size_t)H * W));
         const size_t p = i - (size_t)n * H * W;
-        for (int c = 0; c < CH; ++c) {
-            float gv = 0.f;
-            if (c < 3) {
-                const size_t q = ((size_t)n * 3 + c) * H * W + p;
-                const float d = zout[i * CH + c] - (mt[q] - base[q]) * inv_scale;
-                l += d * d;
-                gv = 2.0f * d * inv;
-            }
-            gz[i * CH + c] = f2bf(gv);
+        uint32_t gb[3];
+        for (int c = 0; c < 3; ++c) {
+            const size_t q = ((size_t)n * 3 + c) * H * W + p;
+            const float d = zout[i * CH + c] - (mt[q] - base[q]) * inv_scale;
+            l += d * d;
+            gb[c] = f2bf(2.0f * d * inv);
         }
+        // the pixel's 32 gradient channels (3.. zero) as four 16-byte stores
+        uint4* go = reinterpret_cast<uint4*>(gz + i * CH);
+        go[0] = make_uint4(gb[0] | gb[1] << 16, gb[2], 0u, 0u);
+        go[1] = make_uint4(0u, 0u, 0u, 0u);
+        go[2] = make_uint4(0u, 0u, 0u, 0u);
+        go[3] = make_uint4(0u, 0u, 0u, 0u);
     }
     red[threadIdx.x] = l;
     __syncthreads();
