@@ -96,7 +96,8 @@ struct RowSplit {
     using F = LaneFFT<LQ, E2, NQ, float2>;
     // LDS (bytes): twiddles W^m (m < PX); FFT scratch; the exchange of the
     // inverse transforms (inverse kernel only); staged m rows (with the y
-    // neighbours); new m rows; reduction slots
+    // neighbours), which the inverse kernel overwrites with the new m rows
+    // once every cell has its field; reduction slots
     static constexpr int O_TW = 0;
     static constexpr int O_SCR = lds_align(PX * 8);
     static constexpr int SCR_BYTES = NG * SC * 8;
@@ -104,15 +105,15 @@ struct RowSplit {
     static constexpr int NR = 2 * RP + 2;
     // the exchange gets its own region unless that would not fit the LDS
     // (then it aliases the scratch, behind one more barrier)
-    static constexpr int SEP_BYTES = lds_align(O_M + NG * LQ * 8) + (NR + 2 * RP) * 3 * PX * 4 + 64;
+    static constexpr int SEP_BYTES = lds_align(O_M + NG * LQ * 8) + NR * 3 * PX * 4 + 64;
     static constexpr bool XALIAS = SEP_BYTES > 160 * 1024;
     static constexpr int O_XCH = XALIAS ? O_SCR : O_M;
     static_assert(NG * LQ * 8 <= SCR_BYTES, "the exchange fits the scratch");
     static constexpr int O_MI = XALIAS ? O_M : lds_align(O_M + NG * LQ * 8);
     template <bool XPER> static constexpr int nxm() { return XPER ? PX : H; }
     template <bool XPER> static constexpr int fwd_bytes() { return lds_align(O_M + 2 * RP * 3 * nxm<XPER>() * 4); }
-    template <bool XPER> static constexpr int o_nm() { return lds_align(O_MI + NR * 3 * nxm<XPER>() * 4); }
-    template <bool XPER> static constexpr int o_wmax() { return lds_align(o_nm<XPER>() + 2 * RP * 3 * nxm<XPER>() * 4); }
+    template <bool XPER> static constexpr int o_nm() { return O_MI; }
+    template <bool XPER> static constexpr int o_wmax() { return lds_align(O_MI + NR * 3 * nxm<XPER>() * 4); }
     template <bool XPER> static constexpr int inv_bytes() { return lds_align(o_wmax<XPER>() + 16 * 4); }
 
     // group gi -> (kind, class, pair), the pair fastest: the groups of one
@@ -348,7 +349,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     float2* scr = (float2*)(lds + R::O_SCR);
     float2* xch = (float2*)(lds + R::O_XCH);
     float* mrow = (float*)(lds + R::O_MI);
-    float* nm = (float*)(lds + R::template o_nm<XPER>());
+    float* nm = (float*)(lds + R::template o_nm<XPER>());   // aliases mrow
     float* wmax = (float*)(lds + R::template o_wmax<XPER>());
     if (st->done) return;
     const int tid = threadIdx.x;
@@ -439,6 +440,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     const int ncb = nrow * nx;
     const float rnx = 1.0f / (float)nx;
     float px_[MAXIT], py_[MAXIT], pz_[MAXIT], ex_[MAXIT], ey_[MAXIT], ez_[MAXIT];
+    float mnx[MAXIT], mny[MAXIT], mnz[MAXIT];   // the new stage state, held until the staged rows are free
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
         px_[it] = py_[it] = pz_[it] = ex_[it] = ey_[it] = ez_[it] = 0.f;
@@ -566,8 +568,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             const float inv = rsqrtf(ax * ax + ay * ay + az * az);
             ax *= inv; ay *= inv; az *= inv;
             mo[qq] = ax; mo[cs + qq] = ay; mo[2 * cs + qq] = az;
-            float* row = nm + ri * 3 * NXM;
-            row[x] = ax; row[NXM + x] = ay; row[2 * NXM + x] = az;
+            mnx[it] = ax; mny[it] = ay; mnz[it] = az;
         }
         if (errm) errmax = fmaxf(errmax, dtau * sqrtf(ex * ex + ey * ey + ez * ez));
     }
@@ -584,7 +585,17 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         if (!stage) return;
     }
     if (stage && p.demag_on && !sa.skip_fwd) {
-        __syncthreads();   // new rows complete, exchange no longer read
+        __syncthreads();   // staged rows and exchange no longer read
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) {
+            const int e = tid + it * NT;
+            if (e >= ncb) continue;
+            int ri, x;
+            split_cell(e, nx, rnx, ri, x);
+            float* row = nm + ri * 3 * NXM;
+            row[x] = mnx[it]; row[NXM + x] = mny[it]; row[2 * NXM + x] = mnz[it];
+        }
+        __syncthreads();   // new rows complete
         R::template forward<NXM, NAT>(g, S, scr, tw, nm, kind, q, pair, lg, gbase, rb);
     }
 }
