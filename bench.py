@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--sur-traj", type=int, default=100, help="surrogate: training trajectories")
     ap.add_argument("--sur-pairs", type=int, default=200, help="surrogate: pairs per trajectory")
     ap.add_argument("--sur-epochs", type=float, default=4.0, help="surrogate: passes over the pairs")
-    ap.add_argument("--sur-window", type=int, default=8, help="surrogate: proposals per round")
+    ap.add_argument("--sur-window", type=int, default=16, help="surrogate: proposals per round")
     ap.add_argument("--sur-held-out", type=int, default=8, help="surrogate: held-out trajectories")
     ap.add_argument("--sur-segments", type=int, default=200, help="surrogate: segments per held-out run")
     return ap.parse_args()
