@@ -79,6 +79,13 @@ struct llg_batch {
     int fix_method = -1;
     hipGraphExec_t gfix = nullptr;
     hipEvent_t ev_in = nullptr;         // start states ready on the caller's stream
+    hipEvent_t ev_out = nullptr;        // end of the last enqueued fixed steps
+    // where each film's state sits (mbuf index), known on the host after
+    // fixed steps without a state read; hcur_ok is cleared by every call that
+    // can move a state otherwise
+    std::vector<int> hcur;
+    bool hcur_ok = false;
+    double fix_dt = 0.0;                // step of the last fixed steps, held in the device states
     bool spec_valid = false;            // S holds the forward x pass of every film's m
 };
 
@@ -506,6 +513,7 @@ void llg_batch_destroy(llg_batch* b) {
     for (auto st : b->aux) (void)hipStreamDestroy(st);
     for (auto e : b->ev) (void)hipEventDestroy(e);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -519,6 +527,7 @@ llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0,
     BCHK(b, hipSetDevice(b->device));
     if (!(max_err > 0) || !(dt0 >= 0) || !isfinite(t_end) || !isfinite(dt0))
         return bfail(b, LLG_E_ARG, "need max_err > 0, dt0 >= 0");
+    b->hcur_ok = false;
     const int nf = (int)b->films.size();
     std::vector<DevState> h;
     llg_status rc = restore_classes(b);
@@ -631,10 +640,10 @@ namespace {
 
 // nsteps fixed steps of every film.  With src, films 0..nload-1 first take
 // new start states src + j * stride (floats), copied on the batch stream once
-// `producer` has reached this point; only those films' health is then
-// checked, and out[j] receives their end-state buffers.  The state block is
-// read twice (two host synchronisations) and written without a wait of its
-// own.
+// `producer` has reached this point, out[j] receives their end-state buffers
+// and no film's health is checked (the caller checks the end states it
+// uses).  The state block is read twice (two host synchronisations) and
+// written without a wait of its own.
 llg_status fixed_core(llg_batch* b, llg_method method, double dt, int64_t nsteps, const float* src, size_t stride,
                       int nload, hipStream_t producer, float** out) {
     Tableau t;
@@ -642,11 +651,12 @@ llg_status fixed_core(llg_batch* b, llg_method method, double dt, int64_t nsteps
     if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return bfail(b, LLG_E_ARG, "need dt > 0, nsteps >= 0");
     if (src && (nload < 1 || nload > (int)b->films.size())) return bfail(b, LLG_E_ARG, "bad start-state count");
     if (nsteps == 0 && !src) return LLG_OK;
+    b->hcur_ok = false;
     std::vector<DevState> h;
     llg_status rc = restore_classes(b);
     if (rc != LLG_OK) return rc;
     if ((rc = read_states(b, h)) != LLG_OK) return rc;
-    const int nchk = src ? nload : (int)h.size();
+    const int nchk = src ? 0 : (int)h.size();
     if (src) {
         if (!b->ev_in) BCHK(b, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
         BCHK(b, hipEventRecord(b->ev_in, producer));
@@ -696,11 +706,20 @@ llg_status fixed_core(llg_batch* b, llg_method method, double dt, int64_t nsteps
     b->spec_valid = true;
     b->k1_valid = false;
     if ((rc = read_states(b, h)) != LLG_OK) return rc;
+    b->hcur.resize(h.size());
+    for (size_t i = 0; i < h.size(); ++i) b->hcur[i] = h[i].cur;
+    b->hcur_ok = true;
+    b->fix_dt = dt;
     for (int i = 0; i < nchk; ++i)
         if (h[i].health) return bfail(b, LLG_E_DIVERGED, "film %d: non-finite field or torque", i);
     if (out)
         for (int j = 0; j < nload; ++j) out[j] = b->films[j].mbuf[h[j].cur];
     return LLG_OK;
+}
+
+__global__ void clear_health_kernel(DevState* st, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) st[i].health = 0;
 }
 
 }  // namespace
@@ -718,6 +737,7 @@ llg_status llg_batch_set_m(llg_batch* b, int film, const float* m, llg_mem where
     if (!b || !m || film < 0 || film >= (int)b->films.size()) return LLG_E_ARG;
     b->err.clear();
     BCHK(b, hipSetDevice(b->device));
+    b->hcur_ok = false;
     std::vector<DevState> h;
     llg_status rc = read_states(b, h);
     if (rc != LLG_OK) return rc;
@@ -749,12 +769,51 @@ llg_status llg_batch_set_m(llg_batch* b, int film, const float* m, llg_mem where
 // ---- shared with the surrogate's speculative verification ------------------
 
 // films 0..nload-1 restart from src + j * stride (device floats, ready once
-// `producer` reaches this call), every film takes nsteps fixed steps, and
-// out[j] names film j's end state; two host synchronisations in all
-llg_status llg_batch_fixed_from_(llg_batch* b, llg_method method, double dt, int64_t nsteps, const float* src,
-                                 size_t stride, int nload, hipStream_t producer, float** out) {
-    if (!b || !src || !out) return LLG_E_ARG;
+// `producer` reaches this call) and every film takes nsteps fixed steps;
+// out[j] names film j's end state.  The first call (and any call after
+// another batch operation or with another method or step) goes through the
+// synchronous path, which also checks health; later calls only enqueue work
+// (no host synchronisation, health not checked: a caller that needs the
+// end states finite checks them).  llg_batch_then_ orders a consumer stream
+// after the enqueued steps.
+llg_status llg_batch_fixed_async_(llg_batch* b, llg_method method, double dt, int64_t nsteps, const float* src,
+                                  size_t stride, int nload, hipStream_t producer, float** out) {
+    if (!b || !src || !out || nsteps < 1 || nload < 1 || nload > (int)b->films.size()) return LLG_E_ARG;
     b->err.clear();
     BCHK(b, hipSetDevice(b->device));
-    return fixed_core(b, method, dt, nsteps, src, stride, nload, producer, out);
+    if (!b->hcur_ok || !b->gfix || b->fix_method != (int)method || b->fix_dt != dt) {
+        const llg_status rc = fixed_core(b, method, dt, nsteps, src, stride, nload, producer, out);
+        if (rc != LLG_OK) return rc;
+    } else {
+        const llg_status rc = restore_classes(b);
+        if (rc != LLG_OK) return rc;
+        if (!b->ev_in) BCHK(b, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+        BCHK(b, hipEventRecord(b->ev_in, producer));
+        BCHK(b, hipStreamWaitEvent(b->stream, b->ev_in, 0));
+        for (int j = 0; j < nload; ++j) {
+            const BatchFilm& f = b->films[j];
+            BCHK(b, hipMemcpyAsync(f.mbuf[b->hcur[j]], src + (size_t)j * stride,
+                                   sizeof(float) * 3 * (size_t)f.g.ncells, hipMemcpyDeviceToDevice, b->stream));
+        }
+        hipLaunchKernelGGL(clear_health_kernel, dim3((nload + 63) / 64), dim3(64), 0, b->stream, b->st, nload);
+        BCHK(b, hipGetLastError());
+        b->spec_valid = false;
+        b->k1_valid = false;
+        PASS(b, PASS_ROW_FWD, b->d_fwd_plain);
+        for (int64_t i = 0; i < nsteps; ++i) BCHK(b, hipGraphLaunch(b->gfix, b->stream));
+        b->spec_valid = true;
+        if (nsteps & 1)
+            for (auto& c : b->hcur) c ^= 1;
+        for (int j = 0; j < nload; ++j) out[j] = b->films[j].mbuf[b->hcur[j]];
+    }
+    if (!b->ev_out) BCHK(b, hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    BCHK(b, hipEventRecord(b->ev_out, b->stream));
+    return LLG_OK;
+}
+
+// makes `consumer` wait for the fixed steps last enqueued on the batch
+llg_status llg_batch_then_(llg_batch* b, hipStream_t consumer) {
+    if (!b) return LLG_E_ARG;
+    if (b->ev_out) BCHK(b, hipStreamWaitEvent(consumer, b->ev_out, 0));
+    return LLG_OK;
 }

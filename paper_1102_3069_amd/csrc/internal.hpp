@@ -235,5 +235,6 @@ hipError_t tensor_at_offsets(const TensorGeom& tg, const int32_t* offs_dev, long
 }  // namespace llg
 
 // batch internals shared with the surrogate (batch.hip)
-llg_status llg_batch_fixed_from_(llg_batch* b, llg_method method, double dt, int64_t nsteps, const float* src,
-                                 size_t stride, int nload, hipStream_t producer, float** out);
+llg_status llg_batch_fixed_async_(llg_batch* b, llg_method method, double dt, int64_t nsteps, const float* src,
+                                  size_t stride, int nload, hipStream_t producer, float** out);
+llg_status llg_batch_then_(llg_batch* b, hipStream_t consumer);

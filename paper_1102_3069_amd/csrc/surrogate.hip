@@ -525,8 +525,8 @@ struct llg_sur {
     bool packed = false;
     float out_scale = 1.f;                     // dm = out_scale * network output
     // speculative verification
-    llg_batch* vb = nullptr;                   // window films advanced by the plain solver
-    llg_batch* eb = nullptr;                   // one film: the Euler predictor
+    llg_batch* vb[2] = {};                     // the plain segments: first and second half of a round
+    llg_batch* eb = nullptr;                   // one film: the coarse step of the proposals' base
     llg_film_desc vdesc = {};                  // the film the batch was built for
     int vwin = 0;
     float* props = nullptr;                    // proposals: window + 1 states
@@ -716,7 +716,8 @@ void llg_sur_destroy(llg_sur* s) {
         if (s->act[l]) (void)hipFree(s->act[l]);
     if (s->props) (void)hipFree(s->props);
     if (s->dmax) (void)hipFree(s->dmax);
-    if (s->vb) llg_batch_destroy(s->vb);
+    for (llg_batch* v : s->vb)
+        if (v) llg_batch_destroy(v);
     if (s->eb) llg_batch_destroy(s->eb);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -973,10 +974,15 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
     const size_t vec = sizeof(float) * 3 * (size_t)ncells;
     llg_sur_stats st = {};
     // the verification batch: `window` copies of the film
-    if (!s->vb || s->vwin != window || !same_film(s->vdesc, *film)) {
-        if (s->vb) llg_batch_destroy(s->vb);
+    // the verification batches (the first ceil(window / 2) and the other
+    // start states of a round) and the coarse-step batch: copies of the film
+    const int hmax = (window + 1) / 2;
+    if (!s->vb[0] || s->vwin != window || !same_film(s->vdesc, *film)) {
+        for (llg_batch*& v : s->vb) {
+            if (v) llg_batch_destroy(v);
+            v = nullptr;
+        }
         if (s->eb) llg_batch_destroy(s->eb);
-        s->vb = nullptr;
         s->eb = nullptr;
         if (s->props) (void)hipFree(s->props);
         if (s->dmax) (void)hipFree(s->dmax);
@@ -986,19 +992,17 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
         SCHK(s, hipMemcpy(h0.data(), m, vec, where == LLG_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
         std::vector<llg_film_desc> fd(window, *film);
         for (auto& f : fd) f.m0 = h0.data();
-        llg_status rc = llg_batch_create(s->device, fd.data(), window, &s->vb);
-        if (rc != LLG_OK) {
-            const std::string why = s->vb ? llg_batch_last_error(s->vb) : "batch creation failed";
-            if (s->vb) llg_batch_destroy(s->vb);
-            s->vb = nullptr;
-            return sfail(s, rc, "verification batch: %s", why.c_str());
-        }
-        rc = llg_batch_create(s->device, fd.data(), 1, &s->eb);
-        if (rc != LLG_OK) {
-            const std::string why = s->eb ? llg_batch_last_error(s->eb) : "batch creation failed";
-            if (s->eb) llg_batch_destroy(s->eb);
-            s->eb = nullptr;
-            return sfail(s, rc, "predictor batch: %s", why.c_str());
+        const int count[3] = {hmax, window - hmax, 1};
+        llg_batch** dst[3] = {&s->vb[0], &s->vb[1], &s->eb};
+        for (int i = 0; i < 3; ++i) {
+            if (count[i] == 0) continue;
+            const llg_status rc = llg_batch_create(s->device, fd.data(), count[i], dst[i]);
+            if (rc != LLG_OK) {
+                const std::string why = *dst[i] ? llg_batch_last_error(*dst[i]) : "batch creation failed";
+                if (*dst[i]) llg_batch_destroy(*dst[i]);
+                *dst[i] = nullptr;
+                return sfail(s, rc, "%s batch: %s", i < 2 ? "verification" : "predictor", why.c_str());
+            }
         }
         s->vdesc = *film;
         s->vdesc.m0 = nullptr;
@@ -1022,66 +1026,71 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
     }
     std::vector<float*> ptr(window);
     std::vector<unsigned> hd(2 * window);
+    const llg_method coarse = predictor == LLG_SUR_BASE_EULER ? LLG_EULER : LLG_RK4;
     int64_t done = 0;
     while (done < n_segments) {
         const int w = (int)std::min<int64_t>(window, n_segments - done);
+        const int h = (w + 1) / 2;   // start states of the first half
         float* P = s->props;
+        const size_t stride = 3 * (size_t)ncells;
+        // plain segments from start states [first, first + count), on the
+        // half's batch stream, overlapping the proposals still to come
+        auto verify = [&](int half, int first, int count) -> llg_status {
+            const llg_status rc = llg_batch_fixed_async_(s->vb[half], LLG_RK4, dt, seg_steps, P + first * stride,
+                                                         stride, count, s->stream, ptr.data() + first);
+            if (rc != LLG_OK) return sfail(s, rc, "verification batch: %s", llg_batch_last_error(s->vb[half]));
+            return LLG_OK;
+        };
         // proposals 1..w, each from the previous one: normalize(base + dm)
         // with base the previous state or its one coarse step (Euler or
         // RK4) over the whole segment by the plain solver
         for (int j = 1; j <= w; ++j) {
-            const float* prev = P + (size_t)(j - 1) * 3 * ncells;
+            llg_status rc = LLG_OK;
+            if (j == h && (rc = verify(0, 0, h)) != LLG_OK) return rc;
+            if (j == w && w > h && (rc = verify(1, h, w - h)) != LLG_OK) return rc;
+            const float* prev = P + (size_t)(j - 1) * stride;
             const float* base = prev;
             if (predictor != LLG_SUR_BASE_STATE) {
                 float* em = nullptr;
-                const llg_status rc = llg_batch_fixed_from_(
-                    s->eb, predictor == LLG_SUR_BASE_EULER ? LLG_EULER : LLG_RK4, dt * seg_steps, 1, prev, 0, 1,
-                    s->stream, &em);
+                rc = llg_batch_fixed_async_(s->eb, coarse, dt * seg_steps, 1, prev, 0, 1, s->stream, &em);
+                if (rc == LLG_OK) rc = llg_batch_then_(s->eb, s->stream);
                 if (rc != LLG_OK) return sfail(s, rc, "predictor batch: %s", llg_batch_last_error(s->eb));
                 base = em;
             }
-            llg_status rc = forward(s, prev, s->dB, 1, false);
+            rc = forward(s, prev, s->dB, 1, false);
             if (rc != LLG_OK) return rc;
             hipLaunchKernelGGL(propose_kernel, dim3((ncells + 255) / 256), dim3(256), 0, s->stream, base,
-                               s->z[NL - 1], P + (size_t)j * 3 * ncells, 1, s->H, s->W, s->out_scale);
+                               s->z[NL - 1], P + (size_t)j * stride, 1, s->H, s->W, s->out_scale);
             SCHK(s, hipGetLastError());
         }
-        // finiteness of the proposals (0 for finite, inf otherwise) and the
-        // number of start states that may go to the plain solver
+        for (int half = 0; half < (w > h ? 2 : 1); ++half) {
+            const llg_status rc = llg_batch_then_(s->vb[half], s->stream);
+            if (rc != LLG_OK) return sfail(s, rc, "verification batch: %s", llg_batch_last_error(s->vb[half]));
+        }
+        // d_j = distance of proposal j to the plain result from its
+        // predecessor (non-finite: infinite), and whether each plain result
+        // is finite (0) or not
         hipLaunchKernelGGL(zero_u32_kernel, dim3((2 * window + 255) / 256), dim3(256), 0, s->stream, s->dmax,
                            2 * window);
         SCHK(s, hipGetLastError());
         for (int j = 1; j <= w; ++j) {
-            const float* pj = P + (size_t)j * 3 * ncells;
-            llg_status rc = max_distance(s, pj, pj, ncells, s->dmax + window + j - 1);
+            llg_status rc = max_distance(s, P + (size_t)j * stride, ptr[j - 1], ncells, s->dmax + j - 1);
+            if (rc == LLG_OK) rc = max_distance(s, ptr[j - 1], ptr[j - 1], ncells, s->dmax + window + j - 1);
             if (rc != LLG_OK) return rc;
         }
-        SCHK(s, hipMemcpyAsync(hd.data() + window, s->dmax + window, sizeof(unsigned) * window,
-                               hipMemcpyDeviceToHost, s->stream));
+        SCHK(s, hipMemcpyAsync(hd.data(), s->dmax, sizeof(unsigned) * 2 * window, hipMemcpyDeviceToHost, s->stream));
         SCHK(s, hipStreamSynchronize(s->stream));
-        int nstart = w;   // films 0..nstart-1 start from proposals 0..nstart-1
-        for (int j = 1; j < w; ++j)
-            if (hd[window + j - 1] != 0u) { nstart = j; break; }
-        // plain segments from every start state, one batched launch per step
-        llg_status rc = llg_batch_fixed_from_(s->vb, LLG_RK4, dt, seg_steps, P, 3 * (size_t)ncells, nstart, s->stream,
-                                              ptr.data());
-        if (rc != LLG_OK) return sfail(s, rc, "verification batch: %s", llg_batch_last_error(s->vb));
-        // distance of every proposal to the plain result from its predecessor
-        for (int j = 1; j <= nstart; ++j) {
-            rc = max_distance(s, P + (size_t)j * 3 * ncells, ptr[j - 1], ncells, s->dmax + j - 1);
-            if (rc != LLG_OK) return rc;
-        }
-        SCHK(s, hipMemcpyAsync(hd.data(), s->dmax, sizeof(unsigned) * window, hipMemcpyDeviceToHost, s->stream));
-        SCHK(s, hipStreamSynchronize(s->stream));
-        int k = nstart;       // segments this round commits
-        int acc = nstart;     // proposals accepted
-        for (int j = 1; j <= nstart; ++j) {
+        int k = w;       // segments this round commits
+        int acc = w;     // proposals accepted
+        for (int j = 1; j <= w; ++j) {
             const float d = bits_to_float(hd[j - 1]);
             st.max_dm_seen = std::max(st.max_dm_seen, (double)d);
             if (!((double)d <= max_dm)) { k = j; acc = j - 1; break; }
             st.max_dm_accepted = std::max(st.max_dm_accepted, (double)d);
         }
-        st.proposals += nstart;
+        if (hd[window + k - 1] != 0u)
+            return sfail(s, LLG_E_DIVERGED, "plain segment %lld: non-finite field or torque", (long long)(done + k - 1));
+        st.proposals += w;
         st.accepted += acc;
         st.rounds += 1;
         st.segments += k;
