@@ -309,11 +309,30 @@ __device__ __forceinline__ void local_field_lds(const Grid& g, const Phys& p, co
     }
 }
 
+// the z neighbours of cell x of row r of a 3D grid (below: bit 0 of the
+// returned mask, above: bit 1; absent at an open z face), loaded from
+// global memory (component stride ncells) ahead of their use
+__device__ __forceinline__ unsigned z_neighbours(const Grid& g, const Phys& p, const float* __restrict__ m, int r,
+                                                 int x, float (&lo)[3], float (&up)[3]) {
+    if (p.cex[2] == 0.f || g.nz < 2) return 0u;
+    const long long cs = g.ncells;
+    const long long i = (long long)r * g.nx + x, sl = (long long)g.ny * g.nx;
+    const int z = r / g.ny;
+    long long il = -1, iu = -1;
+    if (z > 0) il = i - sl; else if (g.pbc[2]) il = i + (long long)(g.nz - 1) * sl;
+    if (z < g.nz - 1) iu = i + sl; else if (g.pbc[2]) iu = i - (long long)(g.nz - 1) * sl;
+    unsigned mask = 0u;
+    if (il >= 0) { lo[0] = m[il]; lo[1] = m[cs + il]; lo[2] = m[2 * cs + il]; mask |= 1u; }
+    if (iu >= 0) { up[0] = m[iu]; up[1] = m[cs + iu]; up[2] = m[2 * cs + iu]; mask |= 2u; }
+    return mask;
+}
+
 // exchange terms of a 3D grid that the staged rows of a block do not hold:
-// the periodic y wrap at the edges of a z plane and the z neighbours, read
-// from global memory (component stride ncells)
+// the periodic y wrap at the edges of a z plane (read from global memory)
+// and the z neighbours (from z_neighbours)
 __device__ __forceinline__ void exchange_wrap_z(const Grid& g, const Phys& p, const float* __restrict__ m, int r,
-                                                int x, int y, float mx, float my, float mz, float& hx, float& hy,
+                                                int x, int y, float mx, float my, float mz, const float (&lo)[3],
+                                                const float (&up)[3], unsigned zmask, float& hx, float& hy,
                                                 float& hz) {
     const long long cs = g.ncells;
     float sx = 0.f, sy = 0.f, sz = 0.f;
@@ -327,12 +346,9 @@ __device__ __forceinline__ void exchange_wrap_z(const Grid& g, const Phys& p, co
         if (y == 0) nb(r + g.ny - 1, p.cex[1]);
         if (y == g.ny - 1) nb(r - (g.ny - 1), p.cex[1]);
     }
-    if (p.cex[2] != 0.f && g.nz > 1) {
-        const int z = r / g.ny;
-        const float c = p.cex[2];
-        if (z > 0) nb(r - g.ny, c); else if (g.pbc[2]) nb(r + (g.nz - 1) * g.ny, c);
-        if (z < g.nz - 1) nb(r + g.ny, c); else if (g.pbc[2]) nb(r - (g.nz - 1) * g.ny, c);
-    }
+    const float c = p.cex[2];
+    if (zmask & 1u) { sx += c * (lo[0] - mx); sy += c * (lo[1] - my); sz += c * (lo[2] - mz); }
+    if (zmask & 2u) { sx += c * (up[0] - mx); sy += c * (up[1] - my); sz += c * (up[2] - mz); }
     hx += sx; hy += sy; hz += sz;
 }
 
@@ -441,6 +457,22 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     const float rnx = 1.0f / (float)nx;
     float px_[MAXIT], py_[MAXIT], pz_[MAXIT], ex_[MAXIT], ey_[MAXIT], ez_[MAXIT];
     float mnx[MAXIT], mny[MAXIT], mnz[MAXIT];   // the new stage state, held until the staged rows are free
+    // 3D: the z neighbours of this thread's cells, loaded while the
+    // transforms run
+    float zlo[MAXIT][3], zup[MAXIT][3];
+    unsigned zmask[MAXIT];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        zmask[it] = 0u;
+        if constexpr (NAT) {
+            const int e = tid + it * NT;
+            if (e < ncb) {
+                int ri, x;
+                split_cell(e, nx, rnx, ri, x);
+                zmask[it] = z_neighbours(g, p, mi, rb + ri, x, zlo[it], zup[it]);
+            }
+        }
+    }
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
         px_[it] = py_[it] = pz_[it] = ex_[it] = ey_[it] = ez_[it] = 0.f;
@@ -511,7 +543,8 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             const float* rmn = (ny > 1 && y > 0) ? rc - 3 * NXM : nullptr;
             const float* rpn = (ny > 1 && y < ny - 1) ? rc + 3 * NXM : nullptr;
             local_field_lds(g, p, rmn, rc, rpn, NXM, r, x, step, hx, hy, hz);
-            exchange_wrap_z(g, p, mi, r, x, y, rc[x], rc[NXM + x], rc[2 * NXM + x], hx, hy, hz);
+            exchange_wrap_z(g, p, mi, r, x, y, rc[x], rc[NXM + x], rc[2 * NXM + x], zlo[it], zup[it], zmask[it], hx,
+                            hy, hz);
         } else {
             local_field_lds(g, p, rm, rc, rp, NXM, r, x, step, hx, hy, hz);
         }
