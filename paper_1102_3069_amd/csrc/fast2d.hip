@@ -391,18 +391,39 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     // ---- global reads: twiddles, m rows rb-1 .. rb+2RP (y neighbours wrap
     // on a periodic y axis), this group's class of the spectrum
     for (int m = tid; m < PX; m += NT) tw[m] = twx[m];
-    for (int rq = 0; rq < R::NR; ++rq) {
+    // staged row rq holds grid row rb - 1 + rq; NAT (3D): the halo rows serve
+    // only as in-plane neighbours, the periodic y wrap and the z neighbours
+    // come from global memory
+    auto staged_row = [&](int rq, bool& ok) {
         int row = rb - 1 + rq;
-        bool ok = row >= 0 && row < g.nrows;
-        // NAT (3D): only the block's own rows are used, neighbours come from
-        // global memory
+        ok = row >= 0 && row < g.nrows;
         if (!NAT && g.pbc[1]) { row = row < 0 ? row + ny : (row >= ny ? row - ny : row); ok = true; }
-        const float* src = mi + row * nx;
-        float* dst = mrow + rq * 3 * NXM;
-        for (int t = tid; t < 3 * nx; t += NT) {
-            const int c = t >= nx ? (t >= 2 * nx ? 2 : 1) : 0;
-            const int x = t - c * nx;
-            dst[c * NXM + x] = ok ? src[c * cs + x] : 0.f;
+        return row;
+    };
+    if ((nx & 3) == 0 && (cs & 3) == 0) {
+        // 16-byte loads: every (row, component) run of nx floats starts
+        // 16-byte aligned
+        const int n4 = nx >> 2;
+        for (int t = tid; t < R::NR * 3 * n4; t += NT) {
+            const int rq = t / (3 * n4), rem = t - rq * 3 * n4;
+            const int c = rem / n4, x4 = rem - c * n4;
+            bool ok;
+            const int row = staged_row(rq, ok);
+            const float4 v = ok ? *reinterpret_cast<const float4*>(mi + (size_t)c * cs + (size_t)row * nx + 4 * x4)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+            *reinterpret_cast<float4*>(mrow + rq * 3 * NXM + c * NXM + 4 * x4) = v;
+        }
+    } else {
+        for (int rq = 0; rq < R::NR; ++rq) {
+            bool ok;
+            const int row = staged_row(rq, ok);
+            const float* src = mi + row * nx;
+            float* dst = mrow + rq * 3 * NXM;
+            for (int t = tid; t < 3 * nx; t += NT) {
+                const int c = t >= nx ? (t >= 2 * nx ? 2 : 1) : 0;
+                const int x = t - c * nx;
+                dst[c * NXM + x] = ok ? src[c * cs + x] : 0.f;
+            }
         }
     }
     float2 z[E2];
