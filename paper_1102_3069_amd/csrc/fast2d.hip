@@ -242,23 +242,73 @@ __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __rest
     const int nx = g.nx;
     const float rnx = 1.0f / (float)nx;
     const int nrow = min(2 * R::RP, g.nrows - rb);
-    for (int e = tid; e < nrow * nx; e += NT) {
-        int ri, x;
-        split_cell(e, nx, rnx, ri, x);
-        const int qq = (rb + ri) * nx + x;
-        float ax, ay, az;
+    // one cell: the stage state (m0 + c1 k1, normalised) or m itself
+    auto cell = [&](int qq, float& ax, float& ay, float& az) {
         if (fa.combine) {
             ax = m0[qq] + c1 * k1[qq];
             ay = m0[cs + qq] + c1 * k1[cs + qq];
             az = m0[2 * cs + qq] + c1 * k1[2 * cs + qq];
             const float inv = rsqrtf(ax * ax + ay * ay + az * az);
             ax *= inv; ay *= inv; az *= inv;
-            mo[qq] = ax; mo[cs + qq] = ay; mo[2 * cs + qq] = az;
         } else {
             ax = mi[qq]; ay = mi[cs + qq]; az = mi[2 * cs + qq];
         }
-        float* row = nm + ri * 3 * NXM;
-        row[x] = ax; row[NXM + x] = ay; row[2 * NXM + x] = az;
+    };
+    if ((nx & 3) == 0 && (cs & 3) == 0) {
+        // four consecutive cells per thread, 16-byte loads and stores (rows
+        // and components start 16-byte aligned); the same arithmetic per
+        // cell as `cell`
+        const int n4 = nx >> 2;
+        auto ld4 = [](const float* p, float (&o)[4]) {
+            const float4 w = *reinterpret_cast<const float4*>(p);
+            o[0] = w.x; o[1] = w.y; o[2] = w.z; o[3] = w.w;
+        };
+        for (int t = tid; t < nrow * n4; t += NT) {
+            const int ri = t / n4, x = 4 * (t - ri * n4);
+            const int qq = (rb + ri) * nx + x;
+            float v[3][4];
+            if (fa.combine) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float a[4], k[4];
+                    ld4(m0 + c * cs + qq, a);
+                    ld4(k1 + c * cs + qq, k);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[c][i] = a[i] + c1 * k[i];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float inv = rsqrtf(v[0][i] * v[0][i] + v[1][i] * v[1][i] + v[2][i] * v[2][i]);
+                    v[0][i] *= inv; v[1][i] *= inv; v[2][i] *= inv;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float a[4];
+                    ld4(mi + c * cs + qq, a);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[c][i] = a[i];
+                }
+            }
+            float* row = nm + ri * 3 * NXM;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float4 w = make_float4(v[c][0], v[c][1], v[c][2], v[c][3]);
+                if (fa.combine) *reinterpret_cast<float4*>(mo + c * cs + qq) = w;
+                *reinterpret_cast<float4*>(row + c * NXM + x) = w;
+            }
+        }
+    } else {
+        for (int e = tid; e < nrow * nx; e += NT) {
+            int ri, x;
+            split_cell(e, nx, rnx, ri, x);
+            const int qq = (rb + ri) * nx + x;
+            float ax, ay, az;
+            cell(qq, ax, ay, az);
+            if (fa.combine) { mo[qq] = ax; mo[cs + qq] = ay; mo[2 * cs + qq] = az; }
+            float* row = nm + ri * 3 * NXM;
+            row[x] = ax; row[NXM + x] = ay; row[2 * NXM + x] = az;
+        }
     }
     __syncthreads();
     R::template forward<NXM, NAT>(g, S, scr, tw, nm, kind, q, pair, lg, gbase, rb);
