@@ -213,6 +213,27 @@ def test_speculative_threshold_zero_is_plain(lib):
     assert np.array_equal(m, s.get_m())
 
 
+@pytest.mark.parametrize("window", [1, 2, 5])
+def test_speculative_zero_threshold_windows(lib, window):
+    """Threshold 0 with one verification batch (window 1), two batches of
+    one film (2) and of three and two films (5), then a second call with
+    another step on the same batches: each call is bit for bit the plain
+    run of the same number of steps."""
+    n = 32
+    prob, m0, run = held_out(n, 79)
+    sur = lib.Surrogate(n, n, max_batch=1)
+    sur.set_params(osg.init_params(2))
+    m = m0
+    for dt, nseg in ((run["dt"], 3), (0.5 * run["dt"], 4)):
+        s = lib.Solver(0)
+        s.set_problem(prob)
+        s.set_m(m)
+        s.step("rk4", dt, 4 * nseg)
+        m, st = sur.advance(prob, m, n_segments=nseg, window=window, seg_steps=4, dt=dt, max_dm=0.0)
+        assert st["segments"] == nseg and st["rounds"] == nseg and st["accepted"] == 0
+        assert np.array_equal(m, s.get_m())
+
+
 def test_speculative_accept_all(lib):
     """With a threshold no proposal can exceed, each round jumps `window`
     segments: the committed state is the plain segment from the last
