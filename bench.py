@@ -115,31 +115,13 @@ def measured_traffic(kind, prob, path=None, key=None):
     return None
 
 
-def tune_batch_variants(llg, films, args):
-    """A batch takes its compiled variants from the process-wide table that
-    llg_autotune fills: tune once per distinct film size, smallest first, so
-    that of the sizes sharing an FFT length the largest (the one that costs
-    most) sets the entry; sizes whose single-film solver has no compiled
-    lengths (the batch pads them) are skipped.  Returns {"nx x ny": (row,
-    column variant)}."""
-    tuned = {}
+def tune_batch(b, args):
+    """The batch's own autotuner (llg_batch_autotune): both compiled variants
+    of every length its films use, timed on evaluations of all films; returns
+    {"row 512": chosen variant, ...}."""
     if args.no_autotune:
-        return tuned
-    for prob, m0 in sorted(films, key=lambda f: int(f[0]["n"][0]) * int(f[0]["n"][1])):
-        key = f"{prob['n'][0]}x{prob['n'][1]}"
-        if key in tuned:
-            continue
-        s = llg.Solver(0)
-        s.set_problem(prob)
-        s.set_m(m0)
-        try:
-            tuned[key] = list(s.autotune(20)[1])
-        except llg.LLGError as e:
-            if "UNSUPPORTED" not in str(e):
-                raise
-            tuned[key] = None
-        del s
-    return {k: v for k, v in tuned.items() if v is not None}
+        return {}
+    return {f"{e['kind']} {e['length']}": e["variant"] for e in b.autotune(30)}
 
 
 def bench_batch(args):
@@ -152,8 +134,8 @@ def bench_batch(args):
     llg.load()
     films, run = workloads.film_batch()
     cells = np.array([int(np.prod(p["n"])) for p, _ in films])
-    tuned = tune_batch_variants(llg, films, args)
     b = llg.Batch(films)
+    tuned = tune_batch(b, args)
     st0 = b.run(run["t_end"], run["tol"], run["dt0"], max_attempts=max(1, args.warmup))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -286,10 +268,10 @@ def bench_sp2(args):
     llg.load()
     films, run = workloads.sp2_films()
     cells = np.array([int(np.prod(p["n"])) for p, _ in films])
-    t_tune = time.perf_counter()
-    tuned = tune_batch_variants(llg, films, args)
-    t_tune = time.perf_counter() - t_tune
     b = llg.Batch(films)
+    t_tune = time.perf_counter()
+    tuned = tune_batch(b, args)
+    t_tune = time.perf_counter() - t_tune
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     st0 = b.run(run["t_end"], run["tol"], run["dt0"], max_attempts=max(1, args.warmup))
@@ -315,7 +297,7 @@ def bench_sp2(args):
                                   "adaptive Dormand-Prince per film, grouped launches",
                       "cells": int(cells.sum()), "evals_max": int(evals.max()),
                       "sweep_s": t1 - t_start, "films_done": int(sum(s["done"] for s in st1)),
-                      "remanence_mx_my": rem, "tuning_s": t_tune, "variants_tuned": len(tuned),
+                      "remanence_mx_my": rem, "tuning_s": t_tune, "variants": tuned,
                       "paper_context": "GTX580: 200 separate runs in 3 min 21 s (Sec. 4.1)"}}
     print(json.dumps(out), flush=True)
 

@@ -333,6 +333,26 @@ llg_status  llg_batch_set_m(llg_batch *b, int film, const float *m, llg_mem wher
 llg_status  llg_batch_get_m(llg_batch *b, int film, float *m, llg_mem where);
 llg_status  llg_batch_get_attempts(llg_batch *b, int film, llg_attempt *out, int64_t cap, int64_t *n);
 
+/* One tuned length of llg_batch_autotune. */
+typedef struct {
+    int kind;                 /* 0: row (x) length Px, 1: column half length L = Py/2 */
+    int length;
+    int variant;              /* chosen compiled variant (0 or 1)                     */
+    double ms[2];             /* ms per H_eff evaluation of every film with variant   */
+                              /* 0 and 1 for this length (-1: not usable)             */
+} llg_tune_entry;
+/* The batch's own autotuner: for every padded row length and every column
+ * length its films use, largest first, times `iters` H_eff evaluations of
+ * all films (forward row pass, column pass, inverse row pass, no state
+ * change) with each compiled variant of that length, the other lengths held,
+ * and keeps the faster in the process-wide variant table (the one
+ * llg_autotune fills; solvers and batches made afterwards use it).  The
+ * batch's launches are rebuilt; film states, times and controllers are left
+ * as they were; results of different variants differ by FP32 rounding only.
+ * out (host, cap entries, may be NULL with cap = 0) receives one entry per
+ * length, *n_out their number (may be NULL). */
+llg_status  llg_batch_autotune(llg_batch *b, int iters, llg_tune_entry *out, int cap, int *n_out);
+
 /* ---- learned surrogate ------------------------------------------------------
  * Not part of the paper's method: a small convolutional network that
  * proposes the state of a film `seg_steps` fixed RK4 steps (Sec. 2.2) ahead,

@@ -67,6 +67,11 @@ class SurStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("length", ctypes.c_int), ("variant", ctypes.c_int),
+                ("ms", ctypes.c_double * 2)]
+
+
 class FilmDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
@@ -123,6 +128,7 @@ _SIGNATURES = {
     "llg_batch_run": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                        ctypes.POINTER(Stats)], ctypes.c_int),
     "llg_batch_step": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_int64], ctypes.c_int),
+    "llg_batch_autotune": ([_P, ctypes.c_int, _P, ctypes.c_int, _P], ctypes.c_int),
     "llg_batch_set_m": ([_P, ctypes.c_int, _P, ctypes.c_int], ctypes.c_int),
     "llg_batch_get_m": ([_P, ctypes.c_int, _P, ctypes.c_int], ctypes.c_int),
     "llg_batch_get_attempts": ([_P, ctypes.c_int, ctypes.POINTER(Attempt), ctypes.c_int64,
@@ -435,6 +441,17 @@ class Batch:
 
     def step(self, method, dt, nsteps=1):
         self._chk(self._lib.llg_batch_step(self._h, METHODS[method], float(dt), int(nsteps)))
+
+    def autotune(self, iters=10):
+        """Tunes the compiled variant of every length the films use (the
+        process-wide table); returns [{"kind": "row"|"col", "length",
+        "variant", "ms": (variant 0, variant 1)}]."""
+        cap = 64
+        ent = (TuneEntry * cap)()
+        n = ctypes.c_int(0)
+        self._chk(self._lib.llg_batch_autotune(self._h, int(iters), ctypes.cast(ent, _P), cap, ctypes.byref(n)))
+        return [{"kind": ("row", "col")[e.kind], "length": e.length, "variant": e.variant,
+                 "ms": (e.ms[0], e.ms[1])} for e in ent[:min(n.value, cap)]]
 
     def set_m(self, film, m):
         if _is_torch(m) and m.is_cuda:

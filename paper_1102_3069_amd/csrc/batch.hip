@@ -20,6 +20,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -731,6 +732,109 @@ llg_status llg_batch_step(llg_batch* b, llg_method method, double dt, int64_t ns
     b->err.clear();
     BCHK(b, hipSetDevice(b->device));
     return fixed_core(b, method, dt, nsteps, nullptr, 0, 0, nullptr, nullptr);
+}
+
+llg_status llg_batch_autotune(llg_batch* b, int iters, llg_tune_entry* out, int cap, int* n_out) {
+    if (!b || iters < 1 || cap < 0 || (cap > 0 && !out)) return LLG_E_ARG;
+    b->err.clear();
+    BCHK(b, hipSetDevice(b->device));
+    const int nf = (int)b->films.size();
+    llg_status rc = restore_classes(b);
+    if (rc != LLG_OK) return rc;
+    std::vector<DevState> h0;
+    if ((rc = read_states(b, h0)) != LLG_OK) return rc;
+    {
+        // finished films skip their launches: time every film
+        std::vector<DevState> ht = h0;
+        for (DevState& s : ht) s.done = 0;
+        if ((rc = write_states(b, ht)) != LLG_OK) return rc;
+    }
+    // the lengths in use, largest first
+    std::vector<int> lens[2];
+    for (const BatchFilm& f : b->films) {
+        const int l[2] = {f.g.Px, f.g.Py / 2};
+        for (int k = 0; k < 2; ++k)
+            if (std::find(lens[k].begin(), lens[k].end(), l[k]) == lens[k].end()) lens[k].push_back(l[k]);
+    }
+    for (auto& v : lens) std::sort(v.begin(), v.end(), std::greater<int>());
+    // every film takes the table's variants; launches rebuilt
+    auto apply = [&]() -> llg_status {
+        for (BatchFilm& f : b->films) {
+            f.rvar = fast2d_row_variant(f.g.Px);
+            f.cvar = fast2d_col_variant(f.g.Py / 2);
+            f.row_blocks = (f.g.nrows + fast2d_row_rows_per_block(f.g.Px, f.rvar) - 1) /
+                           fast2d_row_rows_per_block(f.g.Px, f.rvar);
+            f.col_blocks = (f.g.Px / 2) / fast2d_col_width(f.g.Py / 2, f.cvar);
+        }
+        return build_classes(b, std::vector<char>(nf, 1));
+    };
+    // a variant serves a length if every film of that length can use it
+    auto usable = [&](int kind, int len, int var) {
+        for (const BatchFilm& f : b->films) {
+            if (kind == 0 && f.g.Px == len && !fast2d_row_ok(len, var)) return false;
+            if (kind == 1 && f.g.Py / 2 == len &&
+                (!fast2d_col_ok(len, 1, var) || (f.g.Px / 2) % fast2d_col_width(len, var) != 0))
+                return false;
+        }
+        return true;
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BCHK(b, hipEventCreate(&e0));
+    BCHK(b, hipEventCreate(&e1));
+    struct Events {
+        hipEvent_t a, b;
+        ~Events() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } evs{e0, e1};
+    auto time_evals = [&](double& ms) -> llg_status {
+        for (int it = 0; it <= iters; ++it) {   // the first evaluation warms up
+            if (it == 1) BCHK(b, hipEventRecord(e0, b->stream));
+            PASS(b, PASS_ROW_FWD, b->d_fwd_plain);
+            PASS(b, PASS_COL, nullptr);
+            PASS(b, PASS_ROW_INV, b->d_konly);
+        }
+        BCHK(b, hipEventRecord(e1, b->stream));
+        BCHK(b, hipEventSynchronize(e1));
+        float t = 0.f;
+        BCHK(b, hipEventElapsedTime(&t, e0, e1));
+        ms = t / iters;
+        return LLG_OK;
+    };
+    std::vector<llg_tune_entry> res;
+    auto tune = [&]() -> llg_status {
+        for (int kind = 0; kind < 2; ++kind) {
+            for (int len : lens[kind]) {
+                llg_tune_entry t = {};
+                t.kind = kind;
+                t.length = len;
+                t.variant = kind == 0 ? fast2d_row_variant(len) : fast2d_col_variant(len);
+                for (int v = 0; v < 2; ++v) {
+                    t.ms[v] = -1.0;
+                    if (!usable(kind, len, v)) continue;
+                    if (kind == 0) (void)fast2d_set_row_variant(len, v, false);
+                    else (void)fast2d_set_col_variant(len, v);
+                    if ((rc = apply()) != LLG_OK || (rc = time_evals(t.ms[v])) != LLG_OK) return rc;
+                }
+                if (t.ms[0] >= 0 || t.ms[1] >= 0)
+                    t.variant = (t.ms[1] >= 0 && (t.ms[0] < 0 || t.ms[1] < t.ms[0])) ? 1 : 0;
+                if (kind == 0) (void)fast2d_set_row_variant(len, t.variant, false);
+                else (void)fast2d_set_col_variant(len, t.variant);
+                res.push_back(t);
+            }
+        }
+        return apply();
+    };
+    rc = tune();
+    // the evaluations wrote only scratch (spectra, k1 buffers, the error
+    // word): put every film's state back, also after a failure, and
+    // recompute k1 and the spectrum before the next step
+    const llg_status rw = write_states(b, h0);
+    b->k1_valid = false;
+    b->spec_valid = false;
+    if (rc != LLG_OK) return rc;
+    if (rw != LLG_OK) return rw;
+    for (int i = 0; i < (int)res.size() && i < cap; ++i) out[i] = res[i];
+    if (n_out) *n_out = (int)res.size();
+    return LLG_OK;
 }
 
 llg_status llg_batch_set_m(llg_batch* b, int film, const float* m, llg_mem where) {

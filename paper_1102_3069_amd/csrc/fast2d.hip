@@ -959,6 +959,16 @@ int fast2d_tile_shift() {
     return 2;
 }
 int fast2d_col_variant(int L) { return g_col_var[slot(L)].load(); }
+bool fast2d_set_row_variant(int Px, int var, bool xper) {
+    if (!fast2d_row_ok(Px, var, xper)) return false;
+    g_row_var[slot(Px)].store(var);
+    return true;
+}
+bool fast2d_set_col_variant(int L, int var) {
+    if (!fast2d_col_ok(L, 1, var)) return false;
+    g_col_var[slot(L)].store(var);
+    return true;
+}
 bool fast2d_set_variants(int Px, int rv, int L, int cv, bool xper) {
     if (!fast2d_row_ok(Px, rv, xper) || !fast2d_col_ok(L, 1, cv)) return false;
     g_row_var[slot(Px)].store(rv);

@@ -180,6 +180,8 @@ int fast2d_row_variant(int Px);
 int fast2d_tile_shift();
 int fast2d_col_variant(int L);
 bool fast2d_set_variants(int Px, int row_var, int L, int col_var, bool xper = false);
+bool fast2d_set_row_variant(int Px, int var, bool xper);   // one table entry (false: no such variant)
+bool fast2d_set_col_variant(int L, int var);
 hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, const FwdArgs& fa,
                                DevState* st, hipStream_t s);
 hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, float2* S,

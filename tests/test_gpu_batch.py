@@ -133,3 +133,45 @@ def test_full_sweep_creates_and_steps(lib):
     st = b.run(run["t_end"], run["tol"], run["dt0"], max_attempts=4)
     assert all(s["health"] == 0 for s in st)
     assert all(s["evals"] == 1 + 6 * 4 for s in st)
+
+
+
+def test_batch_autotune(lib):
+    """The batch's own autotuner times both compiled variants of every length
+    its films use, keeps the faster in the shared table and leaves every
+    film's state as it was.  Batches and solvers built afterwards read the
+    tuned table: a film of a new batch still equals its single-film run bit
+    for bit, and stays within FP32 rounding of the untuned result."""
+    films = sweep((32, 64, 96), 21)
+    b = lib.Batch(films)
+    ref = b.run(1e-12, 1e-5, 1e-14)
+    untuned = [b.get_m(i) for i in range(len(films))]
+    try:
+        ent = b.autotune(3)
+        print(ent, flush=True)
+        assert sorted((e["kind"], e["length"]) for e in ent) == \
+            sorted([("row", 64), ("row", 128), ("row", 192), ("col", 32), ("col", 64), ("col", 96)])
+        for e in ent:
+            usable = [v for v in (0, 1) if e["ms"][v] >= 0]
+            assert usable and all(e["ms"][v] > 0 for v in usable)
+            assert e["variant"] == min(usable, key=lambda v: e["ms"][v])
+        for i in range(len(films)):
+            assert np.array_equal(b.get_m(i), untuned[i])
+        assert [s["steps"] for s in b.run(1e-12, 1e-5, 0.0)] == [s["steps"] for s in ref]   # already there
+        t = lib.Batch(films)
+        st = t.run(1e-12, 1e-5, 1e-14)
+        for i, (prob, m0) in enumerate(films):
+            s = lib.Solver(0)
+            s.set_problem(prob)
+            s.set_m(m0)
+            s.run(1e-12, 1e-5, 1e-14)
+            assert np.array_equal(t.get_m(i), s.get_m())
+            assert st[i]["done"] == 1
+            assert maxrel(t.get_m(i), untuned[i]) <= 1e-4
+    finally:
+        for side in (32, 64, 96):
+            prob, m0 = sweep((side,), 0)[0]
+            s = lib.Solver(0)
+            s.set_problem(prob)
+            s.set_m(m0)
+            s.set_variants(0, 0)
