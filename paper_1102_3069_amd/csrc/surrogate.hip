@@ -311,10 +311,13 @@ __global__ void wgrad_reduce1_kernel(const float* part_w, const float* part_b, i
     const int per = (nblk + gridDim.y - 1) / gridDim.y;
     const int b0 = blockIdx.y * per, b1 = min(nblk, b0 + per);
     float s = 0.f;
-    if (i < NWG)
+    if (i < NWG) {
+#pragma unroll 8
         for (int b = b0; b < b1; ++b) s += part_w[(size_t)b * NWG + i];
-    else
+    } else {
+#pragma unroll 8
         for (int b = b0; b < b1; ++b) s += part_b[(size_t)b * CH + i - NWG];
+    }
     part2[(size_t)blockIdx.y * (NWG + CH) + i] = s;
 }
 
@@ -323,6 +326,7 @@ __global__ void wgrad_reduce2_kernel(const float* part2, int nseg, float* gw, fl
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NWG + CH) return;
     float s = 0.f;
+#pragma unroll 8
     for (int k = 0; k < nseg; ++k) s += part2[(size_t)k * (NWG + CH) + i];
     if (i < NWG)
         gw[i] = s;
