@@ -5,7 +5,10 @@
 // (kx fastest, strides in ColArgs).  A block owns a tile of TW consecutive
 // kx at one outer index, so its global reads and writes are rows of TW
 // contiguous complex values; the tile is transposed through LDS so that
-// every transform reads its line contiguously.  An open axis (zero padded
+// every transform reads its line contiguously.  The pass with the kernel
+// product needs the three components of a tile in one block (NC = 3); the
+// plain forward and inverse passes take one component per block (NC = 1),
+// which leaves room in LDS for wider tiles and more blocks per CU.  An open axis (zero padded
 // to 2L) is split into its even and odd frequencies, X[2k] = FFT_L(x),
 // X[2k+1] = FFT_L(x W^n) (W = exp(-2 pi i / 2L)), stored in that order (k
 // of the even half, then of the odd half); one lane group per (component,
@@ -24,11 +27,13 @@ namespace llg {
 
 namespace {
 
-// H = 2 halves (open axis) or 1 (periodic); E elements per lane
-template <int L, int E, int TW, int H>
+// H = 2 halves (open axis) or 1 (periodic); E elements per lane; NC
+// components per block (3, or 1 with the component from the block index)
+template <int L, int E, int TW, int H, int NC>
 struct Tile3 {
+    static_assert(NC == 1 || NC == 3, "one or three components per block");
     static constexpr int P = L / E;             // lanes per transform
-    static constexpr int NG = 3 * TW * H;       // lane groups: component, column, half
+    static constexpr int NG = NC * TW * H;      // lane groups: component, column, half
     static constexpr int NT = NG * P;           // threads per block
     static_assert(64 % P == 0 && NT <= 1024 && NT % 64 == 0, "groups fill whole wavefronts");
     // one LDS line per group, long enough to be that group's FFT scratch;
@@ -58,29 +63,33 @@ __device__ __forceinline__ void kernel6(const ColArgs& a, int kx, int ka, int ko
     }
 }
 
-template <int L, int E, int TW, int H, int MODE>
-__global__ __launch_bounds__((Tile3<L, E, TW, H>::NT)) void col3_tiled(ColArgs a, DevState* __restrict__ st) {
-    using T = Tile3<L, E, TW, H>;
+template <int L, int E, int TW, int H, int NC, int MODE>
+__global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColArgs a, DevState* __restrict__ st) {
+    using T = Tile3<L, E, TW, H, NC>;
     using F = typename T::F;
     constexpr int P = T::P, NT = T::NT;
+    static_assert(MODE != COL_FULL || NC == 3, "the kernel product needs every component");
     extern __shared__ float2 lds[];
     float2* tw = lds;
     float2* X = lds + T::O_X;
     if (st->done) return;
     const int tid = threadIdx.x;
-    const int lb = xcd_remap_blocks(blockIdx.x, gridDim.x);
+    int lb = xcd_remap_blocks(blockIdx.x, gridDim.x);
+    const int per_c = a.nouter * a.ntiles;      // blocks of one component (NC = 1)
+    const int c0 = NC == 3 ? 0 : lb / per_c;    // first component of the block
+    lb -= c0 * per_c;
     const int o = lb / a.ntiles;
     const int tile = lb - o * a.ntiles;
     const int kx0 = tile * TW;
     const int Wt = min(TW, a.nkx - kx0);
-    const float2* in = a.in + o * a.os_in + kx0;
-    float2* out = a.out + o * a.os_out + kx0;
+    const float2* in = a.in + c0 * a.cs_in + o * a.os_in + kx0;
+    float2* out = a.out + c0 * a.cs_out + o * a.os_out + kx0;
 
     // ---- the tile into the lines: n_in rows (zero beyond) into the h = 0
     // lines, or the H L stored frequencies into their half lines
     for (int m = tid; m < H * L; m += NT) tw[m] = a.tw[m];
     if (MODE != COL_INV) {
-        for (int e = tid; e < 3 * L * TW; e += NT) {
+        for (int e = tid; e < NC * L * TW; e += NT) {
             const int w = e % TW, t = e / TW;
             const int n = t % L, c = t / L;
             float2 v = make_float2(0.f, 0.f);
@@ -88,7 +97,7 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H>::NT)) void col3_tiled(ColArgs a
             X[T::line(c, w, 0) + n] = v;
         }
     } else {
-        for (int e = tid; e < 3 * H * L * TW; e += NT) {
+        for (int e = tid; e < NC * H * L * TW; e += NT) {
             const int w = e % TW, t = e / TW;
             const int k = t % (H * L), c = t / (H * L);
             float2 v = make_float2(0.f, 0.f);
@@ -116,36 +125,40 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H>::NT)) void col3_tiled(ColArgs a
 #pragma unroll
         for (int i = 0; i < E; ++i) ln[lg + P * i] = x[i];
         __syncthreads();
-        if (MODE == COL_FWD) {
-            for (int e = tid; e < 3 * H * L * TW; e += NT) {
+        if constexpr (MODE == COL_FWD) {
+            for (int e = tid; e < NC * H * L * TW; e += NT) {
                 const int ww = e % TW, t = e / TW;
                 const int k = t % (H * L), cc = t / (H * L);
                 if (ww < Wt) out[cc * a.cs_out + k * a.as_out + ww] = X[T::line(cc, ww, k / L) + k % L];
             }
             return;
+        } else {
+            // ---- H = K M at every (kx, k) of the tile
+            int ko = o;
+            if (a.o_split) {
+                const int hp = a.Po / 2;
+                ko = 2 * (o % hp) + o / hp;
+            }
+            for (int e = tid; e < TW * H * L; e += NT) {
+                const int pos = e % L, t = e / L;
+                const int hh = t % H, ww = t / H;
+                if (ww >= Wt) continue;
+                float Kv[6];
+                kernel6(a, kx0 + ww, H * pos + hh, ko, Kv);
+                float2* px = X + T::line(0, ww, hh) + pos;
+                float2* py = X + T::line(1, ww, hh) + pos;
+                float2* pz = X + T::line(2, ww, hh) + pos;
+                const float2 Mx = *px, My = *py, Mz = *pz;
+                // K = [xx, yy, zz, xy, xz, yz]
+                *px = make_float2(Kv[0] * Mx.x + Kv[3] * My.x + Kv[4] * Mz.x,
+                                  Kv[0] * Mx.y + Kv[3] * My.y + Kv[4] * Mz.y);
+                *py = make_float2(Kv[3] * Mx.x + Kv[1] * My.x + Kv[5] * Mz.x,
+                                  Kv[3] * Mx.y + Kv[1] * My.y + Kv[5] * Mz.y);
+                *pz = make_float2(Kv[4] * Mx.x + Kv[5] * My.x + Kv[2] * Mz.x,
+                                  Kv[4] * Mx.y + Kv[5] * My.y + Kv[2] * Mz.y);
+            }
+            __syncthreads();
         }
-        // ---- H = K M at every (kx, k) of the tile
-        int ko = o;
-        if (a.o_split) {
-            const int hp = a.Po / 2;
-            ko = 2 * (o % hp) + o / hp;
-        }
-        for (int e = tid; e < TW * H * L; e += NT) {
-            const int pos = e % L, t = e / L;
-            const int hh = t % H, ww = t / H;
-            if (ww >= Wt) continue;
-            float Kv[6];
-            kernel6(a, kx0 + ww, H * pos + hh, ko, Kv);
-            float2* px = X + T::line(0, ww, hh) + pos;
-            float2* py = X + T::line(1, ww, hh) + pos;
-            float2* pz = X + T::line(2, ww, hh) + pos;
-            const float2 Mx = *px, My = *py, Mz = *pz;
-            // K = [xx, yy, zz, xy, xz, yz]
-            *px = make_float2(Kv[0] * Mx.x + Kv[3] * My.x + Kv[4] * Mz.x, Kv[0] * Mx.y + Kv[3] * My.y + Kv[4] * Mz.y);
-            *py = make_float2(Kv[3] * Mx.x + Kv[1] * My.x + Kv[5] * Mz.x, Kv[3] * Mx.y + Kv[1] * My.y + Kv[5] * Mz.y);
-            *pz = make_float2(Kv[4] * Mx.x + Kv[5] * My.x + Kv[2] * Mz.x, Kv[4] * Mx.y + Kv[5] * My.y + Kv[2] * Mz.y);
-        }
-        __syncthreads();
     }
     // ---- inverse transforms; the odd half leaves W^-n times its result
 #pragma unroll
@@ -160,7 +173,7 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H>::NT)) void col3_tiled(ColArgs a
     }
     __syncthreads();
     // ---- rows n < n_out of the tile (even + odd half on an open axis)
-    for (int e = tid; e < 3 * L * TW; e += NT) {
+    for (int e = tid; e < NC * L * TW; e += NT) {
         const int ww = e % TW, t = e / TW;
         const int n = t % L, cc = t / L;
         if (ww >= Wt || n >= a.n_out) continue;
@@ -174,10 +187,16 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H>::NT)) void col3_tiled(ColArgs a
 }
 
 // compiled (length L of one transform, elements per lane, tile width,
-// halves): open axes of 2 L = 32 ... 512, periodic axes of L = 32 ... 256
-#define T3_VARIANTS(X)                                                                              \
+// halves): open axes of 2 L = 32 ... 512, periodic axes of L = 32 ... 256.
+// T3_FULL: the pass with the kernel product (three components per block);
+// T3_ONE: the plain forward and inverse passes (one component per block,
+// tiles twice as wide where that fits)
+#define T3_FULL(X)                                                                                  \
     X(16, 4, 16, 2) X(32, 4, 8, 2) X(64, 8, 8, 2) X(128, 8, 4, 2) X(256, 16, 4, 2) X(32, 4, 16, 1) \
     X(64, 8, 16, 1) X(128, 8, 8, 1) X(256, 16, 8, 1)
+#define T3_ONE(X)                                                                                     \
+    X(16, 4, 32, 2) X(32, 4, 16, 2) X(64, 8, 16, 2) X(128, 8, 8, 2) X(256, 16, 8, 2) X(32, 4, 32, 1) \
+    X(64, 8, 32, 1) X(128, 8, 16, 1) X(256, 16, 16, 1)
 
 hipError_t allow_lds3(const void* fn, int bytes) {
     if (bytes <= 64 * 1024) return hipSuccess;
@@ -187,49 +206,67 @@ hipError_t allow_lds3(const void* fn, int bytes) {
     return e;
 }
 
-template <int L, int E, int TW, int H>
+template <int L, int E, int TW, int H, int NC>
 hipError_t launch_t3(const ColArgs& a, int mode, DevState* st, hipStream_t s) {
-    using T = Tile3<L, E, TW, H>;
+    using T = Tile3<L, E, TW, H, NC>;
     if (a.ntiles != (a.nkx + TW - 1) / TW) return hipErrorInvalidValue;
-    const void* fn = mode == COL_FWD    ? reinterpret_cast<const void*>(&col3_tiled<L, E, TW, H, COL_FWD>)
-                     : mode == COL_FULL ? reinterpret_cast<const void*>(&col3_tiled<L, E, TW, H, COL_FULL>)
-                                        : reinterpret_cast<const void*>(&col3_tiled<L, E, TW, H, COL_INV>);
-    hipError_t e = allow_lds3(fn, T::bytes());
-    if (e != hipSuccess) return e;
-    const dim3 grid((unsigned)(a.nouter * a.ntiles)), block(T::NT);
-    if (mode == COL_FWD)
-        hipLaunchKernelGGL((col3_tiled<L, E, TW, H, COL_FWD>), grid, block, T::bytes(), s, a, st);
-    else if (mode == COL_FULL)
-        hipLaunchKernelGGL((col3_tiled<L, E, TW, H, COL_FULL>), grid, block, T::bytes(), s, a, st);
-    else
-        hipLaunchKernelGGL((col3_tiled<L, E, TW, H, COL_INV>), grid, block, T::bytes(), s, a, st);
+    if ((mode == COL_FULL) != (NC == 3)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(a.nouter * a.ntiles * (3 / NC))), block(T::NT);
+    if constexpr (NC == 3) {
+        const void* fn = reinterpret_cast<const void*>(&col3_tiled<L, E, TW, H, 3, COL_FULL>);
+        hipError_t e = allow_lds3(fn, T::bytes());
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((col3_tiled<L, E, TW, H, 3, COL_FULL>), grid, block, T::bytes(), s, a, st);
+    } else {
+        const void* fn = mode == COL_FWD ? reinterpret_cast<const void*>(&col3_tiled<L, E, TW, H, 1, COL_FWD>)
+                                         : reinterpret_cast<const void*>(&col3_tiled<L, E, TW, H, 1, COL_INV>);
+        hipError_t e = allow_lds3(fn, T::bytes());
+        if (e != hipSuccess) return e;
+        if (mode == COL_FWD)
+            hipLaunchKernelGGL((col3_tiled<L, E, TW, H, 1, COL_FWD>), grid, block, T::bytes(), s, a, st);
+        else
+            hipLaunchKernelGGL((col3_tiled<L, E, TW, H, 1, COL_INV>), grid, block, T::bytes(), s, a, st);
+    }
     return hipGetLastError();
 }
 
 }  // namespace
 
 // the transform length and halves of an axis of FFT length P: open axes
-// (split) use two transforms of P/2
-bool fast3d_col_ok(int P, int split) {
+// (split) use two transforms of P/2; full: the pass with the kernel product
+bool fast3d_col_ok(int P, int split, bool full) {
     const int H = split ? 2 : 1, L = P / H;
-#define CASE(LL, E, TW, HH) if (L == LL && H == HH) return Tile3<LL, E, TW, HH>::bytes() <= 160 * 1024;
-    T3_VARIANTS(CASE)
+    if (full) {
+#define CASE(LL, E, TW, HH) if (L == LL && H == HH) return Tile3<LL, E, TW, HH, 3>::bytes() <= 160 * 1024;
+        T3_FULL(CASE)
 #undef CASE
+    } else {
+#define CASE(LL, E, TW, HH) if (L == LL && H == HH) return Tile3<LL, E, TW, HH, 1>::bytes() <= 160 * 1024;
+        T3_ONE(CASE)
+#undef CASE
+    }
     return false;
 }
 
-int fast3d_col_width(int P, int split) {
+int fast3d_col_width(int P, int split, bool full) {
     const int H = split ? 2 : 1, L = P / H;
+    if (full) {
 #define CASE(LL, E, TW, HH) if (L == LL && H == HH) return TW;
-    T3_VARIANTS(CASE)
+        T3_FULL(CASE)
 #undef CASE
+    } else {
+#define CASE(LL, E, TW, HH) if (L == LL && H == HH) return TW;
+        T3_ONE(CASE)
+#undef CASE
+    }
     return 0;
 }
 
 // a.P the axis FFT length, a.split for an open axis; COL_FWD: n_in <= L
 // rows in, P frequencies out; COL_INV: P in, n_out <= L rows out;
 // COL_FULL: n_in = n_out <= L with the 6-component product; a.ntiles
-// tiles of fast3d_col_width columns per outer index
+// tiles of fast3d_col_width(P, split, mode == COL_FULL) columns per outer
+// index
 hipError_t launch_col3_tiled(const ColArgs& a, int mode, DevState* st, hipStream_t s) {
     const int H = a.split ? 2 : 1, L = a.P / H;
     if (a.P != H * L || a.nkx < 1 || a.nouter < 1 || a.n_in < 1 || a.n_out < 1) return hipErrorInvalidValue;
@@ -237,10 +274,17 @@ hipError_t launch_col3_tiled(const ColArgs& a, int mode, DevState* st, hipStream
     if (mode == COL_INV && !(a.n_in == a.P && a.n_out <= L)) return hipErrorInvalidValue;
     if (mode == COL_FULL && !(a.n_in == a.n_out && a.n_in <= L && a.ncomp == 6)) return hipErrorInvalidValue;
     if (mode != COL_FWD && mode != COL_FULL && mode != COL_INV) return hipErrorInvalidValue;
+    if (mode == COL_FULL) {
 #define CASE(LL, E, TW, HH) \
-    if (L == LL && H == HH) return launch_t3<LL, E, TW, HH>(a, mode, st, s);
-    T3_VARIANTS(CASE)
+        if (L == LL && H == HH) return launch_t3<LL, E, TW, HH, 3>(a, mode, st, s);
+        T3_FULL(CASE)
 #undef CASE
+    } else {
+#define CASE(LL, E, TW, HH) \
+        if (L == LL && H == HH) return launch_t3<LL, E, TW, HH, 1>(a, mode, st, s);
+        T3_ONE(CASE)
+#undef CASE
+    }
     return hipErrorInvalidValue;
 }
 

@@ -207,8 +207,8 @@ struct FilmCol {
 int fast2d_row_rows_per_block(int Px, int var);
 int fast2d_row_classes(int Px, int var = -1);
 // tiled column passes of the 3D path for axes of compiled length (fast3d.hip)
-bool fast3d_col_ok(int P, int split);
-int fast3d_col_width(int P, int split);
+bool fast3d_col_ok(int P, int split, bool full);     // full: the pass with the kernel product
+int fast3d_col_width(int P, int split, bool full);
 hipError_t launch_col3_tiled(const ColArgs& a, int mode, DevState* st, hipStream_t s);
 int fast2d_row_len_at_least(int n);
 int fast2d_col_len_at_least(int n);

@@ -269,7 +269,7 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
     yf.cs_out = (long long)g.nz * g.Py * nkxp; yf.os_out = (long long)g.Py * nkxp; yf.as_out = nkxp;
     yf.n_in = g.ny; yf.n_out = g.Py;
     if (s->fast3dy) {
-        yf.W = fast3d_col_width(g.Py, g.split_y);
+        yf.W = fast3d_col_width(g.Py, g.split_y, false);
         yf.ntiles = (g.nkx + yf.W - 1) / yf.W;
         HIPCHK(s, launch_col3_tiled(yf, COL_FWD, s->st, s->stream));
     } else {
@@ -292,7 +292,7 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
     const int sy_[6] = {1, 1, 1, -1, 1, -1};   // along y: xy, yz odd
     for (int c = 0; c < 6; ++c) { z.sign_a[c] = sz_[c]; z.sign_o[c] = sy_[c]; }
     if (s->fast3dz) {
-        z.W = fast3d_col_width(g.Pz, g.split_z);
+        z.W = fast3d_col_width(g.Pz, g.split_z, true);
         z.ntiles = (g.nkx + z.W - 1) / z.W;
         HIPCHK(s, launch_col3_tiled(z, COL_FULL, s->st, s->stream));
     } else {
@@ -305,7 +305,7 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
     yi.cs_out = (long long)g.nrows * nkxp; yi.os_out = (long long)g.ny * nkxp; yi.as_out = nkxp;
     yi.n_in = g.Py; yi.n_out = g.ny;
     if (s->fast3dy) {
-        yi.W = fast3d_col_width(g.Py, g.split_y);
+        yi.W = fast3d_col_width(g.Py, g.split_y, false);
         yi.ntiles = (g.nkx + yi.W - 1) / yi.W;
         HIPCHK(s, launch_col3_tiled(yi, COL_INV, s->st, s->stream));
     } else {
@@ -659,8 +659,8 @@ llg_status llg_set_geometry(llg_solver* s, int nx, int ny, int nz, int pbc_x, in
                 (P[0] / 2) % fast2d_col_width(Ly) == 0 && !(gen && gen[0] == '1');
     s->fastrows = s->fast2d || (nz > 1 && fast2d_row_ok(P[0], -1, nx == P[0]) && (nx == P[0] || 2 * nx <= P[0]) &&
                                 !(gen && gen[0] == '1'));
-    s->fast3dy = nz > 1 && fast3d_col_ok(P[1], split_y) && ny <= Ly && !(gen && gen[0] == '1');
-    s->fast3dz = nz > 1 && fast3d_col_ok(P[2], split_z) && nz <= Lz && !(gen && gen[0] == '1');
+    s->fast3dy = nz > 1 && fast3d_col_ok(P[1], split_y, false) && ny <= Ly && !(gen && gen[0] == '1');
+    s->fast3dz = nz > 1 && fast3d_col_ok(P[2], split_z, true) && nz <= Lz && !(gen && gen[0] == '1');
     const size_t vec = sizeof(float) * 3 * (size_t)g.ncells;
     HIPCHK(s, make_tw(P[0], &s->twx));
     HIPCHK(s, make_tw(P[1], &s->twy));
