@@ -83,7 +83,7 @@ def _kernel_name(kind, px, py):
 # kernel names of the 3D path (256 x 256 x 64 block: x periodic of 256,
 # y periodic of 256, z open of 2 x 64), per kernel kind
 def _kernel_name_3d(kind):
-    return {"row_fwd": "row_fwd_fast<256, ", "spectral": "col3_tiled<64, 8, 8, 2, 3, 1>",
+    return {"row_fwd": "row_fwd_fast<256, ", "spectral": "col3_tiled<64, 8, 4, 2, 3, 1>",
             "row_inv": "row_inv_fast<256, ", "y_fwd": "col3_tiled<256, 16, 16, 1, 1, 0>",
             "y_inv": "col3_tiled<256, 16, 16, 1, 1, 2>"}.get(kind)
 

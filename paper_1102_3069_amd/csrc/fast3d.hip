@@ -192,7 +192,7 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
 // T3_ONE: the plain forward and inverse passes (one component per block,
 // tiles twice as wide where that fits)
 #define T3_FULL(X)                                                                                  \
-    X(16, 4, 16, 2) X(32, 4, 8, 2) X(64, 8, 8, 2) X(128, 8, 4, 2) X(256, 16, 4, 2) X(32, 4, 16, 1) \
+    X(16, 4, 16, 2) X(32, 4, 8, 2) X(64, 8, 4, 2) X(128, 8, 4, 2) X(256, 16, 4, 2) X(32, 4, 16, 1) \
     X(64, 8, 16, 1) X(128, 8, 8, 1) X(256, 16, 8, 1)
 #define T3_ONE(X)                                                                                     \
     X(16, 4, 32, 2) X(32, 4, 16, 2) X(64, 8, 16, 2) X(128, 8, 8, 2) X(256, 16, 8, 2) X(32, 4, 32, 1) \
