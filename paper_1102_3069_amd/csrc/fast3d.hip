@@ -139,9 +139,11 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
                 const int hp = a.Po / 2;
                 ko = 2 * (o % hp) + o / hp;
             }
+            // consecutive threads take consecutive frequencies ka = H pos + hh,
+            // so the kernel spectrum (stored along ka) is read in whole lines
             for (int e = tid; e < TW * H * L; e += NT) {
-                const int pos = e % L, t = e / L;
-                const int hh = t % H, ww = t / H;
+                const int ka = e % (H * L), ww = e / (H * L);
+                const int pos = ka / H, hh = ka % H;
                 if (ww >= Wt) continue;
                 float Kv[6];
                 kernel6(a, kx0 + ww, H * pos + hh, ko, Kv);
