@@ -344,8 +344,9 @@ typedef struct {
 /* The batch's own autotuner: for every padded row length and every column
  * length its films use, largest first, times `iters` H_eff evaluations of
  * all films (forward row pass, column pass, inverse row pass, no state
- * change) with each compiled variant of that length, the other lengths held,
- * and keeps the faster in the process-wide variant table (the one
+ * change) with each compiled variant of that length, twice in alternating
+ * order, the other lengths held, and keeps the faster (by the better of its
+ * two timings) in the process-wide variant table (the one
  * llg_autotune fills; solvers and batches made afterwards use it).  The
  * batch's launches are rebuilt; film states, times and controllers are left
  * as they were; results of different variants differ by FP32 rounding only.

@@ -807,12 +807,18 @@ llg_status llg_batch_autotune(llg_batch* b, int iters, llg_tune_entry* out, int 
                 t.kind = kind;
                 t.length = len;
                 t.variant = kind == 0 ? fast2d_row_variant(len) : fast2d_col_variant(len);
-                for (int v = 0; v < 2; ++v) {
-                    t.ms[v] = -1.0;
-                    if (!usable(kind, len, v)) continue;
-                    if (kind == 0) (void)fast2d_set_row_variant(len, v, false);
-                    else (void)fast2d_set_col_variant(len, v);
-                    if ((rc = apply()) != LLG_OK || (rc = time_evals(t.ms[v])) != LLG_OK) return rc;
+                // two rounds in alternating order, the faster of each
+                // variant's two timings kept (drift and noise hit both)
+                t.ms[0] = t.ms[1] = -1.0;
+                for (int round = 0; round < 2; ++round) {
+                    for (int v = 0; v < 2; ++v) {
+                        if (!usable(kind, len, v)) continue;
+                        if (kind == 0) (void)fast2d_set_row_variant(len, v, false);
+                        else (void)fast2d_set_col_variant(len, v);
+                        double ms = 0.0;
+                        if ((rc = apply()) != LLG_OK || (rc = time_evals(ms)) != LLG_OK) return rc;
+                        if (t.ms[v] < 0 || ms < t.ms[v]) t.ms[v] = ms;
+                    }
                 }
                 if (t.ms[0] >= 0 || t.ms[1] >= 0)
                     t.variant = (t.ms[1] >= 0 && (t.ms[0] < 0 || t.ms[1] < t.ms[0])) ? 1 : 0;
