@@ -439,10 +439,10 @@ llg_status  llg_sur_conv_check(llg_sur *s, int layer, const float *x, const floa
  * segments of seg_steps RK4 steps of dt (s).  A round chains up to `window`
  * proposals m'_1..m'_w from the current state m'_0, each with the base
  * `predictor` (an LLG_SUR_BASE_* value, coarse steps with T = seg_steps dt;
- * LLG_E_ARG otherwise); two batched plain launches (the first
- * ceil(w/2) start states as soon as they exist, the rest after them, both
- * running beside the remaining proposals) advance m'_0..m'_{w-1} by a
- * segment each, giving p_1..p_w; d_j = max over cells |m'_j - p_j|
+ * LLG_E_ARG otherwise); batched plain launches of up to four start
+ * states each (each as soon as its start states exist, running beside the
+ * remaining proposals) advance m'_0..m'_{w-1} by a segment each, giving
+ * p_1..p_w; d_j = max over cells |m'_j - p_j|
  * (infinite for a non-finite proposal).  With j* the first j where
  * d_j > max_dm (or w + 1), the round commits p_{min(j*, w)} and advances
  * min(j*, w) segments; LLG_E_DIVERGED if that state is not finite.  With

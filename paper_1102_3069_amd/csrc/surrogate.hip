@@ -43,6 +43,7 @@ constexpr int CIN[NL] = {9, 32, 32, 32, 32, 32};
 constexpr int COUT[NL] = {32, 32, 32, 32, 32, 3};
 constexpr float B_SCALE = 0.05f;
 constexpr float LO_SCALE = 256.0f;   // the low part of m is scaled by 2^8 before its own BF16 rounding
+constexpr int kVerifyPart = 4;       // start states per verification batch
 
 // round-to-nearest-even FP32 -> BF16 bits (NaN kept quiet)
 __host__ __device__ inline u16 f2bf(float f) {
@@ -529,7 +530,7 @@ struct llg_sur {
     bool packed = false;
     float out_scale = 1.f;                     // dm = out_scale * network output
     // speculative verification
-    llg_batch* vb[2] = {};                     // the plain segments: first and second half of a round
+    std::vector<llg_batch*> vb;                // the plain segments of a round, in parts of kVerifyPart
     llg_batch* eb = nullptr;                   // one film: the coarse step of the proposals' base
     llg_film_desc vdesc = {};                  // the film the batch was built for
     int vwin = 0;
@@ -722,6 +723,7 @@ void llg_sur_destroy(llg_sur* s) {
     if (s->dmax) (void)hipFree(s->dmax);
     for (llg_batch* v : s->vb)
         if (v) llg_batch_destroy(v);
+    s->vb.clear();
     if (s->eb) llg_batch_destroy(s->eb);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -977,15 +979,13 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
     const int ncells = s->H * s->W;
     const size_t vec = sizeof(float) * 3 * (size_t)ncells;
     llg_sur_stats st = {};
-    // the verification batch: `window` copies of the film
-    // the verification batches (the first ceil(window / 2) and the other
-    // start states of a round) and the coarse-step batch: copies of the film
-    const int hmax = (window + 1) / 2;
-    if (!s->vb[0] || s->vwin != window || !same_film(s->vdesc, *film)) {
-        for (llg_batch*& v : s->vb) {
+    // the verification batches (start states kVerifyPart p ... of a round)
+    // and the coarse-step batch: copies of the film
+    const int nparts = (window + kVerifyPart - 1) / kVerifyPart;
+    if (s->vb.empty() || s->vwin != window || !same_film(s->vdesc, *film)) {
+        for (llg_batch* v : s->vb)
             if (v) llg_batch_destroy(v);
-            v = nullptr;
-        }
+        s->vb.assign(nparts, nullptr);
         if (s->eb) llg_batch_destroy(s->eb);
         s->eb = nullptr;
         if (s->props) (void)hipFree(s->props);
@@ -996,16 +996,18 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
         SCHK(s, hipMemcpy(h0.data(), m, vec, where == LLG_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
         std::vector<llg_film_desc> fd(window, *film);
         for (auto& f : fd) f.m0 = h0.data();
-        const int count[3] = {hmax, window - hmax, 1};
-        llg_batch** dst[3] = {&s->vb[0], &s->vb[1], &s->eb};
-        for (int i = 0; i < 3; ++i) {
-            if (count[i] == 0) continue;
-            const llg_status rc = llg_batch_create(s->device, fd.data(), count[i], dst[i]);
+        for (int i = 0; i <= nparts; ++i) {
+            const int count = i < nparts ? std::min(kVerifyPart, window - i * kVerifyPart) : 1;
+            llg_batch** dst = i < nparts ? &s->vb[i] : &s->eb;
+            const llg_status rc = llg_batch_create(s->device, fd.data(), count, dst);
             if (rc != LLG_OK) {
-                const std::string why = *dst[i] ? llg_batch_last_error(*dst[i]) : "batch creation failed";
-                if (*dst[i]) llg_batch_destroy(*dst[i]);
-                *dst[i] = nullptr;
-                return sfail(s, rc, "%s batch: %s", i < 2 ? "verification" : "predictor", why.c_str());
+                const std::string why = *dst ? llg_batch_last_error(*dst) : "batch creation failed";
+                if (*dst) llg_batch_destroy(*dst);
+                *dst = nullptr;
+                for (llg_batch* v : s->vb)   // the others are rebuilt by the next call
+                    if (v) llg_batch_destroy(v);
+                s->vb.clear();
+                return sfail(s, rc, "%s batch: %s", i < nparts ? "verification" : "predictor", why.c_str());
             }
         }
         s->vdesc = *film;
@@ -1034,24 +1036,27 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
     int64_t done = 0;
     while (done < n_segments) {
         const int w = (int)std::min<int64_t>(window, n_segments - done);
-        const int h = (w + 1) / 2;   // start states of the first half
+        const int parts = (w + kVerifyPart - 1) / kVerifyPart;   // parts this round
         float* P = s->props;
         const size_t stride = 3 * (size_t)ncells;
-        // plain segments from start states [first, first + count), on the
-        // half's batch stream, overlapping the proposals still to come
-        auto verify = [&](int half, int first, int count) -> llg_status {
-            const llg_status rc = llg_batch_fixed_async_(s->vb[half], LLG_RK4, dt, seg_steps, P + first * stride,
+        // plain segments from the start states of part p, on the part's
+        // batch stream, overlapping the proposals still to come
+        auto verify = [&](int p) -> llg_status {
+            const int first = p * kVerifyPart, count = std::min(kVerifyPart, w - first);
+            const llg_status rc = llg_batch_fixed_async_(s->vb[p], LLG_RK4, dt, seg_steps, P + first * stride,
                                                          stride, count, s->stream, ptr.data() + first);
-            if (rc != LLG_OK) return sfail(s, rc, "verification batch: %s", llg_batch_last_error(s->vb[half]));
+            if (rc != LLG_OK) return sfail(s, rc, "verification batch: %s", llg_batch_last_error(s->vb[p]));
             return LLG_OK;
         };
         // proposals 1..w, each from the previous one: normalize(base + dm)
         // with base the previous state or its one coarse step (Euler or
-        // RK4) over the whole segment by the plain solver
+        // RK4) over the whole segment by the plain solver; a part starts as
+        // soon as its last start state exists
+        int launched = 0;
         for (int j = 1; j <= w; ++j) {
             llg_status rc = LLG_OK;
-            if (j == h && (rc = verify(0, 0, h)) != LLG_OK) return rc;
-            if (j == w && w > h && (rc = verify(1, h, w - h)) != LLG_OK) return rc;
+            while (launched < parts && std::min((launched + 1) * kVerifyPart, w) <= j)
+                if ((rc = verify(launched++)) != LLG_OK) return rc;
             const float* prev = P + (size_t)(j - 1) * stride;
             const float* base = prev;
             if (predictor != LLG_SUR_BASE_STATE) {
@@ -1067,9 +1072,9 @@ llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, in
                                s->z[NL - 1], P + (size_t)j * stride, 1, s->H, s->W, s->out_scale);
             SCHK(s, hipGetLastError());
         }
-        for (int half = 0; half < (w > h ? 2 : 1); ++half) {
-            const llg_status rc = llg_batch_then_(s->vb[half], s->stream);
-            if (rc != LLG_OK) return sfail(s, rc, "verification batch: %s", llg_batch_last_error(s->vb[half]));
+        for (int p = 0; p < parts; ++p) {
+            const llg_status rc = llg_batch_then_(s->vb[p], s->stream);
+            if (rc != LLG_OK) return sfail(s, rc, "verification batch: %s", llg_batch_last_error(s->vb[p]));
         }
         // d_j = distance of proposal j to the plain result from its
         // predecessor (non-finite: infinite), and whether each plain result
