@@ -413,7 +413,7 @@ def main():
     s.set_m(m0)
     # compiled-variant choice for these FFT lengths (the autotuner times
     # H_eff evaluations of the start state)
-    tune_ms, tune_choice = s.autotune(20) if not args.no_autotune else ({}, None)
+    tune_ms, tune_choice = s.autotune(50) if not args.no_autotune else ({}, None)
     s.set_m(m0)
     if args.evals_only:
         prof, total = s.profile_evals(args.profile_evals)
