@@ -273,7 +273,10 @@ __device__ __forceinline__ float u24(uint32_t b) {
     return ((float)(b >> 8) + 0.5f) * 5.9604644775390625e-8f;
 }
 
-// unit Gaussian vector of cell `cell` at time step `step`
+// unit Gaussian vector of cell `cell` at time step `step` (Box-Muller on
+// the hardware transcendentals: v_log_f32 is log2, v_sin_f32 / v_cos_f32
+// take their argument in turns, so sin(2 pi u) is one instruction for the
+// uniforms u in (0, 1))
 __device__ __forceinline__ void thermal_eta(uint32_t cell, uint64_t step, uint32_t k0, uint32_t k1,
                                             float& ex, float& ey, float& ez) {
     U4 c;
@@ -283,14 +286,12 @@ __device__ __forceinline__ void thermal_eta(uint32_t cell, uint64_t step, uint32
     c.w = 0u;
     U4 r = philox4x32_10(c, k0, k1);
     const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
-    const float a = sqrtf(-2.0f * logf(u0));
-    const float b = sqrtf(-2.0f * logf(u2));
-    float s1, c1, s3, c3;
-    sincospif(2.0f * u1, &s1, &c1);
-    sincospif(2.0f * u3, &s3, &c3);
-    ex = a * c1;
-    ey = a * s1;
-    ez = b * c3;
+    constexpr float kTwoLn2 = 1.38629436111989061883f;   // -2 ln u = -2 ln 2 log2 u
+    const float a = sqrtf(-kTwoLn2 * __builtin_amdgcn_logf(u0));
+    const float b = sqrtf(-kTwoLn2 * __builtin_amdgcn_logf(u2));
+    ex = a * __builtin_amdgcn_cosf(u1);
+    ey = a * __builtin_amdgcn_sinf(u1);
+    ez = b * __builtin_amdgcn_cosf(u3);
 }
 
 }  // namespace llg
