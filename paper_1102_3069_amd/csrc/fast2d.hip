@@ -359,15 +359,14 @@ __device__ __forceinline__ void local_field_lds(const Grid& g, const Phys& p, co
     }
 }
 
-// the z neighbours of cell x of row r of a 3D grid (below: bit 0 of the
-// returned mask, above: bit 1; absent at an open z face), loaded from
-// global memory (component stride ncells) ahead of their use
+// the z neighbours of cell x of row r (in plane z) of a 3D grid (below:
+// bit 0 of the returned mask, above: bit 1; absent at an open z face),
+// loaded from global memory (component stride ncells) ahead of their use
 __device__ __forceinline__ unsigned z_neighbours(const Grid& g, const Phys& p, const float* __restrict__ m, int r,
-                                                 int x, float (&lo)[3], float (&up)[3]) {
+                                                 int z, int x, float (&lo)[3], float (&up)[3]) {
     if (p.cex[2] == 0.f || g.nz < 2) return 0u;
     const long long cs = g.ncells;
     const long long i = (long long)r * g.nx + x, sl = (long long)g.ny * g.nx;
-    const int z = r / g.ny;
     long long il = -1, iu = -1;
     if (z > 0) il = i - sl; else if (g.pbc[2]) il = i + (long long)(g.nz - 1) * sl;
     if (z < g.nz - 1) iu = i + sl; else if (g.pbc[2]) iu = i - (long long)(g.nz - 1) * sl;
@@ -430,6 +429,13 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     const float dtau = st->dtau;
     const uint64_t step = (uint64_t)st->step;
     const int nx = g.nx, ny = g.ny;
+    // (y, z) of the block's row rb + ri: one division per block, then steps
+    const int y0 = rb % ny, z0 = rb / ny;
+    auto plane_of = [&](int ri, int& y, int& z) {
+        y = y0 + ri;
+        z = z0;
+        while (y >= ny) { y -= ny; ++z; }
+    };
     const int cs = g.ncells;
     const float* mi = resolve(sa.m_in, cur);
     const float* m0 = resolve(sa.m0, cur);
@@ -540,7 +546,9 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             if (e < ncb) {
                 int ri, x;
                 split_cell(e, nx, rnx, ri, x);
-                zmask[it] = z_neighbours(g, p, mi, rb + ri, x, zlo[it], zup[it]);
+                int yr, zr;
+                plane_of(ri, yr, zr);
+                zmask[it] = z_neighbours(g, p, mi, rb + ri, zr, x, zlo[it], zup[it]);
             }
         }
     }
@@ -587,7 +595,8 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         split_cell(e, nx, rnx, ri, x);
         const int pr = ri >> 1, rr = ri & 1;
         const int r = rb + ri;
-        const int y = r < ny ? r : r - ny * (r / ny);
+        int y, zpl;
+        plane_of(ri, y, zpl);
         const float* rc = mrow + (ri + 1) * 3 * NXM;
         const float* rm = (ny > 1 && (y > 0 || g.pbc[1])) ? rc - 3 * NXM : nullptr;
         const float* rp = (ny > 1 && (y < ny - 1 || g.pbc[1])) ? rc + 3 * NXM : nullptr;
