@@ -40,13 +40,18 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default compiled variants")
     ap.add_argument("--evals-only", action="store_true",
                     help="run only the H_eff evaluations of the roofline measurement (for counter runs)")
-    ap.add_argument("--workload", choices=("film512", "film3d", "batch", "sp2", "surrogate", "table1"),
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="worker processes of the all-cores CPU-baseline leg (0: every host core, at most 16)")
+    ap.add_argument("--no-full-run", action="store_true", help="skip the 1 ns Dormand-Prince run of the film")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30, help="copy: bytes per copy")
+    ap.add_argument("--workload", choices=("film512", "film3d", "batch", "sp2", "surrogate", "table1", "copy"),
                     default="film512",
                     help="film512: the 512x512 film (the headline); film3d: the 256x256x64 periodic block "
                          "with the thermal field; batch: the 64-film sweep; "
                          "sp2: 200 relaxations shaped like the static standard problem, in one batch; "
                          "surrogate: train the learned proposer and time speculative verification; "
-                         "table1: Euler step time over the film and cube sizes of the paper's Table 1")
+                         "table1: Euler step time over the film and cube sizes of the paper's Table 1; "
+                         "copy: a plain device copy of --copy-bytes (HBM bandwidth, counter calibration)")
     ap.add_argument("--sur-traj", type=int, default=100, help="surrogate: training trajectories")
     ap.add_argument("--sur-pairs", type=int, default=200, help="surrogate: pairs per trajectory")
     ap.add_argument("--sur-epochs", type=float, default=4.0, help="surrogate: passes over the pairs")
@@ -56,28 +61,129 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(prob, m0, nevals):
-    """The FP64 oracle's H_eff evaluation timed on the host (numpy; its FFTs
-    and array operations run on one thread)."""
+def host_description():
+    """nproc, the cores this process may run on, and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cores": usable, "cpu_model": model}
+
+
+def _oracle_evals(prob, m0, nevals, ready=None, go=None):
+    """Worker of the CPU baseline: builds the oracle's kernel spectrum (not
+    timed), then times nevals FP64 H_eff evaluations of m0."""
     import numpy as np
     from oracle import fields
     m = m0.astype(np.float64)
     fields.heff(m, prob)                  # builds and caches the oracle's kernel spectrum
+    if ready is not None:
+        ready.wait()                      # every worker has built its spectrum
+        go.wait()
     t0 = time.perf_counter()
     for _ in range(nevals):
         fields.heff(m, prob)
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(prob, m0, nevals, threads):
+    """The FP64 oracle's H_eff evaluation timed on the host cores.  numpy's
+    FFTs and array operations run on one thread, so the all-cores leg runs
+    one oracle process per core (each with one BLAS/OpenMP thread), all
+    evaluating the same film at once; the one-thread leg runs alone."""
+    import multiprocessing as mp
     ncells = m0[0].size
-    return {"value": ncells * nevals / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nevals} FP64 H_eff evaluations of the same {prob['n'][0]}x{prob['n'][1]}x1 film "
-                      f"({dt:.1f} s; kernel spectrum built beforehand, not timed)"}
+    host = host_description()
+    one = _oracle_evals(prob, m0, nevals)
+    nproc = threads if threads > 0 else min(16, host["usable_cores"] or 1)
+    per = max(2, nevals // 4)
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        ctx = mp.get_context("spawn")
+        with ctx.Manager() as mgr:
+            ready, go = mgr.Barrier(nproc + 1), mgr.Barrier(nproc + 1)
+            with ctx.Pool(nproc) as pool:
+                res = [pool.apply_async(_oracle_evals, (prob, m0, per, ready, go)) for _ in range(nproc)]
+                ready.wait()
+                t0 = time.perf_counter()
+                go.wait()
+                [r.get() for r in res]
+                wall = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    film = f"{prob['n'][0]}x{prob['n'][1]}x{prob['n'][2]}"
+    return {"value": ncells * per * nproc / wall, "unit": "cell-updates/s", "cores": nproc, "kind": "oracle",
+            "sample": f"{nproc} oracle processes (one thread each) x {per} FP64 H_eff evaluations of the "
+                      f"{film} film, concurrently ({wall:.1f} s wall; kernel spectra built beforehand, not timed)",
+            "host": host,
+            "one_thread": {"value": ncells * nevals / one, "cores": 1,
+                           "sample": f"{nevals} FP64 H_eff evaluations of the same film ({one:.1f} s)"}}
 
 
-# kernel names of the 2D compiled-length path, per kernel kind of
-# llg_profile_evals, for the padded lengths of an n x n film
-def _kernel_name(kind, px, py):
-    return {"row_fwd": f"row_fwd_fast<{px},", "spectral": f"col2d_fast<{py // 2},",
-            "row_inv": f"row_inv_fast<{px},"}.get(kind)
+def copy_bandwidth(nbytes, reps=5):
+    """GB/s (read + write) of a plain device-to-device copy of nbytes, timed
+    with events on torch's current stream (the stream the copy runs on)."""
+    import torch
+    a = torch.ones(nbytes // 4, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9, ms
+
+
+def bench_copy(args):
+    """A plain device copy of --copy-bytes, three dispatches: the measured
+    HBM bandwidth, and the known-size kernel whose FETCH_SIZE / WRITE_SIZE
+    counters calibrate the per-kernel traffic figures."""
+    import torch
+    n = args.copy_bytes // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    gbs, ms = copy_bandwidth(args.copy_bytes)
+    print(json.dumps({"metric": "device copy bandwidth (read + write)", "value": gbs, "unit": "GB/s",
+                      "n_gpus": 1, "ms_per_copy": ms, "bytes_per_copy": args.copy_bytes,
+                      "peak": PEAK_HBM_GBS, "frac": gbs / PEAK_HBM_GBS}), flush=True)
+
+
+# full template names of the 2D compiled-length kernels a film of padded
+# lengths px x py runs with the (row, column) variant pair, per kernel kind
+# of llg_profile_evals (zero-padded x: XPER false; 2D packed layout: NAT false)
+def _kernel_name(kind, px, py, variants):
+    import paper_1102_3069_amd as llg
+    if variants is None:
+        return None
+    re_, rq = llg.variant_shape("row", px, variants[0])
+    ce, cq = llg.variant_shape("col", py // 2, variants[1])
+    return {"row_fwd": f"row_fwd_fast<{px}, {re_}, {rq}, false, false>",
+            "spectral": f"col2d_fast<{py // 2}, {ce}, {cq}>",
+            "row_inv": f"row_inv_fast<{px}, {re_}, {rq}, false, false>"}.get(kind)
 
 
 # kernel names of the 3D path (256 x 256 x 64 block: x periodic of 256,
@@ -88,10 +194,11 @@ def _kernel_name_3d(kind):
             "y_inv": "col3_tiled<256, 16, 16, 1, 1, 2>"}.get(kind)
 
 
-def measured_traffic(kind, prob, path=None, key=None):
+def measured_traffic(kind, prob, path=None, key=None, variants=None):
     """HBM bytes per launch of the kernel from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE summary (scaled by a plain copy), or None when
-    that summary was taken on other kernel sources or another size."""
+    that summary was taken on other kernel sources or another size, or has
+    no entry for the kernel's full template name."""
     import hashlib
     if path is None:
         path = os.path.join(ROOT, "profiles", f"film{prob['n'][0]}_traffic.json")
@@ -108,9 +215,9 @@ def measured_traffic(kind, prob, path=None, key=None):
     if h.hexdigest() != rec.get("source_sha256"):
         return None
     if key is None:
-        key = _kernel_name(kind, 2 * prob["n"][0], 2 * prob["n"][1])
+        key = _kernel_name(kind, 2 * prob["n"][0], 2 * prob["n"][1], variants)
     for name, t in rec["kernels"].items():
-        if key and key in name:
+        if key and key + "(" in name:
             return t["read_bytes"] + t["write_bytes"]
     return None
 
@@ -327,10 +434,12 @@ def bench_surrogate(args):
     del X, E
     torch.cuda.empty_cache()
     train_flops = 236.7e3 * n * n * steps * batch
-    # ablation: the same proposals without the network (dm = 0: the plain
-    # solver's one coarse RK4 step of the whole segment)
-    bare = llg.Surrogate(n, n, max_batch=1)
-    bare.set_params([(np.zeros_like(w), np.zeros_like(b)) for w, b in workloads.surrogate_init(0)])
+    # ablation: the same proposals without the network (all weights zero, so
+    # dm = 0: the plain solver's one coarse RK4 step of the whole segment),
+    # on the same object with its parameters swapped, interleaved with the
+    # network's runs threshold by threshold
+    trained = sur.get_params()
+    zeros = np.zeros_like(trained)
     held, _ = workloads.surrogate_films(args.sur_held_out, seed=6, n_side=n)
     thresholds = (1e-2, 1e-4, 5e-5, 2e-5)
     t_plain = 0.0
@@ -346,12 +455,13 @@ def bench_surrogate(args):
         s.step("rk4", run["dt"], run["seg_steps"] * args.sur_segments)
         t_plain += time.perf_counter() - t0
         m_plain = s.get_m()
-        for kind, net in (("net", sur), ("bare", bare)):
-            net.advance(prob, m_start, n_segments=1, window=args.sur_window, dt=run["dt"])   # builds the batches
-            for th in thresholds:
+        sur.advance(prob, m_start, n_segments=1, window=args.sur_window, dt=run["dt"])   # builds the batches
+        for th in thresholds:
+            for kind, params in (("net", trained), ("bare", zeros)):
+                sur.set_params(params)
                 r = runs[(kind, th)]
                 t0 = time.perf_counter()
-                m_s, st = net.advance(prob, m_start, n_segments=args.sur_segments, window=args.sur_window,
+                m_s, st = sur.advance(prob, m_start, n_segments=args.sur_segments, window=args.sur_window,
                                       dt=run["dt"], max_dm=th)
                 r["t"] += time.perf_counter() - t0
                 r["stats"].append(st)
@@ -366,6 +476,11 @@ def bench_surrogate(args):
     segs = args.sur_held_out * args.sur_segments
     th0 = thresholds[0]
     head = summary("net", th0)
+    # at 1e-2 both arms accept every proposal and do the same work: that
+    # speedup belongs to the scheme (time-parallel verification of
+    # coarse-step proposals); the network's own gain is the ratio of the
+    # arms where their acceptance differs
+    gain = {f"{th:g}": summary("net", th)["speedup"] / summary("bare", th)["speedup"] for th in thresholds}
     out = {"metric": "speedup of speculative verification over plain RK4 at max |dm| <= 1e-2",
            "value": head["speedup"], "unit": "x", "n_gpus": 1, "steps": segs, "warmup": 1,
            "ms_per_step": runs[("net", th0)]["t"] * 1e3 / segs, "higher_is_better": True, "scaling": "weak",
@@ -374,6 +489,10 @@ def bench_surrogate(args):
                                   f"10 RK4 steps (dt 1e-13 s), window {args.sur_window}; proposals "
                                   "normalize(one RK4 step of the whole segment + network correction)",
                       "plain_s": t_plain, "speculative_s": runs[("net", th0)]["t"], **head,
+                      "speedup_source": "at 1e-2 every proposal of both arms is accepted: the speedup comes from "
+                                        "speculative verification of coarse-step proposals, not from the network; "
+                                        "network_gain_over_bare gives the network's own share per threshold",
+                      "network_gain_over_bare": gain,
                       "thresholds": {f"{th:g}": {"network": summary("net", th), "without_network": summary("bare", th)}
                                      for th in thresholds},
                       "train_pairs": npairs, "train_steps": steps,
@@ -383,23 +502,50 @@ def bench_surrogate(args):
     print(json.dumps(out), flush=True)
 
 
+def model_bytes_2d(n, px, py):
+    """Algorithmic bytes of one H_eff evaluation of an n[0] x n[1] film on a
+    px x py FFT grid (FP32): read m and write H, the kernel spectrum read
+    once, and one write + read round trip of the half spectrum for each of
+    the two exchanges between the x and y directions."""
+    cells = n[0] * n[1]
+    spec = 3 * 8 * (px // 2 + 1) * n[1]
+    kern = 4 * 4 * (px // 2 + 1) * (py // 2 + 1)
+    return 2 * 12 * cells + 2 * 2 * spec + kern
+
+
+def full_run(llg, prob, m0, run):
+    """The film from its start state to 1 ns with adaptive Dormand-Prince
+    (tolerance 1e-5): wall time and the work the controller did."""
+    import numpy as np
+    import torch
+    s = llg.Solver(0)
+    s.set_problem(prob)
+    s.set_m(m0)
+    s.run(2e-12, run["tol"], run["dt0"])           # captures the attempt graph
+    s.set_m(m0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.run(run["t_end"], run["tol"], run["dt0"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    m = s.get_m().reshape(3, -1).mean(axis=1)
+    s.close()
+    return {"t_end_s": run["t_end"], "wall_s": wall, "evals": st["evals"], "accepted": st["steps"],
+            "rejected": st["rejected"], "cell_updates_per_s": int(np.prod(prob["n"])) * st["evals"] / wall,
+            "mean_m": [round(float(v), 5) for v in m]}
+
+
 def main():
     args = parse()
-    if args.workload == "surrogate":
-        if args.gpus != 1:
-            print("bench.py runs on one GPU only", file=sys.stderr)
-            sys.exit(2)
-        return bench_surrogate(args)
-    if args.workload in ("batch", "sp2", "film3d", "table1"):
-        if args.gpus != 1:
-            print("bench.py runs on one GPU only", file=sys.stderr)
-            sys.exit(2)
-        return {"batch": bench_batch, "sp2": bench_sp2, "film3d": bench_film3d,
-                "table1": bench_table1}[args.workload](args)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build measures one GPU, and "
+              "how the path would shard over several is described in DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
+    if args.workload in ("batch", "sp2", "film3d", "table1", "copy"):
+        return {"batch": bench_batch, "sp2": bench_sp2, "film3d": bench_film3d,
+                "table1": bench_table1, "copy": bench_copy}[args.workload](args)
     import numpy as np
     import torch
     import paper_1102_3069_amd as llg
@@ -408,17 +554,23 @@ def main():
     llg.load()
     prob, m0, run = workloads.film_512(args.n)
     ncells = int(np.prod(prob["n"]))
+    # the CPU leg first, before this process touches the GPU (its worker
+    # processes are started fresh)
+    cpu = None
+    if not args.no_cpu_baseline and not args.evals_only:
+        cpu = cpu_baseline(prob, m0, args.cpu_baseline_evals, args.cpu_threads)
     s = llg.Solver(0)
     s.set_problem(prob)
     s.set_m(m0)
     # compiled-variant choice for these FFT lengths (the autotuner times
     # H_eff evaluations of the start state)
     tune_ms, tune_choice = s.autotune(50) if not args.no_autotune else ({}, None)
+    variants = s.get_variants()
     s.set_m(m0)
     if args.evals_only:
         prof, total = s.profile_evals(args.profile_evals)
         print(json.dumps({"evals": args.profile_evals, "kernel_ms": prof, "eval_ms": total / args.profile_evals,
-                          "variants": tune_choice}))
+                          "variants": variants}))
         return
     # warm-up attempts (they also capture the graph)
     s.run_attempts(run["t_end"], run["tol"], run["dt0"], max(1, args.warmup))
@@ -438,26 +590,34 @@ def main():
     nbytes = s.kernel_bytes()
     dom = max(prof, key=lambda k: prof[k])
     achieved = nbytes[dom] / (prof[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(dom, prob),
+    px, py = 2 * prob["n"][0], 2 * prob["n"][1]
+    eval_bytes = model_bytes_2d(prob["n"], px, py)
+    copy_gbs, _ = copy_bandwidth(1 << 30)
+    eval_gbs = eval_bytes * value / ncells / 1e9
+    roofline = {"bound": "hbm", "kernel": _kernel_name(dom, px, py, variants) or dom, "achieved": achieved,
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                "traffic": measured_traffic(dom, prob, variants=variants),
                 "kernel_ms": prof, "kernel_bytes": nbytes,
-                "eval_ms": prof_total / args.profile_evals}
-
+                "eval_ms": prof_total / args.profile_evals,
+                "eval_model_bytes": eval_bytes, "eval_gbs": eval_gbs, "eval_frac": eval_gbs / PEAK_HBM_GBS,
+                "copy_gbs": copy_gbs, "eval_frac_of_copy": eval_gbs / copy_gbs}
+    s.close()
+    config = {"workload": f"thin film {prob['n'][0]}x{prob['n'][1]}x1, 4x4x3 nm cells, "
+                          "adaptive Dormand-Prince 5(4) attempts (6 H_eff evals each) toward 1 ns",
+              "cells": ncells, "evals": evals, "sim_time_s": st1["t"],
+              "variants": {"chosen": list(variants),
+                           "eval_ms": {f"{r}{c}": round(v, 5) for (r, c), v in tune_ms.items()}},
+              "paper_context": "GTX580 Euler step at 512^2: 9.53e7 cell-updates/s (Table 1)"}
+    if not args.no_full_run:
+        config["full_run_1ns"] = full_run(llg, prob, m0, run)
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": attempts, "warmup": args.warmup, "ms_per_step": wall * 1e3 / max(attempts, 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"thin film {prob['n'][0]}x{prob['n'][1]}x1, 4x4x3 nm cells, "
-                               "adaptive Dormand-Prince 5(4) attempts (6 H_eff evals each) toward 1 ns",
-                   "cells": ncells, "evals": evals, "sim_time_s": st1["t"],
-                   "variants": {"chosen": tune_choice,
-                                "eval_ms": {f"{r}{c}": round(v, 5) for (r, c), v in tune_ms.items()}},
-                   "paper_context": "GTX580 Euler step at 512^2: 9.53e7 cell-updates/s (Table 1)"},
-        "roofline": roofline,
+        "data": "synthetic", "config": config, "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, m0, args.cpu_baseline_evals)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -252,20 +252,34 @@ llg_status llg_kernel_bytes(llg_solver *s, double *bytes_out, int n_kinds);
 /* ---- tuning -------------------------------------------------------------------
  * The 2D path has two compiled variants (elements per lane, hence lanes and
  * wavefronts per transform) for every row length and every column length.
- * The variant in use for a length is held in a process-wide table shared by
- * every solver and by llg_batch_create; it starts at variant 0.
+ * A process-wide table holds the default variant of each length (variant 0
+ * at start).  llg_set_geometry and llg_batch_create copy the defaults of
+ * their lengths (variant 0 where the default cannot serve the geometry);
+ * a solver or batch then keeps its variants until its own llg_autotune,
+ * llg_set_variants, llg_batch_autotune or llg_batch_set_variant call,
+ * whatever later calls do to the table.
  * llg_autotune times `iters` H_eff evaluations of the solver's current state
  * with each of the four (row, column) variant pairs of its lengths, keeps the
- * fastest in the table and returns the mean milliseconds per evaluation of
- * pair (r, c) in ms_out[2r + c] (-1 if that pair cannot serve this geometry;
- * ms_out may be NULL, n_out its length) and the chosen pair in choice[0..1]
- * (may be NULL).  Solvers and batches made afterwards, and this solver, use
- * the new table entry; results of different variants differ by FP32
- * rounding only.  LLG_E_UNSUPPORTED unless the geometry is 2D with compiled
- * lengths.  llg_set_variants sets the table entry for the solver's lengths
- * directly. */
+ * fastest for this solver and as the table's default, and returns the mean
+ * milliseconds per evaluation of pair (r, c) in ms_out[2r + c] (-1 if that
+ * pair cannot serve this geometry; ms_out may be NULL, n_out its length) and
+ * the chosen pair in choice[0..1] (may be NULL).  Results of different
+ * variants differ by FP32 rounding (each is checked against the FP64 oracle
+ * to 1e-5).  LLG_E_UNSUPPORTED unless the geometry is 2D with compiled
+ * lengths.  llg_set_variants sets the solver's pair, and the table's
+ * defaults for its lengths, directly (LLG_E_ARG if the pair cannot serve the
+ * geometry). */
 llg_status llg_autotune(llg_solver *s, int iters, double *ms_out, int n_out, int *choice);
 llg_status llg_set_variants(llg_solver *s, int row_var, int col_var);
+/* The solver's (row, column) variant pair.  LLG_E_UNSUPPORTED unless the
+ * geometry is 2D with compiled lengths. */
+llg_status llg_get_variants(llg_solver *s, int *row_var, int *col_var);
+/* Shape of a compiled variant: kind 0 a row length Px, kind 1 a column half
+ * length L = Py/2; *elems receives the elements each lane holds in a
+ * transform, *classes the number of frequency classes each padded
+ * transform is split into (2 or 4; one lane group per class).  LLG_E_ARG if
+ * there is no such variant.  Needs no device. */
+llg_status llg_variant_shape(int kind, int length, int variant, int *elems, int *classes);
 
 /* ---- diagnostics ------------------------------------------------------------
  * llg_fft_roundtrip: forward then inverse FP32 FFT, by the library's own FFT
@@ -346,13 +360,23 @@ typedef struct {
  * all films (forward row pass, column pass, inverse row pass, no state
  * change) with each compiled variant of that length, twice in alternating
  * order, the other lengths held, and keeps the faster (by the better of its
- * two timings) in the process-wide variant table (the one
- * llg_autotune fills; solvers and batches made afterwards use it).  The
- * batch's launches are rebuilt; film states, times and controllers are left
- * as they were; results of different variants differ by FP32 rounding only.
+ * two timings) for this batch's films and as the table's default (the table
+ * llg_autotune fills; solvers and batches set up afterwards copy it).  Every
+ * launch argument of the batch is rebuilt for the new variants (the column
+ * pass reads the spectrum in the order the row variant writes it); film
+ * states, times and controllers are left as they were, and the first stage
+ * is evaluated anew on the next step.  Results of different variants differ
+ * by FP32 rounding (each checked against the FP64 oracle to 1e-5).
  * out (host, cap entries, may be NULL with cap = 0) receives one entry per
  * length, *n_out their number (may be NULL). */
 llg_status  llg_batch_autotune(llg_batch *b, int iters, llg_tune_entry *out, int cap, int *n_out);
+/* Sets the compiled variant (0 or 1) of one padded length of this batch:
+ * kind 0 the row (x) length Px, kind 1 the column half length L = Py/2, for
+ * every film of that length; the table of defaults is not changed.  Launch
+ * arguments are rebuilt and the first stage is evaluated anew on the next
+ * step.  LLG_E_ARG if no film uses the length or the variant cannot serve
+ * one of them. */
+llg_status  llg_batch_set_variant(llg_batch *b, int kind, int length, int variant);
 
 /* ---- learned surrogate ------------------------------------------------------
  * Not part of the paper's method: a small convolutional network that

@@ -119,6 +119,9 @@ _SIGNATURES = {
     "llg_autotune": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                       ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "llg_set_variants": ([_P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "llg_get_variants": ([_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "llg_variant_shape": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                           ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "llg_fft_roundtrip": ([_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "llg_demag_tensor": ([_P, _P, ctypes.c_int64, _P], ctypes.c_int),
     "llg_batch_create": ([ctypes.c_int, ctypes.POINTER(FilmDesc), ctypes.c_int, ctypes.POINTER(_P)],
@@ -129,6 +132,7 @@ _SIGNATURES = {
                        ctypes.POINTER(Stats)], ctypes.c_int),
     "llg_batch_step": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_int64], ctypes.c_int),
     "llg_batch_autotune": ([_P, ctypes.c_int, _P, ctypes.c_int, _P], ctypes.c_int),
+    "llg_batch_set_variant": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "llg_batch_set_m": ([_P, ctypes.c_int, _P, ctypes.c_int], ctypes.c_int),
     "llg_batch_get_m": ([_P, ctypes.c_int, _P, ctypes.c_int], ctypes.c_int),
     "llg_batch_get_attempts": ([_P, ctypes.c_int, ctypes.POINTER(Attempt), ctypes.c_int64,
@@ -360,6 +364,11 @@ class Solver:
     def set_variants(self, row_var, col_var):
         self._chk(self._lib.llg_set_variants(self._h, int(row_var), int(col_var)))
 
+    def get_variants(self):
+        r, c = ctypes.c_int(), ctypes.c_int()
+        self._chk(self._lib.llg_get_variants(self._h, ctypes.byref(r), ctypes.byref(c)))
+        return r.value, c.value
+
     def fft_roundtrip(self, data, inverse_only=False):
         """data: complex64 array (batch, n); returns the library's
         forward+inverse (or inverse only) transform divided by n."""
@@ -452,6 +461,11 @@ class Batch:
         self._chk(self._lib.llg_batch_autotune(self._h, int(iters), ctypes.cast(ent, _P), cap, ctypes.byref(n)))
         return [{"kind": ("row", "col")[e.kind], "length": e.length, "variant": e.variant,
                  "ms": (e.ms[0], e.ms[1])} for e in ent[:min(n.value, cap)]]
+
+    def set_variant(self, kind, length, variant):
+        """Compiled variant of one padded length of this batch's films
+        (kind "row": Px, "col": Py / 2)."""
+        self._chk(self._lib.llg_batch_set_variant(self._h, {"row": 0, "col": 1}[kind], int(length), int(variant)))
 
     def set_m(self, film, m):
         if _is_torch(m) and m.is_cuda:
@@ -635,6 +649,18 @@ class Surrogate:
                                             ctypes.byref(st)))
         del keep
         return out, st.as_dict()
+
+
+def variant_shape(kind, length, variant):
+    """(elements per lane, frequency classes) of a compiled variant; kind
+    "row" (length Px) or "col" (length Py / 2)."""
+    lib = load()
+    e, q = ctypes.c_int(), ctypes.c_int()
+    rc = lib.llg_variant_shape({"row": 0, "col": 1}[kind], int(length), int(variant), ctypes.byref(e),
+                               ctypes.byref(q))
+    if rc != LLG_OK:
+        raise LLGError(rc, f"no compiled {kind} variant {variant} of length {length}")
+    return e.value, q.value
 
 
 def mfma_selftest(A, B, device=0):

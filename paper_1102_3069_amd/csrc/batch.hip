@@ -43,8 +43,7 @@ struct BatchFilm {
     float* kb[6] = {};
     float* kfs[2] = {nullptr, nullptr};
     llg_attempt* log = nullptr;
-    int row_blocks = 0, col_blocks = 0;
-    int rvar = 0, cvar = 0;             // compiled variants of its lengths
+    int row_blocks = 0, col_blocks = 0;   // blocks per pass with the variants g.rvar, g.cvar
 };
 
 }  // namespace
@@ -130,10 +129,22 @@ Col2dArgs col_args(const BatchFilm& f) {
     c.nkx_full = f.g.nkx;
     c.nkxp = f.g.nkxp;
     c.tsh = f.g.tsh;
-    c.nq = fast2d_row_classes(f.g.Px, f.rvar);
+    c.nq = fast2d_row_classes(f.g.Px, f.g.rvar);
+    c.var = f.g.cvar;
     c.ny = f.g.ny;
     c.Py = f.g.Py;
     return c;
+}
+
+// the table's default variants where they serve the film's lengths, else
+// variant 0 (the rule of the single-film solver); false if even that fails
+bool pick_variants(Grid& g) {
+    const int L = g.Py / 2;
+    g.rvar = fast2d_row_variant(g.Px);
+    if (!fast2d_row_ok(g.Px, g.rvar)) g.rvar = 0;
+    g.cvar = fast2d_col_variant(L);
+    if (!fast2d_col_ok(L, 1, g.cvar) || (g.Px / 2) % fast2d_col_width(L, g.cvar)) g.cvar = 0;
+    return fast2d_row_ok(g.Px, g.rvar) && fast2d_col_ok(L, 1, g.cvar) && (g.Px / 2) % fast2d_col_width(L, g.cvar) == 0;
 }
 
 FilmRow row_base(const llg_batch* b, int i) {
@@ -144,7 +155,6 @@ FilmRow row_base(const llg_batch* b, int i) {
     r.twx = f.twx;
     r.S = f.S;
     r.st = b->st + i;
-    r.var = f.rvar;
     return r;
 }
 
@@ -166,7 +176,7 @@ llg_status build_classes(llg_batch* b, const std::vector<char>& active) {
         for (int i = 0; i < nf; ++i) {
             if (!active[i]) continue;
             const BatchFilm& f = b->films[i];
-            const std::pair<int, int> k = row ? std::make_pair(f.g.Px, f.rvar) : std::make_pair(f.g.Py / 2, f.cvar);
+            const std::pair<int, int> k = row ? std::make_pair(f.g.Px, f.g.rvar) : std::make_pair(f.g.Py / 2, f.g.cvar);
             if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
         }
         std::sort(keys.begin(), keys.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
@@ -177,8 +187,8 @@ llg_status build_classes(llg_batch* b, const std::vector<char>& active) {
             for (int i = 0; i < nf; ++i) {
                 if (!active[i]) continue;
                 const BatchFilm& f = b->films[i];
-                const bool in = row ? (f.g.Px == k.first && f.rvar == k.second)
-                                    : (f.g.Py / 2 == k.first && f.cvar == k.second);
+                const bool in = row ? (f.g.Px == k.first && f.g.rvar == k.second)
+                                    : (f.g.Py / 2 == k.first && f.g.cvar == k.second);
                 if (!in) continue;
                 const int nb = row ? f.row_blocks : f.col_blocks;
                 for (int j = 0; j < nb; ++j) map.push_back(make_int2(i, j));
@@ -225,10 +235,28 @@ llg_status restore_classes(llg_batch* b) {
     return build_classes(b, all);
 }
 
-// the per-film arguments of every grouped launch of an attempt; buffer
-// roles follow the single-film Dormand-Prince attempt exactly
+void free_launch_args(llg_batch* b) {
+    bfree(b->d_fwd_plain); b->d_fwd_plain = nullptr;
+    bfree(b->d_konly); b->d_konly = nullptr;
+    bfree(b->d_prep); b->d_prep = nullptr;
+    for (auto& p : b->d_stage) { bfree(p); p = nullptr; }
+    bfree(b->d_col); b->d_col = nullptr;
+}
+
+// the per-film arguments of every grouped launch of an attempt, for the
+// films' current variants (the column pass reads the row variant's
+// spectrum order from them), and the block maps; buffer roles follow the
+// single-film Dormand-Prince attempt exactly.  Called whenever a variant
+// changes: arguments built for other variants would misread the spectrum.
 llg_status build_launch_args(llg_batch* b) {
     const int nf = (int)b->films.size();
+    (void)hipStreamSynchronize(b->stream);   // no launch still reads the old arguments
+    free_launch_args(b);
+    for (BatchFilm& f : b->films) {
+        f.row_blocks = (f.g.nrows + fast2d_row_rows_per_block(f.g.Px, f.g.rvar) - 1) /
+                       fast2d_row_rows_per_block(f.g.Px, f.g.rvar);
+        f.col_blocks = (f.g.Px / 2) / fast2d_col_width(f.g.Py / 2, f.g.cvar);
+    }
     const Tableau t = tab_dp45();
     std::vector<FilmRow> fwd_plain(nf), konly(nf), prep(nf), stage[6];
     std::vector<FilmCol> col(nf);
@@ -278,7 +306,6 @@ llg_status build_launch_args(llg_batch* b) {
         }
         col[i].a = col_args(f);
         col[i].st = b->st + i;
-        col[i].var = f.cvar;
     }
     BCHK(b, upload(&b->d_fwd_plain, fwd_plain));
     BCHK(b, upload(&b->d_konly, konly));
@@ -425,10 +452,10 @@ llg_status llg_batch_create(int device, const llg_film_desc* films, int nfilms, 
         if (Px == 0 || L == 0)
             return bfail(b, LLG_E_UNSUPPORTED, "film %d: %d x %d exceeds the compiled batched lengths", i, d.nx,
                          d.ny);
-        f.rvar = fast2d_row_variant(Px);
-        f.cvar = fast2d_col_variant(L);
-        if (!fast2d_row_ok(Px, f.rvar) || !fast2d_col_ok(L, 1, f.cvar) || (Px / 2) % fast2d_col_width(L, f.cvar) ||
-            d.ny > L)
+        Grid vg = {};
+        vg.Px = Px;
+        vg.Py = 2 * L;
+        if (!pick_variants(vg) || d.ny > L)
             return bfail(b, LLG_E_UNSUPPORTED,
                          "film %d: %d x %d needs FFT lengths %d x %d without a compiled batched kernel", i,
                          d.nx, d.ny, Px, Py);
@@ -444,9 +471,8 @@ llg_status llg_batch_create(int device, const llg_film_desc* films, int nfilms, 
         g.nkxp = (g.nkx + 15) / 16 * 16;
         g.tsh = fast2d_tile_shift();
         g.split_y = 1; g.split_z = 0;
-        const int rpb = fast2d_row_rows_per_block(Px, f.rvar);
-        f.row_blocks = (g.nrows + rpb - 1) / rpb;
-        f.col_blocks = (Px / 2) / fast2d_col_width(L, f.cvar);
+        g.rvar = vg.rvar;
+        g.cvar = vg.cvar;
         const size_t vec = sizeof(float) * 3 * (size_t)g.ncells;
         BCHK(b, make_tw(Px, &f.twx));
         BCHK(b, make_tw(Py, &f.twy));
@@ -507,8 +533,7 @@ void llg_batch_destroy(llg_batch* b) {
         for (auto p : f.kfs) bfree(p);
     }
     bfree(b->st);
-    bfree(b->d_fwd_plain); bfree(b->d_konly); bfree(b->d_prep); bfree(b->d_col);
-    for (auto p : b->d_stage) bfree(p);
+    free_launch_args(b);
     for (auto& c : b->rows) bfree(c.map);
     for (auto& c : b->cols) bfree(c.map);
     for (auto st : b->aux) (void)hipStreamDestroy(st);
@@ -757,16 +782,11 @@ llg_status llg_batch_autotune(llg_batch* b, int iters, llg_tune_entry* out, int 
             if (std::find(lens[k].begin(), lens[k].end(), l[k]) == lens[k].end()) lens[k].push_back(l[k]);
     }
     for (auto& v : lens) std::sort(v.begin(), v.end(), std::greater<int>());
-    // every film takes the table's variants; launches rebuilt
+    // every film takes the table's variants; every launch argument and
+    // block map rebuilt for them
     auto apply = [&]() -> llg_status {
-        for (BatchFilm& f : b->films) {
-            f.rvar = fast2d_row_variant(f.g.Px);
-            f.cvar = fast2d_col_variant(f.g.Py / 2);
-            f.row_blocks = (f.g.nrows + fast2d_row_rows_per_block(f.g.Px, f.rvar) - 1) /
-                           fast2d_row_rows_per_block(f.g.Px, f.rvar);
-            f.col_blocks = (f.g.Px / 2) / fast2d_col_width(f.g.Py / 2, f.cvar);
-        }
-        return build_classes(b, std::vector<char>(nf, 1));
+        for (BatchFilm& f : b->films) (void)pick_variants(f.g);
+        return build_launch_args(b);
     };
     // a variant serves a length if every film of that length can use it
     auto usable = [&](int kind, int len, int var) {
@@ -840,6 +860,34 @@ llg_status llg_batch_autotune(llg_batch* b, int iters, llg_tune_entry* out, int 
     if (rw != LLG_OK) return rw;
     for (int i = 0; i < (int)res.size() && i < cap; ++i) out[i] = res[i];
     if (n_out) *n_out = (int)res.size();
+    return LLG_OK;
+}
+
+llg_status llg_batch_set_variant(llg_batch* b, int kind, int length, int variant) {
+    if (!b) return LLG_E_ARG;
+    b->err.clear();
+    BCHK(b, hipSetDevice(b->device));
+    if (kind != 0 && kind != 1) return bfail(b, LLG_E_ARG, "kind must be 0 (row) or 1 (column)");
+    int hits = 0;
+    for (const BatchFilm& f : b->films) {
+        const bool row = kind == 0;
+        if ((row ? f.g.Px : f.g.Py / 2) != length) continue;
+        ++hits;
+        const bool ok = row ? fast2d_row_ok(length, variant)
+                            : fast2d_col_ok(length, 1, variant) && (f.g.Px / 2) % fast2d_col_width(length, variant) == 0;
+        if (!ok) return bfail(b, LLG_E_ARG, "variant %d does not serve %s length %d", variant, row ? "row" : "column", length);
+    }
+    if (!hits) return bfail(b, LLG_E_ARG, "no film uses %s length %d", kind == 0 ? "row" : "column", length);
+    for (BatchFilm& f : b->films) {
+        if (kind == 0 && f.g.Px == length) f.g.rvar = variant;
+        if (kind == 1 && f.g.Py / 2 == length) f.g.cvar = variant;
+    }
+    llg_status rc = build_launch_args(b);
+    if (rc != LLG_OK) return rc;
+    // the spectra and first-stage k's were made with the old variants
+    b->k1_valid = false;
+    b->spec_valid = false;
+    b->hcur_ok = false;
     return LLG_OK;
 }
 

@@ -1059,7 +1059,7 @@ hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, cons
     if (g.nx > g.Px || g.nkxp < g.Px / 2 || g.tsh < 0 || (g.Px / 2) % (1 << g.tsh)) return hipErrorInvalidValue;
     const bool nat = g.nz > 1;
     if (nat && (g.nkxp < g.Px / 2 + 1 || g.nkx != g.Px / 2 + 1)) return hipErrorInvalidValue;
-    const int var = fast2d_row_variant(g.Px);
+    const int var = g.rvar;
 #define CASE(PX, E, NQ, V)                                                                \
     if (g.Px == PX && var == V)                                                           \
         return nat ? launch_row_fwd_t<PX, E, NQ, true>(g, twx, S, fa, st, s)              \
@@ -1076,7 +1076,7 @@ hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, 
     if ((sa.mode == ROW_STAGE || sa.mode == ROW_ERROR) && sa.nk < 1) return hipErrorInvalidValue;
     const bool nat = g.nz > 1;
     if (nat && (g.nkxp < g.Px / 2 + 1 || g.nkx != g.Px / 2 + 1)) return hipErrorInvalidValue;
-    const int var = fast2d_row_variant(g.Px);
+    const int var = g.rvar;
 #define CASE(PX, E, NQ, V)                                                                \
     if (g.Px == PX && var == V)                                                           \
         return nat ? launch_row_inv_t<PX, E, NQ, true>(g, p, twx, S, sa, st, s)           \
@@ -1090,7 +1090,7 @@ hipError_t launch_col2d_fast(const Col2dArgs& a, DevState* st, hipStream_t s) {
     if (a.Py % 2 || a.ny > a.Py / 2 || a.nkx_full != a.nkx + 1 || a.nkx % 2) return hipErrorInvalidValue;
     if (a.tsh < 0 || a.nkx % (1 << a.tsh) || (a.nq != 2 && a.nq != 4) || a.nkx % a.nq) return hipErrorInvalidValue;
     const int L = a.Py / 2;
-    const int var = fast2d_col_variant(L);
+    const int var = a.var;
 #define CASE(LL, E, NQ, V)                                                                \
     if (L == LL && var == V) {                                                            \
         using CF = ColSplit<LL, E, NQ>;                                                   \
@@ -1112,6 +1112,19 @@ int fast2d_row_rows_per_block(int Px, int var) {
 #undef CASE
     return 0;
 }
+bool fast2d_variant_shape(int kind, int len, int var, int* elems, int* classes) {
+    if (kind == 0) {
+#define CASE(PX, E, NQ, V) if (len == PX && var == V) { *elems = E; *classes = NQ; return true; }
+        ROW_VARIANTS(CASE)
+#undef CASE
+    } else if (kind == 1) {
+#define CASE(LL, E, NQ, V) if (len == LL && var == V) { *elems = E; *classes = NQ; return true; }
+        COL_VARIANTS(CASE)
+#undef CASE
+    }
+    return false;
+}
+
 int fast2d_row_classes(int Px, int var) {
     if (var < 0) var = fast2d_row_variant(Px);
 #define CASE(PX, E, NQ, V) if (Px == PX && var == V) return NQ;

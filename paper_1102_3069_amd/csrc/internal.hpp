@@ -25,6 +25,9 @@ struct Grid {
     int nkx, nkxp;
     int split_y, split_z;   // 1 on an open axis: even/odd half transforms
     int tsh;                // 2D compiled path: spectrum columns in tiles of 2^tsh
+    int rvar, cvar;         // compiled-length kernels: variant of the row length Px and of
+                            // the column half length Py/2, fixed when the solver or batch
+                            // is set up (the spectrum layout depends on rvar)
 };
 
 // Spectrum layout of the 2D compiled path: per component, stored columns
@@ -153,6 +156,7 @@ struct Col2dArgs {
     int ny, Py;
     int tsh;                // tile width log2 (see tile_index)
     int nq;                 // frequency classes of the row transforms (column order)
+    int var;                // compiled variant of the column half length Py/2
 };
 
 // ---- launchers (kernels.hip) ------------------------------------------------
@@ -173,7 +177,10 @@ hipError_t launch_fft_test(float2* data, int n, int batch, const FftPlan& pl, co
 
 // ---- 2D fast path (fast2d.hip) ---------------------------------------------------
 // compiled variants per length (elements per lane); var < 0 selects the
-// variant of the process-wide table (llg_autotune), 0 until tuned
+// variant of the process-wide table of defaults (llg_autotune,
+// llg_set_variants, llg_batch_autotune), 0 until tuned.  A solver or batch
+// copies its variants into Grid::rvar / cvar when it is set up, and the
+// launchers below use those copies, never the table.
 bool fast2d_row_ok(int Px, int var = -1, bool xper = false);
 bool fast2d_col_ok(int L, int split, int var = -1);
 int fast2d_row_variant(int Px);
@@ -197,15 +204,16 @@ struct FilmRow {
     DevState* st;
     StageArgs sa;     // row_inv
     FwdArgs fa;       // row_fwd
-    int var;          // compiled variant of the row length
 };
 struct FilmCol {
     Col2dArgs a;
     DevState* st;
-    int var;          // compiled variant of the column length
 };
 int fast2d_row_rows_per_block(int Px, int var);
 int fast2d_row_classes(int Px, int var = -1);
+// elements per lane and frequency classes of a compiled variant (kind 0:
+// row length Px, kind 1: column half length L); false if there is none
+bool fast2d_variant_shape(int kind, int len, int var, int* elems, int* classes);
 // tiled column passes of the 3D path for axes of compiled length (fast3d.hip)
 bool fast3d_col_ok(int P, int split, bool full);     // full: the pass with the kernel product
 int fast3d_col_width(int P, int split, bool full);

@@ -233,7 +233,8 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
         c.nkx_full = g.nkx;
         c.nkxp = g.nkxp;
         c.tsh = g.tsh;
-        c.nq = fast2d_row_classes(g.Px);
+        c.nq = fast2d_row_classes(g.Px, g.rvar);
+        c.var = g.cvar;
         c.ny = g.ny;
         c.Py = g.Py;
         HIPCHK(s, launch_col2d_fast(c, s->st, s->stream));
@@ -337,6 +338,28 @@ llg_status read_state(llg_solver* s, DevState* h) {
 llg_status write_state(llg_solver* s, const DevState* h) {
     HIPCHK(s, hipMemcpyAsync(s->st, h, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
     return sync(s);
+}
+
+// The hot-path kernels return at once while the device state says the run
+// is done, which an adaptive run that reached t_end leaves set.  The calls
+// that only evaluate H_eff lift the flag for their launches and put it back.
+llg_status lift_done(llg_solver* s, int* was) {
+    DevState h;
+    llg_status rc = read_state(s, &h);
+    if (rc != LLG_OK) return rc;
+    *was = h.done;
+    if (!h.done) return LLG_OK;
+    h.done = 0;
+    return write_state(s, &h);
+}
+
+llg_status restore_done(llg_solver* s, int was) {
+    if (!was) return LLG_OK;
+    DevState h;
+    llg_status rc = read_state(s, &h);
+    if (rc != LLG_OK) return rc;
+    h.done = was;
+    return write_state(s, &h);
 }
 
 // H_eff of m (mbuf[cur]) into `out` (device); tracks spectrum validity
@@ -655,9 +678,16 @@ llg_status llg_set_geometry(llg_solver* s, int nx, int ny, int nz, int pbc_x, in
     // LLG_FORCE_GENERIC=1 selects the runtime-length kernels everywhere (used
     // by the tests to check both implementations against the oracle)
     const char* gen = getenv("LLG_FORCE_GENERIC");
-    s->fast2d = nz == 1 && fast2d_row_ok(P[0], -1, nx == P[0]) && fast2d_col_ok(Ly, split_y) && ny <= Ly &&
-                (P[0] / 2) % fast2d_col_width(Ly) == 0 && !(gen && gen[0] == '1');
-    s->fastrows = s->fast2d || (nz > 1 && fast2d_row_ok(P[0], -1, nx == P[0]) && (nx == P[0] || 2 * nx <= P[0]) &&
+    // compiled variants: the table's defaults where they serve this geometry
+    // (else variant 0); kept by this solver until its own llg_autotune or
+    // llg_set_variants, whatever later calls do to the table
+    g.rvar = fast2d_row_variant(P[0]);
+    if (!fast2d_row_ok(P[0], g.rvar, nx == P[0])) g.rvar = 0;
+    g.cvar = fast2d_col_variant(Ly);
+    if (!fast2d_col_ok(Ly, split_y, g.cvar) || (P[0] / 2) % fast2d_col_width(Ly, g.cvar)) g.cvar = 0;
+    s->fast2d = nz == 1 && fast2d_row_ok(P[0], g.rvar, nx == P[0]) && fast2d_col_ok(Ly, split_y, g.cvar) &&
+                ny <= Ly && (P[0] / 2) % fast2d_col_width(Ly, g.cvar) == 0 && !(gen && gen[0] == '1');
+    s->fastrows = s->fast2d || (nz > 1 && fast2d_row_ok(P[0], g.rvar, nx == P[0]) && (nx == P[0] || 2 * nx <= P[0]) &&
                                 !(gen && gen[0] == '1'));
     s->fast3dy = nz > 1 && fast3d_col_ok(P[1], split_y, false) && ny <= Ly && !(gen && gen[0] == '1');
     s->fast3dz = nz > 1 && fast3d_col_ok(P[2], split_z, true) && nz <= Lz && !(gen && gen[0] == '1');
@@ -833,11 +863,14 @@ llg_status llg_eval_heff(llg_solver* s, float* h_out, llg_mem where) {
     if ((rc = ensure_kernel(s)) != LLG_OK) return rc;
     const Phys p = make_phys(s, s->last_dt);
     float* dst = where == LLG_DEVICE ? h_out : s->hbuf;
+    int was = 0;
+    if ((rc = lift_done(s, &was)) != LLG_OK) return rc;
     if ((rc = eval_into(s, dst, p)) != LLG_OK) return rc;
     if (where != LLG_DEVICE)
         HIPCHK(s, hipMemcpyAsync(h_out, s->hbuf, sizeof(float) * 3 * (size_t)s->g.ncells,
                                  hipMemcpyDeviceToHost, s->stream));
-    return sync(s);
+    if ((rc = sync(s)) != LLG_OK) return rc;
+    return restore_done(s, was);
 }
 
 llg_status llg_step(llg_solver* s, llg_method method, double dt, int64_t nsteps) {
@@ -1040,6 +1073,8 @@ llg_status llg_profile_evals(llg_solver* s, int n, double* ms_out, int n_kinds, 
     if ((rc = ensure_kernel(s)) != LLG_OK) return rc;
     const Phys p = make_phys(s, s->last_dt);
     if (!p.demag_on) return fail(s, LLG_E_STATE, "profiling needs the demag term");
+    int was = 0;
+    if ((rc = lift_done(s, &was)) != LLG_OK) return rc;
     std::vector<hipEvent_t> ev(6 * (size_t)n);
     for (auto& e : ev) HIPCHK(s, hipEventCreate(&e));
     for (int i = 0; i < n; ++i) {
@@ -1094,7 +1129,7 @@ llg_status llg_profile_evals(llg_solver* s, int n, double* ms_out, int n_kinds, 
     *total_ms = tot;
     for (auto& e : ev) (void)hipEventDestroy(e);
     s->spec_valid = false;
-    return LLG_OK;
+    return restore_done(s, was);
 }
 
 llg_status llg_autotune(llg_solver* s, int iters, double* ms_out, int n_out, int* choice) {
@@ -1106,8 +1141,10 @@ llg_status llg_autotune(llg_solver* s, int iters, double* ms_out, int n_out, int
     if (!s->fast2d) return fail(s, LLG_E_UNSUPPORTED, "no compiled variants for this geometry");
     const Phys p = make_phys(s, s->last_dt);
     if (!p.demag_on) return fail(s, LLG_E_STATE, "tuning needs the demag term");
+    int was = 0;
+    if ((rc = lift_done(s, &was)) != LLG_OK) return rc;
     const int Px = s->g.Px, L = s->g.Py / 2;
-    const int r0 = fast2d_row_variant(Px), c0 = fast2d_col_variant(L);
+    const int r0 = s->g.rvar, c0 = s->g.cvar;
     double best = 1e300;
     int br = r0, bc = c0;
     hipEvent_t e0, e1;
@@ -1117,7 +1154,11 @@ llg_status llg_autotune(llg_solver* s, int iters, double* ms_out, int n_out, int
         for (int cv = 0; cv < 2; ++cv) {
             const int k = rv * 2 + cv;
             if (ms_out && k < n_out) ms_out[k] = -1.0;
-            if (!fast2d_set_variants(Px, rv, L, cv, s->g.nx == Px) || (Px / 2) % fast2d_col_width(L, cv)) continue;
+            if (!fast2d_row_ok(Px, rv, s->g.nx == Px) || !fast2d_col_ok(L, 1, cv) ||
+                (Px / 2) % fast2d_col_width(L, cv))
+                continue;
+            s->g.rvar = rv;
+            s->g.cvar = cv;
             // one untimed evaluation, then `iters` timed ones (H_eff of the
             // current state, kept on the device)
             for (int it = 0; it <= iters; ++it) {
@@ -1133,7 +1174,13 @@ llg_status llg_autotune(llg_solver* s, int iters, double* ms_out, int n_out, int
                 sa.h_out = s->hbuf;
                 if (row_inv(s, p, sa) != hipSuccess) { rc = LLG_E_DEVICE; break; }
             }
-            if (rc != LLG_OK) { (void)fast2d_set_variants(Px, r0, L, c0, s->g.nx == Px); return fail(s, rc, "tuning launch failed"); }
+            if (rc != LLG_OK) {
+                s->g.rvar = r0;
+                s->g.cvar = c0;
+                invalidate_graphs(s);
+                s->spec_valid = false;
+                return fail(s, rc, "tuning launch failed");
+            }
             HIPCHK(s, hipEventRecord(e1, s->stream));
             HIPCHK(s, hipEventSynchronize(e1));
             float ms = 0.f;
@@ -1145,11 +1192,13 @@ llg_status llg_autotune(llg_solver* s, int iters, double* ms_out, int n_out, int
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    fast2d_set_variants(Px, br, L, bc, s->g.nx == Px);
+    s->g.rvar = br;
+    s->g.cvar = bc;
+    (void)fast2d_set_variants(Px, br, L, bc, s->g.nx == Px);   // default for solvers set up later
     invalidate_graphs(s);
     s->spec_valid = false;
     if (choice) { choice[0] = br; choice[1] = bc; }
-    return LLG_OK;
+    return restore_done(s, was);
 }
 
 llg_status llg_set_variants(llg_solver* s, int row_var, int col_var) {
@@ -1157,10 +1206,28 @@ llg_status llg_set_variants(llg_solver* s, int row_var, int col_var) {
     if (rc != LLG_OK) return rc;
     if (!s->fast2d) return fail(s, LLG_E_UNSUPPORTED, "no compiled variants for this geometry");
     const int Px = s->g.Px, L = s->g.Py / 2;
-    if (!fast2d_set_variants(Px, row_var, L, col_var, s->g.nx == Px) || (Px / 2) % fast2d_col_width(L, col_var))
+    if (!fast2d_row_ok(Px, row_var, s->g.nx == Px) || !fast2d_col_ok(L, 1, col_var) ||
+        (Px / 2) % fast2d_col_width(L, col_var))
         return fail(s, LLG_E_ARG, "no compiled variant (%d, %d) for lengths %d, %d", row_var, col_var, Px, L);
+    s->g.rvar = row_var;
+    s->g.cvar = col_var;
+    (void)fast2d_set_variants(Px, row_var, L, col_var, s->g.nx == Px);   // default for solvers set up later
     invalidate_graphs(s);
     s->spec_valid = false;
+    return LLG_OK;
+}
+
+llg_status llg_variant_shape(int kind, int length, int variant, int* elems, int* classes) {
+    if (!elems || !classes) return LLG_E_ARG;
+    return fast2d_variant_shape(kind, length, variant, elems, classes) ? LLG_OK : LLG_E_ARG;
+}
+
+llg_status llg_get_variants(llg_solver* s, int* row_var, int* col_var) {
+    if (!s || !row_var || !col_var) return LLG_E_ARG;
+    if (!s->have_geom) return fail(s, LLG_E_STATE, "geometry not set");
+    if (!s->fast2d) return fail(s, LLG_E_UNSUPPORTED, "no compiled variants for this geometry");
+    *row_var = s->g.rvar;
+    *col_var = s->g.cvar;
     return LLG_OK;
 }
 

@@ -5,7 +5,7 @@ optionally the per-kernel HBM traffic file that bench.py reports.
 usage: python paper_1102_3069_amd/prof/summarize.py <kernel_stats.csv>
            [fetch.csv write.csv copy_fetch.csv copy_write.csv copy_bytes [traffic.json]]
 
-The copy kernel of copy_probe.py moves copy_bytes per dispatch; the ratio of
+The plain copy of `bench.py --workload copy` moves copy_bytes per dispatch; the ratio of
 that to what its counters read is the scale applied to every kernel.  The
 traffic file records, per kernel name, the scaled bytes read and written per
 dispatch and a hash of the HIP sources the library was built from, so that

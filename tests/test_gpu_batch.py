@@ -136,7 +136,7 @@ def test_full_sweep_creates_and_steps(lib):
 
 
 
-def test_batch_autotune(lib):
+def test_batch_autotune(lib, default_variants):
     """The batch's own autotuner times both compiled variants of every length
     its films use, keeps the faster in the shared table and leaves every
     film's state as it was.  Batches and solvers built afterwards read the
@@ -146,32 +146,98 @@ def test_batch_autotune(lib):
     b = lib.Batch(films)
     ref = b.run(1e-12, 1e-5, 1e-14)
     untuned = [b.get_m(i) for i in range(len(films))]
-    try:
-        ent = b.autotune(3)
-        print(ent, flush=True)
-        assert sorted((e["kind"], e["length"]) for e in ent) == \
-            sorted([("row", 64), ("row", 128), ("row", 192), ("col", 32), ("col", 64), ("col", 96)])
-        for e in ent:
-            usable = [v for v in (0, 1) if e["ms"][v] >= 0]
-            assert usable and all(e["ms"][v] > 0 for v in usable)
-            assert e["variant"] == min(usable, key=lambda v: e["ms"][v])
-        for i in range(len(films)):
-            assert np.array_equal(b.get_m(i), untuned[i])
-        assert [s["steps"] for s in b.run(1e-12, 1e-5, 0.0)] == [s["steps"] for s in ref]   # already there
-        t = lib.Batch(films)
-        st = t.run(1e-12, 1e-5, 1e-14)
-        for i, (prob, m0) in enumerate(films):
-            s = lib.Solver(0)
-            s.set_problem(prob)
-            s.set_m(m0)
-            s.run(1e-12, 1e-5, 1e-14)
-            assert np.array_equal(t.get_m(i), s.get_m())
-            assert st[i]["done"] == 1
-            assert maxrel(t.get_m(i), untuned[i]) <= 1e-4
-    finally:
-        for side in (32, 64, 96):
-            prob, m0 = sweep((side,), 0)[0]
-            s = lib.Solver(0)
-            s.set_problem(prob)
-            s.set_m(m0)
-            s.set_variants(0, 0)
+    ent = b.autotune(3)
+    print(ent, flush=True)
+    assert sorted((e["kind"], e["length"]) for e in ent) == \
+        sorted([("row", 64), ("row", 128), ("row", 192), ("col", 32), ("col", 64), ("col", 96)])
+    for e in ent:
+        usable = [v for v in (0, 1) if e["ms"][v] >= 0]
+        assert usable and all(e["ms"][v] > 0 for v in usable)
+        assert e["variant"] == min(usable, key=lambda v: e["ms"][v])
+    for i in range(len(films)):
+        assert np.array_equal(b.get_m(i), untuned[i])
+    assert [s["steps"] for s in b.run(1e-12, 1e-5, 0.0)] == [s["steps"] for s in ref]   # already there
+    t = lib.Batch(films)
+    st = t.run(1e-12, 1e-5, 1e-14)
+    for i, (prob, m0) in enumerate(films):
+        s = lib.Solver(0)
+        s.set_problem(prob)
+        s.set_m(m0)
+        s.run(1e-12, 1e-5, 1e-14)
+        assert np.array_equal(t.get_m(i), s.get_m())
+        assert st[i]["done"] == 1
+        assert maxrel(t.get_m(i), untuned[i]) <= 1e-4
+
+
+# films whose padded row lengths have a four-class variant 1 (128, 256, 384,
+# 512), two of them square with the single-film padding, three ragged
+# (nx < Px / 2, ny < L)
+FORCED = [((64, 64, 1), 31), ((128, 96, 1), 32), ((150, 30, 1), 33), ((100, 50, 1), 34), ((200, 20, 1), 35)]
+
+
+def test_forced_variants_advance_and_match(lib, default_variants):
+    """A batch whose row lengths are switched from two to four frequency
+    classes (and a column length to its other variant) after creation is
+    advanced itself: every film follows the FP64 oracle, which replays its
+    attempts, to 1e-5, and the square films equal single-film solvers on
+    the same variants bit for bit.  (Launch arguments built for the old row
+    variant would read the spectrum in the wrong column order.)"""
+    films = [workloads.small_problem(n=n, seed=seed, alpha=0.3) for n, seed in FORCED]
+    b = lib.Batch(films)
+    for px in (128, 256, 384, 512):
+        b.set_variant("row", px, 1)
+    b.set_variant("col", 64, 1)
+    with pytest.raises(lib.LLGError) as e:
+        b.set_variant("row", 640, 1)
+    assert e.value.code == lib.LLG_E_ARG
+    st = b.run(2e-12, 1e-5, 1e-14)
+    assert all(s["done"] == 1 for s in st)
+    for i, (prob, m0) in enumerate(films):
+        o = ollg.Solver(prob, m0)
+        o.replay([(dt, ok) for dt, _, ok in b.attempts(i)])
+        e = maxrel(b.get_m(i), o.m)
+        print("forced-variant film", prob["n"], "attempts", len(b.attempts(i)), "m maxrel vs oracle", e, flush=True)
+        assert e <= 1e-5
+    for i, rv, cv in ((0, 1, 1), (1, 1, 0)):
+        prob, m0 = films[i]
+        s = lib.Solver(0)
+        s.set_problem(prob)
+        s.set_variants(rv, cv)
+        s.set_m(m0)
+        s.run(2e-12, 1e-5, 1e-14)
+        assert b.attempts(i) == s.attempts()
+        assert np.array_equal(b.get_m(i), s.get_m()), f"film {i}"
+
+
+def test_batch_autotune_then_advance(lib, default_variants):
+    """The tuned batch object itself keeps integrating correctly: after
+    llg_batch_autotune it is advanced and replayed by the oracle (1e-5),
+    also when the tuner kept four-class rows."""
+    films = [workloads.small_problem(n=n, seed=seed, alpha=0.3) for n, seed in FORCED]
+    b = lib.Batch(films)
+    b.run(1e-12, 1e-5, 1e-14)
+    mid = [b.get_m(i) for i in range(len(films))]
+    seen = [len(b.attempts(i)) for i in range(len(films))]
+    ent = b.autotune(2)
+    print("tuned", ent, flush=True)
+    st = b.run(3e-12, 1e-5, 0.0)
+    assert all(s["done"] == 1 for s in st)
+    for i, (prob, _) in enumerate(films):
+        o = ollg.Solver(prob, mid[i])
+        o.replay([(dt, ok) for dt, _, ok in b.attempts(i)[seen[i]:]])
+        e = maxrel(b.get_m(i), o.m)
+        print("tuned film", prob["n"], "m maxrel vs oracle", e, flush=True)
+        assert e <= 1e-5
+    # the same with the tuner's choices forced the other way round
+    for x in ent:
+        if x["ms"][1 - x["variant"]] >= 0:
+            b.set_variant(x["kind"], x["length"], 1 - x["variant"])
+    mid = [b.get_m(i) for i in range(len(films))]
+    seen = [len(b.attempts(i)) for i in range(len(films))]
+    b.run(5e-12, 1e-5, 0.0)
+    for i, (prob, _) in enumerate(films):
+        o = ollg.Solver(prob, mid[i])
+        o.replay([(dt, ok) for dt, _, ok in b.attempts(i)[seen[i]:]])
+        e = maxrel(b.get_m(i), o.m)
+        print("flipped film", prob["n"], "m maxrel vs oracle", e, flush=True)
+        assert e <= 1e-5

@@ -274,10 +274,14 @@ def test_trained_surrogate_gains(lib):
     then advances a held-out trajectory (past the same burn-in) with
     speculative verification and with the plain solver alone.  Every
     committed state is a plain one and accepted proposals lie within the
-    threshold of their plain segments; at max |dm| <= 1e-2 the speculative
-    run must beat the plain solver's wall time, and at 5e-5, below what the
-    bare coarse step reaches, the network must get far more proposals
-    accepted than the bare step."""
+    threshold of their plain segments.  The two arms, the trained network
+    and the bare coarse step (all weights zero), run on the SAME object
+    (parameters swapped), interleaved per threshold.  At max |dm| <= 1e-2
+    both arms have every proposal accepted and do the same work, so there
+    the speedup over the plain solver is the scheme's (time-parallel
+    verification of coarse-step proposals), not the network's; what the
+    network adds shows at 5e-5, below what the bare coarse step reaches:
+    far more proposals accepted, and a faster run than the bare arm."""
     import torch
     from paper_1102_3069_amd import surrogate_train as tr
     n = 64
@@ -290,8 +294,8 @@ def test_trained_surrogate_gains(lib):
     first, last = np.mean(res["losses"][:20]), np.mean(res["losses"][-20:])
     print(f"loss {first:.3e} -> {last:.3e}; {res['px_per_s']:.3e} px/s", flush=True)
     assert last < first
-    bare = lib.Surrogate(n, n, max_batch=1)
-    bare.set_params([(np.zeros_like(w), np.zeros_like(b)) for w, b in osg.init_params(0)])
+    trained = sur.get_params()
+    zeros = np.zeros_like(trained)
     prob, m0, _ = held_out(n, 1234)
     s = lib.Solver(0)
     s.set_problem(prob)
@@ -309,11 +313,12 @@ def test_trained_surrogate_gains(lib):
     t_plain = time.perf_counter() - t0
     m_plain = s.get_m()
     out = {}
-    for kind, net in (("network", sur), ("bare coarse step", bare)):
-        net.advance(prob, m_start, n_segments=2, window=8, dt=run["dt"])       # warm-up
-        for th in (1e-2, 1e-4, 5e-5, 2e-5):
+    sur.advance(prob, m_start, n_segments=2, window=8, dt=run["dt"])       # warm-up
+    for th in (1e-2, 1e-4, 5e-5, 2e-5):
+        for kind, params in (("network", trained), ("bare coarse step", zeros)):
+            sur.set_params(params)
             t0 = time.perf_counter()
-            m_sur, st = net.advance(prob, m_start, n_segments=nseg, window=8, dt=run["dt"], max_dm=th)
+            m_sur, st = sur.advance(prob, m_start, n_segments=nseg, window=8, dt=run["dt"], max_dm=th)
             t_sur = time.perf_counter() - t0
             dev = float(np.max(np.linalg.norm((m_sur - m_plain).reshape(3, -1), axis=0)))
             acc = st["accepted"] / max(1, st["proposals"])
@@ -324,9 +329,14 @@ def test_trained_surrogate_gains(lib):
             assert st["max_dm_accepted"] <= th
             assert np.allclose(np.linalg.norm(m_sur.reshape(3, -1), axis=0), 1.0, atol=1e-5)
             out[(kind, th)] = (t_plain / t_sur, acc)
-    # what the scheme gains over the plain solver at the 1e-2 bar
-    assert out[("network", 1e-2)][1] >= 0.9
-    assert out[("network", 1e-2)][0] > 1.0
+    # at the 1e-2 bar both arms accept every proposal: the speedup over the
+    # plain solver belongs to the scheme, and the network costs little
+    for kind in ("network", "bare coarse step"):
+        assert out[(kind, 1e-2)][1] >= 0.9
+        assert out[(kind, 1e-2)][0] > 1.0
+    assert out[("network", 1e-2)][0] > 0.8 * out[("bare coarse step", 1e-2)][0]
     # what the network adds to the bare coarse step: at 5e-5 (below the
-    # coarse step's ~1e-4) most of its proposals still pass
+    # coarse step's ~1e-4) most of its proposals still pass, and the run is
+    # faster than the bare arm's
     assert out[("network", 5e-5)][1] >= out[("bare coarse step", 5e-5)][1] + 0.3
+    assert out[("network", 5e-5)][0] > out[("bare coarse step", 5e-5)][0]
