@@ -199,7 +199,13 @@ def test_eval_after_finished_run(lib):
     st = s.run(1e-12, 1e-5, 1e-14)
     assert st["done"] == 1
     h = s.eval_heff()
-    fresh = solver(lib, prob, s.get_m())
+    # the fresh solver takes the final state through set_state, which keeps
+    # m bit for bit (set_m would renormalise it once more)
+    fresh = lib.Solver(0)
+    fresh.set_problem(prob)
+    state, m_fin = s.get_state()
+    fresh.set_state(state, m_fin)
+    assert np.array_equal(fresh.get_m(), s.get_m())
     assert np.array_equal(h, fresh.eval_heff())
     assert s.stats()["done"] == 1
     ref = fields.heff(s.get_m().astype(np.float64), prob)
