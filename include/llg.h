@@ -163,6 +163,22 @@ llg_status llg_get_m(llg_solver *s, float *m, llg_mem where);
  * The thermal term, if enabled, uses the step size of the last llg_step
  * call and the current step counter. */
 llg_status llg_eval_heff(llg_solver *s, float *h_out, llg_mem where);
+/* llg_eval_heff_noalloc: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same evaluation as llg_eval_heff, same kernels and same
+ * result bit for bit, of the field m_dev given by the caller (device memory,
+ * layout above; read only, not checked or renormalised) into h_dev (device,
+ * A/m, same layout).  The solver's own m, spectrum and run state are left as
+ * they are.  The spectrum and a private copy of the device state live in a
+ * static device array of 32 MiB per GPU (held until the process ends), so no
+ * call allocates or frees anything: films up to 1024 x 1024 cells in 2D;
+ * LLG_E_UNSUPPORTED where a geometry's spectra would not fit.  LLG_E_STATE
+ * until the demag kernel spectrum exists (its build allocates: call
+ * llg_eval_heff, llg_step or llg_run once first).  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (several solvers on
+ * different streams or threads) race and must be serialised by the caller.
+ * Returns after the result is in h_dev. */
+llg_status llg_eval_heff_noalloc(llg_solver *s, const float *m_dev, float *h_dev);
 
 /* ---- time integration (Sec. 2.2) --------------------------------------------
  * llg_step: `nsteps` fixed steps of size dt (s) with LLG_EULER, LLG_HEUN,

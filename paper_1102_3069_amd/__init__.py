@@ -101,6 +101,7 @@ _SIGNATURES = {
     "llg_set_m": ([_P, _P, ctypes.c_int], ctypes.c_int),
     "llg_get_m": ([_P, _P, ctypes.c_int], ctypes.c_int),
     "llg_eval_heff": ([_P, _P, ctypes.c_int], ctypes.c_int),
+    "llg_eval_heff_noalloc": ([_P, _P, _P], ctypes.c_int),
     "llg_step": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_int64], ctypes.c_int),
     "llg_run": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                  ctypes.POINTER(Stats)], ctypes.c_int),
@@ -294,6 +295,17 @@ class Solver:
         a = np.empty(self._shape(), dtype=np.float32)
         self._chk(self._lib.llg_eval_heff(self._h, a.ctypes.data_as(_P), LLG_HOST))
         return a
+
+    def eval_heff_noalloc(self, m, out):
+        """llg_eval_heff_noalloc: H_eff of the device field `m` into the
+        device tensor `out` (both torch CUDA float32 tensors of the solver's
+        shape); nothing is allocated by the library."""
+        for t in (m, out):
+            if not (_is_torch(t) and t.is_cuda and t.dtype.is_floating_point and t.element_size() == 4
+                    and t.is_contiguous() and tuple(t.shape) == self._shape()):
+                raise ValueError("m and out must be contiguous float32 CUDA tensors of the solver's shape")
+        self._chk(self._lib.llg_eval_heff_noalloc(self._h, _P(m.data_ptr()), _P(out.data_ptr())))
+        return out
 
     # ---- integration ---------------------------------------------------------
     def step(self, method, dt, nsteps=1):

@@ -15,6 +15,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -37,6 +38,61 @@ struct Graph {
         dt = 0.0;
     }
 };
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Device scratch of llg_eval_heff_noalloc: a private device-state record
+// followed by the spectrum buffers, in one static array that every GPU the
+// library runs on holds from module load to process end.  Host code never
+// passes the array's name to a kernel: it looks up the array's device
+// address once per device (noalloc_scratch_init) and uses that.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kNoAllocBytes = (size_t)32 << 20;   // spectra of films up to 1024 x 1024
+constexpr size_t kNoAllocStateBytes = 256;           // the state record, padded
+static_assert(sizeof(DevState) <= kNoAllocStateBytes, "state record fits its slot");
+
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+char* g_scratch_dev[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// with `device` current: the address of that device's copy of the array
+hipError_t noalloc_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    g_scratch_dev[device] = (char*)ptr;
+    return hipSuccess;
+}
+
+char* noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
+// the scratch state record: the solver's record (time, step counter for the
+// thermal draw) with the done flag, health word and attempt log cleared, so
+// that the evaluation runs whatever the solver's run left and touches none
+// of the solver's own state
+__global__ void noalloc_state_kernel(DevState* __restrict__ dst, const DevState* __restrict__ src) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    DevState h = *src;
+    h.cur = 0;
+    h.done = 0;
+    h.health = 0;
+    h.err_bits = 0u;
+    h.log = nullptr;
+    h.log_cap = 0;
+    *dst = h;
+}
 
 }  // namespace
 
@@ -204,15 +260,27 @@ llg_status ensure_kernel(llg_solver* s) {
     return LLG_OK;
 }
 
+// The buffers an evaluation works in: the spectrum (and, in 3D, the
+// y-transformed spectrum) and the device state the kernels consult.  The
+// solver's own, or those of the no-allocation evaluation.
+struct EvalBufs {
+    float2* S;
+    float2* Sy;
+    DevState* st;
+};
+EvalBufs own_bufs(const llg_solver* s) { return EvalBufs{s->S, s->Sy, s->st}; }
+
 // row passes: packed fast kernels or the generic ones
-hipError_t row_fwd(llg_solver* s, const Phys& p, const FwdArgs& fa) {
-    if (s->fastrows) return launch_row_fwd_fast(s->g, s->twx, s->S, fa, s->st, s->stream);
-    return launch_row_fwd(s->g, p, s->px, s->twx, s->S, fa, s->st, s->stream);
+hipError_t row_fwd(llg_solver* s, const Phys& p, const FwdArgs& fa, const EvalBufs& b) {
+    if (s->fastrows) return launch_row_fwd_fast(s->g, s->twx, b.S, fa, b.st, s->stream);
+    return launch_row_fwd(s->g, p, s->px, s->twx, b.S, fa, b.st, s->stream);
 }
-hipError_t row_inv(llg_solver* s, const Phys& p, const StageArgs& sa) {
-    if (s->fastrows) return launch_row_inv_fast(s->g, p, s->twx, s->S, sa, s->st, s->stream);
-    return launch_row_inv(s->g, p, s->px, s->twx, s->S, sa, s->st, s->stream);
+hipError_t row_inv(llg_solver* s, const Phys& p, const StageArgs& sa, const EvalBufs& b) {
+    if (s->fastrows) return launch_row_inv_fast(s->g, p, s->twx, b.S, sa, b.st, s->stream);
+    return launch_row_inv(s->g, p, s->px, s->twx, b.S, sa, b.st, s->stream);
 }
+hipError_t row_fwd(llg_solver* s, const Phys& p, const FwdArgs& fa) { return row_fwd(s, p, fa, own_bufs(s)); }
+hipError_t row_inv(llg_solver* s, const Phys& p, const StageArgs& sa) { return row_inv(s, p, sa, own_bufs(s)); }
 
 ColArgs col_base(const llg_solver* s) {
     ColArgs a = {};
@@ -221,12 +289,12 @@ ColArgs col_base(const llg_solver* s) {
 }
 
 // the spectral pass(es) between the forward and the inverse x transform
-llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
+llg_status launch_spectral(llg_solver* s, const EvalBufs& b, hipEvent_t* ev_after_y = nullptr) {
     const Grid& g = s->g;
     const long long nkxp = g.nkxp;
     if (two_d(s) && s->fast2d) {
         Col2dArgs c = {};
-        c.S = s->S;
+        c.S = b.S;
         c.K = s->K;
         c.tw = s->twy;
         c.nkx = g.Px / 2;
@@ -237,12 +305,12 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
         c.var = g.cvar;
         c.ny = g.ny;
         c.Py = g.Py;
-        HIPCHK(s, launch_col2d_fast(c, s->st, s->stream));
+        HIPCHK(s, launch_col2d_fast(c, b.st, s->stream));
         return LLG_OK;
     }
     if (two_d(s)) {
         ColArgs a = col_base(s);
-        a.in = s->S; a.out = s->S;
+        a.in = b.S; a.out = b.S;
         a.cs_in = a.cs_out = (long long)g.nrows * nkxp;
         a.os_in = a.os_out = 0;
         a.as_in = a.as_out = nkxp;
@@ -255,7 +323,7 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
         a.Pa = g.Py; a.Po = 1; a.na_c = g.Py / 2 + 1; a.no_c = 1; a.o_split = 0;
         const int sa[6] = {1, 1, 1, -1, 1, -1};
         for (int c = 0; c < 6; ++c) { a.sign_a[c] = sa[c]; a.sign_o[c] = 1; }
-        HIPCHK(s, launch_col(a, s->st, COL_FULL, s->stream));
+        HIPCHK(s, launch_col(a, b.st, COL_FULL, s->stream));
         return LLG_OK;
     }
     // 3D: y forward, z with product, y inverse
@@ -265,20 +333,20 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
     y.P = g.Py; y.split = g.split_y; y.plan = s->py; y.tw = s->twy;
     y.nouter = g.nz;
     ColArgs yf = y;
-    yf.in = s->S; yf.out = s->Sy;
+    yf.in = b.S; yf.out = b.Sy;
     yf.cs_in = (long long)g.nrows * nkxp; yf.os_in = (long long)g.ny * nkxp; yf.as_in = nkxp;
     yf.cs_out = (long long)g.nz * g.Py * nkxp; yf.os_out = (long long)g.Py * nkxp; yf.as_out = nkxp;
     yf.n_in = g.ny; yf.n_out = g.Py;
     if (s->fast3dy) {
         yf.W = fast3d_col_width(g.Py, g.split_y, false);
         yf.ntiles = (g.nkx + yf.W - 1) / yf.W;
-        HIPCHK(s, launch_col3_tiled(yf, COL_FWD, s->st, s->stream));
+        HIPCHK(s, launch_col3_tiled(yf, COL_FWD, b.st, s->stream));
     } else {
-        HIPCHK(s, launch_col(yf, s->st, COL_FWD, s->stream));
+        HIPCHK(s, launch_col(yf, b.st, COL_FWD, s->stream));
     }
     if (ev_after_y) HIPCHK(s, hipEventRecord(ev_after_y[0], s->stream));
     ColArgs z = col_base(s);
-    z.in = s->Sy; z.out = s->Sy;
+    z.in = b.Sy; z.out = b.Sy;
     z.cs_in = z.cs_out = (long long)g.nz * g.Py * nkxp;
     z.os_in = z.os_out = nkxp;
     z.as_in = z.as_out = (long long)g.Py * nkxp;
@@ -295,24 +363,28 @@ llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
     if (s->fast3dz) {
         z.W = fast3d_col_width(g.Pz, g.split_z, true);
         z.ntiles = (g.nkx + z.W - 1) / z.W;
-        HIPCHK(s, launch_col3_tiled(z, COL_FULL, s->st, s->stream));
+        HIPCHK(s, launch_col3_tiled(z, COL_FULL, b.st, s->stream));
     } else {
-        HIPCHK(s, launch_col(z, s->st, COL_FULL, s->stream));
+        HIPCHK(s, launch_col(z, b.st, COL_FULL, s->stream));
     }
     if (ev_after_y) HIPCHK(s, hipEventRecord(ev_after_y[1], s->stream));
     ColArgs yi = y;
-    yi.in = s->Sy; yi.out = s->S;
+    yi.in = b.Sy; yi.out = b.S;
     yi.cs_in = (long long)g.nz * g.Py * nkxp; yi.os_in = (long long)g.Py * nkxp; yi.as_in = nkxp;
     yi.cs_out = (long long)g.nrows * nkxp; yi.os_out = (long long)g.ny * nkxp; yi.as_out = nkxp;
     yi.n_in = g.Py; yi.n_out = g.ny;
     if (s->fast3dy) {
         yi.W = fast3d_col_width(g.Py, g.split_y, false);
         yi.ntiles = (g.nkx + yi.W - 1) / yi.W;
-        HIPCHK(s, launch_col3_tiled(yi, COL_INV, s->st, s->stream));
+        HIPCHK(s, launch_col3_tiled(yi, COL_INV, b.st, s->stream));
     } else {
-        HIPCHK(s, launch_col(yi, s->st, COL_INV, s->stream));
+        HIPCHK(s, launch_col(yi, b.st, COL_INV, s->stream));
     }
     return LLG_OK;
+}
+
+llg_status launch_spectral(llg_solver* s, hipEvent_t* ev_after_y = nullptr) {
+    return launch_spectral(s, own_bufs(s), ev_after_y);
 }
 
 llg_status launch_fwd_plain(llg_solver* s, int sel) {
@@ -594,6 +666,7 @@ llg_status llg_create(int device, void* hip_stream, llg_solver** out) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LLG_E_DEVICE;
     if (device < 0 || device >= ndev) return LLG_E_ARG;
     if (hipSetDevice(device) != hipSuccess) return LLG_E_DEVICE;
+    if (noalloc_scratch_init(device) != hipSuccess) return LLG_E_DEVICE;
     llg_solver* s = new llg_solver();
     s->device = device;
     s->user = (hipStream_t)hip_stream;
@@ -871,6 +944,49 @@ llg_status llg_eval_heff(llg_solver* s, float* h_out, llg_mem where) {
                                  hipMemcpyDeviceToHost, s->stream));
     if ((rc = sync(s)) != LLG_OK) return rc;
     return restore_done(s, was);
+}
+
+llg_status llg_eval_heff_noalloc(llg_solver* s, const float* m_dev, float* h_dev) {
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (!m_dev || !h_dev) return fail(s, LLG_E_ARG, "null m or h");
+    if ((rc = ready(s, false)) != LLG_OK) return rc;
+    const Phys p = make_phys(s, s->last_dt);
+    if (p.demag_on && !s->K_valid)
+        return fail(s, LLG_E_STATE, "demag kernel spectrum not built yet (its build allocates): "
+                                    "call llg_eval_heff, llg_step or llg_run once first");
+    const Grid& g = s->g;
+    const size_t sbytes = (sizeof(float2) * 3 * (size_t)g.nrows * g.nkxp + 255) / 256 * 256;
+    const size_t sybytes = two_d(s) ? 0 : sizeof(float2) * 3 * (size_t)g.nz * g.Py * g.nkxp;
+    const size_t need = kNoAllocStateBytes + sbytes + sybytes;
+    if (need > kNoAllocBytes)
+        return fail(s, LLG_E_UNSUPPORTED, "this geometry needs %zu bytes of scratch, above the %zu-byte "
+                                          "static array of the no-allocation evaluation", need, kNoAllocBytes);
+    char* base = noalloc_scratch(s->device);
+    if (!base) return fail(s, LLG_E_DEVICE, "no scratch address for device %d", s->device);
+    EvalBufs b;
+    b.st = (DevState*)base;
+    b.S = (float2*)(base + kNoAllocStateBytes);
+    b.Sy = two_d(s) ? nullptr : (float2*)(base + kNoAllocStateBytes + sbytes);
+    hipLaunchKernelGGL(noalloc_state_kernel, dim3(1), dim3(64), 0, s->stream, b.st, (const DevState*)s->st);
+    HIPCHK(s, hipGetLastError());
+    if (p.demag_on) {
+        FwdArgs fa = {};
+        fa.m_in = bref(const_cast<float*>(m_dev));
+        fa.combine = 0;
+        fa.m0 = fa.m_in; fa.k1 = fa.m_in; fa.m_out = bref(nullptr);
+        HIPCHK(s, row_fwd(s, make_phys(s, 0.0), fa, b));
+        if ((rc = launch_spectral(s, b)) != LLG_OK) return rc;
+    }
+    StageArgs sa = {};
+    sa.mode = ROW_EVAL;
+    sa.m_in = bref(const_cast<float*>(m_dev));
+    sa.m0 = sa.m_in;
+    sa.m_out = bref(nullptr);
+    sa.k_out = bref(nullptr);
+    sa.h_out = h_dev;
+    HIPCHK(s, row_inv(s, p, sa, b));
+    return sync(s);
 }
 
 llg_status llg_step(llg_solver* s, llg_method method, double dt, int64_t nsteps) {
