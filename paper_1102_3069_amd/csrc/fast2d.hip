@@ -94,12 +94,14 @@ struct RowSplit {
     static_assert(NT <= kRowThreads, "row blocks fit the launch bound");
     static constexpr int SC = LfScratch<LQ>::size;
     using F = LaneFFT<LQ, E2, NQ, float2>;
-    // LDS (bytes): twiddles W^m (m < PX); FFT scratch; the exchange of the
-    // inverse transforms (inverse kernel only); staged m rows (with the y
-    // neighbours), which the inverse kernel overwrites with the new m rows
-    // once every cell has its field; reduction slots
+    // LDS (bytes): twiddles W^m (m < PX); the stage twiddle tables of the
+    // class transforms; FFT scratch; the exchange of the inverse transforms
+    // (inverse kernel only); staged m rows (with the y neighbours), which the
+    // inverse kernel overwrites with the new m rows once every cell has its
+    // field; reduction slots
     static constexpr int O_TW = 0;
-    static constexpr int O_SCR = lds_align(PX * 8);
+    static constexpr int O_TWS = lds_align(PX * 8);
+    static constexpr int O_SCR = lds_align(O_TWS + F::TWS_ALLOC * 8);
     static constexpr int SCR_BYTES = NG * SC * 8;
     static constexpr int O_M = lds_align(O_SCR + SCR_BYTES);   // forward kernel: no exchange
     static constexpr int NR = 2 * RP + 2;
@@ -133,7 +135,7 @@ struct RowSplit {
     // the 3D column passes read them)
     template <int NXM, bool NAT>
     static __device__ __forceinline__ void forward(const Grid& g, float2* __restrict__ S, float2* scr,
-                                                   const float2* tw, const float* nm, int kind, int q,
+                                                   const float2* tw, const float2* tws, const float* nm, int kind, int q,
                                                    int pair, int lg, int gbase, int rb) {
         const int nx = g.nx;
         const int r0 = rb + 2 * pair;
@@ -161,7 +163,7 @@ struct RowSplit {
             z[i] = q ? cmul(acc, tw[n * q]) : acc;
         }
         float2* own = scr + group_of(kind, q, pair) * SC;
-        F::template run<false>(z, own, tw, lg);
+        F::template run<false>(z, own, tws, lg);
         // partners in another class go through LDS (four classes only)
         const float2* pz = nullptr;
         if constexpr (NQ == 4) {
@@ -222,6 +224,7 @@ __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __rest
     constexpr int NXM = R::template nxm<XPER>();
     constexpr int NT = R::NT;
     float2* tw = (float2*)(lds + R::O_TW);
+    float2* tws = (float2*)(lds + R::O_TWS);
     float2* scr = (float2*)(lds + R::O_SCR);
     float* nm = (float*)(lds + R::O_M);
     if (st->done) return;
@@ -232,6 +235,7 @@ __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __rest
     const int gbase = (tid & 63) - lg;
     const int rb = 2 * R::RP * blk;
     for (int m = tid; m < PX; m += NT) tw[m] = twx[m];
+    R::F::fill_tw(tws, twx, tid, NT);
     const int cur = st->cur;
     const float c1 = st->dtau * fa.a1;
     const int cs = g.ncells;
@@ -311,7 +315,7 @@ __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __rest
         }
     }
     __syncthreads();
-    R::template forward<NXM, NAT>(g, S, scr, tw, nm, kind, q, pair, lg, gbase, rb);
+    R::template forward<NXM, NAT>(g, S, scr, tw, tws, nm, kind, q, pair, lg, gbase, rb);
 }
 
 template <int PX, int E2, int NQ, bool XPER, bool NAT>
@@ -411,6 +415,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     constexpr int P = R::P, RP = R::RP, LQ = R::LQ, QC = R::QC, NT = R::NT;
     constexpr int NXM = R::template nxm<XPER>();
     float2* tw = (float2*)(lds + R::O_TW);
+    float2* tws = (float2*)(lds + R::O_TWS);
     float2* scr = (float2*)(lds + R::O_SCR);
     float2* xch = (float2*)(lds + R::O_XCH);
     float* mrow = (float*)(lds + R::O_MI);
@@ -447,6 +452,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     // ---- global reads: twiddles, m rows rb-1 .. rb+2RP (y neighbours wrap
     // on a periodic y axis), this group's class of the spectrum
     for (int m = tid; m < PX; m += NT) tw[m] = twx[m];
+    F::fill_tw(tws, twx, tid, NT);
     // staged row rq holds grid row rb - 1 + rq; NAT (3D): the halo rows serve
     // only as in-plane neighbours, the periodic y wrap and the z neighbours
     // come from global memory
@@ -572,7 +578,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         }
     }
     __syncthreads();   // twiddles and staged rows
-    if (p.demag_on) F::template run<true>(z, scr + gi * R::SC, tw, lg);
+    if (p.demag_on) F::template run<true>(z, scr + gi * R::SC, tws, lg);
     if constexpr (R::XALIAS) __syncthreads();   // every transform has left the scratch
     if (p.demag_on) {
         float2* xo = xch + ((pair * 3 + kind) * NQ + q) * LQ;
@@ -709,7 +715,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             row[x] = mnx[it]; row[NXM + x] = mny[it]; row[2 * NXM + x] = mnz[it];
         }
         __syncthreads();   // new rows complete
-        R::template forward<NXM, NAT>(g, S, scr, tw, nm, kind, q, pair, lg, gbase, rb);
+        R::template forward<NXM, NAT>(g, S, scr, tw, tws, nm, kind, q, pair, lg, gbase, rb);
     }
 }
 
@@ -746,10 +752,11 @@ struct ColSplit {
     static_assert(W >= 1 && NT <= kColThreads, "column blocks fit the launch bound");
     static constexpr int SC = LfScratch<LC>::size;
     using F = LaneFFT<LC, E, NQ, float2>;
-    // LDS (bytes): twiddles, FFT scratch, the spectrum exchange (reused for
-    // the inverse results after a barrier)
+    // LDS (bytes): twiddles, the stage twiddle tables, FFT scratch, the
+    // spectrum exchange (reused for the inverse results after a barrier)
     static constexpr int O_TW = 0;
-    static constexpr int O_SCR = lds_align(PY * 8);
+    static constexpr int O_TWS = lds_align(PY * 8);
+    static constexpr int O_SCR = lds_align(O_TWS + F::TWS_ALLOC * 8);
     static constexpr int O_XCH = lds_align(O_SCR + NG * SC * 8);
     static constexpr int bytes() { return lds_align(O_XCH + NG * LC * 8); }
     static __device__ __forceinline__ int slot(int c, int q, int w) { return (c * NQ + q) * W + w; }
@@ -761,6 +768,7 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     using F = typename CF::F;
     constexpr int P = CF::P, W = CF::W, LC = CF::LC, NT = CF::NT;
     float2* tw = (float2*)(lds + CF::O_TW);
+    float2* tws = (float2*)(lds + CF::O_TWS);
     float2* scr = (float2*)(lds + CF::O_SCR);
     float2* xch = (float2*)(lds + CF::O_XCH);
     if (st->done) return;
@@ -789,6 +797,7 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
         if (NQ == 4 && y + LC < ny) v1[i] = src[(y + LC) << a.tsh];
     }
     for (int m = tid; m < Py; m += NT) tw[m] = a.tw[m];
+    F::fill_tw(tws, a.tw, tid, NT);
     // kernel values at ky = NQ pos + q (mirror compressed along y; xy is
     // odd in ky): diagonal kd, off-diagonal ko (x, y), Nyquist-column kn
     float kd[E], ko[E], kn[E];
@@ -813,7 +822,7 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
         if (NQ == 4) { const float2 t = rot4(v1[i], q); s.x += t.x; s.y += t.y; }
         x[i] = q ? cmul(s, tw[n * q]) : s;
     }
-    F::template run<false>(x, scr + gi * CF::SC, tw, lg);
+    F::template run<false>(x, scr + gi * CF::SC, tws, lg);
     // every class spectrum to LDS
     {
         float2* xo = xch + CF::slot(c, q, w) * LC;
@@ -852,7 +861,7 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
             x[i] = mk2(A.x - B.y, A.y + B.x);
         }
     }
-    F::template run<true>(x, scr + gi * CF::SC, tw, lg);
+    F::template run<true>(x, scr + gi * CF::SC, tws, lg);
     __syncthreads();   // every group has read the exchange
     {
         float2* xo = xch + CF::slot(c, q, w) * LC;

@@ -40,7 +40,8 @@ struct Tile3 {
     // an odd stride spreads the rows of the tile over the banks
     static constexpr int LS = LfScratch<L>::size + 1;
     using F = LaneFFT<L, E, H, float2>;
-    static constexpr int O_X = H * L;           // after the twiddles exp(-2 pi i m / (H L))
+    static constexpr int O_TWS = H * L;         // after the twiddles exp(-2 pi i m / (H L))
+    static constexpr int O_X = O_TWS + F::TWS_ALLOC;   // after the stage twiddle tables
     static constexpr int bytes() { return (O_X + NG * LS) * 8; }
     static __device__ __forceinline__ int line(int c, int w, int h) { return ((c * TW + w) * H + h) * LS; }
 };
@@ -71,6 +72,7 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
     static_assert(MODE != COL_FULL || NC == 3, "the kernel product needs every component");
     extern __shared__ float2 lds[];
     float2* tw = lds;
+    float2* tws = lds + T::O_TWS;
     float2* X = lds + T::O_X;
     if (st->done) return;
     const int tid = threadIdx.x;
@@ -88,6 +90,7 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
     // ---- the tile into the lines: n_in rows (zero beyond) into the h = 0
     // lines, or the H L stored frequencies into their half lines
     for (int m = tid; m < H * L; m += NT) tw[m] = a.tw[m];
+    F::fill_tw(tws, a.tw, tid, NT);
     if (MODE != COL_INV) {
         for (int e = tid; e < NC * L * TW; e += NT) {
             const int w = e % TW, t = e / TW;
@@ -120,7 +123,7 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
             x[i] = h ? cmul(v, tw[n]) : v;
         }
         __syncthreads();   // every half has read its input line
-        F::template run<false>(x, ln, tw, lg);
+        F::template run<false>(x, ln, tws, lg);
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int i = 0; i < E; ++i) ln[lg + P * i] = x[i];
@@ -166,7 +169,7 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
 #pragma unroll
     for (int i = 0; i < E; ++i) x[i] = ln[lg + P * i];
     __builtin_amdgcn_wave_barrier();
-    F::template run<true>(x, ln, tw, lg);
+    F::template run<true>(x, ln, tws, lg);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int i = 0; i < E; ++i) {

@@ -6,13 +6,19 @@
 // divides E): the first stage reads its butterfly inputs straight from the
 // registers, the last one writes its outputs straight back to registers in
 // the same natural layout, and the stages in between exchange through a
-// per-group LDS scratch of L + L/16 elements (padded against bank conflicts).  A group never spans two wavefronts,
+// per-group LDS scratch of L elements.  A group never spans two wavefronts,
 // so no workgroup barrier is needed inside a transform: the lanes of one
 // wavefront issue their LDS operations in program order.
 //
-// Twiddles come from an LDS table tw[m] = exp(-2 pi i m / (L * TM)) that the
-// calling kernel loaded once (TM = 1 or 2 so that one table serves both the
-// half-length transforms of a zero-padded axis and its pre/post twiddles).
+// LDS banks: the scratch index is XOR-swizzled within aligned runs of 32
+// elements (lf_swz), which spreads both the unit-stride reads and the
+// R-strided Stockham stores of a stage over distinct banks; each stage's
+// twiddles sit in a table of their own, ordered (r - 1) * Ns + k, so that
+// the lanes of a wavefront read consecutive (or equal) entries.  The caller
+// fills that table once per workgroup (fill_tw) from the table
+// exp(-2 pi i m / (L * TM)) it already holds (TM = 1 or 2 so that one table
+// serves both the half-length transforms of a zero-padded axis and its
+// pre/post twiddles).
 #pragma once
 
 #include "device_common.hpp"
@@ -89,11 +95,17 @@ constexpr int lf_ns(int L, int E, int s) {
 // shift/mask friendly modulo for the compile-time Ns
 template <int N> __device__ __forceinline__ int cmod(int a) { return a % N; }
 
-// LDS scratch index with one pad element per 16: the Stockham stores of a
-// radix-R stage are R elements apart across lanes, which would otherwise
-// fall into the same few LDS banks.
-__device__ __forceinline__ int lf_pad(int i) { return i + (i >> 4); }
-template <int L> struct LfScratch { static constexpr int size = L + L / 16; };
+// LDS scratch index of element i of a length-L transform: a permutation of
+// 0 .. L-1 that flips the low bits of i (within its aligned run of M + 1
+// elements, M + 1 the largest power of two dividing L, at most 32) by bits
+// 3.. and 7.. of i.  Unit-stride runs and the R-strided runs of the Stockham
+// stores then fall into distinct 8-byte bank pairs.
+template <int L> struct LfSwz {
+    static constexpr int low = L & -L;
+    static constexpr int M = (low < 32 ? low : 32) - 1;
+};
+template <int L> __device__ __forceinline__ int lf_swz(int i) { return i ^ (((i >> 3) ^ (i >> 7)) & LfSwz<L>::M); }
+template <int L> struct LfScratch { static constexpr int size = L; };
 
 template <int L, int E, int TM, typename C>
 struct LaneFFT {
@@ -103,25 +115,59 @@ struct LaneFFT {
     static_assert(L % E == 0 && NS >= 0, "length must factor into radices dividing E");
     static_assert(64 % P == 0, "a lane group must fit one wavefront");
 
+    // twiddle table of stage s >= 1: entry (r - 1) Ns + k = w^(k r TS) of the
+    // caller's table, r = 1 .. R-1, k < Ns
+    static constexpr int tws_count(int s) { return s == 0 ? 0 : (lf_radix(L, E, s) - 1) * lf_ns(L, E, s); }
+    static constexpr int tws_off(int s) {
+        int o = 0;
+        for (int i = 1; i < s; ++i) o += tws_count(i);
+        return o;
+    }
+    static constexpr int TWS = tws_off(NS);                // entries of all stage tables
+    static constexpr int TWS_ALLOC = TWS > 0 ? TWS : 1;    // LDS entries to reserve
+
+    template <int S>
+    static __device__ __forceinline__ void tw_index(int e, int& idx) {
+        if constexpr (S < NS) {
+            constexpr int R = lf_radix(L, E, S), Ns = lf_ns(L, E, S);
+            constexpr int TS = (L / (Ns * R)) * TM, B = tws_off(S), CNT = (R - 1) * Ns;
+            if (e >= B && e < B + CNT) {
+                const int t = e - B;
+                idx = (t % Ns) * (t / Ns + 1) * TS;
+            }
+            tw_index<S + 1>(e, idx);
+        }
+    }
+    // the stage tables from the table full[m] = exp(-2 pi i m / (L TM)),
+    // by threads tid = 0 .. nt-1 of the workgroup (a barrier must follow)
+    template <typename Src>
+    static __device__ __forceinline__ void fill_tw(C* __restrict__ tws, const Src* __restrict__ full, int tid, int nt) {
+        for (int e = tid; e < TWS; e += nt) {
+            int idx = 0;
+            tw_index<1>(e, idx);
+            tws[e] = full[idx];
+        }
+    }
+
     template <int S, bool INV>
-    static __device__ __forceinline__ void stage(C (&x)[E], C* sc, const C* tw, int lg) {
+    static __device__ __forceinline__ void stage(C (&x)[E], C* sc, const C* tws, int lg) {
         constexpr int R = lf_radix(L, E, S);
         constexpr int Ns = lf_ns(L, E, S);
         constexpr int U = E / R;          // butterflies per lane
         constexpr int LR = L / R;
-        constexpr int TS = (L / (Ns * R)) * TM;
+        constexpr int B = tws_off(S);
         constexpr bool FIRST = S == 0, LAST = S == NS - 1;
         C v[U][R];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = lg + P * u;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[u][r] = FIRST ? x[u + r * U] : sc[lf_pad(j + r * LR)];
+            for (int r = 0; r < R; ++r) v[u][r] = FIRST ? x[u + r * U] : sc[lf_swz<L>(j + r * LR)];
             if (Ns > 1) {
                 const int k = cmod<Ns>(j);
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    C w = tw[k * r * TS];
+                    C w = tws[B + (r - 1) * Ns + k];
                     if (INV) w.y = -w.y;
                     v[u][r] = cmul(v[u][r], w);
                 }
@@ -141,24 +187,25 @@ struct LaneFFT {
                 const int k = cmod<Ns>(j);
                 const int d = (j - k) * R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) sc[lf_pad(d + r * Ns)] = v[u][r];
+                for (int r = 0; r < R; ++r) sc[lf_swz<L>(d + r * Ns)] = v[u][r];
             }
             __builtin_amdgcn_wave_barrier();
         }
     }
 
     template <int S, bool INV>
-    static __device__ __forceinline__ void stages(C (&x)[E], C* sc, const C* tw, int lg) {
+    static __device__ __forceinline__ void stages(C (&x)[E], C* sc, const C* tws, int lg) {
         if constexpr (S < NS) {
-            stage<S, INV>(x, sc, tw, lg);
-            stages<S + 1, INV>(x, sc, tw, lg);
+            stage<S, INV>(x, sc, tws, lg);
+            stages<S + 1, INV>(x, sc, tws, lg);
         }
     }
 
-    // unnormalised transform, forward (exp(-i...)) or inverse (exp(+i...))
+    // unnormalised transform, forward (exp(-i...)) or inverse (exp(+i...));
+    // tws: the stage tables (fill_tw)
     template <bool INV>
-    static __device__ __forceinline__ void run(C (&x)[E], C* sc, const C* tw, int lg) {
-        stages<0, INV>(x, sc, tw, lg);
+    static __device__ __forceinline__ void run(C (&x)[E], C* sc, const C* tws, int lg) {
+        stages<0, INV>(x, sc, tws, lg);
     }
 };
 
