@@ -751,12 +751,17 @@ struct ColSplit {
     static constexpr int NT = NG * P;               // threads per block
     static_assert(W >= 1 && NT <= kColThreads, "column blocks fit the launch bound");
     static constexpr int SC = LfScratch<LC>::size;
+    static constexpr int KL = L + 1;                // kernel entries per column (ky = 0 .. L)
     using F = LaneFFT<LC, E, NQ, float2>;
-    // LDS (bytes): twiddles, the stage twiddle tables, FFT scratch, the
-    // spectrum exchange (reused for the inverse results after a barrier)
-    static constexpr int O_TW = 0;
-    static constexpr int O_TWS = lds_align(PY * 8);
-    static constexpr int O_SCR = lds_align(O_TWS + F::TWS_ALLOC * 8);
+    // LDS (bytes): the stage twiddle tables; the block's kernel columns
+    // [w][xx, yy, zz, xy][ky] and the Nyquist column's [xx, yy, zz][ky]
+    // (block 0 only: the packed column); its spectrum columns
+    // [c][w][y] (y < ny); FFT scratch; the spectrum exchange (reused for the
+    // inverse results after a barrier)
+    static constexpr int O_TWS = 0;
+    static constexpr int O_KST = lds_align(F::TWS_ALLOC * 8);
+    static constexpr int O_XST = lds_align(O_KST + (W * 4 + 3) * KL * 4);
+    static constexpr int O_SCR = lds_align(O_XST + 3 * W * L * 8);
     static constexpr int O_XCH = lds_align(O_SCR + NG * SC * 8);
     static constexpr int bytes() { return lds_align(O_XCH + NG * LC * 8); }
     static __device__ __forceinline__ int slot(int c, int q, int w) { return (c * NQ + q) * W + w; }
@@ -766,9 +771,10 @@ template <int L, int E, int NQ>
 __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restrict__ st, int lb, char* lds) {
     using CF = ColSplit<L, E, NQ>;
     using F = typename CF::F;
-    constexpr int P = CF::P, W = CF::W, LC = CF::LC, NT = CF::NT;
-    float2* tw = (float2*)(lds + CF::O_TW);
+    constexpr int P = CF::P, W = CF::W, LC = CF::LC, NT = CF::NT, KL = CF::KL;
     float2* tws = (float2*)(lds + CF::O_TWS);
+    float* kst = (float*)(lds + CF::O_KST);
+    float2* xst = (float2*)(lds + CF::O_XST);
     float2* scr = (float2*)(lds + CF::O_SCR);
     float2* xch = (float2*)(lds + CF::O_XCH);
     if (st->done) return;
@@ -777,50 +783,48 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     const int w = gi % W;
     const int q = (gi / W) % NQ;         // frequency class
     const int c = gi / (NQ * W);         // component
-    const int gbase = (tid & 63) - lg;
     // stored column -> kx: columns are kept in the class order of the rows
-    const int scol = lb * W + w;
     const int kq = a.nkx / a.nq;
-    const int kx = a.nq * (scol % kq) + scol / kq;
+    auto kx_of = [&](int sc) { return a.nq * (sc % kq) + sc / kq; };
+    const int scol = lb * W + w;
     const bool packed = scol == 0;
     const int ny = a.ny, Py = a.Py;
     const int cs = ny * a.nkxp;
-    const int kcs = a.nkx_full * (Py / 2 + 1);
-    // this group's column, zero beyond ny: blocks n + r LC for r < NQ/2
-    float2 v0[E], v1[E];
-    const float2* src = a.S + c * cs + tile_index(0, scol, ny, a.tsh);
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int y = lg + P * i;
-        v0[i] = y < ny ? src[y << a.tsh] : mk2(0.f, 0.f);
-        v1[i] = mk2(0.f, 0.f);
-        if (NQ == 4 && y + LC < ny) v1[i] = src[(y + LC) << a.tsh];
+    const int kcs = a.nkx_full * KL;
+    // ---- global reads, shared by the block through LDS: its W spectrum
+    // columns (the classes of a column read the same values; W consecutive
+    // stored columns are contiguous within a tile row), its kernel columns
+    // (contiguous in ky), the stage twiddles; per lane: the pre/post
+    // twiddles W^(nq) of its elements
+    for (int e = tid; e < 3 * W * ny; e += NT) {
+        const int ww = e % W, t = e / W;
+        const int y = t % ny, cc = t / ny;
+        xst[(cc * W + ww) * L + y] = a.S[cc * cs + tile_index(y, lb * W + ww, ny, a.tsh)];
     }
-    for (int m = tid; m < Py; m += NT) tw[m] = a.tw[m];
+    for (int e = tid; e < W * 4 * KL; e += NT) {
+        const int j = e % KL, t = e / KL;
+        const int comp = t % 4, ww = t / 4;
+        kst[(ww * 4 + comp) * KL + j] = a.K[comp * kcs + kx_of(lb * W + ww) * KL + j];
+    }
+    if (lb == 0)   // the packed column also needs the Nyquist column kx = Px/2
+        for (int e = tid; e < 3 * KL; e += NT) {
+            const int j = e % KL, comp = e / KL;
+            kst[(W * 4 + comp) * KL + j] = a.K[comp * kcs + (a.nkx_full - 1) * KL + j];
+        }
     F::fill_tw(tws, a.tw, tid, NT);
-    // kernel values at ky = NQ pos + q (mirror compressed along y; xy is
-    // odd in ky): diagonal kd, off-diagonal ko (x, y), Nyquist-column kn
-    float kd[E], ko[E], kn[E];
+    float2 twq[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int ky = NQ * (lg + P * i) + q;
-        const bool flip = ky > Py - ky;
-        const int iy = flip ? Py - ky : ky;
-        const int o = kx * (Py / 2 + 1) + iy;
-        kd[i] = a.K[c * kcs + o];
-        ko[i] = 0.f;
-        kn[i] = 0.f;
-        if (c < 2) { const float v = a.K[3 * kcs + o]; ko[i] = flip ? -v : v; }
-        if (packed) kn[i] = a.K[c * kcs + (a.nkx_full - 1) * (Py / 2 + 1) + iy];
-    }
-    __syncthreads();   // twiddle table
+    for (int i = 0; i < E; ++i) twq[i] = q ? a.tw[(lg + P * i) * q] : mk2(1.f, 0.f);
+    __syncthreads();   // staged columns, kernel columns, stage twiddles
+    // this group's column, zero beyond ny: blocks n + r LC for r < NQ/2
+    const float2* col = xst + (c * W + w) * L;
     float2 x[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int n = lg + P * i;
-        float2 s = v0[i];
-        if (NQ == 4) { const float2 t = rot4(v1[i], q); s.x += t.x; s.y += t.y; }
-        x[i] = q ? cmul(s, tw[n * q]) : s;
+        float2 s = n < ny ? col[n] : mk2(0.f, 0.f);
+        if (NQ == 4 && n + LC < ny) { const float2 t = rot4(col[n + LC], q); s.x += t.x; s.y += t.y; }
+        x[i] = q ? cmul(s, twq[i]) : s;
     }
     F::template run<false>(x, scr + gi * CF::SC, tws, lg);
     // every class spectrum to LDS
@@ -830,18 +834,30 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
         for (int i = 0; i < E; ++i) xo[lg + P * i] = x[i];
     }
     __syncthreads();
+    // kernel values at ky = NQ pos + q (mirror compressed along y; xy is
+    // odd in ky)
+    const float* kc = kst + w * 4 * KL;
     if (!packed) {
         // H_x = Kxx M_x + Kxy M_y, H_y = Kxy M_x + Kyy M_y, H_z = Kzz M_z
         if (c < 2) {
             const float2* xp = xch + CF::slot(1 - c, q, w) * LC;
 #pragma unroll
             for (int i = 0; i < E; ++i) {
+                const int ky = NQ * (lg + P * i) + q;
+                const bool flip = ky > Py - ky;
+                const int iy = flip ? Py - ky : ky;
+                const float kd = kc[c * KL + iy], kv = kc[3 * KL + iy];
+                const float ko = flip ? -kv : kv;
                 const float2 o = xp[lg + P * i];
-                x[i] = mk2(kd[i] * x[i].x + ko[i] * o.x, kd[i] * x[i].y + ko[i] * o.y);
+                x[i] = mk2(kd * x[i].x + ko * o.x, kd * x[i].y + ko * o.y);
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < E; ++i) x[i] = mk2(kd[i] * x[i].x, kd[i] * x[i].y);
+            for (int i = 0; i < E; ++i) {
+                const int ky = NQ * (lg + P * i) + q;
+                const float kd = kc[2 * KL + (ky > Py - ky ? Py - ky : ky)];
+                x[i] = mk2(kd * x[i].x, kd * x[i].y);
+            }
         }
     } else {
         // column 0 carries (kx = 0) + i (kx = Px/2): separate with the
@@ -849,15 +865,19 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
         // pack again.  The partner of ky is -ky: class (NQ - q) mod NQ,
         // position (LC - pos) mod LC for q = 0, LC - 1 - pos otherwise.
         const float2* xp = xch + CF::slot(c, (NQ - q) % NQ, w) * LC;
+        const float* kn = kst + W * 4 * KL;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int pos = lg + P * i;
+            const int ky = NQ * pos + q;
+            const int iy = ky > Py - ky ? Py - ky : ky;
             const float2 z = x[i];
             const float2 zp = xp[q == 0 ? (LC - pos) % LC : LC - 1 - pos];
             float2 A = mk2(0.5f * (z.x + zp.x), 0.5f * (z.y - zp.y));
             float2 B = mk2(0.5f * (z.y + zp.y), -0.5f * (z.x - zp.x));
-            A = mk2(kd[i] * A.x, kd[i] * A.y);
-            B = mk2(kn[i] * B.x, kn[i] * B.y);
+            const float kd = kc[c * KL + iy], kv = kn[c * KL + iy];
+            A = mk2(kd * A.x, kd * A.y);
+            B = mk2(kv * B.x, kv * B.y);
             x[i] = mk2(A.x - B.y, A.y + B.x);
         }
     }
@@ -868,7 +888,7 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int n = lg + P * i;
-            xo[n] = q ? cmul(x[i], cconj(tw[n * q])) : x[i];
+            xo[n] = q ? cmul(x[i], cconj(twq[i])) : x[i];
         }
     }
     __syncthreads();
