@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="worker processes of the all-cores CPU-baseline leg (0: every host core, at most 16)")
     ap.add_argument("--no-full-run", action="store_true", help="skip the 1 ns Dormand-Prince run of the film")
+    ap.add_argument("--batch-separate", action="store_true",
+                    help="batch: also time the same films as separate solvers, one after another")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30, help="copy: bytes per copy")
     ap.add_argument("--workload", choices=("film512", "film3d", "batch", "sp2", "surrogate", "table1", "copy"),
                     default="film512",
@@ -259,7 +261,32 @@ def bench_batch(args):
                                   "grouped launches over all films", "cells": int(cells.sum()),
                       "films_done": int(sum(s["done"] for s in st1)),
                       "variants": tuned}}
+    if args.batch_separate:
+        b.close()
+        out["config"]["separate_solvers"] = separate_solvers(llg, films, run, args.steps, wall)
     print(json.dumps(out), flush=True)
+
+
+def separate_solvers(llg, films, run, attempts, batch_wall):
+    """The same films as separate solvers advanced one after another, the
+    same number of attempts each: the cost the grouped launches avoid."""
+    import torch
+    sols = []
+    for p, m0 in films:
+        s = llg.Solver(0)
+        s.set_problem(p)
+        s.set_m(m0)
+        s.run_attempts(run["t_end"], run["tol"], run["dt0"], 10)
+        sols.append(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sols:
+        s.run_attempts(run["t_end"], run["tol"], s.stats()["dt_next"] or run["dt0"], attempts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for s in sols:
+        s.close()
+    return {"ms_per_attempt_all_films": wall * 1e3 / attempts, "slower_than_batch": wall / batch_wall}
 
 
 def bench_film3d(args):

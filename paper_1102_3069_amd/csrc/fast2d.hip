@@ -61,6 +61,20 @@ __device__ __forceinline__ float2 partner_odd(const float2 (&z)[E], int i, int l
 // ---------------------------------------------------------------------------
 constexpr int lds_align(int b) { return (b + 15) / 16 * 16; }
 
+// first row of row block blk.  2D: blocks in row order.  3D (NAT) with whole
+// blocks per z plane: z fastest, so the blocks one XCD runs one after
+// another hold the same y rows of consecutive planes, and the z neighbours
+// a block reads from global memory are the rows its neighbours stage at
+// about the same time (L2 hits instead of a second pass over m)
+template <bool NAT>
+__device__ __forceinline__ int row_block_start(const Grid& g, int blk, int rows_per_block) {
+    if (NAT && g.nz > 1 && g.ny % rows_per_block == 0) {
+        const int z = blk % g.nz, yb = blk / g.nz;
+        return z * g.ny + yb * rows_per_block;
+    }
+    return rows_per_block * blk;
+}
+
 // (row, x) of flat cell index e of rows of length nx, without an integer
 // division: rnx = 1/nx in FP32 gives the row within one, fixed up exactly
 // (e < 2^24)
@@ -233,7 +247,7 @@ __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __rest
     int kind, q, pair;
     R::group(gi, kind, q, pair);
     const int gbase = (tid & 63) - lg;
-    const int rb = 2 * R::RP * blk;
+    const int rb = row_block_start<NAT>(g, blk, 2 * R::RP);
     for (int m = tid; m < PX; m += NT) tw[m] = twx[m];
     R::F::fill_tw(tws, twx, tid, NT);
     const int cur = st->cur;
@@ -427,7 +441,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     int kind, q, pair;
     R::group(gi, kind, q, pair);
     const int gbase = (tid & 63) - lg;
-    const int rb = 2 * RP * blk;                     // first row of the block
+    const int rb = row_block_start<NAT>(g, blk, 2 * RP);   // first row of the block
     const int r0 = rb + 2 * pair;
     const bool v0 = r0 < g.nrows, v1 = r0 + 1 < g.nrows;
     const int cur = st->cur;

@@ -64,6 +64,16 @@ __device__ __forceinline__ void kernel6(const ColArgs& a, int kx, int ka, int ko
     }
 }
 
+// frequency at position j of the order 0, 1, P-1, 2, P-2, ..., so that the
+// two frequencies ko and P - ko that share mirror-compressed kernel rows are
+// adjacent
+__device__ __forceinline__ int mirror_pair_order(int j, int P) {
+    if (j == 0) return 0;
+    const int p = (j + 1) >> 1;
+    if (2 * p == P) return p;
+    return (j & 1) ? p : P - p;
+}
+
 template <int L, int E, int TW, int H, int NC, int MODE>
 __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColArgs a, DevState* __restrict__ st) {
     using T = Tile3<L, E, TW, H, NC>;
@@ -80,8 +90,14 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
     const int per_c = a.nouter * a.ntiles;      // blocks of one component (NC = 1)
     const int c0 = NC == 3 ? 0 : lb / per_c;    // first component of the block
     lb -= c0 * per_c;
-    const int o = lb / a.ntiles;
+    int o = lb / a.ntiles;
     const int tile = lb - o * a.ntiles;
+    if (MODE == COL_FULL && a.nouter == a.Po) {
+        // the product pass over every y frequency: mirror pairs (ko, Po - ko)
+        // one after the other, so the second reads the kernel rows from L2
+        const int ko = mirror_pair_order(o, a.Po);
+        o = a.o_split ? (ko & 1) * (a.Po / 2) + (ko >> 1) : ko;
+    }
     const int kx0 = tile * TW;
     const int Wt = min(TW, a.nkx - kx0);
     const float2* in = a.in + c0 * a.cs_in + o * a.os_in + kx0;
