@@ -114,7 +114,8 @@ const char *llg_last_error(const llg_solver *s);
  * side.  Open axes are zero padded to an FFT length >= 2n made of the
  * factors 2, 3, 5, 7 (Sec. 3.3).  Invalidates m and the demag kernel.
  * LLG_E_UNSUPPORTED if a padded length exceeds the library's limits
- * (x: 2048, y and z: 4096).
+ * (x: 2048, y and z: 4096; x up to 4096 for one-cell-thick films whose
+ * padded y length has a compiled column kernel, e.g. 2048 x 2048).
  */
 llg_status llg_set_geometry(llg_solver *s, int nx, int ny, int nz,
                             int pbc_x, int pbc_y, int pbc_z, int pbc_images);
@@ -320,11 +321,12 @@ llg_status llg_demag_tensor(llg_solver *s, const int32_t *offsets, int64_t count
  * single-film solver (same kernels, same order), so results do not depend
  * on the batch composition.  Each axis of a film is zero padded to the
  * shortest compiled FFT length >= 2 n (x: 64, 128, 192, 256, 384, 512, 768,
- * 1024, 2048; y: twice 32, 64, 96, 128, 192, 256, 384, 512, 1024), which
- * leaves the convolution unchanged (Sec. 3.2 needs only >= 2 n - 1); where
- * that is also the single-film solver's padding (sides 32, 64, 96, 128, 192,
- * 256, 384, 512, 1024) a batched film equals the single-film run bit for
- * bit.  Sides beyond 1024 give LLG_E_UNSUPPORTED.
+ * 1024, 2048, 4096; y: twice 32, 64, 96, 128, 192, 256, 384, 512, 1024,
+ * 2048), which leaves the convolution unchanged (Sec. 3.2 needs only
+ * >= 2 n - 1); where that is also the single-film solver's padding (sides
+ * 32, 64, 96, 128, 192, 256, 384, 512, 1024, 2048) a batched film equals
+ * the single-film run bit for bit.  Sides beyond 2048 give
+ * LLG_E_UNSUPPORTED.
  */
 typedef struct llg_batch llg_batch;
 

@@ -255,7 +255,7 @@ llg_status build_launch_args(llg_batch* b) {
     for (BatchFilm& f : b->films) {
         f.row_blocks = (f.g.nrows + fast2d_row_rows_per_block(f.g.Px, f.g.rvar) - 1) /
                        fast2d_row_rows_per_block(f.g.Px, f.g.rvar);
-        f.col_blocks = (f.g.Px / 2) / fast2d_col_width(f.g.Py / 2, f.g.cvar);
+        f.col_blocks = fast2d_col_blocks(f.g.Py / 2, f.g.cvar, f.g.Px / 2);
     }
     const Tableau t = tab_dp45();
     std::vector<FilmRow> fwd_plain(nf), konly(nf), prep(nf), stage[6];

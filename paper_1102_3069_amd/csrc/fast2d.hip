@@ -16,6 +16,9 @@
 
 #include <atomic>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "cell_physics.hpp"
 #include "internal.hpp"
@@ -113,23 +116,37 @@ struct RowSplit {
     // (inverse kernel only); staged m rows (with the y neighbours), which the
     // inverse kernel overwrites with the new m rows once every cell has its
     // field; reduction slots
+    //
+    // BIG (4096-point rows): there is no room for staged rows beside the
+    // scratch.  The rows the forward transform reads and the new rows the
+    // inverse kernel hands to it alias the scratch (behind a barrier), the
+    // exchange aliases it too, and the inverse kernel reads the stage input
+    // m and its neighbours from global memory instead of staged rows.
+    static constexpr bool BIG = PX >= 4096;
     static constexpr int O_TW = 0;
     static constexpr int O_TWS = lds_align(PX * 8);
     static constexpr int O_SCR = lds_align(O_TWS + F::TWS_ALLOC * 8);
     static constexpr int SCR_BYTES = NG * SC * 8;
-    static constexpr int O_M = lds_align(O_SCR + SCR_BYTES);   // forward kernel: no exchange
+    static constexpr int O_M = BIG ? O_SCR : lds_align(O_SCR + SCR_BYTES);   // forward kernel: no exchange
     static constexpr int NR = 2 * RP + 2;
     // the exchange gets its own region unless that would not fit the LDS
     // (then it aliases the scratch, behind one more barrier)
     static constexpr int SEP_BYTES = lds_align(O_M + NG * LQ * 8) + NR * 3 * PX * 4 + 64;
-    static constexpr bool XALIAS = SEP_BYTES > 160 * 1024;
+    static constexpr bool XALIAS = BIG || SEP_BYTES > 160 * 1024;
     static constexpr int O_XCH = XALIAS ? O_SCR : O_M;
     static_assert(NG * LQ * 8 <= SCR_BYTES, "the exchange fits the scratch");
-    static constexpr int O_MI = XALIAS ? O_M : lds_align(O_M + NG * LQ * 8);
+    static constexpr int O_MI = BIG ? O_SCR : XALIAS ? O_M : lds_align(O_M + NG * LQ * 8);
     template <bool XPER> static constexpr int nxm() { return XPER ? PX : H; }
-    template <bool XPER> static constexpr int fwd_bytes() { return lds_align(O_M + 2 * RP * 3 * nxm<XPER>() * 4); }
+    static constexpr int imax(int a, int b) { return a > b ? a : b; }
+    template <bool XPER> static constexpr int fwd_bytes() {
+        return BIG ? lds_align(O_SCR + imax(SCR_BYTES, 2 * RP * 3 * nxm<XPER>() * 4))
+                   : lds_align(O_M + 2 * RP * 3 * nxm<XPER>() * 4);
+    }
     template <bool XPER> static constexpr int o_nm() { return O_MI; }
-    template <bool XPER> static constexpr int o_wmax() { return lds_align(O_MI + NR * 3 * nxm<XPER>() * 4); }
+    template <bool XPER> static constexpr int o_wmax() {
+        return BIG ? lds_align(O_SCR + imax(SCR_BYTES, 2 * RP * 3 * nxm<XPER>() * 4))
+                   : lds_align(O_MI + NR * 3 * nxm<XPER>() * 4);
+    }
     template <bool XPER> static constexpr int inv_bytes() { return lds_align(o_wmax<XPER>() + 16 * 4); }
 
     // group gi -> (kind, class, pair), the pair fastest: the groups of one
@@ -176,6 +193,7 @@ struct RowSplit {
             }
             z[i] = q ? cmul(acc, tw[n * q]) : acc;
         }
+        if constexpr (BIG) __syncthreads();   // every group has read the rows, which alias the scratch
         float2* own = scr + group_of(kind, q, pair) * SC;
         F::template run<false>(z, own, tws, lg);
         // partners in another class go through LDS (four classes only)
@@ -333,7 +351,7 @@ __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __rest
 }
 
 template <int PX, int E2, int NQ, bool XPER, bool NAT>
-__global__ __launch_bounds__(kRowThreads) void row_fwd_fast(Grid g, const float2* __restrict__ twx,
+__global__ __launch_bounds__((RowSplit<PX, E2, NQ>::NT)) void row_fwd_fast(Grid g, const float2* __restrict__ twx,
                                                             float2* __restrict__ S, FwdArgs fa,
                                                             DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
@@ -426,6 +444,8 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
                                              DevState* __restrict__ st, int blk, char* lds) {
     using R = RowSplit<PX, E2, NQ>;
     using F = typename R::F;
+    constexpr bool BIG = R::BIG;
+    static_assert(!(BIG && NAT), "4096-point rows serve 2D films only");
     constexpr int P = R::P, RP = R::RP, LQ = R::LQ, QC = R::QC, NT = R::NT;
     constexpr int NXM = R::template nxm<XPER>();
     float2* tw = (float2*)(lds + R::O_TW);
@@ -476,7 +496,9 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         if (!NAT && g.pbc[1]) { row = row < 0 ? row + ny : (row >= ny ? row - ny : row); ok = true; }
         return row;
     };
-    if ((nx & 3) == 0 && (cs & 3) == 0) {
+    if (BIG) {
+        // no staged rows: the per-cell work reads m from global memory
+    } else if ((nx & 3) == 0 && (cs & 3) == 0) {
         // 16-byte loads: every (row, component) run of nx floats starts
         // 16-byte aligned
         const int n4 = nx >> 2;
@@ -617,9 +639,19 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         const int r = rb + ri;
         int y, zpl;
         plane_of(ri, y, zpl);
-        const float* rc = mrow + (ri + 1) * 3 * NXM;
-        const float* rm = (ny > 1 && (y > 0 || g.pbc[1])) ? rc - 3 * NXM : nullptr;
-        const float* rp = (ny > 1 && (y < ny - 1 || g.pbc[1])) ? rc + 3 * NXM : nullptr;
+        // the cell's row (component stride cstr) and its y neighbours: staged
+        // rows, or (BIG) the stage input in global memory
+        const int cstr = BIG ? cs : NXM;
+        const float* rc = BIG ? mi + (size_t)r * nx : mrow + (ri + 1) * 3 * NXM;
+        const float* rm = nullptr;
+        const float* rp = nullptr;
+        if (BIG) {
+            if (ny > 1 && y > 0) rm = rc - nx; else if (ny > 1 && g.pbc[1]) rm = rc + (size_t)(ny - 1) * nx;
+            if (ny > 1 && y < ny - 1) rp = rc + nx; else if (ny > 1 && g.pbc[1]) rp = rc - (size_t)(ny - 1) * nx;
+        } else {
+            rm = (ny > 1 && (y > 0 || g.pbc[1])) ? rc - 3 * NXM : nullptr;
+            rp = (ny > 1 && (y < ny - 1 || g.pbc[1])) ? rc + 3 * NXM : nullptr;
+        }
         float hx = 0.f, hy = 0.f, hz = 0.f;
         if (p.demag_on) {
             // x = n + r LQ: sum over the classes of w^{-rq} times the
@@ -646,7 +678,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             exchange_wrap_z(g, p, mi, r, x, y, rc[x], rc[NXM + x], rc[2 * NXM + x], zlo[it], zup[it], zmask[it], hx,
                             hy, hz);
         } else {
-            local_field_lds(g, p, rm, rc, rp, NXM, r, x, step, hx, hy, hz);
+            local_field_lds(g, p, rm, rc, rp, cstr, r, x, step, hx, hy, hz);
         }
         const int qq = r * nx + x;
         if (sa.mode == ROW_EVAL) {
@@ -656,12 +688,12 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             continue;
         }
         float kx, ky, kz;
-        ll_torque(p, rc[x], rc[NXM + x], rc[2 * NXM + x], hx, hy, hz, kx, ky, kz);
+        ll_torque(p, rc[x], rc[cstr + x], rc[2 * cstr + x], hx, hy, hz, kx, ky, kz);
         if (p.stt_on) {
             // D = (j . grad) m from the staged rows: x neighbours in the row,
             // y neighbours in the rows above and below (the cell itself where
             // a free surface has none)
-            const float mx = rc[x], my = rc[NXM + x], mz = rc[2 * NXM + x];
+            const float mx = rc[x], my = rc[cstr + x], mz = rc[2 * cstr + x];
             float Dx = 0.f, Dy = 0.f, Dz = 0.f;
             if (NAT) {
                 stt_gradient(g, p, mi, r, x, mx, my, mz, Dx, Dy, Dz);
@@ -669,15 +701,15 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
                 const int xu = x < nx - 1 ? x + 1 : (g.pbc[0] ? 0 : x);
                 const int xd = x > 0 ? x - 1 : (g.pbc[0] ? nx - 1 : x);
                 Dx += p.cj[0] * (rc[xu] - rc[xd]);
-                Dy += p.cj[0] * (rc[NXM + xu] - rc[NXM + xd]);
-                Dz += p.cj[0] * (rc[2 * NXM + xu] - rc[2 * NXM + xd]);
+                Dy += p.cj[0] * (rc[cstr + xu] - rc[cstr + xd]);
+                Dz += p.cj[0] * (rc[2 * cstr + xu] - rc[2 * cstr + xd]);
             }
             if (!NAT && p.cj[1] != 0.f && ny > 1) {
                 const float* ru = rp ? rp : rc;
                 const float* rd = rm ? rm : rc;
                 Dx += p.cj[1] * (ru[x] - rd[x]);
-                Dy += p.cj[1] * (ru[NXM + x] - rd[NXM + x]);
-                Dz += p.cj[1] * (ru[2 * NXM + x] - rd[2 * NXM + x]);
+                Dy += p.cj[1] * (ru[cstr + x] - rd[cstr + x]);
+                Dz += p.cj[1] * (ru[2 * cstr + x] - rd[2 * cstr + x]);
             }
             stt_torque(p, mx, my, mz, Dx, Dy, Dz, kx, ky, kz);
         }
@@ -734,7 +766,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
 }
 
 template <int PX, int E2, int NQ, bool XPER, bool NAT>
-__global__ __launch_bounds__(kRowThreads) void row_inv_fast(Grid g, Phys p, const float2* __restrict__ twx,
+__global__ __launch_bounds__((RowSplit<PX, E2, NQ>::NT)) void row_inv_fast(Grid g, Phys p, const float2* __restrict__ twx,
                                                             float2* __restrict__ S, StageArgs sa,
                                                             DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
@@ -761,24 +793,41 @@ struct ColSplit {
     static constexpr int LC = PY / NQ;              // length of a class transform
     static constexpr int P = LC / E;                // lanes per class transform
     static constexpr int W = 64 / P;                // columns per block
-    static constexpr int NG = 3 * NQ * W;           // lane groups per block
-    static constexpr int NT = NG * P;               // threads per block
-    static_assert(W >= 1 && NT <= kColThreads, "column blocks fit the launch bound");
     static constexpr int SC = LfScratch<LC>::size;
     static constexpr int KL = L + 1;                // kernel entries per column (ky = 0 .. L)
+    // BIG (half lengths of 2048: 16 or more elements per lane, one column
+    // per wavefront group): the three components of a column do not share a
+    // block.  A block holds either the x and y components of one column
+    // (they meet in the xy product) or the z components of two columns, so
+    // that blocks stay at 2 NQ wavefronts and a wavefront may use 256
+    // registers.  No block-shared copies of the spectrum and kernel columns
+    // (every lane reads its own values from global memory), and the spectrum
+    // exchange aliases the FFT scratch behind extra barriers.
+    static constexpr bool BIG = L >= 2048;
+    static_assert(!BIG || W == 1, "one column per lane group on the longest columns");
+    static constexpr int NG = BIG ? 2 * NQ : 3 * NQ * W;   // lane groups per block
+    static constexpr int NT = NG * P;               // threads per block
+    static_assert(W >= 1 && NT <= kColThreads, "column blocks fit the launch bound");
     using F = LaneFFT<LC, E, NQ, float2>;
+    static_assert(SC >= LC, "the exchange fits the scratch");
+    // blocks of a launch over nkx stored columns
+    static constexpr int blocks(int nkx) { return BIG ? nkx + nkx / 2 : nkx / W; }
     // LDS (bytes): the stage twiddle tables; the block's kernel columns
     // [w][xx, yy, zz, xy][ky] and the Nyquist column's [xx, yy, zz][ky]
-    // (block 0 only: the packed column); its spectrum columns
-    // [c][w][y] (y < ny); FFT scratch; the spectrum exchange (reused for the
-    // inverse results after a barrier)
+    // (block 0 only: the packed column); its spectrum columns [c][w][y]
+    // (y < ny); FFT scratch; the spectrum exchange (reused for the inverse
+    // results after a barrier)
     static constexpr int O_TWS = 0;
     static constexpr int O_KST = lds_align(F::TWS_ALLOC * 8);
-    static constexpr int O_XST = lds_align(O_KST + (W * 4 + 3) * KL * 4);
-    static constexpr int O_SCR = lds_align(O_XST + 3 * W * L * 8);
-    static constexpr int O_XCH = lds_align(O_SCR + NG * SC * 8);
-    static constexpr int bytes() { return lds_align(O_XCH + NG * LC * 8); }
-    static __device__ __forceinline__ int slot(int c, int q, int w) { return (c * NQ + q) * W + w; }
+    static constexpr int O_XST = BIG ? O_KST : lds_align(O_KST + (W * 4 + 3) * KL * 4);
+    static constexpr int O_SCR = BIG ? O_KST : lds_align(O_XST + 3 * W * L * 8);
+    static constexpr int O_XCH = BIG ? O_SCR : lds_align(O_SCR + NG * SC * 8);
+    static constexpr int bytes() { return BIG ? lds_align(O_SCR + NG * SC * 8) : lds_align(O_XCH + NG * LC * 8); }
+    // exchange slot of group (component c, class q, column w); BIG blocks
+    // number their own groups (component or column, then class)
+    static __device__ __forceinline__ int slot(int c, int q, int w) {
+        return BIG ? ((c < 2 ? c : w) * NQ + q) : (c * NQ + q) * W + w;
+    }
 };
 
 template <int L, int E, int NQ>
@@ -786,6 +835,7 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     using CF = ColSplit<L, E, NQ>;
     using F = typename CF::F;
     constexpr int P = CF::P, W = CF::W, LC = CF::LC, NT = CF::NT, KL = CF::KL;
+    constexpr bool BIG = CF::BIG;
     float2* tws = (float2*)(lds + CF::O_TWS);
     float* kst = (float*)(lds + CF::O_KST);
     float2* xst = (float2*)(lds + CF::O_XST);
@@ -794,53 +844,111 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     if (st->done) return;
     const int tid = threadIdx.x;
     const int gi = tid / P, lg = tid % P;
-    const int w = gi % W;
-    const int q = (gi / W) % NQ;         // frequency class
-    const int c = gi / (NQ * W);         // component
+    int w, q, c, scol;
+    if (BIG) {
+        // blocks [0, nkx): x and y of column lb; then z of columns 2j, 2j+1
+        q = gi % NQ;
+        const bool zb = lb >= a.nkx;
+        c = zb ? 2 : gi / NQ;
+        w = zb ? gi / NQ : 0;
+        scol = zb ? 2 * (lb - a.nkx) + w : lb;
+    } else {
+        w = gi % W;
+        q = (gi / W) % NQ;               // frequency class
+        c = gi / (NQ * W);               // component
+        scol = lb * W + w;
+    }
     // stored column -> kx: columns are kept in the class order of the rows
     const int kq = a.nkx / a.nq;
     auto kx_of = [&](int sc) { return a.nq * (sc % kq) + sc / kq; };
-    const int scol = lb * W + w;
+    const int kx = kx_of(scol);
     const bool packed = scol == 0;
     const int ny = a.ny, Py = a.Py;
     const int cs = ny * a.nkxp;
     const int kcs = a.nkx_full * KL;
-    // ---- global reads, shared by the block through LDS: its W spectrum
-    // columns (the classes of a column read the same values; W consecutive
-    // stored columns are contiguous within a tile row), its kernel columns
-    // (contiguous in ky), the stage twiddles; per lane: the pre/post
-    // twiddles W^(nq) of its elements
-    for (int e = tid; e < 3 * W * ny; e += NT) {
-        const int ww = e % W, t = e / W;
-        const int y = t % ny, cc = t / ny;
-        xst[(cc * W + ww) * L + y] = a.S[cc * cs + tile_index(y, lb * W + ww, ny, a.tsh)];
-    }
-    for (int e = tid; e < W * 4 * KL; e += NT) {
-        const int j = e % KL, t = e / KL;
-        const int comp = t % 4, ww = t / 4;
-        kst[(ww * 4 + comp) * KL + j] = a.K[comp * kcs + kx_of(lb * W + ww) * KL + j];
-    }
-    if (lb == 0)   // the packed column also needs the Nyquist column kx = Px/2
-        for (int e = tid; e < 3 * KL; e += NT) {
-            const int j = e % KL, comp = e / KL;
-            kst[(W * 4 + comp) * KL + j] = a.K[comp * kcs + (a.nkx_full - 1) * KL + j];
-        }
-    F::fill_tw(tws, a.tw, tid, NT);
-    float2 twq[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) twq[i] = q ? a.tw[(lg + P * i) * q] : mk2(1.f, 0.f);
-    __syncthreads();   // staged columns, kernel columns, stage twiddles
-    // this group's column, zero beyond ny: blocks n + r LC for r < NQ/2
-    const float2* col = xst + (c * W + w) * L;
+    // kernel values at ky = NQ pos + q (mirror compressed along y; xy is
+    // odd in ky): diagonal kd, off-diagonal ko (x, y), Nyquist column kn
+    float kd[E], ko[E], kn[E];
     float2 x[E];
+    const float2* src = a.S + c * cs + tile_index(0, scol, ny, a.tsh);
+    if constexpr (BIG) {
+        // ---- global reads, per lane: this group's column (zero beyond ny;
+        // blocks n + r LC for r < NQ/2) and its pre-twiddles, combined into
+        // the class input as they arrive; the kernel values follow the
+        // forward transform (fewer live registers through it)
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int n = lg + P * i;
-        float2 s = n < ny ? col[n] : mk2(0.f, 0.f);
-        if (NQ == 4 && n + LC < ny) { const float2 t = rot4(col[n + LC], q); s.x += t.x; s.y += t.y; }
-        x[i] = q ? cmul(s, twq[i]) : s;
+        for (int i = 0; i < E; ++i) {
+            const int y = lg + P * i;
+            float2 v = y < ny ? src[y << a.tsh] : mk2(0.f, 0.f);
+            if (NQ == 4 && y + LC < ny) { const float2 t = rot4(src[(y + LC) << a.tsh], q); v.x += t.x; v.y += t.y; }
+            x[i] = q ? cmul(v, a.tw[y * q]) : v;
+        }
+    } else {
+        // ---- global reads, shared by the block through LDS: its W spectrum
+        // columns (the classes of a column read the same values; W
+        // consecutive stored columns are contiguous within a tile row), its
+        // kernel columns (contiguous in ky)
+        for (int e = tid; e < 3 * W * ny; e += NT) {
+            const int ww = e % W, t = e / W;
+            const int y = t % ny, cc = t / ny;
+            xst[(cc * W + ww) * L + y] = a.S[cc * cs + tile_index(y, lb * W + ww, ny, a.tsh)];
+        }
+        for (int e = tid; e < W * 4 * KL; e += NT) {
+            const int j = e % KL, t = e / KL;
+            const int comp = t % 4, ww = t / 4;
+            kst[(ww * 4 + comp) * KL + j] = a.K[comp * kcs + kx_of(lb * W + ww) * KL + j];
+        }
+        if (lb == 0)   // the packed column also needs the Nyquist column kx = Px/2
+            for (int e = tid; e < 3 * KL; e += NT) {
+                const int j = e % KL, comp = e / KL;
+                kst[(W * 4 + comp) * KL + j] = a.K[comp * kcs + (a.nkx_full - 1) * KL + j];
+            }
+    }
+    // the stage twiddles; per lane (not BIG), the pre/post twiddles W^(nq)
+    // of its elements
+    F::fill_tw(tws, a.tw, tid, NT);
+    float2 twq[BIG ? 1 : E];
+    if constexpr (!BIG) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) twq[i] = q ? a.tw[(lg + P * i) * q] : mk2(1.f, 0.f);
+    }
+    __syncthreads();   // stage twiddles (and the staged columns)
+    if constexpr (!BIG) {
+        const float2* col = xst + (c * W + w) * L;
+        const float* kc = kst + w * 4 * KL;
+        const float* kl = kst + W * 4 * KL;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int n = lg + P * i;
+            float2 v = n < ny ? col[n] : mk2(0.f, 0.f);
+            if (NQ == 4 && n + LC < ny) { const float2 t = rot4(col[n + LC], q); v.x += t.x; v.y += t.y; }
+            x[i] = q ? cmul(v, twq[i]) : v;
+            const int ky = NQ * n + q;
+            const bool flip = ky > Py - ky;
+            const int iy = flip ? Py - ky : ky;
+            kd[i] = kc[c * KL + iy];
+            ko[i] = 0.f;
+            kn[i] = 0.f;
+            if (c < 2) { const float kv = kc[3 * KL + iy]; ko[i] = flip ? -kv : kv; }
+            if (packed) kn[i] = kl[c * KL + iy];
+        }
     }
     F::template run<false>(x, scr + gi * CF::SC, tws, lg);
+    if constexpr (BIG) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int ky = NQ * (lg + P * i) + q;
+            const bool flip = ky > Py - ky;
+            const int iy = flip ? Py - ky : ky;
+            const int o = kx * KL + iy;
+            kd[i] = a.K[c * kcs + o];
+            ko[i] = 0.f;
+            kn[i] = 0.f;
+            if (c < 2) { const float kv = a.K[3 * kcs + o]; ko[i] = flip ? -kv : kv; }
+            if (packed) kn[i] = a.K[c * kcs + (a.nkx_full - 1) * KL + iy];
+        }
+        __syncthreads();   // every transform has left the scratch (the exchange aliases it)
+    }
     // every class spectrum to LDS
     {
         float2* xo = xch + CF::slot(c, q, w) * LC;
@@ -848,30 +956,18 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
         for (int i = 0; i < E; ++i) xo[lg + P * i] = x[i];
     }
     __syncthreads();
-    // kernel values at ky = NQ pos + q (mirror compressed along y; xy is
-    // odd in ky)
-    const float* kc = kst + w * 4 * KL;
     if (!packed) {
         // H_x = Kxx M_x + Kxy M_y, H_y = Kxy M_x + Kyy M_y, H_z = Kzz M_z
         if (c < 2) {
             const float2* xp = xch + CF::slot(1 - c, q, w) * LC;
 #pragma unroll
             for (int i = 0; i < E; ++i) {
-                const int ky = NQ * (lg + P * i) + q;
-                const bool flip = ky > Py - ky;
-                const int iy = flip ? Py - ky : ky;
-                const float kd = kc[c * KL + iy], kv = kc[3 * KL + iy];
-                const float ko = flip ? -kv : kv;
                 const float2 o = xp[lg + P * i];
-                x[i] = mk2(kd * x[i].x + ko * o.x, kd * x[i].y + ko * o.y);
+                x[i] = mk2(kd[i] * x[i].x + ko[i] * o.x, kd[i] * x[i].y + ko[i] * o.y);
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const int ky = NQ * (lg + P * i) + q;
-                const float kd = kc[2 * KL + (ky > Py - ky ? Py - ky : ky)];
-                x[i] = mk2(kd * x[i].x, kd * x[i].y);
-            }
+            for (int i = 0; i < E; ++i) x[i] = mk2(kd[i] * x[i].x, kd[i] * x[i].y);
         }
     } else {
         // column 0 carries (kx = 0) + i (kx = Px/2): separate with the
@@ -879,30 +975,28 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
         // pack again.  The partner of ky is -ky: class (NQ - q) mod NQ,
         // position (LC - pos) mod LC for q = 0, LC - 1 - pos otherwise.
         const float2* xp = xch + CF::slot(c, (NQ - q) % NQ, w) * LC;
-        const float* kn = kst + W * 4 * KL;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int pos = lg + P * i;
-            const int ky = NQ * pos + q;
-            const int iy = ky > Py - ky ? Py - ky : ky;
             const float2 z = x[i];
             const float2 zp = xp[q == 0 ? (LC - pos) % LC : LC - 1 - pos];
             float2 A = mk2(0.5f * (z.x + zp.x), 0.5f * (z.y - zp.y));
             float2 B = mk2(0.5f * (z.y + zp.y), -0.5f * (z.x - zp.x));
-            const float kd = kc[c * KL + iy], kv = kn[c * KL + iy];
-            A = mk2(kd * A.x, kd * A.y);
-            B = mk2(kv * B.x, kv * B.y);
+            A = mk2(kd[i] * A.x, kd[i] * A.y);
+            B = mk2(kn[i] * B.x, kn[i] * B.y);
             x[i] = mk2(A.x - B.y, A.y + B.x);
         }
     }
+    if constexpr (BIG) __syncthreads();   // every group has read the exchange before the scratch is reused
     F::template run<true>(x, scr + gi * CF::SC, tws, lg);
-    __syncthreads();   // every group has read the exchange
+    __syncthreads();   // every group has read the exchange (and left the scratch)
     {
         float2* xo = xch + CF::slot(c, q, w) * LC;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int n = lg + P * i;
-            xo[n] = q ? cmul(x[i], cconj(twq[i])) : x[i];
+            const float2 t = BIG ? (q ? a.tw[n * q] : mk2(1.f, 0.f)) : twq[BIG ? 0 : i];
+            xo[n] = q ? cmul(x[i], cconj(t)) : x[i];
         }
     }
     __syncthreads();
@@ -927,7 +1021,7 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
 }
 
 template <int L, int E, int NQ>
-__global__ __launch_bounds__(kColThreads) void col2d_fast(Col2dArgs a, DevState* __restrict__ st) {
+__global__ __launch_bounds__((ColSplit<L, E, NQ>::NT)) void col2d_fast(Col2dArgs a, DevState* __restrict__ st) {
     extern __shared__ char dyn_lds[];
     col2d_body<L, E, NQ>(a, st, xcd_remap_blocks(blockIdx.x, gridDim.x), dyn_lds);
 }
@@ -942,18 +1036,18 @@ __global__ __launch_bounds__(kColThreads) void col2d_fast(Col2dArgs a, DevState*
 #define ROW_VARIANTS(X) X(64, 4, 2, 0) X(64, 8, 2, 1) X(128, 4, 2, 0) X(128, 4, 4, 1) X(192, 12, 2, 0)    \
     X(192, 6, 2, 1) X(256, 4, 2, 0) X(256, 4, 4, 1) X(384, 12, 2, 0) X(384, 6, 4, 1) X(512, 4, 2, 0)    \
     X(512, 4, 4, 1) X(768, 12, 2, 0) X(768, 6, 4, 1) X(1024, 8, 2, 0) X(1024, 4, 4, 1) X(2048, 8, 4, 0)  \
-    X(2048, 16, 2, 1)
+    X(2048, 16, 2, 1) X(4096, 16, 4, 0) X(4096, 32, 2, 1)
 // columns: (L = Py/2, elements per lane, frequency classes, variant)
 #define COL_VARIANTS(X) X(32, 4, 2, 0) X(32, 8, 2, 1) X(64, 4, 2, 0) X(64, 4, 4, 1) X(96, 12, 2, 0)        \
     X(96, 6, 2, 1) X(128, 4, 2, 0) X(128, 4, 4, 1) X(192, 12, 2, 0) X(192, 6, 4, 1) X(256, 4, 2, 0)       \
     X(256, 4, 4, 1) X(384, 12, 2, 0) X(384, 6, 4, 1) X(512, 8, 2, 0) X(512, 4, 4, 1) X(1024, 16, 2, 0)    \
-    X(1024, 8, 4, 1)
+    X(1024, 8, 4, 1) X(2048, 16, 4, 0) X(2048, 32, 2, 1)
 
 // grouped launches: one launch runs a pass for all films of one length
 // class (same compiled variant); block b works on film map[b].x, local
 // block map[b].y of that film
 template <int PX, int E2, int NQ>
-__global__ __launch_bounds__(kRowThreads) void row_fwd_group(const FilmRow* __restrict__ films,
+__global__ __launch_bounds__((RowSplit<PX, E2, NQ>::NT)) void row_fwd_group(const FilmRow* __restrict__ films,
                                                              const int2* __restrict__ map) {
     extern __shared__ char dyn_lds[];
     const int2 m = map[blockIdx.x];
@@ -962,7 +1056,7 @@ __global__ __launch_bounds__(kRowThreads) void row_fwd_group(const FilmRow* __re
 }
 
 template <int PX, int E2, int NQ>
-__global__ __launch_bounds__(kRowThreads) void row_inv_group(const FilmRow* __restrict__ films,
+__global__ __launch_bounds__((RowSplit<PX, E2, NQ>::NT)) void row_inv_group(const FilmRow* __restrict__ films,
                                                              const int2* __restrict__ map) {
     extern __shared__ char dyn_lds[];
     const int2 m = map[blockIdx.x];
@@ -971,7 +1065,7 @@ __global__ __launch_bounds__(kRowThreads) void row_inv_group(const FilmRow* __re
 }
 
 template <int L, int E, int NQ>
-__global__ __launch_bounds__(kColThreads) void col_group(const FilmCol* __restrict__ films,
+__global__ __launch_bounds__((ColSplit<L, E, NQ>::NT)) void col_group(const FilmCol* __restrict__ films,
                                                          const int2* __restrict__ map) {
     extern __shared__ char dyn_lds[];
     const int2 m = map[blockIdx.x];
@@ -982,19 +1076,12 @@ __global__ __launch_bounds__(kColThreads) void col_group(const FilmCol* __restri
 // LDS of one workgroup on gfx950
 constexpr int kMaxLds = 160 * 1024;
 
-// kernels whose dynamic LDS may exceed 64 KB need the limit raised once;
-// sizes beyond the hardware are refused before any runtime call
-static hipError_t allow_lds(const void* kernel, int bytes) {
-    if (bytes > kMaxLds) return hipErrorInvalidValue;
-    if (bytes <= 65536) return hipSuccess;
-    const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) (void)hipGetLastError();   // leave no error behind for later calls
-    return e;
-}
+// kernels whose dynamic LDS may exceed 64 KB need the limit raised once
+static hipError_t allow_lds(const void* kernel, int bytes) { return raise_lds_limit(kernel, bytes); }
 
-// the variant table: lengths up to 2048 in steps of 32
-std::atomic<int> g_row_var[65], g_col_var[65];
-int slot(int len) { return (len % 32 == 0 && len >= 32 && len <= 2048) ? len / 32 : 0; }
+// the variant table: lengths up to 4096 in steps of 32
+std::atomic<int> g_row_var[129], g_col_var[129];
+int slot(int len) { return (len % 32 == 0 && len >= 32 && len <= 4096) ? len / 32 : 0; }
 
 }  // namespace
 
@@ -1095,6 +1182,31 @@ hipError_t launch_row_inv_t(const Grid& g, const Phys& p, const float2* twx, flo
     return hipGetLastError();
 }
 
+// one compiled variant, packed 2D (nat false) or natural 3D layout; the
+// 4096-point rows serve 2D films only
+template <int PX, int E, int NQ>
+hipError_t launch_row_fwd_v(const Grid& g, const float2* twx, float2* S, const FwdArgs& fa, DevState* st,
+                            hipStream_t s, bool nat) {
+    if constexpr (RowSplit<PX, E, NQ>::BIG) {
+        if (nat) return hipErrorInvalidValue;
+        return launch_row_fwd_t<PX, E, NQ, false>(g, twx, S, fa, st, s);
+    } else {
+        return nat ? launch_row_fwd_t<PX, E, NQ, true>(g, twx, S, fa, st, s)
+                   : launch_row_fwd_t<PX, E, NQ, false>(g, twx, S, fa, st, s);
+    }
+}
+template <int PX, int E, int NQ>
+hipError_t launch_row_inv_v(const Grid& g, const Phys& p, const float2* twx, float2* S, const StageArgs& sa,
+                            DevState* st, hipStream_t s, bool nat) {
+    if constexpr (RowSplit<PX, E, NQ>::BIG) {
+        if (nat) return hipErrorInvalidValue;
+        return launch_row_inv_t<PX, E, NQ, false>(g, p, twx, S, sa, st, s);
+    } else {
+        return nat ? launch_row_inv_t<PX, E, NQ, true>(g, p, twx, S, sa, st, s)
+                   : launch_row_inv_t<PX, E, NQ, false>(g, p, twx, S, sa, st, s);
+    }
+}
+
 // 2D (nz = 1): the packed, tiled spectrum of the column kernel; 3D: the
 // natural layout [c][row][nkxp] of the 3D column passes
 hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, const FwdArgs& fa,
@@ -1103,10 +1215,8 @@ hipError_t launch_row_fwd_fast(const Grid& g, const float2* twx, float2* S, cons
     const bool nat = g.nz > 1;
     if (nat && (g.nkxp < g.Px / 2 + 1 || g.nkx != g.Px / 2 + 1)) return hipErrorInvalidValue;
     const int var = g.rvar;
-#define CASE(PX, E, NQ, V)                                                                \
-    if (g.Px == PX && var == V)                                                           \
-        return nat ? launch_row_fwd_t<PX, E, NQ, true>(g, twx, S, fa, st, s)              \
-                   : launch_row_fwd_t<PX, E, NQ, false>(g, twx, S, fa, st, s);
+#define CASE(PX, E, NQ, V) \
+    if (g.Px == PX && var == V) return launch_row_fwd_v<PX, E, NQ>(g, twx, S, fa, st, s, nat);
     ROW_VARIANTS(CASE)
 #undef CASE
     return hipErrorInvalidValue;
@@ -1120,10 +1230,8 @@ hipError_t launch_row_inv_fast(const Grid& g, const Phys& p, const float2* twx, 
     const bool nat = g.nz > 1;
     if (nat && (g.nkxp < g.Px / 2 + 1 || g.nkx != g.Px / 2 + 1)) return hipErrorInvalidValue;
     const int var = g.rvar;
-#define CASE(PX, E, NQ, V)                                                                \
-    if (g.Px == PX && var == V)                                                           \
-        return nat ? launch_row_inv_t<PX, E, NQ, true>(g, p, twx, S, sa, st, s)           \
-                   : launch_row_inv_t<PX, E, NQ, false>(g, p, twx, S, sa, st, s);
+#define CASE(PX, E, NQ, V) \
+    if (g.Px == PX && var == V) return launch_row_inv_v<PX, E, NQ>(g, p, twx, S, sa, st, s, nat);
     ROW_VARIANTS(CASE)
 #undef CASE
     return hipErrorInvalidValue;
@@ -1140,7 +1248,7 @@ hipError_t launch_col2d_fast(const Col2dArgs& a, DevState* st, hipStream_t s) {
         if (a.nkx % CF::W) return hipErrorInvalidValue;                                   \
         hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&col2d_fast<LL, E, NQ>), CF::bytes()); \
         if (e_ != hipSuccess) return e_;                                                  \
-        hipLaunchKernelGGL((col2d_fast<LL, E, NQ>), dim3(a.nkx / CF::W), dim3(CF::NT), CF::bytes(), s, a, st); \
+        hipLaunchKernelGGL((col2d_fast<LL, E, NQ>), dim3(CF::blocks(a.nkx)), dim3(CF::NT), CF::bytes(), s, a, st); \
         return hipGetLastError();                                                         \
     }
     COL_VARIANTS(CASE)
@@ -1191,6 +1299,14 @@ int fast2d_col_len_at_least(int n) {
     COL_VARIANTS(CASE)
 #undef CASE
     return best;
+}
+
+int fast2d_col_blocks(int L, int var, int nkx) {
+    if (var < 0) var = fast2d_col_variant(L);
+#define CASE(LL, E, NQ, V) if (L == LL && var == V) return ColSplit<LL, E, NQ>::blocks(nkx);
+    COL_VARIANTS(CASE)
+#undef CASE
+    return 0;
 }
 
 int fast2d_col_width(int L, int var) {
@@ -1246,6 +1362,33 @@ hipError_t launch_col_group(int L, int var, const FilmCol* films, const int2* ma
     COL_VARIANTS(CASE)
 #undef CASE
     return hipErrorInvalidValue;
+}
+
+// sizes beyond the hardware are refused before any runtime call; a failed
+// call leaves no error behind for later calls
+hipError_t raise_lds_limit(const void* fn, int bytes) {
+    if (bytes > kMaxLds) return hipErrorInvalidValue;
+    if (bytes <= 65536) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, int> raised;
+    const std::pair<int, const void*> key(dev, fn);
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = raised.find(key);
+        if (it != raised.end() && it->second >= bytes) return hipSuccess;
+    }
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    int& v = raised[key];
+    if (v < bytes) v = bytes;
+    return hipSuccess;
 }
 
 }  // namespace llg

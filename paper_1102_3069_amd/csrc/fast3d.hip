@@ -219,13 +219,7 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
     X(16, 4, 32, 2) X(32, 4, 16, 2) X(64, 8, 16, 2) X(128, 8, 8, 2) X(256, 16, 8, 2) X(32, 4, 32, 1) \
     X(64, 8, 32, 1) X(128, 8, 16, 1) X(256, 16, 16, 1)
 
-hipError_t allow_lds3(const void* fn, int bytes) {
-    if (bytes <= 64 * 1024) return hipSuccess;
-    if (bytes > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) (void)hipGetLastError();
-    return e;
-}
+hipError_t allow_lds3(const void* fn, int bytes) { return raise_lds_limit(fn, bytes); }
 
 template <int L, int E, int TW, int H, int NC>
 hipError_t launch_t3(const ColArgs& a, int mode, DevState* st, hipStream_t s) {

@@ -23,7 +23,7 @@ constexpr double kBohrMagneton = 9.2740100783e-24;   // J/T
 constexpr double kElectronCharge = 1.602176634e-19;  // C
 constexpr double kBoltzmann = 1.380649e-23;
 constexpr double kDtMin = 1e-18;
-constexpr int kMaxPx = 2048;
+constexpr int kMaxPx = 4096;
 constexpr int kMaxHalf = 2048;
 
 // Butcher tableaux (rows of A for stages 2..S, then b)

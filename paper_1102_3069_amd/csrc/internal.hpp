@@ -159,6 +159,11 @@ struct Col2dArgs {
     int var;                // compiled variant of the column half length Py/2
 };
 
+// Raises the dynamic LDS limit of kernel `fn` to `bytes` (needed above 64
+// KB, refused above the 160 KB of a gfx950 workgroup).  The runtime call is
+// made once per (device, kernel); later launches find it in a table.
+hipError_t raise_lds_limit(const void* fn, int bytes);
+
 // ---- launchers (kernels.hip) ------------------------------------------------
 hipError_t launch_row_fwd(const Grid& g, const Phys& p, const FftPlan& px, const float2* twx,
                           float2* S, const FwdArgs& fa, DevState* st, hipStream_t s);
@@ -221,6 +226,8 @@ hipError_t launch_col3_tiled(const ColArgs& a, int mode, DevState* st, hipStream
 int fast2d_row_len_at_least(int n);
 int fast2d_col_len_at_least(int n);
 int fast2d_col_width(int L, int var = -1);
+// blocks of one column launch of a film with nkx stored columns
+int fast2d_col_blocks(int L, int var, int nkx);
 hipError_t launch_row_fwd_group(int Px, int var, const FilmRow* films, const int2* map, int nblocks,
                                 hipStream_t s);
 hipError_t launch_row_inv_group(int Px, int var, const FilmRow* films, const int2* map, int nblocks,

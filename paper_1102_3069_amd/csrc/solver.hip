@@ -764,6 +764,11 @@ llg_status llg_set_geometry(llg_solver* s, int nx, int ny, int nz, int pbc_x, in
                                 !(gen && gen[0] == '1'));
     s->fast3dy = nz > 1 && fast3d_col_ok(P[1], split_y, false) && ny <= Ly && !(gen && gen[0] == '1');
     s->fast3dz = nz > 1 && fast3d_col_ok(P[2], split_z, true) && nz <= Lz && !(gen && gen[0] == '1');
+    // x transforms above 2048 points exist only as compiled 2D row kernels
+    // (the runtime-length kernels stop at 2048)
+    if (P[0] > 2048 && !(s->fast2d && nz == 1))
+        return fail(s, LLG_E_UNSUPPORTED,
+                    "x FFT length %d runs only on the compiled 2D path (one cell thick, compiled y length)", P[0]);
     const size_t vec = sizeof(float) * 3 * (size_t)g.ncells;
     HIPCHK(s, make_tw(P[0], &s->twx));
     HIPCHK(s, make_tw(P[1], &s->twy));
@@ -1191,6 +1196,11 @@ llg_status llg_profile_evals(llg_solver* s, int n, double* ms_out, int n_kinds, 
     if (!p.demag_on) return fail(s, LLG_E_STATE, "profiling needs the demag term");
     int was = 0;
     if ((rc = lift_done(s, &was)) != LLG_OK) return rc;
+    // one untimed evaluation first: the first launch of a kernel in a
+    // process carries one-time runtime work (code object set-up) that is
+    // not the kernel's
+    if ((rc = eval_into(s, s->hbuf, p)) != LLG_OK) return rc;
+    if ((rc = sync(s)) != LLG_OK) return rc;
     std::vector<hipEvent_t> ev(6 * (size_t)n);
     for (auto& e : ev) HIPCHK(s, hipEventCreate(&e));
     for (int i = 0; i < n; ++i) {

@@ -22,8 +22,8 @@ def lib():
 
 
 # every padded length with compiled variants (rows: Px; columns: L = Py / 2)
-ROW_LENGTHS = (64, 128, 192, 256, 384, 512, 768, 1024, 2048)
-COL_LENGTHS = (32, 64, 96, 128, 192, 256, 384, 512, 1024)
+ROW_LENGTHS = (64, 128, 192, 256, 384, 512, 768, 1024, 2048, 4096)
+COL_LENGTHS = (32, 64, 96, 128, 192, 256, 384, 512, 1024, 2048)
 
 
 @pytest.fixture

@@ -70,7 +70,7 @@ def test_batch_film_matches_oracle(lib):
 
 
 def test_batch_rejects_sizes_beyond_the_compiled_lengths(lib):
-    prob, m0 = workloads.small_problem(n=(1100, 4, 1))
+    prob, m0 = workloads.small_problem(n=(2100, 4, 1))     # x padded beyond 4096
     with pytest.raises(lib.LLGError) as e:
         lib.Batch([(prob, m0)])
     assert e.value.code == lib.LLG_E_UNSUPPORTED
@@ -78,10 +78,11 @@ def test_batch_rejects_sizes_beyond_the_compiled_lengths(lib):
 
 def test_batch_ragged_sizes_match_oracle(lib):
     """Films whose 2n is no compiled length are padded further (17 x 9 to
-    64 x 64, 40 x 8 to 128 x 64, ...); the convolution is unchanged, so each
-    film still follows the oracle, which replays its attempts, to 1e-5."""
+    64 x 64, 40 x 8 to 128 x 64, 1100 x 4 to 4096 x 64, ...); the
+    convolution is unchanged, so each film still follows the oracle, which
+    replays its attempts, to 1e-5."""
     films = []
-    for n, seed in [((17, 9, 1), 1), ((40, 8, 1), 2), ((150, 30, 1), 3)]:
+    for n, seed in [((17, 9, 1), 1), ((40, 8, 1), 2), ((150, 30, 1), 3), ((1100, 4, 1), 4)]:
         prob, m0 = workloads.small_problem(n=n, seed=seed, alpha=0.5)
         films.append((prob, m0))
     b = lib.Batch(films)
