@@ -47,7 +47,10 @@ def build(verbose=True):
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    # roctx ranges around the API calls (rocprofv3 --marker-trace)
+    libs = ["-L" + os.path.join(rocm, "lib"), "-Wl,-rpath," + os.path.join(rocm, "lib"), "-lrocprofiler-sdk-roctx"]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + libs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -548,6 +548,7 @@ const char* llg_batch_last_error(const llg_batch* b) { return b ? b->err.c_str()
 
 llg_status llg_batch_run(llg_batch* b, double t_end, double max_err, double dt0, int64_t max_attempts,
                          llg_stats* per_film) {
+    TraceRange trace_("llg_batch_run");
     if (!b) return LLG_E_ARG;
     b->err.clear();
     BCHK(b, hipSetDevice(b->device));
@@ -753,6 +754,7 @@ __global__ void clear_health_kernel(DevState* st, int n) {
 extern "C" {
 
 llg_status llg_batch_step(llg_batch* b, llg_method method, double dt, int64_t nsteps) {
+    TraceRange trace_("llg_batch_step");
     if (!b) return LLG_E_ARG;
     b->err.clear();
     BCHK(b, hipSetDevice(b->device));
@@ -760,6 +762,7 @@ llg_status llg_batch_step(llg_batch* b, llg_method method, double dt, int64_t ns
 }
 
 llg_status llg_batch_autotune(llg_batch* b, int iters, llg_tune_entry* out, int cap, int* n_out) {
+    TraceRange trace_("llg_batch_autotune");
     if (!b || iters < 1 || cap < 0 || (cap > 0 && !out)) return LLG_E_ARG;
     b->err.clear();
     BCHK(b, hipSetDevice(b->device));

@@ -10,11 +10,22 @@
 
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "internal.hpp"
 #include "llg.h"
 
 namespace llg {
 namespace host {
+
+// A roctx range over a host-side scope (an API call, a kernel build, a pass
+// being enqueued); visible with rocprofv3 --marker-trace, free otherwise.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 constexpr double kMu0 = 4.0e-7 * M_PI;
 constexpr double kGammaLL = 1.7595e11;

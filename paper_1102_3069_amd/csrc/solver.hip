@@ -239,6 +239,7 @@ llg_status ready(llg_solver* s, bool need_m) {
 
 llg_status ensure_kernel(llg_solver* s) {
     if (s->K_valid || !(s->terms & LLG_TERM_DEMAG)) return LLG_OK;
+    TraceRange trace_("demag kernel build (FP64)");
     TensorGeom tg = {};
     const double d[3] = {s->dx, s->dy, s->dz};
     const double dm = fmax(d[0], fmax(d[1], d[2]));
@@ -934,6 +935,7 @@ llg_status llg_get_m(llg_solver* s, float* m, llg_mem where) {
 }
 
 llg_status llg_eval_heff(llg_solver* s, float* h_out, llg_mem where) {
+    TraceRange trace_("llg_eval_heff");
     llg_status rc = enter(s);
     if (rc != LLG_OK) return rc;
     if (!h_out) return fail(s, LLG_E_ARG, "null output");
@@ -952,6 +954,7 @@ llg_status llg_eval_heff(llg_solver* s, float* h_out, llg_mem where) {
 }
 
 llg_status llg_eval_heff_noalloc(llg_solver* s, const float* m_dev, float* h_dev) {
+    TraceRange trace_("llg_eval_heff_noalloc");
     llg_status rc = enter(s);
     if (rc != LLG_OK) return rc;
     if (!m_dev || !h_dev) return fail(s, LLG_E_ARG, "null m or h");
@@ -995,6 +998,7 @@ llg_status llg_eval_heff_noalloc(llg_solver* s, const float* m_dev, float* h_dev
 }
 
 llg_status llg_step(llg_solver* s, llg_method method, double dt, int64_t nsteps) {
+    TraceRange trace_("llg_step");
     llg_status rc = enter(s);
     if (rc != LLG_OK) return rc;
     Tableau tf;
@@ -1046,6 +1050,7 @@ llg_status llg_run_attempts(llg_solver* s, double t_end, double max_err, double 
 
 llg_status llg_run_dm(llg_solver* s, llg_method method, double t_end, double max_dm, double dt_max,
                       llg_stats* out) {
+    TraceRange trace_("llg_run_dm");
     llg_status rc = enter(s);
     if (rc != LLG_OK) return rc;
     Tableau tf;
@@ -1187,6 +1192,7 @@ llg_status llg_get_attempts(llg_solver* s, llg_attempt* out, int64_t cap, int64_
 }
 
 llg_status llg_profile_evals(llg_solver* s, int n, double* ms_out, int n_kinds, double* total_ms) {
+    TraceRange trace_("llg_profile_evals");
     llg_status rc = enter(s);
     if (rc != LLG_OK) return rc;
     if (n < 1 || !ms_out || n_kinds < 5 || !total_ms) return fail(s, LLG_E_ARG, "bad profile arguments");
@@ -1259,6 +1265,7 @@ llg_status llg_profile_evals(llg_solver* s, int n, double* ms_out, int n_kinds, 
 }
 
 llg_status llg_autotune(llg_solver* s, int iters, double* ms_out, int n_out, int* choice) {
+    TraceRange trace_("llg_autotune");
     llg_status rc = enter(s);
     if (rc != LLG_OK) return rc;
     if (iters < 1) return fail(s, LLG_E_ARG, "iters must be >= 1");
@@ -1441,6 +1448,7 @@ namespace {
 
 llg_status run_adaptive(llg_solver* s, int method, double t_end, double max_err, double dt0,
                         long long max_attempts, llg_stats* out) {
+    TraceRange trace_("llg_run (adaptive)");
     llg_status rc;
     Adaptive ad;
     if (!adaptive_of(method, &ad)) return fail(s, LLG_E_ARG, "method %d is not an adaptive pair", method);

@@ -29,6 +29,7 @@
 #include <string>
 #include <vector>
 
+#include "host_common.hpp"
 #include "internal.hpp"
 
 namespace {
@@ -778,6 +779,7 @@ llg_status llg_sur_get_grads(llg_sur* s, float* grads, int64_t n) {
 // gradient of the loss (and optionally one Adam step) for a batch
 llg_status llg_sur_train_step(llg_sur* s, const float* m_in, const float* m_target, const float* m_base,
                               const float* B, int batch, llg_mem where, float lr, float* loss) {
+    llg::host::TraceRange trace_("llg_sur_train_step");
     if (!s || !m_in || !m_target || !B || batch < 1 || batch > s->maxb) return LLG_E_ARG;
     SCHK(s, hipSetDevice(s->device));
     if (!s->packed) return sfail(s, LLG_E_STATE, "parameters not set");
@@ -966,6 +968,7 @@ float bits_to_float(unsigned u) {
 
 llg_status llg_sur_advance(llg_sur* s, const llg_film_desc* film, int window, int64_t n_segments, int seg_steps,
                            double dt, int predictor, double max_dm, float* m, llg_mem where, llg_sur_stats* out) {
+    llg::host::TraceRange trace_("llg_sur_advance");
     if (!s || !film || !m || window < 1 || window > 256 || n_segments < 0 || seg_steps < 1 || !(dt > 0) ||
         !(max_dm >= 0) ||
         (predictor != LLG_SUR_BASE_STATE && predictor != LLG_SUR_BASE_EULER && predictor != LLG_SUR_BASE_RK4))
