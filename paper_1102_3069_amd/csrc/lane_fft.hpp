@@ -55,12 +55,11 @@ template <typename C> struct Dft<16, C> {
 };
 
 // ---------------------------------------------------------------------------
-// stage plan: greedy radices from {16, 8, 4, 2, 3, 5, 7} (16 only when RM,
-// the largest radix allowed, is 16), each dividing both the remaining length
-// and E
+// stage plan: greedy radices from {16, 8, 4, 2, 3, 5, 7}, each dividing both
+// the remaining length and E
 // ---------------------------------------------------------------------------
-constexpr int lf_pick(int rem, int E, int RM = 16) {
-    return (RM >= 16 && rem % 16 == 0 && E % 16 == 0) ? 16
+constexpr int lf_pick(int rem, int E) {
+    return (rem % 16 == 0 && E % 16 == 0) ? 16
          : (rem % 8 == 0 && E % 8 == 0) ? 8
          : (rem % 4 == 0 && E % 4 == 0) ? 4
          : (rem % 2 == 0 && E % 2 == 0) ? 2
@@ -68,28 +67,28 @@ constexpr int lf_pick(int rem, int E, int RM = 16) {
          : (rem % 5 == 0 && E % 5 == 0) ? 5
          : (rem % 7 == 0 && E % 7 == 0) ? 7 : 0;
 }
-constexpr int lf_radix(int L, int E, int s, int RM = 16) {
+constexpr int lf_radix(int L, int E, int s) {
     int rem = L;
     for (int i = 0; i < s; ++i) {
-        const int r = lf_pick(rem, E, RM);
+        const int r = lf_pick(rem, E);
         if (r == 0) return 0;
         rem /= r;
     }
-    return rem == 1 ? 1 : lf_pick(rem, E, RM);
+    return rem == 1 ? 1 : lf_pick(rem, E);
 }
-constexpr int lf_nstages(int L, int E, int RM = 16) {
+constexpr int lf_nstages(int L, int E) {
     int rem = L, n = 0;
     while (rem > 1) {
-        const int r = lf_pick(rem, E, RM);
+        const int r = lf_pick(rem, E);
         if (r == 0) return -1;
         rem /= r;
         ++n;
     }
     return n;
 }
-constexpr int lf_ns(int L, int E, int s, int RM = 16) {
+constexpr int lf_ns(int L, int E, int s) {
     int p = 1;
-    for (int i = 0; i < s; ++i) p *= lf_radix(L, E, i, RM);
+    for (int i = 0; i < s; ++i) p *= lf_radix(L, E, i);
     return p;
 }
 
@@ -108,19 +107,17 @@ template <int L> struct LfSwz {
 template <int L> __device__ __forceinline__ int lf_swz(int i) { return i ^ (((i >> 3) ^ (i >> 7)) & LfSwz<L>::M); }
 template <int L> struct LfScratch { static constexpr int size = L; };
 
-// RM: the largest radix of a stage (16, or 8 where a radix-16 stage would
-// need more registers than the kernel can give it)
-template <int L, int E, int TM, typename C, int RM = 16>
+template <int L, int E, int TM, typename C>
 struct LaneFFT {
     static constexpr int P = L / E;
-    static constexpr int NS = lf_nstages(L, E, RM);
+    static constexpr int NS = lf_nstages(L, E);
     static constexpr int SCRATCH = LfScratch<L>::size;   // elements per group
     static_assert(L % E == 0 && NS >= 0, "length must factor into radices dividing E");
     static_assert(64 % P == 0, "a lane group must fit one wavefront");
 
     // twiddle table of stage s >= 1: entry (r - 1) Ns + k = w^(k r TS) of the
     // caller's table, r = 1 .. R-1, k < Ns
-    static constexpr int tws_count(int s) { return s == 0 ? 0 : (lf_radix(L, E, s, RM) - 1) * lf_ns(L, E, s, RM); }
+    static constexpr int tws_count(int s) { return s == 0 ? 0 : (lf_radix(L, E, s) - 1) * lf_ns(L, E, s); }
     static constexpr int tws_off(int s) {
         int o = 0;
         for (int i = 1; i < s; ++i) o += tws_count(i);
@@ -132,7 +129,7 @@ struct LaneFFT {
     template <int S>
     static __device__ __forceinline__ void tw_index(int e, int& idx) {
         if constexpr (S < NS) {
-            constexpr int R = lf_radix(L, E, S, RM), Ns = lf_ns(L, E, S, RM);
+            constexpr int R = lf_radix(L, E, S), Ns = lf_ns(L, E, S);
             constexpr int TS = (L / (Ns * R)) * TM, B = tws_off(S), CNT = (R - 1) * Ns;
             if (e >= B && e < B + CNT) {
                 const int t = e - B;
@@ -154,8 +151,8 @@ struct LaneFFT {
 
     template <int S, bool INV>
     static __device__ __forceinline__ void stage(C (&x)[E], C* sc, const C* tws, int lg) {
-        constexpr int R = lf_radix(L, E, S, RM);
-        constexpr int Ns = lf_ns(L, E, S, RM);
+        constexpr int R = lf_radix(L, E, S);
+        constexpr int Ns = lf_ns(L, E, S);
         constexpr int U = E / R;          // butterflies per lane
         constexpr int LR = L / R;
         constexpr int B = tws_off(S);
