@@ -233,6 +233,25 @@ __device__ __forceinline__ void lds_fft(C* buf, const FftPlan& p, int nbatch,
     }
 }
 
+// dst[m] = src[m] for m < n (n <= N) by threads tid = 0 .. NT-1 of a
+// workgroup: every load is issued before the first store, so the copy costs
+// one memory round trip instead of one per iteration
+template <int N, int NT, typename T>
+__device__ __forceinline__ void copy_batched(T* __restrict__ dst, const T* __restrict__ src, int tid, int n = N) {
+    constexpr int IT = (N + NT - 1) / NT;
+    T v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int m = tid + it * NT;
+        if (m < n) v[it] = src[m];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int m = tid + it * NT;
+        if (m < n) dst[m] = v[it];
+    }
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; give
 // each XCD a contiguous range of logical tiles so that tiles sharing cache
 // lines share one L2 (a bijection of [0, n)).

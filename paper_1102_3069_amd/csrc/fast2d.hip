@@ -261,13 +261,14 @@ __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __rest
     float* nm = (float*)(lds + R::O_M);
     if (st->done) return;
     const int tid = threadIdx.x;
-    const int gi = tid / R::P, lg = tid % R::P;
+    const int gi = R::P == 64 ? __builtin_amdgcn_readfirstlane(tid / R::P) : tid / R::P;
+    const int lg = tid % R::P;
     int kind, q, pair;
     R::group(gi, kind, q, pair);
     const int gbase = (tid & 63) - lg;
     const int rb = row_block_start<NAT>(g, blk, 2 * R::RP);
-    for (int m = tid; m < PX; m += NT) tw[m] = twx[m];
-    R::F::fill_tw(tws, twx, tid, NT);
+    copy_batched<PX, NT>(tw, twx, tid);
+    R::F::template fill_tw<NT>(tws, twx, tid);
     const int cur = st->cur;
     const float c1 = st->dtau * fa.a1;
     const int cs = g.ncells;
@@ -457,7 +458,9 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     float* wmax = (float*)(lds + R::template o_wmax<XPER>());
     if (st->done) return;
     const int tid = threadIdx.x;
-    const int gi = tid / P, lg = tid % P;
+    // a group that fills its wavefront: the group index is wave-uniform
+    const int gi = P == 64 ? __builtin_amdgcn_readfirstlane(tid / P) : tid / P;
+    const int lg = tid % P;
     int kind, q, pair;
     R::group(gi, kind, q, pair);
     const int gbase = (tid & 63) - lg;
@@ -485,8 +488,8 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
 
     // ---- global reads: twiddles, m rows rb-1 .. rb+2RP (y neighbours wrap
     // on a periodic y axis), this group's class of the spectrum
-    for (int m = tid; m < PX; m += NT) tw[m] = twx[m];
-    F::fill_tw(tws, twx, tid, NT);
+    copy_batched<PX, NT>(tw, twx, tid);
+    F::template fill_tw<NT>(tws, twx, tid);
     // staged row rq holds grid row rb - 1 + rq; NAT (3D): the halo rows serve
     // only as in-plane neighbours, the periodic y wrap and the z neighbours
     // come from global memory
@@ -501,15 +504,31 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     } else if ((nx & 3) == 0 && (cs & 3) == 0) {
         // 16-byte loads: every (row, component) run of nx floats starts
         // 16-byte aligned
+        // (the loads of up to eight iterations issued before their LDS stores)
         const int n4 = nx >> 2;
-        for (int t = tid; t < R::NR * 3 * n4; t += NT) {
-            const int rq = t / (3 * n4), rem = t - rq * 3 * n4;
-            const int c = rem / n4, x4 = rem - c * n4;
-            bool ok;
-            const int row = staged_row(rq, ok);
-            const float4 v = ok ? *reinterpret_cast<const float4*>(mi + (size_t)c * cs + (size_t)row * nx + 4 * x4)
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
-            *reinterpret_cast<float4*>(mrow + rq * 3 * NXM + c * NXM + 4 * x4) = v;
+        constexpr int ITR = (R::NR * 3 * (NXM / 4) + NT - 1) / NT;
+        constexpr int CH = ITR < 8 ? ITR : 8;
+#pragma unroll
+        for (int i0 = 0; i0 < ITR; i0 += CH) {
+            float4 v[CH];
+            int dst[CH];
+#pragma unroll
+            for (int ii = 0; ii < CH; ++ii) {
+                const int t = tid + (i0 + ii) * NT;
+                dst[ii] = -1;
+                if (i0 + ii < ITR && t < R::NR * 3 * n4) {
+                    const int rq = t / (3 * n4), rem = t - rq * 3 * n4;
+                    const int c = rem / n4, x4 = rem - c * n4;
+                    bool ok;
+                    const int row = staged_row(rq, ok);
+                    v[ii] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (ok) v[ii] = *reinterpret_cast<const float4*>(mi + (size_t)c * cs + (size_t)row * nx + 4 * x4);
+                    dst[ii] = rq * 3 * NXM + c * NXM + 4 * x4;
+                }
+            }
+#pragma unroll
+            for (int ii = 0; ii < CH; ++ii)
+                if (dst[ii] >= 0) *reinterpret_cast<float4*>(mrow + dst[ii]) = v[ii];
         }
     } else {
         for (int rq = 0; rq < R::NR; ++rq) {
@@ -539,32 +558,53 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             if (v0) sa_ = S + 2 * scs + rs0;
             if (v1) sb_ = S + 2 * scs + rs1;
         }
+        // X[k], k = NQ j + q, from the stored columns kx < PX/2 and the
+        // Hermitian symmetry X[PX - k] = conj X[k] of a real row (class
+        // (NQ - q) mod NQ, index LQ - j for q = 0, LQ - 1 - j otherwise).
+        // Every load first, the conjugations and the packed DC / Nyquist
+        // column after them.
+        // (in chunks of eight elements on the longest rows)
+        constexpr int CZ = E2 < 8 ? E2 : 8;
 #pragma unroll
-        for (int i = 0; i < E2; ++i) {
-            // X[k], k = NQ j + q, from the stored columns kx < PX/2 and the
-            // Hermitian symmetry X[PX - k] = conj X[k] of a real row (class
-            // (NQ - q) mod NQ, index LQ - j for q = 0, LQ - 1 - j otherwise)
+        for (int i0 = 0; i0 < E2; i0 += CZ) {
+        int colv[CZ];
+#pragma unroll
+        for (int ii = 0; ii < CZ; ++ii) {
+            const int i = i0 + ii;
             const int j = lg + P * i;
             const int k = NQ * j + q;
-            float2 A = mk2(0.f, 0.f), B = mk2(0.f, 0.f);
+            const bool up = k > PX / 2;
             if (NAT) {
                 // natural layout: kx = 0 ... PX/2 stored, the rest conjugate
-                const bool up = k > PX / 2;
-                const int col = up ? PX - k : k;
-                if (sa_) { A = sa_[col]; if (up) A.y = -A.y; }
-                if (sb_) { B = sb_[col]; if (up) B.y = -B.y; }
+                colv[ii] = up ? PX - k : k;
             } else if (k == 0 || k == PX / 2) {
-                const bool nyq = k != 0;
-                if (sa_) { const float2 v = sa_[0]; A = mk2(nyq ? v.y : v.x, 0.f); }
-                if (sb_) { const float2 v = sb_[0]; B = mk2(nyq ? v.y : v.x, 0.f); }
+                colv[ii] = 0;
             } else {
-                const bool up = k > PX / 2;
                 const int sc = q == 0 ? (up ? LQ - j : j) : (up ? (NQ - q) * QC + LQ - 1 - j : q * QC + j);
-                const int col = tile_index(0, sc, g.nrows, g.tsh);
-                if (sa_) { A = sa_[col]; if (up) A.y = -A.y; }
-                if (sb_) { B = sb_[col]; if (up) B.y = -B.y; }
+                colv[ii] = tile_index(0, sc, g.nrows, g.tsh);
+            }
+        }
+        float2 za[CZ], zb[CZ];
+#pragma unroll
+        for (int ii = 0; ii < CZ; ++ii) {
+            za[ii] = sa_ ? sa_[colv[ii]] : mk2(0.f, 0.f);
+            zb[ii] = sb_ ? sb_[colv[ii]] : mk2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int ii = 0; ii < CZ; ++ii) {
+            const int i = i0 + ii;
+            const int k = NQ * (lg + P * i) + q;
+            float2 A = za[ii], B = zb[ii];
+            if (!NAT && (k == 0 || k == PX / 2)) {
+                const bool nyq = k != 0;
+                A = mk2(nyq ? A.y : A.x, 0.f);
+                B = mk2(nyq ? B.y : B.x, 0.f);
+            } else if (k > PX / 2) {
+                A.y = -A.y;
+                B.y = -B.y;
             }
             z[i] = mk2(A.x - B.y, A.y + B.x);
+        }
         }
     }
     // ---- the parts of the stage combination that do not depend on this
@@ -594,23 +634,87 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             }
         }
     }
+    // the stage state m0 and the earlier stages' k at this thread's cells.
+    // Up to eight cells per thread: KB of the k's for ITC cells per memory
+    // round trip (every load of a round issued before the first is used; at
+    // most 36 values in flight), accumulated in stage order.  More cells
+    // (4096-point periodic rows): one cell after another.
+    constexpr int KP = kMaxK - 1;
+    const int nprev = (stage || errm) ? sa.nk - 1 : 0;
+    auto used = [&](int j) {
+        return j < nprev && ((stage && dtau * sa.a[j] != 0.f) || (errm && sa.e[j] != 0.f));
+    };
+    if constexpr (MAXIT > 8) {
 #pragma unroll
-    for (int it = 0; it < MAXIT; ++it) {
-        px_[it] = py_[it] = pz_[it] = ex_[it] = ey_[it] = ez_[it] = 0.f;
-        const int e = tid + it * NT;
-        if (e >= ncb || !(stage || errm)) continue;
-        int ri, x;
-        split_cell(e, nx, rnx, ri, x);
-        const int qq = (rb + ri) * nx + x;
-        if (stage) { px_[it] = m0[qq]; py_[it] = m0[cs + qq]; pz_[it] = m0[2 * cs + qq]; }
-        for (int j = 0; j + 1 < sa.nk; ++j) {
-            const float ca = stage ? dtau * sa.a[j] : 0.f;
-            const float ce = errm ? sa.e[j] : 0.f;
-            if (ca == 0.f && ce == 0.f) continue;
-            const float* __restrict__ kj = resolve(sa.kprev[j], cur);
-            const float vx = kj[qq], vy = kj[cs + qq], vz = kj[2 * cs + qq];
-            if (ca != 0.f) { px_[it] += ca * vx; py_[it] += ca * vy; pz_[it] += ca * vz; }
-            if (ce != 0.f) { ex_[it] += ce * vx; ey_[it] += ce * vy; ez_[it] += ce * vz; }
+        for (int it = 0; it < MAXIT; ++it) {
+            px_[it] = py_[it] = pz_[it] = ex_[it] = ey_[it] = ez_[it] = 0.f;
+            const int e = tid + it * NT;
+            if (e >= ncb || !(stage || errm)) continue;
+            int ri, x;
+            split_cell(e, nx, rnx, ri, x);
+            const int qq = (rb + ri) * nx + x;
+            if (stage) { px_[it] = m0[qq]; py_[it] = m0[cs + qq]; pz_[it] = m0[2 * cs + qq]; }
+            for (int j = 0; j < nprev; ++j) {
+                if (!used(j)) continue;
+                const float ca = stage ? dtau * sa.a[j] : 0.f;
+                const float ce = errm ? sa.e[j] : 0.f;
+                const float* __restrict__ kj = resolve(sa.kprev[j], cur);
+                const float vx = kj[qq], vy = kj[cs + qq], vz = kj[2 * cs + qq];
+                if (ca != 0.f) { px_[it] += ca * vx; py_[it] += ca * vy; pz_[it] += ca * vz; }
+                if (ce != 0.f) { ex_[it] += ce * vx; ey_[it] += ce * vy; ez_[it] += ce * vz; }
+            }
+        }
+    } else {
+        int qq_[MAXIT];   // this thread's cells (-1: none)
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) {
+            px_[it] = py_[it] = pz_[it] = ex_[it] = ey_[it] = ez_[it] = 0.f;
+            qq_[it] = -1;
+            const int e = tid + it * NT;
+            if (e >= ncb || !(stage || errm)) continue;
+            int ri, x;
+            split_cell(e, nx, rnx, ri, x);
+            const int qq = (rb + ri) * nx + x;
+            qq_[it] = qq;
+            if (stage) { px_[it] = m0[qq]; py_[it] = m0[cs + qq]; pz_[it] = m0[2 * cs + qq]; }
+        }
+        constexpr int ITC = MAXIT * 3 <= 36 ? MAXIT : 12;
+        constexpr int KB0 = 36 / (3 * ITC);
+        constexpr int KB = KB0 < 1 ? 1 : (KB0 > KP ? KP : KB0);
+#pragma unroll
+        for (int i0 = 0; i0 < MAXIT; i0 += ITC) {
+#pragma unroll
+            for (int j0 = 0; j0 < KP; j0 += KB) {
+                if (j0 >= nprev) break;
+                float kv[KB][ITC][3];
+#pragma unroll
+                for (int jj = 0; jj < KB && j0 + jj < KP; ++jj) {
+                    const int j = j0 + jj;
+                    if (!used(j)) continue;
+                    const float* __restrict__ kj = resolve(sa.kprev[j], cur);
+#pragma unroll
+                    for (int ii = 0; ii < ITC && i0 + ii < MAXIT; ++ii) {
+                        const int qq = qq_[i0 + ii];
+                        if (qq < 0) continue;
+                        kv[jj][ii][0] = kj[qq]; kv[jj][ii][1] = kj[cs + qq]; kv[jj][ii][2] = kj[2 * cs + qq];
+                    }
+                }
+#pragma unroll
+                for (int jj = 0; jj < KB && j0 + jj < KP; ++jj) {
+                    const int j = j0 + jj;
+                    if (!used(j)) continue;
+                    const float ca = stage ? dtau * sa.a[j] : 0.f;
+                    const float ce = errm ? sa.e[j] : 0.f;
+#pragma unroll
+                    for (int ii = 0; ii < ITC && i0 + ii < MAXIT; ++ii) {
+                        const int it = i0 + ii;
+                        if (qq_[it] < 0) continue;
+                        const float vx = kv[jj][ii][0], vy = kv[jj][ii][1], vz = kv[jj][ii][2];
+                        if (ca != 0.f) { px_[it] += ca * vx; py_[it] += ca * vy; pz_[it] += ca * vz; }
+                        if (ce != 0.f) { ex_[it] += ce * vx; ey_[it] += ce * vy; ez_[it] += ce * vz; }
+                    }
+                }
+            }
         }
     }
     __syncthreads();   // twiddles and staged rows
@@ -843,7 +947,9 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     float2* xch = (float2*)(lds + CF::O_XCH);
     if (st->done) return;
     const int tid = threadIdx.x;
-    const int gi = tid / P, lg = tid % P;
+    // a group that fills its wavefront: the group index is wave-uniform
+    const int gi = P == 64 ? __builtin_amdgcn_readfirstlane(tid / P) : tid / P;
+    const int lg = tid % P;
     int w, q, c, scol;
     if (BIG) {
         // blocks [0, nkx): x and y of column lb; then z of columns 2j, 2j+1
@@ -876,41 +982,85 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
         // blocks n + r LC for r < NQ/2) and its pre-twiddles, combined into
         // the class input as they arrive; the kernel values follow the
         // forward transform (fewer live registers through it)
+        float2 v0[E], v1[E], tv[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int y = lg + P * i;
-            float2 v = y < ny ? src[y << a.tsh] : mk2(0.f, 0.f);
-            if (NQ == 4 && y + LC < ny) { const float2 t = rot4(src[(y + LC) << a.tsh], q); v.x += t.x; v.y += t.y; }
-            x[i] = q ? cmul(v, a.tw[y * q]) : v;
+            v0[i] = y < ny ? src[y << a.tsh] : mk2(0.f, 0.f);
+            v1[i] = (NQ == 4 && y + LC < ny) ? src[(y + LC) << a.tsh] : mk2(0.f, 0.f);
+            tv[i] = q ? a.tw[y * q] : mk2(1.f, 0.f);
         }
-    } else {
-        // ---- global reads, shared by the block through LDS: its W spectrum
-        // columns (the classes of a column read the same values; W
-        // consecutive stored columns are contiguous within a tile row), its
-        // kernel columns (contiguous in ky)
-        for (int e = tid; e < 3 * W * ny; e += NT) {
-            const int ww = e % W, t = e / W;
-            const int y = t % ny, cc = t / ny;
-            xst[(cc * W + ww) * L + y] = a.S[cc * cs + tile_index(y, lb * W + ww, ny, a.tsh)];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            float2 v = v0[i];
+            if (NQ == 4) { const float2 t = rot4(v1[i], q); v.x += t.x; v.y += t.y; }
+            x[i] = q ? cmul(v, tv[i]) : v;
         }
-        for (int e = tid; e < W * 4 * KL; e += NT) {
-            const int j = e % KL, t = e / KL;
-            const int comp = t % 4, ww = t / 4;
-            kst[(ww * 4 + comp) * KL + j] = a.K[comp * kcs + kx_of(lb * W + ww) * KL + j];
-        }
-        if (lb == 0)   // the packed column also needs the Nyquist column kx = Px/2
-            for (int e = tid; e < 3 * KL; e += NT) {
-                const int j = e % KL, comp = e / KL;
-                kst[(W * 4 + comp) * KL + j] = a.K[comp * kcs + (a.nkx_full - 1) * KL + j];
-            }
     }
-    // the stage twiddles; per lane (not BIG), the pre/post twiddles W^(nq)
-    // of its elements
-    F::fill_tw(tws, a.tw, tid, NT);
+    // not BIG: the global reads shared by the block through LDS, its W
+    // spectrum columns (the classes of a column read the same values; W
+    // consecutive stored columns are contiguous within a tile row) and its
+    // kernel columns (contiguous in ky); the stage twiddles; per lane, the
+    // pre/post twiddles W^(nq) of its elements.  Every load is issued before
+    // the first LDS store (one memory round trip).
+    constexpr int ITX = BIG ? 1 : (3 * W * L + NT - 1) / NT;
+    constexpr int ITK = BIG ? 1 : (W * 4 * KL + NT - 1) / NT;
+    constexpr int ITN = BIG ? 1 : (3 * KL + NT - 1) / NT;
+    float2 xv[ITX];
+    float kv[ITK], nv[ITN];
+    int xd[ITX];
     float2 twq[BIG ? 1 : E];
     if constexpr (!BIG) {
 #pragma unroll
+        for (int it = 0; it < ITX; ++it) {
+            const int e = tid + it * NT;
+            xd[it] = -1;
+            if (e < 3 * W * ny) {
+                const int ww = e % W, t = e / W;
+                const int y = t % ny, cc = t / ny;
+                xv[it] = a.S[cc * cs + tile_index(y, lb * W + ww, ny, a.tsh)];
+                xd[it] = (cc * W + ww) * L + y;
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < ITK; ++it) {
+            const int e = tid + it * NT;
+            if (e < W * 4 * KL) {
+                const int j = e % KL, t = e / KL;
+                const int comp = t % 4, ww = t / 4;
+                kv[it] = a.K[comp * kcs + kx_of(lb * W + ww) * KL + j];
+            }
+        }
+        if (lb == 0) {   // the packed column also needs the Nyquist column kx = Px/2
+#pragma unroll
+            for (int it = 0; it < ITN; ++it) {
+                const int e = tid + it * NT;
+                if (e < 3 * KL) {
+                    const int j = e % KL, comp = e / KL;
+                    nv[it] = a.K[comp * kcs + (a.nkx_full - 1) * KL + j];
+                }
+            }
+        }
+#pragma unroll
         for (int i = 0; i < E; ++i) twq[i] = q ? a.tw[(lg + P * i) * q] : mk2(1.f, 0.f);
+    }
+    F::template fill_tw<NT>(tws, a.tw, tid);
+    if constexpr (!BIG) {
+#pragma unroll
+        for (int it = 0; it < ITX; ++it)
+            if (xd[it] >= 0) xst[xd[it]] = xv[it];
+#pragma unroll
+        for (int it = 0; it < ITK; ++it) {
+            const int e = tid + it * NT;
+            if (e < W * 4 * KL) kst[e] = kv[it];   // [w][comp][ky]
+        }
+        if (lb == 0) {
+#pragma unroll
+            for (int it = 0; it < ITN; ++it) {
+                const int e = tid + it * NT;
+                if (e < 3 * KL) kst[W * 4 * KL + e] = nv[it];
+            }
+        }
     }
     __syncthreads();   // stage twiddles (and the staged columns)
     if constexpr (!BIG) {
@@ -935,17 +1085,20 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     }
     F::template run<false>(x, scr + gi * CF::SC, tws, lg);
     if constexpr (BIG) {
+        // every load first, the odd-symmetry signs after them
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int ky = NQ * (lg + P * i) + q;
-            const bool flip = ky > Py - ky;
-            const int iy = flip ? Py - ky : ky;
+            const int iy = ky > Py - ky ? Py - ky : ky;
             const int o = kx * KL + iy;
             kd[i] = a.K[c * kcs + o];
-            ko[i] = 0.f;
-            kn[i] = 0.f;
-            if (c < 2) { const float kv = a.K[3 * kcs + o]; ko[i] = flip ? -kv : kv; }
-            if (packed) kn[i] = a.K[c * kcs + (a.nkx_full - 1) * KL + iy];
+            ko[i] = c < 2 ? a.K[3 * kcs + o] : 0.f;
+            kn[i] = packed ? a.K[c * kcs + (a.nkx_full - 1) * KL + iy] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int ky = NQ * (lg + P * i) + q;
+            if (ky > Py - ky) ko[i] = -ko[i];
         }
         __syncthreads();   // every transform has left the scratch (the exchange aliases it)
     }
@@ -992,12 +1145,11 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     __syncthreads();   // every group has read the exchange (and left the scratch)
     {
         float2* xo = xch + CF::slot(c, q, w) * LC;
+        float2 tp[E];   // post-twiddles (BIG: from global memory, all loads first)
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const int n = lg + P * i;
-            const float2 t = BIG ? (q ? a.tw[n * q] : mk2(1.f, 0.f)) : twq[BIG ? 0 : i];
-            xo[n] = q ? cmul(x[i], cconj(t)) : x[i];
-        }
+        for (int i = 0; i < E; ++i) tp[i] = BIG ? (q ? a.tw[(lg + P * i) * q] : mk2(1.f, 0.f)) : twq[BIG ? 0 : i];
+#pragma unroll
+        for (int i = 0; i < E; ++i) xo[lg + P * i] = q ? cmul(x[i], cconj(tp[i])) : x[i];
     }
     __syncthreads();
     // outputs y = n + r LC: the group of class r (r < NQ/2) assembles them

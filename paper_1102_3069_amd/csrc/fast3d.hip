@@ -105,24 +105,35 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
 
     // ---- the tile into the lines: n_in rows (zero beyond) into the h = 0
     // lines, or the H L stored frequencies into their half lines
-    for (int m = tid; m < H * L; m += NT) tw[m] = a.tw[m];
-    F::fill_tw(tws, a.tw, tid, NT);
-    if (MODE != COL_INV) {
-        for (int e = tid; e < NC * L * TW; e += NT) {
+    // (the loads of up to eight iterations issued before their LDS stores)
+    copy_batched<H * L, NT>(tw, a.tw, tid);
+    F::template fill_tw<NT>(tws, a.tw, tid);
+    constexpr int NIN = MODE != COL_INV ? NC * L * TW : NC * H * L * TW;
+    constexpr int ITI = (NIN + NT - 1) / NT, CH = ITI < 8 ? ITI : 8;
+#pragma unroll
+    for (int i0 = 0; i0 < ITI; i0 += CH) {
+        float2 v[CH];
+        int dst[CH];
+#pragma unroll
+        for (int ii = 0; ii < CH; ++ii) {
+            const int e = tid + (i0 + ii) * NT;
+            dst[ii] = -1;
+            if (i0 + ii >= ITI || e >= NIN) continue;
             const int w = e % TW, t = e / TW;
-            const int n = t % L, c = t / L;
-            float2 v = make_float2(0.f, 0.f);
-            if (w < Wt && n < a.n_in) v = in[c * a.cs_in + n * a.as_in + w];
-            X[T::line(c, w, 0) + n] = v;
+            v[ii] = make_float2(0.f, 0.f);
+            if (MODE != COL_INV) {
+                const int n = t % L, c = t / L;
+                if (w < Wt && n < a.n_in) v[ii] = in[c * a.cs_in + n * a.as_in + w];
+                dst[ii] = T::line(c, w, 0) + n;
+            } else {
+                const int k = t % (H * L), c = t / (H * L);
+                if (w < Wt) v[ii] = in[c * a.cs_in + k * a.as_in + w];
+                dst[ii] = T::line(c, w, k / L) + k % L;
+            }
         }
-    } else {
-        for (int e = tid; e < NC * H * L * TW; e += NT) {
-            const int w = e % TW, t = e / TW;
-            const int k = t % (H * L), c = t / (H * L);
-            float2 v = make_float2(0.f, 0.f);
-            if (w < Wt) v = in[c * a.cs_in + k * a.as_in + w];
-            X[T::line(c, w, k / L) + k % L] = v;
-        }
+#pragma unroll
+        for (int ii = 0; ii < CH; ++ii)
+            if (dst[ii] >= 0) X[dst[ii]] = v[ii];
     }
     __syncthreads();
 

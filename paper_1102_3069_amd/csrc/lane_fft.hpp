@@ -139,13 +139,25 @@ struct LaneFFT {
         }
     }
     // the stage tables from the table full[m] = exp(-2 pi i m / (L TM)),
-    // by threads tid = 0 .. nt-1 of the workgroup (a barrier must follow)
-    template <typename Src>
-    static __device__ __forceinline__ void fill_tw(C* __restrict__ tws, const Src* __restrict__ full, int tid, int nt) {
-        for (int e = tid; e < TWS; e += nt) {
-            int idx = 0;
-            tw_index<1>(e, idx);
-            tws[e] = full[idx];
+    // by threads tid = 0 .. NT-1 of the workgroup (a barrier must follow);
+    // every load is issued before the first store
+    template <int NT, typename Src>
+    static __device__ __forceinline__ void fill_tw(C* __restrict__ tws, const Src* __restrict__ full, int tid) {
+        constexpr int IT = (TWS + NT - 1) / NT;
+        C v[IT > 0 ? IT : 1];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = tid + it * NT;
+            if (e < TWS) {
+                int idx = 0;
+                tw_index<1>(e, idx);
+                v[it] = full[idx];
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = tid + it * NT;
+            if (e < TWS) tws[e] = v[it];
         }
     }
 
