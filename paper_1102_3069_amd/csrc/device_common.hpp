@@ -234,23 +234,28 @@ __device__ __forceinline__ void lds_fft(C* buf, const FftPlan& p, int nbatch,
 }
 
 // dst[m] = src[m] for m < n (n <= N) by threads tid = 0 .. NT-1 of a
-// workgroup: every load is issued before the first store, so the copy costs
-// one memory round trip instead of one per iteration
+// workgroup, in two halves: load() issues every read into registers,
+// store() writes them out.  Issuing the loads of several copies before the
+// first store makes them cost one memory round trip together.
 template <int N, int NT, typename T>
-__device__ __forceinline__ void copy_batched(T* __restrict__ dst, const T* __restrict__ src, int tid, int n = N) {
-    constexpr int IT = (N + NT - 1) / NT;
+struct StagedCopy {
+    static constexpr int IT = (N + NT - 1) / NT;
     T v[IT];
+    __device__ __forceinline__ void load(const T* __restrict__ src, int tid, int n = N) {
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int m = tid + it * NT;
-        if (m < n) v[it] = src[m];
+        for (int it = 0; it < IT; ++it) {
+            const int m = tid + it * NT;
+            if (m < n) v[it] = src[m];
+        }
     }
+    __device__ __forceinline__ void store(T* __restrict__ dst, int tid, int n = N) const {
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int m = tid + it * NT;
-        if (m < n) dst[m] = v[it];
+        for (int it = 0; it < IT; ++it) {
+            const int m = tid + it * NT;
+            if (m < n) dst[m] = v[it];
+        }
     }
-}
+};
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; give
 // each XCD a contiguous range of logical tiles so that tiles sharing cache

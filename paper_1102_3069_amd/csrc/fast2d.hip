@@ -267,8 +267,12 @@ __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __rest
     R::group(gi, kind, q, pair);
     const int gbase = (tid & 63) - lg;
     const int rb = row_block_start<NAT>(g, blk, 2 * R::RP);
-    copy_batched<PX, NT>(tw, twx, tid);
-    R::F::template fill_tw<NT>(tws, twx, tid);
+    // the twiddle reads go out with the magnetisation reads below (one
+    // memory round trip); their LDS stores follow those of the rows
+    StagedCopy<PX, NT, float2> twc;
+    twc.load(twx, tid);
+    typename R::F::template TwFill<NT> twf;
+    twf.load(twx, tid);
     const int cur = st->cur;
     const float c1 = st->dtau * fa.a1;
     const int cs = g.ncells;
@@ -347,6 +351,8 @@ __device__ __forceinline__ void row_fwd_body(const Grid& g, const float2* __rest
             row[x] = ax; row[NXM + x] = ay; row[2 * NXM + x] = az;
         }
     }
+    twc.store(tw, tid);
+    twf.store(tws, tid);
     __syncthreads();
     R::template forward<NXM, NAT>(g, S, scr, tw, tws, nm, kind, q, pair, lg, gbase, rb);
 }
@@ -486,10 +492,16 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
     const bool stage = sa.mode == ROW_STAGE;
     const bool errm = sa.mode == ROW_ERROR || ((stage || sa.mode == ROW_KONLY) && sa.with_err);
 
-    // ---- global reads: twiddles, m rows rb-1 .. rb+2RP (y neighbours wrap
-    // on a periodic y axis), this group's class of the spectrum
-    copy_batched<PX, NT>(tw, twx, tid);
-    F::template fill_tw<NT>(tws, twx, tid);
+    // ---- global reads.  Every read of the prologue is issued before the
+    // first one is used (one memory round trip): the twiddles; the staged m
+    // rows rb-1 .. rb+2RP (y neighbours wrap on a periodic y axis); this
+    // group's class of the spectrum; m0 and the first round of the earlier
+    // stages' k at this thread's cells; the 3D z neighbours.  Then the LDS
+    // stores, the spectrum fix-ups and the k sums.
+    StagedCopy<PX, NT, float2> twc;
+    twc.load(twx, tid);
+    typename F::template TwFill<NT> twf;
+    twf.load(twx, tid);
     // staged row rq holds grid row rb - 1 + rq; NAT (3D): the halo rows serve
     // only as in-plane neighbours, the periodic y wrap and the z neighbours
     // come from global memory
@@ -499,57 +511,39 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         if (!NAT && g.pbc[1]) { row = row < 0 ? row + ny : (row >= ny ? row - ny : row); ok = true; }
         return row;
     };
-    if (BIG) {
-        // no staged rows: the per-cell work reads m from global memory
-    } else if ((nx & 3) == 0 && (cs & 3) == 0) {
-        // 16-byte loads: every (row, component) run of nx floats starts
-        // 16-byte aligned
-        // (the loads of up to eight iterations issued before their LDS stores)
-        const int n4 = nx >> 2;
-        constexpr int ITR = (R::NR * 3 * (NXM / 4) + NT - 1) / NT;
-        constexpr int CH = ITR < 8 ? ITR : 8;
+    // 16-byte loads where every (row, component) run of nx floats starts
+    // 16-byte aligned; BIG: no staged rows (the per-cell work reads m from
+    // global memory)
+    const bool vec4 = !BIG && (nx & 3) == 0 && (cs & 3) == 0;
+    const int n4 = nx >> 2;
+    constexpr int ITR = BIG ? 1 : (R::NR * 3 * (NXM / 4) + NT - 1) / NT;
+    constexpr bool ROW1 = ITR <= 8;   // the staged rows in the first round
+    auto row_load = [&](int t, float4& v, int& d) {
+        d = -1;
+        if (t >= R::NR * 3 * n4) return;
+        const int rq = t / (3 * n4), rem = t - rq * 3 * n4;
+        const int c = rem / n4, x4 = rem - c * n4;
+        bool ok;
+        const int row = staged_row(rq, ok);
+        v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ok) v = *reinterpret_cast<const float4*>(mi + (size_t)c * cs + (size_t)row * nx + 4 * x4);
+        d = rq * 3 * NXM + c * NXM + 4 * x4;
+    };
+    float4 rv[ROW1 ? ITR : 1];
+    int rd[ROW1 ? ITR : 1];
+    if (ROW1 && vec4) {
 #pragma unroll
-        for (int i0 = 0; i0 < ITR; i0 += CH) {
-            float4 v[CH];
-            int dst[CH];
-#pragma unroll
-            for (int ii = 0; ii < CH; ++ii) {
-                const int t = tid + (i0 + ii) * NT;
-                dst[ii] = -1;
-                if (i0 + ii < ITR && t < R::NR * 3 * n4) {
-                    const int rq = t / (3 * n4), rem = t - rq * 3 * n4;
-                    const int c = rem / n4, x4 = rem - c * n4;
-                    bool ok;
-                    const int row = staged_row(rq, ok);
-                    v[ii] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (ok) v[ii] = *reinterpret_cast<const float4*>(mi + (size_t)c * cs + (size_t)row * nx + 4 * x4);
-                    dst[ii] = rq * 3 * NXM + c * NXM + 4 * x4;
-                }
-            }
-#pragma unroll
-            for (int ii = 0; ii < CH; ++ii)
-                if (dst[ii] >= 0) *reinterpret_cast<float4*>(mrow + dst[ii]) = v[ii];
-        }
-    } else {
-        for (int rq = 0; rq < R::NR; ++rq) {
-            bool ok;
-            const int row = staged_row(rq, ok);
-            const float* src = mi + row * nx;
-            float* dst = mrow + rq * 3 * NXM;
-            for (int t = tid; t < 3 * nx; t += NT) {
-                const int c = t >= nx ? (t >= 2 * nx ? 2 : 1) : 0;
-                const int x = t - c * nx;
-                dst[c * NXM + x] = ok ? src[c * cs + x] : 0.f;
-            }
-        }
+        for (int it = 0; it < (ROW1 ? ITR : 1); ++it) row_load(tid + it * NT, rv[it], rd[it]);
     }
-    float2 z[E2];
-#pragma unroll
-    for (int i = 0; i < E2; ++i) z[i] = mk2(0.f, 0.f);
+    // X[k], k = NQ j + q, from the stored columns kx < PX/2 and the
+    // Hermitian symmetry X[PX - k] = conj X[k] of a real row (class
+    // (NQ - q) mod NQ, index LQ - j for q = 0, LQ - 1 - j otherwise): the
+    // loads (in the first round unless E2 > 8), then the conjugations and
+    // the packed DC / Nyquist column
+    const int scs = g.nrows * g.nkxp;
+    const float2* sa_ = nullptr;
+    const float2* sb_ = nullptr;
     if (p.demag_on) {
-        const int scs = g.nrows * g.nkxp;
-        const float2* sa_ = nullptr;
-        const float2* sb_ = nullptr;
         const int rs0 = NAT ? r0 * g.nkxp : (r0 << g.tsh);
         const int rs1 = NAT ? (r0 + 1) * g.nkxp : ((r0 + 1) << g.tsh);
         if (kind == 0) { if (v0) { sa_ = S + rs0; sb_ = sa_ + scs; } }
@@ -558,93 +552,114 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
             if (v0) sa_ = S + 2 * scs + rs0;
             if (v1) sb_ = S + 2 * scs + rs1;
         }
-        // X[k], k = NQ j + q, from the stored columns kx < PX/2 and the
-        // Hermitian symmetry X[PX - k] = conj X[k] of a real row (class
-        // (NQ - q) mod NQ, index LQ - j for q = 0, LQ - 1 - j otherwise).
-        // Every load first, the conjugations and the packed DC / Nyquist
-        // column after them.
-        // (in chunks of eight elements on the longest rows)
-        constexpr int CZ = E2 < 8 ? E2 : 8;
-#pragma unroll
-        for (int i0 = 0; i0 < E2; i0 += CZ) {
-        int colv[CZ];
-#pragma unroll
-        for (int ii = 0; ii < CZ; ++ii) {
-            const int i = i0 + ii;
-            const int j = lg + P * i;
-            const int k = NQ * j + q;
-            const bool up = k > PX / 2;
-            if (NAT) {
-                // natural layout: kx = 0 ... PX/2 stored, the rest conjugate
-                colv[ii] = up ? PX - k : k;
-            } else if (k == 0 || k == PX / 2) {
-                colv[ii] = 0;
-            } else {
-                const int sc = q == 0 ? (up ? LQ - j : j) : (up ? (NQ - q) * QC + LQ - 1 - j : q * QC + j);
-                colv[ii] = tile_index(0, sc, g.nrows, g.tsh);
-            }
-        }
-        float2 za[CZ], zb[CZ];
-#pragma unroll
-        for (int ii = 0; ii < CZ; ++ii) {
-            za[ii] = sa_ ? sa_[colv[ii]] : mk2(0.f, 0.f);
-            zb[ii] = sb_ ? sb_[colv[ii]] : mk2(0.f, 0.f);
-        }
-#pragma unroll
-        for (int ii = 0; ii < CZ; ++ii) {
-            const int i = i0 + ii;
-            const int k = NQ * (lg + P * i) + q;
-            float2 A = za[ii], B = zb[ii];
-            if (!NAT && (k == 0 || k == PX / 2)) {
-                const bool nyq = k != 0;
-                A = mk2(nyq ? A.y : A.x, 0.f);
-                B = mk2(nyq ? B.y : B.x, 0.f);
-            } else if (k > PX / 2) {
-                A.y = -A.y;
-                B.y = -B.y;
-            }
-            z[i] = mk2(A.x - B.y, A.y + B.x);
-        }
-        }
     }
-    // ---- the parts of the stage combination that do not depend on this
-    // stage's k: m0 + dtau sum_{j<s} a_j k_j and sum_{j<s} e_j k_j, for the
-    // cells this thread will handle, loaded while the transforms run
+    auto spec_col = [&](int i) {
+        const int j = lg + P * i;
+        const int k = NQ * j + q;
+        const bool up = k > PX / 2;
+        if (NAT) return up ? PX - k : k;   // natural layout: kx = 0 ... PX/2 stored, the rest conjugate
+        if (k == 0 || k == PX / 2) return 0;
+        const int sc = q == 0 ? (up ? LQ - j : j) : (up ? (NQ - q) * QC + LQ - 1 - j : q * QC + j);
+        return tile_index(0, sc, g.nrows, g.tsh);
+    };
+    auto spec_fix = [&](int i, float2 A, float2 B) {
+        const int k = NQ * (lg + P * i) + q;
+        if (!NAT && (k == 0 || k == PX / 2)) {
+            const bool nyq = k != 0;
+            A = mk2(nyq ? A.y : A.x, 0.f);
+            B = mk2(nyq ? B.y : B.x, 0.f);
+        } else if (k > PX / 2) {
+            A.y = -A.y;
+            B.y = -B.y;
+        }
+        return mk2(A.x - B.y, A.y + B.x);
+    };
+    constexpr int CZ = E2 < 8 ? E2 : 8;
+    constexpr bool Z1 = CZ == E2;
+    float2 za[CZ], zb[CZ];
+    auto spec_load = [&](int i0) {
+#pragma unroll
+        for (int ii = 0; ii < CZ; ++ii) {
+            const int col = spec_col(i0 + ii);
+            za[ii] = sa_ ? sa_[col] : mk2(0.f, 0.f);
+            zb[ii] = sb_ ? sb_[col] : mk2(0.f, 0.f);
+        }
+    };
+    if (p.demag_on) spec_load(0);
+    // the parts of the stage combination that do not depend on this stage's
+    // k: m0 + dtau sum_{j<s} a_j k_j and sum_{j<s} e_j k_j at this thread's
+    // cells.  Up to eight cells per thread: KB of the k's for ITC cells per
+    // memory round trip (at most KBUD values in flight), accumulated in
+    // stage order.  More cells (4096-point periodic rows): one after another.
     constexpr int MAXIT = (2 * RP * NXM + NT - 1) / NT;
     const int nrow = min(2 * RP, g.nrows - rb);
     const int ncb = nrow * nx;
     const float rnx = 1.0f / (float)nx;
     float px_[MAXIT], py_[MAXIT], pz_[MAXIT], ex_[MAXIT], ey_[MAXIT], ez_[MAXIT];
     float mnx[MAXIT], mny[MAXIT], mnz[MAXIT];   // the new stage state, held until the staged rows are free
-    // 3D: the z neighbours of this thread's cells, loaded while the
-    // transforms run
-    float zlo[MAXIT][3], zup[MAXIT][3];
-    unsigned zmask[MAXIT];
-#pragma unroll
-    for (int it = 0; it < MAXIT; ++it) {
-        zmask[it] = 0u;
-        if constexpr (NAT) {
-            const int e = tid + it * NT;
-            if (e < ncb) {
-                int ri, x;
-                split_cell(e, nx, rnx, ri, x);
-                int yr, zr;
-                plane_of(ri, yr, zr);
-                zmask[it] = z_neighbours(g, p, mi, rb + ri, zr, x, zlo[it], zup[it]);
-            }
-        }
-    }
-    // the stage state m0 and the earlier stages' k at this thread's cells.
-    // Up to eight cells per thread: KB of the k's for ITC cells per memory
-    // round trip (every load of a round issued before the first is used; at
-    // most 36 values in flight), accumulated in stage order.  More cells
-    // (4096-point periodic rows): one cell after another.
     constexpr int KP = kMaxK - 1;
     const int nprev = (stage || errm) ? sa.nk - 1 : 0;
     auto used = [&](int j) {
         return j < nprev && ((stage && dtau * sa.a[j] != 0.f) || (errm && sa.e[j] != 0.f));
     };
-    if constexpr (MAXIT > 8) {
+    constexpr bool KSER = MAXIT > 8;
+    // values in flight per round: fewer in 3D, whose blocks share a compute
+    // unit three at a time (and whose integrators combine few stages)
+    constexpr int KBUD = NAT ? 3 * MAXIT : 36;
+    constexpr int ITC = KSER ? 1 : (MAXIT * 3 <= KBUD ? MAXIT : KBUD / 3);
+    constexpr int KB0 = KBUD / (3 * ITC);
+    constexpr int KB = KB0 < 1 ? 1 : (KB0 > KP ? KP : KB0);
+    int qq_[KSER ? 1 : MAXIT];   // this thread's cells (-1: none)
+    auto k_load = [&](int i0, int j0, float (&kv)[KB][ITC][3]) {
+#pragma unroll
+        for (int jj = 0; jj < KB && j0 + jj < KP; ++jj) {
+            const int j = j0 + jj;
+            if (!used(j)) continue;
+            const float* __restrict__ kj = resolve(sa.kprev[j], cur);
+#pragma unroll
+            for (int ii = 0; ii < ITC && i0 + ii < MAXIT; ++ii) {
+                const int qq = qq_[KSER ? 0 : i0 + ii];
+                if (qq < 0) continue;
+                kv[jj][ii][0] = kj[qq]; kv[jj][ii][1] = kj[cs + qq]; kv[jj][ii][2] = kj[2 * cs + qq];
+            }
+        }
+    };
+    auto k_add = [&](int i0, int j0, const float (&kv)[KB][ITC][3]) {
+#pragma unroll
+        for (int jj = 0; jj < KB && j0 + jj < KP; ++jj) {
+            const int j = j0 + jj;
+            if (!used(j)) continue;
+            const float ca = stage ? dtau * sa.a[j] : 0.f;
+            const float ce = errm ? sa.e[j] : 0.f;
+#pragma unroll
+            for (int ii = 0; ii < ITC && i0 + ii < MAXIT; ++ii) {
+                const int it = i0 + ii;
+                if (qq_[KSER ? 0 : it] < 0) continue;
+                const float vx = kv[jj][ii][0], vy = kv[jj][ii][1], vz = kv[jj][ii][2];
+                if (ca != 0.f) { px_[it] += ca * vx; py_[it] += ca * vy; pz_[it] += ca * vz; }
+                if (ce != 0.f) { ex_[it] += ce * vx; ey_[it] += ce * vy; ez_[it] += ce * vz; }
+            }
+        }
+    };
+    // with the spectrum in several rounds (E2 > 8) the stage combination is
+    // read after it instead
+    constexpr bool EARLYK = Z1 && !KSER;
+    float kv0[KB][ITC][3];
+    auto m0_load = [&]() {
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) {
+            px_[it] = py_[it] = pz_[it] = ex_[it] = ey_[it] = ez_[it] = 0.f;
+            qq_[it] = -1;
+            const int e = tid + it * NT;
+            if (e >= ncb || !(stage || errm)) continue;
+            int ri, x;
+            split_cell(e, nx, rnx, ri, x);
+            const int qq = (rb + ri) * nx + x;
+            qq_[it] = qq;
+            if (stage) { px_[it] = m0[qq]; py_[it] = m0[cs + qq]; pz_[it] = m0[2 * cs + qq]; }
+        }
+    };
+    if constexpr (KSER) {
 #pragma unroll
         for (int it = 0; it < MAXIT; ++it) {
             px_[it] = py_[it] = pz_[it] = ex_[it] = ey_[it] = ez_[it] = 0.f;
@@ -664,56 +679,88 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
                 if (ce != 0.f) { ex_[it] += ce * vx; ey_[it] += ce * vy; ez_[it] += ce * vz; }
             }
         }
-    } else {
-        int qq_[MAXIT];   // this thread's cells (-1: none)
+    } else if constexpr (EARLYK) {
+        m0_load();
+        k_load(0, 0, kv0);
+    }
+    // 3D: the z neighbours of this thread's cells
+    float zlo[MAXIT][3], zup[MAXIT][3];
+    unsigned zmask[MAXIT];
 #pragma unroll
-        for (int it = 0; it < MAXIT; ++it) {
-            px_[it] = py_[it] = pz_[it] = ex_[it] = ey_[it] = ez_[it] = 0.f;
-            qq_[it] = -1;
+    for (int it = 0; it < MAXIT; ++it) {
+        zmask[it] = 0u;
+        if constexpr (NAT) {
             const int e = tid + it * NT;
-            if (e >= ncb || !(stage || errm)) continue;
-            int ri, x;
-            split_cell(e, nx, rnx, ri, x);
-            const int qq = (rb + ri) * nx + x;
-            qq_[it] = qq;
-            if (stage) { px_[it] = m0[qq]; py_[it] = m0[cs + qq]; pz_[it] = m0[2 * cs + qq]; }
+            if (e < ncb) {
+                int ri, x;
+                split_cell(e, nx, rnx, ri, x);
+                int yr, zr;
+                plane_of(ri, yr, zr);
+                zmask[it] = z_neighbours(g, p, mi, rb + ri, zr, x, zlo[it], zup[it]);
+            }
         }
-        constexpr int ITC = MAXIT * 3 <= 36 ? MAXIT : 12;
-        constexpr int KB0 = 36 / (3 * ITC);
-        constexpr int KB = KB0 < 1 ? 1 : (KB0 > KP ? KP : KB0);
+    }
+    // ---- LDS stores and fix-ups
+    twc.store(tw, tid);
+    twf.store(tws, tid);
+    if (ROW1 && vec4) {
+#pragma unroll
+        for (int it = 0; it < (ROW1 ? ITR : 1); ++it)
+            if (rd[it] >= 0) *reinterpret_cast<float4*>(mrow + rd[it]) = rv[it];
+    } else if (vec4) {
+        // longest staged rows: rounds of eight loads
+#pragma unroll
+        for (int i0 = 0; i0 < ITR; i0 += 8) {
+            float4 v[8];
+            int d[8];
+#pragma unroll
+            for (int ii = 0; ii < 8; ++ii) {
+                d[ii] = -1;
+                if (i0 + ii < ITR) row_load(tid + (i0 + ii) * NT, v[ii], d[ii]);
+            }
+#pragma unroll
+            for (int ii = 0; ii < 8; ++ii)
+                if (d[ii] >= 0) *reinterpret_cast<float4*>(mrow + d[ii]) = v[ii];
+        }
+    } else if (!BIG) {
+        for (int rq = 0; rq < R::NR; ++rq) {
+            bool ok;
+            const int row = staged_row(rq, ok);
+            const float* src = mi + row * nx;
+            float* dst = mrow + rq * 3 * NXM;
+            for (int t = tid; t < 3 * nx; t += NT) {
+                const int c = t >= nx ? (t >= 2 * nx ? 2 : 1) : 0;
+                const int x = t - c * nx;
+                dst[c * NXM + x] = ok ? src[c * cs + x] : 0.f;
+            }
+        }
+    }
+    float2 z[E2];
+#pragma unroll
+    for (int i = 0; i < E2; ++i) z[i] = mk2(0.f, 0.f);
+    if (p.demag_on) {
+#pragma unroll
+        for (int i0 = 0; i0 < E2; i0 += CZ) {
+            if (i0 > 0) spec_load(i0);   // the first round was read above
+#pragma unroll
+            for (int ii = 0; ii < CZ; ++ii) z[i0 + ii] = spec_fix(i0 + ii, za[ii], zb[ii]);
+        }
+    }
+    // the earlier stages' k: the first round (read above), then the rest
+    if constexpr (!KSER) {
+        if constexpr (!EARLYK) m0_load();
 #pragma unroll
         for (int i0 = 0; i0 < MAXIT; i0 += ITC) {
 #pragma unroll
             for (int j0 = 0; j0 < KP; j0 += KB) {
+                if (EARLYK && i0 == 0 && j0 == 0) {
+                    k_add(0, 0, kv0);
+                    continue;
+                }
                 if (j0 >= nprev) break;
                 float kv[KB][ITC][3];
-#pragma unroll
-                for (int jj = 0; jj < KB && j0 + jj < KP; ++jj) {
-                    const int j = j0 + jj;
-                    if (!used(j)) continue;
-                    const float* __restrict__ kj = resolve(sa.kprev[j], cur);
-#pragma unroll
-                    for (int ii = 0; ii < ITC && i0 + ii < MAXIT; ++ii) {
-                        const int qq = qq_[i0 + ii];
-                        if (qq < 0) continue;
-                        kv[jj][ii][0] = kj[qq]; kv[jj][ii][1] = kj[cs + qq]; kv[jj][ii][2] = kj[2 * cs + qq];
-                    }
-                }
-#pragma unroll
-                for (int jj = 0; jj < KB && j0 + jj < KP; ++jj) {
-                    const int j = j0 + jj;
-                    if (!used(j)) continue;
-                    const float ca = stage ? dtau * sa.a[j] : 0.f;
-                    const float ce = errm ? sa.e[j] : 0.f;
-#pragma unroll
-                    for (int ii = 0; ii < ITC && i0 + ii < MAXIT; ++ii) {
-                        const int it = i0 + ii;
-                        if (qq_[it] < 0) continue;
-                        const float vx = kv[jj][ii][0], vy = kv[jj][ii][1], vz = kv[jj][ii][2];
-                        if (ca != 0.f) { px_[it] += ca * vx; py_[it] += ca * vy; pz_[it] += ca * vz; }
-                        if (ce != 0.f) { ex_[it] += ce * vx; ey_[it] += ce * vy; ez_[it] += ce * vz; }
-                    }
-                }
+                k_load(i0, j0, kv);
+                k_add(i0, j0, kv);
             }
         }
     }
@@ -1010,6 +1057,8 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     float kv[ITK], nv[ITN];
     int xd[ITX];
     float2 twq[BIG ? 1 : E];
+    typename F::template TwFill<NT> twf;
+    twf.load(a.tw, tid);
     if constexpr (!BIG) {
 #pragma unroll
         for (int it = 0; it < ITX; ++it) {
@@ -1044,7 +1093,7 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
 #pragma unroll
         for (int i = 0; i < E; ++i) twq[i] = q ? a.tw[(lg + P * i) * q] : mk2(1.f, 0.f);
     }
-    F::template fill_tw<NT>(tws, a.tw, tid);
+    twf.store(tws, tid);
     if constexpr (!BIG) {
 #pragma unroll
         for (int it = 0; it < ITX; ++it)

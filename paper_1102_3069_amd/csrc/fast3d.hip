@@ -56,11 +56,11 @@ __device__ __forceinline__ void kernel6(const ColArgs& a, int kx, int ka, int ko
     const long long cstride = (long long)a.no_c * a.nkx * a.na_c;
     const long long off = ((long long)io * a.nkx + kx) * a.na_c + ia;
 #pragma unroll
+    for (int c = 0; c < 6; ++c) Kv[c] = a.K[c * cstride + off];
+#pragma unroll
     for (int c = 0; c < 6; ++c) {
-        float v = a.K[c * cstride + off];
-        if (fa && a.sign_a[c] < 0) v = -v;
-        if (fo && a.sign_o[c] < 0) v = -v;
-        Kv[c] = v;
+        if (fa && a.sign_a[c] < 0) Kv[c] = -Kv[c];
+        if (fo && a.sign_o[c] < 0) Kv[c] = -Kv[c];
     }
 }
 
@@ -106,8 +106,10 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
     // ---- the tile into the lines: n_in rows (zero beyond) into the h = 0
     // lines, or the H L stored frequencies into their half lines
     // (the loads of up to eight iterations issued before their LDS stores)
-    copy_batched<H * L, NT>(tw, a.tw, tid);
-    F::template fill_tw<NT>(tws, a.tw, tid);
+    StagedCopy<H * L, NT, float2> twc;
+    twc.load(a.tw, tid);
+    typename F::template TwFill<NT> twf;
+    twf.load(a.tw, tid);
     constexpr int NIN = MODE != COL_INV ? NC * L * TW : NC * H * L * TW;
     constexpr int ITI = (NIN + NT - 1) / NT, CH = ITI < 8 ? ITI : 8;
 #pragma unroll
@@ -130,6 +132,10 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
                 if (w < Wt) v[ii] = in[c * a.cs_in + k * a.as_in + w];
                 dst[ii] = T::line(c, w, k / L) + k % L;
             }
+        }
+        if (i0 == 0) {
+            twc.store(tw, tid);
+            twf.store(tws, tid);
         }
 #pragma unroll
         for (int ii = 0; ii < CH; ++ii)
@@ -171,12 +177,28 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
             }
             // consecutive threads take consecutive frequencies ka = H pos + hh,
             // so the kernel spectrum (stored along ka) is read in whole lines
-            for (int e = tid; e < TW * H * L; e += NT) {
+            // (the kernel values of up to three iterations read before their
+            // first use)
+            constexpr int ITP = (TW * H * L + NT - 1) / NT, CK = ITP < 3 ? ITP : 3;
+#pragma unroll
+            for (int i0 = 0; i0 < ITP; i0 += CK) {
+            float Kc[CK][6];
+#pragma unroll
+            for (int ii = 0; ii < CK; ++ii) {
+                const int e = tid + (i0 + ii) * NT;
+                if (i0 + ii >= ITP || e >= TW * H * L) continue;
+                const int ka = e % (H * L), ww = e / (H * L);
+                const int pos = ka / H, hh = ka % H;
+                if (ww < Wt) kernel6(a, kx0 + ww, H * pos + hh, ko, Kc[ii]);
+            }
+#pragma unroll
+            for (int ii = 0; ii < CK; ++ii) {
+                const int e = tid + (i0 + ii) * NT;
+                if (i0 + ii >= ITP || e >= TW * H * L) continue;
                 const int ka = e % (H * L), ww = e / (H * L);
                 const int pos = ka / H, hh = ka % H;
                 if (ww >= Wt) continue;
-                float Kv[6];
-                kernel6(a, kx0 + ww, H * pos + hh, ko, Kv);
+                const float* Kv = Kc[ii];
                 float2* px = X + T::line(0, ww, hh) + pos;
                 float2* py = X + T::line(1, ww, hh) + pos;
                 float2* pz = X + T::line(2, ww, hh) + pos;
@@ -188,6 +210,7 @@ __global__ __launch_bounds__((Tile3<L, E, TW, H, NC>::NT)) void col3_tiled(ColAr
                                   Kv[3] * Mx.y + Kv[1] * My.y + Kv[5] * Mz.y);
                 *pz = make_float2(Kv[4] * Mx.x + Kv[5] * My.x + Kv[2] * Mz.x,
                                   Kv[4] * Mx.y + Kv[5] * My.y + Kv[2] * Mz.y);
+            }
             }
             __syncthreads();
         }

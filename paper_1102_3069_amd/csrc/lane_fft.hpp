@@ -15,7 +15,7 @@
 // R-strided Stockham stores of a stage over distinct banks; each stage's
 // twiddles sit in a table of their own, ordered (r - 1) * Ns + k, so that
 // the lanes of a wavefront read consecutive (or equal) entries.  The caller
-// fills that table once per workgroup (fill_tw) from the table
+// fills that table once per workgroup (TwFill) from the table
 // exp(-2 pi i m / (L * TM)) it already holds (TM = 1 or 2 so that one table
 // serves both the half-length transforms of a zero-padded axis and its
 // pre/post twiddles).
@@ -139,28 +139,33 @@ struct LaneFFT {
         }
     }
     // the stage tables from the table full[m] = exp(-2 pi i m / (L TM)),
-    // by threads tid = 0 .. NT-1 of the workgroup (a barrier must follow);
-    // every load is issued before the first store
-    template <int NT, typename Src>
-    static __device__ __forceinline__ void fill_tw(C* __restrict__ tws, const Src* __restrict__ full, int tid) {
-        constexpr int IT = (TWS + NT - 1) / NT;
+    // by threads tid = 0 .. NT-1 of the workgroup (a barrier must follow),
+    // in two halves like StagedCopy: load() issues the reads, store()
+    // writes the tables
+    template <int NT>
+    struct TwFill {
+        static constexpr int IT = (TWS + NT - 1) / NT;
         C v[IT > 0 ? IT : 1];
+        template <typename Src>
+        __device__ __forceinline__ void load(const Src* __restrict__ full, int tid) {
 #pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            const int e = tid + it * NT;
-            if (e < TWS) {
-                int idx = 0;
-                tw_index<1>(e, idx);
-                v[it] = full[idx];
+            for (int it = 0; it < IT; ++it) {
+                const int e = tid + it * NT;
+                if (e < TWS) {
+                    int idx = 0;
+                    tw_index<1>(e, idx);
+                    v[it] = full[idx];
+                }
             }
         }
+        __device__ __forceinline__ void store(C* __restrict__ tws, int tid) const {
 #pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            const int e = tid + it * NT;
-            if (e < TWS) tws[e] = v[it];
+            for (int it = 0; it < IT; ++it) {
+                const int e = tid + it * NT;
+                if (e < TWS) tws[e] = v[it];
+            }
         }
-    }
-
+    };
     template <int S, bool INV>
     static __device__ __forceinline__ void stage(C (&x)[E], C* sc, const C* tws, int lg) {
         constexpr int R = lf_radix(L, E, S);
@@ -214,7 +219,7 @@ struct LaneFFT {
     }
 
     // unnormalised transform, forward (exp(-i...)) or inverse (exp(+i...));
-    // tws: the stage tables (fill_tw)
+    // tws: the stage tables (TwFill)
     template <bool INV>
     static __device__ __forceinline__ void run(C (&x)[E], C* sc, const C* tws, int lg) {
         stages<0, INV>(x, sc, tws, lg);
