@@ -63,6 +63,12 @@ __device__ __forceinline__ float2 partner_odd(const float2 (&z)[E], int i, int l
 // by cell in row order.
 // ---------------------------------------------------------------------------
 constexpr int lds_align(int b) { return (b + 15) / 16 * 16; }
+// the largest divisor of n that is at most c (chunks that tile n exactly)
+constexpr int divisor_upto(int n, int c) {
+    int d = c < n ? c : n;
+    while (n % d != 0) --d;
+    return d;
+}
 
 // first row of row block blk.  2D: blocks in row order.  3D (NAT) with whole
 // blocks per z plane: z fastest, so the blocks one XCD runs one after
@@ -574,7 +580,7 @@ __device__ __forceinline__ void row_inv_body(const Grid& g, const Phys& p, const
         }
         return mk2(A.x - B.y, A.y + B.x);
     };
-    constexpr int CZ = E2 < 8 ? E2 : 8;
+    constexpr int CZ = divisor_upto(E2, 8);
     constexpr bool Z1 = CZ == E2;
     float2 za[CZ], zb[CZ];
     auto spec_load = [&](int i0) {
@@ -1064,10 +1070,10 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
         for (int it = 0; it < ITX; ++it) {
             const int e = tid + it * NT;
             xd[it] = -1;
-            if (e < 3 * W * ny) {
+            if (e < 3 * W * L) {   // zeros at y >= ny
                 const int ww = e % W, t = e / W;
-                const int y = t % ny, cc = t / ny;
-                xv[it] = a.S[cc * cs + tile_index(y, lb * W + ww, ny, a.tsh)];
+                const int y = t % L, cc = t / L;
+                xv[it] = y < ny ? a.S[cc * cs + tile_index(y, lb * W + ww, ny, a.tsh)] : mk2(0.f, 0.f);
                 xd[it] = (cc * W + ww) * L + y;
             }
         }
@@ -1113,23 +1119,31 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     }
     __syncthreads();   // stage twiddles (and the staged columns)
     if constexpr (!BIG) {
+        // every LDS read first (the staged columns hold zeros at y >= ny;
+        // with four classes n + LC < L), then the class inputs and signs
         const float2* col = xst + (c * W + w) * L;
         const float* kc = kst + w * 4 * KL;
         const float* kl = kst + W * 4 * KL;
+        float2 va[E], vb[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int n = lg + P * i;
-            float2 v = n < ny ? col[n] : mk2(0.f, 0.f);
-            if (NQ == 4 && n + LC < ny) { const float2 t = rot4(col[n + LC], q); v.x += t.x; v.y += t.y; }
+            va[i] = col[n];
+            vb[i] = NQ == 4 ? col[n + LC] : mk2(0.f, 0.f);
+            const int ky = NQ * n + q;
+            const int iy = ky > Py - ky ? Py - ky : ky;
+            kd[i] = kc[c * KL + iy];
+            ko[i] = c < 2 ? kc[3 * KL + iy] : 0.f;
+            kn[i] = packed ? kl[c * KL + iy] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int n = lg + P * i;
+            float2 v = va[i];
+            if (NQ == 4) { const float2 t = rot4(vb[i], q); v.x += t.x; v.y += t.y; }
             x[i] = q ? cmul(v, twq[i]) : v;
             const int ky = NQ * n + q;
-            const bool flip = ky > Py - ky;
-            const int iy = flip ? Py - ky : ky;
-            kd[i] = kc[c * KL + iy];
-            ko[i] = 0.f;
-            kn[i] = 0.f;
-            if (c < 2) { const float kv = kc[3 * KL + iy]; ko[i] = flip ? -kv : kv; }
-            if (packed) kn[i] = kl[c * KL + iy];
+            if (ky > Py - ky) ko[i] = -ko[i];
         }
     }
     F::template run<false>(x, scr + gi * CF::SC, tws, lg);
@@ -1205,18 +1219,25 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     if (2 * q >= NQ) return;
     const int r = q;
     float2* dst = a.S + c * cs + tile_index(0, scol, ny, a.tsh);
+    // (the LDS reads of four elements issued before their sums)
+    constexpr int CE = divisor_upto(E, 4);
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int n = lg + P * i;
-        const int y = n + r * LC;
-        if (y < ny) {
-            float2 s = xch[CF::slot(c, 0, w) * LC + n];
+    for (int i0 = 0; i0 < E; i0 += CE) {
+        float2 u[CE][NQ];
+#pragma unroll
+        for (int ii = 0; ii < CE; ++ii)
+#pragma unroll
+            for (int cq = 0; cq < NQ; ++cq) u[ii][cq] = xch[CF::slot(c, cq, w) * LC + lg + P * (i0 + ii)];
+#pragma unroll
+        for (int ii = 0; ii < CE; ++ii) {
+            const int y = lg + P * (i0 + ii) + r * LC;
+            float2 s = u[ii][0];
 #pragma unroll
             for (int cq = 1; cq < NQ; ++cq) {
-                const float2 t = rot4(xch[CF::slot(c, cq, w) * LC + n], -(r * cq * (4 / NQ)));
+                const float2 t = rot4(u[ii][cq], -(r * cq * (4 / NQ)));
                 s.x += t.x; s.y += t.y;
             }
-            dst[y << a.tsh] = s;
+            if (y < ny) dst[y << a.tsh] = s;
         }
     }
 }
