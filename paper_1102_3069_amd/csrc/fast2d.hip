@@ -1029,25 +1029,28 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     // odd in ky): diagonal kd, off-diagonal ko (x, y), Nyquist column kn
     float kd[E], ko[E], kn[E];
     float2 x[E];
+    float2 twb = mk2(1.f, 0.f);   // BIG: the lane's twiddle W^(lg q)
     const float2* src = a.S + c * cs + tile_index(0, scol, ny, a.tsh);
     if constexpr (BIG) {
         // ---- global reads, per lane: this group's column (zero beyond ny;
         // blocks n + r LC for r < NQ/2) and its pre-twiddles, combined into
         // the class input as they arrive; the kernel values follow the
         // forward transform (fewer live registers through it)
-        float2 v0[E], v1[E], tv[E];
+        // (the pre-twiddle W^(yq), y = lg + P i, as W^(lg q) W^(P i q): one
+        // read per lane, the second factor the same for the whole wavefront)
+        float2 v0[E], v1[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int y = lg + P * i;
             v0[i] = y < ny ? src[y << a.tsh] : mk2(0.f, 0.f);
             v1[i] = (NQ == 4 && y + LC < ny) ? src[(y + LC) << a.tsh] : mk2(0.f, 0.f);
-            tv[i] = q ? a.tw[y * q] : mk2(1.f, 0.f);
         }
+        twb = q ? a.tw[lg * q] : mk2(1.f, 0.f);
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             float2 v = v0[i];
             if (NQ == 4) { const float2 t = rot4(v1[i], q); v.x += t.x; v.y += t.y; }
-            x[i] = q ? cmul(v, tv[i]) : v;
+            x[i] = q ? cmul(v, cmul(twb, a.tw[P * i * q])) : v;
         }
     }
     // not BIG: the global reads shared by the block through LDS, its W
@@ -1208,11 +1211,11 @@ __device__ __forceinline__ void col2d_body(const Col2dArgs& a, DevState* __restr
     __syncthreads();   // every group has read the exchange (and left the scratch)
     {
         float2* xo = xch + CF::slot(c, q, w) * LC;
-        float2 tp[E];   // post-twiddles (BIG: from global memory, all loads first)
 #pragma unroll
-        for (int i = 0; i < E; ++i) tp[i] = BIG ? (q ? a.tw[(lg + P * i) * q] : mk2(1.f, 0.f)) : twq[BIG ? 0 : i];
-#pragma unroll
-        for (int i = 0; i < E; ++i) xo[lg + P * i] = q ? cmul(x[i], cconj(tp[i])) : x[i];
+        for (int i = 0; i < E; ++i) {
+            const float2 t = BIG ? cmul(twb, a.tw[P * i * q]) : twq[BIG ? 0 : i];
+            xo[lg + P * i] = q ? cmul(x[i], cconj(t)) : x[i];
+        }
     }
     __syncthreads();
     // outputs y = n + r LC: the group of class r (r < NQ/2) assembles them
