@@ -103,18 +103,22 @@ __global__ void mfma_selftest_kernel(const u16* A, const u16* B, float* C) {
 // forward convolution (also the data gradient with transposed weights)
 //   in   [N][H][W][32] bf16, wt [9][32 cout][32 cin] bf16, bias [32] (may be null)
 //   z    [N][H][W][32] float (pre-activation, may be null)
+//   zb   [N][H][W][32] bf16 (pre-activation kept for the backward pass, may be null)
 //   a    [N][H][W][32] bf16 (SiLU(z) if act, else z; may be null)
-//   zg   [N][H][W][32] float (may be null): data-gradient mode, a is then
+//   zg   [N][H][W][32] bf16 (may be null): data-gradient mode, a is then
 //        z times SiLU'(zg), the gradient at the previous layer's pre-activation
 // block: 4 waves, 64 pixels of `rows` consecutive rows; a wave: 16 pixels x
 // 32 channels per row, with the weight fragments of all nine taps held in
-// registers across the rows
+// registers across the rows.  The bf16 tiles (a, zb, zg) pass through LDS so
+// that every lane reads or writes 16 contiguous bytes (8 channels of one
+// pixel).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ in, const u16* __restrict__ wt,
                                                        const float* __restrict__ bias, float* __restrict__ z,
-                                                       u16* __restrict__ a, const float* __restrict__ zg, int H,
-                                                       int W, int act, int rows) {
+                                                       u16* __restrict__ zb, u16* __restrict__ a,
+                                                       const u16* __restrict__ zg, int H, int W, int act, int rows) {
     __shared__ u16 ws[9 * CH * CH];
+    __shared__ u16 tile[4][2][16 * CH];   // per wave: [0] a, [1] zb or zg; [pixel][channel]
     const int tid = threadIdx.x;
     for (int i = tid; i < 9 * CH * CH / 8; i += 256)
         reinterpret_cast<uint4*>(ws)[i] = reinterpret_cast<const uint4*>(wt)[i];
@@ -124,6 +128,10 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ i
     const int x0 = blockIdx.x * 64 + wave * 16;
     const int col = lane % 16, kg = lane / 16;
     const size_t img = (size_t)n * H * W;
+    u16* ta = tile[wave][0];
+    u16* tz = tile[wave][1];
+    // the lane's 16-byte chunk of a tile row: pixel lane / 4, channels 8 (lane % 4)
+    const int cpx = lane >> 2, cch = 8 * (lane & 3);
     bf16x8 B0[9], B1[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
@@ -132,42 +140,86 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ i
     }
     const float bias0 = bias ? bias[col] : 0.f, bias1 = bias ? bias[16 + col] : 0.f;
     const int ya = blockIdx.y * rows, yb = min(ya + rows, H);
+    // the A fragments of input rows y-1, y, y+1 (taps v = 0, 1, 2) roll down
+    // the rows; the next input row is read while this row's epilogue runs.
+    // Every lane reads (outside the image: the nearest pixel inside), so that
+    // no load is conditional and the waits stay exact; a row's fragments
+    // outside the image are zeroed in place once they have arrived.
+    auto load_row = [&](int yy, bf16x8 (&dst)[3]) {
+        const int yc = min(max(yy, 0), H - 1);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const int xc = min(max(x0 + col + v - 1, 0), W - 1);
+            dst[v] = load8(in + ((img + (size_t)yc * W + xc) * CH + 8 * kg));
+        }
+    };
+    auto mask_row = [&](int yy, bf16x8 (&r)[3]) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const int xx = x0 + col + v - 1;
+            if (!(yy >= 0 && yy < H && xx >= 0 && xx < W)) r[v] = zero8();
+        }
+    };
+    bf16x8 Ar[3][3];
+    load_row(ya - 1, Ar[0]);
+    load_row(ya, Ar[1]);
+    load_row(ya + 1, Ar[2]);
+    mask_row(ya - 1, Ar[0]);
+    mask_row(ya, Ar[1]);
     for (int y = ya; y < yb; ++y) {
+        mask_row(y + 1, Ar[2]);
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
 #pragma unroll
         for (int u = 0; u < 3; ++u) {
-            const int yy = y + u - 1;
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
-                const int xx = x0 + col + v - 1;
-                bf16x8 A = zero8();
-                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    A = load8(in + ((img + (size_t)yy * W + xx) * CH + 8 * kg));
-                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B0[u * 3 + v], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B1[u * 3 + v], acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar[u][v], B0[u * 3 + v], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar[u][v], B1[u * 3 + v], acc1, 0, 0, 0);
             }
         }
+        const size_t crow = (img + (size_t)y * W + x0 + cpx) * CH + cch;   // the lane's chunk in global memory
+        const bool cin = x0 + cpx < W;
+        uint4 gch = make_uint4(0, 0, 0, 0);
+        if (zg) gch = *reinterpret_cast<const uint4*>(zg + (img + (size_t)y * W + min(x0 + cpx, W - 1)) * CH + cch);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            Ar[0][v] = Ar[1][v];
+            Ar[1][v] = Ar[2][v];
+        }
+        load_row(y + 1 < yb ? y + 2 : H, Ar[2]);   // (row H: zeros, nothing read)
+        if (zg) *reinterpret_cast<uint4*>(tz + cpx * CH + cch) = gch;
+        __builtin_amdgcn_wave_barrier();
         // C layout: lane holds channels col and 16 + col of pixel 4 kg + r
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int x = x0 + 4 * kg + r;
-            if (x >= W) continue;
-            const size_t p = (img + (size_t)y * W + x) * CH;
+            const int px = 4 * kg + r;
             const float v0 = acc0[r] + bias0, v1 = acc1[r] + bias1;
-            if (z) { z[p + col] = v0; z[p + 16 + col] = v1; }
-            if (a) {
-                float o0 = v0, o1 = v1;
-                if (zg) {
-                    o0 *= silu_grad(zg[p + col]);
-                    o1 *= silu_grad(zg[p + 16 + col]);
-                } else if (act) {
-                    o0 = silu(v0);
-                    o1 = silu(v1);
-                }
-                a[p + col] = f2bf(o0);
-                a[p + 16 + col] = f2bf(o1);
+            if (z && x0 + px < W) {
+                const size_t p = (img + (size_t)y * W + x0 + px) * CH;
+                z[p + col] = v0;
+                z[p + 16 + col] = v1;
+            }
+            float o0 = v0, o1 = v1;
+            if (zg) {
+                o0 *= silu_grad(bf2f(tz[px * CH + col]));
+                o1 *= silu_grad(bf2f(tz[px * CH + 16 + col]));
+            } else if (act) {
+                o0 = silu(v0);
+                o1 = silu(v1);
+            }
+            ta[px * CH + col] = f2bf(o0);
+            ta[px * CH + 16 + col] = f2bf(o1);
+            if (zb) {
+                tz[px * CH + col] = f2bf(v0);
+                tz[px * CH + 16 + col] = f2bf(v1);
             }
         }
+        __builtin_amdgcn_wave_barrier();
+        if (cin) {
+            if (a) *reinterpret_cast<uint4*>(a + crow) = *reinterpret_cast<const uint4*>(ta + cpx * CH + cch);
+            if (zb) *reinterpret_cast<uint4*>(zb + crow) = *reinterpret_cast<const uint4*>(tz + cpx * CH + cch);
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -576,12 +628,12 @@ int wg_blocks(const llg_sur* s, int N) {
 
 // convolution rows per forward block: blocks of 64 pixels by `rows` rows,
 // about 2048 of them, at most 16 rows
-void launch_conv(llg_sur* s, const u16* in, const u16* wt, const float* bias, float* z, u16* a, const float* zg,
-                 int N, int act) {
+void launch_conv(llg_sur* s, const u16* in, const u16* wt, const float* bias, float* z, u16* zb, u16* a,
+                 const u16* zg, int N, int act) {
     const long long rb = (long long)((s->W + 63) / 64) * s->H * N;
     const int rows = (int)std::min<long long>(16, std::max<long long>(1, rb / 2048));
     hipLaunchKernelGGL(conv_fwd_kernel, dim3((s->W + 63) / 64, (s->H + rows - 1) / rows, N), dim3(256), 0,
-                       s->stream, in, wt, bias, z, a, zg, s->H, s->W, act, rows);
+                       s->stream, in, wt, bias, z, zb, a, zg, s->H, s->W, act, rows);
 }
 
 // weight and bias gradient of one layer from the pre-activation gradient
@@ -609,9 +661,10 @@ llg_status pack(llg_sur* s) {
     return LLG_OK;
 }
 
-// keep_z: keep every layer's pre-activation (training needs them); else
-// only the last layer's (the output) is written
-llg_status forward(llg_sur* s, const float* m, const float* B, int N, bool keep_z) {
+// keep_z: keep every hidden layer's pre-activation as bf16 for the backward
+// pass (in the first half of its float buffer); the last layer's (the
+// output) and that of layer f32_layer are written as float
+llg_status forward(llg_sur* s, const float* m, const float* B, int N, bool keep_z, int f32_layer = NL - 1) {
     const size_t npx = (size_t)N * s->H * s->W;
     hipLaunchKernelGGL(make_input_kernel, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s->stream, m, B,
                        s->act[0], N, s->H, s->W);
@@ -619,8 +672,10 @@ llg_status forward(llg_sur* s, const float* m, const float* B, int N, bool keep_
     for (int l = 0; l < NL; ++l) {
         // the bias of a layer with fewer than 32 outputs is read through a
         // zero-padded 32-entry copy kept in the gradient buffer's tail
-        launch_conv(s, s->act[l], s->wf[l], s->params + s->boff[l], keep_z || l == NL - 1 ? s->z[l] : nullptr,
-                    l < NL - 1 ? s->act[l + 1] : nullptr, nullptr, N, l < NL - 1 ? 1 : 0);
+        const bool f32 = l == NL - 1 || l == f32_layer;
+        launch_conv(s, s->act[l], s->wf[l], s->params + s->boff[l], f32 ? s->z[l] : nullptr,
+                    keep_z && !f32 ? reinterpret_cast<u16*>(s->z[l]) : nullptr, l < NL - 1 ? s->act[l + 1] : nullptr,
+                    nullptr, N, l < NL - 1 ? 1 : 0);
         SCHK(s, hipGetLastError());
     }
     return LLG_OK;
@@ -819,7 +874,8 @@ llg_status llg_sur_train_step(llg_sur* s, const float* m_in, const float* m_targ
             // data gradient: the same convolution with flipped, transposed
             // weights, times SiLU'(z) of layer l - 1 (every hidden layer has
             // the activation)
-            launch_conv(s, gcur, s->wtr[l], nullptr, nullptr, gnext, s->z[l - 1], batch, 0);
+            launch_conv(s, gcur, s->wtr[l], nullptr, nullptr, nullptr, gnext, reinterpret_cast<const u16*>(s->z[l - 1]),
+                        batch, 0);
             SCHK(s, hipGetLastError());
             std::swap(gcur, gnext);
         }
@@ -882,7 +938,7 @@ llg_status llg_sur_forward_raw(llg_sur* s, const float* m_in, const float* B, in
     const size_t npx = (size_t)batch * s->H * s->W;
     SCHK(s, hipMemcpyAsync(s->dm_in, m_in, npx * 3 * 4, hipMemcpyHostToDevice, s->stream));
     SCHK(s, hipMemcpyAsync(s->dB, B, (size_t)batch * 3 * 4, hipMemcpyHostToDevice, s->stream));
-    llg_status rc = forward(s, s->dm_in, s->dB, batch, true);
+    llg_status rc = forward(s, s->dm_in, s->dB, batch, false, layer);
     if (rc != LLG_OK) return rc;
     SCHK(s, hipMemcpyAsync(z_out, s->z[layer], npx * CH * 4, hipMemcpyDeviceToHost, s->stream));
     SCHK(s, hipStreamSynchronize(s->stream));
@@ -904,7 +960,7 @@ llg_status llg_sur_conv_check(llg_sur* s, int layer, const float* x, const float
     SCHK(s, hipMemcpyAsync(s->g, x, n * 4, hipMemcpyHostToDevice, s->stream));
     hipLaunchKernelGGL(to_bf16_kernel, dim3(nb), dim3(256), 0, s->stream, s->g, s->act[0], n);
     SCHK(s, hipGetLastError());
-    launch_conv(s, s->act[0], s->wf[layer], s->params + s->boff[layer], s->z[0], nullptr, nullptr, batch, 0);
+    launch_conv(s, s->act[0], s->wf[layer], s->params + s->boff[layer], s->z[0], nullptr, nullptr, nullptr, batch, 0);
     SCHK(s, hipGetLastError());
     SCHK(s, hipMemcpyAsync(y, s->z[0], n * 4, hipMemcpyDeviceToHost, s->stream));
     if (gy) {
@@ -919,7 +975,7 @@ llg_status llg_sur_conv_check(llg_sur* s, int layer, const float* x, const float
         hipLaunchKernelGGL(unpack_grad_kernel, dim3((COUT[layer] * CIN[layer] * 9 + 255) / 256), dim3(256), 0,
                            s->stream, s->gwp, CIN[layer], COUT[layer], dgw);
         SCHK(s, hipGetLastError());
-        launch_conv(s, s->gz, s->wtr[layer], nullptr, s->z[1], nullptr, nullptr, batch, 0);
+        launch_conv(s, s->gz, s->wtr[layer], nullptr, s->z[1], nullptr, nullptr, nullptr, batch, 0);
         SCHK(s, hipGetLastError());
         SCHK(s, hipMemcpyAsync(gx, s->z[1], n * 4, hipMemcpyDeviceToHost, s->stream));
         SCHK(s, hipMemcpyAsync(gw, dgw, sizeof(float) * COUT[layer] * CIN[layer] * 9, hipMemcpyDeviceToHost,
