@@ -4,6 +4,17 @@ optionally the per-kernel HBM traffic file that bench.py reports.
 
 usage: python paper_1102_3069_amd/prof/summarize.py <kernel_stats.csv>
            [fetch.csv write.csv copy_fetch.csv copy_write.csv copy_bytes [traffic.json]]
+       python paper_1102_3069_amd/prof/summarize.py --busy <kernel_trace.csv> <pattern> <last_kernel> <count>
+       python paper_1102_3069_amd/prof/summarize.py --counters <counter_collection.csv> [<pattern>]
+
+--counters: the mean per dispatch of every counter of every kernel (whose
+name contains <pattern>) in a counter-collection file.
+
+--busy: over the last <count> intervals that end with a kernel whose name
+contains <last_kernel> (one attempt of a batch each), the union of the
+intervals of every kernel whose name contains <pattern> or <last_kernel>,
+against the span and the sum of their durations (how busy the GPU was and
+how much the launches overlapped).
 
 The plain copy of `bench.py --workload copy` moves copy_bytes per dispatch; the ratio of
 that to what its counters read is the scale applied to every kernel.  The
@@ -70,5 +81,45 @@ def main(argv):
                            "kernels": traffic}, f, indent=1)
 
 
+def busy(path, pattern, last, count):
+    rows = list(csv.DictReader(open(path)))
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in rows)
+    ends = [i for i, x in enumerate(iv) if last in x[2]]
+    if len(ends) < count + 1:
+        raise SystemExit(f"only {len(ends)} kernels match {last!r}")
+    first, end = ends[-count - 1] + 1, ends[-1] + 1
+    sel = [x for x in iv[first:end] if pattern in x[2] or last in x[2]]
+    t0, t1 = sel[0][0], max(e for _, e, _ in sel)
+    union, cs, ce = 0, None, None
+    for s_, e, _ in sel:
+        if ce is None or s_ > ce:
+            if ce is not None:
+                union += ce - cs
+            cs, ce = s_, e
+        else:
+            ce = max(ce, e)
+    union += ce - cs
+    total = sum(e - s_ for s_, e, _ in sel)
+    print(f"{count} intervals, {len(sel)} kernels: span {(t1 - t0) / 1e3:.1f} us "
+          f"({(t1 - t0) / 1e3 / count:.1f} us each), busy (union of kernel intervals) {union / 1e3:.1f} us "
+          f"= {union / (t1 - t0):.3f} of the span, sum of kernel durations {total / 1e3:.1f} us "
+          f"(overlap factor {total / union:.2f})")
+
+
+def counters(path, pattern=""):
+    d = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(path)):
+        if pattern in r["Kernel_Name"]:
+            d[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    for k, cs in d.items():
+        means = ", ".join(f"{c} {sum(v) / len(v):.0f}" for c, v in sorted(cs.items()))
+        print(f"* `{k[:90]}`: {means}")
+
+
 if __name__ == "__main__":
-    main(sys.argv)
+    if len(sys.argv) in (3, 4) and sys.argv[1] == "--counters":
+        counters(sys.argv[2], sys.argv[3] if len(sys.argv) == 4 else "")
+    elif len(sys.argv) == 6 and sys.argv[1] == "--busy":
+        busy(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]))
+    else:
+        main(sys.argv)
