@@ -54,6 +54,8 @@ __host__ __device__ inline u16 f2bf(float f) {
     u += 0x7fffu + ((u >> 16) & 1u);
     return (u16)(u >> 16);
 }
+// the same rounding by the hardware conversion (v_cvt_pk_bf16_f32)
+__device__ inline u16 f2bf_hw(float f) { return __builtin_bit_cast(u16, (__bf16)f); }
 __host__ __device__ inline float bf2f(u16 h) {
     uint32_t u = (uint32_t)h << 16;
     float f;
@@ -74,9 +76,12 @@ __device__ inline bf16x8 zero8() {
     return r;
 }
 
-__device__ inline float silu(float z) { return z / (1.0f + expf(-z)); }
+// SiLU and its derivative on the hardware exp2 and reciprocal (about 1 ulp
+// each; every result is rounded to BF16 afterwards, 2^-9)
+__device__ inline float sigmoid_hw(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ inline float silu(float z) { return z * sigmoid_hw(z); }
 __device__ inline float silu_grad(float z) {
-    const float s = 1.0f / (1.0f + expf(-z));
+    const float s = sigmoid_hw(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -207,11 +212,11 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ i
                 o0 = silu(v0);
                 o1 = silu(v1);
             }
-            ta[px * CH + col] = f2bf(o0);
-            ta[px * CH + 16 + col] = f2bf(o1);
+            ta[px * CH + col] = f2bf_hw(o0);
+            ta[px * CH + 16 + col] = f2bf_hw(o1);
             if (zb) {
-                tz[px * CH + col] = f2bf(v0);
-                tz[px * CH + 16 + col] = f2bf(v1);
+                tz[px * CH + col] = f2bf_hw(v0);
+                tz[px * CH + 16 + col] = f2bf_hw(v1);
             }
         }
         __builtin_amdgcn_wave_barrier();
