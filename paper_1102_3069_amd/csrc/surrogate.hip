@@ -39,6 +39,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16;
 
 constexpr int CH = 32;          // padded channel count of every activation
+constexpr int KC = 4;           // channels of the compact network output (3 used)
 constexpr int NL = 6;           // layers
 constexpr int CIN[NL] = {9, 32, 32, 32, 32, 32};
 constexpr int COUT[NL] = {32, 32, 32, 32, 32, 3};
@@ -108,6 +109,7 @@ __global__ void mfma_selftest_kernel(const u16* A, const u16* B, float* C) {
 // forward convolution (also the data gradient with transposed weights)
 //   in   [N][H][W][32] bf16, wt [9][32 cout][32 cin] bf16, bias [32] (may be null)
 //   z    [N][H][W][32] float (pre-activation, may be null)
+//   zc   [N][H][W][4] float (its first four channels: the network output, may be null)
 //   zb   [N][H][W][32] bf16 (pre-activation kept for the backward pass, may be null)
 //   a    [N][H][W][32] bf16 (SiLU(z) if act, else z; may be null)
 //   zg   [N][H][W][32] bf16 (may be null): data-gradient mode, a is then
@@ -120,7 +122,7 @@ __global__ void mfma_selftest_kernel(const u16* A, const u16* B, float* C) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ in, const u16* __restrict__ wt,
                                                        const float* __restrict__ bias, float* __restrict__ z,
-                                                       u16* __restrict__ zb, u16* __restrict__ a,
+                                                       float* __restrict__ zc, u16* __restrict__ zb, u16* __restrict__ a,
                                                        const u16* __restrict__ zg, int H, int W, int act, int rows) {
     __shared__ u16 ws[9 * CH * CH];
     __shared__ u16 tile[4][2][16 * CH];   // per wave: [0] a, [1] zb or zg; [pixel][channel]
@@ -204,6 +206,7 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ i
                 z[p + col] = v0;
                 z[p + 16 + col] = v1;
             }
+            if (zc && col < KC && x0 + px < W) zc[(img + (size_t)y * W + x0 + px) * KC + col] = v0;
             float o0 = v0, o1 = v1;
             if (zg) {
                 o0 *= silu_grad(bf2f(tz[px * CH + col]));
@@ -442,7 +445,7 @@ __global__ void loss_kernel(const float* zout, const float* base, const float* m
         uint32_t gb[3];
         for (int c = 0; c < 3; ++c) {
             const size_t q = ((size_t)n * 3 + c) * H * W + p;
-            const float d = zout[i * CH + c] - (mt[q] - base[q]) * inv_scale;
+            const float d = zout[i * KC + c] - (mt[q] - base[q]) * inv_scale;
             l += d * d;
             gb[c] = f2bf(2.0f * d * inv);
         }
@@ -484,7 +487,7 @@ __global__ void propose_kernel(const float* base, const float* zout, float* mo, 
     const int n = (int)(i / ((size_t)H * W));
     const size_t p = i - (size_t)n * H * W;
     float v[3];
-    for (int c = 0; c < 3; ++c) v[c] = base[((size_t)n * 3 + c) * H * W + p] + scale * zout[i * CH + c];
+    for (int c = 0; c < 3; ++c) v[c] = base[((size_t)n * 3 + c) * H * W + p] + scale * zout[i * KC + c];
     const float inv = rsqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     for (int c = 0; c < 3; ++c) mo[((size_t)n * 3 + c) * H * W + p] = v[c] * inv;
 }
@@ -633,12 +636,12 @@ int wg_blocks(const llg_sur* s, int N) {
 
 // convolution rows per forward block: blocks of 64 pixels by `rows` rows,
 // about 2048 of them, at most 16 rows
-void launch_conv(llg_sur* s, const u16* in, const u16* wt, const float* bias, float* z, u16* zb, u16* a,
+void launch_conv(llg_sur* s, const u16* in, const u16* wt, const float* bias, float* z, float* zc, u16* zb, u16* a,
                  const u16* zg, int N, int act) {
     const long long rb = (long long)((s->W + 63) / 64) * s->H * N;
     const int rows = (int)std::min<long long>(16, std::max<long long>(1, rb / 2048));
     hipLaunchKernelGGL(conv_fwd_kernel, dim3((s->W + 63) / 64, (s->H + rows - 1) / rows, N), dim3(256), 0,
-                       s->stream, in, wt, bias, z, zb, a, zg, s->H, s->W, act, rows);
+                       s->stream, in, wt, bias, z, zc, zb, a, zg, s->H, s->W, act, rows);
 }
 
 // weight and bias gradient of one layer from the pre-activation gradient
@@ -667,9 +670,10 @@ llg_status pack(llg_sur* s) {
 }
 
 // keep_z: keep every hidden layer's pre-activation as bf16 for the backward
-// pass (in the first half of its float buffer); the last layer's (the
-// output) and that of layer f32_layer are written as float
-llg_status forward(llg_sur* s, const float* m, const float* B, int N, bool keep_z, int f32_layer = NL - 1) {
+// pass (in the first half of its float buffer).  The last layer's (the
+// network output) is written compact, four float channels per pixel, unless
+// f32_layer asks for it; layer f32_layer's is written as float, 32 channels
+llg_status forward(llg_sur* s, const float* m, const float* B, int N, bool keep_z, int f32_layer = -1) {
     const size_t npx = (size_t)N * s->H * s->W;
     hipLaunchKernelGGL(make_input_kernel, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s->stream, m, B,
                        s->act[0], N, s->H, s->W);
@@ -677,10 +681,10 @@ llg_status forward(llg_sur* s, const float* m, const float* B, int N, bool keep_
     for (int l = 0; l < NL; ++l) {
         // the bias of a layer with fewer than 32 outputs is read through a
         // zero-padded 32-entry copy kept in the gradient buffer's tail
-        const bool f32 = l == NL - 1 || l == f32_layer;
-        launch_conv(s, s->act[l], s->wf[l], s->params + s->boff[l], f32 ? s->z[l] : nullptr,
-                    keep_z && !f32 ? reinterpret_cast<u16*>(s->z[l]) : nullptr, l < NL - 1 ? s->act[l + 1] : nullptr,
-                    nullptr, N, l < NL - 1 ? 1 : 0);
+        const bool f32 = l == f32_layer, out = l == NL - 1 && !f32;
+        launch_conv(s, s->act[l], s->wf[l], s->params + s->boff[l], f32 ? s->z[l] : nullptr, out ? s->z[l] : nullptr,
+                    keep_z && l < NL - 1 && !f32 ? reinterpret_cast<u16*>(s->z[l]) : nullptr,
+                    l < NL - 1 ? s->act[l + 1] : nullptr, nullptr, N, l < NL - 1 ? 1 : 0);
         SCHK(s, hipGetLastError());
     }
     return LLG_OK;
@@ -879,8 +883,8 @@ llg_status llg_sur_train_step(llg_sur* s, const float* m_in, const float* m_targ
             // data gradient: the same convolution with flipped, transposed
             // weights, times SiLU'(z) of layer l - 1 (every hidden layer has
             // the activation)
-            launch_conv(s, gcur, s->wtr[l], nullptr, nullptr, nullptr, gnext, reinterpret_cast<const u16*>(s->z[l - 1]),
-                        batch, 0);
+            launch_conv(s, gcur, s->wtr[l], nullptr, nullptr, nullptr, nullptr, gnext,
+                        reinterpret_cast<const u16*>(s->z[l - 1]), batch, 0);
             SCHK(s, hipGetLastError());
             std::swap(gcur, gnext);
         }
@@ -965,7 +969,8 @@ llg_status llg_sur_conv_check(llg_sur* s, int layer, const float* x, const float
     SCHK(s, hipMemcpyAsync(s->g, x, n * 4, hipMemcpyHostToDevice, s->stream));
     hipLaunchKernelGGL(to_bf16_kernel, dim3(nb), dim3(256), 0, s->stream, s->g, s->act[0], n);
     SCHK(s, hipGetLastError());
-    launch_conv(s, s->act[0], s->wf[layer], s->params + s->boff[layer], s->z[0], nullptr, nullptr, nullptr, batch, 0);
+    launch_conv(s, s->act[0], s->wf[layer], s->params + s->boff[layer], s->z[0], nullptr, nullptr, nullptr, nullptr,
+                batch, 0);
     SCHK(s, hipGetLastError());
     SCHK(s, hipMemcpyAsync(y, s->z[0], n * 4, hipMemcpyDeviceToHost, s->stream));
     if (gy) {
@@ -980,7 +985,7 @@ llg_status llg_sur_conv_check(llg_sur* s, int layer, const float* x, const float
         hipLaunchKernelGGL(unpack_grad_kernel, dim3((COUT[layer] * CIN[layer] * 9 + 255) / 256), dim3(256), 0,
                            s->stream, s->gwp, CIN[layer], COUT[layer], dgw);
         SCHK(s, hipGetLastError());
-        launch_conv(s, s->gz, s->wtr[layer], nullptr, s->z[1], nullptr, nullptr, nullptr, batch, 0);
+        launch_conv(s, s->gz, s->wtr[layer], nullptr, s->z[1], nullptr, nullptr, nullptr, nullptr, batch, 0);
         SCHK(s, hipGetLastError());
         SCHK(s, hipMemcpyAsync(gx, s->z[1], n * 4, hipMemcpyDeviceToHost, s->stream));
         SCHK(s, hipMemcpyAsync(gw, dgw, sizeof(float) * COUT[layer] * CIN[layer] * 9, hipMemcpyDeviceToHost,
