@@ -251,20 +251,26 @@ constexpr int WG_SEG = 64;         // segments of the first reduction stage
 constexpr int NWG = 9 * CH * CH;   // weight-gradient entries of one layer
 
 // pixels xs + 4 q .. xs + 4 q + 3 of row y, channels 8 cg .. 8 cg + 7, into
-// dst[channel][4 q + i] (zero outside the image)
-__device__ inline void stage_quad(u16* dst, const u16* __restrict__ src, size_t img, int H, int W, int y, int xs,
-                                  int q, int cg) {
-    unsigned w[4][4];
+// dst[channel][4 q + i] (zero outside the image), in two halves: the reads
+// into registers, then the transposed LDS stores
+__device__ inline void load_quad(uint4 (&v)[4], const u16* __restrict__ src, size_t img, int H, int W, int y, int xs,
+                                 int q, int cg) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int x = xs + 4 * q + i;
-        uint4 v = make_uint4(0, 0, 0, 0);
+        v[i] = make_uint4(0, 0, 0, 0);
         if (y >= 0 && y < H && x >= 0 && x < W)
-            v = *reinterpret_cast<const uint4*>(src + (img + (size_t)y * W + x) * CH + 8 * cg);
-        w[i][0] = v.x;
-        w[i][1] = v.y;
-        w[i][2] = v.z;
-        w[i][3] = v.w;
+            v[i] = *reinterpret_cast<const uint4*>(src + (img + (size_t)y * W + x) * CH + 8 * cg);
+    }
+}
+__device__ inline void store_quad(u16* dst, const uint4 (&v)[4], int q, int cg) {
+    unsigned w[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        w[i][0] = v[i].x;
+        w[i][1] = v[i].y;
+        w[i][2] = v[i].z;
+        w[i][3] = v[i].w;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -277,6 +283,12 @@ __device__ inline void stage_quad(u16* dst, const u16* __restrict__ src, size_t 
         *reinterpret_cast<uint2*>(dst + (8 * cg + 2 * k) * WG_LD + 4 * q) = lo;
         *reinterpret_cast<uint2*>(dst + (8 * cg + 2 * k + 1) * WG_LD + 4 * q) = hi;
     }
+}
+__device__ inline void stage_quad(u16* dst, const u16* __restrict__ src, size_t img, int H, int W, int y, int xs,
+                                  int q, int cg) {
+    uint4 v[4];
+    load_quad(v, src, img, H, W, y, xs, q, cg);
+    store_quad(dst, v, q, cg);
 }
 
 __global__ __launch_bounds__(256) void conv_wgrad_kernel(const u16* __restrict__ gz, const u16* __restrict__ ain,
@@ -302,17 +314,21 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(const u16* __restrict__
         const int r = ya - 1 + tid / 64;
         stage_quad(aT + ((r + 3) % 3) * CH * WG_LD, ain, img, H, W, r, x0, (tid / 4) % 16, tid % 4);
     }
+    // per row y: gT[v][co][px] = gz[y][x0 + px + 1 - v] (threads < 192) and
+    // input row y + 1 into its ring slot (the others); the reads of the next
+    // row's share go out before this row's MFMAs
+    auto load_share = [&](int y, uint4 (&v)[4]) {
+        if (tid < 192) load_quad(v, gz, img, H, W, y, x0 + 1 - tid / 64, (tid / 4) % 16, tid % 4);
+        else load_quad(v, ain, img, H, W, y + 1, x0, (tid - 192) / 4, (tid - 192) % 4);
+    };
+    uint4 share[4];
+    load_share(ya, share);
     for (int y = ya; y < yb; ++y) {
         __syncthreads();
-        if (tid < 192) {
-            // gT[v][co][px] = gz[y][x0 + px + 1 - v]
-            const int v = tid / 64;
-            stage_quad(gT + v * CH * WG_LD, gz, img, H, W, y, x0 + 1 - v, (tid / 4) % 16, tid % 4);
-        } else {
-            const int t = tid - 192;
-            stage_quad(aT + ((y + 1) % 3) * CH * WG_LD, ain, img, H, W, y + 1, x0, t / 4, t % 4);
-        }
+        if (tid < 192) store_quad(gT + (tid / 64) * CH * WG_LD, share, (tid / 4) % 16, tid % 4);
+        else store_quad(aT + ((y + 1) % 3) * CH * WG_LD, share, (tid - 192) / 4, (tid - 192) % 4);
         __syncthreads();
+        if (y + 1 < yb) load_share(y + 1, share);
         {
             const u16* g1 = gT + CH * WG_LD + (tid >> 3) * WG_LD + 8 * (tid & 7);
 #pragma unroll
