@@ -10,7 +10,9 @@ controller, replayed from a captured HIP graph.  The metric counts
 cell-updates = cells x H_eff evaluations per second, with all inputs already
 resident in HBM.
 
-Prints one JSON line; see DESIGN.md for the byte model behind "roofline".
+Prints one JSON line.  "roofline" divides the algorithmic bytes of the
+dominant kernel (what it must read and write: the magnetisation, the spectra,
+the kernel spectrum, the fields; llg_kernel_bytes) by its mean duration.
 """
 import argparse
 import json
@@ -565,8 +567,9 @@ def full_run(llg, prob, m0, run):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build measures one GPU, and "
-              "how the path would shard over several is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the path is measured on one GPU's "
+              "share; a film split over several GPUs needs an all-to-all transpose around the spectral pass, "
+              "which is not built", file=sys.stderr)
         sys.exit(2)
     if args.workload == "surrogate":
         return bench_surrogate(args)

@@ -30,8 +30,7 @@ that they follow:
                    Runge-Kutta integrators listed in Sec. 2.2 (Euler, Heun,
                    classical RK4, Dormand-Prince 5(4) with step control).
 
-Parity unpinned (pinned only by self-consistency, see the design doc's list of
-readings): the exact step-size sequence of the adaptive controller, the
-specific random stream beyond the Philox known-answer vectors, and anything
-the learned surrogate proposes.
+Parity unpinned (pinned only by self-consistency): the exact step-size
+sequence of the adaptive controller, the specific random stream beyond the
+Philox known-answer vectors, and anything the learned surrogate proposes.
 """

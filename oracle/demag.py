@@ -12,7 +12,7 @@ convolution of M with a cell-to-cell kernel, accelerated by zero-padded FFTs
     H_d(r_i) = -Ms * sum_j N(r_i - r_j) . m_j,
 
 with X = r_i - r_j.  The paper does not print a formula for N; this oracle
-reads it as follows (each reading is listed in the design doc):
+reads it as follows:
 
 * offsets within NEAR_CELLS cells (max-norm, in cells): the closed form of
   Newell, Williams & Dunlop (J. Geophys. Res. 98, 9551, 1993), a signed
