@@ -193,8 +193,10 @@ def _kernel_name(kind, px, py, variants):
 # kernel names of the 3D path (256 x 256 x 64 block: x periodic of 256,
 # y periodic of 256, z open of 2 x 64), per kernel kind
 def _kernel_name_3d(kind):
-    return {"row_fwd": "row_fwd_fast<256, ", "spectral": "col3_tiled<64, 8, 4, 2, 3, 1>",
-            "row_inv": "row_inv_fast<256, ", "y_fwd": "col3_tiled<256, 16, 16, 1, 1, 0>",
+    """Full template names of the 3D block's kernels (x periodic 256, the
+    default variants; z open 64, y periodic 256)."""
+    return {"row_fwd": "row_fwd_fast<256, 4, 2, true, true>", "spectral": "col3_tiled<64, 8, 4, 2, 3, 1>",
+            "row_inv": "row_inv_fast<256, 4, 2, true, true>", "y_fwd": "col3_tiled<256, 16, 16, 1, 1, 0>",
             "y_inv": "col3_tiled<256, 16, 16, 1, 1, 2>"}.get(kind)
 
 
