@@ -589,7 +589,9 @@ struct llg_sur {
     u16* wf[NL] = {};                          // bf16 forward weights
     u16* wtr[NL] = {};                         // bf16 transposed/flipped weights
     u16* act[NL] = {};                         // layer inputs (bf16, 32 ch)
-    float* z[NL] = {};                         // pre-activations (float, 32 ch)
+    float* z[NL] = {};                         // pre-activations: bf16 32 ch kept for the backward pass
+                                               // (hidden layers), float 4 ch (network output) or float
+                                               // 32 ch (parity checks)
     float* g = nullptr;                        // gradient w.r.t. a layer's output (float, 32 ch)
     u16* gz = nullptr;                         // gradient w.r.t. pre-activation (bf16)
     u16* gz2 = nullptr;                        // the same for the layer below (ping-pong)
@@ -954,8 +956,9 @@ llg_status llg_sur_predict(llg_sur* s, const float* m_in, const float* m_base, c
     return LLG_OK;
 }
 
-// the pre-activation of the last layer (the net's dm before padding) for a
-// batch, [batch][H][W][32] float into host memory; for parity checks
+// the pre-activation of layer `layer` (the last one: the net's dm before
+// padding) for a batch, [batch][H][W][32] float into host memory; for parity
+// checks
 llg_status llg_sur_forward_raw(llg_sur* s, const float* m_in, const float* B, int batch, int layer, float* z_out) {
     if (!s || !m_in || !B || !z_out || batch < 1 || batch > s->maxb || layer < 0 || layer >= NL) return LLG_E_ARG;
     SCHK(s, hipSetDevice(s->device));
