@@ -30,7 +30,10 @@ that they follow:
                    Runge-Kutta integrators listed in Sec. 2.2 (Euler, Heun,
                    classical RK4, Dormand-Prince 5(4) with step control).
 
-Parity unpinned (pinned only by self-consistency): the exact step-size
-sequence of the adaptive controller, the specific random stream beyond the
-Philox known-answer vectors, and anything the learned surrogate proposes.
+Parity unpinned (pinned only by self-consistency): which Philox counter a
+cell and step draw from (a convention; the generator itself is pinned by
+its known-answer vectors, the draws by their moments), and anything the
+learned surrogate proposes.  The adaptive controller's step sequence is
+pinned against scipy's independent Dormand-Prince and Bogacki-Shampine
+solvers.
 """
