@@ -287,6 +287,21 @@ llg_status llg_kernel_bytes(llg_solver *s, double *bytes_out, int n_kinds);
  * defaults for its lengths, directly (LLG_E_ARG if the pair cannot serve the
  * geometry). */
 llg_status llg_autotune(llg_solver *s, int iters, double *ms_out, int n_out, int *choice);
+/* As llg_autotune, but each pair is timed on what llg_run with LLG_RKDP45
+ * does (Sec. 2.2's adaptive Dormand-Prince 5(4), whose stage kernels also
+ * take the Runge-Kutta combinations and the next forward transform): from
+ * the solver's current state, two untimed attempts (graph capture), then
+ * `attempts` timed ones with tolerance max_err, the first of step dt0 (s;
+ * 0: the controller's next step, LLG_E_STATE if there is none).  Every pair
+ * starts from the same state, and afterwards the solver holds that state
+ * again (m, time, controller, statistics and attempt log as before the
+ * call; the next run evaluates its first stage anew).  ms_out[2r + c]
+ * receives milliseconds per attempt (-1 if the pair cannot serve this
+ * geometry).  Allocates one device copy of m for the duration of the call.
+ * LLG_E_ARG unless attempts >= 1, max_err > 0 and dt0 >= 0; other errors as
+ * llg_autotune. */
+llg_status llg_autotune_attempts(llg_solver *s, double max_err, double dt0, int attempts, double *ms_out,
+                                 int n_out, int *choice);
 llg_status llg_set_variants(llg_solver *s, int row_var, int col_var);
 /* The solver's (row, column) variant pair.  LLG_E_UNSUPPORTED unless the
  * geometry is 2D with compiled lengths. */

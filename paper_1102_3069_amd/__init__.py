@@ -119,6 +119,9 @@ _SIGNATURES = {
     "llg_kernel_bytes": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
     "llg_autotune": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                       ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "llg_autotune_attempts": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+                              ctypes.c_int),
     "llg_set_variants": ([_P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "llg_get_variants": ([_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "llg_variant_shape": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -371,6 +374,15 @@ class Solver:
         ms = (ctypes.c_double * 4)()
         ch = (ctypes.c_int * 2)()
         self._chk(self._lib.llg_autotune(self._h, int(iters), ms, 4, ch))
+        return {(r, c): ms[2 * r + c] for r in range(2) for c in range(2)}, (ch[0], ch[1])
+
+    def autotune_attempts(self, max_err, dt0, attempts=50):
+        """Times the compiled (row, column) variant pairs on adaptive
+        Dormand-Prince attempts from the current state (which is kept);
+        returns ({(r, c): ms per attempt}, (r, c) chosen)."""
+        ms = (ctypes.c_double * 4)()
+        ch = (ctypes.c_int * 2)()
+        self._chk(self._lib.llg_autotune_attempts(self._h, float(max_err), float(dt0), int(attempts), ms, 4, ch))
         return {(r, c): ms[2 * r + c] for r in range(2) for c in range(2)}, (ch[0], ch[1])
 
     def set_variants(self, row_var, col_var):

@@ -144,6 +144,10 @@ struct llg_solver {
     bool k1_valid = false;     // kfs[cur] holds f(m) for the adaptive method
     double last_dt = 0.0;
     Graph gfix, gdp, gdm;
+    // the done flag of the last two launched chunks of step graphs, copied to
+    // pinned host memory behind each chunk (launch_until_done)
+    int* hflag = nullptr;
+    hipEvent_t flag_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -435,6 +439,38 @@ llg_status restore_done(llg_solver* s, int was) {
     return write_state(s, &h);
 }
 
+// Launches a captured step graph in chunks of eight until the device state's
+// done flag is set or `max_launches` graphs have been launched (< 0: no
+// limit), then waits for the stream.  Behind each chunk the flag is copied
+// to pinned host memory and an event recorded; the host reads a chunk's
+// flag only after the next chunk is queued, so the device never waits for
+// the host between chunks.  Graphs launched after the flag was set do
+// nothing (every kernel of a step returns at once while it is set).
+llg_status launch_until_done(llg_solver* s, hipGraphExec_t exec, long long max_launches) {
+    constexpr int kChunk = 8;
+    long long launched = 0;
+    int pend = -1, slot = 0;
+    for (;;) {
+        int nl = kChunk;
+        if (max_launches >= 0 && max_launches - launched < nl) nl = (int)(max_launches - launched);
+        if (max_launches < 0 && launched > (1LL << 32)) nl = 0;
+        if (nl > 0) {
+            for (int i = 0; i < nl; ++i) HIPCHK(s, hipGraphLaunch(exec, s->stream));
+            launched += nl;
+            HIPCHK(s, hipMemcpyAsync(&s->hflag[slot], &s->st->done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+            HIPCHK(s, hipEventRecord(s->flag_ev[slot], s->stream));
+        }
+        if (pend >= 0) {
+            HIPCHK(s, hipEventSynchronize(s->flag_ev[pend]));
+            if (s->hflag[pend]) break;
+        }
+        if (nl <= 0) break;
+        pend = slot;
+        slot ^= 1;
+    }
+    return sync(s);
+}
+
 // H_eff of m (mbuf[cur]) into `out` (device); tracks spectrum validity
 llg_status eval_into(llg_solver* s, float* out, const Phys& p) {
     llg_status rc;
@@ -673,6 +709,9 @@ llg_status llg_create(int device, void* hip_stream, llg_solver** out) {
     s->user = (hipStream_t)hip_stream;
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&s->sync_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->flag_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->flag_ev[1], hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc(&s->hflag, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipMalloc(&s->st, sizeof(DevState)) != hipSuccess ||
         hipMalloc(&s->dflag, sizeof(int)) != hipSuccess) {
         llg_destroy(s);
@@ -695,6 +734,9 @@ void llg_destroy(llg_solver* s) {
     free_dev(s->st);
     free_dev(s->dflag);
     if (s->sync_ev) (void)hipEventDestroy(s->sync_ev);
+    for (auto& e : s->flag_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->hflag) (void)hipHostFree(s->hflag);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -1081,14 +1123,7 @@ llg_status llg_run_dm(llg_solver* s, llg_method method, double t_end, double max
         if ((rc = capture(s, s->gdm, enqueue_dm_step, tf, p)) != LLG_OK) return rc;
         s->gdm.method = (int)method;
     }
-    int done = 0;
-    long long launched = 0;
-    while (!done && launched < (1LL << 32)) {
-        for (int i = 0; i < 8; ++i) HIPCHK(s, hipGraphLaunch(s->gdm.exec, s->stream));
-        launched += 8;
-        HIPCHK(s, hipMemcpyAsync(&done, &s->st->done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-        if ((rc = sync(s)) != LLG_OK) return rc;
-    }
+    if ((rc = launch_until_done(s, s->gdm.exec, -1)) != LLG_OK) return rc;
     if ((rc = read_state(s, &h)) != LLG_OK) return rc;
     s->spec_valid = p.demag_on != 0;
     s->k1_valid = false;
@@ -1334,6 +1369,94 @@ llg_status llg_autotune(llg_solver* s, int iters, double* ms_out, int n_out, int
     return restore_done(s, was);
 }
 
+llg_status llg_autotune_attempts(llg_solver* s, double max_err, double dt0, int attempts, double* ms_out,
+                                 int n_out, int* choice) {
+    TraceRange trace_("llg_autotune_attempts");
+    llg_status rc = enter(s);
+    if (rc != LLG_OK) return rc;
+    if (attempts < 1 || !(max_err > 0) || !isfinite(max_err) || !(dt0 >= 0) || !isfinite(dt0))
+        return fail(s, LLG_E_ARG, "need attempts >= 1, max_err > 0, dt0 >= 0");
+    if ((rc = ready(s, true)) != LLG_OK) return rc;
+    if ((rc = ensure_kernel(s)) != LLG_OK) return rc;
+    if (!s->fast2d) return fail(s, LLG_E_UNSUPPORTED, "no compiled variants for this geometry");
+    const Phys p = make_phys(s, 0.0);
+    if (!p.demag_on) return fail(s, LLG_E_STATE, "tuning needs the demag term");
+    DevState h0;
+    if ((rc = read_state(s, &h0)) != LLG_OK) return rc;
+    if (h0.health) return fail(s, LLG_E_DIVERGED, "state already diverged");
+    if (dt0 == 0 && !(h0.dt_next > 0)) return fail(s, LLG_E_STATE, "dt0 = 0 needs an earlier adaptive step");
+    const double dt_first = dt0 > 0 ? dt0 : h0.dt_next;
+    // every pair starts from the state as it is now: m saved here, the
+    // record restored before each run (the attempt log and statistics with
+    // it); t_end far enough ahead that no run is clipped
+    const double t_end = h0.t + 1e30;
+    const size_t bytes = sizeof(float) * 3 * (size_t)s->g.ncells;
+    float* msave = nullptr;
+    HIPCHK(s, hipMalloc(&msave, bytes));
+    struct Free {
+        float* p;
+        ~Free() { free_dev(p); }
+    } free_msave{msave};
+    HIPCHK(s, hipMemcpyAsync(msave, s->mbuf[h0.cur], bytes, hipMemcpyDeviceToDevice, s->stream));
+    auto restore = [&](bool final) -> llg_status {
+        HIPCHK(s, hipMemcpyAsync(s->mbuf[0], msave, bytes, hipMemcpyDeviceToDevice, s->stream));
+        DevState h = h0;
+        h.cur = 0;
+        h.done = final ? h0.done : 0;
+        h.err_bits = 0u;
+        s->spec_valid = false;
+        s->k1_valid = false;
+        return write_state(s, &h);
+    };
+    const int Px = s->g.Px, L = s->g.Py / 2;
+    const int r0 = s->g.rvar, c0 = s->g.cvar;
+    double best = 1e300;
+    int br = r0, bc = c0;
+    hipEvent_t e0, e1;
+    HIPCHK(s, hipEventCreate(&e0));
+    HIPCHK(s, hipEventCreate(&e1));
+    for (int rv = 0; rv < 2 && rc == LLG_OK; ++rv) {
+        for (int cv = 0; cv < 2 && rc == LLG_OK; ++cv) {
+            const int k = rv * 2 + cv;
+            if (ms_out && k < n_out) ms_out[k] = -1.0;
+            if (!fast2d_row_ok(Px, rv, s->g.nx == Px) || !fast2d_col_ok(L, 1, cv) ||
+                (Px / 2) % fast2d_col_width(L, cv))
+                continue;
+            s->g.rvar = rv;
+            s->g.cvar = cv;
+            invalidate_graphs(s);
+            // untimed: two attempts (the graph capture), then back to the
+            // start state and its first stage; timed: `attempts` attempts
+            if ((rc = restore(false)) != LLG_OK) break;
+            if ((rc = run_adaptive(s, LLG_RKDP45, t_end, max_err, dt_first, 2, nullptr)) != LLG_OK) break;
+            if ((rc = restore(false)) != LLG_OK) break;
+            if ((rc = ensure_k1(s, p)) != LLG_OK) break;
+            if (hipEventRecord(e0, s->stream) != hipSuccess) { rc = fail(s, LLG_E_DEVICE, "event record"); break; }
+            if ((rc = run_adaptive(s, LLG_RKDP45, t_end, max_err, dt_first, attempts, nullptr)) != LLG_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = fail(s, LLG_E_DEVICE, "event timing");
+                break;
+            }
+            const double per = ms / attempts;
+            if (ms_out && k < n_out) ms_out[k] = per;
+            if (per < best) { best = per; br = rv; bc = cv; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    s->g.rvar = rc == LLG_OK ? br : r0;
+    s->g.cvar = rc == LLG_OK ? bc : c0;
+    invalidate_graphs(s);
+    const llg_status rr = restore(true);
+    if (rc != LLG_OK) return rc;
+    if (rr != LLG_OK) return rr;
+    (void)fast2d_set_variants(Px, br, L, bc, s->g.nx == Px);   // default for solvers set up later
+    if (choice) { choice[0] = br; choice[1] = bc; }
+    return LLG_OK;
+}
+
 llg_status llg_set_variants(llg_solver* s, int row_var, int col_var) {
     llg_status rc = enter(s);
     if (rc != LLG_OK) return rc;
@@ -1491,24 +1614,7 @@ llg_status run_adaptive(llg_solver* s, int method, double t_end, double max_err,
         if ((rc = capture(s, s->gdp, ad.fsal ? fsal_body : plain_body, ad.t, p)) != LLG_OK) return rc;
         s->gdp.method = method;
     }
-    const long long a0 = h.nattempt;
-    const int chunk = 8;
-    int done = 0;
-    long long launched = 0;
-    while (!done) {
-        int nl = chunk;
-        if (max_attempts > 0) {
-            const long long left = max_attempts - launched;
-            if (left <= 0) break;
-            if (left < nl) nl = (int)left;
-        }
-        for (int i = 0; i < nl; ++i) HIPCHK(s, hipGraphLaunch(s->gdp.exec, s->stream));
-        launched += nl;
-        HIPCHK(s, hipMemcpyAsync(&done, &s->st->done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-        if ((rc = sync(s)) != LLG_OK) return rc;
-        if (max_attempts < 0 && launched > (1LL << 32)) break;
-    }
-    (void)a0;
+    if ((rc = launch_until_done(s, s->gdp.exec, max_attempts > 0 ? max_attempts : -1)) != LLG_OK) return rc;
     if ((rc = read_state(s, &h)) != LLG_OK) return rc;
     // the state buffers now hold the accepted solution; the x spectrum and
     // k1 buffers follow the last accepted attempt only

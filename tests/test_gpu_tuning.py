@@ -69,6 +69,42 @@ def test_autotune_times_all_pairs(lib, reset_table):
     assert maxrel(s.eval_heff(), ref) <= 1e-5
 
 
+def test_autotune_attempts_keeps_the_state(lib, default_variants):
+    """The attempt-timed tuner (Sec. 2.2's adaptive Dormand-Prince, the
+    benchmarked step) times every pair, keeps the fastest, and leaves m,
+    time, controller, statistics and attempt log as they were; the run that
+    follows equals, bit for bit, a fresh solver restored to the same state
+    with the chosen pair."""
+    prob, m0, run = workloads.film_512(512)
+    s = lib.Solver(0)
+    s.set_problem(prob)
+    s.set_m(m0)
+    s.run_attempts(run["t_end"], run["tol"], run["dt0"], 3)
+    st0, mb = s.get_state()
+    log0 = s.attempts()
+    ms, choice = s.autotune_attempts(run["tol"], 0.0, 8)
+    print("autotune_attempts 512x512:", ms, "->", choice, flush=True)
+    assert all(v > 0 for v in ms.values())
+    assert ms[choice] == min(ms.values())
+    assert s.get_variants() == choice
+    st1, ma = s.get_state()
+    assert st1 == st0
+    assert np.array_equal(ma, mb)
+    assert s.attempts() == log0
+    s.run_attempts(run["t_end"], run["tol"], 0.0, 4)
+    f = lib.Solver(0)
+    f.set_problem(prob)
+    f.set_state(st0, mb)
+    f.set_variants(*choice)
+    f.run_attempts(run["t_end"], run["tol"], 0.0, 4)
+    assert np.array_equal(s.get_m(), f.get_m())
+    assert s.stats()["t"] == f.stats()["t"]
+    with pytest.raises(lib.LLGError):
+        s.autotune_attempts(run["tol"], 0.0, 0)
+    s.close()
+    f.close()
+
+
 def test_batch_follows_the_table(lib, reset_table):
     rng = np.random.default_rng(3)
     films = []
