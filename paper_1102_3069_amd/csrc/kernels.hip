@@ -489,43 +489,60 @@ __global__ void ctrl_fixed_group_kernel(DevState* states, int nfilms, int evals)
 }
 
 // Dormand-Prince step control: accept if err <= tol, next step
-// dt * clamp(0.9 (tol/err)^(1/5), 0.2, 5), last step lands on t_end.
+// dt * clamp(0.9 (tol/err)^(1/5), 0.2, 5), last step lands on t_end.  The
+// record is read into registers in one round of loads, updated there and
+// written back once (the single thread would otherwise wait on one global
+// read after another).
 __device__ void dp45_control(DevState* st) {
-    if (st->done) return;
-    const float errf = __uint_as_float(st->err_bits);
-    st->err_bits = 0u;
+    DevState h = *st;
+    // a finished run is left as it is: the decisions below are computed
+    // either way (register arithmetic only) and the stores skipped, so that
+    // every load of the record is issued before the first branch
+    const bool live = !h.done;
+    const float errf = __uint_as_float(h.err_bits);
     const double err = (double)errf;
-    const double h = st->dt;
-    st->nevals += st->ev_attempt;
-    st->last_err = err;
-    const bool ok = (st->health == 0) && (err <= st->tol);
-    const long long a = st->nattempt++;
-    if (a < st->log_cap && st->log) {
+    const double dt_att = h.dt;
+    h.err_bits = 0u;
+    h.nevals += h.ev_attempt;
+    h.last_err = err;
+    const bool ok = (h.health == 0) && (err <= h.tol);
+    const long long a = h.nattempt++;
+    if (h.health) {
+        h.done = 1;
+    } else {
+        if (ok) {
+            h.t = h.clipped ? h.t_end : h.t + dt_att;
+            h.cur ^= 1;
+            h.step += 1;
+            h.nsteps += 1;
+        } else {
+            h.nrej += 1;
+        }
+        double f = (err == 0.0) ? 5.0 : 0.9 * pow(h.tol / err, h.ctrl_exp);
+        f = fmin(5.0, fmax(0.2, f));
+        const double dn = dt_att * f;
+        h.dt_next = dn;
+        if (dn < h.dt_min) {
+            h.health |= 2;
+            h.done = 1;
+        } else if (ok && h.clipped) {
+            h.done = 1;
+        } else {
+            const double rem = h.t_end - h.t;
+            if (dn >= rem) { h.dt = rem; h.clipped = 1; }
+            else { h.dt = dn; h.clipped = 0; }
+            h.dtau = (float)(h.dt * h.gms);
+        }
+    }
+    if (!live) return;
+    if (a < h.log_cap && h.log) {
         llg_attempt r;
-        r.dt = h;
+        r.dt = dt_att;
         r.err = errf;
         r.accepted = ok ? 1 : 0;
-        st->log[a] = r;
+        h.log[a] = r;
     }
-    if (st->health) { st->done = 1; return; }
-    if (ok) {
-        st->t = st->clipped ? st->t_end : st->t + h;
-        st->cur ^= 1;
-        st->step += 1;
-        st->nsteps += 1;
-    } else {
-        st->nrej += 1;
-    }
-    double f = (err == 0.0) ? 5.0 : 0.9 * pow(st->tol / err, st->ctrl_exp);
-    f = fmin(5.0, fmax(0.2, f));
-    const double dn = h * f;
-    st->dt_next = dn;
-    if (dn < st->dt_min) { st->health |= 2; st->done = 1; return; }
-    if (ok && st->clipped) { st->done = 1; return; }
-    const double rem = st->t_end - st->t;
-    if (dn >= rem) { st->dt = rem; st->clipped = 1; }
-    else { st->dt = dn; st->clipped = 0; }
-    st->dtau = (float)(st->dt * st->gms);
+    *st = h;
 }
 
 __global__ void ctrl_dp45_kernel(DevState* st) {
