@@ -12,7 +12,9 @@ resident in HBM.
 
 Prints one JSON line.  "roofline" divides the algorithmic bytes of the
 dominant kernel (what it must read and write: the magnetisation, the spectra,
-the kernel spectrum, the fields; llg_kernel_bytes) by its mean duration.
+the kernel spectrum, the fields; llg_kernel_bytes) by its mean duration, timed
+by HIP events attached to each of its launches (the kernel's own execution,
+as a profiler's kernel trace measures it; llg_profile_evals).
 """
 import argparse
 import json
@@ -623,8 +625,8 @@ def main():
     attempts = (st1["steps"] + st1["rejected"]) - (st0["steps"] + st0["rejected"])
     value = ncells * evals / wall
 
-    # per-kernel durations (HIP events on the library's stream) and the
-    # algorithmic bytes of each kernel kind
+    # per-kernel durations (HIP events attached to each kernel's launch on
+    # the library's stream) and the algorithmic bytes of each kernel kind
     prof, prof_total = s.profile_evals(args.profile_evals)
     nbytes = s.kernel_bytes()
     dom = max(prof, key=lambda k: prof[k])

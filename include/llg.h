@@ -254,12 +254,17 @@ llg_status llg_set_state(llg_solver *s, const llg_state *in, const float *m, llg
 /* ---- measurement -------------------------------------------------------------
  * llg_profile_evals: runs `n` H_eff evaluations back to back on the solver's
  * stream (forward x pass, spectral pass(es), inverse x pass with the local
- * terms; output kept on the device) and reports, from HIP events recorded on
- * that stream around each kernel, the mean duration in milliseconds of each
- * kernel kind in ms_out[0..n_kinds-1] (0: forward x pass, 1: spectral pass
- * incl. multiply (2D) or the z pass (3D), 2: inverse x pass with local
- * terms, 3: y forward pass (3D), 4: y inverse pass (3D)) and the total
- * wall time in *total_ms.  `n_kinds` must be >= 5.
+ * terms; output kept on the device) and reports the mean duration in
+ * milliseconds of each kernel kind in ms_out[0..n_kinds-1] (0: forward x
+ * pass, 1: spectral pass incl. multiply (2D) or the z pass (3D), 2: inverse
+ * x pass with local terms, 3: y forward pass (3D), 4: y inverse pass (3D)).
+ * Where every pass is one compiled kernel (2D, and 3D with compiled y and z
+ * lengths) the HIP events are attached to each kernel's launch
+ * (hipExtLaunchKernelGGL) and time that kernel's own execution, and
+ * *total_ms is the wall time of `n` further evaluations launched plainly;
+ * otherwise the events are recorded on the stream between the launches
+ * (each interval then also holds the launch of its kernel) and *total_ms
+ * spans the timed evaluations.  `n_kinds` must be >= 5.
  */
 llg_status llg_profile_evals(llg_solver *s, int n, double *ms_out, int n_kinds, double *total_ms);
 /* Algorithmic HBM bytes per evaluation of each kernel kind (same order as

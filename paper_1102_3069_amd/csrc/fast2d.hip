@@ -1373,11 +1373,11 @@ hipError_t launch_row_fwd_t(const Grid& g, const float2* twx, float2* S, const F
     if (g.nx == PX) {
         hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, NQ, true, NAT>), lds_p);
         if (e_ != hipSuccess) return e_;
-        hipLaunchKernelGGL((row_fwd_fast<PX, E, NQ, true, NAT>), grid, dim3(R_::NT), lds_p, s, g, twx, S, fa, st);
+        hot_launch(row_fwd_fast<PX, E, NQ, true, NAT>, grid, dim3(R_::NT), lds_p, s, g, twx, S, fa, st);
     } else if (2 * g.nx <= PX) {
         hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_fwd_fast<PX, E, NQ, false, NAT>), lds_o);
         if (e_ != hipSuccess) return e_;
-        hipLaunchKernelGGL((row_fwd_fast<PX, E, NQ, false, NAT>), grid, dim3(R_::NT), lds_o, s, g, twx, S, fa, st);
+        hot_launch(row_fwd_fast<PX, E, NQ, false, NAT>, grid, dim3(R_::NT), lds_o, s, g, twx, S, fa, st);
     } else {
         return hipErrorInvalidValue;
     }
@@ -1395,11 +1395,11 @@ hipError_t launch_row_inv_t(const Grid& g, const Phys& p, const float2* twx, flo
     if (g.nx == PX) {
         hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, NQ, true, NAT>), lds_p);
         if (e_ != hipSuccess) return e_;
-        hipLaunchKernelGGL((row_inv_fast<PX, E, NQ, true, NAT>), grid, dim3(R_::NT), lds_p, s, g, p, twx, S, sa, st);
+        hot_launch(row_inv_fast<PX, E, NQ, true, NAT>, grid, dim3(R_::NT), lds_p, s, g, p, twx, S, sa, st);
     } else if (2 * g.nx <= PX) {
         hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&row_inv_fast<PX, E, NQ, false, NAT>), lds_o);
         if (e_ != hipSuccess) return e_;
-        hipLaunchKernelGGL((row_inv_fast<PX, E, NQ, false, NAT>), grid, dim3(R_::NT), lds_o, s, g, p, twx, S, sa,
+        hot_launch(row_inv_fast<PX, E, NQ, false, NAT>, grid, dim3(R_::NT), lds_o, s, g, p, twx, S, sa,
                            st);
     } else {
         return hipErrorInvalidValue;
@@ -1473,7 +1473,7 @@ hipError_t launch_col2d_fast(const Col2dArgs& a, DevState* st, hipStream_t s) {
         if (a.nkx % CF::W) return hipErrorInvalidValue;                                   \
         hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&col2d_fast<LL, E, NQ>), CF::bytes()); \
         if (e_ != hipSuccess) return e_;                                                  \
-        hipLaunchKernelGGL((col2d_fast<LL, E, NQ>), dim3(CF::blocks(a.nkx)), dim3(CF::NT), CF::bytes(), s, a, st); \
+        hot_launch(col2d_fast<LL, E, NQ>, dim3(CF::blocks(a.nkx)), dim3(CF::NT), CF::bytes(), s, a, st); \
         return hipGetLastError();                                                         \
     }
     COL_VARIANTS(CASE)

@@ -265,16 +265,16 @@ hipError_t launch_t3(const ColArgs& a, int mode, DevState* st, hipStream_t s) {
         const void* fn = reinterpret_cast<const void*>(&col3_tiled<L, E, TW, H, 3, COL_FULL>);
         hipError_t e = allow_lds3(fn, T::bytes());
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((col3_tiled<L, E, TW, H, 3, COL_FULL>), grid, block, T::bytes(), s, a, st);
+        hot_launch(col3_tiled<L, E, TW, H, 3, COL_FULL>, grid, block, T::bytes(), s, a, st);
     } else {
         const void* fn = mode == COL_FWD ? reinterpret_cast<const void*>(&col3_tiled<L, E, TW, H, 1, COL_FWD>)
                                          : reinterpret_cast<const void*>(&col3_tiled<L, E, TW, H, 1, COL_INV>);
         hipError_t e = allow_lds3(fn, T::bytes());
         if (e != hipSuccess) return e;
         if (mode == COL_FWD)
-            hipLaunchKernelGGL((col3_tiled<L, E, TW, H, 1, COL_FWD>), grid, block, T::bytes(), s, a, st);
+            hot_launch(col3_tiled<L, E, TW, H, 1, COL_FWD>, grid, block, T::bytes(), s, a, st);
         else
-            hipLaunchKernelGGL((col3_tiled<L, E, TW, H, 1, COL_INV>), grid, block, T::bytes(), s, a, st);
+            hot_launch(col3_tiled<L, E, TW, H, 1, COL_INV>, grid, block, T::bytes(), s, a, st);
     }
     return hipGetLastError();
 }

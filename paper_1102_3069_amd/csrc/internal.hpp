@@ -4,6 +4,7 @@
 // runtime calls.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -11,6 +12,29 @@
 #include "llg.h"
 
 namespace llg {
+
+// Kernel timing for llg_profile_evals: while g_kernel_timing holds event
+// pairs, each launch of a compiled hot-path kernel (hot_launch) takes the
+// next pair and has it recorded around its own execution
+// (hipExtLaunchKernelGGL), so that the pair times that kernel alone, as a
+// profiler's kernel trace does; otherwise hot_launch is a plain launch.
+struct KernelTiming {
+    hipEvent_t* ev = nullptr;
+    int left = 0;
+};
+extern thread_local KernelTiming g_kernel_timing;
+
+template <typename F, typename... A>
+inline void hot_launch(F kernel, const dim3& grid, const dim3& block, uint32_t shm, hipStream_t s, A... args) {
+    if (g_kernel_timing.left > 0) {
+        hipEvent_t* e = g_kernel_timing.ev;
+        g_kernel_timing.ev += 2;
+        g_kernel_timing.left -= 1;
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, s, e[0], e[1], 0u, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+    }
+}
 
 // Geometry of the cell grid and of the convolution (FFT) grid.
 //   rows  = ny*nz x-rows of nx cells, row r = k*ny + j

@@ -96,6 +96,10 @@ __global__ void noalloc_state_kernel(DevState* __restrict__ dst, const DevState*
 
 }  // namespace
 
+namespace llg {
+thread_local KernelTiming g_kernel_timing;
+}
+
 struct llg_solver {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -1242,6 +1246,60 @@ llg_status llg_profile_evals(llg_solver* s, int n, double* ms_out, int n_kinds, 
     // not the kernel's
     if ((rc = eval_into(s, s->hbuf, p)) != LLG_OK) return rc;
     if ((rc = sync(s)) != LLG_OK) return rc;
+    // Every pass one compiled kernel: each kernel's own start and end
+    // (events attached to its launch, as a profiler's kernel trace times it).
+    const bool exact = s->fastrows && (two_d(s) ? s->fast2d : (s->fast3dy && s->fast3dz));
+    if (exact) {
+        const int np = two_d(s) ? 3 : 5;    // 2D: fwd, spectral, inv; 3D: fwd, y fwd, z, y inv, inv
+        std::vector<hipEvent_t> ev(2 * (size_t)np * n + 2);
+        for (auto& e : ev) HIPCHK(s, hipEventCreate(&e));
+        struct Guard {
+            std::vector<hipEvent_t>& ev;
+            ~Guard() {
+                g_kernel_timing = KernelTiming{};
+                for (auto& e : ev) (void)hipEventDestroy(e);
+            }
+        } guard{ev};
+        hipEvent_t* T = &ev[2 * (size_t)np * n];
+        for (int i = 0; i < n; ++i) {
+            g_kernel_timing = KernelTiming{&ev[2 * (size_t)np * i], np};
+            if ((rc = launch_fwd_plain(s, 1)) != LLG_OK) return rc;
+            if ((rc = launch_spectral(s)) != LLG_OK) return rc;
+            StageArgs sa = {};
+            sa.mode = ROW_EVAL;
+            sa.m_in = bref_cur(s->mbuf[0], s->mbuf[1], 1);
+            sa.m0 = sa.m_in;
+            sa.m_out = bref(nullptr);
+            sa.k_out = bref(nullptr);
+            sa.h_out = s->hbuf;
+            HIPCHK(s, row_inv(s, p, sa));
+            if (g_kernel_timing.left != 0) return fail(s, LLG_E_DEVICE, "an evaluation launched fewer kernels than timed");
+        }
+        g_kernel_timing = KernelTiming{};
+        // the wall time of an evaluation from `n` more, launched plainly
+        // back to back (the timed launches above carry their events)
+        HIPCHK(s, hipEventRecord(T[0], s->stream));
+        for (int i = 0; i < n; ++i)
+            if ((rc = eval_into(s, s->hbuf, p)) != LLG_OK) return rc;
+        HIPCHK(s, hipEventRecord(T[1], s->stream));
+        if ((rc = sync(s)) != LLG_OK) return rc;
+        // pair index -> kernel kind (0 fwd, 1 spectral / z, 2 inv, 3 y fwd, 4 y inv)
+        const int kind2[3] = {0, 1, 2}, kind3[5] = {0, 3, 1, 4, 2};
+        double acc[5] = {0, 0, 0, 0, 0};
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < np; ++k) {
+                float t = 0.f;
+                HIPCHK(s, hipEventElapsedTime(&t, ev[2 * ((size_t)np * i + k)], ev[2 * ((size_t)np * i + k) + 1]));
+                acc[two_d(s) ? kind2[k] : kind3[k]] += t;
+            }
+        float tot = 0.f;
+        HIPCHK(s, hipEventElapsedTime(&tot, T[0], T[1]));
+        for (int k = 0; k < 5; ++k) ms_out[k] = acc[k] / n;
+        for (int k = 5; k < n_kinds; ++k) ms_out[k] = 0.0;
+        *total_ms = tot;
+        s->spec_valid = false;
+        return restore_done(s, was);
+    }
     std::vector<hipEvent_t> ev(6 * (size_t)n);
     for (auto& e : ev) HIPCHK(s, hipEventCreate(&e));
     for (int i = 0; i < n; ++i) {

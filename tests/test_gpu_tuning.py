@@ -124,3 +124,22 @@ def test_batch_follows_the_table(lib, reset_table):
     for i, s in enumerate(singles):
         s.step("rk4", 1e-13, 5)
         assert np.array_equal(b.get_m(i), s.get_m()), f"film {i}"
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 1), (32, 32, 16)])
+def test_profile_evals_times_each_kernel(lib, shape):
+    """llg_profile_evals: every pass of the evaluation gets a positive
+    kernel time (2D: three kernels; 3D: five), and the kernel times of an
+    evaluation add up to no more than its wall time."""
+    prob, m0 = workloads.small_problem(shape, seed=5)
+    s = lib.Solver(0)
+    s.set_problem(prob)
+    s.set_m(m0)
+    prof, total = s.profile_evals(10)
+    per = total / 10
+    print(shape, {k: round(v * 1e3, 2) for k, v in prof.items()}, "eval", round(per * 1e3, 2), flush=True)
+    want = ("row_fwd", "spectral", "row_inv") + (("y_fwd", "y_inv") if shape[2] > 1 else ())
+    assert all(prof[k] > 0 for k in want)
+    assert all(prof[k] == 0 for k in prof if k not in want)
+    assert sum(prof.values()) <= per * 1.001
+    s.close()
