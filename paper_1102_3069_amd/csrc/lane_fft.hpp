@@ -174,12 +174,21 @@ struct LaneFFT {
         constexpr int LR = L / R;
         constexpr int B = tws_off(S);
         constexpr bool FIRST = S == 0, LAST = S == NS - 1;
+        // power-of-two lengths: every radix, Ns and P are powers of two, so a
+        // scratch index splits into the lane's part and a part fixed by
+        // (u, r) with disjoint bits, and the swizzle (linear over XOR) of the
+        // index is the XOR of the parts' swizzles: one lane value per stage
+        // and a constant per access
+        constexpr bool P2 = (L & (L - 1)) == 0;
+        const int rl = lf_swz<L>(lg);
         C v[U][R];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = lg + P * u;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[u][r] = FIRST ? x[u + r * U] : sc[lf_swz<L>(j + r * LR)];
+            for (int r = 0; r < R; ++r)
+                v[u][r] = FIRST ? x[u + r * U]
+                        : sc[P2 ? (rl ^ lf_swz<L>(P * u + r * LR)) : lf_swz<L>(j + r * LR)];
             if (Ns > 1) {
                 const int k = cmod<Ns>(j);
 #pragma unroll
@@ -198,13 +207,18 @@ struct LaneFFT {
                 for (int r = 0; r < R; ++r) x[u + r * U] = v[u][r];
         } else {
             __builtin_amdgcn_wave_barrier();
+            // the lane's part of the store index: d(lg) with d(j) = (j - j mod Ns) R + j mod Ns
+            const int wl = lf_swz<L>((lg - cmod<Ns>(lg)) * R + cmod<Ns>(lg));
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = lg + P * u;
                 const int k = cmod<Ns>(j);
                 const int d = (j - k) * R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) sc[lf_swz<L>(d + r * Ns)] = v[u][r];
+                for (int r = 0; r < R; ++r) {
+                    const int c = (P * u - cmod<Ns>(P * u)) * R + cmod<Ns>(P * u) + r * Ns;
+                    sc[P2 ? (wl ^ lf_swz<L>(c)) : lf_swz<L>(d + r * Ns)] = v[u][r];
+                }
             }
             __builtin_amdgcn_wave_barrier();
         }
