@@ -98,13 +98,17 @@ template <int N> __device__ __forceinline__ int cmod(int a) { return a % N; }
 // LDS scratch index of element i of a length-L transform: a permutation of
 // 0 .. L-1 that flips the low bits of i (within its aligned run of M + 1
 // elements, M + 1 the largest power of two dividing L, at most 32) by bits
-// 3.. and 7.. of i.  Unit-stride runs and the R-strided runs of the Stockham
-// stores then fall into distinct 8-byte bank pairs.
+// A.. and B.. of i (each flipped bit taken from higher bits, so the map is
+// invertible; it is linear over XOR).  Unit-stride runs and the R-strided
+// runs of the Stockham stores then fall into distinct 8-byte bank pairs.
 template <int L> struct LfSwz {
     static constexpr int low = L & -L;
     static constexpr int M = (low < 32 ? low : 32) - 1;
 };
-template <int L> __device__ __forceinline__ int lf_swz(int i) { return i ^ (((i >> 3) ^ (i >> 7)) & LfSwz<L>::M); }
+template <int L, int A = 3, int B = 7> __device__ __forceinline__ int lf_swz(int i) {
+    return i ^ (((i >> A) ^ (i >> B)) & LfSwz<L>::M);
+}
+
 template <int L> struct LfScratch { static constexpr int size = L; };
 
 template <int L, int E, int TM, typename C>
@@ -112,6 +116,11 @@ struct LaneFFT {
     static constexpr int P = L / E;
     static constexpr int NS = lf_nstages(L, E);
     static constexpr int SCRATCH = LfScratch<L>::size;   // elements per group
+    // swizzle shifts: with four elements per lane (radix-4 stages) bits 2 and
+    // 3 spread the stride-4 stage stores over the banks (bank conflicts of
+    // the 1024-point rows 104448 -> 6144 cycles per launch); otherwise 3 and 7
+    static constexpr int SA = E == 4 ? 2 : 3, SB = E == 4 ? 3 : 7;
+    static __device__ __forceinline__ int swz(int i) { return lf_swz<L, SA, SB>(i); }
     static_assert(L % E == 0 && NS >= 0, "length must factor into radices dividing E");
     static_assert(64 % P == 0, "a lane group must fit one wavefront");
 
@@ -180,7 +189,7 @@ struct LaneFFT {
         // index is the XOR of the parts' swizzles: one lane value per stage
         // and a constant per access
         constexpr bool P2 = (L & (L - 1)) == 0;
-        const int rl = lf_swz<L>(lg);
+        const int rl = swz(lg);
         C v[U][R];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -188,7 +197,7 @@ struct LaneFFT {
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 v[u][r] = FIRST ? x[u + r * U]
-                        : sc[P2 ? (rl ^ lf_swz<L>(P * u + r * LR)) : lf_swz<L>(j + r * LR)];
+                        : sc[P2 ? (rl ^ swz(P * u + r * LR)) : swz(j + r * LR)];
             if (Ns > 1) {
                 const int k = cmod<Ns>(j);
 #pragma unroll
@@ -208,7 +217,7 @@ struct LaneFFT {
         } else {
             __builtin_amdgcn_wave_barrier();
             // the lane's part of the store index: d(lg) with d(j) = (j - j mod Ns) R + j mod Ns
-            const int wl = lf_swz<L>((lg - cmod<Ns>(lg)) * R + cmod<Ns>(lg));
+            const int wl = swz((lg - cmod<Ns>(lg)) * R + cmod<Ns>(lg));
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = lg + P * u;
@@ -217,7 +226,7 @@ struct LaneFFT {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int c = (P * u - cmod<Ns>(P * u)) * R + cmod<Ns>(P * u) + r * Ns;
-                    sc[P2 ? (wl ^ lf_swz<L>(c)) : lf_swz<L>(d + r * Ns)] = v[u][r];
+                    sc[P2 ? (wl ^ swz(c)) : swz(d + r * Ns)] = v[u][r];
                 }
             }
             __builtin_amdgcn_wave_barrier();
