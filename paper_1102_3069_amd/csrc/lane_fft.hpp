@@ -116,10 +116,11 @@ struct LaneFFT {
     static constexpr int P = L / E;
     static constexpr int NS = lf_nstages(L, E);
     static constexpr int SCRATCH = LfScratch<L>::size;   // elements per group
-    // swizzle shifts: with four elements per lane (radix-4 stages) bits 2 and
-    // 3 spread the stride-4 stage stores over the banks (bank conflicts of
-    // the 1024-point rows 104448 -> 6144 cycles per launch); otherwise 3 and 7
-    static constexpr int SA = E == 4 ? 2 : 3, SB = E == 4 ? 3 : 7;
+    // swizzle shifts: plans of radix 4 and below (E not a multiple of 8) take
+    // bits 2 and 3, which spread their stride-2 and stride-4 stage stores
+    // over the banks (bank conflicts of the 1024-point rows 104448 -> 6144
+    // cycles per launch); radix-8 and radix-16 plans take 3 and 7
+    static constexpr int SA = E % 8 == 0 ? 3 : 2, SB = E % 8 == 0 ? 7 : 3;
     static __device__ __forceinline__ int swz(int i) { return lf_swz<L, SA, SB>(i); }
     static_assert(L % E == 0 && NS >= 0, "length must factor into radices dividing E");
     static_assert(64 % P == 0, "a lane group must fit one wavefront");
